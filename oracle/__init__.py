@@ -1,0 +1,376 @@
+"""Oracle: plain FP64 CPU reference of the finite element pipeline.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library (``paper_1708_01773_amd``) and never imports it.
+
+The numerical work lives in ``fe_oracle.c`` (single-threaded, FP64, written
+from the definitions in arXiv 1708.01773: Sect. 3.4 Lagrange bases, Sect. 3.6
+cell-wise assembly, Sect. 3.7 numerical integration, Sect. 10.4 strong
+Dirichlet elimination, Sect. 11.1 COO compression).  This module marshals
+numpy arrays to it through ctypes and adds two pure-Python pieces:
+
+* :func:`coo_compress` -- the paper's build-up in COO form followed by the
+  "compression" that sums duplicate entries and converts to CSR (Sect. 11.1),
+  used as a self-check of the symbolic/numeric CSR path on small inputs;
+* :func:`lanczos_extremes` -- extremal eigenvalue estimates of the
+  preconditioned operator from the CG coefficients (the Lanczos tridiagonal
+  built from CG's alpha/beta, Saad Sect. 6.7.3).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_P = ctypes.c_void_p
+
+
+class OrcProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", _i),
+        ("n", _i * 3),
+        ("k", _i),
+        ("problem", _i),
+        ("lam", _d),
+        ("mu", _d),
+        ("source_kind", _i),
+        ("source", _d * 3),
+        ("dirichlet_kind", _i),
+        ("dirichlet_affine", _d * 12),
+    ]
+
+
+def lib():
+    """Load (building on first use) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.orc_gauss_legendre.argtypes = [_i, _P, _P]
+        L.orc_gauss_legendre.restype = _i
+        L.orc_lagrange_1d.argtypes = [_i, _d, _P, _P]
+        L.orc_lagrange_1d.restype = None
+        L.orc_element_matrix.argtypes = [_i, _i, _i, _P, _d, _d, _d, _P]
+        L.orc_element_matrix.restype = _i
+        L.orc_element_load.argtypes = [_i, _i, _i, _P, _i, _P, _P]
+        L.orc_element_load.restype = _i
+        L.orc_cell_vertices.argtypes = [_i, _P, _P, _i64, _P]
+        L.orc_cell_vertices.restype = None
+        L.orc_number_nodes.argtypes = [_i, _P, _i, ctypes.c_uint, _P, _P, _P]
+        L.orc_number_nodes.restype = None
+        L.orc_cell_dofs.argtypes = [_i, _P, _i, _i, _P, _i64, _P]
+        L.orc_cell_dofs.restype = None
+        L.orc_csr_pattern.argtypes = [_i64, _i, _P, _i64, _P, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+        L.orc_csr_pattern.restype = _i64
+        L.orc_free.argtypes = [_P]
+        L.orc_free.restype = None
+        L.orc_assemble.argtypes = [ctypes.POINTER(OrcProblem), _P, _P, _P, _i64, _P, _P, _P, _P]
+        L.orc_assemble.restype = _i
+        L.orc_assemble_row.argtypes = [ctypes.POINTER(OrcProblem), _P, _P, _P, _i64, _i64, _P, _P, _P]
+        L.orc_assemble_row.restype = _i64
+        L.orc_spmv.argtypes = [_i64, _P, _P, _P, _P, _P]
+        L.orc_spmv.restype = None
+        L.orc_pcg.argtypes = [_i64, _P, _P, _P, _P, _P, _d, _i, _P, _P, _P, _P]
+        L.orc_pcg.restype = _i
+        L.orc_l2_error.argtypes = [ctypes.POINTER(OrcProblem), _P, _P, _P, _i, _i, _P]
+        L.orc_l2_error.restype = _d
+        L.orc_fixed_values.argtypes = [ctypes.POINTER(OrcProblem), _P, _P, _i64, _P]
+        L.orc_fixed_values.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_P) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def lame(young, nu):
+    """Lame parameters of isotropic elasticity from Young's modulus and Poisson's ratio."""
+    lam = young * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = young / (2.0 * (1.0 + nu))
+    return lam, mu
+
+
+class Problem:
+    """Description of one assembly problem (all fields are plain numbers).
+
+    problem: 'poisson' or 'elasticity'; faces: Dirichlet face bitmask
+    (bit 2r: x_r = 0, bit 2r+1: x_r = 1); source_kind 0 none, 1 constant
+    vector, 2 manufactured sin-product load; dirichlet_kind 0 zero, 1 affine
+    (u_D,c = aff[4c] + sum_r aff[4c+1+r] x_r).
+    """
+
+    def __init__(self, dim, n, k, problem="poisson", young=1.0, nu=0.3,
+                 source_kind=0, source=(0.0, 0.0, 0.0), faces=None,
+                 dirichlet_kind=0, dirichlet_affine=None):
+        self.dim = int(dim)
+        n = [int(v) for v in (n if hasattr(n, "__len__") else [n] * dim)]
+        self.n = n + [1] * (3 - len(n))
+        if self.dim == 2:
+            self.n[2] = 1
+        self.k = int(k)
+        self.problem = problem
+        self.young, self.nu = float(young), float(nu)
+        self.source_kind = int(source_kind)
+        self.source = [float(s) for s in source] + [0.0] * (3 - len(source))
+        self.faces = (1 << (2 * dim)) - 1 if faces is None else int(faces)
+        self.dirichlet_kind = int(dirichlet_kind)
+        aff = list(dirichlet_affine) if dirichlet_affine is not None else []
+        self.dirichlet_affine = [float(v) for v in aff] + [0.0] * (12 - len(aff))
+
+    @property
+    def ncomp(self):
+        return self.dim if self.problem == "elasticity" else 1
+
+    @property
+    def ncells(self):
+        return self.n[0] * self.n[1] * (self.n[2] if self.dim == 3 else 1)
+
+    @property
+    def nn(self):
+        return (self.k + 1) ** self.dim
+
+    @property
+    def nloc(self):
+        return self.nn * self.ncomp
+
+    def c_struct(self):
+        s = OrcProblem()
+        s.dim = self.dim
+        for r in range(3):
+            s.n[r] = self.n[r]
+        s.k = self.k
+        s.problem = 1 if self.problem == "elasticity" else 0
+        s.lam, s.mu = lame(self.young, self.nu) if self.problem == "elasticity" else (0.0, 0.0)
+        s.source_kind = self.source_kind
+        for r in range(3):
+            s.source[r] = self.source[r]
+        s.dirichlet_kind = self.dirichlet_kind
+        for r in range(12):
+            s.dirichlet_affine[r] = self.dirichlet_affine[r]
+        return s
+
+
+def gauss_legendre(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    if lib().orc_gauss_legendre(n, _ptr(x), _ptr(w)) != 0:
+        raise ValueError("unsupported number of Gauss points")
+    return x, w
+
+
+def lagrange_1d(k, x):
+    v = np.zeros(k + 1)
+    d = np.zeros(k + 1)
+    lib().orc_lagrange_1d(k, float(x), _ptr(v), _ptr(d))
+    return v, d
+
+
+def element_matrix(dim, k, X, coef=1.0, problem="poisson", young=1.0, nu=0.3):
+    """Element matrix of one cell with vertex coordinates X (2^d x d).
+
+    Returns (A, ok); ok is False if det J <= 0 at a quadrature point."""
+    X = _c(X, np.float64).reshape(-1)
+    ncomp = dim if problem == "elasticity" else 1
+    nloc = (k + 1) ** dim * ncomp
+    A = np.zeros((nloc, nloc))
+    lam, mu = lame(young, nu) if problem == "elasticity" else (0.0, 0.0)
+    rc = lib().orc_element_matrix(dim, k, 1 if problem == "elasticity" else 0, _ptr(X),
+                                  float(coef), lam, mu, _ptr(A))
+    if rc == -2:
+        raise ValueError("unsupported dim/order")
+    return A, rc == 0
+
+
+def element_load(dim, k, ncomp, X, source_kind, source):
+    X = _c(X, np.float64).reshape(-1)
+    src = _c(list(source) + [0.0] * (3 - len(source)), np.float64)
+    f = np.zeros((k + 1) ** dim * ncomp)
+    lib().orc_element_load(dim, k, ncomp, _ptr(X), int(source_kind), _ptr(src), _ptr(f))
+    return f
+
+
+def cell_vertices(dim, n, vxyz, cell):
+    nn = _c(list(n) + [1] * (3 - len(n)), np.int32)
+    v = _c(vxyz, np.float64)
+    X = np.zeros((1 << dim, dim))
+    lib().orc_cell_vertices(dim, _ptr(nn), _ptr(v), int(cell), _ptr(X))
+    return X
+
+
+def number_nodes(dim, n, k, faces):
+    nn = _c(list(n) + [1] * (3 - len(n)), np.int32)
+    nnodes = 1
+    for r in range(dim):
+        nnodes *= n[r] * k + 1
+    code = np.zeros(nnodes, dtype=np.int64)
+    nf = _i64()
+    nx = _i64()
+    lib().orc_number_nodes(dim, _ptr(nn), k, faces, _ptr(code), ctypes.byref(nf), ctypes.byref(nx))
+    return code, nf.value, nx.value
+
+
+def cell_dofs(P: Problem, node_code):
+    nn = _c(P.n, np.int32)
+    out = np.zeros((P.ncells, P.nloc), dtype=np.int64)
+    lib().orc_cell_dofs(P.dim, _ptr(nn), P.k, P.ncomp, _ptr(_c(node_code, np.int64)), P.ncells, _ptr(out))
+    return out
+
+
+def csr_pattern(cdofs, nfree):
+    cdofs = _c(cdofs, np.int64)
+    rowptr = np.zeros(nfree + 1, dtype=np.int64)
+    cptr = ctypes.POINTER(ctypes.c_int32)()
+    nnz = lib().orc_csr_pattern(cdofs.shape[0], cdofs.shape[1], _ptr(cdofs), nfree, _ptr(rowptr),
+                                ctypes.byref(cptr))
+    colind = np.ctypeslib.as_array(cptr, shape=(max(nnz, 1),))[:nnz].copy()
+    lib().orc_free(ctypes.cast(cptr, _P))
+    return rowptr, colind
+
+
+def assemble(P: Problem, vxyz, coef, cdofs, nfree, rowptr, colind):
+    """Numeric assembly; returns (values, rhs, ok)."""
+    s = P.c_struct()
+    vxyz = _c(vxyz, np.float64)
+    coef = None if coef is None else _c(coef, np.float64)
+    cdofs = _c(cdofs, np.int64)
+    values = np.zeros(int(rowptr[-1]))
+    rhs = np.zeros(nfree)
+    rc = lib().orc_assemble(ctypes.byref(s), _ptr(vxyz), _ptr(coef), _ptr(cdofs), nfree,
+                            _ptr(_c(rowptr, np.int64)), _ptr(_c(colind, np.int32)), _ptr(values), _ptr(rhs))
+    return values, rhs, rc == 0
+
+
+def assemble_row(P: Problem, vxyz, coef, cdofs, row, maxlen=4096):
+    """One row (columns, values, rhs entry) of the assembled free-free system."""
+    s = P.c_struct()
+    cols = np.zeros(maxlen, dtype=np.int64)
+    vals = np.zeros(maxlen)
+    rhs = _d()
+    coef = None if coef is None else _c(coef, np.float64)
+    ln = lib().orc_assemble_row(ctypes.byref(s), _ptr(_c(vxyz, np.float64)), _ptr(coef),
+                                _ptr(_c(cdofs, np.int64)), int(row), maxlen, _ptr(cols), _ptr(vals),
+                                ctypes.byref(rhs))
+    if ln < 0:
+        raise ValueError("row longer than maxlen")
+    return cols[:ln].copy(), vals[:ln].copy(), rhs.value
+
+
+def spmv(rowptr, colind, values, x):
+    n = len(rowptr) - 1
+    y = np.zeros(n)
+    lib().orc_spmv(n, _ptr(_c(rowptr, np.int64)), _ptr(_c(colind, np.int32)), _ptr(_c(values, np.float64)),
+                   _ptr(_c(x, np.float64)), _ptr(y))
+    return y
+
+
+def pcg(rowptr, colind, values, b, rtol, maxit, x0=None):
+    """Jacobi PCG.  Returns dict(x, status, iters, relres, alphas, betas)."""
+    n = len(rowptr) - 1
+    x = np.zeros(n) if x0 is None else _c(x0, np.float64).copy()
+    al = np.zeros(max(maxit, 1))
+    be = np.zeros(max(maxit, 1))
+    it = _i()
+    rr = _d()
+    st = lib().orc_pcg(n, _ptr(_c(rowptr, np.int64)), _ptr(_c(colind, np.int32)), _ptr(_c(values, np.float64)),
+                       _ptr(_c(b, np.float64)), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
+                       ctypes.byref(rr), _ptr(al), _ptr(be))
+    return dict(x=x, status=st, iters=it.value, relres=rr.value, alphas=al[:it.value].copy(),
+                betas=be[:it.value].copy())
+
+
+def l2_error(P: Problem, vxyz, cdofs, xfree, kq, exact_kind, exact):
+    s = P.c_struct()
+    ex = _c(list(exact) + [0.0] * (12 - len(exact)), np.float64)
+    return lib().orc_l2_error(ctypes.byref(s), _ptr(_c(vxyz, np.float64)), _ptr(_c(cdofs, np.int64)),
+                              _ptr(_c(xfree, np.float64)), int(kq), int(exact_kind), _ptr(ex))
+
+
+def fixed_values(P: Problem, vxyz, cdofs, nfixed_dofs):
+    s = P.c_struct()
+    out = np.zeros(max(nfixed_dofs, 1))
+    lib().orc_fixed_values(ctypes.byref(s), _ptr(_c(vxyz, np.float64)), _ptr(_c(cdofs, np.int64)),
+                           int(nfixed_dofs), _ptr(out))
+    return out[:nfixed_dofs]
+
+
+class System:
+    """The whole assembled free-free system of a problem on a given mesh."""
+
+    def __init__(self, P: Problem, vxyz, coef=None):
+        self.P = P
+        self.vxyz = _c(vxyz, np.float64)
+        self.coef = None if coef is None else _c(coef, np.float64)
+        self.node_code, nfree_nodes, nfixed_nodes = number_nodes(P.dim, P.n, P.k, P.faces)
+        self.nfree = nfree_nodes * P.ncomp
+        self.nfixed = nfixed_nodes * P.ncomp
+        self.cell_dofs = cell_dofs(P, self.node_code)
+        self.rowptr, self.colind = csr_pattern(self.cell_dofs, self.nfree)
+        self.values, self.rhs, self.ok = assemble(P, self.vxyz, self.coef, self.cell_dofs, self.nfree,
+                                                  self.rowptr, self.colind)
+
+    @property
+    def nnz(self):
+        return int(self.rowptr[-1])
+
+    def dense(self):
+        A = np.zeros((self.nfree, self.nfree))
+        for i in range(self.nfree):
+            for j in range(self.rowptr[i], self.rowptr[i + 1]):
+                A[i, self.colind[j]] = self.values[j]
+        return A
+
+    def scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.values, self.colind, self.rowptr), shape=(self.nfree, self.nfree))
+
+
+def coo_compress(rows, cols, vals, n):
+    """The paper's COO build-up followed by compression (Sect. 11.1): sort the
+    pushed-back (row, col, value) triplets and sum duplicates, giving CSR."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    order = np.lexsort((cols, rows))
+    r, c, v = rows[order], cols[order], vals[order]
+    out_c, out_v, out_r = [], [], []
+    for i in range(len(r)):
+        if out_r and out_r[-1] == r[i] and out_c[-1] == c[i]:
+            out_v[-1] += v[i]
+        else:
+            out_r.append(r[i])
+            out_c.append(c[i])
+            out_v.append(v[i])
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    for rr in out_r:
+        rowptr[rr + 1] += 1
+    rowptr = np.cumsum(rowptr)
+    return rowptr, np.asarray(out_c, dtype=np.int32), np.asarray(out_v)
+
+
+def lanczos_extremes(alphas, betas):
+    """Extremal Ritz values of the preconditioned operator from CG
+    coefficients: T has diagonal 1/a_j + b_{j-1}/a_{j-1} and off-diagonal
+    sqrt(b_j)/a_j (Saad, Sect. 6.7.3)."""
+    m = len(alphas)
+    if m == 0:
+        return float("nan"), float("nan")
+    T = np.zeros((m, m))
+    for j in range(m):
+        T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j + 1 < m:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1])

@@ -1,0 +1,72 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case copies the oracle source, plants one mistake (a dropped term, a
+wrong sign, a transposed operand, a wrong index), builds it into a temporary
+library, swaps it in for the real one and checks that at least one pin fails.
+Everything runs on the CPU; the real oracle is never modified.
+"""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle as O
+from oracle import build as OB
+from tests import test_oracle_pins as PINS
+
+MUTANTS = {
+    "transposed_inverse_jacobian": ("g += Ji[s * dim + i] * gref[s];", "g += Ji[i * dim + s] * gref[s];"),
+    "elasticity_mu_term_untransposed": ("+ mu * grad[a * dim + j] * grad[b * dim + i];",
+                                        "+ mu * grad[a * dim + i] * grad[b * dim + j];"),
+    "lifting_sign": ("else rhs[g[a]] -= A[a * nloc + b] * uD[b];", "else rhs[g[a]] += A[a * nloc + b] * uD[b];"),
+    "dropped_quadrature_weight": ("double wd = w * fabs(qp.detJ) * coef;", "double wd = fabs(qp.detJ) * coef;"),
+    "gauss_weight_scale": ("w[n - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);",
+                           "w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);"),
+    "lagrange_derivative_sign": ("dnum += prod;", "dnum -= prod;"),
+    "local_node_axes_swapped": ("int ar[3] = {a % (k + 1), (a / (k + 1)) % (k + 1), a / ((k + 1) * (k + 1))};\n    int64_t N0",
+                                "int ar[3] = {(a / (k + 1)) % (k + 1), a % (k + 1), a / ((k + 1) * (k + 1))};\n    int64_t N0"),
+    "load_without_shape_function": ("f[a * ncomp + c] += wd * fc * phi[a];", "f[a * ncomp + c] += wd * fc;"),
+    "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
+    "geometry_derivative_sign": ("if (r == s) g *= vr ? 1.0 : -1.0;", "if (r == s) g *= vr ? -1.0 : 1.0;"),
+}
+
+# the pins run against each mutant (small, fast parametrizations)
+PIN_CALLS = [
+    lambda: PINS.test_gauss_legendre_matches_numpy_and_is_exact(3),
+    lambda: PINS.test_lagrange_delta_partition_and_exact_polynomials(2),
+    lambda: PINS.test_paper_bicubic_quad_numbering(),
+    lambda: PINS.test_poisson_element_affine_closed_form(3, 2),
+    lambda: PINS.test_elasticity_element_affine_closed_form(3, 2),
+    lambda: PINS.test_energy_of_linear_fields(),
+    lambda: PINS.test_global_kernel_and_load_without_dirichlet(3, 1, "poisson"),
+    lambda: PINS.test_linear_patch_test(2, 3, 3, "poisson"),
+    lambda: PINS.test_linear_patch_test(3, 1, 3, "elasticity"),
+    lambda: PINS.test_pcg_matches_direct_solve_and_lanczos_bounds(2, 2, "poisson"),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, monkeypatch):
+    old, new = MUTANTS[name]
+    src = open(OB.SRC).read()
+    assert src.count(old) == 1, "mutation site not found exactly once"
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "mut.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        so = os.path.join(td, "libmut.so")
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", so, path, "-lm"], check=True)
+        real = O.lib()
+        monkeypatch.setattr(O, "_lib", None)
+        monkeypatch.setattr(OB, "LIB", so)
+        O.lib()  # loads the mutant with the same argtypes
+        caught = []
+        for call in PIN_CALLS:
+            try:
+                call()
+            except Exception:  # assertion or numerical failure both count
+                caught.append(call)
+        monkeypatch.setattr(O, "_lib", real)
+        assert caught, f"no pin caught mutant {name}"
