@@ -1,0 +1,212 @@
+"""Benchmark of the finite element hot path on one MI355X.
+
+A step is one pass of the whole path over the synthetic workload: element
+integration (K3) + deterministic CSR scatter (K5, with the Jacobi diagonal)
++ Jacobi-PCG to rtol 1e-10 (SpMV K7 and vector kernels K8).  The set-up
+(mesh upload, DOF numbering, CSR pattern) is done once before timing, as the
+pattern is reused by every assembly.  Default workload: 3D Poisson on the
+unit cube, 128^3 Q1 hexahedra with interior vertices jittered by +-0.2h,
+lognormal per-cell coefficients, f = 1, u = 0 on the boundary, FP64.
+
+Prints one JSON line.  Run ``python bench.py`` (1 GPU, 10 timed steps).
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Q1–Q4 hex elements assembled/s, % HBM/MFMA peak; solves/s + p99 latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+WORKLOADS = {
+    "c2": dict(dim=3, n=128, k=1, problem="poisson", precision="fp64", rtol=1e-10,
+               text="3D Poisson -div(k grad u) = 1 on the unit cube, 128^3 Q1 hexes, interior vertices jittered "
+                    "+-0.2h (seed 17080), lognormal per-cell k (seed 17081), u = 0 on the boundary, FP64 assembly "
+                    "+ Jacobi-PCG to rtol 1e-10"),
+    "c1": dict(dim=2, n=32, k=1, problem="poisson", precision="fp64", rtol=1e-10, jitter=0.0, lognormal=False,
+               source_kind=2,
+               text="2D Poisson on the unit square, 32^2 Q1 quads, k = 1, f = 2 pi^2 sin(pi x) sin(pi y), u = 0, "
+                    "FP64 + Jacobi-PCG to rtol 1e-10"),
+}
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def spmv_bytes(n, nnz):
+    """Algorithmic HBM bytes of one CSR SpMV: values + column indices, row
+    pointers, the input vector once and the output vector."""
+    return nnz * 12 + (n + 1) * 8 + 16 * n
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch from committed rocprofv3 counters, or None when the
+    kernel source changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e:
+        return None
+    src = os.path.join(ROOT, e["source"])
+    if not os.path.exists(src) or source_sha(src) != e["source_sha"]:
+        return None
+    return e["bytes_per_launch"]
+
+
+def cpu_baseline(wl, gpu_iters, ncells_full, nnz_full):
+    """The oracle timed on this host on a bounded sample of the same workload:
+    a 64^3 mesh with the same recipe.  The step time of the full workload is
+    scaled from it: per-cell assembly time x cells, plus per-iteration PCG time
+    scaled by nnz x the iteration count the GPU needed."""
+    import numpy as np
+    import oracle as O
+    from fe_inputs import lognormal_coefficients, structured_vertices
+
+    n = 64
+    dim, k = wl["dim"], wl["k"]
+    P = O.Problem(dim, [n] * dim, k, source_kind=wl.get("source_kind", 1), source=(1.0,))
+    v = structured_vertices(dim, n, jitter=wl.get("jitter", 0.2))
+    coef = lognormal_coefficients(P.ncells) if wl.get("lognormal", True) else None
+    t0 = time.perf_counter()
+    S = O.System(P, v, coef)  # numbering + symbolic + numeric assembly
+    t_asm = time.perf_counter() - t0
+    its = 100
+    t0 = time.perf_counter()
+    res = O.pcg(S.rowptr, S.colind, S.values, S.rhs, 0.0, its)
+    t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
+    step = t_asm / P.ncells * ncells_full + t_it * (nnz_full / S.nnz) * gpu_iters
+    return {
+        "value": ncells_full / step, "unit": "elements/s", "cores": 1, "kind": "oracle",
+        "sample": f"oracle (single-threaded C, FP64) on the same recipe at {n}^{dim} cells: assembly "
+                  f"{t_asm:.2f} s for {P.ncells} cells, PCG {t_it * 1e3:.2f} ms/iteration at nnz={S.nnz}; "
+                  f"scaled to the full workload as cells x per-cell assembly + {gpu_iters} iterations x "
+                  f"per-iteration time x nnz ratio ({nnz_full}/{S.nnz})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=None, help="override cells per axis (development)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard as "
+              f"described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from fe_inputs import lognormal_coefficients, structured_vertices
+    from paper_1708_01773_amd import fe as F
+
+    wl = dict(WORKLOADS[args.workload])
+    if args.n:
+        wl["n"] = args.n
+    dim, n, k = wl["dim"], wl["n"], wl["k"]
+    torch.cuda.set_device(0)
+    v = structured_vertices(dim, n, jitter=wl.get("jitter", 0.2))
+    ncells = n ** dim
+    coef = lognormal_coefficients(ncells) if wl.get("lognormal", True) else None
+    mesh = F.create_mesh(dim, [n] * dim, v, coef)
+    coeff = F.make_coeff(wl["problem"], wl["precision"], source_kind=wl.get("source_kind", 1), source=(1.0,),
+                         dim=dim)
+    A = F.Assembly(mesh, k, coeff)
+    A.pattern()
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    print(f"[bench] set-up done: cells={ncells} rows={A.n_rows} nnz={A.nnz}", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        A.assemble(stream)
+        e1.record(stream)
+        x.zero_()
+        info = F.pcg_solve(A.csr, A.rhs, x, wl["rtol"], 100000, ws, stream)
+        return info, e0, e1
+
+    for i in range(args.warmup):
+        info, _, _ = step()
+        print(f"[bench] warmup {i}: iters={info['iters']} relres={info['relres']:.2e}", file=sys.stderr, flush=True)
+    F.set_timing(True)
+    F.get_timing(reset=True)
+    torch.cuda.synchronize()
+    lat, asm_ms, iters = [], [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        info, e0, e1 = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        asm_ms.append(e0.elapsed_time(e1))
+        iters.append(info["iters"])
+        if info["status"] != F.FE_OK:
+            print(f"[bench] step {i}: solver status {info['status']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    tm = F.get_timing(reset=True)
+    F.set_timing(False)
+    print(f"[bench] timed {args.steps} steps in {total:.3f} s", file=sys.stderr, flush=True)
+
+    ms_step = total / args.steps * 1e3
+    spmv_avg_s = tm["spmv_ms"] / max(tm["spmv_calls"], 1) * 1e-3
+    sb = spmv_bytes(A.n_rows, A.nnz)
+    achieved = sb / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
+    traffic = traffic_for("pcg_spmv_kernel")
+    lat_sorted = sorted(lat)
+    p99 = lat_sorted[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+    out = {
+        "metric": METRIC,
+        "value": ncells * args.steps / total,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["text"], "cells": ncells, "order": k, "dofs": A.n_rows, "nnz": A.nnz},
+        "assembly": {"ms_mean": statistics.mean(asm_ms),
+                     "elements_per_s": ncells / (statistics.mean(asm_ms) * 1e-3),
+                     "integrate_ms": tm["integrate_ms"] / max(tm["integrate_calls"], 1),
+                     "scatter_ms": tm["scatter_ms"] / max(tm["scatter_calls"], 1)},
+        "solve": {"pcg_iters": statistics.mean(iters), "relres": info["relres"],
+                  "true_relres": info["true_relres"], "solves_per_s": args.steps / total,
+                  "p50_ms": statistics.median(lat) * 1e3, "p99_ms": p99 * 1e3,
+                  "kappa_est": info["lambda_max_est"] / info["lambda_min_est"] if info["lambda_min_est"] else None},
+        "roofline": {"kernel": "pcg_spmv_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": sb, "avg_launch_us": spmv_avg_s * 1e6,
+                     "launches": tm["spmv_calls"]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, A.nnz)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

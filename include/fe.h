@@ -1,0 +1,231 @@
+/*
+ * fe.h -- C ABI of the MI355X finite element hot path: cell-wise Galerkin
+ * integration on Lagrangian Q_k quadrilaterals/hexahedra, deterministic
+ * scatter into a CSR matrix and right-hand side with strong Dirichlet
+ * elimination, and the CSR SpMV inside a Jacobi-preconditioned CG solve.
+ *
+ * The method follows arXiv 1708.01773 (FEMPAR): the weak problem and its
+ * affine operator F_h(u) = A u - f (Sect. 3.1-3.2), cell-wise assembly
+ * A_[a][b] = sum_K A^K_ab (Sect. 3.6 eq. assembly), numerical integration on
+ * the reference cell (Sect. 3.7 eqs. fematrix and shape_grad), Lagrangian
+ * Q_k elements (Sect. 3.4 eqs. lagbas/lagbasmd, Sect. 3.8), strong Dirichlet
+ * elimination with lifting (Sect. 10.4 eq. dirichlet_bc_discrete_problem),
+ * CSR storage reused across assemblies (Sect. 11.1), and CG among the
+ * library's iterative solvers (Sect. 12).
+ *
+ * General conventions
+ *  - Every call returns fe_status; FE_OK == 0.  No exception crosses the ABI.
+ *    On a non-OK status the output buffers are unspecified and
+ *    fe_last_error() returns a text for the calling thread.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library borrows them for the stream-ordered duration of the
+ *    call and never frees them.  Library-owned device memory (mesh arrays,
+ *    cached patterns and tables) lives until fe_destroy_mesh.
+ *  - fe_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that only enqueue work return as soon as it is enqueued.
+ *  - Index types: row pointers and nnz counts are int64, column indices and
+ *    cell-to-DOF entries int32 (a single system holds < 2^31 rows).
+ *
+ * Data layout and numbering (fixed, so that results are reproducible)
+ *  - Mesh: structured brick of n0 x n1 (x n2) cells; vertex (i,j,l) has id
+ *    i + (n0+1)(j + (n1+1) l) (x fastest); cell (i,j,l) has id
+ *    i + n0 (j + n1 l); local vertex v = v0 + 2 v1 + 4 v2.
+ *  - Reference cell [0,1]^d, equidistant nodes (Sect. 3.15), local node
+ *    a = a0 + (k+1) a1 + (k+1)^2 a2, geometry map of order 1 for every k.
+ *  - Global node lattice (n_r k + 1 nodes per axis).  A node is fixed when
+ *    it lies on a Dirichlet face (bit 2r: x_r = 0, bit 2r+1: x_r = 1).  Free
+ *    nodes are ranked lexicographically (x fastest); vector problems
+ *    interleave components: DOF = ncomp * rank + c, local DOF ncomp * a + c.
+ *  - CSR: rows are free DOFs, columns sorted ascending, every pair of free
+ *    DOFs sharing a cell is stored (structural zeros included).
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *fe_stream; /* hipStream_t */
+
+typedef enum {
+    FE_OK = 0,
+    FE_EINVAL = 1,      /* invalid argument (order, dim, sizes, null pointer, too small workspace) */
+    FE_ENOMEM = 2,      /* device allocation failed or a budget was exceeded */
+    FE_EMESH = 3,       /* a cell has det J <= 0 (at a corner on the host, at a quadrature point on the device) */
+    FE_ENOTCONV = 4,    /* iterative solve reached maxit */
+    FE_EBREAKDOWN = 5,  /* CG breakdown: p.Ap <= 0 or not finite */
+    FE_EDEVICE = 6      /* a HIP runtime call failed */
+} fe_status;
+
+/* Text of the last non-OK status set on the calling thread ("" if none). */
+const char *fe_last_error(void);
+
+/* ABI version (incremented on incompatible changes). */
+int32_t fe_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Mesh (Sect. 7: triangulation; the structured brick generator of Sect. 7.4) */
+/* ------------------------------------------------------------------------ */
+typedef struct fe_mesh_s *fe_mesh; /* opaque, library-owned */
+
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t n[3];             /* cells per axis (n[2] ignored for dim 2); each >= 1 */
+    const double *vertex_xyz; /* host, (n0+1)(n1+1)[(n2+1)] x dim, AoS, x fastest; NULL = uniform grid on [0,1]^d */
+    const double *cell_coeff; /* host, one coefficient per cell; NULL = 1.0 */
+} fe_mesh_desc;
+
+/* Copies the host arrays to the device (the caller may free them on return),
+ * validates the geometry and returns a handle.  Synchronous.
+ * FE_EMESH if det J <= 0 at any cell corner; FE_EINVAL on bad sizes. */
+fe_status fe_create_mesh(const fe_mesh_desc *desc, fe_mesh *out);
+
+/* Frees the mesh and everything cached in it.  Waits for pending work. */
+fe_status fe_destroy_mesh(fe_mesh mesh);
+
+/* Replaces the per-cell coefficients (host array, one per cell).  Synchronous.
+ * Cached patterns and tables stay valid. */
+fe_status fe_set_coefficients(fe_mesh mesh, const double *cell_coeff);
+
+/* ------------------------------------------------------------------------ */
+/* Problem description                                                       */
+/* ------------------------------------------------------------------------ */
+enum { FE_POISSON = 0, FE_ELASTICITY = 1 };
+/* Precision of the element GEMM only.  Geometry (J, det J, J^-1), the load
+ * vector, the scatter accumulation, the CSR values and every solver quantity
+ * stay FP64.  FE_FP16/FE_BF16 round the GEMM inputs and accumulate in FP32. */
+enum { FE_FP64 = 0, FE_FP32 = 1, FE_FP16 = 2, FE_BF16 = 3 };
+enum { FE_SOURCE_NONE = 0, FE_SOURCE_CONST = 1, FE_SOURCE_SINPROD = 2 };
+enum { FE_DIRICHLET_ZERO = 0, FE_DIRICHLET_AFFINE = 1 };
+
+typedef struct {
+    int32_t problem;           /* FE_POISSON: int k grad u . grad v ;
+                                  FE_ELASTICITY: int k (2 mu eps(u):eps(v) + lambda div u div v),
+                                  lambda, mu from young / poisson_ratio; ncomp = dim */
+    int32_t precision;         /* FE_FP64 ... FE_BF16 */
+    double young;              /* elasticity only */
+    double poisson_ratio;      /* elasticity only, in (-1, 0.5) */
+    int32_t source_kind;       /* NONE; CONST: f_c = source[c]; SINPROD: f_c = source[c] d pi^2 prod_r sin(pi x_r) */
+    double source[3];
+    uint32_t dirichlet_faces;  /* bitmask of the 2 dim faces; 0 = no fixed DOFs */
+    int32_t dirichlet_kind;    /* ZERO, or AFFINE: u_D,c(x) = aff[4c] + sum_r aff[4c+1+r] x_r */
+    double dirichlet_affine[12];
+} fe_coeff;
+
+/* CSR of the free-free system.  All pointers are device memory owned by the
+ * caller: rowptr n_rows+1 (int64), colind nnz (int32), values nnz, rhs n_rows,
+ * dinv n_rows (Jacobi: 1 / diagonal). */
+typedef struct {
+    int64_t n_rows;
+    int64_t nnz;
+    int64_t *rowptr;
+    int32_t *colind;
+    double *values;
+    double *rhs;
+    double *dinv;
+} fe_csr;
+
+/* ------------------------------------------------------------------------ */
+/* Assembly                                                                  */
+/* ------------------------------------------------------------------------ */
+/* Sizes of the free-free system of (mesh, order, coeff) and the device
+ * workspace fe_assemble / fe_integrate need (element matrices and loads).
+ * Builds and caches the order-dependent set-up on first use (synchronous).
+ * FE_EINVAL for order outside 1..4 or a bad coeff. */
+fe_status fe_assemble_query(fe_mesh mesh, int32_t order, const fe_coeff *coeff,
+                            int64_t *n_rows, int64_t *nnz, size_t *ws_bytes);
+
+/* Symbolic phase (Sect. 11.1: the pattern is built once and reused by every
+ * later assembly): writes out->rowptr and out->colind.  out->n_rows and
+ * out->nnz must equal the query's values.  Enqueues only. */
+fe_status fe_pattern(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_csr *out, fe_stream stream);
+
+/* Numeric phase: element integration (K3) into the workspace, then the
+ * deterministic scatter (K5) of the free-free entries into out->values, of
+ * loads and Dirichlet lifting into out->rhs, and out->dinv = 1 / diagonal.
+ * Requires the pattern written by fe_pattern in out->rowptr/colind (it is
+ * not read: the scatter evaluates the same positions).  No float atomics:
+ * every value is a sum of its contributions in ascending cell order, so the
+ * result is bitwise reproducible.  Enqueues only; a det J <= 0 found at a
+ * quadrature point is reported by the next fe_get_status. */
+fe_status fe_assemble(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_csr *out,
+                      void *ws, size_t ws_bytes, fe_stream stream);
+
+/* K3 alone: element matrices and loads (with lifting) into the workspace.
+ * Layout of the workspace (elements of type double for FE_FP64, float
+ * otherwise, then the loads as double):
+ *   E[(c / cb) * nloc * nloc + a * nloc + b) * cb + c % cb]   (cb from fe_element_layout)
+ *   F[c * nloc + a]  starting at byte offset *load_offset. */
+fe_status fe_integrate(fe_mesh mesh, int32_t order, const fe_coeff *coeff, void *ws, size_t ws_bytes,
+                       fe_stream stream);
+fe_status fe_element_layout(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int32_t *nloc,
+                            int32_t *cell_block, int32_t *elem_bytes, size_t *load_offset);
+
+/* K5 alone: scatter of a workspace filled by fe_integrate into out. */
+fe_status fe_scatter(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_csr *out, const void *ws,
+                     size_t ws_bytes, fe_stream stream);
+
+/* Cell-to-DOF map (Sect. 10.1 lst_dofs_gids): out[c * nloc + ncomp * a + comp]
+ * = free DOF id, or -1 - fixed DOF id.  out: device, ncells * nloc int32. */
+fe_status fe_cell_dofs(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int32_t *out, fe_stream stream);
+
+/* The cell-to-nnz permutation made explicit: perm[c * nloc^2 + a * nloc + b] =
+ * index into the CSR values that element entry (a, b) of cell c adds to, or
+ * -1 if a or b is fixed.  out: device, ncells * nloc^2 int64. */
+fe_status fe_permutation(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int64_t *perm, fe_stream stream);
+
+/* Waits for the mesh's pending work and returns FE_EMESH if a kernel found
+ * det J <= 0 at a quadrature point since the last call (and clears it). */
+fe_status fe_get_status(fe_mesh mesh);
+
+/* ------------------------------------------------------------------------ */
+/* Solve                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t iters;           /* CG iterations performed */
+    int32_t status;          /* FE_OK, FE_ENOTCONV or FE_EBREAKDOWN */
+    double relres;           /* ||r_j|| / ||b|| of the recursively updated residual */
+    double true_relres;      /* ||b - A x|| / ||b|| recomputed at exit */
+    double lambda_min_est;   /* extremal Ritz values of diag(A)^-1 A (Lanczos from CG coefficients) */
+    double lambda_max_est;
+} fe_solve_info;
+
+/* Workspace bytes fe_pcg_solve needs for n_rows unknowns. */
+fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes);
+
+/* Jacobi-preconditioned CG on A (device CSR with dinv filled): x holds x0 on
+ * entry and the solution on exit (device, n_rows).  Stops when
+ * ||r_j||_2 <= rtol ||b||_2 or after maxit iterations.  Reductions are
+ * deterministic (fixed-order two-stage sums, no float atomics).  Synchronizes
+ * before returning (info is host memory).  Returns info->status. */
+fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
+                       size_t ws_bytes, fe_solve_info *info, fe_stream stream);
+
+/* y = A x (device vectors).  Enqueues only. */
+fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (for benchmarks)                                            */
+/* ------------------------------------------------------------------------ */
+/* When enabled (process-wide), fe_integrate / fe_scatter record HIP events
+ * around their kernels and fe_pcg_solve around every SpMV launch, on the
+ * call's own stream.  fe_get_timing waits for the recorded events, returns
+ * the accumulated kernel times (milliseconds) and launch counts, and clears
+ * them when reset != 0. */
+typedef struct {
+    double integrate_ms, scatter_ms, spmv_ms;
+    int64_t integrate_calls, scatter_calls, spmv_calls;
+} fe_timing;
+
+fe_status fe_set_timing(int32_t enable);
+fe_status fe_get_timing(fe_timing *out, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE_H */

@@ -1,0 +1,456 @@
+// fe_api.hip -- the extern "C" entry points declared in include/fe.h:
+// argument validation, the mesh handle and its cached set-up, and the
+// dispatch to the kernels of fe_setup / fe_integrate / fe_scatter / fe_solve.
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+static thread_local std::string g_last_error;
+
+fe_status set_error(fe_status st, const std::string &msg)
+{
+    if (st != FE_OK) g_last_error = msg;
+    return st;
+}
+
+fe_status hip_error(hipError_t e, const char *what)
+{
+    return set_error(FE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static hipStream_t as_stream(fe_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------------
+struct PendingTime {
+    hipEvent_t a, b;
+    TimedKind kind;
+};
+static std::atomic<bool> g_timing{false};
+static std::mutex g_timing_mu;
+static std::vector<hipEvent_t> g_event_pool;
+static std::vector<PendingTime> g_pending;
+static double g_ms[3] = {0, 0, 0};
+static int64_t g_calls[3] = {0, 0, 0};
+
+static hipEvent_t pooled_event()
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+bool timing_on() { return g_timing.load(); }
+
+hipEvent_t timing_begin(hipStream_t s)
+{
+    if (!g_timing.load()) return nullptr;
+    hipEvent_t e = pooled_event();
+    if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timing_end(hipEvent_t begin, TimedKind kind, hipStream_t s)
+{
+    if (!begin) return;
+    hipEvent_t e = pooled_event();
+    if (!e || hipEventRecord(e, s) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_pending.push_back({begin, e, kind});
+}
+
+// Corner Jacobians of the order-1 map: at corner v the columns of J are the
+// cell edges leaving that corner.  det J > 0 at every corner is necessary for
+// a valid cell; the kernels check every quadrature point as well.
+static bool corners_valid(int dim, const int *n, const double *v, int64_t &bad_cell)
+{
+    const int64_t nx = n[0] + 1, ny = n[1] + 1;
+    const int64_t ncells = int64_t(n[0]) * n[1] * (dim == 3 ? n[2] : 1);
+    for (int64_t c = 0; c < ncells; c++) {
+        const int64_t e0 = c % n[0], e1 = (c / n[0]) % n[1], e2 = dim == 3 ? c / (int64_t(n[0]) * n[1]) : 0;
+        auto vid = [&](int vv) {
+            return (e0 + (vv & 1)) + nx * ((e1 + ((vv >> 1) & 1)) + ny * (dim == 3 ? e2 + ((vv >> 2) & 1) : 0));
+        };
+        for (int vv = 0; vv < (1 << dim); vv++) {
+            double J[3][3];
+            for (int sdir = 0; sdir < dim; sdir++) {
+                const int64_t hi = vid(vv | (1 << sdir)), lo = vid(vv & ~(1 << sdir));
+                for (int r = 0; r < dim; r++) J[r][sdir] = v[hi * dim + r] - v[lo * dim + r];
+            }
+            double det;
+            if (dim == 2)
+                det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            else
+                det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            if (!(det > 0.0)) {
+                bad_cell = c;
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+static fe_status check_coeff(const fe_mesh m, int32_t order, const fe_coeff *c)
+{
+    if (!m) return set_error(FE_EINVAL, "null mesh");
+    if (!c) return set_error(FE_EINVAL, "null coeff");
+    if (order < 1 || order > kMaxOrder) return set_error(FE_EINVAL, "order must be in 1..4");
+    if (c->problem != FE_POISSON && c->problem != FE_ELASTICITY) return set_error(FE_EINVAL, "unknown problem");
+    if (c->precision < FE_FP64 || c->precision > FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+    if (c->source_kind < FE_SOURCE_NONE || c->source_kind > FE_SOURCE_SINPROD)
+        return set_error(FE_EINVAL, "unknown source kind");
+    if (c->dirichlet_kind != FE_DIRICHLET_ZERO && c->dirichlet_kind != FE_DIRICHLET_AFFINE)
+        return set_error(FE_EINVAL, "unknown dirichlet kind");
+    if (c->dirichlet_faces >= (1u << (2 * m->dim))) return set_error(FE_EINVAL, "dirichlet face bit out of range");
+    if (c->problem == FE_ELASTICITY) {
+        if (!(c->poisson_ratio > -1.0 && c->poisson_ratio < 0.5)) return set_error(FE_EINVAL, "poisson ratio out of range");
+        if (!(c->young > 0.0)) return set_error(FE_EINVAL, "young modulus must be positive");
+    }
+    return FE_OK;
+}
+
+static ProblemArgs problem_args(const fe_coeff *c)
+{
+    ProblemArgs p{};
+    p.problem = c->problem;
+    p.precision = c->precision;
+    if (c->problem == FE_ELASTICITY) {
+        const double E = c->young, nu = c->poisson_ratio;
+        p.lambda = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        p.mu = E / (2.0 * (1.0 + nu));
+    }
+    p.source_kind = c->source_kind;
+    for (int i = 0; i < 3; i++) p.source[i] = c->source[i];
+    p.dirichlet_kind = c->dirichlet_kind;
+    for (int i = 0; i < 12; i++) p.aff[i] = c->dirichlet_affine[i];
+    return p;
+}
+
+static MeshArgs mesh_args(const fe_mesh m)
+{
+    MeshArgs a{};
+    a.x = m->d_xyz;
+    a.y = m->d_xyz + m->nverts;
+    a.z = m->dim == 3 ? m->d_xyz + 2 * m->nverts : nullptr;
+    a.coef = m->d_coef;
+    a.n0 = m->n[0];
+    a.n1 = m->n[1];
+    a.n2 = m->dim == 3 ? m->n[2] : 1;
+    a.status = m->d_status;
+    return a;
+}
+
+// Builds (or reuses) the cached set-up for (order, problem, faces).
+static fe_status ensure_space(fe_mesh m, int32_t order, const fe_coeff *c)
+{
+    const int ncomp = c->problem == FE_ELASTICITY ? m->dim : 1;
+    Space &sp = m->space;
+    if (sp.valid && sp.k == order && sp.ncomp == ncomp && sp.faces == c->dirichlet_faces) return FE_OK;
+    return build_space(m, order, ncomp, c->dirichlet_faces, sp);
+}
+
+static fe_status check_csr(const fe_csr *out, const SpaceArgs &sa, bool need_values)
+{
+    if (!out) return set_error(FE_EINVAL, "null csr");
+    if (out->n_rows != sa.n_rows || out->nnz != sa.nnz)
+        return set_error(FE_EINVAL, "csr sizes differ from fe_assemble_query");
+    if (need_values && sa.n_rows > 0 && (!out->values || !out->rhs || !out->dinv))
+        return set_error(FE_EINVAL, "null csr values/rhs/dinv");
+    return FE_OK;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+const char *fe_last_error(void) { return g_last_error.c_str(); }
+
+int32_t fe_version(void) { return 1; }
+
+fe_status fe_create_mesh(const fe_mesh_desc *desc, fe_mesh *out)
+{
+    if (!desc || !out) return set_error(FE_EINVAL, "null argument");
+    *out = nullptr;
+    const int dim = desc->dim;
+    if (dim != 2 && dim != 3) return set_error(FE_EINVAL, "dim must be 2 or 3");
+    int n[3] = {desc->n[0], desc->n[1], dim == 3 ? desc->n[2] : 1};
+    for (int r = 0; r < dim; r++)
+        if (n[r] < 1 || n[r] > (1 << 20)) return set_error(FE_EINVAL, "cells per axis must be in 1..2^20");
+    const int64_t ncells = int64_t(n[0]) * n[1] * n[2];
+    const int64_t nverts = int64_t(n[0] + 1) * (n[1] + 1) * (dim == 3 ? n[2] + 1 : 1);
+    std::vector<double> uni;
+    const double *v = desc->vertex_xyz;
+    if (!v) {
+        uni.resize(size_t(nverts) * dim);
+        for (int64_t id = 0; id < nverts; id++) {
+            const int64_t i = id % (n[0] + 1), j = (id / (n[0] + 1)) % (n[1] + 1), l = id / (int64_t(n[0] + 1) * (n[1] + 1));
+            uni[id * dim + 0] = double(i) / n[0];
+            uni[id * dim + 1] = double(j) / n[1];
+            if (dim == 3) uni[id * dim + 2] = double(l) / n[2];
+        }
+        v = uni.data();
+    }
+    int64_t bad = -1;
+    if (!corners_valid(dim, n, v, bad))
+        return set_error(FE_EMESH, "cell " + std::to_string(bad) + " has det J <= 0 at a corner");
+    if (desc->cell_coeff)
+        for (int64_t c = 0; c < ncells; c++)
+            if (!std::isfinite(desc->cell_coeff[c])) return set_error(FE_EINVAL, "non-finite cell coefficient");
+    fe_mesh m = new fe_mesh_s();
+    m->dim = dim;
+    for (int r = 0; r < 3; r++) m->n[r] = n[r];
+    m->ncells = ncells;
+    m->nverts = nverts;
+    (void)hipGetDevice(&m->device);
+    std::vector<double> soa(size_t(nverts) * dim);
+    for (int64_t id = 0; id < nverts; id++)
+        for (int r = 0; r < dim; r++) soa[size_t(r) * nverts + id] = v[id * dim + r];
+    std::vector<double> coef(size_t(ncells), 1.0);
+    if (desc->cell_coeff) std::memcpy(coef.data(), desc->cell_coeff, sizeof(double) * ncells);
+    hipError_t e = hipMalloc(&m->d_xyz, sizeof(double) * soa.size());
+    if (e == hipSuccess) e = hipMalloc(&m->d_coef, sizeof(double) * ncells);
+    if (e == hipSuccess) e = hipMalloc(&m->d_status, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(m->d_xyz, soa.data(), sizeof(double) * soa.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_coef, coef.data(), sizeof(double) * ncells, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->d_status, 0, sizeof(int32_t));
+    if (e != hipSuccess) {
+        fe_destroy_mesh(m);
+        return e == hipErrorOutOfMemory ? set_error(FE_ENOMEM, "device allocation failed")
+                                        : hip_error(e, "fe_create_mesh");
+    }
+    *out = m;
+    return FE_OK;
+}
+
+fe_status fe_destroy_mesh(fe_mesh m)
+{
+    if (!m) return FE_OK;
+    (void)hipDeviceSynchronize();
+    free_space(m->space);
+    if (m->d_xyz) (void)hipFree(m->d_xyz);
+    if (m->d_coef) (void)hipFree(m->d_coef);
+    if (m->d_status) (void)hipFree(m->d_status);
+    delete m;
+    return FE_OK;
+}
+
+fe_status fe_set_coefficients(fe_mesh m, const double *cell_coeff)
+{
+    if (!m || !cell_coeff) return set_error(FE_EINVAL, "null argument");
+    for (int64_t c = 0; c < m->ncells; c++)
+        if (!std::isfinite(cell_coeff[c])) return set_error(FE_EINVAL, "non-finite cell coefficient");
+    FE_HIP(hipDeviceSynchronize());
+    FE_HIP(hipMemcpy(m->d_coef, cell_coeff, sizeof(double) * m->ncells, hipMemcpyHostToDevice));
+    return FE_OK;
+}
+
+fe_status fe_assemble_query(fe_mesh m, int32_t order, const fe_coeff *c, int64_t *n_rows, int64_t *nnz,
+                            size_t *ws_bytes)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    const SpaceArgs &sa = m->space.args;
+    if (n_rows) *n_rows = sa.n_rows;
+    if (nnz) *nnz = sa.nnz;
+    if (ws_bytes) *ws_bytes = elem_layout(sa, c->precision).total;
+    return FE_OK;
+}
+
+fe_status fe_element_layout(fe_mesh m, int32_t order, const fe_coeff *c, int32_t *nloc, int32_t *cell_block,
+                            int32_t *elem_bytes, size_t *load_offset)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    const ElemLayout el = elem_layout(m->space.args, c->precision);
+    if (nloc) *nloc = m->space.args.nloc;
+    if (cell_block) *cell_block = el.cb;
+    if (elem_bytes) *elem_bytes = el.elem_bytes;
+    if (load_offset) *load_offset = el.f_offset;
+    return FE_OK;
+}
+
+fe_status fe_pattern(fe_mesh m, int32_t order, const fe_coeff *c, fe_csr *out, fe_stream stream)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    st = check_csr(out, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (!out->rowptr || (m->space.args.nnz > 0 && !out->colind)) return set_error(FE_EINVAL, "null rowptr/colind");
+    m->last_stream = as_stream(stream);
+    return launch_pattern(m->space.args, out->rowptr, out->colind, as_stream(stream));
+}
+
+fe_status fe_integrate(fe_mesh m, int32_t order, const fe_coeff *c, void *ws, size_t ws_bytes, fe_stream stream)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    const SpaceArgs &sa = m->space.args;
+    const ElemLayout el = elem_layout(sa, c->precision);
+    if (!ws || ws_bytes < el.total) return set_error(FE_EINVAL, "workspace too small (see fe_assemble_query)");
+    RefTables rt;
+    ref_tables(order, rt);
+    const ProblemArgs pa = problem_args(c);
+    const MeshArgs ma = mesh_args(m);
+    m->last_stream = as_stream(stream);
+    hipEvent_t t0 = timing_begin(as_stream(stream));
+    st = launch_integrate(sa, ma, pa, rt, el, ws, as_stream(stream));
+    if (st == FE_OK) st = launch_lift(sa, ma, pa, m->space.d_cell_dofs, el, ws, as_stream(stream));
+    timing_end(t0, kTimeIntegrate, as_stream(stream));
+    return st;
+}
+
+fe_status fe_scatter(fe_mesh m, int32_t order, const fe_coeff *c, fe_csr *out, const void *ws, size_t ws_bytes,
+                     fe_stream stream)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    const SpaceArgs &sa = m->space.args;
+    st = check_csr(out, sa, true);
+    if (st != FE_OK) return st;
+    const ElemLayout el = elem_layout(sa, c->precision);
+    if (!ws || ws_bytes < el.total) return set_error(FE_EINVAL, "workspace too small (see fe_assemble_query)");
+    m->last_stream = as_stream(stream);
+    hipEvent_t t0 = timing_begin(as_stream(stream));
+    st = launch_scatter(sa, el, ws, out->values, out->rhs, out->dinv, as_stream(stream));
+    timing_end(t0, kTimeScatter, as_stream(stream));
+    return st;
+}
+
+fe_status fe_assemble(fe_mesh m, int32_t order, const fe_coeff *c, fe_csr *out, void *ws, size_t ws_bytes,
+                      fe_stream stream)
+{
+    fe_status st = fe_integrate(m, order, c, ws, ws_bytes, stream);
+    if (st != FE_OK) return st;
+    return fe_scatter(m, order, c, out, ws, ws_bytes, stream);
+}
+
+fe_status fe_cell_dofs(fe_mesh m, int32_t order, const fe_coeff *c, int32_t *out, fe_stream stream)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    if (!out) return set_error(FE_EINVAL, "null output");
+    const SpaceArgs &sa = m->space.args;
+    FE_HIP(hipMemcpyAsync(out, m->space.d_cell_dofs, sizeof(int32_t) * size_t(sa.ncells) * sa.nloc,
+                          hipMemcpyDeviceToDevice, as_stream(stream)));
+    return FE_OK;
+}
+
+fe_status fe_permutation(fe_mesh m, int32_t order, const fe_coeff *c, int64_t *perm, fe_stream stream)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    if (!perm) return set_error(FE_EINVAL, "null output");
+    return launch_permutation(m->space.args, mesh_args(m), perm, as_stream(stream));
+}
+
+fe_status fe_get_status(fe_mesh m)
+{
+    if (!m) return set_error(FE_EINVAL, "null mesh");
+    FE_HIP(hipStreamSynchronize(m->last_stream));
+    int32_t h = 0;
+    FE_HIP(hipMemcpy(&h, m->d_status, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (h) {
+        FE_HIP(hipMemset(m->d_status, 0, sizeof(int32_t)));
+        return set_error(FE_EMESH, "det J <= 0 at a quadrature point");
+    }
+    return FE_OK;
+}
+
+fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes)
+{
+    if (n_rows < 0 || !ws_bytes) return set_error(FE_EINVAL, "bad argument");
+    *ws_bytes = pcg_ws_bytes(n_rows);
+    return FE_OK;
+}
+
+fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
+                       size_t ws_bytes, fe_solve_info *info, fe_stream stream)
+{
+    if (!A || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    if (!A->rowptr || !A->colind || !A->values || !A->dinv) return set_error(FE_EINVAL, "incomplete csr");
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    return pcg_solve(A, b, x, rtol, maxit, ws, ws_bytes, info, as_stream(stream));
+}
+
+fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream)
+{
+    if (!A || !x || !y || !A->rowptr || !A->colind || !A->values) return set_error(FE_EINVAL, "null argument");
+    const double npr = A->n_rows > 0 ? double(A->nnz) / double(A->n_rows) : 1.0;
+    return launch_spmv(A->n_rows, A->rowptr, A->colind, A->values, x, y, npr, as_stream(stream));
+}
+
+fe_status fe_set_timing(int32_t enable)
+{
+    g_timing.store(enable != 0);
+    return FE_OK;
+}
+
+fe_status fe_get_timing(fe_timing *out, int32_t reset)
+{
+    std::vector<PendingTime> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        pend.swap(g_pending);
+    }
+    fe_status st = FE_OK;
+    for (const PendingTime &p : pend) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) st = hip_error(e, "fe_get_timing");
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        g_ms[p.kind] += ms;
+        g_calls[p.kind] += 1;
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (out) {
+        out->integrate_ms = g_ms[0];
+        out->scatter_ms = g_ms[1];
+        out->spmv_ms = g_ms[2];
+        out->integrate_calls = g_calls[0];
+        out->scatter_calls = g_calls[1];
+        out->spmv_calls = g_calls[2];
+    }
+    if (reset)
+        for (int i = 0; i < 3; i++) {
+            g_ms[i] = 0;
+            g_calls[i] = 0;
+        }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// fe_internal.h -- internal declarations of the HIP finite element library.
+// Not part of the ABI (the ABI is include/fe.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fe.h"
+
+namespace fe {
+
+constexpr int kMaxOrder = 4;
+constexpr int kMaxQ1 = kMaxOrder + 1;  // Gauss points per direction (k + 1)
+
+// ---------------------------------------------------------------------------
+// Error handling (thread-local text behind fe_last_error)
+// ---------------------------------------------------------------------------
+fe_status set_error(fe_status st, const std::string &msg);
+fe_status hip_error(hipError_t e, const char *what);
+
+#define FE_HIP(call)                                                   \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return ::fe::hip_error(_e, #call);       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// One axis of the structured node lattice of order k.
+// Node indices run over 0..N (N = n k).  Free indices are [lo, hi] (a
+// Dirichlet face removes the end node).  For every free index i the columns
+// of its row are the node interval [cl, cl + w) clipped to the free range;
+// P is the prefix sum of w over free indices below i.  These three numbers
+// are all the cell-to-nnz map needs along one axis: the sparsity pattern and
+// every element entry's position are tensor products of them.
+// ---------------------------------------------------------------------------
+struct AxisTab {
+    const int64_t *cl;  // device, f entries (absolute node index)
+    const int64_t *w;   // device, f entries
+    const int64_t *P;   // device, f entries
+    int64_t lo, f, N, T;  // first free index, number of free indices, last node index, sum of w
+    int32_t n;            // cells along the axis
+};
+
+// Everything kernels need about a (mesh, order, problem, Dirichlet faces).
+struct SpaceArgs {
+    int32_t dim, k, ncomp, nn, nloc;
+    AxisTab ax[3];
+    int64_t ncells;
+    int64_t n_rows, nnz;
+};
+
+// Device-side view of the mesh.
+struct MeshArgs {
+    const double *x, *y, *z;  // vertex coordinates (SoA)
+    const double *coef;       // per cell
+    int32_t n0, n1, n2;       // cells per axis (n2 = 1 in 2D)
+    int32_t *status;          // device status word (bit 0: det J <= 0 seen)
+};
+
+// Problem parameters used inside kernels.
+struct ProblemArgs {
+    int32_t problem;  // 0 Poisson, 1 elasticity
+    int32_t precision;
+    double lambda, mu;
+    int32_t source_kind;
+    double source[3];
+    int32_t dirichlet_kind;
+    double aff[12];
+};
+
+// 1D reference data: Gauss points/weights on [0,1] and Lagrange values /
+// derivatives of the equidistant basis at those points, table[i * nq1 + q].
+struct RefTables {
+    double gx[kMaxQ1], gw[kMaxQ1];
+    double L[kMaxQ1 * kMaxQ1], D[kMaxQ1 * kMaxQ1];
+};
+
+// Layout of the element workspace written by K3 and read by K5.
+struct ElemLayout {
+    int32_t cb;          // cells per block of the blocked layout
+    int32_t elem_bytes;  // 8 (double) or 4 (float)
+    size_t e_bytes;      // bytes of E (padded to 256)
+    size_t f_offset;     // byte offset of F
+    size_t total;        // bytes of the whole workspace
+};
+
+// Cached order-dependent set-up of a mesh.
+struct Space {
+    int32_t k = 0, ncomp = 0;
+    uint32_t faces = 0xffffffffu;
+    SpaceArgs args{};
+    int64_t *d_axis = nullptr;     // 3 axes x {cl, w, P} device buffer
+    int32_t *d_cell_dofs = nullptr;
+    bool valid = false;
+};
+
+}  // namespace fe
+
+struct fe_mesh_s {
+    int32_t dim = 0;
+    int32_t n[3] = {1, 1, 1};
+    int64_t ncells = 0, nverts = 0;
+    double *d_xyz = nullptr;  // SoA: x | y | z
+    double *d_coef = nullptr;
+    int32_t *d_status = nullptr;
+    int32_t device = 0;
+    hipStream_t last_stream = nullptr;
+    fe::Space space;
+};
+
+namespace fe {
+
+// Set-up (fe_setup.hip)
+fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp);
+void free_space(Space &sp);
+fe_status launch_pattern(const SpaceArgs &sa, int64_t *rowptr, int32_t *colind, hipStream_t s);
+fe_status launch_cell_dofs(const SpaceArgs &sa, const MeshArgs &ma, int32_t *out, hipStream_t s);
+fe_status launch_permutation(const SpaceArgs &sa, const MeshArgs &ma, int64_t *perm, hipStream_t s);
+void ref_tables(int k, RefTables &t);
+
+// Integration (fe_integrate.hip)
+ElemLayout elem_layout(const SpaceArgs &sa, int precision);
+fe_status launch_integrate(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                           const ElemLayout &el, void *ws, hipStream_t s);
+fe_status launch_lift(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const int32_t *cell_dofs,
+                      const ElemLayout &el, void *ws, hipStream_t s);
+
+// Scatter (fe_scatter.hip)
+fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *ws, double *values, double *rhs,
+                         double *dinv, hipStream_t s);
+
+// Solver (fe_solve.hip)
+size_t pcg_ws_bytes(int64_t n);
+fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
+                      double *y, double nnz_per_row, hipStream_t s);
+fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
+                    fe_solve_info *info, hipStream_t s);
+
+// Kernel timing (fe_set_timing / fe_get_timing): event pairs recorded on the
+// launching stream around timed kernels.
+enum TimedKind { kTimeIntegrate = 0, kTimeScatter = 1, kTimeSpmv = 2 };
+bool timing_on();
+hipEvent_t timing_begin(hipStream_t s);                    // nullptr when timing is off
+void timing_end(hipEvent_t begin, TimedKind kind, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Device helpers shared by the kernels
+// ---------------------------------------------------------------------------
+// Cells along one axis that contain both node indices i and j (at most 2):
+// e in [max(ceil(max(i,j)/k) - 1, 0), min(floor(min(i,j)/k), n - 1)].
+__device__ __forceinline__ void shared_cells(int64_t i, int64_t j, int32_t k, int32_t n, int64_t &elo,
+                                             int64_t &ehi)
+{
+    int64_t mx = i > j ? i : j, mn = i < j ? i : j;
+    int64_t a = (mx + k - 1) / k - 1;
+    elo = a > 0 ? a : 0;
+    int64_t b = mn / k;
+    ehi = b < n - 1 ? b : n - 1;
+}
+
+// Map a linear block id so that consecutive logical blocks run on the same
+// XCD (the hardware dispatches block b to XCD b % 8).
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks)
+{
+    const int64_t nx = 8;
+    if (nblocks < nx) return bid;
+    int64_t per = nblocks / nx, rem = nblocks % nx;
+    int64_t x = bid % nx, j = bid / nx;
+    // XCD x owns logical blocks [start_x, start_x + per + (x < rem))
+    int64_t start = x * per + (x < rem ? x : rem);
+    return start + j;
+}
+
+}  // namespace fe

@@ -1,0 +1,303 @@
+"""Thin ctypes binding of the C ABI in include/fe.h (argument marshalling only).
+
+Every step of the finite element path runs in the HIP kernels of libfe.so;
+PyTorch is used here only to own device buffers and to provide streams.  If the
+library is missing the import fails loudly: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfe.so")
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EMESH, FE_ENOTCONV, FE_EBREAKDOWN, FE_EDEVICE = range(7)
+STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EMESH", 4: "FE_ENOTCONV",
+                5: "FE_EBREAKDOWN", 6: "FE_EDEVICE"}
+FE_POISSON, FE_ELASTICITY = 0, 1
+FE_FP64, FE_FP32, FE_FP16, FE_BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FE_FP64, "fp32": FE_FP32, "fp16": FE_FP16, "bf16": FE_BF16}
+FE_SOURCE_NONE, FE_SOURCE_CONST, FE_SOURCE_SINPROD = 0, 1, 2
+FE_DIRICHLET_ZERO, FE_DIRICHLET_AFFINE = 0, 1
+
+# every entry point include/fe.h declares
+EXPORTS = [
+    "fe_last_error", "fe_version", "fe_create_mesh", "fe_destroy_mesh", "fe_set_coefficients",
+    "fe_assemble_query", "fe_pattern", "fe_assemble", "fe_integrate", "fe_element_layout", "fe_scatter",
+    "fe_cell_dofs", "fe_permutation", "fe_get_status", "fe_pcg_query", "fe_pcg_solve", "fe_spmv",
+    "fe_set_timing", "fe_get_timing",
+]
+
+_c = ctypes
+_P = _c.c_void_p
+
+
+class FeError(RuntimeError):
+    def __init__(self, status, where, text):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {text}")
+
+
+class MeshDesc(_c.Structure):
+    _fields_ = [("dim", _c.c_int32), ("n", _c.c_int32 * 3), ("vertex_xyz", _P), ("cell_coeff", _P)]
+
+
+class Coeff(_c.Structure):
+    _fields_ = [("problem", _c.c_int32), ("precision", _c.c_int32), ("young", _c.c_double),
+                ("poisson_ratio", _c.c_double), ("source_kind", _c.c_int32), ("source", _c.c_double * 3),
+                ("dirichlet_faces", _c.c_uint32), ("dirichlet_kind", _c.c_int32),
+                ("dirichlet_affine", _c.c_double * 12)]
+
+
+class Csr(_c.Structure):
+    _fields_ = [("n_rows", _c.c_int64), ("nnz", _c.c_int64), ("rowptr", _P), ("colind", _P), ("values", _P),
+                ("rhs", _P), ("dinv", _P)]
+
+
+class SolveInfo(_c.Structure):
+    _fields_ = [("iters", _c.c_int32), ("status", _c.c_int32), ("relres", _c.c_double),
+                ("true_relres", _c.c_double), ("lambda_min_est", _c.c_double), ("lambda_max_est", _c.c_double)]
+
+
+class Timing(_c.Structure):
+    _fields_ = [("integrate_ms", _c.c_double), ("scatter_ms", _c.c_double), ("spmv_ms", _c.c_double),
+                ("integrate_calls", _c.c_int64), ("scatter_calls", _c.c_int64), ("spmv_calls", _c.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfe.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch first: libfe.so then binds to the HIP runtime torch already
+        # loaded (same soname), so the process holds a single HIP runtime
+        import torch  # noqa: F401
+        L = _c.CDLL(LIB_PATH)
+        L.fe_last_error.restype = _c.c_char_p
+        L.fe_version.restype = _c.c_int32
+        sigs = {
+            "fe_create_mesh": [_c.POINTER(MeshDesc), _c.POINTER(_P)],
+            "fe_destroy_mesh": [_P],
+            "fe_set_coefficients": [_P, _P],
+            "fe_assemble_query": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_int64),
+                                  _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
+            "fe_pattern": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P],
+            "fe_assemble": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_integrate": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _c.c_size_t, _P],
+            "fe_element_layout": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_int32),
+                                  _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_size_t)],
+            "fe_scatter": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_cell_dofs": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _P],
+            "fe_permutation": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _P],
+            "fe_get_status": [_P],
+            "fe_pcg_query": [_c.c_int64, _c.POINTER(_c.c_size_t)],
+            "fe_pcg_solve": [_c.POINTER(Csr), _P, _P, _c.c_double, _c.c_int32, _P, _c.c_size_t,
+                             _c.POINTER(SolveInfo), _P],
+            "fe_spmv": [_c.POINTER(Csr), _P, _P, _P],
+            "fe_set_timing": [_c.c_int32],
+            "fe_get_timing": [_c.POINTER(Timing), _c.c_int32],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _c.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, where):
+    if st != FE_OK:
+        raise FeError(st, where, lib().fe_last_error().decode())
+    return st
+
+
+def _stream(stream):
+    """hipStream_t of a torch stream (None: torch's current stream)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _P(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else _P(t.data_ptr())
+
+
+def make_coeff(problem="poisson", precision="fp64", young=1.0, nu=0.3, source_kind=FE_SOURCE_NONE,
+               source=(0.0, 0.0, 0.0), faces=None, dim=3, dirichlet_kind=FE_DIRICHLET_ZERO, affine=None):
+    c = Coeff()
+    c.problem = FE_ELASTICITY if problem == "elasticity" else FE_POISSON
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.young, c.poisson_ratio = float(young), float(nu)
+    c.source_kind = int(source_kind)
+    src = list(source) + [0.0] * (3 - len(source))
+    for i in range(3):
+        c.source[i] = float(src[i])
+    c.dirichlet_faces = ((1 << (2 * dim)) - 1) if faces is None else int(faces)
+    c.dirichlet_kind = int(dirichlet_kind)
+    aff = list(affine) if affine is not None else []
+    aff = aff + [0.0] * (12 - len(aff))
+    for i in range(12):
+        c.dirichlet_affine[i] = float(aff[i])
+    return c
+
+
+class Mesh:
+    """Owning wrapper of an fe_mesh handle."""
+
+    def __init__(self, dim, n, vertices=None, coeff=None):
+        import numpy as np
+        d = MeshDesc()
+        d.dim = int(dim)
+        n = list(n) if hasattr(n, "__len__") else [int(n)] * dim
+        n = n + [1] * (3 - len(n))
+        for i in range(3):
+            d.n[i] = int(n[i])
+        self._v = None if vertices is None else np.ascontiguousarray(vertices, dtype=np.float64)
+        self._k = None if coeff is None else np.ascontiguousarray(coeff, dtype=np.float64)
+        d.vertex_xyz = None if self._v is None else self._v.ctypes.data_as(_P)
+        d.cell_coeff = None if self._k is None else self._k.ctypes.data_as(_P)
+        h = _P()
+        _check(lib().fe_create_mesh(_c.byref(d), _c.byref(h)), "fe_create_mesh")
+        self.handle = h
+        self.dim = int(dim)
+        self.n = n[:dim]
+        self._v = self._k = None
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().fe_destroy_mesh(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_mesh(dim, n, vertices=None, coeff=None):
+    return Mesh(dim, n, vertices, coeff)
+
+
+def set_coefficients(mesh, coeff):
+    import numpy as np
+    k = np.ascontiguousarray(coeff, dtype=np.float64)
+    _check(lib().fe_set_coefficients(mesh.handle, k.ctypes.data_as(_P)), "fe_set_coefficients")
+
+
+def assemble_query(mesh, order, coeff):
+    nr, nz, ws = _c.c_int64(), _c.c_int64(), _c.c_size_t()
+    _check(lib().fe_assemble_query(mesh.handle, int(order), _c.byref(coeff), _c.byref(nr), _c.byref(nz),
+                                   _c.byref(ws)), "fe_assemble_query")
+    return nr.value, nz.value, ws.value
+
+
+def element_layout(mesh, order, coeff):
+    nloc, cb, eb, off = _c.c_int32(), _c.c_int32(), _c.c_int32(), _c.c_size_t()
+    _check(lib().fe_element_layout(mesh.handle, int(order), _c.byref(coeff), _c.byref(nloc), _c.byref(cb),
+                                   _c.byref(eb), _c.byref(off)), "fe_element_layout")
+    return nloc.value, cb.value, eb.value, off.value
+
+
+def csr_struct(n_rows, nnz, rowptr=None, colind=None, values=None, rhs=None, dinv=None):
+    c = Csr()
+    c.n_rows, c.nnz = int(n_rows), int(nnz)
+    c.rowptr, c.colind, c.values, c.rhs, c.dinv = (_ptr(rowptr), _ptr(colind), _ptr(values), _ptr(rhs),
+                                                   _ptr(dinv))
+    return c
+
+
+def pattern(mesh, order, coeff, csr, stream=None):
+    _check(lib().fe_pattern(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _stream(stream)), "fe_pattern")
+
+
+def assemble(mesh, order, coeff, csr, ws, stream=None):
+    _check(lib().fe_assemble(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream(stream)), "fe_assemble")
+
+
+def integrate(mesh, order, coeff, ws, stream=None):
+    _check(lib().fe_integrate(mesh.handle, int(order), _c.byref(coeff), _ptr(ws), ws.numel() * ws.element_size(),
+                              _stream(stream)), "fe_integrate")
+
+
+def scatter(mesh, order, coeff, csr, ws, stream=None):
+    _check(lib().fe_scatter(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(ws),
+                            ws.numel() * ws.element_size(), _stream(stream)), "fe_scatter")
+
+
+def cell_dofs(mesh, order, coeff, out, stream=None):
+    _check(lib().fe_cell_dofs(mesh.handle, int(order), _c.byref(coeff), _ptr(out), _stream(stream)), "fe_cell_dofs")
+
+
+def permutation(mesh, order, coeff, out, stream=None):
+    _check(lib().fe_permutation(mesh.handle, int(order), _c.byref(coeff), _ptr(out), _stream(stream)),
+           "fe_permutation")
+
+
+def get_status(mesh):
+    return lib().fe_get_status(mesh.handle)
+
+
+def pcg_query(n_rows):
+    ws = _c.c_size_t()
+    _check(lib().fe_pcg_query(int(n_rows), _c.byref(ws)), "fe_pcg_query")
+    return ws.value
+
+
+def pcg_solve(csr, b, x, rtol, maxit, ws, stream=None, check=True):
+    """Returns a dict with iters, status, relres, true_relres, lambda_min_est, lambda_max_est."""
+    info = SolveInfo()
+    st = lib().fe_pcg_solve(_c.byref(csr), _ptr(b), _ptr(x), float(rtol), int(maxit), _ptr(ws),
+                            ws.numel() * ws.element_size(), _c.byref(info), _stream(stream))
+    out = dict(iters=info.iters, status=info.status, relres=info.relres, true_relres=info.true_relres,
+               lambda_min_est=info.lambda_min_est, lambda_max_est=info.lambda_max_est)
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_pcg_solve")
+    return out
+
+
+def spmv(csr, x, y, stream=None):
+    _check(lib().fe_spmv(_c.byref(csr), _ptr(x), _ptr(y), _stream(stream)), "fe_spmv")
+
+
+def set_timing(enable):
+    _check(lib().fe_set_timing(1 if enable else 0), "fe_set_timing")
+
+
+def get_timing(reset=True):
+    t = Timing()
+    _check(lib().fe_get_timing(_c.byref(t), 1 if reset else 0), "fe_get_timing")
+    return {f: getattr(t, f) for f, _ in Timing._fields_}
+
+
+class Assembly:
+    """Device buffers (torch tensors) of one assembled system plus its workspace."""
+
+    def __init__(self, mesh, order, coeff, device="cuda"):
+        import torch
+        self.mesh, self.order, self.coeff = mesh, int(order), coeff
+        self.n_rows, self.nnz, ws_bytes = assemble_query(mesh, order, coeff)
+        dev = torch.device(device)
+        self.rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=dev)
+        self.colind = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        self.values = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        self.rhs = torch.empty(max(self.n_rows, 1), dtype=torch.float64, device=dev)
+        self.dinv = torch.empty(max(self.n_rows, 1), dtype=torch.float64, device=dev)
+        self.ws = torch.empty(max(ws_bytes, 8), dtype=torch.uint8, device=dev)
+        self.csr = csr_struct(self.n_rows, self.nnz, self.rowptr, self.colind, self.values, self.rhs, self.dinv)
+
+    def pattern(self, stream=None):
+        pattern(self.mesh, self.order, self.coeff, self.csr, stream)
+
+    def assemble(self, stream=None):
+        assemble(self.mesh, self.order, self.coeff, self.csr, self.ws, stream)
+
+    def integrate(self, stream=None):
+        integrate(self.mesh, self.order, self.coeff, self.ws, stream)
+
+    def scatter(self, stream=None):
+        scatter(self.mesh, self.order, self.coeff, self.csr, self.ws, stream)

@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/fe.h declares, and rejects invalid arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1708_01773_amd import fe as F
+from fe_inputs import structured_vertices
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "fe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fe_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert header_functions() == sorted(F.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(F.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(L, name), name
+    assert F.lib().fe_version() >= 1
+
+
+def test_struct_sizes_match_header_layout():
+    # int32 dim, int32 n[3], two pointers
+    assert ctypes.sizeof(F.MeshDesc) == 32
+    assert ctypes.sizeof(F.Csr) == 56
+    assert ctypes.sizeof(F.SolveInfo) == 40
+    assert F.Coeff.dirichlet_affine.offset + 96 == ctypes.sizeof(F.Coeff)
+
+
+def test_invalid_mesh_arguments_rejected_on_host():
+    d = F.MeshDesc()
+    d.dim = 4
+    h = ctypes.c_void_p()
+    assert F.lib().fe_create_mesh(ctypes.byref(d), ctypes.byref(h)) == F.FE_EINVAL
+    assert "dim" in F.lib().fe_last_error().decode()
+    d.dim = 3
+    d.n[0], d.n[1], d.n[2] = 2, 0, 2
+    assert F.lib().fe_create_mesh(ctypes.byref(d), ctypes.byref(h)) == F.FE_EINVAL
+    with pytest.raises(F.FeError):
+        F.create_mesh(3, [2, 2, 2], coeff=np.array([1.0] * 7 + [np.nan]))
+
+
+def test_inverted_cell_rejected_on_host():
+    v = structured_vertices(3, 2)
+    # move the centre vertex far beyond its neighbours so a corner Jacobian flips
+    centre = 1 + 3 * (1 + 3 * 1)
+    v[centre] = [1.2, 1.2, 1.2]
+    with pytest.raises(F.FeError) as e:
+        F.create_mesh(3, [2, 2, 2], v)
+    assert e.value.status == F.FE_EMESH
+
+
+def test_null_and_bad_arguments_rejected():
+    L = F.lib()
+    c = F.make_coeff()
+    n_rows, nnz, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    assert L.fe_assemble_query(None, 1, ctypes.byref(c), ctypes.byref(n_rows), ctypes.byref(nnz),
+                               ctypes.byref(ws)) == F.FE_EINVAL
+    assert L.fe_pcg_query(-1, ctypes.byref(ws)) == F.FE_EINVAL
+    assert L.fe_pcg_query(1000, ctypes.byref(ws)) == F.FE_OK and ws.value > 3 * 8000
+    assert L.fe_pcg_solve(None, None, None, 1e-8, 10, None, 0, None, None) == F.FE_EINVAL
+    assert L.fe_spmv(None, None, None, None) == F.FE_EINVAL

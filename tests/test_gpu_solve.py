@@ -1,0 +1,119 @@
+"""GPU parity of the CSR SpMV (K7) and Jacobi-PCG (K8) against the oracle."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle as O
+from paper_1708_01773_amd import fe as F
+from tests.gpu_util import Pair, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_csr_from_oracle(S):
+    rowptr = torch.from_numpy(S.rowptr).cuda()
+    colind = torch.from_numpy(S.colind.astype(np.int32)).cuda()
+    values = torch.from_numpy(S.values).cuda()
+    diag = S.scipy().diagonal()
+    dinv = torch.from_numpy(1.0 / diag).cuda()
+    rhs = torch.from_numpy(S.rhs).cuda()
+    return F.csr_struct(S.nfree, S.nnz, rowptr, colind, values, rhs, dinv), (rowptr, colind, values, rhs, dinv)
+
+
+@pytest.mark.parametrize("dim,n,k,prob", [(2, [32, 32], 1, "poisson"), (3, [7, 6, 5], 1, "poisson"),
+                                          (3, [3, 3, 2], 3, "poisson"), (3, [3, 2, 2], 2, "elasticity")])
+def test_spmv_matches_oracle(dim, n, k, prob):
+    say(f"[spmv] dim={dim} n={n} k={k} {prob}")
+    pair = Pair(dim, n, k, prob)
+    A = pair.gpu_assembly()
+    x = np.random.Generator(np.random.PCG64(3)).standard_normal(A.n_rows)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty_like(xd)
+    F.spmv(A.csr, xd, y)
+    torch.cuda.synchronize()
+    S = pair.system
+    yo = O.spmv(S.rowptr, S.colind, S.values, x)
+    # same matrix (bit-exact structure, values to 1e-12), different summation order
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x))
+    assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+
+
+def test_c1_solution_matches_oracle():
+    """configs[0]: 2D Poisson, 32x32 Q1, k = 1, sin-product load, u = 0 on the
+    boundary, FP64 CSR + Jacobi-PCG to rtol 1e-10; then both solved to
+    stagnation (rtol 1e-14) must agree to 1e-12."""
+    say("[pcg] C1")
+    pair = Pair(2, [32, 32], 1, lognormal=False, jitter=0.0, source_kind=2, source=(1.0,))
+    A = pair.gpu_assembly()
+    S = pair.system
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    info = F.pcg_solve(A.csr, A.rhs, x, 1e-10, 1000, ws)
+    say(info)
+    assert info["status"] == F.FE_OK and info["relres"] <= 1e-10
+    orc = O.pcg(S.rowptr, S.colind, S.values, S.rhs, 1e-10, 1000)
+    assert abs(info["iters"] - orc["iters"]) <= 2
+    xd = spla.spsolve(S.scipy().tocsc(), S.rhs)
+    kappa = info["lambda_max_est"] / info["lambda_min_est"]
+    assert rel(x.cpu().numpy(), xd) <= 10 * kappa * 1e-10
+    x.zero_()
+    info = F.pcg_solve(A.csr, A.rhs, x, 1e-14, 5000, ws)
+    orc = O.pcg(S.rowptr, S.colind, S.values, S.rhs, 1e-14, 5000)
+    assert info["status"] == F.FE_OK and orc["status"] == 0
+    assert rel(x.cpu().numpy(), orc["x"]) <= 1e-12
+    # discretisation error of the manufactured solution
+    err = O.l2_error(pair.P, pair.v, S.cell_dofs, x.cpu().numpy(), 4, 1, [1.0])
+    assert err < 2e-3
+
+
+@pytest.mark.parametrize("dim,n,k,prob", [(3, [6, 5, 4], 1, "poisson"), (3, [3, 3, 3], 2, "poisson"),
+                                          (3, [3, 2, 2], 2, "elasticity"), (2, [4, 3], 4, "poisson")])
+def test_pcg_solution_matches_direct_solve(dim, n, k, prob):
+    say(f"[pcg] dim={dim} n={n} k={k} {prob}")
+    pair = Pair(dim, n, k, prob, source=(1.0, 0.5, -1.0))
+    A = pair.gpu_assembly()
+    S = pair.system
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    info = F.pcg_solve(A.csr, A.rhs, x, 1e-14, 20000, ws)
+    say(info)
+    assert info["status"] == F.FE_OK
+    xd = spla.spsolve(S.scipy().tocsc(), S.rhs)
+    kappa = info["lambda_max_est"] / info["lambda_min_est"]
+    assert rel(x.cpu().numpy(), xd) <= max(1e-11, 100 * kappa * 1e-14)
+    # Lanczos estimates lie inside the spectrum of D^-1/2 A D^-1/2
+    Ad = S.dense()
+    d = 1.0 / np.sqrt(np.diag(Ad))
+    ev = np.linalg.eigvalsh(Ad * d[:, None] * d[None, :])
+    assert ev[0] * (1 - 1e-8) <= info["lambda_min_est"] <= info["lambda_max_est"] <= ev[-1] * (1 + 1e-8)
+    # the true residual is reported
+    assert info["true_relres"] <= 1e-12
+
+
+def test_pcg_is_deterministic_and_reports_failures():
+    pair = Pair(3, [5, 5, 5], 1)
+    A = pair.gpu_assembly()
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    x1 = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    i1 = F.pcg_solve(A.csr, A.rhs, x1, 1e-12, 1000, ws)
+    i2 = F.pcg_solve(A.csr, A.rhs, x2, 1e-12, 1000, ws)
+    assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+    x1.zero_()
+    i3 = F.pcg_solve(A.csr, A.rhs, x1, 1e-12, 3, ws)
+    assert i3["status"] == F.FE_ENOTCONV and i3["iters"] == 3
+    # an indefinite diagonal matrix breaks CG down
+    rowptr = torch.tensor([0, 1, 2], dtype=torch.int64, device="cuda")
+    colind = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    vals = torch.tensor([1.0, -1.0], dtype=torch.float64, device="cuda")
+    dinv = torch.tensor([1.0, 1.0], dtype=torch.float64, device="cuda")
+    b = torch.tensor([1.0, 1.0], dtype=torch.float64, device="cuda")
+    csr = F.csr_struct(2, 2, rowptr, colind, vals, None, dinv)
+    xb = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ws2 = torch.empty(F.pcg_query(2), dtype=torch.uint8, device="cuda")
+    i4 = F.pcg_solve(csr, b, xb, 1e-12, 10, ws2)
+    assert i4["status"] == F.FE_EBREAKDOWN
+    # initial guess = exact solution: converged at iteration 0
+    i5 = F.pcg_solve(A.csr, A.rhs, x2, 1e-10, 10, ws)
+    assert i5["status"] == F.FE_OK and i5["iters"] == 0
