@@ -64,6 +64,23 @@ hipEvent_t timing_begin(hipStream_t s)
     return e;
 }
 
+hipEvent_t timing_mark(hipStream_t s) { return timing_begin(s); }
+
+void timing_commit(hipEvent_t a, hipEvent_t b, TimedKind kind)
+{
+    if (!a || !b) return;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_pending.push_back({a, b, kind});
+}
+
+void timing_release(hipEvent_t e)
+{
+    if (!e) return;
+    (void)hipEventSynchronize(e);
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_event_pool.push_back(e);
+}
+
 void timing_end(hipEvent_t begin, TimedKind kind, hipStream_t s)
 {
     if (!begin) return;

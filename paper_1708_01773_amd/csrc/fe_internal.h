@@ -144,6 +144,9 @@ enum TimedKind { kTimeIntegrate = 0, kTimeScatter = 1, kTimeSpmv = 2 };
 bool timing_on();
 hipEvent_t timing_begin(hipStream_t s);                    // nullptr when timing is off
 void timing_end(hipEvent_t begin, TimedKind kind, hipStream_t s);
+hipEvent_t timing_mark(hipStream_t s);                     // records a pooled event (nullptr when off)
+void timing_commit(hipEvent_t a, hipEvent_t b, TimedKind kind);
+void timing_release(hipEvent_t e);
 
 // ---------------------------------------------------------------------------
 // Device helpers shared by the kernels

@@ -2,15 +2,26 @@
 // gradients (the CG the paper lists among its iterative solvers, Sect. 12;
 // the preconditioner M = diag(A)).
 //
-// Per iteration three kernels run: q = A p with the partial sums of p.q,
-// x/r updates with the partial sums of r.z and r.r (z = M^-1 r is never
-// stored), and p = z + beta p.  Every reduction is two-stage and
-// deterministic: a fixed grid writes one partial per block (wave shuffles,
-// then LDS, in a fixed order), and the last block to finish -- detected with
-// an integer counter, never a float atomic -- sums the partials in index
-// order and updates the solver state in device memory.  A device-side "done"
-// flag makes the remaining kernels of a chunk exit at once, so the host reads
-// the state only once per chunk of iterations.
+// Iteration j runs three kernels:
+//   spmv(j):  q = A p                      partials of p.q
+//   upd(j):   alpha = rho_j / p.q;  x += alpha p;  r -= alpha q
+//                                          partials of r.z and r.r (z = M^-1 r, never stored)
+//   dir(j):   beta = rho_{j+1} / rho_j;  stop if ||r|| <= rtol ||b||;  p = z + beta p
+// Reductions are deterministic and use no atomics and no fences: every block
+// writes one partial with a plain store, and every block of the *next* kernel
+// sums all partials in index order (the kernel boundary makes them visible),
+// so all blocks agree bit for bit on the scalar.  Scalars that outlive a
+// kernel (rho, the stop flag) are written by block 0 into slots indexed by
+// the iteration parity, which the host passes in, so no kernel reads a slot
+// it also writes.  A device-side stop flag makes the remaining kernels of a
+// chunk of iterations exit at once; the host reads the state once per chunk.
+//
+// SpMV: rows with few non-zeros use a wave-level CSR-stream scheme (a wave
+// stages the products of a run of rows in LDS with coalesced loads, then
+// L lanes per row sum them); long rows use one wave per row straight from
+// memory.  A row is always summed in the same lane-strided order followed by
+// the same butterfly, so the result does not depend on the path taken.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -19,29 +30,40 @@
 
 namespace fe {
 
-constexpr int kBlock = 256;
-constexpr int kMaxBlocks = 2048;
-constexpr int kHist = 4096;  // CG coefficients kept for the Lanczos estimates
+constexpr int kBlock = 512;
+constexpr int kWaves = kBlock / 64;
+constexpr int kGrid = 1024;     // blocks of every solver kernel (each owns a contiguous chunk)
+constexpr int kHist = 4096;     // CG coefficients kept for the Lanczos estimates
+constexpr int kWaveCap = 256;   // products staged in LDS per wave (2 KB)
 
 struct PcgState {
-    double rho, pq, alpha, beta, rr, bb, rtol2, true_rr;
-    int32_t iter, done, status, maxit;
-    uint32_t counter[4];
+    double rho[2];  // rho_j in slot j & 1
+    double bb, rr, true_rr;
+    int32_t iter, done, status, pad;
 };
 
 struct PcgWs {
     PcgState *st;
-    double *part;  // 3 * kMaxBlocks partial sums
-    double *hist;  // 2 * kHist (alpha, beta)
+    double *p1;    // kGrid partials of p.q
+    double *p2;    // 2 x kGrid partials of r.z, r.r
+    double *p3;    // 3 x kGrid partials of the initial r.z, r.r, b.b (and the final residual)
+    double *hist;  // 2 x kHist (alpha, beta)
     double *r, *p, *q;
+};
+
+// How a CSR matrix is traversed.
+struct SpmvPlan {
+    int mode;  // 0: wave-level CSR-stream, 1: wave per row
+    int rpb;   // rows per wave-iteration (stream mode)
+    int lanes; // lanes per row
 };
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t pcg_ws_bytes(int64_t n)
 {
-    return align256(sizeof(PcgState)) + align256(3 * kMaxBlocks * sizeof(double)) +
-           align256(2 * kHist * sizeof(double)) + 3 * align256(size_t(n) * sizeof(double));
+    return align256(sizeof(PcgState)) + 6 * align256(kGrid * sizeof(double)) + align256(2 * kHist * sizeof(double)) +
+           3 * align256(size_t(n) * sizeof(double));
 }
 
 static PcgWs carve(void *ws, int64_t n)
@@ -50,8 +72,12 @@ static PcgWs carve(void *ws, int64_t n)
     PcgWs w;
     w.st = reinterpret_cast<PcgState *>(p);
     p += align256(sizeof(PcgState));
-    w.part = reinterpret_cast<double *>(p);
-    p += align256(3 * kMaxBlocks * sizeof(double));
+    w.p1 = reinterpret_cast<double *>(p);
+    p += align256(kGrid * sizeof(double));
+    w.p2 = reinterpret_cast<double *>(p);
+    p += 2 * align256(kGrid * sizeof(double));
+    w.p3 = reinterpret_cast<double *>(p);
+    p += 3 * align256(kGrid * sizeof(double));
     w.hist = reinterpret_cast<double *>(p);
     p += align256(2 * kHist * sizeof(double));
     w.r = reinterpret_cast<double *>(p);
@@ -62,72 +88,85 @@ static PcgWs carve(void *ws, int64_t n)
     return w;
 }
 
+static SpmvPlan plan_for(int64_t n, int64_t nnz)
+{
+    const double avg = n > 0 ? double(nnz) / double(n) : 1.0;
+    SpmvPlan pl{};
+    if (avg >= 96.0) {
+        pl.mode = 1;
+        pl.rpb = 1;
+        pl.lanes = 64;
+        return pl;
+    }
+    int rpw = 32;  // a run's rpw + 1 row pointers sit in one wave's lanes
+    while (rpw > 1 && rpw * avg > double(kWaveCap)) rpw /= 2;
+    pl.mode = 0;
+    pl.rpb = rpw;
+    pl.lanes = 64 / rpw;
+    return pl;
+}
+
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
+template <int W>
+__device__ __forceinline__ double butterfly(double v)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
     return v;
 }
 
-// Sum of v over the block, in a fixed order; valid in thread 0.
+// Sum over the block in a fixed order; the result is returned in every thread.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV])
+__device__ __forceinline__ void block_sum_all(double (&v)[NV])
 {
     __shared__ double sh[NV][kBlock / 64];
+    __shared__ double res[NV];
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
 #pragma unroll
     for (int t = 0; t < NV; t++) {
-        const double s = wave_sum(v[t]);
+        const double s = butterfly<64>(v[t]);
         if (lane == 0) sh[t][wid] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int t = 0; t < NV; t++) {
-            double s = 0.0;
-            for (int w = 0; w < kBlock / 64; w++) s += sh[t][w];
-            out[t] = s;
-        }
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; w++) s += sh[threadIdx.x][w];
+        res[threadIdx.x] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NV; t++) v[t] = res[t];
+    __syncthreads();
 }
 
-// Writes the block's partials, and returns true in every thread of the last
-// block to finish; then `tot` (valid in thread 0) holds the grand totals,
-// summed over the blocks in index order.
+// Block partials of v -> part[t * kGrid + blockIdx.x].
 template <int NV>
-__device__ bool grid_sum(double (&v)[NV], double *part, uint32_t *counter, double (&tot)[NV])
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *part)
 {
-    __shared__ bool last;
-    double bs[NV];
-    block_sum<NV>(v, bs);
-    if (threadIdx.x == 0) {
+    block_sum_all<NV>(v);
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int t = 0; t < NV; t++) part[t * kMaxBlocks + blockIdx.x] = bs[t];
-        __threadfence();
-        const uint32_t prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc[NV];
+        for (int t = 0; t < NV; t++) part[t * kGrid + blockIdx.x] = v[t];
+}
+
+// Grand totals of partials written by a previous kernel of `nparts` blocks;
+// identical in every thread of every block.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *part, int nparts, double (&tot)[NV])
+{
 #pragma unroll
     for (int t = 0; t < NV; t++) {
-        acc[t] = 0.0;
-        for (int b = threadIdx.x; b < int(gridDim.x); b += kBlock)
-            acc[t] += static_cast<volatile double *>(part)[t * kMaxBlocks + b];
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += kBlock) s += part[t * kGrid + b];
+        tot[t] = s;
     }
-    __syncthreads();
-    block_sum<NV>(acc, tot);
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
+    block_sum_all<NV>(tot);
 }
 
 // ---------------------------------------------------------------------------
-// Row dot product of a CSR row with L lanes (deterministic butterfly)
+// Row traversal
 // ---------------------------------------------------------------------------
 template <int L>
 __device__ __forceinline__ double row_dot(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
@@ -136,42 +175,133 @@ __device__ __forceinline__ double row_dot(const int64_t *__restrict__ rowptr, co
 {
     const int64_t b = rowptr[row], e = rowptr[row + 1];
     double s = 0.0;
-    for (int64_t j = b + lane; j < e; j += L) s += val[j] * x[colind[j]];
+    int64_t j = b + lane;
+    // four loads in flight per lane, summed in the same lane-strided order
+    for (; j + 3 * L < e; j += 4 * L) {
+        double v[4];
+        int32_t c[4];
 #pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-    return s;
+        for (int u = 0; u < 4; u++) {
+            v[u] = val[j + u * L];
+            c[u] = colind[j + u * L];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) s += v[u] * x[c[u]];
+    }
+    for (; j < e; j += L) s += val[j] * x[colind[j]];
+    return butterfly<L>(s);
 }
 
-// Rows [lo, hi) of logical block `lb` out of `nb` blocks.
-__device__ __forceinline__ void block_rows(int64_t n, int64_t lb, int64_t nb, int64_t &lo, int64_t &hi)
+// LDS writes of a wave made visible to the other lanes of the same wave.
+__device__ __forceinline__ void wave_lds_sync()
 {
-    const int64_t chunk = (n + nb - 1) / nb;
-    lo = lb * chunk;
-    hi = lo + chunk < n ? lo + chunk : n;
-    if (lo > n) lo = n;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int L>
+// Calls f(row, A_row . x) once per row handled by this wave (in the first
+// lane of the row's lane group).  Wave-level CSR-stream: the rows are cut
+// into runs of RPW; run t is handled by logical wave t mod (number of waves),
+// so the waves active at any moment work on neighbouring rows and share the
+// gathered entries of x in cache (blocks are renumbered so that a contiguous
+// range of logical waves runs on one XCD).  A wave loads the run's RPW + 1 row
+// pointers with one coalesced load, stages the products of the run in its own
+// LDS slice with coalesced loads of values and column indices, then
+// LW = 64 / RPW lanes per row sum them.  A run longer than the slice is summed
+// straight from memory in the same lane order.
+template <int RPW, typename Fn>
+__device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ colind, const double *__restrict__ val,
+                                                 const double *__restrict__ x, Fn f)
+{
+    constexpr int LW = 64 / RPW;
+    __shared__ double prod[kWaves][kWaveCap];
+    double *my = prod[threadIdx.x / 64];
+    const int lane = threadIdx.x % 64, grp = lane / LW, sub = lane % LW;
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    const int64_t lw = xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
+    const int64_t runs = (n + RPW - 1) / RPW;
+    for (int64_t run = lw; run < runs; run += nw) {
+        const int64_t r0 = run * RPW;
+        const int64_t r1 = std::min<int64_t>(r0 + RPW, n);
+        const int64_t rp = (lane <= RPW && r0 + lane <= n) ? rowptr[r0 + lane] : 0;
+        const int64_t base = __shfl(rp, 0), end = __shfl(rp, int(r1 - r0));
+        const int64_t rb = __shfl(rp, grp), re = __shfl(rp, grp + 1);
+        const int64_t row = r0 + grp;
+        double s = 0.0;
+        if (end - base <= kWaveCap) {
+            for (int64_t j = base + lane; j < end; j += 64) my[j - base] = val[j] * x[colind[j]];
+            wave_lds_sync();
+            if (row < r1)
+                for (int64_t t = rb - base + sub; t < re - base; t += LW) s += my[t];
+            s = butterfly<LW>(s);
+            wave_lds_sync();
+        } else if (row < r1) {
+            for (int64_t j = rb + sub; j < re; j += LW) s += val[j] * x[colind[j]];
+            s = butterfly<LW>(s);
+        }
+        if (row < r1 && sub == 0) f(row, s);
+    }
+}
+
+// One wave per row (long rows), 64 lanes.
+template <typename Fn>
+__device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ colind, const double *__restrict__ val,
+                                              const double *__restrict__ x, Fn f)
+{
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    const int64_t lw = xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    for (int64_t row = lw; row < n; row += nw) {
+        const double s = row_dot<64>(rowptr, colind, val, x, row, lane);
+        if (lane == 0) f(row, s);
+    }
+}
+
+// Dispatch on the plan (mode, rows per wave-iteration) at compile time.
+#define FE_PLAN_DISPATCH(PL, BODY)                                 \
+    do {                                                           \
+        if ((PL).mode == 1) {                                      \
+            constexpr int kMode = 1, kRpb = 1;                     \
+            BODY;                                                  \
+        } else {                                                   \
+            switch ((PL).rpb) {                                    \
+                case 32: { constexpr int kMode = 0, kRpb = 32; BODY; } break; \
+                case 16: { constexpr int kMode = 0, kRpb = 16; BODY; } break; \
+                case 8: { constexpr int kMode = 0, kRpb = 8; BODY; } break;   \
+                case 4: { constexpr int kMode = 0, kRpb = 4; BODY; } break;   \
+                case 2: { constexpr int kMode = 0, kRpb = 2; BODY; } break;   \
+                default: { constexpr int kMode = 0, kRpb = 1; BODY; } break;  \
+            }                                                      \
+        }                                                          \
+    } while (0)
+
+template <int MODE, int RPW, typename Fn>
+__device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val,
+                                         const double *x, Fn f)
+{
+    if constexpr (MODE == 1)
+        for_rows_wave(n, rowptr, colind, val, x, f);
+    else
+        for_rows_wstream<RPW>(n, rowptr, colind, val, x, f);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <int MODE, int RPB>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, const int64_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ colind,
                                                        const double *__restrict__ val, const double *__restrict__ x,
                                                        double *__restrict__ y)
 {
-    constexpr int G = kBlock / L;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    int64_t lo, hi;
-    block_rows(n, lb, gridDim.x, lo, hi);
-    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
-    for (int64_t r0 = lo; r0 < hi; r0 += G) {
-        const int64_t row = r0 + grp;
-        double s = 0.0;
-        if (row < hi) s = row_dot<L>(rowptr, colind, val, x, row, lane);
-        if (row < hi && lane == 0) y[row] = s;
-    }
+    for_rows<MODE, RPB>(n, rowptr, colind, val, x, [&](int64_t row, double s) { y[row] = s; });
 }
 
-// r = b - A x; z = dinv r; p = z; sums r.z, r.r, b.b
-template <int L>
+// r = b - A x; p = z = dinv r; partials of r.z, r.r, b.b
+template <int MODE, int RPB>
 __global__ __launch_bounds__(kBlock) void pcg_init_kernel(int64_t n, const int64_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ colind,
                                                            const double *__restrict__ val,
@@ -179,205 +309,173 @@ __global__ __launch_bounds__(kBlock) void pcg_init_kernel(int64_t n, const int64
                                                            const double *__restrict__ b, const double *__restrict__ x,
                                                            PcgWs w)
 {
-    constexpr int G = kBlock / L;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    int64_t lo, hi;
-    block_rows(n, lb, gridDim.x, lo, hi);
-    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int64_t r0 = lo; r0 < hi; r0 += G) {
-        const int64_t row = r0 + grp;
-        if (row < hi) {
-            const double ax = row_dot<L>(rowptr, colind, val, x, row, lane);
-            if (lane == 0) {
-                const double r = b[row] - ax;
-                const double z = dinv[row] * r;
-                w.r[row] = r;
-                w.p[row] = z;
-                v[0] += r * z;
-                v[1] += r * r;
-                v[2] += b[row] * b[row];
-            }
-        }
-    }
-    double tot[3];
-    if (grid_sum<3>(v, w.part, &w.st->counter[0], tot) && threadIdx.x == 0) {
+    for_rows<MODE, RPB>(n, rowptr, colind, val, x, [&](int64_t row, double ax) {
+        const double r = b[row] - ax;
+        const double z = dinv[row] * r;
+        w.r[row] = r;
+        w.p[row] = z;
+        v[0] += r * z;
+        v[1] += r * r;
+        v[2] += b[row] * b[row];
+    });
+    write_partials<3>(v, w.p3);
+}
+
+__global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(PcgWs w, int nparts, double rtol2, int maxit)
+{
+    double t[3];
+    reduce_partials<3>(w.p3, nparts, t);
+    if (threadIdx.x == 0) {
         PcgState *st = w.st;
-        st->rho = tot[0];
-        st->rr = tot[1];
-        st->bb = tot[2];
+        st->rho[0] = t[0];
+        st->rr = t[1];
+        st->bb = t[2];
         st->iter = 0;
         st->status = FE_OK;
-        st->done = (tot[1] <= st->rtol2 * tot[2]) ? 1 : 0;
-        if (!st->done && st->maxit <= 0) {
+        st->done = 0;
+        if (t[1] <= rtol2 * t[2]) {
+            st->done = 1;
+        } else if (maxit <= 0) {
             st->done = 1;
             st->status = FE_ENOTCONV;
         }
     }
 }
 
-// q = A p; sum p.q; alpha = rho / p.q
-template <int L>
+// q = A p; partials of p.q
+template <int MODE, int RPB>
 __global__ __launch_bounds__(kBlock) void pcg_spmv_kernel(int64_t n, const int64_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ colind,
                                                            const double *__restrict__ val, PcgWs w)
 {
     if (w.st->done) return;
-    constexpr int G = kBlock / L;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    int64_t lo, hi;
-    block_rows(n, lb, gridDim.x, lo, hi);
-    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
     double v[1] = {0.0};
-    for (int64_t r0 = lo; r0 < hi; r0 += G) {
-        const int64_t row = r0 + grp;
-        if (row < hi) {
-            const double s = row_dot<L>(rowptr, colind, val, w.p, row, lane);
-            if (lane == 0) {
-                w.q[row] = s;
-                v[0] += w.p[row] * s;
-            }
-        }
-    }
-    double tot[1];
-    if (grid_sum<1>(v, w.part, &w.st->counter[1], tot) && threadIdx.x == 0) {
-        PcgState *st = w.st;
-        st->pq = tot[0];
-        if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-            st->done = 1;
-            st->status = FE_EBREAKDOWN;
-        } else {
-            st->alpha = st->rho / tot[0];
-        }
-    }
+    const double *__restrict__ p = w.p;
+    double *__restrict__ q = w.q;
+    for_rows<MODE, RPB>(n, rowptr, colind, val, p, [&](int64_t row, double s) {
+        q[row] = s;
+        v[0] += p[row] * s;
+    });
+    write_partials<1>(v, w.p1);
 }
 
-// x += alpha p; r -= alpha q; sums r.z (z = dinv r) and r.r; beta; convergence
-__global__ __launch_bounds__(kBlock) void pcg_update_kernel(int64_t n, const double *__restrict__ dinv,
-                                                             double *__restrict__ x, PcgWs w)
+// Elements [lo, hi) of this block for the vector kernels.
+__device__ __forceinline__ void owned_elems(int64_t n, int64_t &lo, int64_t &hi)
+{
+    const int64_t nb = gridDim.x;
+    const int64_t lb = xcd_block(blockIdx.x, nb);
+    const int64_t per = ((n + nb - 1) / nb + 1) / 2 * 2;  // even, so double2 accesses stay aligned
+    lo = std::min<int64_t>(lb * per, n);
+    hi = std::min<int64_t>(lo + per, n);
+}
+
+// alpha = rho_j / p.q; x += alpha p; r -= alpha q; partials of r.z, r.r
+__global__ __launch_bounds__(kBlock) void pcg_update_kernel(int64_t n, int j, int nparts,
+                                                             const double *__restrict__ dinv, double *__restrict__ x,
+                                                             PcgWs w)
 {
     if (w.st->done) return;
-    const double alpha = w.st->alpha;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    int64_t lo, hi;
-    block_rows(n, lb, gridDim.x, lo, hi);
-    double v[2] = {0.0, 0.0};
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        x[i] += alpha * w.p[i];
-        const double r = w.r[i] - alpha * w.q[i];
-        w.r[i] = r;
-        v[0] += r * (dinv[i] * r);
-        v[1] += r * r;
-    }
-    double tot[2];
-    if (grid_sum<2>(v, w.part, &w.st->counter[2], tot) && threadIdx.x == 0) {
-        PcgState *st = w.st;
-        const double beta = tot[0] / st->rho;
-        const int it = st->iter;
-        if (it < kHist) {
-            w.hist[it] = st->alpha;
-            w.hist[kHist + it] = beta;
+    double pq[1];
+    reduce_partials<1>(w.p1, nparts, pq);
+    if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            w.st->done = 1;
+            w.st->status = FE_EBREAKDOWN;
         }
-        st->beta = beta;
-        st->rho = tot[0];
-        st->rr = tot[1];
-        st->iter = it + 1;
-        if (tot[1] <= st->rtol2 * st->bb) {
+        return;
+    }
+    const double alpha = w.st->rho[j & 1] / pq[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && j < kHist) w.hist[j] = alpha;
+    int64_t lo, hi;
+    owned_elems(n, lo, hi);
+    double v[2] = {0.0, 0.0};
+    const double *__restrict__ p = w.p;
+    const double *__restrict__ q = w.q;
+    double *__restrict__ r = w.r;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v[0] += ri * (dinv[i] * ri);
+        v[1] += ri * ri;
+    }
+    write_partials<2>(v, w.p2);
+}
+
+// beta = rho_{j+1} / rho_j; convergence test; p = z + beta p
+__global__ __launch_bounds__(kBlock) void pcg_dir_kernel(int64_t n, int j, int nparts, double rtol2,
+                                                          const double *__restrict__ dinv, PcgWs w)
+{
+    if (w.st->done) return;
+    double t[2];
+    reduce_partials<2>(w.p2, nparts, t);
+    const double rho_old = w.st->rho[j & 1];
+    const double beta = t[0] / rho_old;
+    const bool conv = t[1] <= rtol2 * w.st->bb;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        PcgState *st = w.st;
+        st->rho[(j + 1) & 1] = t[0];
+        st->rr = t[1];
+        st->iter = j + 1;
+        if (j < kHist) w.hist[kHist + j] = beta;
+        if (conv) {
             st->done = 1;
             st->status = FE_OK;
-        } else if (it + 1 >= st->maxit) {
-            st->done = 1;
-            st->status = FE_ENOTCONV;
         }
     }
-}
-
-// p = dinv r + beta p
-__global__ __launch_bounds__(kBlock) void pcg_dir_kernel(int64_t n, const double *__restrict__ dinv, PcgWs w)
-{
-    if (w.st->done) return;
-    const double beta = w.st->beta;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    if (conv) return;
     int64_t lo, hi;
-    block_rows(n, lb, gridDim.x, lo, hi);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) w.p[i] = dinv[i] * w.r[i] + beta * w.p[i];
+    owned_elems(n, lo, hi);
+    const double *__restrict__ r = w.r;
+    double *__restrict__ p = w.p;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) p[i] = dinv[i] * r[i] + beta * p[i];
 }
 
-// sum over rows of (b - A x)^2
-template <int L>
+// partials of (b - A x)^2
+template <int MODE, int RPB>
 __global__ __launch_bounds__(kBlock) void resid_kernel(int64_t n, const int64_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ colind,
                                                         const double *__restrict__ val, const double *__restrict__ b,
                                                         const double *__restrict__ x, PcgWs w)
 {
-    constexpr int G = kBlock / L;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    int64_t lo, hi;
-    block_rows(n, lb, gridDim.x, lo, hi);
-    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
     double v[1] = {0.0};
-    for (int64_t r0 = lo; r0 < hi; r0 += G) {
-        const int64_t row = r0 + grp;
-        if (row < hi) {
-            const double ax = row_dot<L>(rowptr, colind, val, x, row, lane);
-            if (lane == 0) v[0] += (b[row] - ax) * (b[row] - ax);
-        }
-    }
-    double tot[1];
-    if (grid_sum<1>(v, w.part, &w.st->counter[3], tot) && threadIdx.x == 0) w.st->true_rr = tot[0];
+    for_rows<MODE, RPB>(n, rowptr, colind, val, x, [&](int64_t row, double ax) {
+        const double d = b[row] - ax;
+        v[0] += d * d;
+    });
+    write_partials<1>(v, w.p3);
 }
 
-__global__ void pcg_state_init_kernel(PcgState *st, double rtol2, int maxit)
+__global__ __launch_bounds__(kBlock) void resid_finish_kernel(PcgWs w, int nparts)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->rho = st->pq = st->alpha = st->beta = st->rr = st->bb = st->true_rr = 0.0;
-        st->rtol2 = rtol2;
-        st->iter = 0;
-        st->done = 0;
-        st->status = FE_OK;
-        st->maxit = maxit;
-        for (int i = 0; i < 4; i++) st->counter[i] = 0u;
-    }
+    double t[1];
+    reduce_partials<1>(w.p3, nparts, t);
+    if (threadIdx.x == 0) w.st->true_rr = t[0];
 }
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-static int lanes_for(double nnz_per_row)
+static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
-    int L = 2;
-    while (L < 64 && 2 * L <= nnz_per_row / 2.0) L *= 2;
-    return L;
+    const int64_t runs = (n + pl.rpb - 1) / pl.rpb;
+    return int(std::max<int64_t>(1, std::min<int64_t>(kGrid, (runs + kWaves - 1) / kWaves)));
 }
 
-static int grid_for(int64_t n, int L)
+static int grid_elems(int64_t n)
 {
-    const int64_t per = kBlock / L;
-    int64_t g = (n + per - 1) / per;
-    if (g > kMaxBlocks) g = kMaxBlocks;
-    if (g < 1) g = 1;
-    return int(g);
+    return int(std::max<int64_t>(1, std::min<int64_t>(kGrid, (n + kBlock - 1) / kBlock)));
 }
-
-#define FE_LANES_DISPATCH(L, CALL) \
-    switch (L) {                   \
-        case 2: CALL(2); break;    \
-        case 4: CALL(4); break;    \
-        case 8: CALL(8); break;    \
-        case 16: CALL(16); break;  \
-        case 32: CALL(32); break;  \
-        default: CALL(64); break;  \
-    }
 
 fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
                       double *y, double nnz_per_row, hipStream_t s)
 {
     if (n == 0) return FE_OK;
-    const int L = lanes_for(nnz_per_row);
-    const int grid = grid_for(n, L);
-#define FE_SPMV(LV) hipLaunchKernelGGL(spmv_kernel<LV>, dim3(grid), dim3(kBlock), 0, s, n, rowptr, colind, val, x, y)
-    FE_LANES_DISPATCH(L, FE_SPMV)
-#undef FE_SPMV
+    const SpmvPlan pl = plan_for(n, int64_t(nnz_per_row * double(n) + 0.5));
+    const int g = grid_rows(n, pl);
+    FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb><<<dim3(g), dim3(kBlock), 0, s>>>(n, rowptr,
+                                             colind, val, x, y)));
     FE_HIP(hipGetLastError());
     return FE_OK;
 }
@@ -440,43 +538,48 @@ fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, in
         info->status = FE_OK;
         return FE_OK;
     }
-    const double npr = double(A->nnz) / double(n);
-    const int L = lanes_for(npr);
-    const int gs = grid_for(n, L);                       // SpMV-shaped kernels
-    const int gv = int(std::min<int64_t>(kMaxBlocks, (n + kBlock - 1) / kBlock));  // vector kernels
-    hipLaunchKernelGGL(pcg_state_init_kernel, dim3(1), dim3(64), 0, s, w.st, rtol * rtol, maxit);
-#define FE_INIT(LV) \
-    hipLaunchKernelGGL(pcg_init_kernel<LV>, dim3(gs), dim3(kBlock), 0, s, n, A->rowptr, A->colind, A->values, A->dinv, b, x, w)
-    FE_LANES_DISPATCH(L, FE_INIT)
-#undef FE_INIT
+    const SpmvPlan pl = plan_for(n, A->nnz);
+    const int gr = grid_rows(n, pl);
+    const int ge = grid_elems(n);
+    const double rtol2 = rtol * rtol;
+    FE_PLAN_DISPATCH(pl, (pcg_init_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(n,
+                                             A->rowptr, A->colind, A->values, A->dinv, b, x, w)));
+    hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr, rtol2, maxit);
     FE_HIP(hipGetLastError());
     int chunk = 8;
-    int launched = 0;
-    while (true) {
-        for (int i = 0; i < chunk && launched < maxit; i++, launched++) {
-#define FE_SPMVK(LV) \
-    hipLaunchKernelGGL(pcg_spmv_kernel<LV>, dim3(gs), dim3(kBlock), 0, s, n, A->rowptr, A->colind, A->values, w)
-            hipEvent_t t0 = timing_begin(s);
-            FE_LANES_DISPATCH(L, FE_SPMVK)
-            timing_end(t0, kTimeSpmv, s);
-#undef FE_SPMVK
-            hipLaunchKernelGGL(pcg_update_kernel, dim3(gv), dim3(kBlock), 0, s, n, A->dinv, x, w);
-            hipLaunchKernelGGL(pcg_dir_kernel, dim3(gv), dim3(kBlock), 0, s, n, A->dinv, w);
+    int j = 0;
+    // SpMV launches timed when timing is on; the ones issued after convergence
+    // (which exit at once) are dropped once the iteration count is known
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+    while (j < maxit) {
+        for (int i = 0; i < chunk && j < maxit; i++, j++) {
+            hipEvent_t t0 = timing_mark(s);
+            FE_PLAN_DISPATCH(pl, (pcg_spmv_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(n, A->rowptr, A->colind, A->values, w)));
+            if (t0) marks.emplace_back(t0, timing_mark(s));
+            hipLaunchKernelGGL(pcg_update_kernel, dim3(ge), dim3(kBlock), 0, s, n, j, gr, A->dinv, x, w);
+            hipLaunchKernelGGL(pcg_dir_kernel, dim3(ge), dim3(kBlock), 0, s, n, j, ge, rtol2, A->dinv, w);
         }
         FE_HIP(hipGetLastError());
         FE_HIP(hipMemcpyAsync(pin.h, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
         FE_HIP(hipStreamSynchronize(s));
-        if (pin.h->done || launched >= maxit) break;
+        if (pin.h->done) break;
         if (chunk < 128) chunk *= 2;
     }
-#define FE_RES(LV) \
-    hipLaunchKernelGGL(resid_kernel<LV>, dim3(gs), dim3(kBlock), 0, s, n, A->rowptr, A->colind, A->values, b, x, w)
-    FE_LANES_DISPATCH(L, FE_RES)
-#undef FE_RES
+    FE_PLAN_DISPATCH(pl, (resid_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(n, A->rowptr,
+                                             A->colind, A->values, b, x, w)));
+    hipLaunchKernelGGL(resid_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr);
     FE_HIP(hipGetLastError());
     FE_HIP(hipMemcpyAsync(pin.h, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     FE_HIP(hipStreamSynchronize(s));
     const PcgState st = *pin.h;
+    for (size_t i = 0; i < marks.size(); i++) {
+        if (int(i) < st.iter) {
+            timing_commit(marks[i].first, marks[i].second, kTimeSpmv);
+        } else {
+            timing_release(marks[i].first);
+            timing_release(marks[i].second);
+        }
+    }
     info->iters = st.iter;
     info->status = st.done ? st.status : FE_ENOTCONV;
     const double bn = std::sqrt(st.bb);
@@ -487,10 +590,10 @@ fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, in
         std::vector<double> h(2 * kHist);
         FE_HIP(hipMemcpy(h.data(), w.hist, sizeof(double) * 2 * kHist, hipMemcpyDeviceToHost));
         std::vector<double> d(m), e(m > 1 ? m - 1 : 1);
-        for (int j = 0; j < m; j++) {
-            const double a = h[j], bprev = j > 0 ? h[kHist + j - 1] : 0.0, aprev = j > 0 ? h[j - 1] : 1.0;
-            d[j] = 1.0 / a + (j > 0 ? bprev / aprev : 0.0);
-            if (j + 1 < m) e[j] = std::sqrt(h[kHist + j]) / a;
+        for (int i = 0; i < m; i++) {
+            const double a = h[i];
+            d[i] = 1.0 / a + (i > 0 ? h[kHist + i - 1] / h[i - 1] : 0.0);
+            if (i + 1 < m) e[i] = std::sqrt(h[kHist + i]) / a;
         }
         tridiag_extremes(d, e, info->lambda_min_est, info->lambda_max_est);
     }
