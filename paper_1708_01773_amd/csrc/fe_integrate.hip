@@ -10,6 +10,7 @@
 // Load:       F_(a,c) = sum_q w_q |det J_q| f_c(x_q) phi_a(xi_q)
 // Lifting:    F_a -= sum_{b fixed} A_ab u_D(b)   (Sect. 10.4)
 #include <cmath>
+#include <type_traits>
 
 #include "fe_internal.h"
 
@@ -116,24 +117,54 @@ __device__ __forceinline__ double geometry(const double X[][3], const double xi[
 // Q1 scalar kernel: one thread per cell, element matrix in registers (the 36
 // upper-triangle entries in 3D), written in the blocked layout
 // E[(c/64)][a*8+b][c%64] so that a wave's stores of one entry are 512
-// contiguous bytes.  Q1 is HBM-bound (6 flop per byte of E), so this runs on
-// the FP64 vector units.
+// contiguous bytes.  Q1 is HBM-bound (6 flop per byte of E) and its 8 x 8 x 24
+// product would fill a quarter of a 16 x 16 matrix tile, so it runs on the
+// vector units in every precision.  PREC > 0: the two GEMM operands (the
+// gradients, and the gradients times w_q k |det J_q|) are rounded to FP32 /
+// FP16 / BF16 and accumulated in FP32, the result stored as FP32; for FP16 /
+// BF16 they are first scaled by per-cell powers of two (undone exactly).
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int PREC>
+__device__ __forceinline__ float round_in(double v)
+{
+    if (PREC == FE_FP16) return float(_Float16(float(v)));
+    if (PREC == FE_BF16) return float(__bf16(float(v)));
+    return float(v);
+}
+
+template <int DIM, int PREC>
 __global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt,
-                                                     double *__restrict__ E, double *__restrict__ F)
+                                                     void *__restrict__ Ev, double *__restrict__ F)
 {
     constexpr int NN = 1 << DIM;
     constexpr int NT = NN * (NN + 1) / 2;
+    using Acc = typename std::conditional<PREC == FE_FP64, double, float>::type;
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t cell = bid * blockDim.x + threadIdx.x;
     if (cell >= s.ncells) return;
     double X[NN][3];
     load_vertices<DIM>(m, cell, X);
     const double coef = m.coef[cell];
-    double acc[NT];
+    // per-cell operand scaling for FP16 / BF16
+    double alpha = 1.0, beta = 1.0;
+    if (PREC == FE_FP16 || PREC == FE_BF16) {
+        double wmax = 0.0, det0 = 0.0;
 #pragma unroll
-    for (int t = 0; t < NT; t++) acc[t] = 0.0;
+        for (int q = 0; q < NN; q++) {
+            const int q0 = q & 1, q1 = (q >> 1) & 1, q2 = (q >> 2) & 1;
+            const double xi[3] = {rt.gx[q0], rt.gx[q1], DIM == 3 ? rt.gx[q2] : 0.0};
+            double J[9], Ji[9], xq[3];
+            const double det = geometry<DIM>(X, xi, J, Ji, xq);
+            if (q == 0) det0 = det;
+            wmax = fmax(wmax, rt.gw[q0] * rt.gw[q1] * (DIM == 3 ? rt.gw[q2] : 1.0) * fabs(det) * coef);
+        }
+        const double h = DIM == 3 ? cbrt(fabs(det0)) : sqrt(fabs(det0));
+        alpha = exp2(floor(log2(h > 0.0 ? h : 1.0)));
+        beta = alpha * (wmax > 0.0 ? exp2(-floor(log2(wmax))) : 1.0);
+    }
+    Acc acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) acc[t] = Acc(0);
     double fl[NN];
 #pragma unroll
     for (int a = 0; a < NN; a++) fl[a] = 0.0;
@@ -148,6 +179,7 @@ __global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, Pro
         bad |= !(det > 0.0);
         const double wdet = w * fabs(det);
         const double wd = wdet * coef;
+        const double fq = source_value(p, DIM, xq, 0);
         // physical gradients of the 2^d shape functions (Sect. 3.7 eq. shape_grad)
         double g[NN][DIM];
 #pragma unroll
@@ -161,11 +193,11 @@ __global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, Pro
                 gr[0] = D0 * L1 * L2;
                 gr[1] = L0 * D1 * L2;
                 gr[2] = L0 * L1 * D2;
-                fl[a] += wdet * source_value(p, DIM, xq, 0) * (L0 * L1 * L2);
+                fl[a] += wdet * fq * (L0 * L1 * L2);
             } else {
                 gr[0] = D0 * L1;
                 gr[1] = L0 * D1;
-                fl[a] += wdet * source_value(p, DIM, xq, 0) * (L0 * L1);
+                fl[a] += wdet * fq * (L0 * L1);
             }
 #pragma unroll
             for (int i = 0; i < DIM; i++) {
@@ -175,27 +207,48 @@ __global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, Pro
                 g[a][i] = v;
             }
         }
-        int t = 0;
+        if (PREC == FE_FP64) {
+            int t = 0;
 #pragma unroll
-        for (int a = 0; a < NN; a++)
+            for (int a = 0; a < NN; a++)
 #pragma unroll
-            for (int b = a; b < NN; b++, t++) {
-                double dot = 0.0;
+                for (int b = a; b < NN; b++, t++) {
+                    double dot = 0.0;
 #pragma unroll
-                for (int i = 0; i < DIM; i++) dot += g[a][i] * g[b][i];
-                acc[t] += wd * dot;
-            }
+                    for (int i = 0; i < DIM; i++) dot += g[a][i] * g[b][i];
+                    acc[t] += Acc(wd * dot);
+                }
+        } else {
+            float ga[NN][DIM], hb[NN][DIM];
+#pragma unroll
+            for (int a = 0; a < NN; a++)
+#pragma unroll
+                for (int i = 0; i < DIM; i++) {
+                    ga[a][i] = round_in<PREC>(g[a][i] * alpha);
+                    hb[a][i] = round_in<PREC>(g[a][i] * wd * beta);
+                }
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NN; a++)
+#pragma unroll
+                for (int b = a; b < NN; b++, t++)
+#pragma unroll
+                    for (int i = 0; i < DIM; i++) acc[t] = fmaf(ga[a][i], hb[b][i], float(acc[t]));
+        }
     }
     if (bad) atomicOr(m.status, 1);
+    const double unscale = 1.0 / (alpha * beta);
     const int64_t blk = cell / 64, lane = cell % 64;
-    double *Eb = E + blk * (NN * NN * 64) + lane;
+    using Out = Acc;
+    Out *Eb = static_cast<Out *>(Ev) + blk * (NN * NN * 64) + lane;
     int t = 0;
 #pragma unroll
     for (int a = 0; a < NN; a++)
 #pragma unroll
         for (int b = a; b < NN; b++, t++) {
-            Eb[(a * NN + b) * 64] = acc[t];
-            if (b != a) Eb[(b * NN + a) * 64] = acc[t];
+            const Out v = PREC == FE_FP64 ? acc[t] : Out(double(acc[t]) * unscale);
+            Eb[(a * NN + b) * 64] = v;
+            if (b != a) Eb[(b * NN + a) * 64] = v;
         }
 #pragma unroll
     for (int a = 0; a < NN; a++) F[cell * NN + a] = fl[a];
@@ -442,18 +495,33 @@ static fe_status launch_tiled(const SpaceArgs &sa, const MeshArgs &ma, const Pro
 fe_status launch_integrate(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
                            const ElemLayout &el, void *ws, hipStream_t s)
 {
-    if (pa.precision != FE_FP64) return set_error(FE_EINVAL, "precision not supported by this build");
     double *E = static_cast<double *>(ws);
     double *F = reinterpret_cast<double *>(static_cast<char *>(ws) + el.f_offset);
     if (sa.ncells == 0) return FE_OK;
+    if (sa.dim == 3 && sa.k >= 2) return launch_integrate_mfma(sa, ma, pa, rt, ws, F, s);
     fe_status st = FE_OK;
     if (sa.k == 1 && sa.ncomp == 1) {
         const int64_t grid = (sa.ncells + 255) / 256;
-        if (sa.dim == 3)
-            hipLaunchKernelGGL(k3_q1_kernel<3>, dim3(grid), dim3(256), 0, s, sa, ma, pa, rt, E, F);
-        else
-            hipLaunchKernelGGL(k3_q1_kernel<2>, dim3(grid), dim3(256), 0, s, sa, ma, pa, rt, E, F);
+#define FE_Q1(D, P) hipLaunchKernelGGL((k3_q1_kernel<D, P>), dim3(grid), dim3(256), 0, s, sa, ma, pa, rt, ws, F)
+        if (sa.dim == 3) {
+            switch (pa.precision) {
+                case FE_FP64: FE_Q1(3, FE_FP64); break;
+                case FE_FP32: FE_Q1(3, FE_FP32); break;
+                case FE_FP16: FE_Q1(3, FE_FP16); break;
+                default: FE_Q1(3, FE_BF16); break;
+            }
+        } else {
+            switch (pa.precision) {
+                case FE_FP64: FE_Q1(2, FE_FP64); break;
+                case FE_FP32: FE_Q1(2, FE_FP32); break;
+                case FE_FP16: FE_Q1(2, FE_FP16); break;
+                default: FE_Q1(2, FE_BF16); break;
+            }
+        }
+#undef FE_Q1
         FE_HIP(hipGetLastError());
+    } else if (pa.precision != FE_FP64) {
+        return set_error(FE_EINVAL, "reduced-precision integration needs 3D hexahedra (any order) or scalar Q1");
     } else if (sa.dim == 3) {
         st = pa.problem == 1 ? launch_tiled<3, 1>(sa, ma, pa, rt, E, F, s) : launch_tiled<3, 0>(sa, ma, pa, rt, E, F, s);
     } else {

@@ -1,0 +1,445 @@
+// fe_integrate_mfma.hip -- K3 on the matrix cores: element matrices of Q_k
+// hexahedra (k >= 2) as small GEMMs on MFMA (Sect. 3.7 eq. fematrix; the
+// Poisson element loop of Sect. 8.5 written as a contraction).
+//
+// With G[(c,q)][a] = (grad phi_a)_c at quadrature point q (physical, FP64
+// geometry) and w_q = w_q k_K |det J_q|:
+//   Poisson     A[a][b]        = sum_(c,q) G[(c,q)][a] w_q G[(c,q)][b]          (K = d nq)
+//   Elasticity  M_ij[a][b]     = sum_q G[(i,q)][a] w_q G[(j,q)][b]              (9 Gram blocks, K = nq)
+//               A[(a,i)][(b,j)] = lambda M_ij + mu (M_ji + delta_ij sum_l M_ll)  (combined per lane)
+// A workgroup owns one cell (or a part of its tile pairs): it stages the
+// physical gradients of a slab of quadrature points in LDS, then every wave
+// accumulates its node-tile pairs (ta <= tb, 16 x 16 each) with MFMA; the
+// lower triangle is written as the mirror of the upper one.
+//
+// Precision policies: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4),
+// FP16 / BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x32).  The
+// gradients are always computed in FP64 and rounded to the input type; for
+// FP16/BF16 the operands are scaled by powers of two chosen per cell (the
+// A operand by ~h, the B operand additionally by 1/max_q w_q) so that they
+// sit near 1, and the result is unscaled exactly.
+#include <cmath>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
+
+struct PolF64 {
+    using S = double;
+    using Acc = d4_t;
+    using Out = double;
+    static constexpr int KM = 4;
+    static constexpr bool KFAST = false;       // LDS layout [c][q][node]
+    static constexpr bool ROW_INTERLEAVED = true;  // D register r of lane l is row 4 r + l / 16
+    static constexpr bool SCALED = false;
+    __device__ static Acc zero() { return Acc{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static Acc mma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+
+struct PolF32 {
+    using S = float;
+    using Acc = f4_t;
+    using Out = float;
+    static constexpr int KM = 4;
+    static constexpr bool KFAST = false;
+    static constexpr bool ROW_INTERLEAVED = false;  // row 4 (l / 16) + r
+    static constexpr bool SCALED = false;
+    __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static Acc mma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+struct PolF16 {
+    using S = _Float16;
+    using V = h8_t;
+    using Acc = f4_t;
+    using Out = float;
+    static constexpr int KM = 32;
+    static constexpr bool KFAST = true;  // LDS layout [c][node][q]: a lane reads 8 consecutive q
+    static constexpr bool ROW_INTERLEAVED = false;
+    static constexpr bool SCALED = true;
+    __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static Acc mma(V a, V b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
+struct PolBF16 {
+    using S = __bf16;
+    using V = b8_t;
+    using Acc = f4_t;
+    using Out = float;
+    static constexpr int KM = 32;
+    static constexpr bool KFAST = true;
+    static constexpr bool ROW_INTERLEAVED = false;
+    static constexpr bool SCALED = true;
+    __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static Acc mma(V a, V b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+template <int DIM>
+__device__ __forceinline__ double geometry_mf(const double X[][3], const double xi[3], double Ji[9], double xq[3])
+{
+    double J[9];
+    for (int t = 0; t < 9; t++) J[t] = 0.0;
+    xq[0] = xq[1] = xq[2] = 0.0;
+    for (int v = 0; v < (1 << DIM); v++) {
+        double Nv = 1.0, dN[3];
+        for (int r = 0; r < DIM; r++) Nv *= ((v >> r) & 1) ? xi[r] : 1.0 - xi[r];
+        for (int sd = 0; sd < DIM; sd++) {
+            double g = 1.0;
+            for (int r = 0; r < DIM; r++)
+                g *= (r == sd) ? (((v >> r) & 1) ? 1.0 : -1.0) : (((v >> r) & 1) ? xi[r] : 1.0 - xi[r]);
+            dN[sd] = g;
+        }
+        for (int r = 0; r < DIM; r++) {
+            xq[r] += X[v][r] * Nv;
+            for (int sd = 0; sd < DIM; sd++) J[r * DIM + sd] += X[v][r] * dN[sd];
+        }
+    }
+    const double c00 = J[4] * J[8] - J[5] * J[7];
+    const double c01 = J[5] * J[6] - J[3] * J[8];
+    const double c02 = J[3] * J[7] - J[4] * J[6];
+    const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+    const double id = 1.0 / det;
+    Ji[0] = c00 * id;
+    Ji[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+    Ji[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+    Ji[3] = c01 * id;
+    Ji[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+    Ji[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+    Ji[6] = c02 * id;
+    Ji[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+    Ji[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+    return det;
+}
+
+__device__ __forceinline__ double source_value_mf(const ProblemArgs &p, const double *x, int c)
+{
+    if (p.source_kind == FE_SOURCE_CONST) return p.source[c];
+    if (p.source_kind == FE_SOURCE_SINPROD) {
+        const double s = sin(M_PI * x[0]) * sin(M_PI * x[1]) * sin(M_PI * x[2]);
+        return p.source[c] * 3.0 * (M_PI * M_PI) * s;
+    }
+    return 0.0;
+}
+
+// (ta, tb) of pair p in the upper-triangle enumeration of NT x NT tiles.
+__device__ __forceinline__ void pair_tiles(int p, int NT, int &ta, int &tb)
+{
+    ta = 0;
+    while (p >= NT - ta) {
+        p -= NT - ta;
+        ta++;
+    }
+    tb = ta + p;
+}
+
+// One workgroup = 4 waves = (cell, part).  NNP = padded node count (multiple
+// of 16), PPW = max node-tile pairs per wave, QS = quadrature points per slab.
+template <class Pol, int PROB, int NNP, int PPW, int QS>
+__global__ __launch_bounds__(256) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt, int parts,
+                                                      typename Pol::Out *__restrict__ E, double *__restrict__ F)
+{
+    constexpr int DIM = 3;
+    constexpr int NT = NNP / 16;
+    constexpr int NP = NT * (NT + 1) / 2;
+    constexpr int NC = PROB == 1 ? DIM : 1;        // DOF components
+    constexpr int NCP = PROB == 1 ? DIM * DIM : 1;  // accumulator tiles per pair
+    constexpr int NW = 4;
+    using S = typename Pol::S;
+    using Acc = typename Pol::Acc;
+    using Out = typename Pol::Out;
+
+    const int k = s.k, k1 = k + 1, nn = s.nn, nloc = s.nloc;
+    const int nq = k1 * k1 * k1;
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t cell = bid / parts;
+    const int part = int(bid % parts);
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+
+    __shared__ double sX[8][3];
+    __shared__ double sL[kMaxQ1 * kMaxQ1], sD[kMaxQ1 * kMaxQ1], sGX[kMaxQ1], sGW[kMaxQ1];
+    __shared__ double sJi[QS][9];
+    __shared__ double sW[QS], sWd[QS], sXq[QS][3];
+    __shared__ double sScale[2];  // alpha, beta (powers of two)
+    __shared__ int sBad;
+    // gradients (and the scaled B operand for FP16/BF16)
+    __shared__ __attribute__((aligned(16))) S sG[DIM][Pol::KFAST ? NNP : QS][Pol::KFAST ? QS : NNP];
+    __shared__ __attribute__((aligned(16))) S sH[Pol::SCALED ? DIM : 1][Pol::SCALED ? NNP : 1][Pol::SCALED ? QS : 1];
+    __shared__ S sWs[Pol::KFAST ? 1 : QS];
+
+    if (tid < 8) {
+        const int64_t e0 = cell % m.n0, e1 = (cell / m.n0) % m.n1, e2 = cell / (int64_t(m.n0) * m.n1);
+        const int64_t vid = (e0 + (tid & 1)) + int64_t(m.n0 + 1) * ((e1 + ((tid >> 1) & 1)) + int64_t(m.n1 + 1) * (e2 + ((tid >> 2) & 1)));
+        sX[tid][0] = m.x[vid];
+        sX[tid][1] = m.y[vid];
+        sX[tid][2] = m.z[vid];
+    }
+    if (tid < k1 * k1) {
+        sL[tid] = rt.L[tid];
+        sD[tid] = rt.D[tid];
+    }
+    if (tid < k1) {
+        sGX[tid] = rt.gx[tid];
+        sGW[tid] = rt.gw[tid];
+    }
+    if (tid == 0) sBad = 0;
+    const double coef = m.coef[cell];
+    __syncthreads();
+
+    // per-cell operand scaling (FP16/BF16 only): alpha ~ h, beta = alpha / 2^floor(log2 max_q w_q)
+    if (Pol::SCALED) {
+        __shared__ double sWmax[256];
+        double wl = 0.0, det0 = 0.0;
+        for (int q = tid; q < nq; q += blockDim.x) {
+            const int q0 = q % k1, q1 = (q / k1) % k1, q2 = q / (k1 * k1);
+            const double xi[3] = {sGX[q0], sGX[q1], sGX[q2]};
+            double Xl[8][3], Ji[9], xq[3];
+            for (int v = 0; v < 8; v++)
+                for (int r = 0; r < 3; r++) Xl[v][r] = sX[v][r];
+            const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
+            wl = fmax(wl, sGW[q0] * sGW[q1] * sGW[q2] * fabs(det) * coef);
+            if (q == 0) det0 = det;
+        }
+        sWmax[tid] = wl;
+        __syncthreads();
+        if (tid == 0) {
+            double wmax = 0.0;
+            for (int t = 0; t < blockDim.x; t++) wmax = fmax(wmax, sWmax[t]);
+            const double h = cbrt(fabs(det0) > 0.0 ? fabs(det0) : 1.0);
+            const double alpha = exp2(floor(log2(h)));
+            const double beta = alpha * (wmax > 0.0 ? exp2(-floor(log2(wmax))) : 1.0);
+            sScale[0] = alpha;
+            sScale[1] = beta;
+        }
+        __syncthreads();
+    }
+    const double alpha = Pol::SCALED ? sScale[0] : 1.0;
+    const double beta = Pol::SCALED ? sScale[1] : 1.0;
+
+    // tile pairs of this wave
+    int pta[PPW], ptb[PPW];
+    bool pok[PPW];
+#pragma unroll
+    for (int t = 0; t < PPW; t++) {
+        const int pidx = (part * NW + wave) + t * (parts * NW);
+        pok[t] = pidx < NP;
+        pair_tiles(pok[t] ? pidx : 0, NT, pta[t], ptb[t]);
+    }
+    Acc acc[PPW][NCP];
+#pragma unroll
+    for (int t = 0; t < PPW; t++)
+#pragma unroll
+        for (int c = 0; c < NCP; c++) acc[t][c] = Pol::zero();
+    const bool do_load = (part == 0);
+    double facc[(NNP * NC + 255) / 256];
+#pragma unroll
+    for (int t = 0; t < (NNP * NC + 255) / 256; t++) facc[t] = 0.0;
+
+    const int i16 = lane % 16, g4 = lane / 16;
+    for (int q0s = 0; q0s < nq; q0s += QS) {
+        const int qn = min(QS, nq - q0s);
+        if (tid < QS) {
+            if (tid < qn) {
+                const int q = q0s + tid;
+                const int a0 = q % k1, a1 = (q / k1) % k1, a2 = q / (k1 * k1);
+                const double xi[3] = {sGX[a0], sGX[a1], sGX[a2]};
+                double Xl[8][3], Ji[9], xq[3];
+                for (int v = 0; v < 8; v++)
+                    for (int r = 0; r < 3; r++) Xl[v][r] = sX[v][r];
+                const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
+                if (!(det > 0.0)) sBad = 1;
+                const double wd = sGW[a0] * sGW[a1] * sGW[a2] * fabs(det);
+                sWd[tid] = wd;
+                sW[tid] = wd * coef;
+                for (int t = 0; t < 9; t++) sJi[tid][t] = Ji[t];
+                for (int r = 0; r < 3; r++) sXq[tid][r] = xq[r];
+            } else {
+                sWd[tid] = 0.0;
+                sW[tid] = 0.0;
+                for (int t = 0; t < 9; t++) sJi[tid][t] = 0.0;
+                for (int r = 0; r < 3; r++) sXq[tid][r] = 0.0;
+            }
+        }
+        __syncthreads();
+        // physical gradients of every (padded) node at the slab's points
+        for (int idx = tid; idx < QS * NNP; idx += blockDim.x) {
+            const int qq = idx / NNP, node = idx % NNP;
+            double g[3] = {0.0, 0.0, 0.0};
+            if (qq < qn && node < nn) {
+                const int q = q0s + qq;
+                const int b0 = q % k1, b1 = (q / k1) % k1, b2 = q / (k1 * k1);
+                const int n0 = node % k1, n1 = (node / k1) % k1, n2 = node / (k1 * k1);
+                const double L0 = sL[n0 * k1 + b0], L1 = sL[n1 * k1 + b1], L2 = sL[n2 * k1 + b2];
+                const double gr[3] = {sD[n0 * k1 + b0] * L1 * L2, L0 * sD[n1 * k1 + b1] * L2, L0 * L1 * sD[n2 * k1 + b2]};
+                for (int c = 0; c < 3; c++) g[c] = sJi[qq][0 * 3 + c] * gr[0] + sJi[qq][1 * 3 + c] * gr[1] + sJi[qq][2 * 3 + c] * gr[2];
+            }
+            for (int c = 0; c < 3; c++) {
+                if (Pol::KFAST) {
+                    sG[c][node][qq] = S(g[c] * alpha);
+                    if (Pol::SCALED) sH[c][node][qq] = S(g[c] * sW[qq] * beta);
+                } else {
+                    sG[c][qq][node] = S(g[c]);
+                }
+            }
+        }
+        if (!Pol::KFAST && tid < QS) sWs[tid] = S(sW[tid]);
+        __syncthreads();
+        // MFMA over the slab
+#pragma unroll
+        for (int t = 0; t < PPW; t++) {
+            if (!pok[t]) continue;
+            const int ra = pta[t] * 16 + i16, rb = ptb[t] * 16 + i16;
+            for (int k0 = 0; k0 < QS; k0 += Pol::KM) {
+                if constexpr (Pol::KFAST) {
+                    using V = typename Pol::V;
+                    V av[DIM], bv[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) {
+                        av[c] = *reinterpret_cast<const V *>(&sG[c][ra][k0 + 8 * g4]);
+                        bv[c] = *reinterpret_cast<const V *>(&sH[c][rb][k0 + 8 * g4]);
+                    }
+                    if (PROB == 0) {
+#pragma unroll
+                        for (int c = 0; c < DIM; c++) acc[t][0] = Pol::mma(av[c], bv[c], acc[t][0]);
+                    } else {
+#pragma unroll
+                        for (int c1 = 0; c1 < DIM; c1++)
+#pragma unroll
+                            for (int c2 = 0; c2 < DIM; c2++)
+                                acc[t][c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[t][c1 * DIM + c2]);
+                    }
+                } else {
+                    const int kq = k0 + g4;
+                    const S wk = sWs[kq];
+                    S av[DIM], bv[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) {
+                        av[c] = sG[c][kq][ra];
+                        bv[c] = wk * sG[c][kq][rb];
+                    }
+                    if (PROB == 0) {
+#pragma unroll
+                        for (int c = 0; c < DIM; c++) acc[t][0] = Pol::mma(av[c], bv[c], acc[t][0]);
+                    } else {
+#pragma unroll
+                        for (int c1 = 0; c1 < DIM; c1++)
+#pragma unroll
+                            for (int c2 = 0; c2 < DIM; c2++)
+                                acc[t][c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[t][c1 * DIM + c2]);
+                    }
+                }
+            }
+        }
+        // load vector (FP64, VALU) on the part-0 workgroup
+        if (do_load) {
+#pragma unroll
+            for (int t = 0; t < (NNP * NC + 255) / 256; t++) {
+                const int row = tid + 256 * t;
+                if (row < nloc) {
+                    const int a = row / NC, c = row % NC;
+                    const int n0 = a % k1, n1 = (a / k1) % k1, n2 = a / (k1 * k1);
+                    for (int qq = 0; qq < qn; qq++) {
+                        const int q = q0s + qq;
+                        const int b0 = q % k1, b1 = (q / k1) % k1, b2 = q / (k1 * k1);
+                        const double phi = sL[n0 * k1 + b0] * sL[n1 * k1 + b1] * sL[n2 * k1 + b2];
+                        const double xq[3] = {sXq[qq][0], sXq[qq][1], sXq[qq][2]};
+                        facc[t] += sWd[qq] * source_value_mf(p, xq, c) * phi;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && sBad) atomicOr(m.status, 1);
+    const double unscale = 1.0 / (alpha * beta);
+    Out *Ec = E + cell * int64_t(nloc) * nloc;
+#pragma unroll
+    for (int t = 0; t < PPW; t++) {
+        if (!pok[t]) continue;
+        const int col = ptb[t] * 16 + i16;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = pta[t] * 16 + (Pol::ROW_INTERLEAVED ? 4 * r + g4 : 4 * g4 + r);
+            if (row >= nn || col >= nn) continue;
+            // on a diagonal tile only the upper triangle is taken, and mirrored,
+            // so the element matrix is exactly symmetric in every precision
+            const bool diag = pta[t] == ptb[t];
+            if (diag && row > col) continue;
+            if (PROB == 0) {
+                const Out v = Out(double(acc[t][0][r]) * unscale);
+                Ec[int64_t(row) * nloc + col] = v;
+                if (row != col) Ec[int64_t(col) * nloc + row] = v;
+            } else {
+                double tr = 0.0;
+#pragma unroll
+                for (int l = 0; l < DIM; l++) tr += double(acc[t][l * DIM + l][r]);
+#pragma unroll
+                for (int c1 = 0; c1 < DIM; c1++)
+#pragma unroll
+                    for (int c2 = 0; c2 < DIM; c2++) {
+                        if (row == col && c1 > c2) continue;
+                        double v = p.lambda * double(acc[t][c1 * DIM + c2][r]) + p.mu * double(acc[t][c2 * DIM + c1][r]);
+                        if (c1 == c2) v += p.mu * tr;
+                        const Out o = Out(v * unscale);
+                        Ec[int64_t(row * NC + c1) * nloc + col * NC + c2] = o;
+                        if (row != col || c1 != c2) Ec[int64_t(col * NC + c2) * nloc + row * NC + c1] = o;
+                    }
+            }
+        }
+    }
+    if (do_load) {
+#pragma unroll
+        for (int t = 0; t < (NNP * NC + 255) / 256; t++) {
+            const int row = tid + 256 * t;
+            if (row < nloc) F[cell * nloc + row] = facc[t];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch: (order, problem) -> padded node count, pairs per wave, parts per cell
+// ---------------------------------------------------------------------------
+template <class Pol, int PROB, int NNP, int PPW, int QS>
+static fe_status launch_one(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                            void *E, double *F, hipStream_t s)
+{
+    constexpr int NT = NNP / 16, NP = NT * (NT + 1) / 2;
+    const int parts = (NP + 4 * PPW - 1) / (4 * PPW);
+    const int64_t grid = sa.ncells * parts;
+    if (grid == 0) return FE_OK;
+    hipLaunchKernelGGL((k3_mfma_kernel<Pol, PROB, NNP, PPW, QS>), dim3(grid), dim3(256), 0, s, sa, ma, pa, rt, parts,
+                       static_cast<typename Pol::Out *>(E), F);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+template <class Pol>
+static fe_status launch_pol(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                            void *E, double *F, hipStream_t s)
+{
+    constexpr int QS = Pol::KFAST ? 32 : 16;
+    const bool el = pa.problem == FE_ELASTICITY;
+    switch (sa.k) {
+        case 2: return el ? launch_one<Pol, 1, 32, 1, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 32, 1, QS>(sa, ma, pa, rt, E, F, s);
+        case 3: return el ? launch_one<Pol, 1, 64, 2, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 64, 3, QS>(sa, ma, pa, rt, E, F, s);
+        case 4: return el ? launch_one<Pol, 1, 128, 2, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 128, 9, QS>(sa, ma, pa, rt, E, F, s);
+        default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
+    }
+}
+
+fe_status launch_integrate_mfma(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                                void *E, double *F, hipStream_t s)
+{
+    switch (pa.precision) {
+        case FE_FP64: return launch_pol<PolF64>(sa, ma, pa, rt, E, F, s);
+        case FE_FP32: return launch_pol<PolF32>(sa, ma, pa, rt, E, F, s);
+        case FE_FP16: return launch_pol<PolF16>(sa, ma, pa, rt, E, F, s);
+        default: return launch_pol<PolBF16>(sa, ma, pa, rt, E, F, s);
+    }
+}
+
+}  // namespace fe

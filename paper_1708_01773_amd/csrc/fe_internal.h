@@ -124,6 +124,8 @@ void ref_tables(int k, RefTables &t);
 ElemLayout elem_layout(const SpaceArgs &sa, int precision);
 fe_status launch_integrate(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
                            const ElemLayout &el, void *ws, hipStream_t s);
+fe_status launch_integrate_mfma(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                                void *E, double *F, hipStream_t s);
 fe_status launch_lift(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const int32_t *cell_dofs,
                       const ElemLayout &el, void *ws, hipStream_t s);
 

@@ -1,0 +1,63 @@
+"""Reduced-precision element integration (FP32, and FP16 / BF16 inputs with
+FP32 accumulation) against the FP64 oracle.
+
+Error model: each GEMM operand is rounded once (unit roundoff u: FP32 6.0e-8,
+FP16 4.9e-4, BF16 3.9e-3), products are exact in FP32 and summed in FP32 over
+K <= 3 nq terms.  Per entry |dE| <= (2u + K u32) sum_k |G_ka||H_kb|, and the
+sums of absolute values exceed |E| by a cancellation factor c (rows of a
+stiffness matrix sum to zero; c is a few units).  With c <= 8 the relative
+Frobenius error is bounded by 8 (2u + K u32): FP32 2e-4, FP16 1e-2, BF16
+7e-2 (K = 375 at Q4).  The CSR structure is unchanged (bit-exact) and the
+load vector stays FP64."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1708_01773_amd import fe as F
+from tests.gpu_util import MATRIX_RTOL, Pair, element_matrices, rel, say
+
+pytestmark = pytest.mark.gpu
+
+U = {"fp32": 6.0e-8, "fp16": 4.9e-4, "bf16": 3.9e-3}
+
+
+def bound(prec, K):
+    return 8.0 * (2 * U[prec] + K * U["fp32"])
+
+
+CASES = [(1, "poisson", [5, 4, 3]), (2, "poisson", [3, 2, 2]), (3, "poisson", [2, 2, 2]), (4, "poisson", [2, 1, 2]),
+         (2, "elasticity", [2, 2, 2]), (3, "elasticity", [2, 1, 2]), (4, "elasticity", [1, 1, 2])]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("k,prob,n", CASES)
+def test_reduced_precision_elements(prec, k, prob, n):
+    say(f"[precision] {prec} k={k} {prob} n={n}")
+    pair = Pair(3, n, k, prob, precision=prec, source=(1.0, 0.0, -1.0))
+    A = pair.gpu_assembly()
+    cells = list(range(pair.P.ncells))
+    Es, Fl = element_matrices(pair, A, cells)
+    worst = 0.0
+    for c, E in zip(cells, Es):
+        assert np.array_equal(E, E.T), "element matrix must be exactly symmetric"
+        worst = max(worst, rel(E, pair.oracle_element(c)))
+    K = (3 if prob == "poisson" else 1) * (k + 1) ** 3
+    say(f"   worst element rel err {worst:.2e} (bound {bound(prec, K):.1e})")
+    assert worst <= bound(prec, K)
+    # the structure is the same as FP64, the load vector stays FP64
+    S = pair.system
+    np.testing.assert_array_equal(A.rowptr.cpu().numpy(), S.rowptr)
+    np.testing.assert_array_equal(A.colind.cpu().numpy(), S.colind)
+    assert rel(A.rhs.cpu().numpy(), S.rhs) <= MATRIX_RTOL
+    ev = rel(A.values.cpu().numpy(), S.values)
+    say(f"   CSR values rel err {ev:.2e}")
+    assert ev <= bound(prec, K)
+
+
+def test_fp64_matrix_cores_are_deterministic():
+    pair = Pair(3, [3, 3, 2], 3, "elasticity")
+    A = pair.gpu_assembly()
+    v1 = A.values.clone()
+    A.assemble()
+    torch.cuda.synchronize()
+    assert torch.equal(v1, A.values)
