@@ -30,6 +30,12 @@ WORKLOADS = {
                text="3D Poisson -div(k grad u) = 1 on the unit cube, 128^3 Q1 hexes, interior vertices jittered "
                     "+-0.2h (seed 17080), lognormal per-cell k (seed 17081), u = 0 on the boundary, FP64 assembly "
                     "+ Jacobi-PCG to rtol 1e-10"),
+    "c3q2": dict(dim=3, n=48, k=2, problem="elasticity", precision="fp64", rtol=1e-10, lognormal=False,
+                 text="3D linear elasticity (E = 1, nu = 0.3), 48^3 Q2 hexes, jittered +-0.2h, f = (0,0,-1), clamped"),
+    "c3q3": dict(dim=3, n=32, k=3, problem="elasticity", precision="fp64", rtol=1e-10, lognormal=False,
+                 text="3D linear elasticity (E = 1, nu = 0.3), 32^3 Q3 hexes, jittered +-0.2h, f = (0,0,-1), clamped"),
+    "c3q4": dict(dim=3, n=24, k=4, problem="elasticity", precision="fp64", rtol=1e-10, lognormal=False,
+                 text="3D linear elasticity (E = 1, nu = 0.3), 24^3 Q4 hexes, jittered +-0.2h, f = (0,0,-1), clamped"),
     "c1": dict(dim=2, n=32, k=1, problem="poisson", precision="fp64", rtol=1e-10, jitter=0.0, lognormal=False,
                source_kind=2,
                text="2D Poisson on the unit square, 32^2 Q1 quads, k = 1, f = 2 pi^2 sin(pi x) sin(pi y), u = 0, "
@@ -96,6 +102,45 @@ def cpu_baseline(wl, gpu_iters, ncells_full, nnz_full):
     }
 
 
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+
+
+def k3_flops(wl, ncells):
+    """Algorithmic flops of element integration: Poisson 2 nn^2 d nq, elasticity
+    18 nn^2 nq per cell (geometry excluded)."""
+    d, k = wl["dim"], wl["k"]
+    nn = nq = (k + 1) ** d
+    per = 18 * nn * nn * nq if wl["problem"] == "elasticity" else 2 * nn * nn * d * nq
+    return per * ncells
+
+
+def assemble_only(args, wl, A, ncells, F, torch):
+    for _ in range(args.warmup):
+        A.assemble()
+    torch.cuda.synchronize()
+    F.set_timing(True)
+    F.get_timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        A.assemble()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    tm = F.get_timing(reset=True)
+    F.set_timing(False)
+    k3 = tm["integrate_ms"] / max(tm["integrate_calls"], 1) * 1e-3
+    k5 = tm["scatter_ms"] / max(tm["scatter_calls"], 1) * 1e-3
+    fl = k3_flops(wl, ncells)
+    peak = PEAK_TFLOPS[wl["precision"]]
+    out = {"metric": "hex elements assembled/s (assembly only)", "value": ncells * args.steps / total,
+           "unit": "elements/s", "steps": args.steps, "ms_per_step": total / args.steps * 1e3,
+           "dtype": wl["precision"], "config": {"workload": wl["text"], "cells": ncells, "order": wl["k"],
+                                                "dofs": A.n_rows, "nnz": A.nnz},
+           "k3": {"ms": k3 * 1e3, "algorithmic_tflops": fl / k3 / 1e12, "peak_tflops": peak,
+                  "frac": fl / k3 / 1e12 / peak},
+           "k5": {"ms": k5 * 1e3}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +148,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=None, help="override cells per axis (development)")
+    ap.add_argument("--k", type=int, default=None, help="override the order (development)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp16", "bf16"],
+                    help="element-GEMM precision (the solve stays FP64)")
+    ap.add_argument("--phase", default="step", choices=["step", "assemble"],
+                    help="step = assemble + PCG (default); assemble = assembly only, K3 against the matrix-core peak")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -130,14 +180,18 @@ def main():
     wl = dict(WORKLOADS[args.workload])
     if args.n:
         wl["n"] = args.n
+    if args.k:
+        wl["k"] = args.k
+    if args.precision:
+        wl["precision"] = args.precision
     dim, n, k = wl["dim"], wl["n"], wl["k"]
     torch.cuda.set_device(0)
     v = structured_vertices(dim, n, jitter=wl.get("jitter", 0.2))
     ncells = n ** dim
     coef = lognormal_coefficients(ncells) if wl.get("lognormal", True) else None
     mesh = F.create_mesh(dim, [n] * dim, v, coef)
-    coeff = F.make_coeff(wl["problem"], wl["precision"], source_kind=wl.get("source_kind", 1), source=(1.0,),
-                         dim=dim)
+    src = (0.0, 0.0, -1.0) if wl["problem"] == "elasticity" else (1.0,)
+    coeff = F.make_coeff(wl["problem"], wl["precision"], source_kind=wl.get("source_kind", 1), source=src, dim=dim)
     A = F.Assembly(mesh, k, coeff)
     A.pattern()
     ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
@@ -145,6 +199,8 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] set-up done: cells={ncells} rows={A.n_rows} nnz={A.nnz}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
+    if args.phase == "assemble":
+        return assemble_only(args, wl, A, ncells, F, torch)
 
     def step():
         e0 = torch.cuda.Event(enable_timing=True)
