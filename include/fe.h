@@ -206,8 +206,58 @@ fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes);
 fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
                        size_t ws_bytes, fe_solve_info *info, fe_stream stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched solve: many independent systems in one sequence of launches       */
+/* ------------------------------------------------------------------------ */
+/* Workspace bytes fe_pcg_solve_batch needs for nprob systems of n_rows[i]
+ * unknowns (host array). */
+fe_status fe_pcg_batch_query(int32_t nprob, const int64_t *n_rows, size_t *ws_bytes);
+
+/* The Jacobi-PCG of fe_pcg_solve (Sect. 12) applied to nprob independent
+ * systems at once: every kernel launch covers all systems, each owning its
+ * own range of workgroups, partial sums and iteration state, and chunks of
+ * iterations are replayed from a captured HIP graph.  A, b, x and infos are
+ * host arrays of nprob entries; A[i] is a device CSR with dinv filled, b[i]
+ * and x[i] device vectors of A[i].n_rows (x[i]: x0 on entry, solution on
+ * exit).  Each system stops on its own criterion ||r|| <= rtol ||b|| or at
+ * maxit; its result is bitwise the same as that of fe_pcg_solve on it alone
+ * (same kernels, same reduction order).  Systems with n_rows == 0 are
+ * skipped.  Synchronizes before returning; returns FE_OK if every system
+ * converged, else the first failing status (infos[i].status per system).
+ * infos[i].lambda_*_est are filled only when nprob == 1. */
+fe_status fe_pcg_solve_batch(int32_t nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
+                             int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, fe_stream stream);
+
 /* y = A x (device vectors).  Enqueues only. */
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Mixed precision: iterative refinement                                     */
+/* ------------------------------------------------------------------------ */
+/* values32[j] = (float) A->values[j] (device, nnz floats).  Enqueues only. */
+fe_status fe_csr_to_fp32(const fe_csr *A, float *values32, fe_stream stream);
+
+typedef struct {
+    int32_t outer_iters;  /* corrections applied */
+    int32_t inner_iters;  /* CG iterations summed over the corrections */
+    int32_t status;       /* FE_OK or FE_ENOTCONV */
+    double relres;        /* ||b - A_hi x|| / ||b|| in FP64 at exit */
+} fe_refine_info;
+
+/* Workspace bytes fe_refine_solve needs for n_rows unknowns. */
+fe_status fe_refine_query(int64_t n_rows, size_t *ws_bytes);
+
+/* Solves A_hi x = b to ||b - A_hi x||_2 <= rtol ||b||_2 by iterative
+ * refinement: the residual is formed in FP64 with A_hi; each correction d
+ * solves A_lo d = r approximately by Jacobi-PCG to inner_rtol (at most
+ * max_inner iterations) and x += d.  A_lo has the pattern of A_hi; its values
+ * are read from values32 (FP32) when that pointer is not NULL, otherwise from
+ * A_lo->values (for example a matrix assembled with reduced-precision element
+ * integration); A_lo->dinv is its Jacobi diagonal.  x holds x0 on entry.
+ * Synchronizes; returns info->status. */
+fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *values32, const double *b, double *x,
+                          double rtol, double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws,
+                          size_t ws_bytes, fe_refine_info *info, fe_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (for benchmarks)                                            */

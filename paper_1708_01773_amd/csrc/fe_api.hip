@@ -408,7 +408,7 @@ fe_status fe_get_status(fe_mesh m)
 fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes)
 {
     if (n_rows < 0 || !ws_bytes) return set_error(FE_EINVAL, "bad argument");
-    *ws_bytes = pcg_ws_bytes(n_rows);
+    *ws_bytes = pcg_solve_ws_bytes(n_rows);
     return FE_OK;
 }
 
@@ -421,11 +421,62 @@ fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol,
     return pcg_solve(A, b, x, rtol, maxit, ws, ws_bytes, info, as_stream(stream));
 }
 
+fe_status fe_pcg_batch_query(int32_t nprob, const int64_t *n_rows, size_t *ws_bytes)
+{
+    if (nprob < 0 || (nprob > 0 && !n_rows) || !ws_bytes) return set_error(FE_EINVAL, "bad argument");
+    for (int i = 0; i < nprob; i++)
+        if (n_rows[i] < 0) return set_error(FE_EINVAL, "negative n_rows");
+    *ws_bytes = pcg_batch_ws_bytes(nprob, n_rows);
+    return FE_OK;
+}
+
+fe_status fe_pcg_solve_batch(int32_t nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
+                             int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, fe_stream stream)
+{
+    if (nprob < 0) return set_error(FE_EINVAL, "negative nprob");
+    if (nprob == 0) return FE_OK;
+    if (!A || !b || !x || !ws || !infos) return set_error(FE_EINVAL, "null argument");
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    for (int i = 0; i < nprob; i++) {
+        if (A[i].n_rows < 0 || A[i].nnz < 0) return set_error(FE_EINVAL, "negative size");
+        if (A[i].n_rows > 0 && (!A[i].rowptr || !A[i].colind || !A[i].values || !A[i].dinv || !b[i] || !x[i]))
+            return set_error(FE_EINVAL, "incomplete csr or null vector");
+    }
+    return pcg_solve_batch(nprob, A, b, x, rtol, maxit, ws, ws_bytes, infos, as_stream(stream));
+}
+
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream)
 {
     if (!A || !x || !y || !A->rowptr || !A->colind || !A->values) return set_error(FE_EINVAL, "null argument");
     const double npr = A->n_rows > 0 ? double(A->nnz) / double(A->n_rows) : 1.0;
     return launch_spmv(A->n_rows, A->rowptr, A->colind, A->values, x, y, npr, as_stream(stream));
+}
+
+fe_status fe_csr_to_fp32(const fe_csr *A, float *values32, fe_stream stream)
+{
+    if (!A || !values32 || (A->nnz > 0 && !A->values)) return set_error(FE_EINVAL, "null argument");
+    return csr_to_fp32(A, values32, as_stream(stream));
+}
+
+fe_status fe_refine_query(int64_t n_rows, size_t *ws_bytes)
+{
+    if (n_rows < 0 || !ws_bytes) return set_error(FE_EINVAL, "bad argument");
+    *ws_bytes = refine_ws_bytes(n_rows);
+    return FE_OK;
+}
+
+fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *values32, const double *b, double *x,
+                          double rtol, double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws,
+                          size_t ws_bytes, fe_refine_info *info, fe_stream stream)
+{
+    if (!A_hi || !A_lo || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    if (!A_hi->rowptr || !A_hi->colind || !A_hi->values || !A_lo->rowptr || !A_lo->colind || !A_lo->dinv ||
+        (!values32 && !A_lo->values))
+        return set_error(FE_EINVAL, "incomplete csr");
+    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || max_outer < 0 || max_inner < 1)
+        return set_error(FE_EINVAL, "bad tolerances or iteration limits");
+    return refine_solve(A_hi, A_lo, values32, b, x, rtol, inner_rtol, max_outer, max_inner, ws, ws_bytes, info,
+                        as_stream(stream));
 }
 
 fe_status fe_set_timing(int32_t enable)

@@ -137,8 +137,17 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
 size_t pcg_ws_bytes(int64_t n);
 fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
                       double *y, double nnz_per_row, hipStream_t s);
+size_t pcg_solve_ws_bytes(int64_t n);
 fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
                     fe_solve_info *info, hipStream_t s);
+size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows);
+fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
+                          int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s);
+size_t refine_ws_bytes(int64_t n);
+fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s);
+fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,
+                       double rtol, double inner_rtol, int max_outer, int max_inner, void *ws, size_t ws_bytes,
+                       fe_refine_info *info, hipStream_t s);
 
 // Kernel timing (fe_set_timing / fe_get_timing): event pairs recorded on the
 // launching stream around timed kernels.

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "fe_internal.h"
@@ -39,7 +40,9 @@ constexpr int kWaveCap = 256;   // products staged in LDS per wave (2 KB)
 struct PcgState {
     double rho[2];  // rho_j in slot j & 1
     double bb, rr, true_rr;
-    int32_t iter, done, status, pad;
+    int32_t iter;      // current iteration j (advanced by the dir kernel)
+    int32_t iter_upd;  // j as seen by the update kernel, read by the dir kernel
+    int32_t done, status;
 };
 
 struct PcgWs {
@@ -49,6 +52,20 @@ struct PcgWs {
     double *p3;    // 3 x kGrid partials of the initial r.z, r.r, b.b (and the final residual)
     double *hist;  // 2 x kHist (alpha, beta)
     double *r, *p, *q;
+};
+
+// One problem of a (possibly batched) solve, as the kernels see it.
+struct PcgProb {
+    int64_t n, nnz;
+    const int64_t *rowptr;
+    const int32_t *colind;
+    const void *val;
+    const double *dinv, *b;
+    double *x;
+    PcgWs w;
+    double rtol2;
+    int32_t maxit;
+    int32_t nbr, nbe;  // blocks of the row kernels / of the vector kernels
 };
 
 // How a CSR matrix is traversed.
@@ -88,6 +105,7 @@ static PcgWs carve(void *ws, int64_t n)
     return w;
 }
 
+// Device slot for the problem table of a single-problem solve (inside its workspace).
 static SpmvPlan plan_for(int64_t n, int64_t nnz)
 {
     const double avg = n > 0 ? double(nnz) / double(n) : 1.0;
@@ -168,9 +186,9 @@ __device__ __forceinline__ void reduce_partials(const double *part, int nparts, 
 // ---------------------------------------------------------------------------
 // Row traversal
 // ---------------------------------------------------------------------------
-template <int L>
+template <int L, typename VT>
 __device__ __forceinline__ double row_dot(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
-                                          const double *__restrict__ val, const double *__restrict__ x, int64_t row,
+                                          const VT *__restrict__ val, const double *__restrict__ x, int64_t row,
                                           int lane)
 {
     const int64_t b = rowptr[row], e = rowptr[row + 1];
@@ -182,13 +200,13 @@ __device__ __forceinline__ double row_dot(const int64_t *__restrict__ rowptr, co
         int32_t c[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            v[u] = val[j + u * L];
+            v[u] = double(val[j + u * L]);
             c[u] = colind[j + u * L];
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) s += v[u] * x[c[u]];
     }
-    for (; j < e; j += L) s += val[j] * x[colind[j]];
+    for (; j < e; j += L) s += double(val[j]) * x[colind[j]];
     return butterfly<L>(s);
 }
 
@@ -204,23 +222,24 @@ __device__ __forceinline__ void wave_lds_sync()
 // lane of the row's lane group).  Wave-level CSR-stream: the rows are cut
 // into runs of RPW; run t is handled by logical wave t mod (number of waves),
 // so the waves active at any moment work on neighbouring rows and share the
-// gathered entries of x in cache (blocks are renumbered so that a contiguous
-// range of logical waves runs on one XCD).  A wave loads the run's RPW + 1 row
-// pointers with one coalesced load, stages the products of the run in its own
-// LDS slice with coalesced loads of values and column indices, then
-// LW = 64 / RPW lanes per row sum them.  A run longer than the slice is summed
-// straight from memory in the same lane order.
-template <int RPW, typename Fn>
+// gathered entries of x in cache (the single-problem launch renumbers blocks
+// so that a contiguous range of logical waves runs on one XCD).  A wave loads
+// the run's RPW + 1 row pointers with one coalesced load, stages the products
+// of the run in its own LDS slice with coalesced loads of values and column
+// indices, then LW = 64 / RPW lanes per row sum them.  A run longer than the
+// slice is summed straight from memory in the same lane order.
+// lb / nb: this block's index among the nb blocks working on the matrix.
+template <int RPW, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__restrict__ rowptr,
-                                                 const int32_t *__restrict__ colind, const double *__restrict__ val,
-                                                 const double *__restrict__ x, Fn f)
+                                                 const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                                 const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
 {
     constexpr int LW = 64 / RPW;
     __shared__ double prod[kWaves][kWaveCap];
     double *my = prod[threadIdx.x / 64];
     const int lane = threadIdx.x % 64, grp = lane / LW, sub = lane % LW;
-    const int64_t nw = int64_t(gridDim.x) * kWaves;
-    const int64_t lw = xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
+    const int64_t nw = nb * kWaves;
+    const int64_t lw = lb * kWaves + threadIdx.x / 64;
     const int64_t runs = (n + RPW - 1) / RPW;
     for (int64_t run = lw; run < runs; run += nw) {
         const int64_t r0 = run * RPW;
@@ -231,14 +250,14 @@ __device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__res
         const int64_t row = r0 + grp;
         double s = 0.0;
         if (end - base <= kWaveCap) {
-            for (int64_t j = base + lane; j < end; j += 64) my[j - base] = val[j] * x[colind[j]];
+            for (int64_t j = base + lane; j < end; j += 64) my[j - base] = double(val[j]) * x[colind[j]];
             wave_lds_sync();
             if (row < r1)
                 for (int64_t t = rb - base + sub; t < re - base; t += LW) s += my[t];
             s = butterfly<LW>(s);
             wave_lds_sync();
         } else if (row < r1) {
-            for (int64_t j = rb + sub; j < re; j += LW) s += val[j] * x[colind[j]];
+            for (int64_t j = rb + sub; j < re; j += LW) s += double(val[j]) * x[colind[j]];
             s = butterfly<LW>(s);
         }
         if (row < r1 && sub == 0) f(row, s);
@@ -246,13 +265,13 @@ __device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__res
 }
 
 // One wave per row (long rows), 64 lanes.
-template <typename Fn>
+template <typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ colind, const double *__restrict__ val,
-                                              const double *__restrict__ x, Fn f)
+                                              const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                              const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
 {
-    const int64_t nw = int64_t(gridDim.x) * kWaves;
-    const int64_t lw = xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
+    const int64_t nw = nb * kWaves;
+    const int64_t lw = lb * kWaves + threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     for (int64_t row = lw; row < n; row += nw) {
         const double s = row_dot<64>(rowptr, colind, val, x, row, lane);
@@ -278,65 +297,101 @@ __device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restri
         }                                                          \
     } while (0)
 
-template <int MODE, int RPW, typename Fn>
-__device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val,
-                                         const double *x, Fn f)
+template <int MODE, int RPW, typename VT, typename Fn>
+__device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const VT *val,
+                                         const double *x, int64_t lb, int64_t nb, Fn f)
 {
     if constexpr (MODE == 1)
-        for_rows_wave(n, rowptr, colind, val, x, f);
+        for_rows_wave(n, rowptr, colind, val, x, lb, nb, f);
     else
-        for_rows_wstream<RPW>(n, rowptr, colind, val, x, f);
+        for_rows_wstream<RPW, VT>(n, rowptr, colind, val, x, lb, nb, f);
+}
+
+// Problem of block blockIdx.x in a launch whose problem p owns blocks
+// [boff[p], boff[p+1]); returns the block's index within its problem.
+__device__ __forceinline__ int find_problem(const int32_t *__restrict__ boff, int nprob, int64_t &lb, int64_t &nb)
+{
+    int lo = 0, hi = nprob;  // boff[lo] <= b < boff[hi]
+    const int b = int(blockIdx.x);
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (boff[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    nb = boff[lo + 1] - boff[lo];
+    lb = b - boff[lo];
+    if (nprob == 1) lb = xcd_block(lb, nb);
+    return lo;
+}
+
+// Elements [lo, hi) of logical block lb of nb for the vector kernels.
+__device__ __forceinline__ void owned_elems(int64_t n, int64_t lb, int64_t nb, int64_t &lo, int64_t &hi)
+{
+    const int64_t per = ((n + nb - 1) / nb + 1) / 2 * 2;
+    lo = std::min<int64_t>(lb * per, n);
+    hi = std::min<int64_t>(lo + per, n);
 }
 
 // ---------------------------------------------------------------------------
-// Kernels
+// Kernels (every one serves any number of problems: problem p owns the blocks
+// [boff[p], boff[p+1]) of the launch)
 // ---------------------------------------------------------------------------
-template <int MODE, int RPB>
+template <int MODE, int RPB, typename VT>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, const int64_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ colind,
-                                                       const double *__restrict__ val, const double *__restrict__ x,
+                                                       const VT *__restrict__ val, const double *__restrict__ x,
                                                        double *__restrict__ y)
 {
-    for_rows<MODE, RPB>(n, rowptr, colind, val, x, [&](int64_t row, double s) { y[row] = s; });
+    for_rows<MODE, RPB, VT>(n, rowptr, colind, val, x, xcd_block(blockIdx.x, gridDim.x), gridDim.x,
+                            [&](int64_t row, double s) { y[row] = s; });
 }
 
 // r = b - A x; p = z = dinv r; partials of r.z, r.r, b.b
-template <int MODE, int RPB>
-__global__ __launch_bounds__(kBlock) void pcg_init_kernel(int64_t n, const int64_t *__restrict__ rowptr,
-                                                           const int32_t *__restrict__ colind,
-                                                           const double *__restrict__ val,
-                                                           const double *__restrict__ dinv,
-                                                           const double *__restrict__ b, const double *__restrict__ x,
-                                                           PcgWs w)
+template <int MODE, int RPB, typename VT>
+__global__ __launch_bounds__(kBlock) void pcg_init_kernel(const PcgProb *__restrict__ probs,
+                                                           const int32_t *__restrict__ boff, int nprob)
 {
+    int64_t lb, nb;
+    const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     double v[3] = {0.0, 0.0, 0.0};
-    for_rows<MODE, RPB>(n, rowptr, colind, val, x, [&](int64_t row, double ax) {
-        const double r = b[row] - ax;
-        const double z = dinv[row] * r;
-        w.r[row] = r;
-        w.p[row] = z;
-        v[0] += r * z;
-        v[1] += r * r;
-        v[2] += b[row] * b[row];
-    });
-    write_partials<3>(v, w.p3);
+    const double *__restrict__ b = P.b;
+    const double *__restrict__ dinv = P.dinv;
+    double *__restrict__ r = P.w.r;
+    double *__restrict__ pv = P.w.p;
+    for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), P.x, lb, nb,
+                            [&](int64_t row, double ax) {
+                                const double rr = b[row] - ax;
+                                const double z = dinv[row] * rr;
+                                r[row] = rr;
+                                pv[row] = z;
+                                v[0] += rr * z;
+                                v[1] += rr * rr;
+                                v[2] += b[row] * b[row];
+                            });
+    double t[3] = {v[0], v[1], v[2]};
+    block_sum_all<3>(t);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < 3; i++) P.w.p3[i * kGrid + lb] = t[i];
 }
 
-__global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(PcgWs w, int nparts, double rtol2, int maxit)
+// one block per problem: initial scalars and stop test
+__global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(const PcgProb *__restrict__ probs)
 {
+    const PcgProb &P = probs[blockIdx.x];
     double t[3];
-    reduce_partials<3>(w.p3, nparts, t);
+    reduce_partials<3>(P.w.p3, P.nbr, t);
     if (threadIdx.x == 0) {
-        PcgState *st = w.st;
+        PcgState *st = P.w.st;
         st->rho[0] = t[0];
         st->rr = t[1];
         st->bb = t[2];
         st->iter = 0;
+        st->iter_upd = 0;
         st->status = FE_OK;
         st->done = 0;
-        if (t[1] <= rtol2 * t[2]) {
+        if (t[1] <= P.rtol2 * t[2]) {
             st->done = 1;
-        } else if (maxit <= 0) {
+        } else if (P.maxit <= 0) {
             st->done = 1;
             st->status = FE_ENOTCONV;
         }
@@ -344,55 +399,56 @@ __global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(PcgWs w, int np
 }
 
 // q = A p; partials of p.q
-template <int MODE, int RPB>
-__global__ __launch_bounds__(kBlock) void pcg_spmv_kernel(int64_t n, const int64_t *__restrict__ rowptr,
-                                                           const int32_t *__restrict__ colind,
-                                                           const double *__restrict__ val, PcgWs w)
+template <int MODE, int RPB, typename VT>
+__global__ __launch_bounds__(kBlock) void pcg_spmv_kernel(const PcgProb *__restrict__ probs,
+                                                           const int32_t *__restrict__ boff, int nprob)
 {
-    if (w.st->done) return;
+    int64_t lb, nb;
+    const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
+    if (P.w.st->done) return;
     double v[1] = {0.0};
-    const double *__restrict__ p = w.p;
-    double *__restrict__ q = w.q;
-    for_rows<MODE, RPB>(n, rowptr, colind, val, p, [&](int64_t row, double s) {
-        q[row] = s;
-        v[0] += p[row] * s;
-    });
-    write_partials<1>(v, w.p1);
-}
-
-// Elements [lo, hi) of this block for the vector kernels.
-__device__ __forceinline__ void owned_elems(int64_t n, int64_t &lo, int64_t &hi)
-{
-    const int64_t nb = gridDim.x;
-    const int64_t lb = xcd_block(blockIdx.x, nb);
-    const int64_t per = ((n + nb - 1) / nb + 1) / 2 * 2;  // even, so double2 accesses stay aligned
-    lo = std::min<int64_t>(lb * per, n);
-    hi = std::min<int64_t>(lo + per, n);
+    const double *__restrict__ p = P.w.p;
+    double *__restrict__ q = P.w.q;
+    for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), p, lb, nb,
+                            [&](int64_t row, double s) {
+                                q[row] = s;
+                                v[0] += p[row] * s;
+                            });
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) P.w.p1[lb] = v[0];
 }
 
 // alpha = rho_j / p.q; x += alpha p; r -= alpha q; partials of r.z, r.r
-__global__ __launch_bounds__(kBlock) void pcg_update_kernel(int64_t n, int j, int nparts,
-                                                             const double *__restrict__ dinv, double *__restrict__ x,
-                                                             PcgWs w)
+__global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__restrict__ probs,
+                                                             const int32_t *__restrict__ boff, int nprob)
 {
-    if (w.st->done) return;
+    int64_t lb, nb;
+    const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
+    PcgState *st = P.w.st;
+    if (st->done) return;
+    const int j = st->iter;
     double pq[1];
-    reduce_partials<1>(w.p1, nparts, pq);
+    reduce_partials<1>(P.w.p1, P.nbr, pq);
     if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            w.st->done = 1;
-            w.st->status = FE_EBREAKDOWN;
+        if (lb == 0 && threadIdx.x == 0) {
+            st->done = 1;
+            st->status = FE_EBREAKDOWN;
         }
         return;
     }
-    const double alpha = w.st->rho[j & 1] / pq[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && j < kHist) w.hist[j] = alpha;
+    const double alpha = st->rho[j & 1] / pq[0];
+    if (lb == 0 && threadIdx.x == 0) {
+        st->iter_upd = j;
+        if (j < kHist) P.w.hist[j] = alpha;
+    }
     int64_t lo, hi;
-    owned_elems(n, lo, hi);
+    owned_elems(P.n, lb, nb, lo, hi);
     double v[2] = {0.0, 0.0};
-    const double *__restrict__ p = w.p;
-    const double *__restrict__ q = w.q;
-    double *__restrict__ r = w.r;
+    const double *__restrict__ p = P.w.p;
+    const double *__restrict__ q = P.w.q;
+    const double *__restrict__ dinv = P.dinv;
+    double *__restrict__ r = P.w.r;
+    double *__restrict__ x = P.x;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
@@ -400,58 +456,73 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(int64_t n, int j, in
         v[0] += ri * (dinv[i] * ri);
         v[1] += ri * ri;
     }
-    write_partials<2>(v, w.p2);
+    block_sum_all<2>(v);
+    if (threadIdx.x == 0) {
+        P.w.p2[lb] = v[0];
+        P.w.p2[kGrid + lb] = v[1];
+    }
 }
 
-// beta = rho_{j+1} / rho_j; convergence test; p = z + beta p
-__global__ __launch_bounds__(kBlock) void pcg_dir_kernel(int64_t n, int j, int nparts, double rtol2,
-                                                          const double *__restrict__ dinv, PcgWs w)
+// beta = rho_{j+1} / rho_j; stop test; p = z + beta p
+__global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restrict__ probs,
+                                                          const int32_t *__restrict__ boff, int nprob)
 {
-    if (w.st->done) return;
+    int64_t lb, nb;
+    const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
+    PcgState *st = P.w.st;
+    if (st->done) return;
+    const int j = st->iter_upd;
     double t[2];
-    reduce_partials<2>(w.p2, nparts, t);
-    const double rho_old = w.st->rho[j & 1];
+    reduce_partials<2>(P.w.p2, P.nbe, t);
+    const double rho_old = st->rho[j & 1];
     const double beta = t[0] / rho_old;
-    const bool conv = t[1] <= rtol2 * w.st->bb;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        PcgState *st = w.st;
+    const bool conv = t[1] <= P.rtol2 * st->bb;
+    if (lb == 0 && threadIdx.x == 0) {
         st->rho[(j + 1) & 1] = t[0];
         st->rr = t[1];
         st->iter = j + 1;
-        if (j < kHist) w.hist[kHist + j] = beta;
+        if (j < kHist) P.w.hist[kHist + j] = beta;
         if (conv) {
             st->done = 1;
             st->status = FE_OK;
+        } else if (j + 1 >= P.maxit) {
+            st->done = 1;
+            st->status = FE_ENOTCONV;
         }
     }
     if (conv) return;
     int64_t lo, hi;
-    owned_elems(n, lo, hi);
-    const double *__restrict__ r = w.r;
-    double *__restrict__ p = w.p;
+    owned_elems(P.n, lb, nb, lo, hi);
+    const double *__restrict__ r = P.w.r;
+    const double *__restrict__ dinv = P.dinv;
+    double *__restrict__ p = P.w.p;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) p[i] = dinv[i] * r[i] + beta * p[i];
 }
 
 // partials of (b - A x)^2
-template <int MODE, int RPB>
-__global__ __launch_bounds__(kBlock) void resid_kernel(int64_t n, const int64_t *__restrict__ rowptr,
-                                                        const int32_t *__restrict__ colind,
-                                                        const double *__restrict__ val, const double *__restrict__ b,
-                                                        const double *__restrict__ x, PcgWs w)
+template <int MODE, int RPB, typename VT>
+__global__ __launch_bounds__(kBlock) void resid_kernel(const PcgProb *__restrict__ probs,
+                                                        const int32_t *__restrict__ boff, int nprob)
 {
+    int64_t lb, nb;
+    const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     double v[1] = {0.0};
-    for_rows<MODE, RPB>(n, rowptr, colind, val, x, [&](int64_t row, double ax) {
-        const double d = b[row] - ax;
-        v[0] += d * d;
-    });
-    write_partials<1>(v, w.p3);
+    const double *__restrict__ b = P.b;
+    for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), P.x, lb, nb,
+                            [&](int64_t row, double ax) {
+                                const double d = b[row] - ax;
+                                v[0] += d * d;
+                            });
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) P.w.p3[lb] = v[0];
 }
 
-__global__ __launch_bounds__(kBlock) void resid_finish_kernel(PcgWs w, int nparts)
+__global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__restrict__ probs)
 {
+    const PcgProb &P = probs[blockIdx.x];
     double t[1];
-    reduce_partials<1>(w.p3, nparts, t);
-    if (threadIdx.x == 0) w.st->true_rr = t[0];
+    reduce_partials<1>(P.w.p3, P.nbr, t);
+    if (threadIdx.x == 0) P.w.st->true_rr = t[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -474,7 +545,7 @@ fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, c
     if (n == 0) return FE_OK;
     const SpmvPlan pl = plan_for(n, int64_t(nnz_per_row * double(n) + 0.5));
     const int g = grid_rows(n, pl);
-    FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb><<<dim3(g), dim3(kBlock), 0, s>>>(n, rowptr,
+    FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb, double><<<dim3(g), dim3(kBlock), 0, s>>>(n, rowptr,
                                              colind, val, x, y)));
     FE_HIP(hipGetLastError());
     return FE_OK;
@@ -525,81 +596,441 @@ struct PinnedState {
     }
 };
 
-fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
-                    fe_solve_info *info, hipStream_t s)
+// ---------------------------------------------------------------------------
+// PCG engine: any number of problems solved together.  Problems are grouped
+// by SpMV plan and value type (template parameters of the row kernels); the
+// vector kernels serve all problems in one launch.  Chunks of iterations are
+// launched directly or replayed from a captured HIP graph.
+// ---------------------------------------------------------------------------
+struct PcgJob {
+    int64_t n, nnz;
+    const int64_t *rowptr;
+    const int32_t *colind;
+    const void *val;
+    bool fp32;  // values stored as float
+    const double *dinv, *b;
+    double *x;
+    void *ws;
+    fe_solve_info *info;
+};
+
+__global__ __launch_bounds__(kBlock) void count_active_kernel(const PcgProb *__restrict__ probs, int nprob,
+                                                               int32_t *active)
 {
-    const int64_t n = A->n_rows;
-    if (ws_bytes < pcg_ws_bytes(n)) return set_error(FE_EINVAL, "pcg workspace too small");
+    __shared__ int32_t cnt[kBlock];
+    int32_t c = 0;
+    for (int i = threadIdx.x; i < nprob; i += kBlock) c += probs[i].w.st->done ? 0 : 1;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int i = 0; i < kBlock; i++) t += cnt[i];
+        *active = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void gather_states_kernel(const PcgProb *__restrict__ probs, int nprob,
+                                                                PcgState *out)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nprob; i += gridDim.x * kBlock) out[i] = *probs[i].w.st;
+}
+
+size_t pcg_table_bytes(int nprob)
+{
+    return align256(sizeof(PcgProb) * size_t(nprob)) + align256(sizeof(int32_t) * (3 * size_t(nprob) + 16)) +
+           align256(sizeof(PcgState) * size_t(nprob)) + 256;
+}
+
+struct Group {
+    SpmvPlan pl;
+    bool fp32;
+    int first, count;  // problems [first, first + count) of the sorted table
+    int32_t *d_boff;   // count + 1 block offsets of the row kernels
+    int grid;
+};
+
+template <typename VT>
+static void launch_rows_group(int which, const Group &g, const PcgProb *probs, hipStream_t s)
+{
+    const PcgProb *tp = probs + g.first;
+    switch (which) {
+        case 0:
+            FE_PLAN_DISPATCH(g.pl, (pcg_init_kernel<kMode, kRpb, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count)));
+            break;
+        case 1:
+            FE_PLAN_DISPATCH(g.pl, (pcg_spmv_kernel<kMode, kRpb, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count)));
+            break;
+        default:
+            FE_PLAN_DISPATCH(g.pl, (resid_kernel<kMode, kRpb, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count)));
+            break;
+    }
+}
+
+static void launch_rows(int which, const Group &g, const PcgProb *probs, hipStream_t s)
+{
+    if (g.fp32) launch_rows_group<float>(which, g, probs, s);
+    else launch_rows_group<double>(which, g, probs, s);
+}
+
+// Stream on which iteration chunks are captured (one per thread and device):
+// capture only records launches, and the caller's stream may be the null
+// stream, which cannot be captured.  The graph is launched on the caller's
+// stream.
+static fe_status capture_stream(hipStream_t &out)
+{
+    static thread_local std::vector<hipStream_t> streams;
+    int dev = 0;
+    FE_HIP(hipGetDevice(&dev));
+    if (int(streams.size()) <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) FE_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    out = streams[dev];
+    return FE_OK;
+}
+
+static fe_status pcg_engine(std::vector<PcgJob> &jobs, double rtol, int maxit, void *table, bool use_graph,
+                            hipStream_t s)
+{
+    const int nprob = int(jobs.size());
+    for (PcgJob &jb : jobs) std::memset(jb.info, 0, sizeof(fe_solve_info));
+    // order: problems with work, grouped by (plan, value type)
+    std::vector<int> order;
+    std::vector<SpmvPlan> plans(nprob);
+    for (int i = 0; i < nprob; i++) {
+        plans[i] = plan_for(jobs[i].n, jobs[i].nnz);
+        if (jobs[i].n > 0) order.push_back(i);
+        else jobs[i].info->status = FE_OK;
+    }
+    auto key = [&](int i) { return (plans[i].mode * 64 + plans[i].rpb) * 2 + (jobs[i].fp32 ? 1 : 0); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    const int np = int(order.size());
+    if (np == 0) return FE_OK;
+    // device table: probs | boff_e | group boffs | states
+    char *tb = static_cast<char *>(table);
+    PcgProb *d_probs = reinterpret_cast<PcgProb *>(tb);
+    int32_t *d_ints = reinterpret_cast<int32_t *>(tb + align256(sizeof(PcgProb) * size_t(np)));
+    PcgState *d_states = reinterpret_cast<PcgState *>(tb + align256(sizeof(PcgProb) * size_t(np)) +
+                                                      align256(sizeof(int32_t) * (3 * size_t(np) + 16)));
+    int32_t *d_active = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(d_states) +
+                                                    align256(sizeof(PcgState) * size_t(np)));
+    std::vector<PcgProb> hp(np);
+    std::vector<int32_t> hi(3 * size_t(np) + 16, 0);
+    std::vector<Group> groups;
+    const double rtol2 = rtol * rtol;
+    int32_t eoff = 0;
+    for (int t = 0; t < np; t++) {
+        const PcgJob &jb = jobs[order[t]];
+        PcgProb &P = hp[t];
+        P.n = jb.n;
+        P.nnz = jb.nnz;
+        P.rowptr = jb.rowptr;
+        P.colind = jb.colind;
+        P.val = jb.val;
+        P.dinv = jb.dinv;
+        P.b = jb.b;
+        P.x = jb.x;
+        P.w = carve(jb.ws, jb.n);
+        P.rtol2 = rtol2;
+        P.maxit = maxit;
+        const SpmvPlan &pl = plans[order[t]];
+        const int64_t runs = (jb.n + pl.rpb - 1) / pl.rpb;
+        P.nbr = int32_t(std::max<int64_t>(1, std::min<int64_t>(kGrid, (runs + kWaves - 1) / kWaves)));
+        P.nbe = int32_t(std::max<int64_t>(1, std::min<int64_t>(kGrid, (jb.n + kBlock - 1) / kBlock)));
+        hi[t] = eoff;
+        eoff += P.nbe;
+        if (groups.empty() || key(order[groups.back().first]) != key(order[t])) {
+            Group g{};
+            g.pl = pl;
+            g.fp32 = jb.fp32;
+            g.first = t;
+            g.count = 0;
+            groups.push_back(g);
+        }
+        groups.back().count++;
+    }
+    hi[np] = eoff;
+    const int ge = eoff;
+    int pos = np + 1;
+    std::vector<int> gpos(groups.size());
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        Group &g = groups[gi];
+        gpos[gi] = pos;
+        int32_t off = 0;
+        for (int t = 0; t < g.count; t++) {
+            hi[pos + t] = off;
+            off += hp[g.first + t].nbr;
+        }
+        hi[pos + g.count] = off;
+        g.grid = off;
+        g.d_boff = d_ints + pos;
+        pos += g.count + 1;
+    }
+    FE_HIP(hipMemcpyAsync(d_probs, hp.data(), sizeof(PcgProb) * size_t(np), hipMemcpyHostToDevice, s));
+    FE_HIP(hipMemcpyAsync(d_ints, hi.data(), sizeof(int32_t) * size_t(pos), hipMemcpyHostToDevice, s));
+    for (const Group &g : groups) launch_rows(0, g, d_probs, s);
+    hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(np), dim3(kBlock), 0, s, d_probs);
+    FE_HIP(hipGetLastError());
+
     static thread_local PinnedState pin;
     if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
-    PcgWs w = carve(ws, n);
-    std::memset(info, 0, sizeof(*info));
-    if (n == 0) {
-        info->status = FE_OK;
-        return FE_OK;
-    }
-    const SpmvPlan pl = plan_for(n, A->nnz);
-    const int gr = grid_rows(n, pl);
-    const int ge = grid_elems(n);
-    const double rtol2 = rtol * rtol;
-    FE_PLAN_DISPATCH(pl, (pcg_init_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(n,
-                                             A->rowptr, A->colind, A->values, A->dinv, b, x, w)));
-    hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr, rtol2, maxit);
-    FE_HIP(hipGetLastError());
-    int chunk = 8;
-    int j = 0;
-    // SpMV launches timed when timing is on; the ones issued after convergence
-    // (which exit at once) are dropped once the iteration count is known
+    int32_t *h_active = reinterpret_cast<int32_t *>(pin.h);
+    const bool timed = timing_on() && !use_graph && np == 1;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+    auto one_iteration = [&](hipStream_t q) {
+        for (const Group &g : groups) {
+            hipEvent_t t0 = timed ? timing_mark(q) : nullptr;
+            launch_rows(1, g, d_probs, q);
+            if (t0) marks.emplace_back(t0, timing_mark(q));
+        }
+        hipLaunchKernelGGL(pcg_update_kernel, dim3(ge), dim3(kBlock), 0, q, d_probs, d_ints, np);
+        hipLaunchKernelGGL(pcg_dir_kernel, dim3(ge), dim3(kBlock), 0, q, d_probs, d_ints, np);
+    };
+    struct GraphHold {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t e = nullptr;
+        ~GraphHold()
+        {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } hold;
+    hipGraphExec_t &exec = hold.e;
+    hipGraph_t &graph = hold.g;
+    const int gchunk = 16;
+    if (use_graph && maxit > 0) {
+        hipStream_t cs = nullptr;
+        fe_status cst = capture_stream(cs);
+        if (cst != FE_OK) return cst;
+        FE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < gchunk; i++) one_iteration(cs);
+        hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, cs, d_probs, np, d_active);
+        const hipError_t ce = hipStreamEndCapture(cs, &graph);
+        if (ce != hipSuccess) return set_error(FE_EDEVICE, "graph capture failed");
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            return set_error(FE_EDEVICE, "graph instantiation failed");
+    }
+    int j = 0, chunk = 8;
     while (j < maxit) {
-        for (int i = 0; i < chunk && j < maxit; i++, j++) {
-            hipEvent_t t0 = timing_mark(s);
-            FE_PLAN_DISPATCH(pl, (pcg_spmv_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(n, A->rowptr, A->colind, A->values, w)));
-            if (t0) marks.emplace_back(t0, timing_mark(s));
-            hipLaunchKernelGGL(pcg_update_kernel, dim3(ge), dim3(kBlock), 0, s, n, j, gr, A->dinv, x, w);
-            hipLaunchKernelGGL(pcg_dir_kernel, dim3(ge), dim3(kBlock), 0, s, n, j, ge, rtol2, A->dinv, w);
+        if (exec) {
+            FE_HIP(hipGraphLaunch(exec, s));
+            j += gchunk;
+        } else {
+            for (int i = 0; i < chunk && j < maxit; i++, j++) one_iteration(s);
+            hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, s, d_probs, np, d_active);
+            if (chunk < 128) chunk *= 2;
         }
         FE_HIP(hipGetLastError());
-        FE_HIP(hipMemcpyAsync(pin.h, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        FE_HIP(hipMemcpyAsync(h_active, d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         FE_HIP(hipStreamSynchronize(s));
-        if (pin.h->done) break;
-        if (chunk < 128) chunk *= 2;
+        if (*h_active == 0) break;
     }
-    FE_PLAN_DISPATCH(pl, (resid_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(n, A->rowptr,
-                                             A->colind, A->values, b, x, w)));
-    hipLaunchKernelGGL(resid_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr);
+    for (const Group &g : groups) launch_rows(2, g, d_probs, s);
+    hipLaunchKernelGGL(resid_finish_kernel, dim3(np), dim3(kBlock), 0, s, d_probs);
+    hipLaunchKernelGGL(gather_states_kernel, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d_probs, np,
+                       d_states);
     FE_HIP(hipGetLastError());
-    FE_HIP(hipMemcpyAsync(pin.h, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    std::vector<PcgState> hs(np);
+    FE_HIP(hipMemcpyAsync(hs.data(), d_states, sizeof(PcgState) * size_t(np), hipMemcpyDeviceToHost, s));
     FE_HIP(hipStreamSynchronize(s));
-    const PcgState st = *pin.h;
     for (size_t i = 0; i < marks.size(); i++) {
-        if (int(i) < st.iter) {
+        if (int(i) < hs[0].iter) {
             timing_commit(marks[i].first, marks[i].second, kTimeSpmv);
         } else {
             timing_release(marks[i].first);
             timing_release(marks[i].second);
         }
     }
-    info->iters = st.iter;
-    info->status = st.done ? st.status : FE_ENOTCONV;
-    const double bn = std::sqrt(st.bb);
-    info->relres = bn > 0 ? std::sqrt(st.rr) / bn : std::sqrt(st.rr);
-    info->true_relres = bn > 0 ? std::sqrt(st.true_rr) / bn : std::sqrt(st.true_rr);
-    const int m = std::min(st.iter, kHist);
-    if (m > 0) {
-        std::vector<double> h(2 * kHist);
-        FE_HIP(hipMemcpy(h.data(), w.hist, sizeof(double) * 2 * kHist, hipMemcpyDeviceToHost));
-        std::vector<double> d(m), e(m > 1 ? m - 1 : 1);
-        for (int i = 0; i < m; i++) {
-            const double a = h[i];
-            d[i] = 1.0 / a + (i > 0 ? h[kHist + i - 1] / h[i - 1] : 0.0);
-            if (i + 1 < m) e[i] = std::sqrt(h[kHist + i]) / a;
-        }
-        tridiag_extremes(d, e, info->lambda_min_est, info->lambda_max_est);
+    fe_status worst = FE_OK;
+    for (int t = 0; t < np; t++) {
+        const PcgState &st = hs[t];
+        fe_solve_info *info = jobs[order[t]].info;
+        info->iters = st.iter;
+        info->status = st.done ? st.status : FE_ENOTCONV;
+        const double bn = std::sqrt(st.bb);
+        info->relres = bn > 0 ? std::sqrt(st.rr) / bn : std::sqrt(st.rr);
+        info->true_relres = bn > 0 ? std::sqrt(st.true_rr) / bn : std::sqrt(st.true_rr);
+        if (info->status != FE_OK && worst == FE_OK) worst = fe_status(info->status);
     }
-    if (info->status == FE_ENOTCONV) set_error(FE_ENOTCONV, "pcg reached maxit");
-    if (info->status == FE_EBREAKDOWN) set_error(FE_EBREAKDOWN, "pcg breakdown: p.Ap <= 0 or not finite");
-    return fe_status(info->status);
+    // Lanczos estimates from the CG coefficients (single problem)
+    if (np == 1) {
+        fe_solve_info *info = jobs[order[0]].info;
+        const int m = std::min(hs[0].iter, kHist);
+        if (m > 0) {
+            std::vector<double> h(2 * kHist);
+            FE_HIP(hipMemcpy(h.data(), hp[0].w.hist, sizeof(double) * 2 * kHist, hipMemcpyDeviceToHost));
+            std::vector<double> d(m), e(m > 1 ? m - 1 : 1);
+            for (int i = 0; i < m; i++) {
+                const double a = h[i];
+                d[i] = 1.0 / a + (i > 0 ? h[kHist + i - 1] / h[i - 1] : 0.0);
+                if (i + 1 < m) e[i] = std::sqrt(h[kHist + i]) / a;
+            }
+            tridiag_extremes(d, e, info->lambda_min_est, info->lambda_max_est);
+        }
+    }
+    if (worst == FE_ENOTCONV) set_error(FE_ENOTCONV, "pcg reached maxit");
+    if (worst == FE_EBREAKDOWN) set_error(FE_EBREAKDOWN, "pcg breakdown: p.Ap <= 0 or not finite");
+    return worst;
+}
+
+template <typename VT>
+static fe_status pcg_run(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind, const VT *val,
+                         const double *dinv, const double *b, double *x, double rtol, int maxit, void *ws,
+                         size_t ws_bytes, fe_solve_info *info, hipStream_t s)
+{
+    if (ws_bytes < pcg_ws_bytes(n) + pcg_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
+    std::vector<PcgJob> jobs(1);
+    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info};
+    void *table = static_cast<char *>(ws) + pcg_ws_bytes(n);
+    // small systems are launch-bound: replay the iterations from a HIP graph
+    const bool graph = n < (int64_t(1) << 18);
+    return pcg_engine(jobs, rtol, maxit, table, graph, s);
+}
+
+fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
+                    fe_solve_info *info, hipStream_t s)
+{
+    return pcg_run<double>(A->n_rows, A->nnz, A->rowptr, A->colind, A->values, A->dinv, b, x, rtol, maxit, ws,
+                           ws_bytes, info, s);
+}
+
+size_t pcg_solve_ws_bytes(int64_t n) { return pcg_ws_bytes(n) + pcg_table_bytes(1); }
+
+fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
+                          int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s)
+{
+    size_t need = pcg_table_bytes(nprob);
+    for (int i = 0; i < nprob; i++) need += pcg_ws_bytes(A[i].n_rows);
+    if (ws_bytes < need) return set_error(FE_EINVAL, "batch pcg workspace too small");
+    std::vector<PcgJob> jobs(nprob);
+    char *p = static_cast<char *>(ws) + pcg_table_bytes(nprob);
+    for (int i = 0; i < nprob; i++) {
+        jobs[i] = PcgJob{A[i].n_rows, A[i].nnz, A[i].rowptr, A[i].colind, A[i].values, false, A[i].dinv,
+                         b[i], x[i], p, &infos[i]};
+        p += pcg_ws_bytes(A[i].n_rows);
+    }
+    return pcg_engine(jobs, rtol, maxit, ws, true, s);
+}
+
+size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows)
+{
+    size_t need = pcg_table_bytes(nprob);
+    for (int i = 0; i < nprob; i++) need += pcg_ws_bytes(n_rows[i]);
+    return need;
+}
+
+// ---------------------------------------------------------------------------
+// Iterative refinement (precision form): outer residual in FP64 with the FP64
+// matrix, inner Jacobi-PCG on a lower-precision operator, x += correction.
+// ---------------------------------------------------------------------------
+// r = b - A x; partials of r.r
+template <int MODE, int RPB>
+__global__ __launch_bounds__(kBlock) void resid_vec_kernel(int64_t n, const int64_t *__restrict__ rowptr,
+                                                            const int32_t *__restrict__ colind,
+                                                            const double *__restrict__ val,
+                                                            const double *__restrict__ b, const double *__restrict__ x,
+                                                            double *__restrict__ r, PcgWs w)
+{
+    double v[2] = {0.0, 0.0};
+    for_rows<MODE, RPB, double>(n, rowptr, colind, val, x, xcd_block(blockIdx.x, gridDim.x), gridDim.x,
+                                [&](int64_t row, double ax) {
+        const double d = b[row] - ax;
+        r[row] = d;
+        v[0] += d * d;
+        v[1] += b[row] * b[row];
+    });
+    write_partials<2>(v, w.p3);
+}
+
+__global__ __launch_bounds__(kBlock) void resid_vec_finish_kernel(PcgWs w, int nparts)
+{
+    double t[2];
+    reduce_partials<2>(w.p3, nparts, t);
+    if (threadIdx.x == 0) {
+        w.st->true_rr = t[0];
+        w.st->bb = t[1];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void axpy_kernel(int64_t n, const double *__restrict__ d, double *__restrict__ x)
+{
+    for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) x[i] += d[i];
+}
+
+__global__ __launch_bounds__(kBlock) void demote_kernel(int64_t nnz, const double *__restrict__ v, float *__restrict__ o)
+{
+    for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < nnz; i += int64_t(gridDim.x) * kBlock)
+        o[i] = float(v[i]);
+}
+
+size_t refine_ws_bytes(int64_t n)
+{
+    return pcg_ws_bytes(n) + pcg_table_bytes(1) + 2 * align256(size_t(n) * sizeof(double));
+}
+
+fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s)
+{
+    if (A->nnz == 0) return FE_OK;
+    const int64_t grid = std::min<int64_t>((A->nnz + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(demote_kernel, dim3(grid), dim3(kBlock), 0, s, A->nnz, A->values, values32);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,
+                       double rtol, double inner_rtol, int max_outer, int max_inner, void *ws, size_t ws_bytes,
+                       fe_refine_info *info, hipStream_t s)
+{
+    const int64_t n = Ahi->n_rows;
+    std::memset(info, 0, sizeof(*info));
+    if (ws_bytes < refine_ws_bytes(n)) return set_error(FE_EINVAL, "refinement workspace too small");
+    if (Alo->n_rows != n || Alo->nnz != Ahi->nnz) return set_error(FE_EINVAL, "A_lo must have the pattern of A_hi");
+    if (n == 0) return FE_OK;
+    static thread_local PinnedState pin;
+    if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
+    char *base = static_cast<char *>(ws);
+    void *pws = base;
+    const size_t inner_bytes = pcg_ws_bytes(n) + pcg_table_bytes(1);
+    double *r = reinterpret_cast<double *>(base + inner_bytes);
+    double *d = reinterpret_cast<double *>(base + inner_bytes + align256(size_t(n) * sizeof(double)));
+    PcgWs w = carve(pws, n);
+    const SpmvPlan pl = plan_for(n, Ahi->nnz);
+    const int gr = grid_rows(n, pl);
+    const int ge = grid_elems(n);
+    info->status = FE_ENOTCONV;
+    for (int it = 0; it <= max_outer; it++) {
+        FE_PLAN_DISPATCH(pl, (resid_vec_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(
+                                 n, Ahi->rowptr, Ahi->colind, Ahi->values, b, x, r, w)));
+        hipLaunchKernelGGL(resid_vec_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr);
+        FE_HIP(hipGetLastError());
+        FE_HIP(hipMemcpyAsync(pin.h, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        FE_HIP(hipStreamSynchronize(s));
+        const double bn = std::sqrt(pin.h->bb), rn = std::sqrt(pin.h->true_rr);
+        info->relres = bn > 0 ? rn / bn : rn;
+        if (info->relres <= rtol) {
+            info->status = FE_OK;
+            break;
+        }
+        if (it == max_outer) break;
+        // correction: A_lo d = r, from d = 0
+        FE_HIP(hipMemsetAsync(d, 0, sizeof(double) * size_t(n), s));
+        fe_solve_info inner;
+        fe_status st;
+        if (values32)
+            st = pcg_run<float>(n, Alo->nnz, Alo->rowptr, Alo->colind, values32, Alo->dinv, r, d, inner_rtol,
+                                max_inner, pws, inner_bytes, &inner, s);
+        else
+            st = pcg_run<double>(n, Alo->nnz, Alo->rowptr, Alo->colind, Alo->values, Alo->dinv, r, d, inner_rtol,
+                                 max_inner, pws, inner_bytes, &inner, s);
+        info->inner_iters += inner.iters;
+        info->outer_iters = it + 1;
+        if (st == FE_EBREAKDOWN || st == FE_EDEVICE || st == FE_EINVAL) {
+            info->status = st;
+            return st;
+        }
+        hipLaunchKernelGGL(axpy_kernel, dim3(ge), dim3(kBlock), 0, s, n, d, x);
+        FE_HIP(hipGetLastError());
+    }
+    if (info->status == FE_ENOTCONV) return set_error(FE_ENOTCONV, "iterative refinement reached max_outer");
+    return FE_OK;
 }
 
 }  // namespace fe

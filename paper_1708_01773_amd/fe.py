@@ -24,7 +24,8 @@ EXPORTS = [
     "fe_last_error", "fe_version", "fe_create_mesh", "fe_destroy_mesh", "fe_set_coefficients",
     "fe_assemble_query", "fe_pattern", "fe_assemble", "fe_integrate", "fe_element_layout", "fe_scatter",
     "fe_cell_dofs", "fe_permutation", "fe_get_status", "fe_pcg_query", "fe_pcg_solve", "fe_spmv",
-    "fe_set_timing", "fe_get_timing",
+    "fe_set_timing", "fe_get_timing", "fe_csr_to_fp32", "fe_refine_query", "fe_refine_solve",
+    "fe_pcg_batch_query", "fe_pcg_solve_batch",
 ]
 
 _c = ctypes
@@ -56,6 +57,11 @@ class Csr(_c.Structure):
 class SolveInfo(_c.Structure):
     _fields_ = [("iters", _c.c_int32), ("status", _c.c_int32), ("relres", _c.c_double),
                 ("true_relres", _c.c_double), ("lambda_min_est", _c.c_double), ("lambda_max_est", _c.c_double)]
+
+
+class RefineInfo(_c.Structure):
+    _fields_ = [("outer_iters", _c.c_int32), ("inner_iters", _c.c_int32), ("status", _c.c_int32),
+                ("relres", _c.c_double)]
 
 
 class Timing(_c.Structure):
@@ -98,7 +104,14 @@ def lib():
                              _c.POINTER(SolveInfo), _P],
             "fe_spmv": [_c.POINTER(Csr), _P, _P, _P],
             "fe_set_timing": [_c.c_int32],
+            "fe_csr_to_fp32": [_c.POINTER(Csr), _P, _P],
+            "fe_refine_query": [_c.c_int64, _c.POINTER(_c.c_size_t)],
+            "fe_refine_solve": [_c.POINTER(Csr), _c.POINTER(Csr), _P, _P, _P, _c.c_double, _c.c_double, _c.c_int32,
+                                _c.c_int32, _P, _c.c_size_t, _c.POINTER(RefineInfo), _P],
             "fe_get_timing": [_c.POINTER(Timing), _c.c_int32],
+            "fe_pcg_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
+            "fe_pcg_solve_batch": [_c.c_int32, _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P), _c.c_double,
+                                   _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -260,8 +273,51 @@ def pcg_solve(csr, b, x, rtol, maxit, ws, stream=None, check=True):
     return out
 
 
+def pcg_batch_query(n_rows):
+    arr = (_c.c_int64 * max(1, len(n_rows)))(*[int(v) for v in n_rows])
+    ws = _c.c_size_t()
+    _check(lib().fe_pcg_batch_query(len(n_rows), arr, _c.byref(ws)), "fe_pcg_batch_query")
+    return ws.value
+
+
+def pcg_solve_batch(csrs, bs, xs, rtol, maxit, ws, stream=None, check=True):
+    """Solves len(csrs) systems in one engine pass; returns (status, [info dicts])."""
+    n = len(csrs)
+    A = (Csr * max(1, n))(*csrs)
+    B = (_P * max(1, n))(*[_ptr(b) for b in bs])
+    X = (_P * max(1, n))(*[_ptr(x) for x in xs])
+    infos = (SolveInfo * max(1, n))()
+    st = lib().fe_pcg_solve_batch(n, A, B, X, float(rtol), int(maxit), _ptr(ws), ws.numel() * ws.element_size(),
+                                  infos, _stream(stream))
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_pcg_solve_batch")
+    out = [dict(iters=i.iters, status=i.status, relres=i.relres, true_relres=i.true_relres) for i in infos[:n]]
+    return st, out
+
+
 def spmv(csr, x, y, stream=None):
     _check(lib().fe_spmv(_c.byref(csr), _ptr(x), _ptr(y), _stream(stream)), "fe_spmv")
+
+
+def csr_to_fp32(csr, values32, stream=None):
+    _check(lib().fe_csr_to_fp32(_c.byref(csr), _ptr(values32), _stream(stream)), "fe_csr_to_fp32")
+
+
+def refine_query(n_rows):
+    ws = _c.c_size_t()
+    _check(lib().fe_refine_query(int(n_rows), _c.byref(ws)), "fe_refine_query")
+    return ws.value
+
+
+def refine_solve(A_hi, A_lo, b, x, rtol, inner_rtol, max_outer, max_inner, ws, values32=None, stream=None):
+    """Iterative refinement; returns dict(outer_iters, inner_iters, status, relres)."""
+    info = RefineInfo()
+    st = lib().fe_refine_solve(_c.byref(A_hi), _c.byref(A_lo), _ptr(values32), _ptr(b), _ptr(x), float(rtol),
+                               float(inner_rtol), int(max_outer), int(max_inner), _ptr(ws),
+                               ws.numel() * ws.element_size(), _c.byref(info), _stream(stream))
+    if st not in (FE_OK, FE_ENOTCONV):
+        _check(st, "fe_refine_solve")
+    return dict(outer_iters=info.outer_iters, inner_iters=info.inner_iters, status=info.status, relres=info.relres)
 
 
 def set_timing(enable):
