@@ -170,6 +170,26 @@ fe_status fe_element_layout(fe_mesh mesh, int32_t order, const fe_coeff *coeff, 
 fe_status fe_scatter(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_csr *out, const void *ws,
                      size_t ws_bytes, fe_stream stream);
 
+/* Batched numeric phase: the assembly of fe_assemble (Sect. 3.6 eq. assembly,
+ * Sect. 3.7) for nprob problems of different meshes, orders, problems and
+ * precisions in one call.  Problems are grouped by kernel class (dimension,
+ * order, components, precision); each class is one integration launch and
+ * one scatter launch in which every problem owns its own range of
+ * workgroups.  Classes without a batched kernel (2D orders >= 2, Q1
+ * elasticity) and the Dirichlet lifting are launched per problem.  Each
+ * problem's output is bitwise that of fe_assemble on it alone.
+ *   meshes, orders, coeffs, out: host arrays of nprob entries.  A mesh may
+ *   appear more than once only with the same order, problem and faces.
+ *   out[i]: device CSR with the pattern of fe_pattern, sizes from the query.
+ *   ws: device workspace of the size fe_assemble_batch_query reports (job
+ *   tables plus every problem's element workspace).
+ * Waits for the stream's earlier work before enqueueing (the job table is
+ * staged from host memory), then enqueues only. */
+fe_status fe_assemble_batch_query(int32_t nprob, const fe_mesh *meshes, const int32_t *orders,
+                                  const fe_coeff *coeffs, int64_t *n_rows, int64_t *nnz, size_t *ws_bytes);
+fe_status fe_assemble_batch(int32_t nprob, const fe_mesh *meshes, const int32_t *orders, const fe_coeff *coeffs,
+                            fe_csr *out, void *ws, size_t ws_bytes, fe_stream stream);
+
 /* Cell-to-DOF map (Sect. 10.1 lst_dofs_gids): out[c * nloc + ncomp * a + comp]
  * = free DOF id, or -1 - fixed DOF id.  out: device, ncells * nloc int32. */
 fe_status fe_cell_dofs(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int32_t *out, fe_stream stream);

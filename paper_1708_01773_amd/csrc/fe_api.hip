@@ -1,6 +1,7 @@
 // fe_api.hip -- the extern "C" entry points declared in include/fe.h:
 // argument validation, the mesh handle and its cached set-up, and the
 // dispatch to the kernels of fe_setup / fe_integrate / fe_scatter / fe_solve.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -367,6 +368,193 @@ fe_status fe_assemble(fe_mesh m, int32_t order, const fe_coeff *c, fe_csr *out, 
     fe_status st = fe_integrate(m, order, c, ws, ws_bytes, stream);
     if (st != FE_OK) return st;
     return fe_scatter(m, order, c, out, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Batched assembly: problems grouped by kernel class, one launch per class
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace fe {
+
+struct BatchLayout {
+    size_t table, boff, total;
+    std::vector<size_t> ws_off;
+    std::vector<ElemLayout> el;
+};
+
+static fe_status batch_prepare(int32_t nprob, const fe_mesh *meshes, const int32_t *orders, const fe_coeff *coeffs,
+                               BatchLayout &L)
+{
+    if (nprob < 0) return set_error(FE_EINVAL, "negative nprob");
+    if (nprob > 0 && (!meshes || !orders || !coeffs)) return set_error(FE_EINVAL, "null argument");
+    for (int i = 0; i < nprob; i++) {
+        fe_status st = check_coeff(meshes[i], orders[i], &coeffs[i]);
+        if (st != FE_OK) return st;
+    }
+    // a mesh may appear more than once only with the same space
+    for (int i = 0; i < nprob; i++)
+        for (int j = 0; j < i; j++)
+            if (meshes[i] == meshes[j]) {
+                const int nci = coeffs[i].problem == FE_ELASTICITY ? meshes[i]->dim : 1;
+                const int ncj = coeffs[j].problem == FE_ELASTICITY ? meshes[j]->dim : 1;
+                if (orders[i] != orders[j] || nci != ncj || coeffs[i].dirichlet_faces != coeffs[j].dirichlet_faces)
+                    return set_error(FE_EINVAL, "a mesh repeated in a batch needs the same order, problem and faces");
+            }
+    L.el.resize(nprob);
+    L.ws_off.resize(nprob);
+    L.table = 0;
+    L.boff = align256(sizeof(AsmJob) * 2 * size_t(std::max(nprob, 1)));
+    size_t off = L.boff + align256(sizeof(int32_t) * (4 * size_t(nprob) + 16));
+    for (int i = 0; i < nprob; i++) {
+        fe_status st = ensure_space(meshes[i], orders[i], &coeffs[i]);
+        if (st != FE_OK) return st;
+        L.el[i] = elem_layout(meshes[i]->space.args, coeffs[i].precision);
+        L.ws_off[i] = off;
+        off += align256(L.el[i].total);
+    }
+    L.total = off;
+    return FE_OK;
+}
+
+}  // namespace fe
+
+extern "C" {
+
+fe_status fe_assemble_batch_query(int32_t nprob, const fe_mesh *meshes, const int32_t *orders,
+                                  const fe_coeff *coeffs, int64_t *n_rows, int64_t *nnz, size_t *ws_bytes)
+{
+    BatchLayout L;
+    fe_status st = batch_prepare(nprob, meshes, orders, coeffs, L);
+    if (st != FE_OK) return st;
+    for (int i = 0; i < nprob; i++) {
+        if (n_rows) n_rows[i] = meshes[i]->space.args.n_rows;
+        if (nnz) nnz[i] = meshes[i]->space.args.nnz;
+    }
+    if (ws_bytes) *ws_bytes = L.total;
+    return FE_OK;
+}
+
+fe_status fe_assemble_batch(int32_t nprob, const fe_mesh *meshes, const int32_t *orders, const fe_coeff *coeffs,
+                            fe_csr *out, void *ws, size_t ws_bytes, fe_stream stream)
+{
+    BatchLayout L;
+    fe_status st = batch_prepare(nprob, meshes, orders, coeffs, L);
+    if (st != FE_OK) return st;
+    if (nprob == 0) return FE_OK;
+    if (!out) return set_error(FE_EINVAL, "null csr array");
+    if (!ws || ws_bytes < L.total) return set_error(FE_EINVAL, "workspace too small (see fe_assemble_batch_query)");
+    for (int i = 0; i < nprob; i++) {
+        st = check_csr(&out[i], meshes[i]->space.args, true);
+        if (st != FE_OK) return st;
+    }
+    hipStream_t s = as_stream(stream);
+    char *base = static_cast<char *>(ws);
+    std::vector<AsmJob> jobs(nprob);
+    for (int i = 0; i < nprob; i++) {
+        AsmJob &J = jobs[i];
+        fe_mesh m = meshes[i];
+        m->last_stream = s;
+        J.s = m->space.args;
+        J.m = mesh_args(m);
+        J.p = problem_args(&coeffs[i]);
+        ref_tables(orders[i], J.rt);
+        J.E = base + L.ws_off[i];
+        J.F = reinterpret_cast<double *>(base + L.ws_off[i] + L.el[i].f_offset);
+        J.values = out[i].values;
+        J.rhs = out[i].rhs;
+        J.dinv = out[i].dinv;
+        J.parts = 1;
+    }
+    // classes: integration by (dim, order, components, precision) for the
+    // batchable kernels; scatter by (element layout, components)
+    std::vector<int> iorder, sorder, single;
+    for (int i = 0; i < nprob; i++) {
+        if (jobs[i].s.ncells == 0) continue;
+        if (integrate_batchable(jobs[i].s, jobs[i].p)) iorder.push_back(i);
+        else single.push_back(i);
+    }
+    auto ikey = [&](int i) {
+        const AsmJob &J = jobs[i];
+        return ((J.s.dim * 8 + J.s.k) * 4 + J.s.ncomp) * 4 + J.p.precision;
+    };
+    auto skey = [&](int i) {
+        return (L.el[i].cb > 1 ? 1000 : 0) + L.el[i].elem_bytes * 10 + jobs[i].s.ncomp;
+    };
+    std::stable_sort(iorder.begin(), iorder.end(), [&](int a, int b) { return ikey(a) < ikey(b); });
+    for (int i = 0; i < nprob; i++)
+        if (jobs[i].s.n_rows > 0) sorder.push_back(i);
+    std::stable_sort(sorder.begin(), sorder.end(), [&](int a, int b) { return skey(a) < skey(b); });
+    // device table in the order: integration classes, then scatter classes
+    struct Launch {
+        int first, count, grid;
+        size_t boff_pos;
+        int job0;  // host job index of the class
+    };
+    std::vector<AsmJob> table;
+    std::vector<int32_t> boff;
+    std::vector<Launch> il, sl;
+    auto build = [&](const std::vector<int> &ord, auto key, bool integ, std::vector<Launch> &ls) -> fe_status {
+        size_t t = 0;
+        while (t < ord.size()) {
+            size_t u = t;
+            while (u < ord.size() && key(ord[u]) == key(ord[t])) u++;
+            Launch l{int(table.size()), int(u - t), 0, boff.size(), ord[t]};
+            int64_t acc = 0;
+            for (size_t v = t; v < u; v++) {
+                AsmJob J = jobs[ord[v]];
+                int32_t parts = 1;
+                const int64_t nb = integ ? integrate_blocks(J.s, J.p, parts) : scatter_blocks(J.s, L.el[ord[v]]);
+                J.parts = parts;
+                boff.push_back(int32_t(acc));
+                acc += nb;
+                if (acc > int64_t(INT32_MAX)) return set_error(FE_EINVAL, "batch class exceeds 2^31 workgroups");
+                table.push_back(J);
+            }
+            boff.push_back(int32_t(acc));
+            l.grid = int(acc);
+            ls.push_back(l);
+            t = u;
+        }
+        return FE_OK;
+    };
+    st = build(iorder, ikey, true, il);
+    if (st != FE_OK) return st;
+    st = build(sorder, skey, false, sl);
+    if (st != FE_OK) return st;
+    if (sizeof(int32_t) * boff.size() > align256(sizeof(int32_t) * (4 * size_t(nprob) + 16)) ||
+        table.size() > size_t(2 * nprob))
+        return set_error(FE_EINVAL, "internal batch table overflow");
+    AsmJob *d_table = reinterpret_cast<AsmJob *>(base + L.table);
+    int32_t *d_boff = reinterpret_cast<int32_t *>(base + L.boff);
+    if (!table.empty()) {
+        FE_HIP(hipMemcpyAsync(d_table, table.data(), sizeof(AsmJob) * table.size(), hipMemcpyHostToDevice, s));
+        FE_HIP(hipMemcpyAsync(d_boff, boff.data(), sizeof(int32_t) * boff.size(), hipMemcpyHostToDevice, s));
+        // the host vectors go away on return: wait for the staged copies
+        FE_HIP(hipStreamSynchronize(s));
+    }
+    hipEvent_t t0 = timing_begin(s);
+    for (const Launch &l : il) {
+        st = launch_integrate_batch(jobs[l.job0], d_table + l.first, d_boff + l.boff_pos, l.count, l.grid, s);
+        if (st != FE_OK) return st;
+    }
+    for (int i : single) {
+        st = launch_integrate(jobs[i].s, jobs[i].m, jobs[i].p, jobs[i].rt, L.el[i], jobs[i].E, s);
+        if (st != FE_OK) return st;
+    }
+    for (int i = 0; i < nprob; i++) {
+        st = launch_lift(jobs[i].s, jobs[i].m, jobs[i].p, meshes[i]->space.d_cell_dofs, L.el[i], jobs[i].E, s);
+        if (st != FE_OK) return st;
+    }
+    timing_end(t0, kTimeIntegrate, s);
+    t0 = timing_begin(s);
+    for (const Launch &l : sl) {
+        st = launch_scatter_batch(jobs[l.job0], L.el[l.job0], d_table + l.first, d_boff + l.boff_pos, l.count,
+                                  l.grid, s);
+        if (st != FE_OK) return st;
+    }
+    timing_end(t0, kTimeScatter, s);
+    return FE_OK;
 }
 
 fe_status fe_cell_dofs(fe_mesh m, int32_t order, const fe_coeff *c, int32_t *out, fe_stream stream)

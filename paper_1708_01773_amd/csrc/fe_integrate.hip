@@ -133,13 +133,13 @@ __device__ __forceinline__ float round_in(double v)
 }
 
 template <int DIM, int PREC>
-__global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt,
-                                                     void *__restrict__ Ev, double *__restrict__ F)
+__device__ __forceinline__ void k3_q1_body(const SpaceArgs &s, const MeshArgs &m, const ProblemArgs &p,
+                                           const RefTables &rt, void *__restrict__ Ev, double *__restrict__ F,
+                                           int64_t bid)
 {
     constexpr int NN = 1 << DIM;
     constexpr int NT = NN * (NN + 1) / 2;
     using Acc = typename std::conditional<PREC == FE_FP64, double, float>::type;
-    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t cell = bid * blockDim.x + threadIdx.x;
     if (cell >= s.ncells) return;
     double X[NN][3];
@@ -252,6 +252,22 @@ __global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, Pro
         }
 #pragma unroll
     for (int a = 0; a < NN; a++) F[cell * NN + a] = fl[a];
+}
+
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k3_q1_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt,
+                                                     void *__restrict__ Ev, double *__restrict__ F)
+{
+    k3_q1_body<DIM, PREC>(s, m, p, rt, Ev, F, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k3_q1_batch_kernel(const AsmJob *__restrict__ jobs,
+                                                           const int32_t *__restrict__ boff, int njobs)
+{
+    int64_t lb, nb;
+    const AsmJob &J = jobs[find_job(boff, njobs, lb, nb)];
+    k3_q1_body<DIM, PREC>(J.s, J.m, J.p, J.rt, J.E, J.F, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -552,6 +568,49 @@ fe_status launch_lift(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs
             hipLaunchKernelGGL((k3_lift_kernel<2, float>), dim3(sa.ncells), dim3(64), 0, s, sa, ma, pa, cell_dofs,
                                el.cb, E, F);
     }
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches (one launch per kernel class, jobs in a device table)
+// ---------------------------------------------------------------------------
+bool integrate_batchable(const SpaceArgs &sa, const ProblemArgs &pa)
+{
+    return (sa.k == 1 && sa.ncomp == 1) || (sa.dim == 3 && sa.k >= 2);
+}
+
+int64_t integrate_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts)
+{
+    parts = 1;
+    if (sa.dim == 3 && sa.k >= 2) return mfma_blocks(sa, pa, parts);
+    return (sa.ncells + 255) / 256;
+}
+
+fe_status launch_integrate_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
+                                 hipStream_t s)
+{
+    if (grid == 0) return FE_OK;
+    const SpaceArgs &sa = h.s;
+    if (sa.dim == 3 && sa.k >= 2) return launch_mfma_batch(h, jobs, boff, njobs, grid, s);
+    if (!(sa.k == 1 && sa.ncomp == 1)) return set_error(FE_EINVAL, "no batched kernel for this class");
+#define FE_Q1B(D, P) hipLaunchKernelGGL((k3_q1_batch_kernel<D, P>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs)
+    if (sa.dim == 3) {
+        switch (h.p.precision) {
+            case FE_FP64: FE_Q1B(3, FE_FP64); break;
+            case FE_FP32: FE_Q1B(3, FE_FP32); break;
+            case FE_FP16: FE_Q1B(3, FE_FP16); break;
+            default: FE_Q1B(3, FE_BF16); break;
+        }
+    } else {
+        switch (h.p.precision) {
+            case FE_FP64: FE_Q1B(2, FE_FP64); break;
+            case FE_FP32: FE_Q1B(2, FE_FP32); break;
+            case FE_FP16: FE_Q1B(2, FE_FP16); break;
+            default: FE_Q1B(2, FE_BF16); break;
+        }
+    }
+#undef FE_Q1B
     FE_HIP(hipGetLastError());
     return FE_OK;
 }

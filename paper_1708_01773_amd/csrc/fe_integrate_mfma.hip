@@ -140,8 +140,9 @@ __device__ __forceinline__ void pair_tiles(int p, int NT, int &ta, int &tb)
 // One workgroup = 4 waves = (cell, part).  NNP = padded node count (multiple
 // of 16), PPW = max node-tile pairs per wave, QS = quadrature points per slab.
 template <class Pol, int PROB, int NNP, int PPW, int QS>
-__global__ __launch_bounds__(256) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt, int parts,
-                                                      typename Pol::Out *__restrict__ E, double *__restrict__ F)
+__device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs &m, const ProblemArgs &p,
+                                             const RefTables &rt, int parts, typename Pol::Out *__restrict__ E,
+                                             double *__restrict__ F, int64_t bid)
 {
     constexpr int DIM = 3;
     constexpr int NT = NNP / 16;
@@ -155,7 +156,6 @@ __global__ __launch_bounds__(256) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, P
 
     const int k = s.k, k1 = k + 1, nn = s.nn, nloc = s.nloc;
     const int nq = k1 * k1 * k1;
-    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t cell = bid / parts;
     const int part = int(bid % parts);
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
@@ -400,6 +400,23 @@ __global__ __launch_bounds__(256) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, P
     }
 }
 
+template <class Pol, int PROB, int NNP, int PPW, int QS>
+__global__ __launch_bounds__(256) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt, int parts,
+                                                      typename Pol::Out *__restrict__ E, double *__restrict__ F)
+{
+    k3_mfma_body<Pol, PROB, NNP, PPW, QS>(s, m, p, rt, parts, E, F, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <class Pol, int PROB, int NNP, int PPW, int QS>
+__global__ __launch_bounds__(256) void k3_mfma_batch_kernel(const AsmJob *__restrict__ jobs,
+                                                             const int32_t *__restrict__ boff, int njobs)
+{
+    int64_t lb, nb;
+    const AsmJob &J = jobs[find_job(boff, njobs, lb, nb)];
+    k3_mfma_body<Pol, PROB, NNP, PPW, QS>(J.s, J.m, J.p, J.rt, J.parts, static_cast<typename Pol::Out *>(J.E), J.F,
+                                          lb);
+}
+
 // ---------------------------------------------------------------------------
 // Launch: (order, problem) -> padded node count, pairs per wave, parts per cell
 // ---------------------------------------------------------------------------
@@ -440,6 +457,58 @@ fe_status launch_integrate_mfma(const SpaceArgs &sa, const MeshArgs &ma, const P
         case FE_FP16: return launch_pol<PolF16>(sa, ma, pa, rt, E, F, s);
         default: return launch_pol<PolBF16>(sa, ma, pa, rt, E, F, s);
     }
+}
+
+// Batched: the class (precision, order, problem) is that of the host job h.
+template <class Pol, int PROB, int NNP, int PPW, int QS>
+static fe_status launch_batch_one(const AsmJob *jobs, const int32_t *boff, int njobs, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_mfma_batch_kernel<Pol, PROB, NNP, PPW, QS>), dim3(grid), dim3(256), 0, s, jobs, boff,
+                       njobs);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+template <class Pol>
+static fe_status launch_batch_pol(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
+                                  hipStream_t s)
+{
+    constexpr int QS = Pol::KFAST ? 32 : 16;
+    const bool el = h.p.problem == FE_ELASTICITY;
+    switch (h.s.k) {
+        case 2: return el ? launch_batch_one<Pol, 1, 32, 1, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 32, 1, QS>(jobs, boff, njobs, grid, s);
+        case 3: return el ? launch_batch_one<Pol, 1, 64, 2, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 64, 3, QS>(jobs, boff, njobs, grid, s);
+        case 4: return el ? launch_batch_one<Pol, 1, 128, 2, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 128, 9, QS>(jobs, boff, njobs, grid, s);
+        default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
+    }
+}
+
+fe_status launch_mfma_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
+                            hipStream_t s)
+{
+    switch (h.p.precision) {
+        case FE_FP64: return launch_batch_pol<PolF64>(h, jobs, boff, njobs, grid, s);
+        case FE_FP32: return launch_batch_pol<PolF32>(h, jobs, boff, njobs, grid, s);
+        case FE_FP16: return launch_batch_pol<PolF16>(h, jobs, boff, njobs, grid, s);
+        default: return launch_batch_pol<PolBF16>(h, jobs, boff, njobs, grid, s);
+    }
+}
+
+// Workgroups per cell of the matrix-core kernel (same table as launch_pol).
+int64_t mfma_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts)
+{
+    const bool el = pa.problem == FE_ELASTICITY;
+    int nnp = 32, ppw = 1;
+    if (sa.k == 3) {
+        nnp = 64;
+        ppw = el ? 2 : 3;
+    } else if (sa.k == 4) {
+        nnp = 128;
+        ppw = el ? 2 : 9;
+    }
+    const int nt = nnp / 16, np = nt * (nt + 1) / 2;
+    parts = (np + 4 * ppw - 1) / (4 * ppw);
+    return sa.ncells * parts;
 }
 
 }  // namespace fe

@@ -26,6 +26,8 @@ fe_status hip_error(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::fe::hip_error(_e, #call);       \
     } while (0)
 
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 // ---------------------------------------------------------------------------
 // One axis of the structured node lattice of order k.
 // Node indices run over 0..N (N = n k).  Free indices are [lo, hi] (a
@@ -86,6 +88,18 @@ struct ElemLayout {
     size_t total;        // bytes of the whole workspace
 };
 
+// One problem of a batched assembly launch (device table entry).
+struct AsmJob {
+    SpaceArgs s;
+    MeshArgs m;
+    ProblemArgs p;
+    RefTables rt;
+    void *E;      // element matrices (layout of elem_layout)
+    double *F;    // element load vectors
+    double *values, *rhs, *dinv;
+    int32_t parts;  // matrix-core workgroups per cell
+};
+
 // Cached order-dependent set-up of a mesh.
 struct Space {
     int32_t k = 0, ncomp = 0;
@@ -128,6 +142,19 @@ fe_status launch_integrate_mfma(const SpaceArgs &sa, const MeshArgs &ma, const P
                                 void *E, double *F, hipStream_t s);
 fe_status launch_lift(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const int32_t *cell_dofs,
                       const ElemLayout &el, void *ws, hipStream_t s);
+
+// Batched launches: every job of one launch shares the kernel class named by
+// the host job h (dimension, order, problem, precision); grid = boff[njobs].
+bool integrate_batchable(const SpaceArgs &sa, const ProblemArgs &pa);
+int64_t integrate_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts);
+int64_t mfma_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts);
+fe_status launch_mfma_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
+                            hipStream_t s);
+fe_status launch_integrate_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
+                                 hipStream_t s);
+int64_t scatter_blocks(const SpaceArgs &sa, const ElemLayout &el);
+fe_status launch_scatter_batch(const AsmJob &h, const ElemLayout &el, const AsmJob *jobs, const int32_t *boff,
+                               int njobs, int grid, hipStream_t s);
 
 // Scatter (fe_scatter.hip)
 fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *ws, double *values, double *rhs,
@@ -185,6 +212,22 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks)
     // XCD x owns logical blocks [start_x, start_x + per + (x < rem))
     int64_t start = x * per + (x < rem ? x : rem);
     return start + j;
+}
+
+// Job of block blockIdx.x in a launch whose job j owns the blocks
+// [boff[j], boff[j+1]); lb = block index within the job, nb = its blocks.
+__device__ __forceinline__ int find_job(const int32_t *__restrict__ boff, int njobs, int64_t &lb, int64_t &nb)
+{
+    int lo = 0, hi = njobs;  // boff[lo] <= b < boff[hi]
+    const int b = int(blockIdx.x);
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (boff[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    nb = boff[lo + 1] - boff[lo];
+    lb = b - boff[lo];
+    return lo;
 }
 
 }  // namespace fe

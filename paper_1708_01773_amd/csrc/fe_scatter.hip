@@ -152,14 +152,14 @@ __device__ __forceinline__ void wave_lds_fence()
 }
 
 template <int CB, typename ET>
-__global__ __launch_bounds__(256) void k5_rows_kernel(SpaceArgs s, const ET *__restrict__ E,
-                                                      const double *__restrict__ F, double *__restrict__ values,
-                                                      double *__restrict__ rhs, double *__restrict__ dinv)
+__device__ __forceinline__ void k5_rows_body(const SpaceArgs &s, const ET *__restrict__ E,
+                                             const double *__restrict__ F, double *__restrict__ values,
+                                             double *__restrict__ rhs, double *__restrict__ dinv, int64_t bid)
 {
     __shared__ double stage[4][64 * kRowsCap];
     double *my = stage[threadIdx.x / 64];
     const int lane = threadIdx.x % 64;
-    const int64_t r0 = (xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / 64) * 64;
+    const int64_t r0 = (bid * 4 + threadIdx.x / 64) * 64;
     if (r0 >= s.n_rows) return;  // the whole wave leaves together
     const int nvalid = int(s.n_rows - r0 < 64 ? s.n_rows - r0 : 64);
     const int64_t row = r0 + lane;
@@ -191,17 +191,35 @@ __global__ __launch_bounds__(256) void k5_rows_kernel(SpaceArgs s, const ET *__r
     for (int t = lane; t < total; t += 64) values[base + t] = my[t];
 }
 
+template <int CB, typename ET>
+__global__ __launch_bounds__(256) void k5_rows_kernel(SpaceArgs s, const ET *__restrict__ E,
+                                                      const double *__restrict__ F, double *__restrict__ values,
+                                                      double *__restrict__ rhs, double *__restrict__ dinv)
+{
+    k5_rows_body<CB, ET>(s, E, F, values, rhs, dinv, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int CB, typename ET>
+__global__ __launch_bounds__(256) void k5_rows_batch_kernel(const AsmJob *__restrict__ jobs,
+                                                            const int32_t *__restrict__ boff, int njobs)
+{
+    int64_t lb, nb;
+    const AsmJob &J = jobs[find_job(boff, njobs, lb, nb)];
+    k5_rows_body<CB, ET>(J.s, static_cast<const ET *>(J.E), J.F, J.values, J.rhs, J.dinv, lb);
+}
+
 // ---------------------------------------------------------------------------
 // Cell-major layout: wave per row, lanes over consecutive CSR positions
 // ---------------------------------------------------------------------------
 template <int NC, typename ET>
-__global__ __launch_bounds__(256) void k5_entries_kernel(SpaceArgs s, const ET *__restrict__ E,
-                                                         const double *__restrict__ F, double *__restrict__ values,
-                                                         double *__restrict__ rhs, double *__restrict__ dinv)
+__device__ __forceinline__ void k5_entries_body(const SpaceArgs &s, const ET *__restrict__ E,
+                                                const double *__restrict__ F, double *__restrict__ values,
+                                                double *__restrict__ rhs, double *__restrict__ dinv, int64_t lb,
+                                                int64_t nb)
 {
     const int lane = threadIdx.x % 64;
-    const int64_t nw = int64_t(gridDim.x) * 4;
-    const int64_t lw = xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / 64;
+    const int64_t nw = nb * 4;
+    const int64_t lw = lb * 4 + threadIdx.x / 64;
     for (int64_t row = lw; row < s.n_rows; row += nw) {
         const RowGeom g = row_geom(s, row);
         const int wx = g.w0 * NC;   // entries per x-run
@@ -232,6 +250,23 @@ __global__ __launch_bounds__(256) void k5_entries_kernel(SpaceArgs s, const ET *
         }
         if (lane == 0) rhs[row] = row_rhs(s, g, F);
     }
+}
+
+template <int NC, typename ET>
+__global__ __launch_bounds__(256) void k5_entries_kernel(SpaceArgs s, const ET *__restrict__ E,
+                                                         const double *__restrict__ F, double *__restrict__ values,
+                                                         double *__restrict__ rhs, double *__restrict__ dinv)
+{
+    k5_entries_body<NC, ET>(s, E, F, values, rhs, dinv, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+template <int NC, typename ET>
+__global__ __launch_bounds__(256) void k5_entries_batch_kernel(const AsmJob *__restrict__ jobs,
+                                                               const int32_t *__restrict__ boff, int njobs)
+{
+    int64_t lb, nb;
+    const AsmJob &J = jobs[find_job(boff, njobs, lb, nb)];
+    k5_entries_body<NC, ET>(J.s, static_cast<const ET *>(J.E), J.F, J.values, J.rhs, J.dinv, lb, nb);
 }
 
 fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *ws, double *values, double *rhs,
@@ -266,6 +301,43 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
             else FE_K5E(3, float);
         }
 #undef FE_K5E
+    }
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+// Workgroups of one problem in the batched scatter (same shapes as launch_scatter).
+int64_t scatter_blocks(const SpaceArgs &sa, const ElemLayout &el)
+{
+    if (sa.n_rows == 0) return 0;
+    if (el.cb > 1) return (sa.n_rows + 255) / 256;
+    return std::min<int64_t>((sa.n_rows + 3) / 4, 8192);
+}
+
+fe_status launch_scatter_batch(const AsmJob &h, const ElemLayout &el, const AsmJob *jobs, const int32_t *boff,
+                               int njobs, int grid, hipStream_t s)
+{
+    if (grid == 0) return FE_OK;
+    if (el.cb > 1) {
+        if (el.cb != 64) return set_error(FE_EINVAL, "unexpected element layout");
+        if (el.elem_bytes == 8)
+            hipLaunchKernelGGL((k5_rows_batch_kernel<64, double>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+        else
+            hipLaunchKernelGGL((k5_rows_batch_kernel<64, float>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+    } else {
+#define FE_K5B(NCV, T) \
+    hipLaunchKernelGGL((k5_entries_batch_kernel<NCV, T>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs)
+        if (h.s.ncomp == 1) {
+            if (el.elem_bytes == 8) FE_K5B(1, double);
+            else FE_K5B(1, float);
+        } else if (h.s.ncomp == 2) {
+            if (el.elem_bytes == 8) FE_K5B(2, double);
+            else FE_K5B(2, float);
+        } else {
+            if (el.elem_bytes == 8) FE_K5B(3, double);
+            else FE_K5B(3, float);
+        }
+#undef FE_K5B
     }
     FE_HIP(hipGetLastError());
     return FE_OK;

@@ -75,7 +75,6 @@ struct SpmvPlan {
     int lanes; // lanes per row
 };
 
-static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t pcg_ws_bytes(int64_t n)
 {

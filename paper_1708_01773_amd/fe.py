@@ -25,7 +25,7 @@ EXPORTS = [
     "fe_assemble_query", "fe_pattern", "fe_assemble", "fe_integrate", "fe_element_layout", "fe_scatter",
     "fe_cell_dofs", "fe_permutation", "fe_get_status", "fe_pcg_query", "fe_pcg_solve", "fe_spmv",
     "fe_set_timing", "fe_get_timing", "fe_csr_to_fp32", "fe_refine_query", "fe_refine_solve",
-    "fe_pcg_batch_query", "fe_pcg_solve_batch",
+    "fe_pcg_batch_query", "fe_pcg_solve_batch", "fe_assemble_batch_query", "fe_assemble_batch",
 ]
 
 _c = ctypes
@@ -109,6 +109,10 @@ def lib():
             "fe_refine_solve": [_c.POINTER(Csr), _c.POINTER(Csr), _P, _P, _P, _c.c_double, _c.c_double, _c.c_int32,
                                 _c.c_int32, _P, _c.c_size_t, _c.POINTER(RefineInfo), _P],
             "fe_get_timing": [_c.POINTER(Timing), _c.c_int32],
+            "fe_assemble_batch_query": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
+                                        _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
+            "fe_assemble_batch": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
+                                  _c.POINTER(Csr), _P, _c.c_size_t, _P],
             "fe_pcg_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
             "fe_pcg_solve_batch": [_c.c_int32, _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P), _c.c_double,
                                    _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
@@ -357,3 +361,71 @@ class Assembly:
 
     def scatter(self, stream=None):
         scatter(self.mesh, self.order, self.coeff, self.csr, self.ws, stream)
+
+
+def assemble_batch_query(meshes, orders, coeffs):
+    """Per-problem (n_rows, nnz) lists and the batch workspace bytes."""
+    n = len(meshes)
+    M = (_P * max(1, n))(*[m.handle for m in meshes])
+    O = (_c.c_int32 * max(1, n))(*[int(k) for k in orders])
+    C = (Coeff * max(1, n))(*coeffs)
+    nr = (_c.c_int64 * max(1, n))()
+    nz = (_c.c_int64 * max(1, n))()
+    ws = _c.c_size_t()
+    _check(lib().fe_assemble_batch_query(n, M, O, C, nr, nz, _c.byref(ws)), "fe_assemble_batch_query")
+    return list(nr[:n]), list(nz[:n]), ws.value
+
+
+def assemble_batch(meshes, orders, coeffs, csrs, ws, stream=None):
+    n = len(meshes)
+    M = (_P * max(1, n))(*[m.handle for m in meshes])
+    O = (_c.c_int32 * max(1, n))(*[int(k) for k in orders])
+    C = (Coeff * max(1, n))(*coeffs)
+    A = (Csr * max(1, n))(*csrs)
+    _check(lib().fe_assemble_batch(n, M, O, C, A, _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "fe_assemble_batch")
+
+
+class BatchAssembly:
+    """Device buffers of a batch of independent systems: one CSR (pattern
+    written once at construction), right-hand side, diagonal inverse and
+    solution per problem, the batched assembly workspace and the batched
+    solver workspace."""
+
+    def __init__(self, meshes, orders, coeffs, device="cuda", stream=None):
+        import torch
+        self.meshes, self.orders, self.coeffs = list(meshes), [int(k) for k in orders], list(coeffs)
+        self.n_rows, self.nnz, ws_bytes = assemble_batch_query(self.meshes, self.orders, self.coeffs)
+        dev = torch.device(device)
+        self.rowptr, self.colind, self.values, self.rhs, self.dinv, self.x, self.csrs = [], [], [], [], [], [], []
+        for m, k, c, nr, nz in zip(self.meshes, self.orders, self.coeffs, self.n_rows, self.nnz):
+            rp = torch.empty(nr + 1, dtype=torch.int64, device=dev)
+            ci = torch.empty(max(nz, 1), dtype=torch.int32, device=dev)
+            va = torch.empty(max(nz, 1), dtype=torch.float64, device=dev)
+            rh = torch.empty(max(nr, 1), dtype=torch.float64, device=dev)
+            di = torch.empty(max(nr, 1), dtype=torch.float64, device=dev)
+            csr = csr_struct(nr, nz, rp, ci, va, rh, di)
+            pattern(m, k, c, csr, stream)
+            self.rowptr.append(rp)
+            self.colind.append(ci)
+            self.values.append(va)
+            self.rhs.append(rh)
+            self.dinv.append(di)
+            self.x.append(torch.zeros(max(nr, 1), dtype=torch.float64, device=dev))
+            self.csrs.append(csr)
+        self.ws = torch.empty(max(ws_bytes, 8), dtype=torch.uint8, device=dev)
+        self.solve_ws = torch.empty(max(pcg_batch_query(self.n_rows), 8), dtype=torch.uint8, device=dev)
+
+    def assemble(self, stream=None):
+        assemble_batch(self.meshes, self.orders, self.coeffs, self.csrs, self.ws, stream)
+
+    def solve(self, rtol, maxit, stream=None, zero_x=True):
+        """Batched Jacobi-PCG from x = 0 (or the current x); returns (status, infos)."""
+        if zero_x:
+            for x in self.x:
+                x.zero_()
+        return pcg_solve_batch(self.csrs, self.rhs, self.x, rtol, maxit, self.solve_ws, stream)
+
+    def device_bytes(self):
+        t = [self.ws, self.solve_ws] + self.rowptr + self.colind + self.values + self.rhs + self.dinv + self.x
+        return sum(v.numel() * v.element_size() for v in t)

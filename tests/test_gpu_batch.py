@@ -87,3 +87,73 @@ def test_batch_is_deterministic_and_stops_per_system():
     # empty batch
     st, infos = F.pcg_solve_batch([], [], [], 1e-12, 10, ws)
     assert st == F.FE_OK and infos == []
+
+
+# (dim, n, k, problem, precision, dirichlet): every kernel class, the per-problem
+# fallbacks (2D order >= 2, Q1 elasticity), an affine lifting and an empty system
+ASM = [(3, [5, 4, 3], 1, "poisson", "fp64", 0), (3, [6, 3, 2], 1, "poisson", "fp32", 0),
+       (3, [3, 2, 2], 2, "poisson", "fp32", 0), (3, [2, 3, 2], 3, "poisson", "fp64", 0),
+       (3, [2, 2, 1], 4, "poisson", "fp16", 0), (3, [2, 2, 2], 2, "elasticity", "bf16", 0),
+       (2, [5, 4], 1, "poisson", "fp64", 0), (2, [3, 2], 3, "poisson", "fp64", 0),
+       (3, [2, 2, 2], 1, "elasticity", "fp64", 0), (3, [3, 3, 2], 2, "poisson", "fp64", 1),
+       (3, [1, 1, 1], 1, "poisson", "fp64", 0), (3, [4, 4, 4], 1, "poisson", "fp32", 0)]
+
+
+def _asm_pairs():
+    pairs = []
+    for i, (dim, n, k, prob, prec, dk) in enumerate(ASM):
+        aff = None
+        if dk:
+            aff = [0.3, -0.2, 0.1, 0.5, 1.0, -0.5, 0.25, 0.0, 0.75, -1.0, 0.5, 0.2][: (1 if prob == "poisson" else dim) * (dim + 1)]
+        pairs.append(Pair(dim, n, k, prob, precision=prec, seed=100 + i, dirichlet_kind=dk, affine=aff))
+    return pairs
+
+
+def test_batch_assembly_matches_single_bitwise():
+    say(f"[batch assembly] {len(ASM)} problems")
+    pairs = _asm_pairs()
+    B = F.BatchAssembly([p.mesh for p in pairs], [p.k for p in pairs], [p.coeff for p in pairs])
+    for rep in range(2):  # re-assembly reuses the pattern and the workspace
+        B.assemble()
+        torch.cuda.synchronize()
+        for i, p in enumerate(pairs):
+            A = p.gpu_assembly()
+            assert (A.n_rows, A.nnz) == (B.n_rows[i], B.nnz[i])
+            if A.n_rows == 0:
+                continue
+            assert torch.equal(A.rowptr, B.rowptr[i]) and torch.equal(A.colind[: A.nnz], B.colind[i][: A.nnz])
+            assert torch.equal(A.values[: A.nnz], B.values[i][: A.nnz]), f"values of problem {i}"
+            assert torch.equal(A.rhs[: A.n_rows], B.rhs[i][: A.n_rows]), f"rhs of problem {i}"
+            assert torch.equal(A.dinv[: A.n_rows], B.dinv[i][: A.n_rows]), f"dinv of problem {i}"
+    # FP64 problems against the oracle (structure bit-exact, values 1e-12)
+    for i, p in enumerate(pairs):
+        if ASM[i][4] != "fp64" or B.n_rows[i] == 0:
+            continue
+        S = p.system
+        np.testing.assert_array_equal(B.rowptr[i].cpu().numpy(), S.rowptr)
+        np.testing.assert_array_equal(B.colind[i][: S.nnz].cpu().numpy(), S.colind)
+        assert rel(B.values[i][: S.nnz].cpu().numpy(), S.values) <= 1e-12
+        assert rel(B.rhs[i][: S.nfree].cpu().numpy(), S.rhs) <= 1e-12
+    # batched solve of the assembled batch
+    st, infos = B.solve(1e-10, 5000)
+    assert st == F.FE_OK and all(i["status"] == F.FE_OK for i in infos)
+
+
+def test_batch_assembly_rejects_bad_batches():
+    a = Pair(3, [2, 2, 2], 1)
+    b = Pair(3, [2, 2, 2], 2)
+    # one mesh twice with different orders
+    with pytest.raises(F.FeError):
+        F.assemble_batch_query([a.mesh, a.mesh], [1, 2], [a.coeff, a.coeff])
+    # the same mesh twice with the same space is fine
+    nr, nz, ws = F.assemble_batch_query([a.mesh, a.mesh], [1, 1], [a.coeff, a.coeff])
+    assert nr[0] == nr[1] and nz[0] == nz[1] and ws > 0
+    # workspace too small
+    B = F.BatchAssembly([a.mesh, b.mesh], [1, 2], [a.coeff, b.coeff])
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(F.FeError):
+        F.assemble_batch([a.mesh, b.mesh], [1, 2], [a.coeff, b.coeff], B.csrs, small)
+    # empty batch
+    nr, nz, _ = F.assemble_batch_query([], [], [])
+    assert nr == [] and nz == []
+    F.assemble_batch([], [], [], [], small)
