@@ -175,6 +175,67 @@ def mixed_form(args, wl, mesh, A, x_fp64, F, torch, stream, ncells, lo="fp32"):
             "rel_error_vs_fp64_solution": err}
 
 
+def batch_form(args, F, torch):
+    """Batching form: a sample of the 512-problem batch (3D Poisson, n uniform
+    in [8, 64], order uniform in {1, 2, 3}) with FP32 element integration and
+    FP64 Jacobi-PCG, run as batched waves, against the same problems run one by
+    one (same precision: results must be bitwise equal) and against the plain
+    FP64 path one by one (the solution error of FP32 integration)."""
+    from fe_inputs import batch_specs
+    from paper_1708_01773_amd import batch as BT
+
+    rtol, maxit = 1e-10, 100000
+    specs = batch_specs(512)
+    sample = specs[: args.batch_sample]
+    run = BT.BatchRun(sample, precision="fp32", budget=int(args.batch_budget_gb * (1 << 30)))
+    print(f"[bench] batch form: {len(sample)} problems, {len(run.waves)} wave(s), "
+          f"{sum(run.nnz) / 1e9:.2f} G nnz", file=sys.stderr, flush=True)
+    tuned = run.autotune()
+    print("[bench] batch form: autotuned " + ", ".join(
+        f"class {c}: mode {t['chosen']['mode']} rpw {t['chosen']['rows_per_wave']}" for c, t in tuned.items()),
+        file=sys.stderr, flush=True)
+    ref64, ref32 = {}, {}
+    seq64 = BT.run_sequential([BT.make_problem(i, n, k, "fp64") for i, (n, k) in enumerate(sample)], rtol, maxit,
+                              keep=lambda i, x: ref64.__setitem__(i, x.clone()))
+    print(f"[bench] batch form: sequential FP64 {seq64['assemble_s'] + seq64['solve_s']:.2f} s", file=sys.stderr,
+          flush=True)
+    seq32 = BT.run_sequential(run.problems, rtol, maxit, keep=lambda i, x: ref32.__setitem__(i, x.clone()))
+    print(f"[bench] batch form: sequential FP32 {seq32['assemble_s'] + seq32['solve_s']:.2f} s", file=sys.stderr,
+          flush=True)
+    same = [True]
+    err = [0.0]
+
+    def keep(i, x):
+        same[0] = same[0] and torch.equal(x, ref32[i])
+        r = ref64[i]
+        if r.numel():
+            err[0] = max(err[0], (torch.linalg.vector_norm(x - r) / torch.linalg.vector_norm(r)).item())
+
+    res = run.run(rtol, maxit, keep=keep)
+    t_b = res["assemble_s"] + res["solve_s"]
+    t_s = seq32["assemble_s"] + seq32["solve_s"]
+    print(f"[bench] batch form: batched {t_b:.2f} s (set-up {res['setup_s']:.2f} s)", file=sys.stderr, flush=True)
+    iters = [i["iters"] for i in res["infos"]]
+    return {
+        "sample": f"first {len(sample)} of the 512 problems drawn with seed 17082 (n uniform in [8, 64], order "
+                  f"uniform in 1..3); per-problem seeds 17080/17081 + 1000 (i + 1)",
+        "problems": len(sample), "cells": run.cells, "dofs": sum(run.n_rows), "nnz": sum(run.nnz),
+        "waves": len(run.waves), "budget_gb": args.batch_budget_gb, "integration": "fp32", "solve": "fp64",
+        "rtol": rtol, "status_ok": res["status"] == F.FE_OK, "iters_min": min(iters), "iters_max": max(iters),
+        "batched": {"s": t_b, "assemble_s": res["assemble_s"], "solve_s": res["solve_s"],
+                    "setup_s": res["setup_s"], "problems_per_s": len(sample) / t_b,
+                    "elements_per_s": run.cells / t_b},
+        "sequential_same_precision": {"s": t_s, "assemble_s": seq32["assemble_s"], "solve_s": seq32["solve_s"],
+                                      "problems_per_s": len(sample) / t_s},
+        "sequential_plain_fp64": {"s": seq64["assemble_s"] + seq64["solve_s"]},
+        "speedup_vs_sequential": t_s / t_b,
+        "bitwise_equal_to_sequential": bool(same[0]),
+        "max_rel_error_vs_plain_fp64_solution": err[0],
+        "autotuned_spmv": {str(c): {"mode": t["chosen"]["mode"], "rows_per_wave": t["chosen"]["rows_per_wave"],
+                                    "us": t["chosen"]["us"]} for c, t in tuned.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +250,10 @@ def main():
     ap.add_argument("--phase", default="step", choices=["step", "assemble"],
                     help="step = assemble + PCG (default); assemble = assembly only, K3 against the matrix-core peak")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-sample", type=int, default=16,
+                    help="problems of the 512-problem batch run by the batching form (0 = skip)")
+    ap.add_argument("--batch-budget-gb", type=float, default=160.0, help="device memory per batch wave")
+    ap.add_argument("--form", default=None, choices=["batch"], help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -211,6 +276,11 @@ def main():
 
     from fe_inputs import lognormal_coefficients, structured_vertices
     from paper_1708_01773_amd import fe as F
+
+    if args.form == "batch":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "batch", **batch_form(args, F, torch)}), flush=True)
+        return
 
     wl = dict(WORKLOADS[args.workload])
     if args.n:
@@ -307,6 +377,10 @@ def main():
     if not args.no_forms and wl["precision"] == "fp64":
         print("[bench] mixed-precision form", file=sys.stderr, flush=True)
         out["forms"] = {"mixed_refine": mixed_form(args, wl, mesh, A, x, F, torch, stream, ncells)}
+        if args.batch_sample > 0 and args.workload == "c2":
+            del A, ws, x
+            torch.cuda.empty_cache()
+            out["forms"]["batch"] = batch_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, A.nnz)

@@ -248,6 +248,33 @@ fe_status fe_pcg_batch_query(int32_t nprob, const int64_t *n_rows, size_t *ws_by
 fe_status fe_pcg_solve_batch(int32_t nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
                              int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, fe_stream stream);
 
+/* ------------------------------------------------------------------------ */
+/* SpMV plans and their autotuner                                            */
+/* ------------------------------------------------------------------------ */
+/* A plan is how the CSR SpMV of fe_spmv / fe_pcg_solve / fe_pcg_solve_batch
+ * walks the rows: mode 0 = wave-level CSR-stream with rows_per_wave rows
+ * (1..32) per wave iteration, mode 1 = one wave per row.  Without tuning a
+ * plan follows from the average row length nnz / n_rows; fe_spmv_autotune
+ * times every plan on a matrix (reps launches each, after a warm-up launch)
+ * and makes the fastest the plan of every matrix of the same row-length class
+ * (half octaves of nnz / n_rows) in this process.  The plan fixes each row's
+ * summation order: results are bitwise reproducible for a fixed plan table.
+ *   ws: device, fe_spmv_autotune_query bytes.  tried: host, up to max_tried
+ *   entries (us = mean launch time in microseconds); chosen: host.
+ *   Synchronizes.  fe_spmv_tuning_reset forgets every tuned plan. */
+typedef struct {
+    int32_t mode;
+    int32_t rows_per_wave;
+    double us;
+} fe_spmv_plan;
+
+fe_status fe_spmv_autotune_query(int64_t n_rows, size_t *ws_bytes);
+fe_status fe_spmv_autotune(const fe_csr *A, int32_t reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried,
+                           int32_t max_tried, int32_t *n_tried, fe_spmv_plan *chosen, fe_stream stream);
+fe_status fe_spmv_tuning_reset(void);
+/* The plan a matrix of n_rows rows and nnz entries gets now, and its class. */
+fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32_t *row_class);
+
 /* y = A x (device vectors).  Enqueues only. */
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream);
 

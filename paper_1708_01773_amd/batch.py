@@ -1,0 +1,148 @@
+"""Batched form: many independent 3D Poisson problems of uneven size and
+order assembled and solved together through the batched C ABI calls, in
+waves whose device memory fits a budget.
+
+Every problem is the scalar problem -div(k grad u) = 1 on the unit cube with
+u = 0 on the boundary, on an n^3 brick with interior vertices jittered by
++-0.2 h and lognormal per-cell coefficients; problem i draws its jitter and
+coefficients from its own seeds, so a problem is the same whichever batch or
+wave it lands in.
+"""
+import time
+
+from fe_inputs import lognormal_coefficients, problem_seeds, structured_vertices
+
+from . import fe as F
+
+
+def make_problem(i, n, k, precision="fp32"):
+    """(mesh, order, coeff) of problem i of a batch."""
+    sj, sc = problem_seeds(i)
+    v = structured_vertices(3, n, jitter=0.2, seed=sj)
+    coef = lognormal_coefficients(n ** 3, seed=sc)
+    mesh = F.create_mesh(3, [n, n, n], v, coef)
+    coeff = F.make_coeff("poisson", precision, source_kind=F.FE_SOURCE_CONST, source=(1.0,), dim=3)
+    return mesh, int(k), coeff
+
+
+def problem_bytes(n_rows, nnz, asm_ws_bytes):
+    """Device bytes one problem holds while its wave runs: CSR (int64 row
+    pointers, int32 columns, FP64 values), rhs, Jacobi diagonal, solution,
+    the PCG vectors (r, p, q) and its element workspace."""
+    return 8 * (n_rows + 1) + 12 * nnz + 3 * 8 * n_rows + 3 * 8 * n_rows + 256 * 1024 + asm_ws_bytes
+
+
+def plan_waves(sizes, budget):
+    """Greedy waves in problem order: a wave takes problems while their bytes
+    fit the budget.  A problem larger than the budget cannot run."""
+    waves, cur, used = [], [], 0
+    for i, b in enumerate(sizes):
+        if b > budget:
+            raise ValueError(f"problem {i} needs {b} bytes, more than the budget {budget}")
+        if cur and used + b > budget:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(i)
+        used += b
+    if cur:
+        waves.append(cur)
+    return waves
+
+
+class BatchRun:
+    """Meshes of a list of (n, k) specs, their sizes and wave plan."""
+
+    def __init__(self, specs, precision="fp32", budget=160 << 30, first_index=0):
+        self.specs = list(specs)
+        self.precision = precision
+        self.problems = [make_problem(first_index + i, n, k, precision) for i, (n, k) in enumerate(self.specs)]
+        self.sizes, self.n_rows, self.nnz = [], [], []
+        for mesh, k, coeff in self.problems:
+            nr, nz, ws = F.assemble_query(mesh, k, coeff)
+            self.n_rows.append(nr)
+            self.nnz.append(nz)
+            self.sizes.append(problem_bytes(nr, nz, ws))
+        self.waves = plan_waves(self.sizes, budget)
+        self.cells = sum(n ** 3 for n, _ in self.specs)
+
+    def autotune(self, reps=10):
+        """Tunes the SpMV plan of every row-length class in the batch on its
+        largest matrix (assembled alone for the purpose)."""
+        best = {}
+        for i, (nr, nz) in enumerate(zip(self.n_rows, self.nnz)):
+            if nr == 0:
+                continue
+            cls = F.spmv_plan_of(nr, nz)[2]
+            if cls not in best or nz > self.nnz[best[cls]]:
+                best[cls] = i
+        chosen = {}
+        for cls, i in sorted(best.items()):
+            mesh, k, coeff = self.problems[i]
+            A = F.Assembly(mesh, k, coeff)
+            A.pattern()
+            A.assemble()
+            ch, tried = F.spmv_autotune(A.csr, reps)
+            chosen[cls] = dict(chosen=ch, tried=tried, matrix=dict(problem=i, n_rows=self.n_rows[i], nnz=self.nnz[i]))
+            del A
+        return chosen
+
+    def run(self, rtol, maxit, keep=None, stream=None):
+        """Assembles and solves every wave; returns per-phase times and the
+        per-problem solver infos.  keep(i, x) is called with each solution."""
+        import torch
+        infos = [None] * len(self.specs)
+        t_setup = t_asm = t_solve = 0.0
+        status = F.FE_OK
+        for wave in self.waves:
+            ts = time.perf_counter()
+            probs = [self.problems[i] for i in wave]
+            B = F.BatchAssembly([p[0] for p in probs], [p[1] for p in probs], [p[2] for p in probs],
+                                stream=stream)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            B.assemble(stream)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            st, inf = B.solve(rtol, maxit, stream)
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            t_setup += ta - ts
+            t_asm += tb - ta
+            t_solve += tc - tb
+            if st != F.FE_OK and status == F.FE_OK:
+                status = st
+            for j, i in enumerate(wave):
+                infos[i] = inf[j]
+                if keep is not None:
+                    keep(i, B.x[j][: B.n_rows[j]])
+            del B
+            torch.cuda.empty_cache()
+        return dict(status=status, setup_s=t_setup, assemble_s=t_asm, solve_s=t_solve, infos=infos)
+
+
+def run_sequential(problems, rtol, maxit, keep=None, stream=None):
+    """The plain path, one problem at a time: fe_assemble then fe_pcg_solve
+    (set-up outside the timed part)."""
+    import torch
+    t_asm = t_solve = 0.0
+    infos = []
+    for i, (mesh, k, coeff) in enumerate(problems):
+        A = F.Assembly(mesh, k, coeff)
+        A.pattern()
+        ws = torch.empty(max(F.pcg_query(A.n_rows), 8), dtype=torch.uint8, device="cuda")
+        x = torch.zeros(max(A.n_rows, 1), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        A.assemble(stream)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        info = F.pcg_solve(A.csr, A.rhs, x, rtol, maxit, ws, stream) if A.n_rows else dict(iters=0, status=F.FE_OK)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        t_asm += tb - ta
+        t_solve += tc - tb
+        infos.append(info)
+        if keep is not None:
+            keep(i, x[: A.n_rows])
+        del A, ws, x
+    return dict(assemble_s=t_asm, solve_s=t_solve, infos=infos)

@@ -633,6 +633,37 @@ fe_status fe_pcg_solve_batch(int32_t nprob, const fe_csr *A, const double *const
     return pcg_solve_batch(nprob, A, b, x, rtol, maxit, ws, ws_bytes, infos, as_stream(stream));
 }
 
+fe_status fe_spmv_autotune_query(int64_t n_rows, size_t *ws_bytes)
+{
+    if (n_rows < 0 || !ws_bytes) return set_error(FE_EINVAL, "bad argument");
+    *ws_bytes = autotune_ws_bytes(n_rows);
+    return FE_OK;
+}
+
+fe_status fe_spmv_autotune(const fe_csr *A, int32_t reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried,
+                           int32_t max_tried, int32_t *n_tried, fe_spmv_plan *chosen, fe_stream stream)
+{
+    if (!A || !ws || !A->rowptr || !A->colind || !A->values) return set_error(FE_EINVAL, "null argument");
+    if (reps < 1 || max_tried < 0 || (max_tried > 0 && !tried)) return set_error(FE_EINVAL, "bad reps/max_tried");
+    int nt = 0;
+    const fe_status st = spmv_autotune(A, reps, ws, ws_bytes, tried, max_tried, &nt, chosen, as_stream(stream));
+    if (n_tried) *n_tried = nt;
+    return st;
+}
+
+fe_status fe_spmv_tuning_reset(void)
+{
+    spmv_tuning_reset();
+    return FE_OK;
+}
+
+fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32_t *row_class)
+{
+    if (n_rows < 0 || nnz < 0) return set_error(FE_EINVAL, "negative size");
+    spmv_plan_of(n_rows, nnz, plan, row_class);
+    return FE_OK;
+}
+
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream)
 {
     if (!A || !x || !y || !A->rowptr || !A->colind || !A->values) return set_error(FE_EINVAL, "null argument");

@@ -170,6 +170,11 @@ fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, in
 size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows);
 fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
                           int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s);
+size_t autotune_ws_bytes(int64_t n);
+fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried, int max_tried,
+                        int *n_tried, fe_spmv_plan *chosen, hipStream_t s);
+void spmv_tuning_reset();
+void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls);
 size_t refine_ws_bytes(int64_t n);
 fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s);
 fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,

@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -105,9 +107,8 @@ static PcgWs carve(void *ws, int64_t n)
 }
 
 // Device slot for the problem table of a single-problem solve (inside its workspace).
-static SpmvPlan plan_for(int64_t n, int64_t nnz)
+static SpmvPlan heuristic_plan(double avg)
 {
-    const double avg = n > 0 ? double(nnz) / double(n) : 1.0;
     SpmvPlan pl{};
     if (avg >= 96.0) {
         pl.mode = 1;
@@ -121,6 +122,29 @@ static SpmvPlan plan_for(int64_t n, int64_t nnz)
     pl.rpb = rpw;
     pl.lanes = 64 / rpw;
     return pl;
+}
+
+// Plans measured by the autotuner, per class of average row length (half
+// octaves of nnz / n).  A plan fixes the summation order of every row, so a
+// matrix gets the same plan alone and in a batch as long as the table is not
+// changed in between.
+static std::mutex g_tune_mu;
+static std::map<int, SpmvPlan> g_tuned;
+
+static int plan_class(int64_t n, int64_t nnz)
+{
+    const double avg = n > 0 ? double(nnz) / double(n) : 1.0;
+    return int(std::floor(2.0 * std::log2(std::max(avg, 1.0))));
+}
+
+static SpmvPlan plan_for(int64_t n, int64_t nnz)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(plan_class(n, nnz));
+        if (it != g_tuned.end()) return it->second;
+    }
+    return heuristic_plan(n > 0 ? double(nnz) / double(n) : 1.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,6 +618,81 @@ struct PinnedState {
         if (h) (void)hipHostFree(h);
     }
 };
+
+// ---------------------------------------------------------------------------
+// SpMV autotuner: times every plan on a matrix and keeps the fastest for the
+// matrix's row-length class.
+// ---------------------------------------------------------------------------
+static const SpmvPlan kCandidates[] = {{0, 1, 64}, {0, 2, 32}, {0, 4, 16}, {0, 8, 8}, {0, 16, 4}, {0, 32, 2}, {1, 1, 64}};
+
+size_t autotune_ws_bytes(int64_t n) { return 2 * align256(size_t(std::max<int64_t>(n, 1)) * sizeof(double)); }
+
+fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried, int max_tried,
+                        int *n_tried, fe_spmv_plan *chosen, hipStream_t s)
+{
+    const int64_t n = A->n_rows;
+    if (ws_bytes < autotune_ws_bytes(n)) return set_error(FE_EINVAL, "autotune workspace too small");
+    double *x = static_cast<double *>(ws);
+    double *y = reinterpret_cast<double *>(static_cast<char *>(ws) + align256(size_t(std::max<int64_t>(n, 1)) * 8));
+    if (n_tried) *n_tried = 0;
+    if (n == 0) return set_error(FE_EINVAL, "empty matrix");
+    FE_HIP(hipMemsetAsync(x, 0, sizeof(double) * size_t(n), s));
+    hipEvent_t e0, e1;
+    FE_HIP(hipEventCreate(&e0));
+    FE_HIP(hipEventCreate(&e1));
+    int best = -1;
+    double best_us = 0.0;
+    const int ncand = int(sizeof(kCandidates) / sizeof(kCandidates[0]));
+    fe_status st = FE_OK;
+    for (int c = 0; c < ncand && st == FE_OK; c++) {
+        const SpmvPlan &pl = kCandidates[c];
+        const int g = grid_rows(n, pl);
+        for (int r = -1; r < reps; r++) {
+            if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = set_error(FE_EDEVICE, "event record failed");
+            FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb, double><<<dim3(g), dim3(kBlock), 0, s>>>(
+                                     n, A->rowptr, A->colind, A->values, x, y)));
+        }
+        if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess) {
+            st = set_error(FE_EDEVICE, "autotune launch failed");
+            break;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = set_error(FE_EDEVICE, "event timing failed");
+            break;
+        }
+        const double us = 1000.0 * double(ms) / double(reps);
+        if (tried && c < max_tried) tried[c] = fe_spmv_plan{pl.mode, pl.rpb, us};
+        if (n_tried) *n_tried = std::min(c + 1, max_tried);
+        if (best < 0 || us < best_us) {
+            best = c;
+            best_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FE_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[plan_class(n, A->nnz)] = kCandidates[best];
+    }
+    if (chosen) *chosen = fe_spmv_plan{kCandidates[best].mode, kCandidates[best].rpb, best_us};
+    return FE_OK;
+}
+
+void spmv_tuning_reset()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
+
+void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls)
+{
+    const SpmvPlan pl = plan_for(n, nnz);
+    if (plan) *plan = fe_spmv_plan{pl.mode, pl.rpb, 0.0};
+    if (cls) *cls = plan_class(n, nnz);
+}
 
 // ---------------------------------------------------------------------------
 // PCG engine: any number of problems solved together.  Problems are grouped

@@ -26,6 +26,7 @@ EXPORTS = [
     "fe_cell_dofs", "fe_permutation", "fe_get_status", "fe_pcg_query", "fe_pcg_solve", "fe_spmv",
     "fe_set_timing", "fe_get_timing", "fe_csr_to_fp32", "fe_refine_query", "fe_refine_solve",
     "fe_pcg_batch_query", "fe_pcg_solve_batch", "fe_assemble_batch_query", "fe_assemble_batch",
+    "fe_spmv_autotune_query", "fe_spmv_autotune", "fe_spmv_tuning_reset", "fe_spmv_plan_of",
 ]
 
 _c = ctypes
@@ -57,6 +58,10 @@ class Csr(_c.Structure):
 class SolveInfo(_c.Structure):
     _fields_ = [("iters", _c.c_int32), ("status", _c.c_int32), ("relres", _c.c_double),
                 ("true_relres", _c.c_double), ("lambda_min_est", _c.c_double), ("lambda_max_est", _c.c_double)]
+
+
+class SpmvPlan(_c.Structure):
+    _fields_ = [("mode", _c.c_int32), ("rows_per_wave", _c.c_int32), ("us", _c.c_double)]
 
 
 class RefineInfo(_c.Structure):
@@ -113,6 +118,11 @@ def lib():
                                         _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
             "fe_assemble_batch": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
                                   _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_spmv_autotune_query": [_c.c_int64, _c.POINTER(_c.c_size_t)],
+            "fe_spmv_autotune": [_c.POINTER(Csr), _c.c_int32, _P, _c.c_size_t, _c.POINTER(SpmvPlan), _c.c_int32,
+                                 _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
+            "fe_spmv_tuning_reset": [],
+            "fe_spmv_plan_of": [_c.c_int64, _c.c_int64, _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
             "fe_pcg_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
             "fe_pcg_solve_batch": [_c.c_int32, _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P), _c.c_double,
                                    _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
@@ -297,6 +307,34 @@ def pcg_solve_batch(csrs, bs, xs, rtol, maxit, ws, stream=None, check=True):
         _check(st, "fe_pcg_solve_batch")
     out = [dict(iters=i.iters, status=i.status, relres=i.relres, true_relres=i.true_relres) for i in infos[:n]]
     return st, out
+
+
+def spmv_autotune(csr, reps=20, stream=None):
+    """Times every SpMV plan on csr and keeps the fastest for its row-length
+    class; returns (chosen, tried) as dicts (mode, rows_per_wave, us)."""
+    import torch
+    q = _c.c_size_t()
+    _check(lib().fe_spmv_autotune_query(int(csr.n_rows), _c.byref(q)), "fe_spmv_autotune_query")
+    ws = torch.empty(max(q.value, 8), dtype=torch.uint8, device="cuda")
+    tried = (SpmvPlan * 16)()
+    nt = _c.c_int32()
+    ch = SpmvPlan()
+    _check(lib().fe_spmv_autotune(_c.byref(csr), int(reps), _ptr(ws), q.value, tried, 16, _c.byref(nt),
+                                  _c.byref(ch), _stream(stream)), "fe_spmv_autotune")
+    d = lambda p: dict(mode=p.mode, rows_per_wave=p.rows_per_wave, us=p.us)
+    return d(ch), [d(t) for t in tried[: nt.value]]
+
+
+def spmv_tuning_reset():
+    _check(lib().fe_spmv_tuning_reset(), "fe_spmv_tuning_reset")
+
+
+def spmv_plan_of(n_rows, nnz):
+    """(mode, rows_per_wave, row_class) a matrix of this size gets now."""
+    p = SpmvPlan()
+    c = _c.c_int32()
+    _check(lib().fe_spmv_plan_of(int(n_rows), int(nnz), _c.byref(p), _c.byref(c)), "fe_spmv_plan_of")
+    return p.mode, p.rows_per_wave, c.value
 
 
 def spmv(csr, x, y, stream=None):

@@ -72,3 +72,30 @@ def test_null_and_bad_arguments_rejected():
     assert L.fe_pcg_query(1000, ctypes.byref(ws)) == F.FE_OK and ws.value > 3 * 8000
     assert L.fe_pcg_solve(None, None, None, 1e-8, 10, None, 0, None, None) == F.FE_EINVAL
     assert L.fe_spmv(None, None, None, None) == F.FE_EINVAL
+
+
+def test_batch_and_tuning_entry_points_validate_on_host():
+    L = F.lib()
+    ws = ctypes.c_size_t()
+    assert ctypes.sizeof(F.SpmvPlan) == 16
+    assert L.fe_pcg_batch_query(-1, None, ctypes.byref(ws)) == F.FE_EINVAL
+    rows = (ctypes.c_int64 * 2)(1000, -5)
+    assert L.fe_pcg_batch_query(2, rows, ctypes.byref(ws)) == F.FE_EINVAL
+    rows[1] = 10
+    assert L.fe_pcg_batch_query(2, rows, ctypes.byref(ws)) == F.FE_OK
+    one = ctypes.c_size_t()
+    assert L.fe_pcg_query(1000, ctypes.byref(one)) == F.FE_OK
+    assert ws.value > one.value  # two systems need more than one
+    assert L.fe_pcg_solve_batch(0, None, None, None, 1e-8, 10, None, 0, None, None) == F.FE_OK
+    assert L.fe_pcg_solve_batch(-1, None, None, None, 1e-8, 10, None, 0, None, None) == F.FE_EINVAL
+    assert L.fe_assemble_batch_query(-1, None, None, None, None, None, ctypes.byref(ws)) == F.FE_EINVAL
+    assert L.fe_assemble_batch_query(0, None, None, None, None, None, ctypes.byref(ws)) == F.FE_OK
+    assert L.fe_assemble_batch_query(2, None, None, None, None, None, ctypes.byref(ws)) == F.FE_EINVAL
+    assert L.fe_spmv_autotune(None, 5, None, 0, None, 0, None, None, None) == F.FE_EINVAL
+    assert L.fe_spmv_autotune_query(-1, ctypes.byref(ws)) == F.FE_EINVAL
+    # untuned plans follow the row length: short rows share a wave, long rows get one each
+    assert L.fe_spmv_tuning_reset() == F.FE_OK
+    mode, rpw, cls = F.spmv_plan_of(1000, 27000)
+    assert mode == 0 and rpw * 27 <= 256 and rpw * 2 * 27 > 256
+    mode, rpw, cls2 = F.spmv_plan_of(1000, 343000)
+    assert mode == 1 and cls2 > cls

@@ -157,3 +157,31 @@ def test_batch_assembly_rejects_bad_batches():
     nr, nz, _ = F.assemble_batch_query([], [], [])
     assert nr == [] and nz == []
     F.assemble_batch([], [], [], [], small)
+
+
+def test_spmv_autotuner_picks_a_measured_plan_and_keeps_results():
+    import oracle as O
+    pair = Pair(3, [10, 9, 8], 2)
+    A = pair.gpu_assembly()
+    S = pair.system
+    x = np.random.Generator(np.random.PCG64(5)).standard_normal(A.n_rows)
+    xd = torch.from_numpy(x).cuda()
+    yo = O.spmv(S.rowptr, S.colind, S.values, x)
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x))
+    F.spmv_tuning_reset()
+    try:
+        untuned = F.spmv_plan_of(A.n_rows, A.nnz)
+        chosen, tried = F.spmv_autotune(A.csr, reps=5)
+        say(f"[autotune] untuned {untuned} chosen {chosen}")
+        assert len(tried) == 7 and all(t["us"] > 0 for t in tried)
+        assert chosen["us"] == min(t["us"] for t in tried)
+        mode, rpw, _ = F.spmv_plan_of(A.n_rows, A.nnz)
+        assert (mode, rpw) == (chosen["mode"], chosen["rows_per_wave"])
+        # every candidate plan computes the same product up to rounding
+        y = torch.empty_like(xd)
+        F.spmv(A.csr, xd, y)
+        torch.cuda.synchronize()
+        assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+    finally:
+        F.spmv_tuning_reset()
+    assert F.spmv_plan_of(A.n_rows, A.nnz) == untuned
