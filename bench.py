@@ -236,6 +236,69 @@ def batch_form(args, F, torch):
     }
 
 
+def serve_form(args, F, torch):
+    """Serving form: a bounded sample of the seeded Poisson-process request
+    stream (3D Poisson, n log-uniform in [8, 96], order uniform in 1..4, rtol
+    1e-8) replayed against the library's server.  The sample keeps, in arrival
+    order, the requests of at most --serve-max-dofs unknowns (thinning a
+    Poisson process by size keeps it a Poisson process, at the kept fraction of
+    the rate).  Three requests are re-run alone through the plain path and
+    compared bitwise with their result in the mix."""
+    from fe_inputs import serving_requests
+    from paper_1708_01773_amd import serve as SV
+
+    rtol, maxit = 1e-8, 200000
+    drawn = serving_requests(2000, args.serve_rate)
+    kept = [(t, n, k, i) for i, (t, n, k) in enumerate(drawn) if (n * k - 1) ** 3 <= args.serve_max_dofs]
+    kept = kept[: args.serve_requests]
+    t_first = kept[0][0]
+    span = kept[-1][0] - t_first
+    stream = [(t - t_first, n, k, i) for (t, n, k, i) in kept]
+    print(f"[bench] serving form: {len(stream)} requests over {span:.2f} s of arrivals", file=sys.stderr, flush=True)
+    srv = F.Server(int(args.serve_budget_gb * (1 << 30)), max_active=args.serve_slots)
+    probes = {}
+    order = sorted(range(len(stream)), key=lambda j: (stream[j][1] * stream[j][2]) ** 3)
+    for j in (order[0], order[len(order) // 2], order[-1]):
+        probes[j] = None
+
+    def keep(j, ticket, r):
+        if j in probes and r["state"] == F.FE_REQ_DONE:
+            x = torch.empty(r["n_rows"], dtype=torch.float64, device="cuda")
+            srv.solution(ticket, x)
+            probes[j] = x
+
+    results, makespan = SV.run_stream(srv, stream, rtol=rtol, maxit=maxit, on_done=keep)
+    stats = srv.stats()
+    srv.close()
+    summary = SV.summarize(results, makespan)
+    same = True
+    for j, x_mix in probes.items():
+        _, n, k, i = stream[j]
+        a = SV.request_inputs(i, n, k)
+        mesh = F.create_mesh(3, a["n"], a["vertices"], a["cell_coeff"])
+        A = F.Assembly(mesh, k, a["coeff"])
+        A.pattern()
+        A.assemble()
+        x = torch.zeros(max(A.n_rows, 1), dtype=torch.float64, device="cuda")
+        ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+        F.pcg_solve(A.csr, A.rhs, x, rtol, maxit, ws)
+        torch.cuda.synchronize()
+        same = same and x_mix is not None and torch.equal(x[: A.n_rows], x_mix)
+        del A, mesh, x, ws
+    print(f"[bench] serving form: {summary['solves_per_s']:.1f} solves/s, p50 {summary['p50_ms']:.1f} ms, "
+          f"p99 {summary['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return {
+        "sample": f"first {len(stream)} requests with at most {args.serve_max_dofs} unknowns of the stream drawn "
+                  f"with seed 17083 at {args.serve_rate}/s (n log-uniform in [8, 96], order uniform in 1..4); "
+                  f"{len(stream)} of {kept[-1][3] + 1} drawn requests kept",
+        "arrival_rate_per_s": (len(stream) - 1) / span if span > 0 else None,
+        "rtol": rtol, "budget_gb": args.serve_budget_gb, "max_active": args.serve_slots, **summary,
+        "peak_in_flight": stats["peak_solving"], "peak_bytes": stats["peak_in_use"],
+        "admission_waits": stats["admission_waits"], "chunks": stats["chunks"],
+        "bitwise_equal_alone_vs_mix": bool(same), "checked_alone": len(probes),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,7 +316,12 @@ def main():
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="problems of the 512-problem batch run by the batching form (0 = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0, help="device memory per batch wave")
-    ap.add_argument("--form", default=None, choices=["batch"], help="run only this form and print its JSON")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving form (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrival rate of the drawn stream (1/s)")
+    ap.add_argument("--serve-max-dofs", type=int, default=1000000, help="largest request kept in the sample")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--form", default=None, choices=["batch", "serve"], help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -280,6 +348,10 @@ def main():
     if args.form == "batch":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "batch", **batch_form(args, F, torch)}), flush=True)
+        return
+    if args.form == "serve":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "serve", **serve_form(args, F, torch)}), flush=True)
         return
 
     wl = dict(WORKLOADS[args.workload])
@@ -381,6 +453,8 @@ def main():
             del A, ws, x
             torch.cuda.empty_cache()
             out["forms"]["batch"] = batch_form(args, F, torch)
+        if args.serve_requests > 0 and args.workload == "c2":
+            out["forms"]["serve"] = serve_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, A.nnz)

@@ -307,6 +307,77 @@ fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *v
                           size_t ws_bytes, fe_refine_info *info, fe_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: a request loop with admission by device-memory budget            */
+/* ------------------------------------------------------------------------ */
+/* A server owns one device-memory budget on the current device and two host
+ * threads.  Each request is one assemble-and-solve of the system above
+ * (Sect. 3.6-3.7 assembly, Sect. 10.4 Dirichlet elimination, Jacobi-PCG of
+ * Sect. 12) on its own structured mesh.  Requests are admitted in submission
+ * order when their bytes (CSR, vectors and PCG state, element workspace
+ * during assembly, mesh arrays) fit the remaining budget and fewer than
+ * max_active are in flight; set-up and assembly run on one stream while the
+ * CG iterations of every request in flight run as batched chunks on another,
+ * new requests joining between chunks (continuous batching).  A request's
+ * result is bitwise that of fe_assemble + fe_pcg_solve on it alone.  A
+ * finished request keeps its system and solution on the device until
+ * fe_server_release.  Calls are thread-safe. */
+typedef struct fe_server_s *fe_server;
+
+typedef struct {
+    fe_mesh_desc mesh;  /* host arrays, copied by fe_server_submit */
+    int32_t order;      /* 1..4 */
+    fe_coeff coeff;
+    double rtol;        /* ||r|| <= rtol ||b|| */
+    int32_t maxit;
+} fe_request;
+
+typedef enum {
+    FE_REQ_QUEUED = 0,
+    FE_REQ_SETUP = 1,    /* admitted: mesh, pattern, assembly */
+    FE_REQ_SOLVING = 2,  /* in the batched CG chunks */
+    FE_REQ_DONE = 3,     /* status = the solver's status */
+    FE_REQ_FAILED = 4    /* status = the error; fe_last_error() has its text after poll/wait */
+} fe_request_state;
+
+typedef struct {
+    int32_t state;
+    int32_t status;
+    int64_t n_rows, nnz;
+    int64_t bytes;  /* device bytes charged at admission */
+    int32_t iters;
+    double relres, true_relres;
+    double t_submit, t_admit, t_ready, t_done;  /* seconds on fe_server_clock */
+} fe_result;
+
+typedef struct {
+    int64_t budget, arena_bytes, mesh_reserve, in_use, peak_in_use, peak_arena;
+    int32_t queued, setting_up, solving, peak_solving;
+    int64_t submitted, admitted, completed, rejected, chunks;
+    int64_t admission_waits;  /* times the head of the queue waited for memory or a slot */
+} fe_server_stats;
+
+/* hbm_budget: device bytes the server may hold (allocated at creation: one
+ * arena plus a reserve of budget / 8 for mesh arrays).  FE_ENOMEM if the
+ * device cannot hold it. */
+fe_status fe_server_create(size_t hbm_budget, int32_t max_active, fe_server *out);
+/* Queues a request; FE_ENOMEM if it can never fit the budget, FE_EINVAL for
+ * invalid sizes or parameters (others are reported as FE_REQ_FAILED). */
+fe_status fe_server_submit(fe_server server, const fe_request *req, uint64_t *ticket);
+fe_status fe_server_poll(fe_server server, uint64_t ticket, fe_result *out);
+/* Waits until the request is done or failed, or timeout_s passed (then
+ * out->state tells which). */
+fe_status fe_server_wait(fe_server server, uint64_t ticket, double timeout_s, fe_result *out);
+/* Copies the n = n_rows solution values of a done request into x (device or
+ * host memory); synchronous. */
+fe_status fe_server_solution(fe_server server, uint64_t ticket, double *x, int64_t n);
+/* Frees a done or failed request's device memory and forgets the ticket. */
+fe_status fe_server_release(fe_server server, uint64_t ticket);
+fe_status fe_server_get_stats(fe_server server, fe_server_stats *out);
+double fe_server_clock(fe_server server);
+/* Stops admitting, fails queued requests, finishes those in flight, frees all. */
+fe_status fe_server_destroy(fe_server server);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (for benchmarks)                                            */
 /* ------------------------------------------------------------------------ */
 /* When enabled (process-wide), fe_integrate / fe_scatter record HIP events

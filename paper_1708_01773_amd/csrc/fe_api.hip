@@ -175,12 +175,19 @@ static MeshArgs mesh_args(const fe_mesh m)
 }
 
 // Builds (or reuses) the cached set-up for (order, problem, faces).
-static fe_status ensure_space(fe_mesh m, int32_t order, const fe_coeff *c)
+static fe_status ensure_space(fe_mesh m, int32_t order, const fe_coeff *c, hipStream_t s = nullptr)
 {
     const int ncomp = c->problem == FE_ELASTICITY ? m->dim : 1;
     Space &sp = m->space;
     if (sp.valid && sp.k == order && sp.ncomp == ncomp && sp.faces == c->dirichlet_faces) return FE_OK;
-    return build_space(m, order, ncomp, c->dirichlet_faces, sp);
+    return build_space(m, order, ncomp, c->dirichlet_faces, sp, s);
+}
+
+fe_status prepare_space(fe_mesh m, int32_t order, const fe_coeff *c, hipStream_t s)
+{
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    return ensure_space(m, order, c, s);
 }
 
 static fe_status check_csr(const fe_csr *out, const SpaceArgs &sa, bool need_values)

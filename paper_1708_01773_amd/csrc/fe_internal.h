@@ -127,7 +127,11 @@ struct fe_mesh_s {
 namespace fe {
 
 // Set-up (fe_setup.hip)
-fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp);
+fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp, hipStream_t s);
+// Rows and nonzeros of a structured space, from the axis tables on the host.
+void space_sizes(int dim, const int32_t *n, int k, int ncomp, uint32_t faces, int64_t &n_rows, int64_t &nnz);
+// Validates (mesh, order, coeff) and builds the cached space on stream s.
+fe_status prepare_space(fe_mesh m, int32_t order, const fe_coeff *c, hipStream_t s);
 void free_space(Space &sp);
 fe_status launch_pattern(const SpaceArgs &sa, int64_t *rowptr, int32_t *colind, hipStream_t s);
 fe_status launch_cell_dofs(const SpaceArgs &sa, const MeshArgs &ma, int32_t *out, hipStream_t s);
@@ -162,6 +166,36 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
 
 // Solver (fe_solve.hip)
 size_t pcg_ws_bytes(int64_t n);
+
+// PCG engine over a set of problems (fe_solve.hip).  A job's ws holds
+// pcg_ws_bytes(n) bytes of its own state and vectors; the set's table lives
+// in engine_table_bytes(number of jobs) bytes of device memory.  Jobs with
+// n == 0 are left out of the set.
+struct PcgJob {
+    int64_t n, nnz;
+    const int64_t *rowptr;
+    const int32_t *colind;
+    const void *val;
+    bool fp32;  // values stored as float
+    const double *dinv, *b;
+    double *x;
+    void *ws;
+    fe_solve_info *info;  // filled by engine_finish (may be null)
+    double rtol;
+    int maxit;
+};
+struct EngineSet;
+EngineSet *engine_create();
+void engine_destroy(EngineSet *E);
+size_t engine_table_bytes(int njobs);
+fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table, hipStream_t s);
+int engine_size(const EngineSet &E);
+const PcgJob &engine_job(const EngineSet &E, int t);  // t-th job of the sorted set
+fe_status engine_init(EngineSet &E, hipStream_t s);
+fe_status engine_iterate(EngineSet &E, int iters, hipStream_t s);
+fe_status engine_states(EngineSet &E, hipStream_t s);  // synchronizes
+bool engine_done(const EngineSet &E, int t);           // from the last engine_states / engine_finish
+fe_status engine_finish(EngineSet &E, hipStream_t s);  // true residuals + infos; synchronizes
 fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
                       double *y, double nnz_per_row, hipStream_t s);
 size_t pcg_solve_ws_bytes(int64_t n);

@@ -109,7 +109,7 @@ static void axis_table(int64_t n, int64_t N, int k, bool lo_fixed, bool hi_fixed
     (void)n;
 }
 
-fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp)
+fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp, hipStream_t s)
 {
     free_space(sp);
     SpaceArgs &a = sp.args;
@@ -151,7 +151,7 @@ fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp)
         off += 3 * f;
     }
     FE_HIP(hipMalloc(&sp.d_axis, sizeof(int64_t) * host.size()));
-    FE_HIP(hipMemcpy(sp.d_axis, host.data(), sizeof(int64_t) * host.size(), hipMemcpyHostToDevice));
+    FE_HIP(hipMemcpyAsync(sp.d_axis, host.data(), sizeof(int64_t) * host.size(), hipMemcpyHostToDevice, s));
     for (int r = 0; r < 3; r++) {
         const int64_t f = a.ax[r].f;
         a.ax[r].cl = sp.d_axis + offs[r];
@@ -163,14 +163,28 @@ fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp)
     ma.n0 = a.ax[0].n;
     ma.n1 = a.ax[1].n;
     ma.n2 = a.ax[2].n;
-    fe_status st = launch_cell_dofs(a, ma, sp.d_cell_dofs, nullptr);
+    fe_status st = launch_cell_dofs(a, ma, sp.d_cell_dofs, s);
     if (st != FE_OK) return st;
-    FE_HIP(hipDeviceSynchronize());
+    // the host table above must outlive the copy
+    FE_HIP(hipStreamSynchronize(s));
     sp.k = k;
     sp.ncomp = ncomp;
     sp.faces = faces;
     sp.valid = true;
     return FE_OK;
+}
+
+void space_sizes(int dim, const int32_t *n, int k, int ncomp, uint32_t faces, int64_t &n_rows, int64_t &nnz)
+{
+    std::vector<int64_t> cl, w, P;
+    int64_t f[3] = {1, 1, 1}, T[3] = {1, 1, 1};
+    for (int r = 0; r < dim; r++) {
+        int64_t lo;
+        axis_table(n[r], int64_t(n[r]) * k, k, (faces >> (2 * r)) & 1u, (faces >> (2 * r + 1)) & 1u, cl, w, P, lo,
+                   f[r], T[r]);
+    }
+    n_rows = f[0] * f[1] * f[2] * ncomp;
+    nnz = int64_t(ncomp) * ncomp * T[0] * T[1] * T[2];
 }
 
 void free_space(Space &sp)

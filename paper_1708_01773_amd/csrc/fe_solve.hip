@@ -700,18 +700,6 @@ void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls)
 // vector kernels serve all problems in one launch.  Chunks of iterations are
 // launched directly or replayed from a captured HIP graph.
 // ---------------------------------------------------------------------------
-struct PcgJob {
-    int64_t n, nnz;
-    const int64_t *rowptr;
-    const int32_t *colind;
-    const void *val;
-    bool fp32;  // values stored as float
-    const double *dinv, *b;
-    double *x;
-    void *ws;
-    fe_solve_info *info;
-};
-
 __global__ __launch_bounds__(kBlock) void count_active_kernel(const PcgProb *__restrict__ probs, int nprob,
                                                                int32_t *active)
 {
@@ -733,10 +721,11 @@ __global__ __launch_bounds__(kBlock) void gather_states_kernel(const PcgProb *__
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < nprob; i += gridDim.x * kBlock) out[i] = *probs[i].w.st;
 }
 
-size_t pcg_table_bytes(int nprob)
+size_t engine_table_bytes(int nprob)
 {
-    return align256(sizeof(PcgProb) * size_t(nprob)) + align256(sizeof(int32_t) * (3 * size_t(nprob) + 16)) +
-           align256(sizeof(PcgState) * size_t(nprob)) + 256;
+    return align256(sizeof(PcgProb) * size_t(std::max(nprob, 1))) +
+           align256(sizeof(int32_t) * (3 * size_t(nprob) + 16)) +
+           align256(sizeof(PcgState) * size_t(std::max(nprob, 1))) + 256;
 }
 
 struct Group {
@@ -746,6 +735,27 @@ struct Group {
     int32_t *d_boff;   // count + 1 block offsets of the row kernels
     int grid;
 };
+
+// A set of problems launched together: the device table is sorted by (SpMV
+// plan, value type) so that each row-kernel instantiation is one launch; the
+// vector kernels cover the whole table in one launch.
+struct EngineSet {
+    std::vector<PcgJob> jobs;   // sorted like the table
+    std::vector<PcgProb> hp;
+    std::vector<int32_t> hi;
+    std::vector<Group> groups;
+    std::vector<PcgState> hs;
+    int np = 0, ge = 0;
+    PcgProb *d_probs = nullptr;
+    int32_t *d_ints = nullptr;
+    PcgState *d_states = nullptr;
+    int32_t *d_active = nullptr;
+};
+
+EngineSet *engine_create() { return new EngineSet(); }
+void engine_destroy(EngineSet *E) { delete E; }
+int engine_size(const EngineSet &E) { return E.np; }
+const PcgJob &engine_job(const EngineSet &E, int t) { return E.jobs[t]; }
 
 template <typename VT>
 static void launch_rows_group(int which, const Group &g, const PcgProb *probs, hipStream_t s)
@@ -770,6 +780,149 @@ static void launch_rows(int which, const Group &g, const PcgProb *probs, hipStre
     else launch_rows_group<double>(which, g, probs, s);
 }
 
+fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table, hipStream_t s)
+{
+    std::vector<int> order;
+    std::vector<SpmvPlan> plans(njobs);
+    for (int i = 0; i < njobs; i++) {
+        plans[i] = plan_for(jobs[i].n, jobs[i].nnz);
+        if (jobs[i].n > 0) order.push_back(i);
+    }
+    auto key = [&](int i) { return (plans[i].mode * 64 + plans[i].rpb) * 2 + (jobs[i].fp32 ? 1 : 0); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    const int np = int(order.size());
+    E.np = np;
+    E.jobs.clear();
+    E.hp.assign(np, PcgProb{});
+    E.hi.assign(3 * size_t(np) + 16, 0);
+    E.groups.clear();
+    E.hs.assign(np, PcgState{});
+    if (np == 0) return FE_OK;
+    char *tb = static_cast<char *>(table);
+    const size_t sp = align256(sizeof(PcgProb) * size_t(np));
+    const size_t si = align256(sizeof(int32_t) * (3 * size_t(np) + 16));
+    const size_t ss = align256(sizeof(PcgState) * size_t(np));
+    E.d_probs = reinterpret_cast<PcgProb *>(tb);
+    E.d_ints = reinterpret_cast<int32_t *>(tb + sp);
+    E.d_states = reinterpret_cast<PcgState *>(tb + sp + si);
+    E.d_active = reinterpret_cast<int32_t *>(tb + sp + si + ss);
+    int32_t eoff = 0;
+    for (int t = 0; t < np; t++) {
+        const PcgJob &jb = jobs[order[t]];
+        E.jobs.push_back(jb);
+        PcgProb &P = E.hp[t];
+        P.n = jb.n;
+        P.nnz = jb.nnz;
+        P.rowptr = jb.rowptr;
+        P.colind = jb.colind;
+        P.val = jb.val;
+        P.dinv = jb.dinv;
+        P.b = jb.b;
+        P.x = jb.x;
+        P.w = carve(jb.ws, jb.n);
+        P.rtol2 = jb.rtol * jb.rtol;
+        P.maxit = jb.maxit;
+        const SpmvPlan &pl = plans[order[t]];
+        P.nbr = grid_rows(jb.n, pl);
+        P.nbe = grid_elems(jb.n);
+        E.hi[t] = eoff;
+        eoff += P.nbe;
+        if (E.groups.empty() || key(order[E.groups.back().first]) != key(order[t])) {
+            Group g{};
+            g.pl = pl;
+            g.fp32 = jb.fp32;
+            g.first = t;
+            g.count = 0;
+            E.groups.push_back(g);
+        }
+        E.groups.back().count++;
+    }
+    E.hi[np] = eoff;
+    E.ge = eoff;
+    int pos = np + 1;
+    for (Group &g : E.groups) {
+        int32_t off = 0;
+        for (int t = 0; t < g.count; t++) {
+            E.hi[pos + t] = off;
+            off += E.hp[g.first + t].nbr;
+        }
+        E.hi[pos + g.count] = off;
+        g.grid = off;
+        g.d_boff = E.d_ints + pos;
+        pos += g.count + 1;
+    }
+    FE_HIP(hipMemcpyAsync(E.d_probs, E.hp.data(), sizeof(PcgProb) * size_t(np), hipMemcpyHostToDevice, s));
+    FE_HIP(hipMemcpyAsync(E.d_ints, E.hi.data(), sizeof(int32_t) * size_t(pos), hipMemcpyHostToDevice, s));
+    return FE_OK;
+}
+
+// r = b - A x, p = z, first scalars and stop test of every problem of the set
+fe_status engine_init(EngineSet &E, hipStream_t s)
+{
+    if (E.np == 0) return FE_OK;
+    for (const Group &g : E.groups) launch_rows(0, g, E.d_probs, s);
+    hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(E.np), dim3(kBlock), 0, s, E.d_probs);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+// One CG iteration of every problem still running; marks are event pairs
+// around the SpMV launches when timing is requested.
+static void engine_iteration(const EngineSet &E, hipStream_t q, std::vector<std::pair<hipEvent_t, hipEvent_t>> *marks)
+{
+    for (const Group &g : E.groups) {
+        hipEvent_t t0 = marks ? timing_mark(q) : nullptr;
+        launch_rows(1, g, E.d_probs, q);
+        if (t0) marks->emplace_back(t0, timing_mark(q));
+    }
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(E.ge), dim3(kBlock), 0, q, E.d_probs, E.d_ints, E.np);
+    hipLaunchKernelGGL(pcg_dir_kernel, dim3(E.ge), dim3(kBlock), 0, q, E.d_probs, E.d_ints, E.np);
+}
+
+fe_status engine_iterate(EngineSet &E, int iters, hipStream_t s)
+{
+    if (E.np == 0) return FE_OK;
+    for (int i = 0; i < iters; i++) engine_iteration(E, s, nullptr);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+// Copies every problem's state to E.hs (waits for the stream).
+fe_status engine_states(EngineSet &E, hipStream_t s)
+{
+    if (E.np == 0) return FE_OK;
+    hipLaunchKernelGGL(gather_states_kernel, dim3((E.np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, E.d_probs, E.np,
+                       E.d_states);
+    FE_HIP(hipGetLastError());
+    FE_HIP(hipMemcpyAsync(E.hs.data(), E.d_states, sizeof(PcgState) * size_t(E.np), hipMemcpyDeviceToHost, s));
+    FE_HIP(hipStreamSynchronize(s));
+    return FE_OK;
+}
+
+// True residuals of every problem of the set, then their states and infos.
+fe_status engine_finish(EngineSet &E, hipStream_t s)
+{
+    if (E.np == 0) return FE_OK;
+    for (const Group &g : E.groups) launch_rows(2, g, E.d_probs, s);
+    hipLaunchKernelGGL(resid_finish_kernel, dim3(E.np), dim3(kBlock), 0, s, E.d_probs);
+    FE_HIP(hipGetLastError());
+    fe_status st = engine_states(E, s);
+    if (st != FE_OK) return st;
+    for (int t = 0; t < E.np; t++) {
+        const PcgState &h = E.hs[t];
+        fe_solve_info *info = E.jobs[t].info;
+        if (!info) continue;
+        info->iters = h.iter;
+        info->status = h.done ? h.status : FE_ENOTCONV;
+        const double bn = std::sqrt(h.bb);
+        info->relres = bn > 0 ? std::sqrt(h.rr) / bn : std::sqrt(h.rr);
+        info->true_relres = bn > 0 ? std::sqrt(h.true_rr) / bn : std::sqrt(h.true_rr);
+    }
+    return FE_OK;
+}
+
+bool engine_done(const EngineSet &E, int t) { return E.hs[t].done != 0; }
+
 // Stream on which iteration chunks are captured (one per thread and device):
 // capture only records launches, and the caller's stream may be the null
 // stream, which cannot be captured.  The graph is launched on the caller's
@@ -785,103 +938,27 @@ static fe_status capture_stream(hipStream_t &out)
     return FE_OK;
 }
 
-static fe_status pcg_engine(std::vector<PcgJob> &jobs, double rtol, int maxit, void *table, bool use_graph,
-                            hipStream_t s)
+static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_graph, hipStream_t s)
 {
-    const int nprob = int(jobs.size());
-    for (PcgJob &jb : jobs) std::memset(jb.info, 0, sizeof(fe_solve_info));
-    // order: problems with work, grouped by (plan, value type)
-    std::vector<int> order;
-    std::vector<SpmvPlan> plans(nprob);
-    for (int i = 0; i < nprob; i++) {
-        plans[i] = plan_for(jobs[i].n, jobs[i].nnz);
-        if (jobs[i].n > 0) order.push_back(i);
-        else jobs[i].info->status = FE_OK;
+    for (PcgJob &jb : jobs) {
+        std::memset(jb.info, 0, sizeof(fe_solve_info));
+        if (jb.n == 0) jb.info->status = FE_OK;
     }
-    auto key = [&](int i) { return (plans[i].mode * 64 + plans[i].rpb) * 2 + (jobs[i].fp32 ? 1 : 0); };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
-    const int np = int(order.size());
+    EngineSet E;
+    fe_status st = engine_build(E, jobs.data(), int(jobs.size()), table, s);
+    if (st != FE_OK) return st;
+    const int np = E.np;
     if (np == 0) return FE_OK;
-    // device table: probs | boff_e | group boffs | states
-    char *tb = static_cast<char *>(table);
-    PcgProb *d_probs = reinterpret_cast<PcgProb *>(tb);
-    int32_t *d_ints = reinterpret_cast<int32_t *>(tb + align256(sizeof(PcgProb) * size_t(np)));
-    PcgState *d_states = reinterpret_cast<PcgState *>(tb + align256(sizeof(PcgProb) * size_t(np)) +
-                                                      align256(sizeof(int32_t) * (3 * size_t(np) + 16)));
-    int32_t *d_active = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(d_states) +
-                                                    align256(sizeof(PcgState) * size_t(np)));
-    std::vector<PcgProb> hp(np);
-    std::vector<int32_t> hi(3 * size_t(np) + 16, 0);
-    std::vector<Group> groups;
-    const double rtol2 = rtol * rtol;
-    int32_t eoff = 0;
-    for (int t = 0; t < np; t++) {
-        const PcgJob &jb = jobs[order[t]];
-        PcgProb &P = hp[t];
-        P.n = jb.n;
-        P.nnz = jb.nnz;
-        P.rowptr = jb.rowptr;
-        P.colind = jb.colind;
-        P.val = jb.val;
-        P.dinv = jb.dinv;
-        P.b = jb.b;
-        P.x = jb.x;
-        P.w = carve(jb.ws, jb.n);
-        P.rtol2 = rtol2;
-        P.maxit = maxit;
-        const SpmvPlan &pl = plans[order[t]];
-        const int64_t runs = (jb.n + pl.rpb - 1) / pl.rpb;
-        P.nbr = int32_t(std::max<int64_t>(1, std::min<int64_t>(kGrid, (runs + kWaves - 1) / kWaves)));
-        P.nbe = int32_t(std::max<int64_t>(1, std::min<int64_t>(kGrid, (jb.n + kBlock - 1) / kBlock)));
-        hi[t] = eoff;
-        eoff += P.nbe;
-        if (groups.empty() || key(order[groups.back().first]) != key(order[t])) {
-            Group g{};
-            g.pl = pl;
-            g.fp32 = jb.fp32;
-            g.first = t;
-            g.count = 0;
-            groups.push_back(g);
-        }
-        groups.back().count++;
-    }
-    hi[np] = eoff;
-    const int ge = eoff;
-    int pos = np + 1;
-    std::vector<int> gpos(groups.size());
-    for (size_t gi = 0; gi < groups.size(); gi++) {
-        Group &g = groups[gi];
-        gpos[gi] = pos;
-        int32_t off = 0;
-        for (int t = 0; t < g.count; t++) {
-            hi[pos + t] = off;
-            off += hp[g.first + t].nbr;
-        }
-        hi[pos + g.count] = off;
-        g.grid = off;
-        g.d_boff = d_ints + pos;
-        pos += g.count + 1;
-    }
-    FE_HIP(hipMemcpyAsync(d_probs, hp.data(), sizeof(PcgProb) * size_t(np), hipMemcpyHostToDevice, s));
-    FE_HIP(hipMemcpyAsync(d_ints, hi.data(), sizeof(int32_t) * size_t(pos), hipMemcpyHostToDevice, s));
-    for (const Group &g : groups) launch_rows(0, g, d_probs, s);
-    hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(np), dim3(kBlock), 0, s, d_probs);
-    FE_HIP(hipGetLastError());
+    st = engine_init(E, s);
+    if (st != FE_OK) return st;
+    int maxit = 0;
+    for (const PcgJob &jb : E.jobs) maxit = std::max(maxit, jb.maxit);
 
     static thread_local PinnedState pin;
     if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
     int32_t *h_active = reinterpret_cast<int32_t *>(pin.h);
     const bool timed = timing_on() && !use_graph && np == 1;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
-    auto one_iteration = [&](hipStream_t q) {
-        for (const Group &g : groups) {
-            hipEvent_t t0 = timed ? timing_mark(q) : nullptr;
-            launch_rows(1, g, d_probs, q);
-            if (t0) marks.emplace_back(t0, timing_mark(q));
-        }
-        hipLaunchKernelGGL(pcg_update_kernel, dim3(ge), dim3(kBlock), 0, q, d_probs, d_ints, np);
-        hipLaunchKernelGGL(pcg_dir_kernel, dim3(ge), dim3(kBlock), 0, q, d_probs, d_ints, np);
-    };
     struct GraphHold {
         hipGraph_t g = nullptr;
         hipGraphExec_t e = nullptr;
@@ -891,46 +968,37 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, double rtol, int maxit, v
             if (g) (void)hipGraphDestroy(g);
         }
     } hold;
-    hipGraphExec_t &exec = hold.e;
-    hipGraph_t &graph = hold.g;
     const int gchunk = 16;
     if (use_graph && maxit > 0) {
         hipStream_t cs = nullptr;
-        fe_status cst = capture_stream(cs);
-        if (cst != FE_OK) return cst;
+        st = capture_stream(cs);
+        if (st != FE_OK) return st;
         FE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < gchunk; i++) one_iteration(cs);
-        hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, cs, d_probs, np, d_active);
-        const hipError_t ce = hipStreamEndCapture(cs, &graph);
-        if (ce != hipSuccess) return set_error(FE_EDEVICE, "graph capture failed");
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        for (int i = 0; i < gchunk; i++) engine_iteration(E, cs, nullptr);
+        hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, cs, E.d_probs, np, E.d_active);
+        if (hipStreamEndCapture(cs, &hold.g) != hipSuccess) return set_error(FE_EDEVICE, "graph capture failed");
+        if (hipGraphInstantiate(&hold.e, hold.g, nullptr, nullptr, 0) != hipSuccess)
             return set_error(FE_EDEVICE, "graph instantiation failed");
     }
     int j = 0, chunk = 8;
     while (j < maxit) {
-        if (exec) {
-            FE_HIP(hipGraphLaunch(exec, s));
+        if (hold.e) {
+            FE_HIP(hipGraphLaunch(hold.e, s));
             j += gchunk;
         } else {
-            for (int i = 0; i < chunk && j < maxit; i++, j++) one_iteration(s);
-            hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, s, d_probs, np, d_active);
+            for (int i = 0; i < chunk && j < maxit; i++, j++) engine_iteration(E, s, timed ? &marks : nullptr);
+            hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, s, E.d_probs, np, E.d_active);
             if (chunk < 128) chunk *= 2;
         }
         FE_HIP(hipGetLastError());
-        FE_HIP(hipMemcpyAsync(h_active, d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FE_HIP(hipMemcpyAsync(h_active, E.d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         FE_HIP(hipStreamSynchronize(s));
         if (*h_active == 0) break;
     }
-    for (const Group &g : groups) launch_rows(2, g, d_probs, s);
-    hipLaunchKernelGGL(resid_finish_kernel, dim3(np), dim3(kBlock), 0, s, d_probs);
-    hipLaunchKernelGGL(gather_states_kernel, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d_probs, np,
-                       d_states);
-    FE_HIP(hipGetLastError());
-    std::vector<PcgState> hs(np);
-    FE_HIP(hipMemcpyAsync(hs.data(), d_states, sizeof(PcgState) * size_t(np), hipMemcpyDeviceToHost, s));
-    FE_HIP(hipStreamSynchronize(s));
+    st = engine_finish(E, s);
+    if (st != FE_OK) return st;
     for (size_t i = 0; i < marks.size(); i++) {
-        if (int(i) < hs[0].iter) {
+        if (int(i) < E.hs[0].iter) {
             timing_commit(marks[i].first, marks[i].second, kTimeSpmv);
         } else {
             timing_release(marks[i].first);
@@ -939,22 +1007,16 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, double rtol, int maxit, v
     }
     fe_status worst = FE_OK;
     for (int t = 0; t < np; t++) {
-        const PcgState &st = hs[t];
-        fe_solve_info *info = jobs[order[t]].info;
-        info->iters = st.iter;
-        info->status = st.done ? st.status : FE_ENOTCONV;
-        const double bn = std::sqrt(st.bb);
-        info->relres = bn > 0 ? std::sqrt(st.rr) / bn : std::sqrt(st.rr);
-        info->true_relres = bn > 0 ? std::sqrt(st.true_rr) / bn : std::sqrt(st.true_rr);
-        if (info->status != FE_OK && worst == FE_OK) worst = fe_status(info->status);
+        const int stt = E.jobs[t].info->status;
+        if (stt != FE_OK && worst == FE_OK) worst = fe_status(stt);
     }
     // Lanczos estimates from the CG coefficients (single problem)
     if (np == 1) {
-        fe_solve_info *info = jobs[order[0]].info;
-        const int m = std::min(hs[0].iter, kHist);
+        fe_solve_info *info = E.jobs[0].info;
+        const int m = std::min(E.hs[0].iter, kHist);
         if (m > 0) {
             std::vector<double> h(2 * kHist);
-            FE_HIP(hipMemcpy(h.data(), hp[0].w.hist, sizeof(double) * 2 * kHist, hipMemcpyDeviceToHost));
+            FE_HIP(hipMemcpy(h.data(), E.hp[0].w.hist, sizeof(double) * 2 * kHist, hipMemcpyDeviceToHost));
             std::vector<double> d(m), e(m > 1 ? m - 1 : 1);
             for (int i = 0; i < m; i++) {
                 const double a = h[i];
@@ -974,13 +1036,13 @@ static fe_status pcg_run(int64_t n, int64_t nnz, const int64_t *rowptr, const in
                          const double *dinv, const double *b, double *x, double rtol, int maxit, void *ws,
                          size_t ws_bytes, fe_solve_info *info, hipStream_t s)
 {
-    if (ws_bytes < pcg_ws_bytes(n) + pcg_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
+    if (ws_bytes < pcg_ws_bytes(n) + engine_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
     std::vector<PcgJob> jobs(1);
-    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info};
+    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit};
     void *table = static_cast<char *>(ws) + pcg_ws_bytes(n);
     // small systems are launch-bound: replay the iterations from a HIP graph
     const bool graph = n < (int64_t(1) << 18);
-    return pcg_engine(jobs, rtol, maxit, table, graph, s);
+    return pcg_engine(jobs, table, graph, s);
 }
 
 fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
@@ -990,27 +1052,27 @@ fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, in
                            ws_bytes, info, s);
 }
 
-size_t pcg_solve_ws_bytes(int64_t n) { return pcg_ws_bytes(n) + pcg_table_bytes(1); }
+size_t pcg_solve_ws_bytes(int64_t n) { return pcg_ws_bytes(n) + engine_table_bytes(1); }
 
 fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
                           int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s)
 {
-    size_t need = pcg_table_bytes(nprob);
+    size_t need = engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) need += pcg_ws_bytes(A[i].n_rows);
     if (ws_bytes < need) return set_error(FE_EINVAL, "batch pcg workspace too small");
     std::vector<PcgJob> jobs(nprob);
-    char *p = static_cast<char *>(ws) + pcg_table_bytes(nprob);
+    char *p = static_cast<char *>(ws) + engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) {
         jobs[i] = PcgJob{A[i].n_rows, A[i].nnz, A[i].rowptr, A[i].colind, A[i].values, false, A[i].dinv,
-                         b[i], x[i], p, &infos[i]};
+                         b[i], x[i], p, &infos[i], rtol, maxit};
         p += pcg_ws_bytes(A[i].n_rows);
     }
-    return pcg_engine(jobs, rtol, maxit, ws, true, s);
+    return pcg_engine(jobs, ws, true, s);
 }
 
 size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows)
 {
-    size_t need = pcg_table_bytes(nprob);
+    size_t need = engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) need += pcg_ws_bytes(n_rows[i]);
     return need;
 }
@@ -1061,7 +1123,7 @@ __global__ __launch_bounds__(kBlock) void demote_kernel(int64_t nnz, const doubl
 
 size_t refine_ws_bytes(int64_t n)
 {
-    return pcg_ws_bytes(n) + pcg_table_bytes(1) + 2 * align256(size_t(n) * sizeof(double));
+    return pcg_ws_bytes(n) + engine_table_bytes(1) + 2 * align256(size_t(n) * sizeof(double));
 }
 
 fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s)
@@ -1086,7 +1148,7 @@ fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values
     if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
     char *base = static_cast<char *>(ws);
     void *pws = base;
-    const size_t inner_bytes = pcg_ws_bytes(n) + pcg_table_bytes(1);
+    const size_t inner_bytes = pcg_ws_bytes(n) + engine_table_bytes(1);
     double *r = reinterpret_cast<double *>(base + inner_bytes);
     double *d = reinterpret_cast<double *>(base + inner_bytes + align256(size_t(n) * sizeof(double)));
     PcgWs w = carve(pws, n);

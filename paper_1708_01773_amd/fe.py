@@ -27,7 +27,11 @@ EXPORTS = [
     "fe_set_timing", "fe_get_timing", "fe_csr_to_fp32", "fe_refine_query", "fe_refine_solve",
     "fe_pcg_batch_query", "fe_pcg_solve_batch", "fe_assemble_batch_query", "fe_assemble_batch",
     "fe_spmv_autotune_query", "fe_spmv_autotune", "fe_spmv_tuning_reset", "fe_spmv_plan_of",
+    "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_wait", "fe_server_solution",
+    "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
 ]
+
+FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
 
 _c = ctypes
 _P = _c.c_void_p
@@ -58,6 +62,27 @@ class Csr(_c.Structure):
 class SolveInfo(_c.Structure):
     _fields_ = [("iters", _c.c_int32), ("status", _c.c_int32), ("relres", _c.c_double),
                 ("true_relres", _c.c_double), ("lambda_min_est", _c.c_double), ("lambda_max_est", _c.c_double)]
+
+
+class Request(_c.Structure):
+    _fields_ = [("mesh", MeshDesc), ("order", _c.c_int32), ("coeff", Coeff), ("rtol", _c.c_double),
+                ("maxit", _c.c_int32)]
+
+
+class Result(_c.Structure):
+    _fields_ = [("state", _c.c_int32), ("status", _c.c_int32), ("n_rows", _c.c_int64), ("nnz", _c.c_int64),
+                ("bytes", _c.c_int64), ("iters", _c.c_int32), ("relres", _c.c_double),
+                ("true_relres", _c.c_double), ("t_submit", _c.c_double), ("t_admit", _c.c_double),
+                ("t_ready", _c.c_double), ("t_done", _c.c_double)]
+
+
+class ServerStats(_c.Structure):
+    _fields_ = [("budget", _c.c_int64), ("arena_bytes", _c.c_int64), ("mesh_reserve", _c.c_int64),
+                ("in_use", _c.c_int64), ("peak_in_use", _c.c_int64), ("peak_arena", _c.c_int64),
+                ("queued", _c.c_int32), ("setting_up", _c.c_int32), ("solving", _c.c_int32),
+                ("peak_solving", _c.c_int32), ("submitted", _c.c_int64), ("admitted", _c.c_int64),
+                ("completed", _c.c_int64), ("rejected", _c.c_int64), ("chunks", _c.c_int64),
+                ("admission_waits", _c.c_int64)]
 
 
 class SpmvPlan(_c.Structure):
@@ -123,6 +148,14 @@ def lib():
                                  _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
             "fe_spmv_tuning_reset": [],
             "fe_spmv_plan_of": [_c.c_int64, _c.c_int64, _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
+            "fe_server_create": [_c.c_size_t, _c.c_int32, _c.POINTER(_P)],
+            "fe_server_submit": [_P, _c.POINTER(Request), _c.POINTER(_c.c_uint64)],
+            "fe_server_poll": [_P, _c.c_uint64, _c.POINTER(Result)],
+            "fe_server_wait": [_P, _c.c_uint64, _c.c_double, _c.POINTER(Result)],
+            "fe_server_solution": [_P, _c.c_uint64, _P, _c.c_int64],
+            "fe_server_release": [_P, _c.c_uint64],
+            "fe_server_get_stats": [_P, _c.POINTER(ServerStats)],
+            "fe_server_destroy": [_P],
             "fe_pcg_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
             "fe_pcg_solve_batch": [_c.c_int32, _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P), _c.c_double,
                                    _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
@@ -131,6 +164,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = _c.c_int
+        L.fe_server_clock.argtypes = [_P]
+        L.fe_server_clock.restype = _c.c_double
         _lib = L
     return _lib
 
@@ -467,3 +502,74 @@ class BatchAssembly:
     def device_bytes(self):
         t = [self.ws, self.solve_ws] + self.rowptr + self.colind + self.values + self.rhs + self.dinv + self.x
         return sum(v.numel() * v.element_size() for v in t)
+
+
+def _result_dict(r):
+    return {f: getattr(r, f) for f, _ in Result._fields_}
+
+
+class Server:
+    """Owning wrapper of an fe_server: budget in bytes, max_active requests in flight."""
+
+    def __init__(self, budget, max_active=64):
+        h = _P()
+        _check(lib().fe_server_create(int(budget), int(max_active), _c.byref(h)), "fe_server_create")
+        self.handle = h
+
+    def submit(self, dim, n, order, coeff, rtol, maxit, vertices=None, cell_coeff=None):
+        import numpy as np
+        q = Request()
+        q.mesh.dim = int(dim)
+        n = list(n) + [1] * (3 - len(n))
+        for i in range(3):
+            q.mesh.n[i] = int(n[i])
+        v = None if vertices is None else np.ascontiguousarray(vertices, dtype=np.float64)
+        k = None if cell_coeff is None else np.ascontiguousarray(cell_coeff, dtype=np.float64)
+        q.mesh.vertex_xyz = None if v is None else v.ctypes.data_as(_P)
+        q.mesh.cell_coeff = None if k is None else k.ctypes.data_as(_P)
+        q.order = int(order)
+        q.coeff = coeff
+        q.rtol = float(rtol)
+        q.maxit = int(maxit)
+        t = _c.c_uint64()
+        _check(lib().fe_server_submit(self.handle, _c.byref(q), _c.byref(t)), "fe_server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        r = Result()
+        st = lib().fe_server_poll(self.handle, int(ticket), _c.byref(r))
+        d = _result_dict(r)
+        d["error"] = lib().fe_last_error().decode() if st != FE_OK else ""
+        return d
+
+    def wait(self, ticket, timeout=600.0):
+        r = Result()
+        st = lib().fe_server_wait(self.handle, int(ticket), float(timeout), _c.byref(r))
+        d = _result_dict(r)
+        d["error"] = lib().fe_last_error().decode() if st != FE_OK else ""
+        return d
+
+    def solution(self, ticket, out):
+        _check(lib().fe_server_solution(self.handle, int(ticket), _ptr(out), int(out.numel())), "fe_server_solution")
+
+    def release(self, ticket):
+        _check(lib().fe_server_release(self.handle, int(ticket)), "fe_server_release")
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().fe_server_get_stats(self.handle, _c.byref(s)), "fe_server_get_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def clock(self):
+        return lib().fe_server_clock(self.handle)
+
+    def close(self):
+        if self.handle:
+            _check(lib().fe_server_destroy(self.handle), "fe_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
