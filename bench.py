@@ -48,9 +48,13 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def spmv_bytes(n, nnz):
-    """Algorithmic HBM bytes of one CSR SpMV: values + column indices, row
-    pointers, the input vector once and the output vector."""
+def spmv_bytes(n, nnz, mode="csr"):
+    """Algorithmic HBM bytes of one SpMV.  csr: values + column indices, row
+    pointers, the input vector once and the output vector.  mesh (pattern
+    evaluated from the mesh): values, the input vector once and the output
+    vector."""
+    if mode == "mesh":
+        return nnz * 8 + 16 * n
     return nnz * 12 + (n + 1) * 8 + 16 * n
 
 
@@ -281,7 +285,7 @@ def serve_form(args, F, torch):
         A.assemble()
         x = torch.zeros(max(A.n_rows, 1), dtype=torch.float64, device="cuda")
         ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
-        F.pcg_solve(A.csr, A.rhs, x, rtol, maxit, ws)
+        A.solve(x, rtol, maxit, ws)
         torch.cuda.synchronize()
         same = same and x_mix is not None and torch.equal(x[: A.n_rows], x_mix)
         del A, mesh, x, ws
@@ -313,6 +317,9 @@ def main():
     ap.add_argument("--phase", default="step", choices=["step", "assemble"],
                     help="step = assemble + PCG (default); assemble = assembly only, K3 against the matrix-core peak")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--spmv", default="mesh", choices=["mesh", "csr"],
+                    help="mesh: pattern evaluated from the mesh (fe_pcg_solve_mesh); csr: row pointers and column "
+                         "indices read (fe_pcg_solve)")
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="problems of the 512-problem batch run by the batching form (0 = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0, help="device memory per batch wave")
@@ -386,7 +393,10 @@ def main():
         A.assemble(stream)
         e1.record(stream)
         x.zero_()
-        info = F.pcg_solve(A.csr, A.rhs, x, wl["rtol"], 100000, ws, stream)
+        if args.spmv == "mesh":
+            info = A.solve(x, wl["rtol"], 100000, ws, stream)
+        else:
+            info = F.pcg_solve(A.csr, A.rhs, x, wl["rtol"], 100000, ws, stream)
         return info, e0, e1
 
     for i in range(args.warmup):
@@ -414,9 +424,10 @@ def main():
 
     ms_step = total / args.steps * 1e3
     spmv_avg_s = tm["spmv_ms"] / max(tm["spmv_calls"], 1) * 1e-3
-    sb = spmv_bytes(A.n_rows, A.nnz)
+    sb = spmv_bytes(A.n_rows, A.nnz, args.spmv)
     achieved = sb / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
-    traffic = traffic_for("pcg_spmv_kernel")
+    kname = "pcg_spmv_kernel<2>" if args.spmv == "mesh" else "pcg_spmv_kernel<0>"
+    traffic = traffic_for(kname)
     lat_sorted = sorted(lat)
     p99 = lat_sorted[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
     out = {
@@ -441,7 +452,8 @@ def main():
                   "true_relres": info["true_relres"], "solves_per_s": args.steps / total,
                   "p50_ms": statistics.median(lat) * 1e3, "p99_ms": p99 * 1e3,
                   "kappa_est": info["lambda_max_est"] / info["lambda_min_est"] if info["lambda_min_est"] else None},
-        "roofline": {"kernel": "pcg_spmv_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": kname, "traversal": "pattern evaluated from the mesh" if args.spmv == "mesh" else
+                     "CSR row pointers and column indices read", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": sb, "avg_launch_us": spmv_avg_s * 1e6,
                      "launches": tm["spmv_calls"]},

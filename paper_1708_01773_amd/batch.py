@@ -121,8 +121,8 @@ class BatchRun:
 
 
 def run_sequential(problems, rtol, maxit, keep=None, stream=None):
-    """The plain path, one problem at a time: fe_assemble then fe_pcg_solve
-    (set-up outside the timed part)."""
+    """The plain path, one problem at a time: fe_assemble then
+    fe_pcg_solve_mesh (set-up outside the timed part)."""
     import torch
     t_asm = t_solve = 0.0
     infos = []
@@ -136,7 +136,7 @@ def run_sequential(problems, rtol, maxit, keep=None, stream=None):
         A.assemble(stream)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        info = F.pcg_solve(A.csr, A.rhs, x, rtol, maxit, ws, stream) if A.n_rows else dict(iters=0, status=F.FE_OK)
+        info = A.solve(x, rtol, maxit, ws, stream) if A.n_rows else dict(iters=0, status=F.FE_OK)
         torch.cuda.synchronize()
         tc = time.perf_counter()
         t_asm += tb - ta

@@ -671,6 +671,54 @@ fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32
     return FE_OK;
 }
 
+fe_status fe_pcg_solve_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, const double *b, double *x,
+                            double rtol, int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *info,
+                            fe_stream stream)
+{
+    if (!A || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    st = check_csr(A, m->space.args, true);
+    if (st != FE_OK) return st;
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    m->last_stream = as_stream(stream);
+    return pcg_solve_mesh(A, m->space.args, b, x, rtol, maxit, ws, ws_bytes, info, as_stream(stream));
+}
+
+fe_status fe_spmv_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, const double *x, double *y,
+                       fe_stream stream)
+{
+    if (!A || !x || !y) return set_error(FE_EINVAL, "null argument");
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    st = check_csr(A, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (A->nnz > 0 && !A->values) return set_error(FE_EINVAL, "null csr values");
+    m->last_stream = as_stream(stream);
+    return launch_spmv_struct(m->space.args, A->values, x, y, as_stream(stream));
+}
+
+fe_status fe_pcg_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const int32_t *orders, const fe_coeff *coeffs,
+                                  const fe_csr *A, const double *const *b, double *const *x, double rtol,
+                                  int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, fe_stream stream)
+{
+    BatchLayout L;
+    fe_status st = batch_prepare(nprob, meshes, orders, coeffs, L);
+    if (st != FE_OK) return st;
+    if (nprob == 0) return FE_OK;
+    if (!A || !b || !x || !ws || !infos) return set_error(FE_EINVAL, "null argument");
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    std::vector<const SpaceArgs *> sas(nprob);
+    for (int i = 0; i < nprob; i++) {
+        st = check_csr(&A[i], meshes[i]->space.args, true);
+        if (st != FE_OK) return st;
+        if (A[i].n_rows > 0 && (!b[i] || !x[i])) return set_error(FE_EINVAL, "null vector");
+        sas[i] = &meshes[i]->space.args;
+        meshes[i]->last_stream = as_stream(stream);
+    }
+    return pcg_solve_batch(nprob, A, b, x, rtol, maxit, ws, ws_bytes, infos, as_stream(stream), sas.data());
+}
+
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream)
 {
     if (!A || !x || !y || !A->rowptr || !A->colind || !A->values) return set_error(FE_EINVAL, "null argument");

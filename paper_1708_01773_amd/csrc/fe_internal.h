@@ -183,6 +183,7 @@ struct PcgJob {
     fe_solve_info *info;  // filled by engine_finish (may be null)
     double rtol;
     int maxit;
+    const SpaceArgs *sa = nullptr;  // structured pattern of a mesh-assembled system (FP64 values), or null
 };
 struct EngineSet;
 EngineSet *engine_create();
@@ -202,8 +203,14 @@ size_t pcg_solve_ws_bytes(int64_t n);
 fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
                     fe_solve_info *info, hipStream_t s);
 size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows);
+// sas: per system, the space whose closed-form pattern the SpMV evaluates
+// instead of reading column indices (null array or entry: generic CSR).
 fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
-                          int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s);
+                          int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s,
+                          const SpaceArgs *const *sas = nullptr);
+fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,
+                         void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s);
+fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s);
 size_t autotune_ws_bytes(int64_t n);
 fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried, int max_tried,
                         int *n_tried, fe_spmv_plan *chosen, hipStream_t s);

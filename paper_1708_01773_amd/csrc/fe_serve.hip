@@ -13,7 +13,8 @@
 //    the requests that stopped.
 // A request's arithmetic does not depend on the others in flight: the same
 // kernels, plans and per-request reduction order as fe_assemble and
-// fe_pcg_solve, so its result is bitwise that of the request served alone.
+// fe_pcg_solve_mesh, so its result is bitwise that of the request served
+// alone.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -236,7 +237,7 @@ static fe_status setup_request(fe_server S, Req &R)
     if (R.n_rows > 0) {
         FE_HIP(hipMemsetAsync(R.x, 0, sizeof(double) * n, s));
         R.job = PcgJob{R.n_rows, R.nnz, R.csr.rowptr, R.csr.colind, R.csr.values, false, R.csr.dinv, R.csr.rhs,
-                       R.x, R.pcg_ws, &R.info, R.rtol, R.maxit};
+                       R.x, R.pcg_ws, &R.info, R.rtol, R.maxit, &R.mesh->space.args};
         std::unique_ptr<EngineSet, void (*)(EngineSet *)> E(engine_create(), engine_destroy);
         st = engine_build(*E, &R.job, 1, table, s);
         if (st != FE_OK) return st;

@@ -68,11 +68,13 @@ struct PcgProb {
     double rtol2;
     int32_t maxit;
     int32_t nbr, nbe;  // blocks of the row kernels / of the vector kernels
+    SpaceArgs sa;      // pattern of a system assembled on a structured brick (mode 2)
 };
 
 // How a CSR matrix is traversed.
 struct SpmvPlan {
-    int mode;  // 0: wave-level CSR-stream, 1: wave per row
+    int mode;  // 0: wave-level CSR-stream, 1: wave per row, 2: structured (pattern evaluated)
+    int nc = 1;  // components (mode 2)
     int rpb;   // rows per wave-iteration (stream mode)
     int lanes; // lanes per row
 };
@@ -244,13 +246,14 @@ __device__ __forceinline__ void wave_lds_sync()
 // Calls f(row, A_row . x) once per row handled by this wave (in the first
 // lane of the row's lane group).  Wave-level CSR-stream: the rows are cut
 // into runs of RPW; run t is handled by logical wave t mod (number of waves),
-// so the waves active at any moment work on neighbouring rows and share the
-// gathered entries of x in cache (the single-problem launch renumbers blocks
-// so that a contiguous range of logical waves runs on one XCD).  A wave loads
-// the run's RPW + 1 row pointers with one coalesced load, stages the products
-// of the run in its own LDS slice with coalesced loads of values and column
-// indices, then LW = 64 / RPW lanes per row sum them.  A run longer than the
-// slice is summed straight from memory in the same lane order.
+// so the waves of a workgroup work on neighbouring rows and share the
+// gathered entries of x in cache (a mapping of workgroups to XCDs measured
+// 3% slower than the hardware's round robin, so none is applied).  A wave
+// loads the run's RPW + 1 row pointers with one coalesced load, issues every
+// load of the run's values and column indices before the first gather of x,
+// stages the products in its own LDS slice, then LW = 64 / RPW lanes per row
+// sum them.  A run longer than the slice is summed straight from memory in
+// the same lane order.
 // lb / nb: this block's index among the nb blocks working on the matrix.
 template <int RPW, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__restrict__ rowptr,
@@ -273,7 +276,21 @@ __device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__res
         const int64_t row = r0 + grp;
         double s = 0.0;
         if (end - base <= kWaveCap) {
-            for (int64_t j = base + lane; j < end; j += 64) my[j - base] = double(val[j]) * x[colind[j]];
+            // every load of the run is issued before the first gather
+            constexpr int CH = kWaveCap / 64;
+            int32_t c[CH];
+            double a[CH], xv[CH];
+#pragma unroll
+            for (int u = 0; u < CH; u++) {
+                const int64_t j = base + lane + 64 * u;
+                const bool ok = j < end;
+                c[u] = ok ? colind[j] : 0;
+                a[u] = ok ? double(val[j]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; u++) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < CH; u++) my[lane + 64 * u] = a[u] * xv[u];
             wave_lds_sync();
             if (row < r1)
                 for (int64_t t = rb - base + sub; t < re - base; t += LW) s += my[t];
@@ -303,22 +320,232 @@ __device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restri
 }
 
 // Dispatch on the plan (mode, rows per wave-iteration) at compile time.
+#define FE_PLAN_CASE(M, R, N, BODY) { constexpr int kMode = M, kRpb = R, kNc = N; (void)kNc; BODY; } break;
 #define FE_PLAN_DISPATCH(PL, BODY)                                 \
     do {                                                           \
         if ((PL).mode == 1) {                                      \
-            constexpr int kMode = 1, kRpb = 1;                     \
+            constexpr int kMode = 1, kRpb = 1, kNc = 1;            \
             BODY;                                                  \
         } else {                                                   \
             switch ((PL).rpb) {                                    \
-                case 32: { constexpr int kMode = 0, kRpb = 32; BODY; } break; \
-                case 16: { constexpr int kMode = 0, kRpb = 16; BODY; } break; \
-                case 8: { constexpr int kMode = 0, kRpb = 8; BODY; } break;   \
-                case 4: { constexpr int kMode = 0, kRpb = 4; BODY; } break;   \
-                case 2: { constexpr int kMode = 0, kRpb = 2; BODY; } break;   \
-                default: { constexpr int kMode = 0, kRpb = 1; BODY; } break;  \
+                case 32: FE_PLAN_CASE(0, 32, 1, BODY)              \
+                case 16: FE_PLAN_CASE(0, 16, 1, BODY)              \
+                case 8: FE_PLAN_CASE(0, 8, 1, BODY)                \
+                case 4: FE_PLAN_CASE(0, 4, 1, BODY)                \
+                case 2: FE_PLAN_CASE(0, 2, 1, BODY)                \
+                default: FE_PLAN_CASE(0, 1, 1, BODY)               \
             }                                                      \
         }                                                          \
     } while (0)
+
+// floor(a / d) for 0 <= a < 2^31, 0 < d, with inv = 1 / d: the double
+// estimate is off by at most one and is corrected exactly.
+__device__ __forceinline__ int32_t div_exact(int32_t a, int32_t d, double inv)
+{
+    int32_t q = int32_t((double(a) + 0.5) * inv);
+    const int32_t r = a - q * d;
+    q += r < 0 ? -1 : (r >= d ? 1 : 0);
+    return q;
+}
+
+// Interval of columns of free node i along one axis and the prefix P(i) of
+// the interval widths over the free nodes below i: closed forms of the axis
+// tables built on the host (the unclipped interval of a vertex node is
+// [i - k, i + k], of an element-interior node [k floor(i / k), + k]; the ends
+// of the free range [lo, hi] clip them).  swlo = unclipped widths below lo.
+struct AxisClosed {
+    int32_t lo, hi, N, swlo;
+};
+
+__device__ __forceinline__ void axis_row(const AxisClosed &A, int32_t k, double kinv, int32_t i, int32_t &w,
+                                         int32_t &cl, int32_t &P)
+{
+    if (A.N == 0) {  // the third axis of a 2D mesh
+        w = 1;
+        cl = 0;
+        P = 0;
+        return;
+    }
+    const int32_t m = i - div_exact(i, k, kinv) * k;
+    const int32_t low = A.lo == 0 ? (i == 0 ? k : 0) : ((i >= 1 && i <= k) ? 1 : 0);
+    const int32_t high = A.hi == A.N ? (i == A.N ? k : 0) : ((i >= A.N - k && i <= A.N - 1) ? 1 : 0);
+    w = (m == 0 ? 2 * k + 1 : k + 1) - low - high;
+    cl = (m == 0 ? i - k : i - m) + low;
+    // unclipped widths of nodes 0..i-1: i (k + 1) + k ceil(i / k)
+    P = i * (k + 1) + k * div_exact(i + k - 1, k, kinv) - A.swlo;
+    P -= A.lo == 0 ? (i >= 1 ? k : 0) : max(0, min(i - 1, k));
+    if (A.hi != A.N) P -= max(0, i - max(A.lo, A.N - k));
+}
+
+// Rows of a system assembled on a structured brick, with the pattern
+// evaluated instead of read.  Row (free node (t0, t1, t2), component c) has
+// the columns of the node box [cl, cl + w) per axis, all components, in
+// lexicographic order; its values start at the closed-form position of the
+// scatter.  Position p of the row decodes as p = ((j2 w1 + j1) w0 + j0) NC + cc
+// and its column is NC rank(cl + j) + cc.  Nothing but the values and x is
+// loaded, so a lane's loads wait on no other load.
+// RPW rows per wave step, LW = 64 / RPW lanes per row, two runs of four
+// positions per lane in flight.  A wave takes its runs in batches of LW
+// (64 rows): each lane
+// evaluates the geometry of one row of the batch, and the lanes of a row
+// receive it by shuffles.  Each row is summed in lane order (positions sub,
+// sub + LW, ... per lane, then a butterfly over the LW lanes).
+template <int RPW, int NC, typename Fn>
+__device__ __forceinline__ void for_rows_struct(const SpaceArgs &s, const double *__restrict__ val,
+                                                const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
+{
+    constexpr int LW = 64 / RPW;
+    const int lane = threadIdx.x % 64, g = lane / LW, sub = lane % LW;
+    const int64_t n = s.n_rows;
+    const int64_t nw = nb * kWaves, lw = lb * kWaves + threadIdx.x / 64;
+    const int64_t runs = (n + RPW - 1) / RPW;
+    const int32_t k = s.k;
+    const double kinv = 1.0 / double(k);
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * (k + 1) + k * ((A[r].lo + k - 1) / k);
+    }
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const double f0inv = 1.0 / double(f0), f1inv = 1.0 / double(f1);
+    const int64_t T0 = s.ax[0].T, T1 = s.ax[1].T;
+    const int32_t sy = NC * f0, sz = NC * f0 * f1;  // column steps of one node in y / in z
+    for (int64_t b0 = lw; b0 < runs; b0 += int64_t(LW) * nw) {
+        // geometry of row (run b0 + (lane / RPW) nw, lane % RPW) in this lane
+        int32_t gstart_lo = 0, gstart_hi = 0, gcol = 0, gshape = 0, glen = 0;
+        {
+            const int64_t row = (b0 + int64_t(lane / RPW) * nw) * RPW + lane % RPW;
+            if (row < n) {
+                const int32_t r32 = int32_t(row);
+                const int32_t R = r32 / NC, c = r32 - R * NC;
+                const int32_t q = div_exact(R, f0, f0inv), t0 = R - q * f0;
+                const int32_t t2 = div_exact(q, f1, f1inv), t1 = q - t2 * f1;
+                int32_t w0, w1, w2, cl0, cl1, cl2, P0, P1, P2;
+                axis_row(A[0], k, kinv, A[0].lo + t0, w0, cl0, P0);
+                axis_row(A[1], k, kinv, A[1].lo + t1, w1, cl1, P1);
+                axis_row(A[2], k, kinv, A[2].lo + t2, w2, cl2, P2);
+                const int64_t S = int64_t(P2) * T1 * T0 + int64_t(w2) * P1 * T0 + int64_t(w2 * w1) * P0;
+                const int32_t wx = w0 * NC;
+                glen = wx * w1 * w2;
+                const int64_t start = int64_t(NC) * NC * S + int64_t(c) * glen;
+                gstart_lo = int32_t(uint32_t(uint64_t(start)));
+                gstart_hi = int32_t(uint32_t(uint64_t(start) >> 32));
+                gcol = NC * ((cl0 - A[0].lo) + f0 * ((cl1 - A[1].lo) + f1 * (cl2 - A[2].lo)));
+                gshape = wx | (w1 << 16);
+            }
+        }
+        // two runs per step: eight positions per lane in flight
+        for (int u = 0; u < LW; u += 2) {
+            if (b0 + int64_t(u) * nw >= runs) break;
+            int64_t start[2], row[2];
+            int32_t len[2], colbase[2], wx[2], w1[2];
+            uint32_t mx[2], my[2];
+            double sum[2];
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int src = (u + h) * RPW + g;
+                row[h] = (b0 + int64_t(u + h) * nw) * RPW + g;
+                len[h] = __shfl(glen, src);
+                colbase[h] = __shfl(gcol, src);
+                const int32_t shape = __shfl(gshape, src);
+                start[h] = int64_t((uint64_t(uint32_t(__shfl(gstart_hi, src))) << 32) |
+                                   uint64_t(uint32_t(__shfl(gstart_lo, src))));
+                const bool live = row[h] < n;
+                wx[h] = live ? (shape & 0xffff) : 1;
+                w1[h] = live ? (shape >> 16) : 1;
+                if (!live) len[h] = 0;
+                // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8]: exact for
+                // p < 2^12, d <= 27 (the approximate reciprocal is within 1e-6 relative)
+                mx[h] = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx[h]))) + 2u;
+                my[h] = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1[h]))) + 2u;
+                sum[h] = 0.0;
+            }
+            auto chunk = [&](int h, int32_t p0, double (&a4)[4], double (&x4)[4]) {
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const int32_t pos = p0 + sub + t * LW;
+                    const bool ok = pos < len[h];
+                    const int32_t pc = ok ? pos : 0;
+                    const int32_t qy = int32_t((uint32_t(pc) * mx[h]) >> 20);
+                    const int32_t xx = pc - qy * wx[h];
+                    const int32_t j2 = int32_t((uint32_t(qy) * my[h]) >> 20);
+                    const int32_t j1 = qy - j2 * w1[h];
+                    a4[t] = ok ? val[start[h] + pc] : 0.0;
+                    x4[t] = x[colbase[h] + xx + sy * j1 + sz * j2];
+                }
+            };
+            {
+                double a0[4], x0[4], a1[4], x1[4];
+                chunk(0, 0, a0, x0);
+                chunk(1, 0, a1, x1);
+#pragma unroll
+                for (int t = 0; t < 4; t++) sum[0] += a0[t] * x0[t];
+#pragma unroll
+                for (int t = 0; t < 4; t++) sum[1] += a1[t] * x1[t];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                for (int32_t p0 = 4 * LW; p0 < len[h]; p0 += 4 * LW) {
+                    double a4[4], x4[4];
+                    chunk(h, p0, a4, x4);
+#pragma unroll
+                    for (int t = 0; t < 4; t++) sum[h] += a4[t] * x4[t];
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const double t = butterfly<LW>(sum[h]);
+                if (row[h] < n && sub == 0) f(row[h], t);
+            }
+        }
+    }
+}
+
+// Dispatch on the plan at compile time: kMode, kRpb (rows per wave) and kNc
+// (components, structured mode only).  FE_PLAN_DISPATCH_ALL adds the
+// structured plans (FP64 values only).
+#define FE_SPLAN_DISPATCH(PL, BODY)                                                            \
+    switch ((PL).nc * 100 + (PL).rpb) {                                                        \
+        case 116: FE_PLAN_CASE(2, 16, 1, BODY)                                                 \
+        case 108: FE_PLAN_CASE(2, 8, 1, BODY)                                                  \
+        case 104: FE_PLAN_CASE(2, 4, 1, BODY)                                                  \
+        case 102: FE_PLAN_CASE(2, 2, 1, BODY)                                                  \
+        case 101: FE_PLAN_CASE(2, 1, 1, BODY)                                                  \
+        case 208: FE_PLAN_CASE(2, 8, 2, BODY)                                                  \
+        case 204: FE_PLAN_CASE(2, 4, 2, BODY)                                                  \
+        case 202: FE_PLAN_CASE(2, 2, 2, BODY)                                                  \
+        case 201: FE_PLAN_CASE(2, 1, 2, BODY)                                                  \
+        case 302: FE_PLAN_CASE(2, 2, 3, BODY)                                                  \
+        default: FE_PLAN_CASE(2, 1, 3, BODY)                                                   \
+    }
+#define FE_PLAN_DISPATCH_ALL(PL, BODY)                                                         \
+    do {                                                                                       \
+        if ((PL).mode == 2) {                                                                  \
+            FE_SPLAN_DISPATCH(PL, BODY)                                                        \
+        } else {                                                                               \
+            FE_PLAN_DISPATCH(PL, BODY);                                                        \
+        }                                                                                      \
+    } while (0)
+
+// Largest run of rows per wave whose lanes cover a longest row in at most
+// four steps (one wave per row beyond that).
+static SpmvPlan struct_plan(const SpaceArgs &sa)
+{
+    int L = sa.ncomp;
+    for (int r = 0; r < sa.dim; r++) L *= 2 * sa.k + 1;
+    SpmvPlan pl{};
+    pl.mode = 2;
+    pl.nc = sa.ncomp;
+    const int maxr = sa.ncomp == 1 ? 16 : (sa.ncomp == 2 ? 8 : 2);
+    int rpw = maxr;
+    while (rpw > 1 && (64 / rpw) * 4 < L) rpw /= 2;
+    pl.rpb = rpw;
+    pl.lanes = 64 / rpw;
+    return pl;
+}
 
 template <int MODE, int RPW, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const VT *val,
@@ -328,6 +555,16 @@ __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const
         for_rows_wave(n, rowptr, colind, val, x, lb, nb, f);
     else
         for_rows_wstream<RPW, VT>(n, rowptr, colind, val, x, lb, nb, f);
+}
+
+// Row traversal of one problem of a PCG table.
+template <int MODE, int RPB, int NC, typename VT, typename Fn>
+__device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
+{
+    if constexpr (MODE == 2)
+        for_rows_struct<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+    else
+        for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), x, lb, nb, f);
 }
 
 // Problem of block blockIdx.x in a launch whose problem p owns blocks
@@ -343,7 +580,6 @@ __device__ __forceinline__ int find_problem(const int32_t *__restrict__ boff, in
     }
     nb = boff[lo + 1] - boff[lo];
     lb = b - boff[lo];
-    if (nprob == 1) lb = xcd_block(lb, nb);
     return lo;
 }
 
@@ -365,12 +601,19 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, const int64_t *
                                                        const VT *__restrict__ val, const double *__restrict__ x,
                                                        double *__restrict__ y)
 {
-    for_rows<MODE, RPB, VT>(n, rowptr, colind, val, x, xcd_block(blockIdx.x, gridDim.x), gridDim.x,
+    for_rows<MODE, RPB, VT>(n, rowptr, colind, val, x, blockIdx.x, gridDim.x,
                             [&](int64_t row, double s) { y[row] = s; });
 }
 
+template <int RPB, int NC>
+__global__ __launch_bounds__(kBlock) void spmv_struct_kernel(SpaceArgs sa, const double *__restrict__ val,
+                                                              const double *__restrict__ x, double *__restrict__ y)
+{
+    for_rows_struct<RPB, NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
+}
+
 // r = b - A x; p = z = dinv r; partials of r.z, r.r, b.b
-template <int MODE, int RPB, typename VT>
+template <int MODE, int RPB, int NC, typename VT>
 __global__ __launch_bounds__(kBlock) void pcg_init_kernel(const PcgProb *__restrict__ probs,
                                                            const int32_t *__restrict__ boff, int nprob)
 {
@@ -381,8 +624,7 @@ __global__ __launch_bounds__(kBlock) void pcg_init_kernel(const PcgProb *__restr
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ r = P.w.r;
     double *__restrict__ pv = P.w.p;
-    for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), P.x, lb, nb,
-                            [&](int64_t row, double ax) {
+    for_rows_p<MODE, RPB, NC, VT>(P, P.x, lb, nb, [&](int64_t row, double ax) {
                                 const double rr = b[row] - ax;
                                 const double z = dinv[row] * rr;
                                 r[row] = rr;
@@ -422,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(const PcgProb *
 }
 
 // q = A p; partials of p.q
-template <int MODE, int RPB, typename VT>
+template <int MODE, int RPB, int NC, typename VT>
 __global__ __launch_bounds__(kBlock) void pcg_spmv_kernel(const PcgProb *__restrict__ probs,
                                                            const int32_t *__restrict__ boff, int nprob)
 {
@@ -432,8 +674,7 @@ __global__ __launch_bounds__(kBlock) void pcg_spmv_kernel(const PcgProb *__restr
     double v[1] = {0.0};
     const double *__restrict__ p = P.w.p;
     double *__restrict__ q = P.w.q;
-    for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), p, lb, nb,
-                            [&](int64_t row, double s) {
+    for_rows_p<MODE, RPB, NC, VT>(P, p, lb, nb, [&](int64_t row, double s) {
                                 q[row] = s;
                                 v[0] += p[row] * s;
                             });
@@ -523,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
 }
 
 // partials of (b - A x)^2
-template <int MODE, int RPB, typename VT>
+template <int MODE, int RPB, int NC, typename VT>
 __global__ __launch_bounds__(kBlock) void resid_kernel(const PcgProb *__restrict__ probs,
                                                         const int32_t *__restrict__ boff, int nprob)
 {
@@ -531,8 +772,7 @@ __global__ __launch_bounds__(kBlock) void resid_kernel(const PcgProb *__restrict
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     double v[1] = {0.0};
     const double *__restrict__ b = P.b;
-    for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), P.x, lb, nb,
-                            [&](int64_t row, double ax) {
+    for_rows_p<MODE, RPB, NC, VT>(P, P.x, lb, nb, [&](int64_t row, double ax) {
                                 const double d = b[row] - ax;
                                 v[0] += d * d;
                             });
@@ -757,27 +997,27 @@ void engine_destroy(EngineSet *E) { delete E; }
 int engine_size(const EngineSet &E) { return E.np; }
 const PcgJob &engine_job(const EngineSet &E, int t) { return E.jobs[t]; }
 
-template <typename VT>
-static void launch_rows_group(int which, const Group &g, const PcgProb *probs, hipStream_t s)
-{
-    const PcgProb *tp = probs + g.first;
-    switch (which) {
-        case 0:
-            FE_PLAN_DISPATCH(g.pl, (pcg_init_kernel<kMode, kRpb, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count)));
-            break;
-        case 1:
-            FE_PLAN_DISPATCH(g.pl, (pcg_spmv_kernel<kMode, kRpb, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count)));
-            break;
-        default:
-            FE_PLAN_DISPATCH(g.pl, (resid_kernel<kMode, kRpb, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count)));
-            break;
+#define FE_ROWS_KERNELS(DISPATCH, VT)                                                                                \
+    switch (which) {                                                                                                  \
+        case 0:                                                                                                       \
+            DISPATCH(g.pl, (pcg_init_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count))); \
+            break;                                                                                                    \
+        case 1:                                                                                                       \
+            DISPATCH(g.pl, (pcg_spmv_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count))); \
+            break;                                                                                                    \
+        default:                                                                                                      \
+            DISPATCH(g.pl, (resid_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count))); \
+            break;                                                                                                    \
     }
-}
 
 static void launch_rows(int which, const Group &g, const PcgProb *probs, hipStream_t s)
 {
-    if (g.fp32) launch_rows_group<float>(which, g, probs, s);
-    else launch_rows_group<double>(which, g, probs, s);
+    const PcgProb *tp = probs + g.first;
+    if (g.fp32) {
+        FE_ROWS_KERNELS(FE_PLAN_DISPATCH, float)
+    } else {
+        FE_ROWS_KERNELS(FE_PLAN_DISPATCH_ALL, double)
+    }
 }
 
 fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table, hipStream_t s)
@@ -785,10 +1025,13 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
     std::vector<int> order;
     std::vector<SpmvPlan> plans(njobs);
     for (int i = 0; i < njobs; i++) {
-        plans[i] = plan_for(jobs[i].n, jobs[i].nnz);
+        if (jobs[i].sa && jobs[i].fp32) return set_error(FE_EINVAL, "structured traversal needs FP64 values");
+        plans[i] = jobs[i].sa ? struct_plan(*jobs[i].sa) : plan_for(jobs[i].n, jobs[i].nnz);
         if (jobs[i].n > 0) order.push_back(i);
     }
-    auto key = [&](int i) { return (plans[i].mode * 64 + plans[i].rpb) * 2 + (jobs[i].fp32 ? 1 : 0); };
+    auto key = [&](int i) {
+        return ((plans[i].mode * 64 + plans[i].rpb) * 4 + plans[i].nc) * 2 + (jobs[i].fp32 ? 1 : 0);
+    };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     const int np = int(order.size());
     E.np = np;
@@ -822,6 +1065,7 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
         P.w = carve(jb.ws, jb.n);
         P.rtol2 = jb.rtol * jb.rtol;
         P.maxit = jb.maxit;
+        if (jb.sa) P.sa = *jb.sa;
         const SpmvPlan &pl = plans[order[t]];
         P.nbr = grid_rows(jb.n, pl);
         P.nbe = grid_elems(jb.n);
@@ -1034,11 +1278,11 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_gra
 template <typename VT>
 static fe_status pcg_run(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind, const VT *val,
                          const double *dinv, const double *b, double *x, double rtol, int maxit, void *ws,
-                         size_t ws_bytes, fe_solve_info *info, hipStream_t s)
+                         size_t ws_bytes, fe_solve_info *info, hipStream_t s, const SpaceArgs *sa = nullptr)
 {
     if (ws_bytes < pcg_ws_bytes(n) + engine_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
     std::vector<PcgJob> jobs(1);
-    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit};
+    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit, sa};
     void *table = static_cast<char *>(ws) + pcg_ws_bytes(n);
     // small systems are launch-bound: replay the iterations from a HIP graph
     const bool graph = n < (int64_t(1) << 18);
@@ -1052,10 +1296,28 @@ fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, in
                            ws_bytes, info, s);
 }
 
+fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,
+                         void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s)
+{
+    return pcg_run<double>(A->n_rows, A->nnz, A->rowptr, A->colind, A->values, A->dinv, b, x, rtol, maxit, ws,
+                           ws_bytes, info, s, &sa);
+}
+
+fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s)
+{
+    if (sa.n_rows == 0) return FE_OK;
+    const SpmvPlan pl = struct_plan(sa);
+    const int g = grid_rows(sa.n_rows, pl);
+    FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kRpb, kNc><<<dim3(g), dim3(kBlock), 0, s>>>(sa, val, x, y)));
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
 size_t pcg_solve_ws_bytes(int64_t n) { return pcg_ws_bytes(n) + engine_table_bytes(1); }
 
 fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, double *const *x, double rtol,
-                          int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s)
+                          int maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, hipStream_t s,
+                          const SpaceArgs *const *sas)
 {
     size_t need = engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) need += pcg_ws_bytes(A[i].n_rows);
@@ -1064,7 +1326,7 @@ fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, do
     char *p = static_cast<char *>(ws) + engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) {
         jobs[i] = PcgJob{A[i].n_rows, A[i].nnz, A[i].rowptr, A[i].colind, A[i].values, false, A[i].dinv,
-                         b[i], x[i], p, &infos[i], rtol, maxit};
+                         b[i], x[i], p, &infos[i], rtol, maxit, sas ? sas[i] : nullptr};
         p += pcg_ws_bytes(A[i].n_rows);
     }
     return pcg_engine(jobs, ws, true, s);
@@ -1090,7 +1352,7 @@ __global__ __launch_bounds__(kBlock) void resid_vec_kernel(int64_t n, const int6
                                                             double *__restrict__ r, PcgWs w)
 {
     double v[2] = {0.0, 0.0};
-    for_rows<MODE, RPB, double>(n, rowptr, colind, val, x, xcd_block(blockIdx.x, gridDim.x), gridDim.x,
+    for_rows<MODE, RPB, double>(n, rowptr, colind, val, x, blockIdx.x, gridDim.x,
                                 [&](int64_t row, double ax) {
         const double d = b[row] - ax;
         r[row] = d;

@@ -29,6 +29,7 @@ EXPORTS = [
     "fe_spmv_autotune_query", "fe_spmv_autotune", "fe_spmv_tuning_reset", "fe_spmv_plan_of",
     "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_wait", "fe_server_solution",
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
+    "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -148,6 +149,12 @@ def lib():
                                  _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
             "fe_spmv_tuning_reset": [],
             "fe_spmv_plan_of": [_c.c_int64, _c.c_int64, _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
+            "fe_spmv_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _P, _P],
+            "fe_pcg_solve_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _P, _c.c_double,
+                                  _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
+            "fe_pcg_solve_batch_mesh": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
+                                        _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P), _c.c_double, _c.c_int32,
+                                        _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
             "fe_server_create": [_c.c_size_t, _c.c_int32, _c.POINTER(_P)],
             "fe_server_submit": [_P, _c.POINTER(Request), _c.POINTER(_c.c_uint64)],
             "fe_server_poll": [_P, _c.c_uint64, _c.POINTER(Result)],
@@ -372,6 +379,43 @@ def spmv_plan_of(n_rows, nnz):
     return p.mode, p.rows_per_wave, c.value
 
 
+def _info_dict(info):
+    return dict(iters=info.iters, status=info.status, relres=info.relres, true_relres=info.true_relres,
+                lambda_min_est=info.lambda_min_est, lambda_max_est=info.lambda_max_est)
+
+
+def pcg_solve_mesh(mesh, order, coeff, csr, b, x, rtol, maxit, ws, stream=None, check=True):
+    """Jacobi-PCG of a system assembled on mesh, with the pattern evaluated from the mesh."""
+    info = SolveInfo()
+    st = lib().fe_pcg_solve_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(b), _ptr(x),
+                                 float(rtol), int(maxit), _ptr(ws), ws.numel() * ws.element_size(), _c.byref(info),
+                                 _stream(stream))
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_pcg_solve_mesh")
+    return _info_dict(info)
+
+
+def spmv_mesh(mesh, order, coeff, csr, x, y, stream=None):
+    _check(lib().fe_spmv_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(x), _ptr(y),
+                              _stream(stream)), "fe_spmv_mesh")
+
+
+def pcg_solve_batch_mesh(meshes, orders, coeffs, csrs, bs, xs, rtol, maxit, ws, stream=None, check=True):
+    n = len(csrs)
+    M = (_P * max(1, n))(*[m.handle for m in meshes])
+    O = (_c.c_int32 * max(1, n))(*[int(k) for k in orders])
+    C = (Coeff * max(1, n))(*coeffs)
+    A = (Csr * max(1, n))(*csrs)
+    B = (_P * max(1, n))(*[_ptr(b) for b in bs])
+    X = (_P * max(1, n))(*[_ptr(x) for x in xs])
+    infos = (SolveInfo * max(1, n))()
+    st = lib().fe_pcg_solve_batch_mesh(n, M, O, C, A, B, X, float(rtol), int(maxit), _ptr(ws),
+                                       ws.numel() * ws.element_size(), infos, _stream(stream))
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_pcg_solve_batch_mesh")
+    return st, [dict(iters=i.iters, status=i.status, relres=i.relres, true_relres=i.true_relres) for i in infos[:n]]
+
+
 def spmv(csr, x, y, stream=None):
     _check(lib().fe_spmv(_c.byref(csr), _ptr(x), _ptr(y), _stream(stream)), "fe_spmv")
 
@@ -435,6 +479,10 @@ class Assembly:
     def scatter(self, stream=None):
         scatter(self.mesh, self.order, self.coeff, self.csr, self.ws, stream)
 
+    def solve(self, x, rtol, maxit, ws, stream=None):
+        """Jacobi-PCG with the pattern evaluated from the mesh (fe_pcg_solve_mesh)."""
+        return pcg_solve_mesh(self.mesh, self.order, self.coeff, self.csr, self.rhs, x, rtol, maxit, ws, stream)
+
 
 def assemble_batch_query(meshes, orders, coeffs):
     """Per-problem (n_rows, nnz) lists and the batch workspace bytes."""
@@ -492,11 +540,15 @@ class BatchAssembly:
     def assemble(self, stream=None):
         assemble_batch(self.meshes, self.orders, self.coeffs, self.csrs, self.ws, stream)
 
-    def solve(self, rtol, maxit, stream=None, zero_x=True):
-        """Batched Jacobi-PCG from x = 0 (or the current x); returns (status, infos)."""
+    def solve(self, rtol, maxit, stream=None, zero_x=True, structured=True):
+        """Batched Jacobi-PCG from x = 0 (or the current x); returns (status, infos).
+        structured: evaluate the pattern from the meshes (fe_pcg_solve_batch_mesh)."""
         if zero_x:
             for x in self.x:
                 x.zero_()
+        if structured:
+            return pcg_solve_batch_mesh(self.meshes, self.orders, self.coeffs, self.csrs, self.rhs, self.x, rtol,
+                                        maxit, self.solve_ws, stream)
         return pcg_solve_batch(self.csrs, self.rhs, self.x, rtol, maxit, self.solve_ws, stream)
 
     def device_bytes(self):

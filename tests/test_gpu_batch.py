@@ -185,3 +185,22 @@ def test_spmv_autotuner_picks_a_measured_plan_and_keeps_results():
     finally:
         F.spmv_tuning_reset()
     assert F.spmv_plan_of(A.n_rows, A.nnz) == untuned
+
+
+def test_batch_with_evaluated_pattern_matches_single_bitwise():
+    built = _build(seed0=70)
+    live = [(p, A) for p, A in built if A.n_rows]
+    singles = []
+    for pair, A in live:
+        x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+        ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+        info = A.solve(x, 1e-12, 5000, ws)
+        assert info["status"] == F.FE_OK
+        singles.append((x, info))
+    xs = [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda") for _, A in live]
+    ws = torch.empty(F.pcg_batch_query([A.n_rows for _, A in live]), dtype=torch.uint8, device="cuda")
+    st, infos = F.pcg_solve_batch_mesh([p.mesh for p, _ in live], [p.k for p, _ in live], [p.coeff for p, _ in live],
+                                       [A.csr for _, A in live], [A.rhs for _, A in live], xs, 1e-12, 5000, ws)
+    assert st == F.FE_OK
+    for (x1, i1), xb, ib in zip(singles, xs, infos):
+        assert ib["iters"] == i1["iters"] and torch.equal(xb, x1)

@@ -27,7 +27,7 @@ def _alone(i, n, k, rtol, maxit):
     x = torch.zeros(max(A.n_rows, 1), dtype=torch.float64, device="cuda")
     if A.n_rows:
         ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
-        info = F.pcg_solve(A.csr, A.rhs, x, rtol, maxit, ws)
+        info = A.solve(x, rtol, maxit, ws)
     else:
         info = dict(iters=0, status=F.FE_OK)
     torch.cuda.synchronize()
