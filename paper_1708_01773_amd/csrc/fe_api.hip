@@ -486,7 +486,7 @@ fe_status fe_assemble_batch(int32_t nprob, const fe_mesh *meshes, const int32_t 
         return ((J.s.dim * 8 + J.s.k) * 4 + J.s.ncomp) * 4 + J.p.precision;
     };
     auto skey = [&](int i) {
-        return (L.el[i].cb > 1 ? 1000 : 0) + L.el[i].elem_bytes * 10 + jobs[i].s.ncomp;
+        return (L.el[i].cb > 1 ? 1000 : 0) + jobs[i].s.dim * 100 + L.el[i].elem_bytes * 10 + jobs[i].s.ncomp;
     };
     std::stable_sort(iorder.begin(), iorder.end(), [&](int a, int b) { return ikey(a) < ikey(b); });
     for (int i = 0; i < nprob; i++)

@@ -15,8 +15,10 @@
 // Two traversals, matched to the two element layouts written by K3:
 //  * blocked layout (Q1 scalar, E[c/64][a*8+b][c%64]): one thread per row;
 //    consecutive threads own consecutive rows, whose cells are consecutive,
-//    so every element read of a wave is contiguous.  The 27-entry rows are
-//    staged in LDS and the wave writes its rows' CSR range contiguously.
+//    so every element read of a wave is contiguous.  The cells around the
+//    row's node and their local columns are unrolled at compile time into
+//    register accumulators of the row's 3^d stencil; the rows are staged in
+//    LDS and the wave writes its rows' CSR range contiguously.
 //  * cell-major layout (E[c][a][b]): one wave per row, lanes over 64
 //    consecutive CSR positions; entries along an x-run of columns come from
 //    consecutive b of the same cell, so reads and writes are both contiguous.
@@ -26,7 +28,6 @@
 
 namespace fe {
 
-constexpr int kRowsCap = 27;  // longest row of the blocked (Q1 scalar) layout: 3^3
 
 struct RowGeom {
     int64_t I0, I1, I2;     // node indices of the row
@@ -151,12 +152,20 @@ __device__ __forceinline__ void wave_lds_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int CB, typename ET>
-__device__ __forceinline__ void k5_rows_body(const SpaceArgs &s, const ET *__restrict__ E,
-                                             const double *__restrict__ F, double *__restrict__ values,
-                                             double *__restrict__ rhs, double *__restrict__ dinv, int64_t bid)
+// Q1 scalar: the 2^DIM cells around a row's node and the 2^DIM local columns
+// of each are unrolled at compile time, so every element entry lands in a
+// register accumulator of the row's 3^DIM stencil.  The cells are visited in
+// ascending id, which is the summation order of every entry (as in
+// entry_sum); contributions to fixed columns are accumulated and dropped.
+template <int DIM, typename ET>
+__device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restrict__ E,
+                                           const double *__restrict__ F, double *__restrict__ values,
+                                           double *__restrict__ rhs, double *__restrict__ dinv, int64_t bid)
 {
-    __shared__ double stage[4][64 * kRowsCap];
+    constexpr int NN = 1 << DIM;                // nodes per cell
+    constexpr int NS = DIM == 3 ? 27 : 9;       // stencil entries
+    constexpr int CB = 64;                      // cells per block of E
+    __shared__ double stage[4][64 * NS];
     double *my = stage[threadIdx.x / 64];
     const int lane = threadIdx.x % 64;
     const int64_t r0 = (bid * 4 + threadIdx.x / 64) * 64;
@@ -165,9 +174,30 @@ __device__ __forceinline__ void k5_rows_body(const SpaceArgs &s, const ET *__res
     const int64_t row = r0 + lane;
     RowGeom g{};
     int len = 0;
+    double acc[NS];
+#pragma unroll
+    for (int t = 0; t < NS; t++) acc[t] = 0.0;
+    double fsum = 0.0;
     if (lane < nvalid) {
         g = row_geom(s, row);
-        len = g.w0 * g.w1 * g.w2 * s.ncomp;
+        len = g.w0 * g.w1 * g.w2;
+        const int64_t n0 = s.ax[0].n, n1 = s.ax[1].n, n2 = s.ax[2].n;
+#pragma unroll
+        for (int c = 0; c < NN; c++) {
+            const int d0 = (c & 1) - 1, d1 = ((c >> 1) & 1) - 1, d2 = DIM == 3 ? ((c >> 2) & 1) - 1 : 0;
+            const int64_t e0 = g.I0 + d0, e1 = g.I1 + d1, e2 = g.I2 + d2;
+            if (e0 < 0 || e0 >= n0 || e1 < 0 || e1 >= n1 || e2 < 0 || e2 >= n2) continue;
+            const int64_t cell = e0 + n0 * (e1 + n1 * e2);
+            const int a = -d0 - 2 * d1 - 4 * d2;
+            const ET *__restrict__ Ec = E + (cell / CB) * (NN * NN * CB) + (cell % CB) + a * NN * CB;
+#pragma unroll
+            for (int b = 0; b < NN; b++) {
+                const int s0 = d0 + (b & 1) + 1, s1 = d1 + ((b >> 1) & 1) + 1;
+                const int s2 = DIM == 3 ? d2 + ((b >> 2) & 1) + 1 : 0;
+                acc[(s2 * 3 + s1) * 3 + s0] += double(Ec[b * CB]);
+            }
+            fsum += F[cell * NN + a];
+        }
     }
     // the wave's rows are consecutive, so their CSR ranges are contiguous
     const int64_t base = __shfl(g.start, 0);
@@ -176,36 +206,37 @@ __device__ __forceinline__ void k5_rows_body(const SpaceArgs &s, const ET *__res
     const int total = int(last_start - base) + last_len;
     if (lane < nvalid) {
         double *out = my + (g.start - base);
-        int pos = 0;
-        for (int64_t J2 = g.cl2; J2 < g.cl2 + g.w2; J2++)
-            for (int64_t J1 = g.cl1; J1 < g.cl1 + g.w1; J1++)
-                for (int64_t J0 = g.cl0; J0 < g.cl0 + g.w0; J0++)
-                    for (int cc = 0; cc < s.ncomp; cc++, pos++) {
-                        const double v = entry_sum<1, CB>(s, g, J0, J1, J2, cc, E);
-                        out[pos] = v;
-                        if (J0 == g.I0 && J1 == g.I1 && J2 == g.I2 && cc == g.c) dinv[row] = 1.0 / v;
-                    }
-        rhs[row] = row_rhs(s, g, F);
+        const int o0 = int(g.cl0 - (g.I0 - 1)), o1 = int(g.cl1 - (g.I1 - 1));
+        const int o2 = DIM == 3 ? int(g.cl2 - (g.I2 - 1)) : 0;
+#pragma unroll
+        for (int t = 0; t < NS; t++) {
+            const int s0 = t % 3, s1 = (t / 3) % 3, s2 = t / 9;
+            const int j0 = s0 - o0, j1 = s1 - o1, j2 = s2 - o2;
+            if (j0 >= 0 && j0 < g.w0 && j1 >= 0 && j1 < g.w1 && j2 >= 0 && j2 < g.w2)
+                out[(j2 * g.w1 + j1) * g.w0 + j0] = acc[t];
+        }
+        dinv[row] = 1.0 / acc[NS / 2];
+        rhs[row] = fsum;
     }
     wave_lds_fence();
     for (int t = lane; t < total; t += 64) values[base + t] = my[t];
 }
 
-template <int CB, typename ET>
-__global__ __launch_bounds__(256) void k5_rows_kernel(SpaceArgs s, const ET *__restrict__ E,
-                                                      const double *__restrict__ F, double *__restrict__ values,
-                                                      double *__restrict__ rhs, double *__restrict__ dinv)
+template <int DIM, typename ET>
+__global__ __launch_bounds__(256) void k5_q1_kernel(SpaceArgs s, const ET *__restrict__ E, const double *__restrict__ F,
+                                                    double *__restrict__ values, double *__restrict__ rhs,
+                                                    double *__restrict__ dinv)
 {
-    k5_rows_body<CB, ET>(s, E, F, values, rhs, dinv, xcd_block(blockIdx.x, gridDim.x));
+    k5_q1_body<DIM, ET>(s, E, F, values, rhs, dinv, xcd_block(blockIdx.x, gridDim.x));
 }
 
-template <int CB, typename ET>
-__global__ __launch_bounds__(256) void k5_rows_batch_kernel(const AsmJob *__restrict__ jobs,
-                                                            const int32_t *__restrict__ boff, int njobs)
+template <int DIM, typename ET>
+__global__ __launch_bounds__(256) void k5_q1_batch_kernel(const AsmJob *__restrict__ jobs,
+                                                          const int32_t *__restrict__ boff, int njobs)
 {
     int64_t lb, nb;
     const AsmJob &J = jobs[find_job(boff, njobs, lb, nb)];
-    k5_rows_body<CB, ET>(J.s, static_cast<const ET *>(J.E), J.F, J.values, J.rhs, J.dinv, lb);
+    k5_q1_body<DIM, ET>(J.s, static_cast<const ET *>(J.E), J.F, J.values, J.rhs, J.dinv, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,12 +309,17 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
         // thread per row: 4 waves of 64 rows per block
         const int64_t grid = (sa.n_rows + 255) / 256;
         if (el.cb != 64) return set_error(FE_EINVAL, "unexpected element layout");
-        if (el.elem_bytes == 8)
-            hipLaunchKernelGGL((k5_rows_kernel<64, double>), dim3(grid), dim3(256), 0, s, sa,
-                               static_cast<const double *>(ws), F, values, rhs, dinv);
-        else
-            hipLaunchKernelGGL((k5_rows_kernel<64, float>), dim3(grid), dim3(256), 0, s, sa,
-                               static_cast<const float *>(ws), F, values, rhs, dinv);
+#define FE_K5Q(D, T)                                                                                           \
+    hipLaunchKernelGGL((k5_q1_kernel<D, T>), dim3(grid), dim3(256), 0, s, sa, static_cast<const T *>(ws), F, values, \
+                       rhs, dinv)
+        if (sa.dim == 3) {
+            if (el.elem_bytes == 8) FE_K5Q(3, double);
+            else FE_K5Q(3, float);
+        } else {
+            if (el.elem_bytes == 8) FE_K5Q(2, double);
+            else FE_K5Q(2, float);
+        }
+#undef FE_K5Q
     } else {
         // wave per row, rows interleaved over a grid that fills the chip
         const int64_t grid = std::min<int64_t>((sa.n_rows + 3) / 4, 8192);
@@ -320,10 +356,17 @@ fe_status launch_scatter_batch(const AsmJob &h, const ElemLayout &el, const AsmJ
     if (grid == 0) return FE_OK;
     if (el.cb > 1) {
         if (el.cb != 64) return set_error(FE_EINVAL, "unexpected element layout");
-        if (el.elem_bytes == 8)
-            hipLaunchKernelGGL((k5_rows_batch_kernel<64, double>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
-        else
-            hipLaunchKernelGGL((k5_rows_batch_kernel<64, float>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+        if (h.s.dim == 3) {
+            if (el.elem_bytes == 8)
+                hipLaunchKernelGGL((k5_q1_batch_kernel<3, double>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+            else
+                hipLaunchKernelGGL((k5_q1_batch_kernel<3, float>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+        } else {
+            if (el.elem_bytes == 8)
+                hipLaunchKernelGGL((k5_q1_batch_kernel<2, double>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+            else
+                hipLaunchKernelGGL((k5_q1_batch_kernel<2, float>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs);
+        }
     } else {
 #define FE_K5B(NCV, T) \
     hipLaunchKernelGGL((k5_entries_batch_kernel<NCV, T>), dim3(grid), dim3(256), 0, s, jobs, boff, njobs)

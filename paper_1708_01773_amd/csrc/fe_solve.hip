@@ -583,6 +583,48 @@ __device__ __forceinline__ int find_problem(const int32_t *__restrict__ boff, in
     return lo;
 }
 
+// Vector access in pairs of neighbours (16-byte loads and stores); m = 2, or
+// 1 for the last, odd element of a range.
+__device__ __forceinline__ void load_pair(const double *__restrict__ a, int64_t i, int m, double (&o)[2])
+{
+    if (m == 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(a + i);
+        o[0] = t.x;
+        o[1] = t.y;
+    } else {
+        o[0] = a[i];
+        o[1] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void store_pair(double *__restrict__ a, int64_t i, int m, const double (&v)[2])
+{
+    if (m == 2) *reinterpret_cast<double2 *>(a + i) = make_double2(v[0], v[1]);
+    else a[i] = v[0];
+}
+
+// Visits the pairs (i, i + 1) of [lo, hi) (lo even) owned by this thread:
+// body(i, m) issues the pair's loads and returns the work that uses them, so
+// that the loads of two pairs are in flight before either pair's work runs.
+// The visiting order, and so every partial sum, is fixed.
+template <typename Body>
+__device__ __forceinline__ void for_pairs(int64_t lo, int64_t hi, Body body)
+{
+    for (int64_t i0 = lo + 2 * int64_t(threadIdx.x); i0 < hi; i0 += 4 * int64_t(kBlock)) {
+        const int64_t i1 = i0 + 2 * int64_t(kBlock);
+        const int m0 = hi - i0 >= 2 ? 2 : 1;
+        auto w0 = body(i0, m0);
+        if (i1 < hi) {
+            const int m1 = hi - i1 >= 2 ? 2 : 1;
+            auto w1 = body(i1, m1);
+            w0();
+            w1();
+        } else {
+            w0();
+        }
+    }
+}
+
 // Elements [lo, hi) of logical block lb of nb for the vector kernels.
 __device__ __forceinline__ void owned_elems(int64_t n, int64_t lb, int64_t nb, int64_t &lo, int64_t &hi)
 {
@@ -713,13 +755,28 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__res
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ r = P.w.r;
     double *__restrict__ x = P.x;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        v[0] += ri * (dinv[i] * ri);
-        v[1] += ri * ri;
-    }
+    for_pairs(lo, hi, [&](int64_t i, int m) {
+        double pp[2], qq[2], rr[2], xx[2], dd[2];
+        load_pair(p, i, m, pp);
+        load_pair(q, i, m, qq);
+        load_pair(r, i, m, rr);
+        load_pair(x, i, m, xx);
+        load_pair(dinv, i, m, dd);
+        return [=, &v]() {
+            double xn[2], rn[2];
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                xn[e] = xx[e] + alpha * pp[e];
+                rn[e] = rr[e] - alpha * qq[e];
+                if (e < m) {
+                    v[0] += rn[e] * (dd[e] * rn[e]);
+                    v[1] += rn[e] * rn[e];
+                }
+            }
+            store_pair(x, i, m, xn);
+            store_pair(r, i, m, rn);
+        };
+    });
     block_sum_all<2>(v);
     if (threadIdx.x == 0) {
         P.w.p2[lb] = v[0];
@@ -760,7 +817,18 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
     const double *__restrict__ r = P.w.r;
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ p = P.w.p;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) p[i] = dinv[i] * r[i] + beta * p[i];
+    for_pairs(lo, hi, [&](int64_t i, int m) {
+        double rr[2], dd[2], pp[2];
+        load_pair(r, i, m, rr);
+        load_pair(dinv, i, m, dd);
+        load_pair(p, i, m, pp);
+        return [=]() {
+            double pn[2];
+#pragma unroll
+            for (int e = 0; e < 2; e++) pn[e] = dd[e] * rr[e] + beta * pp[e];
+            store_pair(p, i, m, pn);
+        };
+    });
 }
 
 // partials of (b - A x)^2
