@@ -426,7 +426,7 @@ def main():
     spmv_avg_s = tm["spmv_ms"] / max(tm["spmv_calls"], 1) * 1e-3
     sb = spmv_bytes(A.n_rows, A.nnz, args.spmv)
     achieved = sb / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
-    kname = "pcg_spmv_kernel<2>" if args.spmv == "mesh" else "pcg_spmv_kernel<0>"
+    kname = "pcg_spmv_kernel/mesh" if args.spmv == "mesh" else "pcg_spmv_kernel/csr"
     traffic = traffic_for(kname)
     lat_sorted = sorted(lat)
     p99 = lat_sorted[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]

@@ -73,7 +73,8 @@ struct PcgProb {
 
 // How a CSR matrix is traversed.
 struct SpmvPlan {
-    int mode;  // 0: wave-level CSR-stream, 1: wave per row, 2: structured (pattern evaluated)
+    int mode;  // 0: wave-level CSR-stream, 1: wave per row, 2: structured (pattern evaluated),
+               // 3: structured short rows, two lanes per row (rpb = longest row)
     int nc = 1;  // components (mode 2)
     int rpb;   // rows per wave-iteration (stream mode)
     int lanes; // lanes per row
@@ -504,26 +505,123 @@ __device__ __forceinline__ void for_rows_struct(const SpaceArgs &s, const double
     }
 }
 
+// Short rows (at most LMAX <= 32 entries): 32 rows per wave step and two
+// lanes per row (lane l holds row l % 32 and the positions
+// [h H, h H + H) of it, h = l / 32, H = (LMAX + 1) / 2).  The values of the
+// step's rows, contiguous in CSR, are loaded with coalesced loads into the
+// wave's LDS slice; the x loads of neighbouring rows at the same position are
+// neighbours in memory, so they coalesce too.  A row is the sum of its two
+// half sums, each taken in position order.
+template <int LMAX, int NC, typename Fn>
+__device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double *__restrict__ val,
+                                               const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
+{
+    constexpr int RW = 32, H = (LMAX + 1) / 2, CAP = RW * LMAX, CH = (CAP + 63) / 64;
+    __shared__ double stage[kWaves][CAP];
+    double *my = stage[threadIdx.x / 64];
+    const int lane = threadIdx.x % 64, rl = lane % RW, h = lane / RW;
+    const int64_t n = s.n_rows;
+    const int64_t nw = nb * kWaves, lw = lb * kWaves + threadIdx.x / 64;
+    const int64_t runs = (n + RW - 1) / RW;
+    const int32_t k = s.k;
+    const double kinv = 1.0 / double(k);
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * (k + 1) + k * ((A[r].lo + k - 1) / k);
+    }
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const double f0inv = 1.0 / double(f0), f1inv = 1.0 / double(f1);
+    const int64_t T0 = s.ax[0].T, T1 = s.ax[1].T;
+    const int32_t sy = NC * f0, sz = NC * f0 * f1;
+    for (int64_t run = lw; run < runs; run += nw) {
+        const int64_t row = run * RW + rl;
+        const bool live = row < n;
+        int64_t start = 0;
+        int32_t len = 0, colbase = 0, wx = 1, w1 = 1;
+        if (live) {
+            const int32_t r32 = int32_t(row);
+            const int32_t R = r32 / NC, c = r32 - R * NC;
+            const int32_t q = div_exact(R, f0, f0inv), t0 = R - q * f0;
+            const int32_t t2 = div_exact(q, f1, f1inv), t1 = q - t2 * f1;
+            int32_t w0, w2, cl0, cl1, cl2, P0, P1, P2;
+            axis_row(A[0], k, kinv, A[0].lo + t0, w0, cl0, P0);
+            axis_row(A[1], k, kinv, A[1].lo + t1, w1, cl1, P1);
+            axis_row(A[2], k, kinv, A[2].lo + t2, w2, cl2, P2);
+            const int64_t S = int64_t(P2) * T1 * T0 + int64_t(w2) * P1 * T0 + int64_t(w2 * w1) * P0;
+            wx = w0 * NC;
+            len = wx * w1 * w2;
+            start = int64_t(NC) * NC * S + int64_t(c) * len;
+            colbase = NC * ((cl0 - A[0].lo) + f0 * ((cl1 - A[1].lo) + f1 * (cl2 - A[2].lo)));
+        }
+        const int nv = int(n - run * RW < RW ? n - run * RW : RW);
+        const int64_t base = __shfl(start, 0);
+        const int total = int(__shfl(start, nv - 1) - base) + __shfl(len, nv - 1);
+        {
+            double t4[CH];
+#pragma unroll
+            for (int u = 0; u < CH; u++) {
+                const int t = lane + 64 * u;
+                t4[u] = t < total ? val[base + t] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; u++)
+                if (lane + 64 * u < CAP) my[lane + 64 * u] = t4[u];
+        }
+        wave_lds_sync();
+        // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8] (p < 32, d <= 27)
+        const uint32_t mx = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
+        const uint32_t my1 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
+        const int off = int(start - base);
+        double a[H], xv[H];
+#pragma unroll
+        for (int t = 0; t < H; t++) {
+            const int32_t pos = h * H + t;
+            const bool ok = pos < len;
+            const int32_t pc = ok ? pos : 0;
+            const int32_t qy = int32_t((uint32_t(pc) * mx) >> 20);
+            const int32_t xx = pc - qy * wx;
+            const int32_t j2 = int32_t((uint32_t(qy) * my1) >> 20);
+            const int32_t j1 = qy - j2 * w1;
+            xv[t] = x[colbase + xx + sy * j1 + sz * j2];
+            a[t] = ok ? my[off + pc] : 0.0;
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int t = 0; t < H; t++) sum += a[t] * xv[t];
+        const double upper = __shfl(sum, (lane + RW) % 64);
+        if (h == 0 && live) f(row, sum + upper);
+        wave_lds_sync();
+    }
+}
+
 // Dispatch on the plan at compile time: kMode, kRpb (rows per wave) and kNc
 // (components, structured mode only).  FE_PLAN_DISPATCH_ALL adds the
 // structured plans (FP64 values only).
 #define FE_SPLAN_DISPATCH(PL, BODY)                                                            \
-    switch ((PL).nc * 100 + (PL).rpb) {                                                        \
-        case 116: FE_PLAN_CASE(2, 16, 1, BODY)                                                 \
-        case 108: FE_PLAN_CASE(2, 8, 1, BODY)                                                  \
-        case 104: FE_PLAN_CASE(2, 4, 1, BODY)                                                  \
-        case 102: FE_PLAN_CASE(2, 2, 1, BODY)                                                  \
-        case 101: FE_PLAN_CASE(2, 1, 1, BODY)                                                  \
-        case 208: FE_PLAN_CASE(2, 8, 2, BODY)                                                  \
-        case 204: FE_PLAN_CASE(2, 4, 2, BODY)                                                  \
-        case 202: FE_PLAN_CASE(2, 2, 2, BODY)                                                  \
-        case 201: FE_PLAN_CASE(2, 1, 2, BODY)                                                  \
-        case 302: FE_PLAN_CASE(2, 2, 3, BODY)                                                  \
+    switch ((PL).mode * 1000 + (PL).nc * 100 + (PL).rpb) {                                     \
+        case 3127: FE_PLAN_CASE(3, 27, 1, BODY)                                                \
+        case 3109: FE_PLAN_CASE(3, 9, 1, BODY)                                                 \
+        case 3125: FE_PLAN_CASE(3, 25, 1, BODY)                                                \
+        case 3218: FE_PLAN_CASE(3, 18, 2, BODY)                                                \
+        case 2116: FE_PLAN_CASE(2, 16, 1, BODY)                                                 \
+        case 2108: FE_PLAN_CASE(2, 8, 1, BODY)                                                  \
+        case 2104: FE_PLAN_CASE(2, 4, 1, BODY)                                                  \
+        case 2102: FE_PLAN_CASE(2, 2, 1, BODY)                                                  \
+        case 2101: FE_PLAN_CASE(2, 1, 1, BODY)                                                  \
+        case 2208: FE_PLAN_CASE(2, 8, 2, BODY)                                                  \
+        case 2204: FE_PLAN_CASE(2, 4, 2, BODY)                                                  \
+        case 2202: FE_PLAN_CASE(2, 2, 2, BODY)                                                  \
+        case 2201: FE_PLAN_CASE(2, 1, 2, BODY)                                                  \
+        case 2302: FE_PLAN_CASE(2, 2, 3, BODY)                                                  \
         default: FE_PLAN_CASE(2, 1, 3, BODY)                                                   \
     }
 #define FE_PLAN_DISPATCH_ALL(PL, BODY)                                                         \
     do {                                                                                       \
-        if ((PL).mode == 2) {                                                                  \
+        if ((PL).mode >= 2) {                                                                  \
             FE_SPLAN_DISPATCH(PL, BODY)                                                        \
         } else {                                                                               \
             FE_PLAN_DISPATCH(PL, BODY);                                                        \
@@ -537,8 +635,15 @@ static SpmvPlan struct_plan(const SpaceArgs &sa)
     int L = sa.ncomp;
     for (int r = 0; r < sa.dim; r++) L *= 2 * sa.k + 1;
     SpmvPlan pl{};
-    pl.mode = 2;
     pl.nc = sa.ncomp;
+    // rows of at most 32 entries with an instantiated length: two lanes per row
+    if ((sa.ncomp == 1 && (L == 27 || L == 9 || L == 25)) || (sa.ncomp == 2 && L == 18)) {
+        pl.mode = 3;
+        pl.rpb = L;
+        pl.lanes = 2;
+        return pl;
+    }
+    pl.mode = 2;
     const int maxr = sa.ncomp == 1 ? 16 : (sa.ncomp == 2 ? 8 : 2);
     int rpw = maxr;
     while (rpw > 1 && (64 / rpw) * 4 < L) rpw /= 2;
@@ -561,7 +666,9 @@ __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const
 template <int MODE, int RPB, int NC, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
 {
-    if constexpr (MODE == 2)
+    if constexpr (MODE == 3)
+        for_rows_short<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+    else if constexpr (MODE == 2)
         for_rows_struct<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else
         for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), x, lb, nb, f);
@@ -647,11 +754,14 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, const int64_t *
                             [&](int64_t row, double s) { y[row] = s; });
 }
 
-template <int RPB, int NC>
+template <int MODE, int RPB, int NC>
 __global__ __launch_bounds__(kBlock) void spmv_struct_kernel(SpaceArgs sa, const double *__restrict__ val,
                                                               const double *__restrict__ x, double *__restrict__ y)
 {
-    for_rows_struct<RPB, NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
+    if constexpr (MODE == 3)
+        for_rows_short<RPB, NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
+    else
+        for_rows_struct<RPB, NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
 }
 
 // r = b - A x; p = z = dinv r; partials of r.z, r.r, b.b
@@ -861,7 +971,8 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 // ---------------------------------------------------------------------------
 static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
-    const int64_t runs = (n + pl.rpb - 1) / pl.rpb;
+    const int rows_per_run = pl.mode == 3 ? 32 : pl.rpb;
+    const int64_t runs = (n + rows_per_run - 1) / rows_per_run;
     return int(std::max<int64_t>(1, std::min<int64_t>(kGrid, (runs + kWaves - 1) / kWaves)));
 }
 
@@ -1376,7 +1487,7 @@ fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const doubl
     if (sa.n_rows == 0) return FE_OK;
     const SpmvPlan pl = struct_plan(sa);
     const int g = grid_rows(sa.n_rows, pl);
-    FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kRpb, kNc><<<dim3(g), dim3(kBlock), 0, s>>>(sa, val, x, y)));
+    FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(kBlock), 0, s>>>(sa, val, x, y)));
     FE_HIP(hipGetLastError());
     return FE_OK;
 }
