@@ -154,19 +154,25 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
     using Acc = typename Pol::Acc;
     using Out = typename Pol::Out;
 
-    const int k = s.k, k1 = k + 1, nn = s.nn, nloc = s.nloc;
-    const int nq = k1 * k1 * k1;
+    // nodes per direction (compile time: the padded node count fixes the order)
+    constexpr int K1 = NNP == 32 ? 3 : (NNP == 64 ? 4 : 5);
+    constexpr int NQ = K1 * K1 * K1;  // quadrature points = nodes
+    constexpr int TPQ = 256 / QS;     // threads per quadrature point in the gradient stage
+    constexpr int NPT = NNP / TPQ;    // nodes per thread in the gradient stage
+    static_assert(256 % QS == 0 && NNP % TPQ == 0, "gradient stage shape");
+    const int nn = NQ, nloc = s.nloc;
     const int64_t cell = bid / parts;
     const int part = int(bid % parts);
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
 
     __shared__ double sX[8][3];
-    __shared__ double sL[kMaxQ1 * kMaxQ1], sD[kMaxQ1 * kMaxQ1], sGX[kMaxQ1], sGW[kMaxQ1];
-    __shared__ double sJi[QS][9];
-    __shared__ double sW[QS], sWd[QS], sXq[QS][3];
+    __shared__ double sL[K1 * K1], sD[K1 * K1];
+    // geometry of every quadrature point of the cell
+    __shared__ double sJi[NQ][9];
+    __shared__ double sW[NQ], sWd[NQ], sXq[NQ][3];
     __shared__ double sScale[2];  // alpha, beta (powers of two)
     __shared__ int sBad;
-    // gradients (and the scaled B operand for FP16/BF16)
+    // gradients (and the scaled B operand for FP16/BF16) of a slab of points
     __shared__ __attribute__((aligned(16))) S sG[DIM][Pol::KFAST ? NNP : QS][Pol::KFAST ? QS : NNP];
     __shared__ __attribute__((aligned(16))) S sH[Pol::SCALED ? DIM : 1][Pol::SCALED ? NNP : 1][Pol::SCALED ? QS : 1];
     __shared__ S sWs[Pol::KFAST ? 1 : QS];
@@ -178,37 +184,37 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
         sX[tid][1] = m.y[vid];
         sX[tid][2] = m.z[vid];
     }
-    if (tid < k1 * k1) {
+    if (tid < K1 * K1) {
         sL[tid] = rt.L[tid];
         sD[tid] = rt.D[tid];
-    }
-    if (tid < k1) {
-        sGX[tid] = rt.gx[tid];
-        sGW[tid] = rt.gw[tid];
     }
     if (tid == 0) sBad = 0;
     const double coef = m.coef[cell];
     __syncthreads();
+    for (int q = tid; q < NQ; q += 256) {
+        const int a0 = q % K1, a1 = (q / K1) % K1, a2 = q / (K1 * K1);
+        const double xi[3] = {rt.gx[a0], rt.gx[a1], rt.gx[a2]};
+        double Xl[8][3], Ji[9], xq[3];
+        for (int v = 0; v < 8; v++)
+            for (int r = 0; r < 3; r++) Xl[v][r] = sX[v][r];
+        const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
+        if (!(det > 0.0)) sBad = 1;
+        const double wd = rt.gw[a0] * rt.gw[a1] * rt.gw[a2] * fabs(det);
+        sWd[q] = wd;
+        sW[q] = wd * coef;
+        for (int t = 0; t < 9; t++) sJi[q][t] = Ji[t];
+        for (int r = 0; r < 3; r++) sXq[q][r] = xq[r];
+        if (q == 0) sScale[0] = det;
+    }
+    __syncthreads();
 
     // per-cell operand scaling (FP16/BF16 only): alpha ~ h, beta = alpha / 2^floor(log2 max_q w_q)
     if (Pol::SCALED) {
-        __shared__ double sWmax[256];
-        double wl = 0.0, det0 = 0.0;
-        for (int q = tid; q < nq; q += blockDim.x) {
-            const int q0 = q % k1, q1 = (q / k1) % k1, q2 = q / (k1 * k1);
-            const double xi[3] = {sGX[q0], sGX[q1], sGX[q2]};
-            double Xl[8][3], Ji[9], xq[3];
-            for (int v = 0; v < 8; v++)
-                for (int r = 0; r < 3; r++) Xl[v][r] = sX[v][r];
-            const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
-            wl = fmax(wl, sGW[q0] * sGW[q1] * sGW[q2] * fabs(det) * coef);
-            if (q == 0) det0 = det;
-        }
-        sWmax[tid] = wl;
         __syncthreads();
         if (tid == 0) {
             double wmax = 0.0;
-            for (int t = 0; t < blockDim.x; t++) wmax = fmax(wmax, sWmax[t]);
+            for (int q = 0; q < NQ; q++) wmax = fmax(wmax, sW[q]);
+            const double det0 = sScale[0];
             const double h = cbrt(fabs(det0) > 0.0 ? fabs(det0) : 1.0);
             const double alpha = exp2(floor(log2(h)));
             const double beta = alpha * (wmax > 0.0 ? exp2(-floor(log2(wmax))) : 1.0);
@@ -240,53 +246,48 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
     for (int t = 0; t < (NNP * NC + 255) / 256; t++) facc[t] = 0.0;
 
     const int i16 = lane % 16, g4 = lane / 16;
-    for (int q0s = 0; q0s < nq; q0s += QS) {
-        const int qn = min(QS, nq - q0s);
-        if (tid < QS) {
-            if (tid < qn) {
-                const int q = q0s + tid;
-                const int a0 = q % k1, a1 = (q / k1) % k1, a2 = q / (k1 * k1);
-                const double xi[3] = {sGX[a0], sGX[a1], sGX[a2]};
-                double Xl[8][3], Ji[9], xq[3];
-                for (int v = 0; v < 8; v++)
-                    for (int r = 0; r < 3; r++) Xl[v][r] = sX[v][r];
-                const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
-                if (!(det > 0.0)) sBad = 1;
-                const double wd = sGW[a0] * sGW[a1] * sGW[a2] * fabs(det);
-                sWd[tid] = wd;
-                sW[tid] = wd * coef;
-                for (int t = 0; t < 9; t++) sJi[tid][t] = Ji[t];
-                for (int r = 0; r < 3; r++) sXq[tid][r] = xq[r];
-            } else {
-                sWd[tid] = 0.0;
-                sW[tid] = 0.0;
-                for (int t = 0; t < 9; t++) sJi[tid][t] = 0.0;
-                for (int r = 0; r < 3; r++) sXq[tid][r] = 0.0;
+    // gradient stage: thread -> (point qq of the slab, nodes sub, sub + TPQ, ...)
+    const int gq = tid / TPQ, gsub = tid % TPQ;
+    for (int q0s = 0; q0s < NQ; q0s += QS) {
+        const int qn = min(QS, NQ - q0s);
+        {
+            const int q = q0s + gq;
+            const bool live = gq < qn;
+            double Ji[9];
+            int b0 = 0, b1 = 0, b2 = 0;
+            double w = 0.0;
+            if (live) {
+#pragma unroll
+                for (int t = 0; t < 9; t++) Ji[t] = sJi[q][t];
+                b0 = q % K1;
+                b1 = (q / K1) % K1;
+                b2 = q / (K1 * K1);
+                w = sW[q];
             }
-        }
-        __syncthreads();
-        // physical gradients of every (padded) node at the slab's points
-        for (int idx = tid; idx < QS * NNP; idx += blockDim.x) {
-            const int qq = idx / NNP, node = idx % NNP;
-            double g[3] = {0.0, 0.0, 0.0};
-            if (qq < qn && node < nn) {
-                const int q = q0s + qq;
-                const int b0 = q % k1, b1 = (q / k1) % k1, b2 = q / (k1 * k1);
-                const int n0 = node % k1, n1 = (node / k1) % k1, n2 = node / (k1 * k1);
-                const double L0 = sL[n0 * k1 + b0], L1 = sL[n1 * k1 + b1], L2 = sL[n2 * k1 + b2];
-                const double gr[3] = {sD[n0 * k1 + b0] * L1 * L2, L0 * sD[n1 * k1 + b1] * L2, L0 * L1 * sD[n2 * k1 + b2]};
-                for (int c = 0; c < 3; c++) g[c] = sJi[qq][0 * 3 + c] * gr[0] + sJi[qq][1 * 3 + c] * gr[1] + sJi[qq][2 * 3 + c] * gr[2];
-            }
-            for (int c = 0; c < 3; c++) {
-                if (Pol::KFAST) {
-                    sG[c][node][qq] = S(g[c] * alpha);
-                    if (Pol::SCALED) sH[c][node][qq] = S(g[c] * sW[qq] * beta);
-                } else {
-                    sG[c][qq][node] = S(g[c]);
+#pragma unroll
+            for (int j = 0; j < NPT; j++) {
+                const int node = gsub + TPQ * j;
+                double g[3] = {0.0, 0.0, 0.0};
+                if (live && node < nn) {
+                    const int n0 = node % K1, n1 = (node / K1) % K1, n2 = node / (K1 * K1);
+                    const double L0 = sL[n0 * K1 + b0], L1 = sL[n1 * K1 + b1], L2 = sL[n2 * K1 + b2];
+                    const double gr[3] = {sD[n0 * K1 + b0] * L1 * L2, L0 * sD[n1 * K1 + b1] * L2,
+                                          L0 * L1 * sD[n2 * K1 + b2]};
+#pragma unroll
+                    for (int c = 0; c < 3; c++) g[c] = Ji[0 * 3 + c] * gr[0] + Ji[1 * 3 + c] * gr[1] + Ji[2 * 3 + c] * gr[2];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    if (Pol::KFAST) {
+                        sG[c][node][gq] = S(g[c] * alpha);
+                        if (Pol::SCALED) sH[c][node][gq] = S(g[c] * w * beta);
+                    } else {
+                        sG[c][gq][node] = S(g[c]);
+                    }
                 }
             }
+            if (!Pol::KFAST && gsub == 0) sWs[gq] = S(w);
         }
-        if (!Pol::KFAST && tid < QS) sWs[tid] = S(sW[tid]);
         __syncthreads();
         // MFMA over the slab
 #pragma unroll
@@ -341,13 +342,13 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
                 const int row = tid + 256 * t;
                 if (row < nloc) {
                     const int a = row / NC, c = row % NC;
-                    const int n0 = a % k1, n1 = (a / k1) % k1, n2 = a / (k1 * k1);
+                    const int n0 = a % K1, n1 = (a / K1) % K1, n2 = a / (K1 * K1);
                     for (int qq = 0; qq < qn; qq++) {
                         const int q = q0s + qq;
-                        const int b0 = q % k1, b1 = (q / k1) % k1, b2 = q / (k1 * k1);
-                        const double phi = sL[n0 * k1 + b0] * sL[n1 * k1 + b1] * sL[n2 * k1 + b2];
-                        const double xq[3] = {sXq[qq][0], sXq[qq][1], sXq[qq][2]};
-                        facc[t] += sWd[qq] * source_value_mf(p, xq, c) * phi;
+                        const int b0 = q % K1, b1 = (q / K1) % K1, b2 = q / (K1 * K1);
+                        const double phi = sL[n0 * K1 + b0] * sL[n1 * K1 + b1] * sL[n2 * K1 + b2];
+                        const double xq[3] = {sXq[q][0], sXq[q][1], sXq[q][2]};
+                        facc[t] += sWd[q] * source_value_mf(p, xq, c) * phi;
                     }
                 }
             }
@@ -401,14 +402,14 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
 }
 
 template <class Pol, int PROB, int NNP, int PPW, int QS>
-__global__ __launch_bounds__(256) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt, int parts,
+__global__ __launch_bounds__(256, 2) void k3_mfma_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, RefTables rt, int parts,
                                                       typename Pol::Out *__restrict__ E, double *__restrict__ F)
 {
     k3_mfma_body<Pol, PROB, NNP, PPW, QS>(s, m, p, rt, parts, E, F, xcd_block(blockIdx.x, gridDim.x));
 }
 
 template <class Pol, int PROB, int NNP, int PPW, int QS>
-__global__ __launch_bounds__(256) void k3_mfma_batch_kernel(const AsmJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, 2) void k3_mfma_batch_kernel(const AsmJob *__restrict__ jobs,
                                                              const int32_t *__restrict__ boff, int njobs)
 {
     int64_t lb, nb;
