@@ -235,8 +235,9 @@ def batch_form(args, F, torch):
         "speedup_vs_sequential": t_s / t_b,
         "bitwise_equal_to_sequential": bool(same[0]),
         "max_rel_error_vs_plain_fp64_solution": err[0],
-        "autotuned_spmv": {str(c): {"mode": t["chosen"]["mode"], "rows_per_wave": t["chosen"]["rows_per_wave"],
-                                    "us": t["chosen"]["us"]} for c, t in tuned.items()},
+        "autotuned_spmv": {f"order {t['matrix']['order']}": {
+            "mode": t["chosen"]["mode"], "rows_per_wave": t["chosen"]["rows_per_wave"], "us": t["chosen"]["us"],
+            "tried_us": [round(x["us"], 2) for x in t["tried"]]} for c, t in tuned.items()},
     }
 
 
@@ -469,7 +470,7 @@ def main():
             out["forms"]["serve"] = serve_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, A.nnz)
+        out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, out["config"]["nnz"])
     print(json.dumps(out), flush=True)
 
 

@@ -297,6 +297,17 @@ fe_status fe_spmv_autotune_query(int64_t n_rows, size_t *ws_bytes);
 fe_status fe_spmv_autotune(const fe_csr *A, int32_t reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried,
                            int32_t max_tried, int32_t *n_tried, fe_spmv_plan *chosen, fe_stream stream);
 fe_status fe_spmv_tuning_reset(void);
+/* The same for the evaluated-pattern traversal of fe_spmv_mesh /
+ * fe_pcg_solve_mesh / fe_pcg_solve_batch_mesh: plans are modes 2 (lanes per
+ * row, rows_per_wave runs) and 3 (short rows, two lanes per row; rows_per_wave
+ * reports the longest row), timed on A assembled on (mesh, order, coeff); the
+ * fastest becomes the plan of every mesh system with the same longest row and
+ * component count.  ws: fe_spmv_autotune_query(A->n_rows) bytes. */
+fe_status fe_spmv_autotune_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A, int32_t reps,
+                                void *ws, size_t ws_bytes, fe_spmv_plan *tried, int32_t max_tried, int32_t *n_tried,
+                                fe_spmv_plan *chosen, fe_stream stream);
+fe_status fe_spmv_plan_of_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_spmv_plan *plan,
+                               int32_t *row_class);
 /* The plan a matrix of n_rows rows and nnz entries gets now, and its class. */
 fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32_t *row_class);
 

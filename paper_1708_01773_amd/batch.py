@@ -66,14 +66,15 @@ class BatchRun:
         self.cells = sum(n ** 3 for n, _ in self.specs)
 
     def autotune(self, reps=10):
-        """Tunes the SpMV plan of every row-length class in the batch on its
-        largest matrix (assembled alone for the purpose)."""
+        """Tunes the evaluated-pattern SpMV plan of every row class in the batch
+        (longest row, components) on its largest matrix, assembled alone for
+        the purpose; the batched solve then uses the tuned plans."""
         best = {}
-        for i, (nr, nz) in enumerate(zip(self.n_rows, self.nnz)):
-            if nr == 0:
+        for i, (mesh, k, coeff) in enumerate(self.problems):
+            if self.n_rows[i] == 0:
                 continue
-            cls = F.spmv_plan_of(nr, nz)[2]
-            if cls not in best or nz > self.nnz[best[cls]]:
+            cls = F.spmv_plan_of_mesh(mesh, k, coeff)[2]
+            if cls not in best or self.nnz[i] > self.nnz[best[cls]]:
                 best[cls] = i
         chosen = {}
         for cls, i in sorted(best.items()):
@@ -81,8 +82,9 @@ class BatchRun:
             A = F.Assembly(mesh, k, coeff)
             A.pattern()
             A.assemble()
-            ch, tried = F.spmv_autotune(A.csr, reps)
-            chosen[cls] = dict(chosen=ch, tried=tried, matrix=dict(problem=i, n_rows=self.n_rows[i], nnz=self.nnz[i]))
+            ch, tried = F.spmv_autotune_mesh(mesh, k, coeff, A.csr, reps)
+            chosen[cls] = dict(chosen=ch, tried=tried,
+                               matrix=dict(problem=i, order=k, n_rows=self.n_rows[i], nnz=self.nnz[i]))
             del A
         return chosen
 

@@ -658,6 +658,33 @@ fe_status fe_spmv_autotune(const fe_csr *A, int32_t reps, void *ws, size_t ws_by
     return st;
 }
 
+fe_status fe_spmv_autotune_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, int32_t reps, void *ws,
+                                size_t ws_bytes, fe_spmv_plan *tried, int32_t max_tried, int32_t *n_tried,
+                                fe_spmv_plan *chosen, fe_stream stream)
+{
+    if (!A || !ws) return set_error(FE_EINVAL, "null argument");
+    if (reps < 1 || max_tried < 0 || (max_tried > 0 && !tried)) return set_error(FE_EINVAL, "bad reps/max_tried");
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    st = check_csr(A, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (A->nnz > 0 && !A->values) return set_error(FE_EINVAL, "null csr values");
+    m->last_stream = as_stream(stream);
+    int nt = 0;
+    st = spmv_autotune_struct(m->space.args, A->values, reps, ws, ws_bytes, tried, max_tried, &nt, chosen,
+                              as_stream(stream));
+    if (n_tried) *n_tried = nt;
+    return st;
+}
+
+fe_status fe_spmv_plan_of_mesh(fe_mesh m, int32_t order, const fe_coeff *c, fe_spmv_plan *plan, int32_t *row_class)
+{
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    spmv_plan_of_struct(m->space.args, plan, row_class);
+    return FE_OK;
+}
+
 fe_status fe_spmv_tuning_reset(void)
 {
     spmv_tuning_reset();

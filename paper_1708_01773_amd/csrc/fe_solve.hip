@@ -616,7 +616,9 @@ __device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double 
         case 2204: FE_PLAN_CASE(2, 4, 2, BODY)                                                  \
         case 2202: FE_PLAN_CASE(2, 2, 2, BODY)                                                  \
         case 2201: FE_PLAN_CASE(2, 1, 2, BODY)                                                  \
-        case 2302: FE_PLAN_CASE(2, 2, 3, BODY)                                                  \
+        case 2308: FE_PLAN_CASE(2, 8, 3, BODY)                                                 \
+        case 2304: FE_PLAN_CASE(2, 4, 3, BODY)                                                 \
+        case 2302: FE_PLAN_CASE(2, 2, 3, BODY)                                                 \
         default: FE_PLAN_CASE(2, 1, 3, BODY)                                                   \
     }
 #define FE_PLAN_DISPATCH_ALL(PL, BODY)                                                         \
@@ -628,10 +630,26 @@ __device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double 
         }                                                                                      \
     } while (0)
 
-// Largest run of rows per wave whose lanes cover a longest row in at most
-// four steps (one wave per row beyond that).
+// Row class of the evaluated-pattern traversal: (longest row, components).
+static int struct_class(const SpaceArgs &sa)
+{
+    int L = sa.ncomp;
+    for (int r = 0; r < sa.dim; r++) L *= 2 * sa.k + 1;
+    return L * 4 + sa.ncomp;
+}
+
+static std::map<int, SpmvPlan> g_stuned;  // evaluated-pattern plans measured by the autotuner
+
+// The plan of an evaluated-pattern system: the autotuned one of its class,
+// else short rows (at most 32 entries, instantiated lengths) two lanes per
+// row, longer rows eight rows per wave step.
 static SpmvPlan struct_plan(const SpaceArgs &sa)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_stuned.find(struct_class(sa));
+        if (it != g_stuned.end()) return it->second;
+    }
     int L = sa.ncomp;
     for (int r = 0; r < sa.dim; r++) L *= 2 * sa.k + 1;
     SpmvPlan pl{};
@@ -643,12 +661,11 @@ static SpmvPlan struct_plan(const SpaceArgs &sa)
         pl.lanes = 2;
         return pl;
     }
+    // eight rows per wave step (8 lanes per row, the rest of a long row in
+    // further steps of 32 positions): measured fastest for Q2-Q3 rows
     pl.mode = 2;
-    const int maxr = sa.ncomp == 1 ? 16 : (sa.ncomp == 2 ? 8 : 2);
-    int rpw = maxr;
-    while (rpw > 1 && (64 / rpw) * 4 < L) rpw /= 2;
-    pl.rpb = rpw;
-    pl.lanes = 64 / rpw;
+    pl.rpb = 8;
+    pl.lanes = 8;
     return pl;
 }
 
@@ -1104,6 +1121,7 @@ void spmv_tuning_reset()
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
+    g_stuned.clear();
 }
 
 void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls)
@@ -1111,6 +1129,78 @@ void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls)
     const SpmvPlan pl = plan_for(n, nnz);
     if (plan) *plan = fe_spmv_plan{pl.mode, pl.rpb, 0.0};
     if (cls) *cls = plan_class(n, nnz);
+}
+
+// Evaluated-pattern plans: every rows-per-wave of the lanes-per-row traversal
+// instantiated for the component count, and the short-row traversal where it
+// exists for the row length.
+static std::vector<SpmvPlan> struct_candidates(const SpaceArgs &sa)
+{
+    int L = sa.ncomp;
+    for (int r = 0; r < sa.dim; r++) L *= 2 * sa.k + 1;
+    std::vector<SpmvPlan> c;
+    const int nc = sa.ncomp;
+    const std::vector<int> rpws = nc == 1 ? std::vector<int>{16, 8, 4, 2, 1}
+                                          : std::vector<int>{8, 4, 2, 1};
+    for (int r : rpws) c.push_back(SpmvPlan{2, nc, r, 64 / r});
+    if ((nc == 1 && (L == 27 || L == 9 || L == 25)) || (nc == 2 && L == 18)) c.push_back(SpmvPlan{3, nc, L, 2});
+    return c;
+}
+
+fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int reps, void *ws, size_t ws_bytes,
+                               fe_spmv_plan *tried, int max_tried, int *n_tried, fe_spmv_plan *chosen, hipStream_t s)
+{
+    const int64_t n = sa.n_rows;
+    if (n_tried) *n_tried = 0;
+    if (n == 0) return set_error(FE_EINVAL, "empty system");
+    if (ws_bytes < autotune_ws_bytes(n)) return set_error(FE_EINVAL, "autotune workspace too small");
+    double *x = static_cast<double *>(ws);
+    double *y = reinterpret_cast<double *>(static_cast<char *>(ws) + align256(size_t(n) * 8));
+    FE_HIP(hipMemsetAsync(x, 0, sizeof(double) * size_t(n), s));
+    const std::vector<SpmvPlan> cand = struct_candidates(sa);
+    hipEvent_t e0, e1;
+    FE_HIP(hipEventCreate(&e0));
+    FE_HIP(hipEventCreate(&e1));
+    int best = -1;
+    double best_us = 0.0;
+    fe_status st = FE_OK;
+    for (size_t c = 0; c < cand.size() && st == FE_OK; c++) {
+        const SpmvPlan &pl = cand[c];
+        const int g = grid_rows(n, pl);
+        for (int r = -1; r < reps; r++) {
+            if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = set_error(FE_EDEVICE, "event record failed");
+            FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(kBlock), 0, s>>>(sa, values, x, y)));
+        }
+        float ms = 0.0f;
+        if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = set_error(FE_EDEVICE, "autotune launch failed");
+            break;
+        }
+        const double us = 1000.0 * double(ms) / double(reps);
+        if (tried && int(c) < max_tried) tried[c] = fe_spmv_plan{pl.mode, pl.rpb, us};
+        if (n_tried) *n_tried = std::min(int(c) + 1, max_tried);
+        if (best < 0 || us < best_us) {
+            best = int(c);
+            best_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FE_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_stuned[struct_class(sa)] = cand[best];
+    }
+    if (chosen) *chosen = fe_spmv_plan{cand[best].mode, cand[best].rpb, best_us};
+    return FE_OK;
+}
+
+void spmv_plan_of_struct(const SpaceArgs &sa, fe_spmv_plan *plan, int32_t *cls)
+{
+    const SpmvPlan pl = struct_plan(sa);
+    if (plan) *plan = fe_spmv_plan{pl.mode, pl.rpb, 0.0};
+    if (cls) *cls = struct_class(sa);
 }
 
 // ---------------------------------------------------------------------------

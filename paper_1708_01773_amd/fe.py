@@ -29,7 +29,7 @@ EXPORTS = [
     "fe_spmv_autotune_query", "fe_spmv_autotune", "fe_spmv_tuning_reset", "fe_spmv_plan_of",
     "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_wait", "fe_server_solution",
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
-    "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh",
+    "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -155,6 +155,9 @@ def lib():
             "fe_pcg_solve_batch_mesh": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
                                         _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P), _c.c_double, _c.c_int32,
                                         _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
+            "fe_spmv_autotune_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _c.c_int32, _P, _c.c_size_t,
+                                      _c.POINTER(SpmvPlan), _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
+            "fe_spmv_plan_of_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
             "fe_server_create": [_c.c_size_t, _c.c_int32, _c.POINTER(_P)],
             "fe_server_submit": [_P, _c.POINTER(Request), _c.POINTER(_c.c_uint64)],
             "fe_server_poll": [_P, _c.c_uint64, _c.POINTER(Result)],
@@ -365,6 +368,32 @@ def spmv_autotune(csr, reps=20, stream=None):
                                   _c.byref(ch), _stream(stream)), "fe_spmv_autotune")
     d = lambda p: dict(mode=p.mode, rows_per_wave=p.rows_per_wave, us=p.us)
     return d(ch), [d(t) for t in tried[: nt.value]]
+
+
+def spmv_autotune_mesh(mesh, order, coeff, csr, reps=20, stream=None):
+    """Times every evaluated-pattern plan on csr (assembled on mesh) and keeps
+    the fastest for its row class; returns (chosen, tried)."""
+    import torch
+    q = _c.c_size_t()
+    _check(lib().fe_spmv_autotune_query(int(csr.n_rows), _c.byref(q)), "fe_spmv_autotune_query")
+    ws = torch.empty(max(q.value, 8), dtype=torch.uint8, device="cuda")
+    tried = (SpmvPlan * 16)()
+    nt = _c.c_int32()
+    ch = SpmvPlan()
+    _check(lib().fe_spmv_autotune_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), int(reps), _ptr(ws),
+                                       q.value, tried, 16, _c.byref(nt), _c.byref(ch), _stream(stream)),
+           "fe_spmv_autotune_mesh")
+    d = lambda p: dict(mode=p.mode, rows_per_wave=p.rows_per_wave, us=p.us)
+    return d(ch), [d(t) for t in tried[: nt.value]]
+
+
+def spmv_plan_of_mesh(mesh, order, coeff):
+    """(mode, rows_per_wave, row_class) of the evaluated-pattern traversal now."""
+    p = SpmvPlan()
+    c = _c.c_int32()
+    _check(lib().fe_spmv_plan_of_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(p), _c.byref(c)),
+           "fe_spmv_plan_of_mesh")
+    return p.mode, p.rows_per_wave, c.value
 
 
 def spmv_tuning_reset():

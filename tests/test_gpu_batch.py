@@ -204,3 +204,40 @@ def test_batch_with_evaluated_pattern_matches_single_bitwise():
     assert st == F.FE_OK
     for (x1, i1), xb, ib in zip(singles, xs, infos):
         assert ib["iters"] == i1["iters"] and torch.equal(xb, x1)
+
+
+def test_mesh_spmv_autotuner_picks_a_measured_plan_and_keeps_results():
+    import oracle as O
+    pair = Pair(3, [6, 5, 4], 2)
+    A = pair.gpu_assembly()
+    S = pair.system
+    x = np.random.Generator(np.random.PCG64(6)).standard_normal(A.n_rows)
+    xd = torch.from_numpy(x).cuda()
+    yo = O.spmv(S.rowptr, S.colind, S.values, x)
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x))
+    F.spmv_tuning_reset()
+    try:
+        untuned = F.spmv_plan_of_mesh(pair.mesh, pair.k, pair.coeff)
+        chosen, tried = F.spmv_autotune_mesh(pair.mesh, pair.k, pair.coeff, A.csr, reps=5)
+        say(f"[autotune mesh] untuned {untuned} chosen {chosen}")
+        assert len(tried) == 5 and chosen["us"] == min(t["us"] for t in tried)
+        assert F.spmv_plan_of_mesh(pair.mesh, pair.k, pair.coeff)[:2] == (chosen["mode"], chosen["rows_per_wave"])
+        y = torch.empty_like(xd)
+        F.spmv_mesh(pair.mesh, pair.k, pair.coeff, A.csr, xd, y)
+        torch.cuda.synchronize()
+        assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+        # every plan of a short-row class (3D Q1: 27 entries) includes the two-lane traversal
+        q1 = Pair(3, [5, 4, 4], 1)
+        A1 = q1.gpu_assembly()
+        ch1, tried1 = F.spmv_autotune_mesh(q1.mesh, 1, q1.coeff, A1.csr, reps=5)
+        assert len(tried1) == 6 and any(t["mode"] == 3 for t in tried1)
+        y1 = torch.empty(A1.n_rows, dtype=torch.float64, device="cuda")
+        x1 = torch.ones(A1.n_rows, dtype=torch.float64, device="cuda")
+        F.spmv_mesh(q1.mesh, 1, q1.coeff, A1.csr, x1, y1)
+        S1 = q1.system
+        y1o = O.spmv(S1.rowptr, S1.colind, S1.values, np.ones(A1.n_rows))
+        sc1 = O.spmv(S1.rowptr, S1.colind, np.abs(S1.values), np.ones(A1.n_rows))
+        assert np.all(np.abs(y1.cpu().numpy() - y1o) <= 1e-12 * sc1 + 1e-300)
+    finally:
+        F.spmv_tuning_reset()
+    assert F.spmv_plan_of_mesh(pair.mesh, pair.k, pair.coeff) == untuned
