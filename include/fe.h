@@ -158,13 +158,16 @@ fe_status fe_assemble(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_csr
 
 /* K3 alone: element matrices and loads (with lifting) into the workspace.
  * Layout of the workspace (elements of type double for FE_FP64, float
- * otherwise, then the loads as double):
- *   E[(c / cb) * nloc * nloc + a * nloc + b) * cb + c % cb]   (cb from fe_element_layout)
+ * otherwise, then the loads as double), cb and packed from fe_element_layout:
+ *   E[((c / cb) * ne + e) * cb + c % cb]
+ *     packed = 0: e = a * nloc + b, ne = nloc * nloc;
+ *     packed = 1 (Q1 scalar; element matrices are symmetric): only a <= b is
+ *       stored, e = a * nloc - a (a - 1) / 2 + (b - a), ne = nloc (nloc + 1) / 2;
  *   F[c * nloc + a]  starting at byte offset *load_offset. */
 fe_status fe_integrate(fe_mesh mesh, int32_t order, const fe_coeff *coeff, void *ws, size_t ws_bytes,
                        fe_stream stream);
 fe_status fe_element_layout(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int32_t *nloc,
-                            int32_t *cell_block, int32_t *elem_bytes, size_t *load_offset);
+                            int32_t *cell_block, int32_t *elem_bytes, size_t *load_offset, int32_t *packed);
 
 /* K5 alone: scatter of a workspace filled by fe_integrate into out. */
 fe_status fe_scatter(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_csr *out, const void *ws,

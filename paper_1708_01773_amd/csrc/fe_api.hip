@@ -302,7 +302,7 @@ fe_status fe_assemble_query(fe_mesh m, int32_t order, const fe_coeff *c, int64_t
 }
 
 fe_status fe_element_layout(fe_mesh m, int32_t order, const fe_coeff *c, int32_t *nloc, int32_t *cell_block,
-                            int32_t *elem_bytes, size_t *load_offset)
+                            int32_t *elem_bytes, size_t *load_offset, int32_t *packed)
 {
     fe_status st = check_coeff(m, order, c);
     if (st != FE_OK) return st;
@@ -313,6 +313,7 @@ fe_status fe_element_layout(fe_mesh m, int32_t order, const fe_coeff *c, int32_t
     if (cell_block) *cell_block = el.cb;
     if (elem_bytes) *elem_bytes = el.elem_bytes;
     if (load_offset) *load_offset = el.f_offset;
+    if (packed) *packed = el.packed;
     return FE_OK;
 }
 

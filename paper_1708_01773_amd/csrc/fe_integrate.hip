@@ -21,9 +21,11 @@ ElemLayout elem_layout(const SpaceArgs &sa, int precision)
     ElemLayout el{};
     const bool q1_scalar = sa.k == 1 && sa.ncomp == 1;
     el.cb = q1_scalar ? 64 : 1;
+    el.packed = q1_scalar ? 1 : 0;
+    el.ne = q1_scalar ? sa.nloc * (sa.nloc + 1) / 2 : sa.nloc * sa.nloc;
     el.elem_bytes = precision == FE_FP64 ? 8 : 4;
     const int64_t cells_pad = (sa.ncells + el.cb - 1) / el.cb * el.cb;
-    el.e_bytes = (size_t(cells_pad) * sa.nloc * sa.nloc * el.elem_bytes + 255) / 256 * 256;
+    el.e_bytes = (size_t(cells_pad) * el.ne * el.elem_bytes + 255) / 256 * 256;
     el.f_offset = el.e_bytes;
     el.total = el.f_offset + (size_t(sa.ncells) * sa.nloc * sizeof(double) + 255) / 256 * 256;
     return el;
@@ -240,16 +242,10 @@ __device__ __forceinline__ void k3_q1_body(const SpaceArgs &s, const MeshArgs &m
     const double unscale = 1.0 / (alpha * beta);
     const int64_t blk = cell / 64, lane = cell % 64;
     using Out = Acc;
-    Out *Eb = static_cast<Out *>(Ev) + blk * (NN * NN * 64) + lane;
-    int t = 0;
+    // packed upper triangle, entry t = (a, b), a <= b, in row-major order
+    Out *Eb = static_cast<Out *>(Ev) + blk * (NT * 64) + lane;
 #pragma unroll
-    for (int a = 0; a < NN; a++)
-#pragma unroll
-        for (int b = a; b < NN; b++, t++) {
-            const Out v = PREC == FE_FP64 ? acc[t] : Out(double(acc[t]) * unscale);
-            Eb[(a * NN + b) * 64] = v;
-            if (b != a) Eb[(b * NN + a) * 64] = v;
-        }
+    for (int t = 0; t < NT; t++) Eb[t * 64] = PREC == FE_FP64 ? acc[t] : Out(double(acc[t]) * unscale);
 #pragma unroll
     for (int a = 0; a < NN; a++) F[cell * NN + a] = fl[a];
 }
@@ -443,7 +439,8 @@ __global__ __launch_bounds__(256) void k3_tiled_kernel(SpaceArgs s, MeshArgs m, 
 // ---------------------------------------------------------------------------
 template <int DIM, typename ET>
 __global__ __launch_bounds__(64) void k3_lift_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p, const int32_t *cell_dofs,
-                                                     int cb, const ET *__restrict__ E, double *__restrict__ F)
+                                                     int cb, int packed, int ne, const ET *__restrict__ E,
+                                                     double *__restrict__ F)
 {
     const int64_t cell = blockIdx.x;
     const int nloc = s.nloc, k = s.k, k1 = k + 1, nc = s.ncomp;
@@ -465,8 +462,7 @@ __global__ __launch_bounds__(64) void k3_lift_kernel(SpaceArgs s, MeshArgs m, Pr
             geometry<DIM>(X, xi, J, Ji, xb);
             double u = p.aff[4 * c];
             for (int r = 0; r < DIM; r++) u += p.aff[4 * c + 1 + r] * xb[r];
-            const int64_t idx = ((cell / cb) * int64_t(nloc) * nloc + int64_t(a) * nloc + b) * cb + cell % cb;
-            lift += double(E[idx]) * u;
+            lift += double(E[elem_index(cell, a, b, nloc, cb, packed, ne)]) * u;
         }
         F[cell * nloc + a] -= lift;
     }
@@ -555,18 +551,18 @@ fe_status launch_lift(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs
         const double *E = static_cast<const double *>(ws);
         if (sa.dim == 3)
             hipLaunchKernelGGL((k3_lift_kernel<3, double>), dim3(sa.ncells), dim3(64), 0, s, sa, ma, pa, cell_dofs,
-                               el.cb, E, F);
+                               el.cb, el.packed, el.ne, E, F);
         else
             hipLaunchKernelGGL((k3_lift_kernel<2, double>), dim3(sa.ncells), dim3(64), 0, s, sa, ma, pa, cell_dofs,
-                               el.cb, E, F);
+                               el.cb, el.packed, el.ne, E, F);
     } else {
         const float *E = static_cast<const float *>(ws);
         if (sa.dim == 3)
             hipLaunchKernelGGL((k3_lift_kernel<3, float>), dim3(sa.ncells), dim3(64), 0, s, sa, ma, pa, cell_dofs,
-                               el.cb, E, F);
+                               el.cb, el.packed, el.ne, E, F);
         else
             hipLaunchKernelGGL((k3_lift_kernel<2, float>), dim3(sa.ncells), dim3(64), 0, s, sa, ma, pa, cell_dofs,
-                               el.cb, E, F);
+                               el.cb, el.packed, el.ne, E, F);
     }
     FE_HIP(hipGetLastError());
     return FE_OK;

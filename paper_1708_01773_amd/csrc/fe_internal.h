@@ -82,6 +82,8 @@ struct RefTables {
 // Layout of the element workspace written by K3 and read by K5.
 struct ElemLayout {
     int32_t cb;          // cells per block of the blocked layout
+    int32_t packed;      // 1: only the upper triangle a <= b is stored (Q1 scalar)
+    int32_t ne;          // entries stored per cell (nloc^2, or nloc (nloc + 1) / 2 when packed)
     int32_t elem_bytes;  // 8 (double) or 4 (float)
     size_t e_bytes;      // bytes of E (padded to 256)
     size_t f_offset;     // byte offset of F
@@ -261,6 +263,19 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks)
     // XCD x owns logical blocks [start_x, start_x + per + (x < rem))
     int64_t start = x * per + (x < rem ? x : rem);
     return start + j;
+}
+
+// Position of element entry (a, b) of cell c in the element workspace.
+__host__ __device__ __forceinline__ int64_t elem_index(int64_t c, int a, int b, int nloc, int cb, int packed, int ne)
+{
+    int e;
+    if (packed) {
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        e = lo * nloc - lo * (lo - 1) / 2 + (hi - lo);
+    } else {
+        e = a * nloc + b;
+    }
+    return ((c / cb) * int64_t(ne) + e) * cb + c % cb;
 }
 
 // Job of block blockIdx.x in a launch whose job j owns the blocks

@@ -13,7 +13,8 @@
 // stored, which saves its 4-8 bytes per element entry of HBM traffic.
 //
 // Two traversals, matched to the two element layouts written by K3:
-//  * blocked layout (Q1 scalar, E[c/64][a*8+b][c%64]): one thread per row;
+//  * blocked layout (Q1 scalar, upper triangle packed, E[c/64][t(a,b)][c%64]):
+//    one thread per row;
 //    consecutive threads own consecutive rows, whose cells are consecutive,
 //    so every element read of a wave is contiguous.  The cells around the
 //    row's node and their local columns are unrolled at compile time into
@@ -87,9 +88,9 @@ __device__ __forceinline__ RowGeom row_geom(const SpaceArgs &s, int64_t row)
     return g;
 }
 
-// Sum of the contributions to entry (row g, column node J, component cc),
-// ascending in cell id.  NC components, CB cells per block of E.
-template <int NC, int CB, typename ET>
+// Sum of the contributions to entry (row g, column node J, component cc) of
+// the cell-major layout E[c][a][b], ascending in cell id.  NC components.
+template <int NC, typename ET>
 __device__ __forceinline__ double entry_sum(const SpaceArgs &s, const RowGeom &g, int64_t J0, int64_t J1, int64_t J2,
                                            int cc, const ET *__restrict__ E)
 {
@@ -110,12 +111,7 @@ __device__ __forceinline__ double entry_sum(const SpaceArgs &s, const RowGeom &g
                 const int64_t cell = e0 + n0 * (e1 + n1 * int64_t(e2));
                 const int la = (a0 + k1 * (a1 + k1 * a2)) * NC + g.c;
                 const int lb = (b0 + k1 * (b1 + k1 * b2)) * NC + cc;
-                int64_t idx;
-                if (CB == 1)
-                    idx = cell * nl2 + int64_t(la) * nloc + lb;
-                else
-                    idx = ((cell / CB) * nl2 + int64_t(la) * nloc + lb) * CB + cell % CB;
-                sum += double(E[idx]);
+                sum += double(E[cell * nl2 + int64_t(la) * nloc + lb]);
             }
         }
     }
@@ -163,6 +159,7 @@ __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restr
                                            double *__restrict__ rhs, double *__restrict__ dinv, int64_t bid)
 {
     constexpr int NN = 1 << DIM;                // nodes per cell
+    constexpr int NT = NN * (NN + 1) / 2;       // stored entries per cell (upper triangle)
     constexpr int NS = DIM == 3 ? 27 : 9;       // stencil entries
     constexpr int CB = 64;                      // cells per block of E
     __shared__ double stage[4][64 * NS];
@@ -189,12 +186,15 @@ __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restr
             if (e0 < 0 || e0 >= n0 || e1 < 0 || e1 >= n1 || e2 < 0 || e2 >= n2) continue;
             const int64_t cell = e0 + n0 * (e1 + n1 * e2);
             const int a = -d0 - 2 * d1 - 4 * d2;
-            const ET *__restrict__ Ec = E + (cell / CB) * (NN * NN * CB) + (cell % CB) + a * NN * CB;
+            // packed upper triangle: entry (min(a, b), max(a, b))
+            const ET *__restrict__ Ec = E + (cell / CB) * (NT * CB) + (cell % CB);
 #pragma unroll
             for (int b = 0; b < NN; b++) {
                 const int s0 = d0 + (b & 1) + 1, s1 = d1 + ((b >> 1) & 1) + 1;
                 const int s2 = DIM == 3 ? d2 + ((b >> 2) & 1) + 1 : 0;
-                acc[(s2 * 3 + s1) * 3 + s0] += double(Ec[b * CB]);
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                const int t = lo * NN - lo * (lo - 1) / 2 + (hi - lo);
+                acc[(s2 * 3 + s1) * 3 + s0] += double(Ec[t * CB]);
             }
             fsum += F[cell * NN + a];
         }
@@ -267,7 +267,7 @@ __device__ __forceinline__ void k5_entries_body(const SpaceArgs &s, const ET *__
         for (int pos = lane; pos < len; pos += 64) {
             const int j0 = x / NC, cc = x - j0 * NC;
             const int64_t J0 = g.cl0 + j0, J1 = g.cl1 + j1, J2 = g.cl2 + j2;
-            const double v = entry_sum<NC, 1>(s, g, J0, J1, J2, cc, E);
+            const double v = entry_sum<NC>(s, g, J0, J1, J2, cc, E);
             values[g.start + pos] = v;
             if (J0 == g.I0 && J1 == g.I1 && J2 == g.I2 && cc == g.c) dinv[row] = 1.0 / v;
             x += 64;

@@ -125,7 +125,8 @@ def lib():
             "fe_assemble": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
             "fe_integrate": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _c.c_size_t, _P],
             "fe_element_layout": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_int32),
-                                  _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_size_t)],
+                                  _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_size_t),
+                                  _c.POINTER(_c.c_int32)],
             "fe_scatter": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
             "fe_cell_dofs": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _P],
             "fe_permutation": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _P],
@@ -268,10 +269,11 @@ def assemble_query(mesh, order, coeff):
 
 
 def element_layout(mesh, order, coeff):
-    nloc, cb, eb, off = _c.c_int32(), _c.c_int32(), _c.c_int32(), _c.c_size_t()
+    """(nloc, cells per block, element bytes, load offset, packed upper triangle)."""
+    nloc, cb, eb, off, pk = _c.c_int32(), _c.c_int32(), _c.c_int32(), _c.c_size_t(), _c.c_int32()
     _check(lib().fe_element_layout(mesh.handle, int(order), _c.byref(coeff), _c.byref(nloc), _c.byref(cb),
-                                   _c.byref(eb), _c.byref(off)), "fe_element_layout")
-    return nloc.value, cb.value, eb.value, off.value
+                                   _c.byref(eb), _c.byref(off), _c.byref(pk)), "fe_element_layout")
+    return nloc.value, cb.value, eb.value, off.value, pk.value
 
 
 def csr_struct(n_rows, nnz, rowptr=None, colind=None, values=None, rhs=None, dinv=None):

@@ -52,14 +52,23 @@ class Pair:
 def element_matrices(pair, A, cells):
     """Element matrices of the given cells read from the K3 workspace."""
     import torch
-    nloc, cb, eb, off = F.element_layout(pair.mesh, pair.k, pair.coeff)
+    nloc, cb, eb, off, packed = F.element_layout(pair.mesh, pair.k, pair.coeff)
     dt = torch.float64 if eb == 8 else torch.float32
     ncells = pair.P.ncells
     ncells_pad = (ncells + cb - 1) // cb * cb
-    E = A.ws[: ncells_pad * nloc * nloc * eb].view(dt).view(ncells_pad // cb, nloc * nloc, cb)
+    ne = nloc * (nloc + 1) // 2 if packed else nloc * nloc
+    E = A.ws[: ncells_pad * ne * eb].view(dt).view(ncells_pad // cb, ne, cb)
     out = []
     for c in cells:
-        out.append(E[c // cb, :, c % cb].double().cpu().numpy().reshape(nloc, nloc))
+        e = E[c // cb, :, c % cb].double().cpu().numpy()
+        if packed:  # upper triangle, row-major
+            M = np.zeros((nloc, nloc))
+            iu = np.triu_indices(nloc)
+            M[iu] = e
+            M = M + np.triu(M, 1).T
+            out.append(M)
+        else:
+            out.append(e.reshape(nloc, nloc))
     Fl = A.ws[off: off + ncells * nloc * 8].view(torch.float64).view(ncells, nloc)
     return out, Fl.cpu().numpy()
 
