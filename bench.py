@@ -199,17 +199,22 @@ def batch_form(args, F, torch):
         f"class {c}: mode {t['chosen']['mode']} rpw {t['chosen']['rows_per_wave']}" for c, t in tuned.items()),
         file=sys.stderr, flush=True)
     ref64, ref32 = {}, {}
-    seq64 = BT.run_sequential([BT.make_problem(i, n, k, "fp64") for i, (n, k) in enumerate(sample)], rtol, maxit,
-                              keep=lambda i, x: ref64.__setitem__(i, x.clone()))
-    print(f"[bench] batch form: sequential FP64 {seq64['assemble_s'] + seq64['solve_s']:.2f} s", file=sys.stderr,
-          flush=True)
-    seq32 = BT.run_sequential(run.problems, rtol, maxit, keep=lambda i, x: ref32.__setitem__(i, x.clone()))
-    print(f"[bench] batch form: sequential FP32 {seq32['assemble_s'] + seq32['solve_s']:.2f} s", file=sys.stderr,
-          flush=True)
+    if args.batch_no_sequential:
+        seq64 = seq32 = None
+    else:
+        seq64 = BT.run_sequential([BT.make_problem(i, n, k, "fp64") for i, (n, k) in enumerate(sample)], rtol, maxit,
+                                  keep=lambda i, x: ref64.__setitem__(i, x.clone()))
+        print(f"[bench] batch form: sequential FP64 {seq64['assemble_s'] + seq64['solve_s']:.2f} s", file=sys.stderr,
+              flush=True)
+        seq32 = BT.run_sequential(run.problems, rtol, maxit, keep=lambda i, x: ref32.__setitem__(i, x.clone()))
+        print(f"[bench] batch form: sequential FP32 {seq32['assemble_s'] + seq32['solve_s']:.2f} s", file=sys.stderr,
+              flush=True)
     same = [True]
     err = [0.0]
 
     def keep(i, x):
+        if seq32 is None:
+            return
         same[0] = same[0] and torch.equal(x, ref32[i])
         r = ref64[i]
         if r.numel():
@@ -217,7 +222,7 @@ def batch_form(args, F, torch):
 
     res = run.run(rtol, maxit, keep=keep)
     t_b = res["assemble_s"] + res["solve_s"]
-    t_s = seq32["assemble_s"] + seq32["solve_s"]
+    t_s = seq32["assemble_s"] + seq32["solve_s"] if seq32 else None
     print(f"[bench] batch form: batched {t_b:.2f} s (set-up {res['setup_s']:.2f} s)", file=sys.stderr, flush=True)
     iters = [i["iters"] for i in res["infos"]]
     return {
@@ -230,11 +235,12 @@ def batch_form(args, F, torch):
                     "setup_s": res["setup_s"], "problems_per_s": len(sample) / t_b,
                     "elements_per_s": run.cells / t_b},
         "sequential_same_precision": {"s": t_s, "assemble_s": seq32["assemble_s"], "solve_s": seq32["solve_s"],
-                                      "problems_per_s": len(sample) / t_s},
-        "sequential_plain_fp64": {"s": seq64["assemble_s"] + seq64["solve_s"]},
-        "speedup_vs_sequential": t_s / t_b,
-        "bitwise_equal_to_sequential": bool(same[0]),
-        "max_rel_error_vs_plain_fp64_solution": err[0],
+                                      "problems_per_s": len(sample) / t_s} if seq32 else None,
+        "sequential_plain_fp64": {"s": seq64["assemble_s"] + seq64["solve_s"]} if seq64 else None,
+        "speedup_vs_sequential": t_s / t_b if t_s else None,
+        "bitwise_equal_to_sequential": bool(same[0]) if seq32 else None,
+        "max_rel_error_vs_plain_fp64_solution": err[0] if seq64 else None,
+        "waves_detail": [{"problems": len(w), "bytes": sum(run.sizes[i] for i in w)} for w in run.waves],
         "autotuned_spmv": {f"order {t['matrix']['order']}": {
             "mode": t["chosen"]["mode"], "rows_per_wave": t["chosen"]["rows_per_wave"], "us": t["chosen"]["us"],
             "tried_us": [round(x["us"], 2) for x in t["tried"]]} for c, t in tuned.items()},
@@ -324,6 +330,8 @@ def main():
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="problems of the 512-problem batch run by the batching form (0 = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0, help="device memory per batch wave")
+    ap.add_argument("--batch-no-sequential", action="store_true",
+                    help="batching form: skip the one-by-one comparison runs (for the full 512-problem batch)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving form (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="arrival rate of the drawn stream (1/s)")
     ap.add_argument("--serve-max-dofs", type=int, default=1000000, help="largest request kept in the sample")
