@@ -302,15 +302,22 @@ fe_status fe_spmv_autotune(const fe_csr *A, int32_t reps, void *ws, size_t ws_by
 fe_status fe_spmv_tuning_reset(void);
 /* The same for the evaluated-pattern traversal of fe_spmv_mesh /
  * fe_pcg_solve_mesh / fe_pcg_solve_batch_mesh: plans are modes 2 (lanes per
- * row, rows_per_wave runs) and 3 (short rows, two lanes per row; rows_per_wave
- * reports the longest row), timed on A assembled on (mesh, order, coeff); the
- * fastest becomes the plan of every mesh system with the same longest row and
- * component count.  ws: fe_spmv_autotune_query(A->n_rows) bytes. */
+ * row, rows_per_wave runs), 3 (short rows, two lanes per row; rows_per_wave
+ * reports the longest row) and, for the Q1 scalar pattern, 4 (the values of 32
+ * rows and the runs of x they touch staged in LDS with wide loads; two lanes
+ * per row in the order of mode 3, so modes 3 and 4 give bitwise the same
+ * products), timed on A assembled on (mesh, order, coeff); the fastest
+ * becomes the plan of every mesh system with the same longest row and
+ * component count.  ws: fe_spmv_autotune_query(A->n_rows) bytes.
+ * fe_spmv_plan_set_mesh makes `plan` (mode and rows_per_wave of one of the
+ * plans the autotuner would time; us is ignored) the plan of that class
+ * without timing; FE_EINVAL for any other plan. */
 fe_status fe_spmv_autotune_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A, int32_t reps,
                                 void *ws, size_t ws_bytes, fe_spmv_plan *tried, int32_t max_tried, int32_t *n_tried,
                                 fe_spmv_plan *chosen, fe_stream stream);
 fe_status fe_spmv_plan_of_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_spmv_plan *plan,
                                int32_t *row_class);
+fe_status fe_spmv_plan_set_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_spmv_plan *plan);
 /* The plan a matrix of n_rows rows and nnz entries gets now, and its class. */
 fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32_t *row_class);
 

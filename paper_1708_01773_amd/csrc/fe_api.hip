@@ -686,6 +686,14 @@ fe_status fe_spmv_plan_of_mesh(fe_mesh m, int32_t order, const fe_coeff *c, fe_s
     return FE_OK;
 }
 
+fe_status fe_spmv_plan_set_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_spmv_plan *plan)
+{
+    if (!plan) return set_error(FE_EINVAL, "null plan");
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    return spmv_plan_set_struct(m->space.args, *plan);
+}
+
 fe_status fe_spmv_tuning_reset(void)
 {
     spmv_tuning_reset();

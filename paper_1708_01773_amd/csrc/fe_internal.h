@@ -43,6 +43,7 @@ struct AxisTab {
     const int64_t *P;   // device, f entries
     int64_t lo, f, N, T;  // first free index, number of free indices, last node index, sum of w
     int32_t n;            // cells along the axis
+    double finv;          // 1 / f (0 when f = 0)
 };
 
 // Everything kernels need about a (mesh, order, problem, Dirichlet faces).
@@ -221,6 +222,7 @@ void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls);
 fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int reps, void *ws, size_t ws_bytes,
                                fe_spmv_plan *tried, int max_tried, int *n_tried, fe_spmv_plan *chosen, hipStream_t s);
 void spmv_plan_of_struct(const SpaceArgs &sa, fe_spmv_plan *plan, int32_t *cls);
+fe_status spmv_plan_set_struct(const SpaceArgs &sa, const fe_spmv_plan &plan);
 size_t refine_ws_bytes(int64_t n);
 fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s);
 fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,

@@ -130,6 +130,7 @@ fe_status build_space(fe_mesh mesh, int k, int ncomp, uint32_t faces, Space &sp,
         const bool lo_fixed = active && ((faces >> (2 * r)) & 1u);
         const bool hi_fixed = active && ((faces >> (2 * r + 1)) & 1u);
         axis_table(t.n, t.N, k, lo_fixed, hi_fixed, cl[r], w[r], P[r], t.lo, t.f, t.T);
+        t.finv = t.f > 0 ? 1.0 / double(t.f) : 0.0;
         total += 3 * t.f;
     }
     int64_t nfree_nodes = a.ax[0].f * a.ax[1].f * a.ax[2].f;

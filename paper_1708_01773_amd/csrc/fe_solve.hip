@@ -35,9 +35,27 @@ namespace fe {
 
 constexpr int kBlock = 512;
 constexpr int kWaves = kBlock / 64;
-constexpr int kGrid = 1024;     // blocks of every solver kernel (each owns a contiguous chunk)
+constexpr int kGrid = 1024;     // most blocks of a CSR or lanes-per-row kernel (each owns a contiguous chunk)
+constexpr int kPartMax = 32768; // most blocks of a row kernel of the Q1 traversal (one partial each)
+constexpr int kGridE = 256;     // most blocks of the vector kernels (update, dir)
 constexpr int kHist = 4096;     // CG coefficients kept for the Lanczos estimates
 constexpr int kWaveCap = 256;   // products staged in LDS per wave (2 KB)
+
+// Device pointers read from a problem table are generic pointers; naming
+// them global lets the compiler use global loads and stores, which do not
+// count against the LDS counter the way flat accesses do.
+#define FE_GLOBAL __attribute__((address_space(1)))
+typedef double fe_dpair __attribute__((ext_vector_type(2)));  // 16-byte access of two doubles
+template <typename T>
+__device__ __forceinline__ const FE_GLOBAL T *as_global(const T *p)
+{
+    return (const FE_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ FE_GLOBAL T *as_global(T *p)
+{
+    return (FE_GLOBAL T *)p;
+}
 
 struct PcgState {
     double rho[2];  // rho_j in slot j & 1
@@ -49,9 +67,10 @@ struct PcgState {
 
 struct PcgWs {
     PcgState *st;
-    double *p1;    // kGrid partials of p.q
+    double *p1;    // ps partials of p.q (one per block of the row kernel)
     double *p2;    // 2 x kGrid partials of r.z, r.r
-    double *p3;    // 3 x kGrid partials of the initial r.z, r.r, b.b (and the final residual)
+    double *p3;    // 3 x ps partials of the initial r.z, r.r, b.b (and the final residual)
+    int32_t ps;    // partial slots of the row kernels
     double *hist;  // 2 x kHist (alpha, beta)
     double *r, *p, *q;
 };
@@ -74,17 +93,26 @@ struct PcgProb {
 // How a CSR matrix is traversed.
 struct SpmvPlan {
     int mode;  // 0: wave-level CSR-stream, 1: wave per row, 2: structured (pattern evaluated),
-               // 3: structured short rows, two lanes per row (rpb = longest row)
+               // 3: structured short rows, two lanes per row (rpb = longest row),
+               // 4: structured Q1 scalar rows, values and x runs staged in LDS (rpb = longest row)
     int nc = 1;  // components (mode 2)
     int rpb;   // rows per wave-iteration (stream mode)
     int lanes; // lanes per row
 };
 
 
+// Partial slots of the row kernels of an n-row system: kGrid, or one per
+// block of the Q1 traversal (128 rows each) up to kPartMax.
+static int32_t part_slots(int64_t n)
+{
+    return int32_t(std::max<int64_t>(kGrid, std::min<int64_t>(kPartMax, (n + 127) / 128)));
+}
+
 size_t pcg_ws_bytes(int64_t n)
 {
-    return align256(sizeof(PcgState)) + 6 * align256(kGrid * sizeof(double)) + align256(2 * kHist * sizeof(double)) +
-           3 * align256(size_t(n) * sizeof(double));
+    const size_t ps = size_t(part_slots(n));
+    return align256(sizeof(PcgState)) + 4 * align256(ps * sizeof(double)) + 2 * align256(kGrid * sizeof(double)) +
+           align256(2 * kHist * sizeof(double)) + 3 * align256(size_t(n) * sizeof(double));
 }
 
 static PcgWs carve(void *ws, int64_t n)
@@ -93,12 +121,13 @@ static PcgWs carve(void *ws, int64_t n)
     PcgWs w;
     w.st = reinterpret_cast<PcgState *>(p);
     p += align256(sizeof(PcgState));
+    w.ps = part_slots(n);
     w.p1 = reinterpret_cast<double *>(p);
-    p += align256(kGrid * sizeof(double));
+    p += align256(size_t(w.ps) * sizeof(double));
     w.p2 = reinterpret_cast<double *>(p);
     p += 2 * align256(kGrid * sizeof(double));
     w.p3 = reinterpret_cast<double *>(p);
-    p += 3 * align256(kGrid * sizeof(double));
+    p += 3 * align256(size_t(w.ps) * sizeof(double));
     w.hist = reinterpret_cast<double *>(p);
     p += align256(2 * kHist * sizeof(double));
     w.r = reinterpret_cast<double *>(p);
@@ -161,11 +190,12 @@ __device__ __forceinline__ double butterfly(double v)
     return v;
 }
 
-// Sum over the block in a fixed order; the result is returned in every thread.
-template <int NV>
+// Sum over a block of B threads in a fixed order; the result is returned in
+// every thread.
+template <int NV, int B = kBlock>
 __device__ __forceinline__ void block_sum_all(double (&v)[NV])
 {
-    __shared__ double sh[NV][kBlock / 64];
+    __shared__ double sh[NV][B / 64];
     __shared__ double res[NV];
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
 #pragma unroll
@@ -176,7 +206,7 @@ __device__ __forceinline__ void block_sum_all(double (&v)[NV])
     __syncthreads();
     if (threadIdx.x < NV) {
         double s = 0.0;
-        for (int w = 0; w < kBlock / 64; w++) s += sh[threadIdx.x][w];
+        for (int w = 0; w < B / 64; w++) s += sh[threadIdx.x][w];
         res[threadIdx.x] = s;
     }
     __syncthreads();
@@ -185,26 +215,37 @@ __device__ __forceinline__ void block_sum_all(double (&v)[NV])
     __syncthreads();
 }
 
-// Block partials of v -> part[t * kGrid + blockIdx.x].
+// Block partials of v -> part[t * stride + blockIdx.x].
 template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], double *part)
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *part, int stride)
 {
     block_sum_all<NV>(v);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int t = 0; t < NV; t++) part[t * kGrid + blockIdx.x] = v[t];
+        for (int t = 0; t < NV; t++) part[t * stride + blockIdx.x] = v[t];
 }
 
-// Grand totals of partials written by a previous kernel of `nparts` blocks;
-// identical in every thread of every block.
+// Grand totals of partials part[t * stride + b], b < nparts, written by a
+// previous kernel of `nparts` blocks; identical in every thread of every
+// block.  A thread sums its partials b = tid + j kBlock into accumulator
+// j mod 8 (eight loads in flight) and adds the eight in a fixed tree.
 template <int NV>
-__device__ __forceinline__ void reduce_partials(const double *part, int nparts, double (&tot)[NV])
+__device__ __forceinline__ void reduce_partials(const double *gpart, int nparts, int stride, double (&tot)[NV])
 {
+    const FE_GLOBAL double *__restrict__ part = as_global(gpart);
 #pragma unroll
     for (int t = 0; t < NV; t++) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nparts; b += kBlock) s += part[t * kGrid + b];
-        tot[t] = s;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = threadIdx.x;
+        for (; b + 7 * kBlock < nparts; b += 8 * kBlock) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = part[t * stride + b + u * kBlock];
+#pragma unroll
+            for (int u = 0; u < 8; u++) a[u] += v[u];
+        }
+        for (int u = 0; b < nparts; b += kBlock, u++) a[u] += part[t * stride + b];
+        tot[t] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     block_sum_all<NV>(tot);
 }
@@ -213,10 +254,14 @@ __device__ __forceinline__ void reduce_partials(const double *part, int nparts, 
 // Row traversal
 // ---------------------------------------------------------------------------
 template <int L, typename VT>
-__device__ __forceinline__ double row_dot(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
-                                          const VT *__restrict__ val, const double *__restrict__ x, int64_t row,
+__device__ __forceinline__ double row_dot(const int64_t *__restrict__ growptr, const int32_t *__restrict__ gcolind,
+                                          const VT *__restrict__ gval, const double *__restrict__ gx, int64_t row,
                                           int lane)
 {
+    const FE_GLOBAL int64_t *__restrict__ rowptr = as_global(growptr);
+    const FE_GLOBAL int32_t *__restrict__ colind = as_global(gcolind);
+    const FE_GLOBAL VT *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
     const int64_t b = rowptr[row], e = rowptr[row + 1];
     double s = 0.0;
     int64_t j = b + lane;
@@ -257,10 +302,14 @@ __device__ __forceinline__ void wave_lds_sync()
 // the same lane order.
 // lb / nb: this block's index among the nb blocks working on the matrix.
 template <int RPW, typename VT, typename Fn>
-__device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__restrict__ rowptr,
-                                                 const int32_t *__restrict__ colind, const VT *__restrict__ val,
-                                                 const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
+__device__ __forceinline__ void for_rows_wstream(int64_t n, const int64_t *__restrict__ growptr,
+                                                 const int32_t *__restrict__ gcolind, const VT *__restrict__ gval,
+                                                 const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
+    const FE_GLOBAL int64_t *__restrict__ rowptr = as_global(growptr);
+    const FE_GLOBAL int32_t *__restrict__ colind = as_global(gcolind);
+    const FE_GLOBAL VT *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
     constexpr int LW = 64 / RPW;
     __shared__ double prod[kWaves][kWaveCap];
     double *my = prod[threadIdx.x / 64];
@@ -392,9 +441,11 @@ __device__ __forceinline__ void axis_row(const AxisClosed &A, int32_t k, double 
 // receive it by shuffles.  Each row is summed in lane order (positions sub,
 // sub + LW, ... per lane, then a butterfly over the LW lanes).
 template <int RPW, int NC, typename Fn>
-__device__ __forceinline__ void for_rows_struct(const SpaceArgs &s, const double *__restrict__ val,
-                                                const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
+__device__ __forceinline__ void for_rows_struct(const SpaceArgs &s, const double *__restrict__ gval,
+                                                const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
     constexpr int LW = 64 / RPW;
     const int lane = threadIdx.x % 64, g = lane / LW, sub = lane % LW;
     const int64_t n = s.n_rows;
@@ -513,9 +564,11 @@ __device__ __forceinline__ void for_rows_struct(const SpaceArgs &s, const double
 // neighbours in memory, so they coalesce too.  A row is the sum of its two
 // half sums, each taken in position order.
 template <int LMAX, int NC, typename Fn>
-__device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double *__restrict__ val,
-                                               const double *__restrict__ x, int64_t lb, int64_t nb, Fn f)
+__device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double *__restrict__ gval,
+                                               const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
     constexpr int RW = 32, H = (LMAX + 1) / 2, CAP = RW * LMAX, CH = (CAP + 63) / 64;
     __shared__ double stage[kWaves][CAP];
     double *my = stage[threadIdx.x / 64];
@@ -598,11 +651,156 @@ __device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double 
     }
 }
 
+// Rows of the lowest-order scalar pattern (Q1, one component; longest row
+// 3^d): row r couples the free nodes of the 3^d box around its node, so its
+// columns are r + dx + f0 dy + f0 f1 dz for the offsets d in {-1, 0, 1}^d that
+// stay in the free range.  A wave step takes 32 consecutive rows.  Their
+// values, contiguous in CSR, are loaded with 16-byte loads into the wave's LDS
+// slice, and every entry of x they touch lies in 3^(d-1) runs of 34
+// consecutive unknowns (the rows' own line of nodes and its neighbour lines in
+// y and z, widened by one node each side), which are loaded into LDS too: a
+// 3D step issues 7 + 5 wide loads instead of one load per entry.  Two lanes
+// per row sum the two halves of its positions in position order and the row
+// is lower half + upper half, the order of the short-row traversal, so both
+// give bitwise the same products.  Blocks of kQ1Block threads.  Plan mode 4;
+// mode 5 is its instantiation with one step per wave, used whenever the
+// partial slots cover that many blocks.
+constexpr int kQ1Block = 256, kQ1Waves = kQ1Block / 64;
+
+
+template <int DIM>
+struct Q1Step {
+    static constexpr int L = DIM == 3 ? 27 : 9;  // longest row
+    static constexpr int RW = 32;                // rows per wave step
+    static constexpr int H = (L + 1) / 2;        // positions per lane
+    static constexpr int CAP = RW * L;           // most values of a step
+    static constexpr int PCAP = CAP / 2 + 1;     // 16-byte slots (the step may start at an odd index)
+    static constexpr int PCH = (PCAP + 63) / 64;
+    static constexpr int SEG = RW + 2;           // unknowns of one run of x
+    static constexpr int NSEG = DIM == 3 ? 9 : 3;
+    static constexpr int XS = NSEG * SEG;
+    static constexpr int XCH = (XS + 63) / 64;
+};
+
+template <int DIM, bool ONE, typename Fn>
+__device__ __forceinline__ void for_rows_q1(const SpaceArgs &s, const double *__restrict__ gval,
+                                            const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+{
+    using S = Q1Step<DIM>;
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
+    __shared__ __align__(16) double vst[kQ1Waves][2 * S::PCAP];
+    __shared__ double xst[kQ1Waves][S::XS];
+    double *mv = vst[threadIdx.x / 64];
+    double *mx = xst[threadIdx.x / 64];
+    const int lane = threadIdx.x % 64, rl = lane % S::RW, h = lane / S::RW;
+    const int64_t n = s.n_rows;
+    const int64_t nw = nb * kQ1Waves, lw = lb * kQ1Waves + threadIdx.x / 64;
+    const int64_t runs = (n + S::RW - 1) / S::RW;
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * 2 + A[r].lo;  // unclipped widths below lo (k = 1)
+    }
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const double f0inv = s.ax[0].finv, f1inv = s.ax[1].finv;
+    const int64_t T0 = s.ax[0].T, T1 = s.ax[1].T;
+    auto step = [&](int64_t run) {
+        const int64_t r0 = run * S::RW, row = r0 + rl;
+        const bool live = row < n;
+        int64_t start = 0;
+        int32_t len = 0, wx = 1, w1 = 1, e0 = 0, e1 = 0, e2 = 0;
+        if (live) {
+            const int32_t r32 = int32_t(row);
+            const int32_t q = div_exact(r32, f0, f0inv), t0 = r32 - q * f0;
+            const int32_t t2 = div_exact(q, f1, f1inv), t1 = q - t2 * f1;
+            int32_t w0, w2, cl0, cl1, cl2, P0, P1, P2;
+            axis_row(A[0], 1, 1.0, A[0].lo + t0, w0, cl0, P0);
+            axis_row(A[1], 1, 1.0, A[1].lo + t1, w1, cl1, P1);
+            axis_row(A[2], 1, 1.0, A[2].lo + t2, w2, cl2, P2);
+            start = int64_t(P2) * T1 * T0 + int64_t(w2) * P1 * T0 + int64_t(w2 * w1) * P0;
+            wx = w0;
+            len = w0 * w1 * w2;
+            // slot of the first column along each axis: offset of the box's low end + 1
+            e0 = cl0 - (A[0].lo + t0) + 1;
+            e1 = cl1 - (A[1].lo + t1) + 1;
+            e2 = DIM == 3 ? cl2 - (A[2].lo + t2) + 1 : 0;
+        }
+        const int nv = int(n - r0 < S::RW ? n - r0 : S::RW);
+        const int64_t base = __shfl(start, 0);
+        const int total = int(__shfl(start, nv - 1) - base) + __shfl(len, nv - 1);
+        double xs[S::XCH];
+#pragma unroll
+        for (int u = 0; u < S::XCH; u++) {
+            // slot i: unknown r0 - 1 + kk + f0 dy + f0 f1 dz of run (dy, dz)
+            const int i = lane + 64 * u;
+            const int sg = i / S::SEG, kk = i - sg * S::SEG;
+            const int dy = sg % 3 - 1, dz = sg / 3 - 1;
+            int64_t a = r0 + kk - 1 + dy * f0 + (DIM == 3 ? int64_t(dz) * f0 * f1 : 0);
+            a = a < 0 ? 0 : (a >= n ? n - 1 : a);  // slots past either end are never read
+            xs[u] = x[a];
+        }
+        // values [base, base + total) from the even index at or below base
+        const int64_t abase = base & ~int64_t(1);
+        const int lead = int(base - abase), tot = lead + total;
+        fe_dpair vv[S::PCH];
+#pragma unroll
+        for (int u = 0; u < S::PCH; u++) {
+            const int i = lane + 64 * u;
+            const int64_t e = abase + 2 * int64_t(i);
+            if (2 * i + 1 < tot) vv[u] = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(val + e);
+            else if (2 * i < tot) vv[u] = fe_dpair{val[e], 0.0};
+            else vv[u] = fe_dpair{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < S::XCH; u++)
+            if (lane + 64 * u < S::XS) mx[lane + 64 * u] = xs[u];
+#pragma unroll
+        for (int u = 0; u < S::PCH; u++)
+            if (lane + 64 * u < S::PCAP) reinterpret_cast<fe_dpair *>(mv)[lane + 64 * u] = vv[u];
+        wave_lds_sync();
+        // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8] (p < 32, d <= 3)
+        const uint32_t m0 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
+        const uint32_t m1 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
+        const int off = int(start - base) + lead;
+        double sum = 0.0;
+#pragma unroll
+        for (int t = 0; t < S::H; t++) {
+            const int32_t pos = h * S::H + t;
+            const bool ok = pos < len;
+            const int32_t pc = ok ? pos : 0;
+            const int32_t qy = int32_t((uint32_t(pc) * m0) >> 20);
+            const int32_t j0 = pc - qy * wx;
+            const int32_t j2 = int32_t((uint32_t(qy) * m1) >> 20);
+            const int32_t j1 = qy - j2 * w1;
+            const int32_t sg = DIM == 3 ? (e1 + j1) + 3 * (e2 + j2) : e1 + j1;
+            sum += (ok ? mv[off + pc] : 0.0) * mx[sg * S::SEG + rl + e0 + j0];
+        }
+        const double upper = __shfl(sum, (lane + S::RW) % 64);
+        if (h == 0 && live) f(row, sum + upper);
+        wave_lds_sync();
+    };
+    // ONE: the grid has a wave per step (a loop-free body keeps four waves
+    // per SIMD without spills); else wave-strided steps
+    if constexpr (ONE) {
+        if (lw < runs) step(lw);
+    } else {
+        for (int64_t run = lw; run < runs; run += nw) step(run);
+    }
+}
+
 // Dispatch on the plan at compile time: kMode, kRpb (rows per wave) and kNc
 // (components, structured mode only).  FE_PLAN_DISPATCH_ALL adds the
 // structured plans (FP64 values only).
 #define FE_SPLAN_DISPATCH(PL, BODY)                                                            \
     switch ((PL).mode * 1000 + (PL).nc * 100 + (PL).rpb) {                                     \
+        case 5127: FE_PLAN_CASE(5, 27, 1, BODY)                                                \
+        case 5109: FE_PLAN_CASE(5, 9, 1, BODY)                                                 \
+        case 4127: FE_PLAN_CASE(4, 27, 1, BODY)                                                \
+        case 4109: FE_PLAN_CASE(4, 9, 1, BODY)                                                 \
         case 3127: FE_PLAN_CASE(3, 27, 1, BODY)                                                \
         case 3109: FE_PLAN_CASE(3, 9, 1, BODY)                                                 \
         case 3125: FE_PLAN_CASE(3, 25, 1, BODY)                                                \
@@ -643,7 +841,7 @@ static std::map<int, SpmvPlan> g_stuned;  // evaluated-pattern plans measured by
 // The plan of an evaluated-pattern system: the autotuned one of its class,
 // else short rows (at most 32 entries, instantiated lengths) two lanes per
 // row, longer rows eight rows per wave step.
-static SpmvPlan struct_plan(const SpaceArgs &sa)
+static SpmvPlan struct_plan_of_class(const SpaceArgs &sa)
 {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -654,6 +852,13 @@ static SpmvPlan struct_plan(const SpaceArgs &sa)
     for (int r = 0; r < sa.dim; r++) L *= 2 * sa.k + 1;
     SpmvPlan pl{};
     pl.nc = sa.ncomp;
+    // the Q1 scalar pattern: values and the touched runs of x staged in LDS
+    if (sa.ncomp == 1 && sa.k == 1) {
+        pl.mode = 4;
+        pl.rpb = L;
+        pl.lanes = 2;
+        return pl;
+    }
     // rows of at most 32 entries with an instantiated length: two lanes per row
     if ((sa.ncomp == 1 && (L == 27 || L == 9 || L == 25)) || (sa.ncomp == 2 && L == 18)) {
         pl.mode = 3;
@@ -669,6 +874,17 @@ static SpmvPlan struct_plan(const SpaceArgs &sa)
     return pl;
 }
 
+// The launch form of a plan: mode 4 becomes its one-step-per-wave
+// instantiation (mode 5) when the partial slots hold a block per 128 rows.
+static SpmvPlan launch_form(SpmvPlan pl, int64_t n)
+{
+    if (pl.mode == 4 && (n + 127) / 128 <= part_slots(n)) pl.mode = 5;
+    return pl;
+}
+
+// The plan an evaluated-pattern system is launched with.
+static SpmvPlan struct_plan(const SpaceArgs &sa) { return launch_form(struct_plan_of_class(sa), sa.n_rows); }
+
 template <int MODE, int RPW, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const VT *val,
                                          const double *x, int64_t lb, int64_t nb, Fn f)
@@ -683,7 +899,9 @@ __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const
 template <int MODE, int RPB, int NC, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
 {
-    if constexpr (MODE == 3)
+    if constexpr (MODE == 4 || MODE == 5)
+        for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+    else if constexpr (MODE == 3)
         for_rows_short<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 2)
         for_rows_struct<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
@@ -709,10 +927,11 @@ __device__ __forceinline__ int find_problem(const int32_t *__restrict__ boff, in
 
 // Vector access in pairs of neighbours (16-byte loads and stores); m = 2, or
 // 1 for the last, odd element of a range.
-__device__ __forceinline__ void load_pair(const double *__restrict__ a, int64_t i, int m, double (&o)[2])
+__device__ __forceinline__ void load_pair(const double *__restrict__ ga, int64_t i, int m, double (&o)[2])
 {
+    const FE_GLOBAL double *__restrict__ a = as_global(ga);
     if (m == 2) {
-        const double2 t = *reinterpret_cast<const double2 *>(a + i);
+        const fe_dpair t = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(a + i);
         o[0] = t.x;
         o[1] = t.y;
     } else {
@@ -721,9 +940,10 @@ __device__ __forceinline__ void load_pair(const double *__restrict__ a, int64_t 
     }
 }
 
-__device__ __forceinline__ void store_pair(double *__restrict__ a, int64_t i, int m, const double (&v)[2])
+__device__ __forceinline__ void store_pair(double *__restrict__ ga, int64_t i, int m, const double (&v)[2])
 {
-    if (m == 2) *reinterpret_cast<double2 *>(a + i) = make_double2(v[0], v[1]);
+    FE_GLOBAL double *__restrict__ a = as_global(ga);
+    if (m == 2) *reinterpret_cast<FE_GLOBAL fe_dpair *>(a + i) = fe_dpair{v[0], v[1]};
     else a[i] = v[0];
 }
 
@@ -757,6 +977,9 @@ __device__ __forceinline__ void owned_elems(int64_t n, int64_t lb, int64_t nb, i
     hi = std::min<int64_t>(lo + per, n);
 }
 
+// Threads per block of the row kernels of a plan mode.
+constexpr int rows_block(int mode) { return mode >= 4 ? kQ1Block : kBlock; }
+
 // ---------------------------------------------------------------------------
 // Kernels (every one serves any number of problems: problem p owns the blocks
 // [boff[p], boff[p+1]) of the launch)
@@ -772,10 +995,14 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, const int64_t *
 }
 
 template <int MODE, int RPB, int NC>
-__global__ __launch_bounds__(kBlock) void spmv_struct_kernel(SpaceArgs sa, const double *__restrict__ val,
-                                                              const double *__restrict__ x, double *__restrict__ y)
+__global__ __launch_bounds__(rows_block(MODE)) void spmv_struct_kernel(SpaceArgs sa, const double *__restrict__ val,
+                                                                        const double *__restrict__ x,
+                                                                        double *__restrict__ y)
 {
-    if constexpr (MODE == 3)
+    if constexpr (MODE == 4 || MODE == 5)
+        for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(sa, val, x, blockIdx.x, gridDim.x,
+                                                  [&](int64_t row, double s) { y[row] = s; });
+    else if constexpr (MODE == 3)
         for_rows_short<RPB, NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
     else
         for_rows_struct<RPB, NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
@@ -783,16 +1010,16 @@ __global__ __launch_bounds__(kBlock) void spmv_struct_kernel(SpaceArgs sa, const
 
 // r = b - A x; p = z = dinv r; partials of r.z, r.r, b.b
 template <int MODE, int RPB, int NC, typename VT>
-__global__ __launch_bounds__(kBlock) void pcg_init_kernel(const PcgProb *__restrict__ probs,
+__global__ __launch_bounds__(rows_block(MODE)) void pcg_init_kernel(const PcgProb *__restrict__ probs,
                                                            const int32_t *__restrict__ boff, int nprob)
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     double v[3] = {0.0, 0.0, 0.0};
-    const double *__restrict__ b = P.b;
-    const double *__restrict__ dinv = P.dinv;
-    double *__restrict__ r = P.w.r;
-    double *__restrict__ pv = P.w.p;
+    const FE_GLOBAL double *__restrict__ b = as_global(P.b);
+    const FE_GLOBAL double *__restrict__ dinv = as_global(P.dinv);
+    FE_GLOBAL double *__restrict__ r = as_global(P.w.r);
+    FE_GLOBAL double *__restrict__ pv = as_global(P.w.p);
     for_rows_p<MODE, RPB, NC, VT>(P, P.x, lb, nb, [&](int64_t row, double ax) {
                                 const double rr = b[row] - ax;
                                 const double z = dinv[row] * rr;
@@ -803,9 +1030,9 @@ __global__ __launch_bounds__(kBlock) void pcg_init_kernel(const PcgProb *__restr
                                 v[2] += b[row] * b[row];
                             });
     double t[3] = {v[0], v[1], v[2]};
-    block_sum_all<3>(t);
+    block_sum_all<3, rows_block(MODE)>(t);
     if (threadIdx.x == 0)
-        for (int i = 0; i < 3; i++) P.w.p3[i * kGrid + lb] = t[i];
+        for (int i = 0; i < 3; i++) P.w.p3[i * P.w.ps + lb] = t[i];
 }
 
 // one block per problem: initial scalars and stop test
@@ -813,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(const PcgProb *
 {
     const PcgProb &P = probs[blockIdx.x];
     double t[3];
-    reduce_partials<3>(P.w.p3, P.nbr, t);
+    reduce_partials<3>(P.w.p3, P.nbr, P.w.ps, t);
     if (threadIdx.x == 0) {
         PcgState *st = P.w.st;
         st->rho[0] = t[0];
@@ -834,20 +1061,20 @@ __global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(const PcgProb *
 
 // q = A p; partials of p.q
 template <int MODE, int RPB, int NC, typename VT>
-__global__ __launch_bounds__(kBlock) void pcg_spmv_kernel(const PcgProb *__restrict__ probs,
+__global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgProb *__restrict__ probs,
                                                            const int32_t *__restrict__ boff, int nprob)
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     if (P.w.st->done) return;
     double v[1] = {0.0};
-    const double *__restrict__ p = P.w.p;
-    double *__restrict__ q = P.w.q;
-    for_rows_p<MODE, RPB, NC, VT>(P, p, lb, nb, [&](int64_t row, double s) {
+    const FE_GLOBAL double *__restrict__ p = as_global(P.w.p);
+    FE_GLOBAL double *__restrict__ q = as_global(P.w.q);
+    for_rows_p<MODE, RPB, NC, VT>(P, P.w.p, lb, nb, [&](int64_t row, double s) {
                                 q[row] = s;
                                 v[0] += p[row] * s;
                             });
-    block_sum_all<1>(v);
+    block_sum_all<1, rows_block(MODE)>(v);
     if (threadIdx.x == 0) P.w.p1[lb] = v[0];
 }
 
@@ -861,7 +1088,7 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__res
     if (st->done) return;
     const int j = st->iter;
     double pq[1];
-    reduce_partials<1>(P.w.p1, P.nbr, pq);
+    reduce_partials<1>(P.w.p1, P.nbr, P.w.ps, pq);
     if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
         if (lb == 0 && threadIdx.x == 0) {
             st->done = 1;
@@ -921,7 +1148,7 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
     if (st->done) return;
     const int j = st->iter_upd;
     double t[2];
-    reduce_partials<2>(P.w.p2, P.nbe, t);
+    reduce_partials<2>(P.w.p2, P.nbe, kGrid, t);
     const double rho_old = st->rho[j & 1];
     const double beta = t[0] / rho_old;
     const bool conv = t[1] <= P.rtol2 * st->bb;
@@ -960,18 +1187,18 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
 
 // partials of (b - A x)^2
 template <int MODE, int RPB, int NC, typename VT>
-__global__ __launch_bounds__(kBlock) void resid_kernel(const PcgProb *__restrict__ probs,
+__global__ __launch_bounds__(rows_block(MODE)) void resid_kernel(const PcgProb *__restrict__ probs,
                                                         const int32_t *__restrict__ boff, int nprob)
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     double v[1] = {0.0};
-    const double *__restrict__ b = P.b;
+    const FE_GLOBAL double *__restrict__ b = as_global(P.b);
     for_rows_p<MODE, RPB, NC, VT>(P, P.x, lb, nb, [&](int64_t row, double ax) {
                                 const double d = b[row] - ax;
                                 v[0] += d * d;
                             });
-    block_sum_all<1>(v);
+    block_sum_all<1, rows_block(MODE)>(v);
     if (threadIdx.x == 0) P.w.p3[lb] = v[0];
 }
 
@@ -979,7 +1206,7 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 {
     const PcgProb &P = probs[blockIdx.x];
     double t[1];
-    reduce_partials<1>(P.w.p3, P.nbr, t);
+    reduce_partials<1>(P.w.p3, P.nbr, P.w.ps, t);
     if (threadIdx.x == 0) P.w.st->true_rr = t[0];
 }
 
@@ -988,14 +1215,22 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 // ---------------------------------------------------------------------------
 static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
-    const int rows_per_run = pl.mode == 3 ? 32 : pl.rpb;
+    const int rows_per_run = pl.mode >= 3 ? 32 : pl.rpb;
+    const int waves = rows_block(pl.mode) / 64;
     const int64_t runs = (n + rows_per_run - 1) / rows_per_run;
-    return int(std::max<int64_t>(1, std::min<int64_t>(kGrid, (runs + kWaves - 1) / kWaves)));
+    // the Q1 traversal: up to one block per partial slot (mode 5: exactly one
+    // wave per step); the others: at most kGrid blocks
+    const int64_t cap = pl.mode >= 4 ? part_slots(n) : kGrid;
+    return int(std::max<int64_t>(1, std::min<int64_t>(cap, (runs + waves - 1) / waves)));
 }
 
+// Blocks of the vector kernels of an n-row problem: at most kGridE, since
+// every block of the update kernel re-reads all partials of the SpMV before
+// its first vector access (256 blocks measured 4% faster per C2 iteration
+// than 1024 with one SpMV partial per 128 rows).
 static int grid_elems(int64_t n)
 {
-    return int(std::max<int64_t>(1, std::min<int64_t>(kGrid, (n + kBlock - 1) / kBlock)));
+    return int(std::max<int64_t>(1, std::min<int64_t>(kGridE, (n + kBlock - 1) / kBlock)));
 }
 
 fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
@@ -1144,6 +1379,7 @@ static std::vector<SpmvPlan> struct_candidates(const SpaceArgs &sa)
                                           : std::vector<int>{8, 4, 2, 1};
     for (int r : rpws) c.push_back(SpmvPlan{2, nc, r, 64 / r});
     if ((nc == 1 && (L == 27 || L == 9 || L == 25)) || (nc == 2 && L == 18)) c.push_back(SpmvPlan{3, nc, L, 2});
+    if (nc == 1 && sa.k == 1) c.push_back(SpmvPlan{4, nc, L, 2});
     return c;
 }
 
@@ -1165,11 +1401,11 @@ fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int re
     double best_us = 0.0;
     fe_status st = FE_OK;
     for (size_t c = 0; c < cand.size() && st == FE_OK; c++) {
-        const SpmvPlan &pl = cand[c];
+        const SpmvPlan pl = launch_form(cand[c], n);
         const int g = grid_rows(n, pl);
         for (int r = -1; r < reps; r++) {
             if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = set_error(FE_EDEVICE, "event record failed");
-            FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(kBlock), 0, s>>>(sa, values, x, y)));
+            FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(sa, values, x, y)));
         }
         float ms = 0.0f;
         if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
@@ -1178,7 +1414,7 @@ fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int re
             break;
         }
         const double us = 1000.0 * double(ms) / double(reps);
-        if (tried && int(c) < max_tried) tried[c] = fe_spmv_plan{pl.mode, pl.rpb, us};
+        if (tried && int(c) < max_tried) tried[c] = fe_spmv_plan{cand[c].mode, cand[c].rpb, us};
         if (n_tried) *n_tried = std::min(int(c) + 1, max_tried);
         if (best < 0 || us < best_us) {
             best = int(c);
@@ -1196,9 +1432,20 @@ fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int re
     return FE_OK;
 }
 
+fe_status spmv_plan_set_struct(const SpaceArgs &sa, const fe_spmv_plan &plan)
+{
+    for (const SpmvPlan &c : struct_candidates(sa))
+        if (c.mode == plan.mode && c.rpb == plan.rows_per_wave) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_stuned[struct_class(sa)] = c;
+            return FE_OK;
+        }
+    return set_error(FE_EINVAL, "not a plan of this system's row class");
+}
+
 void spmv_plan_of_struct(const SpaceArgs &sa, fe_spmv_plan *plan, int32_t *cls)
 {
-    const SpmvPlan pl = struct_plan(sa);
+    const SpmvPlan pl = struct_plan_of_class(sa);
     if (plan) *plan = fe_spmv_plan{pl.mode, pl.rpb, 0.0};
     if (cls) *cls = struct_class(sa);
 }
@@ -1269,13 +1516,13 @@ const PcgJob &engine_job(const EngineSet &E, int t) { return E.jobs[t]; }
 #define FE_ROWS_KERNELS(DISPATCH, VT)                                                                                \
     switch (which) {                                                                                                  \
         case 0:                                                                                                       \
-            DISPATCH(g.pl, (pcg_init_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count))); \
+            DISPATCH(g.pl, (pcg_init_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(rows_block(kMode)), 0, s>>>(tp, g.d_boff, g.count))); \
             break;                                                                                                    \
         case 1:                                                                                                       \
-            DISPATCH(g.pl, (pcg_spmv_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count))); \
+            DISPATCH(g.pl, (pcg_spmv_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(rows_block(kMode)), 0, s>>>(tp, g.d_boff, g.count))); \
             break;                                                                                                    \
         default:                                                                                                      \
-            DISPATCH(g.pl, (resid_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(kBlock), 0, s>>>(tp, g.d_boff, g.count))); \
+            DISPATCH(g.pl, (resid_kernel<kMode, kRpb, kNc, VT><<<dim3(g.grid), dim3(rows_block(kMode)), 0, s>>>(tp, g.d_boff, g.count))); \
             break;                                                                                                    \
     }
 
@@ -1577,7 +1824,7 @@ fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const doubl
     if (sa.n_rows == 0) return FE_OK;
     const SpmvPlan pl = struct_plan(sa);
     const int g = grid_rows(sa.n_rows, pl);
-    FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(kBlock), 0, s>>>(sa, val, x, y)));
+    FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(sa, val, x, y)));
     FE_HIP(hipGetLastError());
     return FE_OK;
 }
@@ -1628,13 +1875,13 @@ __global__ __launch_bounds__(kBlock) void resid_vec_kernel(int64_t n, const int6
         v[0] += d * d;
         v[1] += b[row] * b[row];
     });
-    write_partials<2>(v, w.p3);
+    write_partials<2>(v, w.p3, w.ps);
 }
 
 __global__ __launch_bounds__(kBlock) void resid_vec_finish_kernel(PcgWs w, int nparts)
 {
     double t[2];
-    reduce_partials<2>(w.p3, nparts, t);
+    reduce_partials<2>(w.p3, nparts, w.ps, t);
     if (threadIdx.x == 0) {
         w.st->true_rr = t[0];
         w.st->bb = t[1];

@@ -30,6 +30,7 @@ EXPORTS = [
     "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_wait", "fe_server_solution",
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
+    "fe_spmv_plan_set_mesh",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -159,6 +160,7 @@ def lib():
             "fe_spmv_autotune_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _c.c_int32, _P, _c.c_size_t,
                                       _c.POINTER(SpmvPlan), _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
             "fe_spmv_plan_of_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
+            "fe_spmv_plan_set_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan)],
             "fe_server_create": [_c.c_size_t, _c.c_int32, _c.POINTER(_P)],
             "fe_server_submit": [_P, _c.POINTER(Request), _c.POINTER(_c.c_uint64)],
             "fe_server_poll": [_P, _c.c_uint64, _c.POINTER(Result)],
@@ -387,6 +389,13 @@ def spmv_autotune_mesh(mesh, order, coeff, csr, reps=20, stream=None):
            "fe_spmv_autotune_mesh")
     d = lambda p: dict(mode=p.mode, rows_per_wave=p.rows_per_wave, us=p.us)
     return d(ch), [d(t) for t in tried[: nt.value]]
+
+
+def spmv_plan_set_mesh(mesh, order, coeff, mode, rows_per_wave):
+    """Make (mode, rows_per_wave) the evaluated-pattern plan of this system's row class."""
+    p = SpmvPlan(int(mode), int(rows_per_wave), 0.0)
+    _check(lib().fe_spmv_plan_set_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(p)),
+           "fe_spmv_plan_set_mesh")
 
 
 def spmv_plan_of_mesh(mesh, order, coeff):

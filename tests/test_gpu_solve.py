@@ -174,3 +174,76 @@ def test_mesh_solve_rejects_a_foreign_system():
     x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
     with pytest.raises(F.FeError):
         F.pcg_solve_mesh(b.mesh, 1, b.coeff, A.csr, A.rhs, x, 1e-8, 100, ws)
+
+
+# The Q1 scalar class: the LDS-staged traversal (mode 4) sums every row in
+# the order of the two-lane traversal (mode 3), so its products must be
+# bitwise the same; PCG solves group the fused dot-product partials by block
+# (blocks differ between the two), so they agree to rounding.
+@pytest.mark.parametrize("dim,n,faces", [(3, [7, 6, 5], None), (3, [9, 4, 6], 0b011010), (2, [33, 17], None),
+                                         (2, [5, 40], 0b0110)])
+def test_q1_staged_traversal_is_bitwise_the_two_lane_traversal(dim, n, faces):
+    pair = Pair(dim, n, 1, faces=faces, seed=11)
+    A = pair.gpu_assembly()
+    say(f"[q1 staged] dim {dim} n {n} faces {faces} rows {A.n_rows}")
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(12)).standard_normal(A.n_rows)).cuda()
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    ys, sols, infos = [], [], []
+    F.spmv_tuning_reset()
+    try:
+        for mode in (3, 4):
+            F.spmv_plan_set_mesh(pair.mesh, 1, pair.coeff, mode, 3 ** dim)
+            assert F.spmv_plan_of_mesh(pair.mesh, 1, pair.coeff)[:2] == (mode, 3 ** dim)
+            y = torch.empty_like(x)
+            F.spmv_mesh(pair.mesh, 1, pair.coeff, A.csr, x, y)
+            u = torch.zeros_like(x)
+            infos.append(A.solve(u, 1e-10, 5000, ws))
+            torch.cuda.synchronize()
+            ys.append(y)
+            sols.append(u)
+        with pytest.raises(F.FeError):
+            F.spmv_plan_set_mesh(pair.mesh, 1, pair.coeff, 3, 25)
+    finally:
+        F.spmv_tuning_reset()
+    assert torch.equal(ys[0], ys[1])
+    assert all(i["status"] == F.FE_OK for i in infos) and abs(infos[0]["iters"] - infos[1]["iters"]) <= 1
+    assert float(torch.linalg.vector_norm(sols[0] - sols[1]) / torch.linalg.vector_norm(sols[0])) <= 1e-9
+    S = pair.system
+    yo = O.spmv(S.rowptr, S.colind, S.values, x.cpu().numpy())
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x.cpu().numpy()))
+    assert np.all(np.abs(ys[1].cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+
+
+def test_q1_staged_traversal_with_wave_strided_steps():
+    """Above 128 x 32768 rows the traversal's blocks take several steps each
+    (the one-step form needs a partial slot per 128 rows): compared row by row
+    with the CSR traversal of the same matrix."""
+    n = 163  # 162^3 = 4.25M free nodes
+    pair = Pair(3, [n, n, n], 1, seed=13)
+    A = pair.gpu_assembly()
+    assert A.n_rows > 128 * 32768
+    say(f"[q1 strided] rows {A.n_rows} nnz {A.nnz}")
+    assert F.spmv_plan_of_mesh(pair.mesh, 1, pair.coeff)[0] == 4
+    g = torch.Generator(device="cuda").manual_seed(14)
+    x = torch.rand(A.n_rows, dtype=torch.float64, device="cuda", generator=g) + 1.0
+    y = torch.empty_like(x)
+    yc = torch.empty_like(x)
+    F.spmv_mesh(pair.mesh, 1, pair.coeff, A.csr, x, y)
+    F.spmv(A.csr, x, yc)
+    absv = A.values.abs()
+    Cabs = F.csr_struct(A.n_rows, A.nnz, A.rowptr, A.colind, absv, A.rhs, A.dinv)
+    scale = torch.empty_like(x)
+    F.spmv(Cabs, x, scale)
+    torch.cuda.synchronize()
+    assert bool(torch.all((y - yc).abs() <= 1e-13 * scale))
+    # and a PCG solve through it converges like the CSR solve
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    u = torch.zeros_like(x)
+    info = A.solve(u, 1e-8, 20000, ws)
+    uc = torch.zeros_like(x)
+    infoc = F.pcg_solve(A.csr, A.rhs, uc, 1e-8, 20000, ws)
+    torch.cuda.synchronize()
+    say(f"   iters mesh {info['iters']} csr {infoc['iters']}")
+    assert info["status"] == F.FE_OK and infoc["status"] == F.FE_OK
+    assert abs(info["iters"] - infoc["iters"]) <= 2
+    assert float(torch.linalg.vector_norm(u - uc) / torch.linalg.vector_norm(uc)) <= 1e-6
