@@ -662,7 +662,8 @@ __device__ __forceinline__ void for_rows_short(const SpaceArgs &s, const double 
 // 3D step issues 7 + 5 wide loads instead of one load per entry.  Two lanes
 // per row sum the two halves of its positions in position order and the row
 // is lower half + upper half, the order of the short-row traversal, so both
-// give bitwise the same products.  Blocks of kQ1Block threads.  Plan mode 4;
+// give bitwise the same products.  f(row, A_row . x), or f(row, A_row . x,
+// x[row]) when f takes three arguments.  Blocks of kQ1Block threads.  Plan mode 4;
 // mode 5 is its instantiation with one step per wave, used whenever the
 // partial slots cover that many blocks.
 constexpr int kQ1Block = 256, kQ1Waves = kQ1Block / 64;
@@ -780,7 +781,13 @@ __device__ __forceinline__ void for_rows_q1(const SpaceArgs &s, const double *__
             sum += (ok ? mv[off + pc] : 0.0) * mx[sg * S::SEG + rl + e0 + j0];
         }
         const double upper = __shfl(sum, (lane + S::RW) % 64);
-        if (h == 0 && live) f(row, sum + upper);
+        // x[row] sits in the rows' own run (dy = dz = 0) at slot rl + 1
+        if (h == 0 && live) {
+            if constexpr (std::is_invocable_v<Fn, int64_t, double, double>)
+                f(row, sum + upper, mx[(DIM == 3 ? 4 : 1) * S::SEG + rl + 1]);
+            else
+                f(row, sum + upper);
+        }
         wave_lds_sync();
     };
     // ONE: the grid has a wave per step (a loop-free body keeps four waves
@@ -1067,15 +1074,24 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgPro
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     if (P.w.st->done) return;
-    double v[1] = {0.0};
+    double v = 0.0;
     const FE_GLOBAL double *__restrict__ p = as_global(P.w.p);
     FE_GLOBAL double *__restrict__ q = as_global(P.w.q);
-    for_rows_p<MODE, RPB, NC, VT>(P, P.w.p, lb, nb, [&](int64_t row, double s) {
+    // the Q1 traversal hands over p[row] from its LDS copy of p
+    for_rows_p<MODE, RPB, NC, VT>(P, P.w.p, lb, nb, [&](int64_t row, double s, double prow = 0.0) {
                                 q[row] = s;
-                                v[0] += p[row] * s;
+                                v += (MODE >= 4 ? prow : p[row]) * s;
                             });
-    block_sum_all<1, rows_block(MODE)>(v);
-    if (threadIdx.x == 0) P.w.p1[lb] = v[0];
+    // block partial: wave sums, then wave 0's lane 0 adds them in wave order
+    __shared__ double wsum[rows_block(MODE) / 64];
+    const double t = butterfly<64>(v);
+    if (threadIdx.x % 64 == 0) wsum[threadIdx.x / 64] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double u = 0.0;
+        for (int w = 0; w < rows_block(MODE) / 64; w++) u += wsum[w];
+        as_global(P.w.p1)[lb] = u;
+    }
 }
 
 // alpha = rho_j / p.q; x += alpha p; r -= alpha q; partials of r.z, r.r
