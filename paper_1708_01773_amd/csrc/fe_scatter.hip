@@ -21,8 +21,11 @@
 //    register accumulators of the row's 3^d stencil; the rows are staged in
 //    LDS and the wave writes its rows' CSR range contiguously.
 //  * cell-major layout (E[c][a][b]): one wave per row, lanes over 64
-//    consecutive CSR positions; entries along an x-run of columns come from
-//    consecutive b of the same cell, so reads and writes are both contiguous.
+//    consecutive CSR positions (two positions per lane and step); entries
+//    along an x-run of columns come from consecutive b of the same cell, so
+//    reads and writes are both contiguous.  The element-matrix index of an
+//    entry is a sum of per-axis terms, tabulated per row in LDS, and every
+//    contribution of an entry is loaded before any is added.
 #include <algorithm>
 
 #include "fe_internal.h"
@@ -88,56 +91,6 @@ __device__ __forceinline__ RowGeom row_geom(const SpaceArgs &s, int64_t row)
     return g;
 }
 
-// Sum of the contributions to entry (row g, column node J, component cc) of
-// the cell-major layout E[c][a][b], ascending in cell id.  NC components.
-template <int NC, typename ET>
-__device__ __forceinline__ double entry_sum(const SpaceArgs &s, const RowGeom &g, int64_t J0, int64_t J1, int64_t J2,
-                                           int cc, const ET *__restrict__ E)
-{
-    const int k = s.k, k1 = k + 1, nloc = s.nloc;
-    const int64_t nl2 = int64_t(nloc) * nloc;
-    const int64_t n0 = s.ax[0].n, n1 = s.ax[1].n;
-    int32_t e0lo, e0hi, e1lo, e1hi, e2lo, e2hi;
-    axis_cells(g.I0, g.v0, g.m0, J0, s.ax[0].n, e0lo, e0hi);
-    axis_cells(g.I1, g.v1, g.m1, J1, s.ax[1].n, e1lo, e1hi);
-    axis_cells(g.I2, g.v2, g.m2, J2, s.ax[2].n, e2lo, e2hi);
-    double sum = 0.0;
-    for (int32_t e2 = e2lo; e2 <= e2hi; e2++) {
-        const int a2 = int(g.I2 - int64_t(e2) * k), b2 = int(J2 - int64_t(e2) * k);
-        for (int32_t e1 = e1lo; e1 <= e1hi; e1++) {
-            const int a1 = int(g.I1 - int64_t(e1) * k), b1 = int(J1 - int64_t(e1) * k);
-            for (int32_t e0 = e0lo; e0 <= e0hi; e0++) {
-                const int a0 = int(g.I0 - int64_t(e0) * k), b0 = int(J0 - int64_t(e0) * k);
-                const int64_t cell = e0 + n0 * (e1 + n1 * int64_t(e2));
-                const int la = (a0 + k1 * (a1 + k1 * a2)) * NC + g.c;
-                const int lb = (b0 + k1 * (b1 + k1 * b2)) * NC + cc;
-                sum += double(E[cell * nl2 + int64_t(la) * nloc + lb]);
-            }
-        }
-    }
-    return sum;
-}
-
-// rhs of a row: loads (with lifting) of every cell holding the node.
-__device__ __forceinline__ double row_rhs(const SpaceArgs &s, const RowGeom &g, const double *__restrict__ F)
-{
-    const int k = s.k, k1 = k + 1, nc = s.ncomp, nloc = s.nloc;
-    const int64_t n0 = s.ax[0].n, n1 = s.ax[1].n;
-    int32_t e0lo, e0hi, e1lo, e1hi, e2lo, e2hi;
-    axis_cells(g.I0, g.v0, g.m0, g.I0, s.ax[0].n, e0lo, e0hi);
-    axis_cells(g.I1, g.v1, g.m1, g.I1, s.ax[1].n, e1lo, e1hi);
-    axis_cells(g.I2, g.v2, g.m2, g.I2, s.ax[2].n, e2lo, e2hi);
-    double f = 0.0;
-    for (int64_t e2 = e2lo; e2 <= e2hi; e2++)
-        for (int64_t e1 = e1lo; e1 <= e1hi; e1++)
-            for (int64_t e0 = e0lo; e0 <= e0hi; e0++) {
-                const int64_t cell = e0 + n0 * (e1 + n1 * e2);
-                const int la = (int(g.I0 - e0 * k) + k1 * (int(g.I1 - e1 * k) + k1 * int(g.I2 - e2 * k))) * nc + g.c;
-                f += F[cell * nloc + la];
-            }
-    return f;
-}
-
 // ---------------------------------------------------------------------------
 // Blocked layout: thread per row, rows staged in LDS, contiguous writes
 // ---------------------------------------------------------------------------
@@ -151,8 +104,9 @@ __device__ __forceinline__ void wave_lds_fence()
 // Q1 scalar: the 2^DIM cells around a row's node and the 2^DIM local columns
 // of each are unrolled at compile time, so every element entry lands in a
 // register accumulator of the row's 3^DIM stencil.  The cells are visited in
-// ascending id, which is the summation order of every entry (as in
-// entry_sum); contributions to fixed columns are accumulated and dropped.
+// ascending id, which is the summation order of every entry (as in the
+// cell-major traversal); contributions to fixed columns are accumulated and
+// dropped.
 template <int DIM, typename ET>
 __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restrict__ E,
                                            const double *__restrict__ F, double *__restrict__ values,
@@ -242,44 +196,198 @@ __global__ __launch_bounds__(256) void k5_q1_batch_kernel(const AsmJob *__restri
 // ---------------------------------------------------------------------------
 // Cell-major layout: wave per row, lanes over consecutive CSR positions
 // ---------------------------------------------------------------------------
+// Per-axis address tables of a row.  Along axis r the column node J = cl_r + j
+// (j < w_r <= 2k + 1) shares with the row node I one or two cells e (see
+// axis_cells); the element-matrix index of entry (row, column) in cell
+// (e0, e1, e2) is a sum of per-axis terms,
+//   e_r cs_r nloc^2 + (I_r - e_r k) s_r nloc + (J_r - e_r k) s_r  (s_r = NC (k+1)^r,
+//   cs_0 = 1, cs_1 = n0, cs_2 = n0 n1)
+// plus c nloc + cc, so a row stores off[r][j][d] for its first (d = 0) and
+// second (d = 1) cell along each axis and cnt[r][j] = 1 or 2.
+constexpr int kAxMax = 9;  // 2k + 1 for k <= 4
+
+struct RowTables {
+    int64_t off[3][kAxMax][2];
+    int32_t cnt[3][kAxMax];
+};
+
+__device__ __forceinline__ void build_row_tables(const SpaceArgs &s, const RowGeom &g, int nc, RowTables &t,
+                                                 int lane)
+{
+    if (lane < 3 * kAxMax) {
+        const int r = lane / kAxMax, j = lane - r * kAxMax;
+        const int32_t w = r == 0 ? g.w0 : (r == 1 ? g.w1 : g.w2);
+        if (j < w) {
+            const int k = s.k, nloc = s.nloc;
+            const int64_t I = r == 0 ? g.I0 : (r == 1 ? g.I1 : g.I2);
+            const int32_t v = r == 0 ? g.v0 : (r == 1 ? g.v1 : g.v2);
+            const int32_t m = r == 0 ? g.m0 : (r == 1 ? g.m1 : g.m2);
+            const int64_t J = (r == 0 ? g.cl0 : (r == 1 ? g.cl1 : g.cl2)) + j;
+            int32_t elo, ehi;
+            axis_cells(I, v, m, J, s.ax[r].n, elo, ehi);
+            int64_t cs = int64_t(nloc) * nloc, sr = nc;
+            for (int q = 0; q < r; q++) {
+                cs *= s.ax[q].n;
+                sr *= k + 1;
+            }
+            for (int d = 0; d < 2; d++) {
+                const int64_t e = elo + (d <= ehi - elo ? d : 0);
+                t.off[r][j][d] = e * cs + (I - e * k) * sr * nloc + (J - e * k) * sr;
+            }
+            t.cnt[r][j] = ehi - elo + 1;
+        }
+    }
+}
+
+// Entry (row, position pos): contributions of cells u = d0 + 2 d1 + 4 d2
+// (d_r < cnt_r) loaded together and summed in ascending u, which is
+// ascending cell id, the summation order of every CSR entry.
+template <int NC, typename ET>
+__device__ __forceinline__ double entry_from_tables(const RowTables &t, const ET *__restrict__ E, int64_t base,
+                                                    int j0, int j1, int j2)
+{
+    const int64_t a0 = t.off[0][j0][0], a1 = t.off[0][j0][1];
+    const int64_t b0 = t.off[1][j1][0], b1 = t.off[1][j1][1];
+    const int64_t c0 = t.off[2][j2][0], c1 = t.off[2][j2][1];
+    const int n0 = t.cnt[0][j0], n1 = t.cnt[1][j1], n2 = t.cnt[2][j2];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int d0 = u & 1, d1 = (u >> 1) & 1, d2 = u >> 2;
+        v[u] = 0.0;
+        if (d0 < n0 && d1 < n1 && d2 < n2)
+            v[u] = double(E[base + (d0 ? a1 : a0) + (d1 ? b1 : b0) + (d2 ? c1 : c0)]);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int d0 = u & 1, d1 = (u >> 1) & 1, d2 = u >> 2;
+        if (d0 < n0 && d1 < n1 && d2 < n2) sum += v[u];
+    }
+    return sum;
+}
+
+// Row geometry from the closed forms of the axis tables (no table loads);
+// the fields of row_geom.
+template <int NC>
+__device__ __forceinline__ RowGeom row_geom_closed(const SpaceArgs &s, const AxisClosed (&A)[3], double kinv,
+                                                   int64_t row)
+{
+    RowGeom g;
+    const int32_t k = s.k;
+    const int32_t r32 = int32_t(row);
+    const int32_t R = r32 / NC;
+    g.c = r32 - R * NC;
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const int32_t q = div_exact(R, f0, s.ax[0].finv), t0 = R - q * f0;
+    const int32_t t2 = div_exact(q, f1, s.ax[1].finv), t1 = q - t2 * f1;
+    int32_t w0, w1, w2, cl0, cl1, cl2, P0, P1, P2;
+    axis_row(A[0], k, kinv, A[0].lo + t0, w0, cl0, P0);
+    axis_row(A[1], k, kinv, A[1].lo + t1, w1, cl1, P1);
+    axis_row(A[2], k, kinv, A[2].lo + t2, w2, cl2, P2);
+    g.I0 = A[0].lo + t0;
+    g.I1 = A[1].lo + t1;
+    g.I2 = A[2].lo + t2;
+    g.w0 = w0;
+    g.w1 = w1;
+    g.w2 = w2;
+    g.cl0 = cl0;
+    g.cl1 = cl1;
+    g.cl2 = cl2;
+    g.v0 = div_exact(int32_t(g.I0), k, kinv);
+    g.v1 = div_exact(int32_t(g.I1), k, kinv);
+    g.v2 = div_exact(int32_t(g.I2), k, kinv);
+    g.m0 = int32_t(g.I0) - g.v0 * k;
+    g.m1 = int32_t(g.I1) - g.v1 * k;
+    g.m2 = int32_t(g.I2) - g.v2 * k;
+    const int64_t T0 = s.ax[0].T, T1 = s.ax[1].T;
+    const int64_t S = int64_t(P2) * T1 * T0 + int64_t(w2) * P1 * T0 + int64_t(w2) * w1 * P0;
+    g.start = int64_t(NC) * NC * S + int64_t(g.c) * NC * (int64_t(w0) * w1 * w2);
+    return g;
+}
+
 template <int NC, typename ET>
 __device__ __forceinline__ void k5_entries_body(const SpaceArgs &s, const ET *__restrict__ E,
                                                 const double *__restrict__ F, double *__restrict__ values,
                                                 double *__restrict__ rhs, double *__restrict__ dinv, int64_t lb,
                                                 int64_t nb)
 {
+    __shared__ RowTables tabs[4];
+    RowTables &t = tabs[threadIdx.x / 64];
     const int lane = threadIdx.x % 64;
     const int64_t nw = nb * 4;
     const int64_t lw = lb * 4 + threadIdx.x / 64;
+    const int32_t k = s.k, k1 = k + 1;
+    const double kinv = 1.0 / double(k);
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * (k + 1) + k * ((A[r].lo + k - 1) / k);
+    }
     for (int64_t row = lw; row < s.n_rows; row += nw) {
-        const RowGeom g = row_geom(s, row);
+        const RowGeom g = row_geom_closed<NC>(s, A, kinv, row);
+        build_row_tables(s, g, NC, t, lane);
+        // rhs: lanes u < 8 load the loads of the row node's cells u = d0 + 2 d1 + 4 d2
+        double fu = 0.0;
+        bool fok = false;
+        if (lane < 8) {
+            int32_t e0lo, e0hi, e1lo, e1hi, e2lo, e2hi;
+            axis_cells(g.I0, g.v0, g.m0, g.I0, s.ax[0].n, e0lo, e0hi);
+            axis_cells(g.I1, g.v1, g.m1, g.I1, s.ax[1].n, e1lo, e1hi);
+            axis_cells(g.I2, g.v2, g.m2, g.I2, s.ax[2].n, e2lo, e2hi);
+            const int32_t e0 = e0lo + (lane & 1), e1 = e1lo + ((lane >> 1) & 1), e2 = e2lo + (lane >> 2);
+            fok = e0 <= e0hi && e1 <= e1hi && e2 <= e2hi;
+            if (fok) {
+                const int64_t cell = e0 + int64_t(s.ax[0].n) * (e1 + int64_t(s.ax[1].n) * e2);
+                const int la = (int(g.I0 - int64_t(e0) * k) +
+                                k1 * (int(g.I1 - int64_t(e1) * k) + k1 * int(g.I2 - int64_t(e2) * k))) * NC + g.c;
+                fu = F[cell * s.nloc + la];
+            }
+        }
+        wave_lds_fence();
         const int wx = g.w0 * NC;   // entries per x-run
         const int len = wx * g.w1 * g.w2;
-        // mixed-radix position (j2, j1, x) of this lane's entry, advanced by 64 per step
-        int x = lane, j1 = 0, j2 = 0;
-        while (x >= wx) {
-            x -= wx;
-            if (++j1 == g.w1) {
-                j1 = 0;
-                j2++;
+        const int64_t base = int64_t(g.c) * s.nloc;
+        // the diagonal's position
+        const int pd = ((int(g.I2 - g.cl2) * g.w1 + int(g.I1 - g.cl1)) * g.w0 + int(g.I0 - g.cl0)) * NC + g.c;
+        // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8] (p < 2^12, d <= 27)
+        const uint32_t mx = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
+        const uint32_t my = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(g.w1))) + 2u;
+        auto decode = [&](int pos, int &j0, int &j1, int &j2, int &cc) {
+            const int q = int((uint32_t(pos) * mx) >> 20), x = pos - q * wx;
+            j2 = int((uint32_t(q) * my) >> 20);
+            j1 = q - j2 * g.w1;
+            j0 = x / NC;
+            cc = x - j0 * NC;
+        };
+        // two entries per lane and step (positions pos, pos + 64), their loads in flight together
+        for (int pos = lane; pos < len; pos += 128) {
+            int a0, a1, a2, ac, b0 = 0, b1 = 0, b2 = 0, bc = 0;
+            decode(pos, a0, a1, a2, ac);
+            const bool hb = pos + 64 < len;
+            if (hb) decode(pos + 64, b0, b1, b2, bc);
+            const double va = entry_from_tables<NC>(t, E, base + ac, a0, a1, a2);
+            const double vb = hb ? entry_from_tables<NC>(t, E, base + bc, b0, b1, b2) : 0.0;
+            values[g.start + pos] = va;
+            if (pos == pd) dinv[row] = 1.0 / va;
+            if (hb) {
+                values[g.start + pos + 64] = vb;
+                if (pos + 64 == pd) dinv[row] = 1.0 / vb;
             }
         }
-        for (int pos = lane; pos < len; pos += 64) {
-            const int j0 = x / NC, cc = x - j0 * NC;
-            const int64_t J0 = g.cl0 + j0, J1 = g.cl1 + j1, J2 = g.cl2 + j2;
-            const double v = entry_sum<NC>(s, g, J0, J1, J2, cc, E);
-            values[g.start + pos] = v;
-            if (J0 == g.I0 && J1 == g.I1 && J2 == g.I2 && cc == g.c) dinv[row] = 1.0 / v;
-            x += 64;
-            while (x >= wx) {
-                x -= wx;
-                if (++j1 == g.w1) {
-                    j1 = 0;
-                    j2++;
-                }
-            }
+        // rhs summed in ascending cell order
+        double f = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const double fv = __shfl(fu, u);
+            const bool ok = __shfl(int(fok), u) != 0;
+            if (ok) f += fv;
         }
-        if (lane == 0) rhs[row] = row_rhs(s, g, F);
+        if (lane == 0) rhs[row] = f;
+        wave_lds_fence();
     }
 }
 

@@ -388,44 +388,6 @@ __device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restri
         }                                                          \
     } while (0)
 
-// floor(a / d) for 0 <= a < 2^31, 0 < d, with inv = 1 / d: the double
-// estimate is off by at most one and is corrected exactly.
-__device__ __forceinline__ int32_t div_exact(int32_t a, int32_t d, double inv)
-{
-    int32_t q = int32_t((double(a) + 0.5) * inv);
-    const int32_t r = a - q * d;
-    q += r < 0 ? -1 : (r >= d ? 1 : 0);
-    return q;
-}
-
-// Interval of columns of free node i along one axis and the prefix P(i) of
-// the interval widths over the free nodes below i: closed forms of the axis
-// tables built on the host (the unclipped interval of a vertex node is
-// [i - k, i + k], of an element-interior node [k floor(i / k), + k]; the ends
-// of the free range [lo, hi] clip them).  swlo = unclipped widths below lo.
-struct AxisClosed {
-    int32_t lo, hi, N, swlo;
-};
-
-__device__ __forceinline__ void axis_row(const AxisClosed &A, int32_t k, double kinv, int32_t i, int32_t &w,
-                                         int32_t &cl, int32_t &P)
-{
-    if (A.N == 0) {  // the third axis of a 2D mesh
-        w = 1;
-        cl = 0;
-        P = 0;
-        return;
-    }
-    const int32_t m = i - div_exact(i, k, kinv) * k;
-    const int32_t low = A.lo == 0 ? (i == 0 ? k : 0) : ((i >= 1 && i <= k) ? 1 : 0);
-    const int32_t high = A.hi == A.N ? (i == A.N ? k : 0) : ((i >= A.N - k && i <= A.N - 1) ? 1 : 0);
-    w = (m == 0 ? 2 * k + 1 : k + 1) - low - high;
-    cl = (m == 0 ? i - k : i - m) + low;
-    // unclipped widths of nodes 0..i-1: i (k + 1) + k ceil(i / k)
-    P = i * (k + 1) + k * div_exact(i + k - 1, k, kinv) - A.swlo;
-    P -= A.lo == 0 ? (i >= 1 ? k : 0) : max(0, min(i - 1, k));
-    if (A.hi != A.N) P -= max(0, i - max(A.lo, A.N - k));
-}
 
 // Rows of a system assembled on a structured brick, with the pattern
 // evaluated instead of read.  Row (free node (t0, t1, t2), component c) has
