@@ -420,6 +420,9 @@ __global__ __launch_bounds__(256, 2) void k3_mfma_batch_kernel(const AsmJob *__r
 
 // ---------------------------------------------------------------------------
 // Launch: (order, problem) -> padded node count, pairs per wave, parts per cell
+// (measured: Q3 elasticity 3.75 ms with one pair per wave against 5.57 ms with
+// two, Q4 elasticity 9.0 ms with two against 9.7 ms with one; 32^3 and 24^3
+// cells)
 // ---------------------------------------------------------------------------
 template <class Pol, int PROB, int NNP, int PPW, int QS>
 static fe_status launch_one(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
@@ -443,7 +446,7 @@ static fe_status launch_pol(const SpaceArgs &sa, const MeshArgs &ma, const Probl
     const bool el = pa.problem == FE_ELASTICITY;
     switch (sa.k) {
         case 2: return el ? launch_one<Pol, 1, 32, 1, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 32, 1, QS>(sa, ma, pa, rt, E, F, s);
-        case 3: return el ? launch_one<Pol, 1, 64, 2, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 64, 3, QS>(sa, ma, pa, rt, E, F, s);
+        case 3: return el ? launch_one<Pol, 1, 64, 1, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 64, 3, QS>(sa, ma, pa, rt, E, F, s);
         case 4: return el ? launch_one<Pol, 1, 128, 2, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 128, 9, QS>(sa, ma, pa, rt, E, F, s);
         default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
     }
@@ -478,7 +481,7 @@ static fe_status launch_batch_pol(const AsmJob &h, const AsmJob *jobs, const int
     const bool el = h.p.problem == FE_ELASTICITY;
     switch (h.s.k) {
         case 2: return el ? launch_batch_one<Pol, 1, 32, 1, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 32, 1, QS>(jobs, boff, njobs, grid, s);
-        case 3: return el ? launch_batch_one<Pol, 1, 64, 2, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 64, 3, QS>(jobs, boff, njobs, grid, s);
+        case 3: return el ? launch_batch_one<Pol, 1, 64, 1, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 64, 3, QS>(jobs, boff, njobs, grid, s);
         case 4: return el ? launch_batch_one<Pol, 1, 128, 2, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 128, 9, QS>(jobs, boff, njobs, grid, s);
         default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
     }
@@ -502,7 +505,7 @@ int64_t mfma_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts)
     int nnp = 32, ppw = 1;
     if (sa.k == 3) {
         nnp = 64;
-        ppw = el ? 2 : 3;
+        ppw = el ? 1 : 3;
     } else if (sa.k == 4) {
         nnp = 128;
         ppw = el ? 2 : 9;
