@@ -211,32 +211,36 @@ struct RowTables {
     int32_t cnt[3][kAxMax];
 };
 
+// One axis of the tables (R compile time, so no field of the row's geometry
+// or of the argument struct is indexed at run time, which would put them in
+// private memory): lane j < w_R fills column j.
+template <int R>
+__device__ __forceinline__ void build_axis_table(const SpaceArgs &s, int64_t I, int32_t v, int32_t m, int64_t cl,
+                                                 int32_t w, int nc, RowTables &t, int lane)
+{
+    if (lane < w) {
+        const int k = s.k, nloc = s.nloc;
+        const int64_t J = cl + lane;
+        int32_t elo, ehi;
+        axis_cells(I, v, m, J, s.ax[R].n, elo, ehi);
+        const int64_t nl2 = int64_t(nloc) * nloc;
+        const int64_t cs = R == 0 ? nl2 : (R == 1 ? nl2 * s.ax[0].n : nl2 * s.ax[0].n * s.ax[1].n);
+        const int64_t sr = R == 0 ? nc : (R == 1 ? nc * (k + 1) : nc * (k + 1) * (k + 1));
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const int64_t e = elo + (d <= ehi - elo ? d : 0);
+            t.off[R][lane][d] = e * cs + (I - e * k) * sr * nloc + (J - e * k) * sr;
+        }
+        t.cnt[R][lane] = ehi - elo + 1;
+    }
+}
+
 __device__ __forceinline__ void build_row_tables(const SpaceArgs &s, const RowGeom &g, int nc, RowTables &t,
                                                  int lane)
 {
-    if (lane < 3 * kAxMax) {
-        const int r = lane / kAxMax, j = lane - r * kAxMax;
-        const int32_t w = r == 0 ? g.w0 : (r == 1 ? g.w1 : g.w2);
-        if (j < w) {
-            const int k = s.k, nloc = s.nloc;
-            const int64_t I = r == 0 ? g.I0 : (r == 1 ? g.I1 : g.I2);
-            const int32_t v = r == 0 ? g.v0 : (r == 1 ? g.v1 : g.v2);
-            const int32_t m = r == 0 ? g.m0 : (r == 1 ? g.m1 : g.m2);
-            const int64_t J = (r == 0 ? g.cl0 : (r == 1 ? g.cl1 : g.cl2)) + j;
-            int32_t elo, ehi;
-            axis_cells(I, v, m, J, s.ax[r].n, elo, ehi);
-            int64_t cs = int64_t(nloc) * nloc, sr = nc;
-            for (int q = 0; q < r; q++) {
-                cs *= s.ax[q].n;
-                sr *= k + 1;
-            }
-            for (int d = 0; d < 2; d++) {
-                const int64_t e = elo + (d <= ehi - elo ? d : 0);
-                t.off[r][j][d] = e * cs + (I - e * k) * sr * nloc + (J - e * k) * sr;
-            }
-            t.cnt[r][j] = ehi - elo + 1;
-        }
-    }
+    build_axis_table<0>(s, g.I0, g.v0, g.m0, g.cl0, g.w0, nc, t, lane);
+    build_axis_table<1>(s, g.I1, g.v1, g.m1, g.cl1, g.w1, nc, t, lane);
+    build_axis_table<2>(s, g.I2, g.v2, g.m2, g.cl2, g.w2, nc, t, lane);
 }
 
 // Entry (row, position pos): contributions of cells u = d0 + 2 d1 + 4 d2
