@@ -58,16 +58,17 @@ def spmv_bytes(n, nnz, mode="csr"):
     return nnz * 12 + (n + 1) * 8 + 16 * n
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch from committed rocprofv3 counters, or None when the
-    kernel source changed since they were taken."""
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counters of this kernel on
+    this workload, or None when there are none or the kernel source changed
+    since they were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     e = t.get(kernel)
-    if not e:
+    if not e or e.get("bench_workload") != workload:
         return None
     src = os.path.join(ROOT, e["source"])
     if not os.path.exists(src) or source_sha(src) != e["source_sha"]:
@@ -436,7 +437,7 @@ def main():
     sb = spmv_bytes(A.n_rows, A.nnz, args.spmv)
     achieved = sb / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
     kname = "pcg_spmv_kernel/mesh" if args.spmv == "mesh" else "pcg_spmv_kernel/csr"
-    traffic = traffic_for(kname)
+    traffic = traffic_for(kname, args.workload)
     lat_sorted = sorted(lat)
     p99 = lat_sorted[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
     out = {
