@@ -221,7 +221,9 @@ def batch_form(args, F, torch):
         if r.numel():
             err[0] = max(err[0], (torch.linalg.vector_norm(x - r) / torch.linalg.vector_norm(r)).item())
 
-    res = run.run(rtol, maxit, keep=keep)
+    res = run.run(rtol, maxit, keep=keep, progress=lambda w, nw, ta, ts: print(
+        f"[bench] batch form: wave {w + 1}/{nw} assembled in {ta:.2f} s, solved in {ts:.2f} s", file=sys.stderr,
+        flush=True))
     t_b = res["assemble_s"] + res["solve_s"]
     t_s = seq32["assemble_s"] + seq32["solve_s"] if seq32 else None
     print(f"[bench] batch form: batched {t_b:.2f} s (set-up {res['setup_s']:.2f} s)", file=sys.stderr, flush=True)

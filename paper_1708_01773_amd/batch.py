@@ -16,11 +16,20 @@ from . import fe as F
 
 
 def make_problem(i, n, k, precision="fp32"):
-    """(mesh, order, coeff) of problem i of a batch."""
+    """(mesh, order, coeff) of problem i of a batch.  A jitter draw of +-0.2 h
+    can invert a cell (about one mesh in a few hundred of 64^3 cells); the
+    library refuses such a mesh, and the problem then takes the next draw
+    (jitter seed + 1 for every attempt), so it stays the same in every run."""
     sj, sc = problem_seeds(i)
-    v = structured_vertices(3, n, jitter=0.2, seed=sj)
     coef = lognormal_coefficients(n ** 3, seed=sc)
-    mesh = F.create_mesh(3, [n, n, n], v, coef)
+    for attempt in range(16):
+        v = structured_vertices(3, n, jitter=0.2, seed=sj + attempt)
+        try:
+            mesh = F.create_mesh(3, [n, n, n], v, coef)
+            break
+        except F.FeError as e:
+            if e.status != F.FE_EMESH or attempt == 15:
+                raise
     coeff = F.make_coeff("poisson", precision, source_kind=F.FE_SOURCE_CONST, source=(1.0,), dim=3)
     return mesh, int(k), coeff
 
@@ -88,9 +97,10 @@ class BatchRun:
             del A
         return chosen
 
-    def run(self, rtol, maxit, keep=None, stream=None):
+    def run(self, rtol, maxit, keep=None, stream=None, progress=None):
         """Assembles and solves every wave; returns per-phase times and the
-        per-problem solver infos.  keep(i, x) is called with each solution."""
+        per-problem solver infos.  keep(i, x) is called with each solution,
+        progress(w, nwaves, assemble_s, solve_s) after each wave."""
         import torch
         infos = [None] * len(self.specs)
         t_setup = t_asm = t_solve = 0.0
@@ -118,6 +128,8 @@ class BatchRun:
                 if keep is not None:
                     keep(i, B.x[j][: B.n_rows[j]])
             del B
+            if progress is not None:
+                progress(self.waves.index(wave), len(self.waves), tb - ta, tc - tb)
             torch.cuda.empty_cache()
         return dict(status=status, setup_s=t_setup, assemble_s=t_asm, solve_s=t_solve, infos=infos)
 
