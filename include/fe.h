@@ -303,10 +303,13 @@ fe_status fe_spmv_tuning_reset(void);
 /* The same for the evaluated-pattern traversal of fe_spmv_mesh /
  * fe_pcg_solve_mesh / fe_pcg_solve_batch_mesh: plans are modes 2 (lanes per
  * row, rows_per_wave runs), 3 (short rows, two lanes per row; rows_per_wave
- * reports the longest row) and, for the Q1 scalar pattern, 4 (the values of 32
+ * reports the longest row), for the Q1 scalar pattern 4 (the values of 32
  * rows and the runs of x they touch staged in LDS with wide loads; two lanes
  * per row in the order of mode 3, so modes 3 and 4 give bitwise the same
- * products), timed on A assembled on (mesh, order, coeff); the fastest
+ * products), and for every other pattern 6 (rows_per_wave 8: x over the
+ * column box of 32 consecutive rows of a line of nodes staged in LDS per
+ * workgroup; bitwise the same products as mode 2 with 8 rows per wave),
+ * timed on A assembled on (mesh, order, coeff); the fastest
  * becomes the plan of every mesh system with the same longest row and
  * component count.  ws: fe_spmv_autotune_query(A->n_rows) bytes.
  * fe_spmv_plan_set_mesh makes `plan` (mode and rows_per_wave of one of the

@@ -94,7 +94,9 @@ struct PcgProb {
 struct SpmvPlan {
     int mode;  // 0: wave-level CSR-stream, 1: wave per row, 2: structured (pattern evaluated),
                // 3: structured short rows, two lanes per row (rpb = longest row),
-               // 4: structured Q1 scalar rows, values and x runs staged in LDS (rpb = longest row)
+               // 4: structured Q1 scalar rows, values and x runs staged in LDS (rpb = longest row),
+               // 5: mode 4 with one wave step per wave (launch form only),
+               // 6: structured rows, x of a 32-row chunk's column box staged per block (rpb 8)
     int nc = 1;  // components (mode 2)
     int rpb;   // rows per wave-iteration (stream mode)
     int lanes; // lanes per row
@@ -761,11 +763,109 @@ __device__ __forceinline__ void for_rows_q1(const SpaceArgs &s, const double *__
     }
 }
 
+// Rows of any evaluated pattern, x staged per block (plan mode 6).  A block
+// takes a chunk of kXbRows consecutive rows of one line of nodes (t1, t2
+// fixed): their column boxes share the y and z ranges, and their x ranges lie
+// in the union [cl0(first node), cl0(last node) + w0(last node)).  The block
+// loads x over that box -- w1 w2 runs of NC (xb - xa) consecutive unknowns,
+// coalesced -- into LDS once; then each wave sums eight rows, eight lanes per
+// row, values read from memory and x from LDS, in the order of the
+// lanes-per-row traversal with eight rows per wave (bitwise the same
+// products).  Chunks never cross a line of nodes.
+constexpr int kXbRows = 32;   // rows per chunk: 4 waves x 8 rows
+constexpr int kXbCap = 4864;  // staged doubles: (2k+1)^2 runs of NC (nodes of a chunk + 2k), k <= 4
+
+template <int NC, typename Fn>
+__device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double *__restrict__ gval,
+                                                const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+{
+    constexpr int RPW = 8, LW = 64 / RPW;
+    __shared__ double sx[kXbCap];
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / LW, sub = lane % LW;
+    const int32_t k = s.k;
+    const double kinv = 1.0 / double(k);
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * (k + 1) + k * ((A[r].lo + k - 1) / k);
+    }
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const int64_t T0 = s.ax[0].T, T1 = s.ax[1].T;
+    const int64_t rpl = int64_t(NC) * f0;                      // rows per line of nodes
+    const int64_t cpl = (rpl + kXbRows - 1) / kXbRows;         // chunks per line
+    const int64_t nchunks = int64_t(f1) * s.ax[2].f * cpl;
+    for (int64_t ch = lb; ch < nchunks; ch += nb) {
+        const int64_t line = ch / cpl, q = ch - line * cpl;
+        const int32_t t1 = int32_t(line % f1), t2 = int32_t(line / f1);
+        const int64_t lr0 = q * kXbRows;                        // first row of the chunk within its line
+        const int64_t lr1 = lr0 + kXbRows < rpl ? lr0 + kXbRows : rpl;
+        int32_t wa, cla, Pa, wb, clb, Pb, w1, cl1, P1, w2, cl2, P2;
+        axis_row(A[0], k, kinv, A[0].lo + int32_t(lr0 / NC), wa, cla, Pa);
+        axis_row(A[0], k, kinv, A[0].lo + int32_t((lr1 - 1) / NC), wb, clb, Pb);
+        axis_row(A[1], k, kinv, A[1].lo + t1, w1, cl1, P1);
+        axis_row(A[2], k, kinv, A[2].lo + t2, w2, cl2, P2);
+        const int32_t xa = cla, run = NC * (clb + wb - cla);    // staged nodes [xa, xb) along x
+        const int32_t nst = run * w1 * w2;
+        __syncthreads();  // the previous chunk's reads of sx are done
+        for (int e = threadIdx.x; e < nst; e += 256) {
+            const int rr = e / run, i = e - rr * run;
+            const int jz = rr / w1, jy = rr - jz * w1;
+            const int64_t col = int64_t(NC) * ((xa - A[0].lo) + int64_t(f0) * ((cl1 + jy - A[1].lo) +
+                                                                               int64_t(f1) * (cl2 + jz - A[2].lo))) + i;
+            sx[e] = x[col];
+        }
+        __syncthreads();
+        const int64_t lrow = lr0 + RPW * wave + g;
+        const bool live = lrow < lr1;
+        const int64_t row = line * rpl + lrow;
+        double sum = 0.0;
+        if (live) {
+            const int32_t t0 = int32_t(lrow / NC), c = int32_t(lrow - int64_t(t0) * NC);
+            int32_t w0, cl0, P0;
+            axis_row(A[0], k, kinv, A[0].lo + t0, w0, cl0, P0);
+            const int64_t S = int64_t(P2) * T1 * T0 + int64_t(w2) * P1 * T0 + int64_t(w2 * w1) * P0;
+            const int32_t wx = w0 * NC, len = wx * w1 * w2;
+            const int64_t start = int64_t(NC) * NC * S + int64_t(c) * len;
+            const int32_t xoff = NC * (cl0 - xa);
+            // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8] (p < 2^12, d <= 27)
+            const uint32_t mx = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
+            const uint32_t my = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
+            for (int32_t p0 = 0; p0 < len; p0 += 4 * LW) {
+                double a4[4], x4[4];
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const int32_t pos = p0 + sub + t * LW;
+                    const bool ok = pos < len;
+                    const int32_t pc = ok ? pos : 0;
+                    const int32_t qy = int32_t((uint32_t(pc) * mx) >> 20);
+                    const int32_t xx = pc - qy * wx;
+                    const int32_t j2 = int32_t((uint32_t(qy) * my) >> 20);
+                    const int32_t j1 = qy - j2 * w1;
+                    a4[t] = ok ? val[start + pc] : 0.0;
+                    x4[t] = sx[(j2 * w1 + j1) * run + xoff + xx];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; t++) sum += a4[t] * x4[t];
+            }
+        }
+        const double t = butterfly<LW>(sum);
+        if (live && sub == 0) f(row, t);
+    }
+}
+
 // Dispatch on the plan at compile time: kMode, kRpb (rows per wave) and kNc
 // (components, structured mode only).  FE_PLAN_DISPATCH_ALL adds the
 // structured plans (FP64 values only).
 #define FE_SPLAN_DISPATCH(PL, BODY)                                                            \
     switch ((PL).mode * 1000 + (PL).nc * 100 + (PL).rpb) {                                     \
+        case 6108: FE_PLAN_CASE(6, 8, 1, BODY)                                                 \
+        case 6208: FE_PLAN_CASE(6, 8, 2, BODY)                                                 \
+        case 6308: FE_PLAN_CASE(6, 8, 3, BODY)                                                 \
         case 5127: FE_PLAN_CASE(5, 27, 1, BODY)                                                \
         case 5109: FE_PLAN_CASE(5, 9, 1, BODY)                                                 \
         case 4127: FE_PLAN_CASE(4, 27, 1, BODY)                                                \
@@ -835,8 +935,19 @@ static SpmvPlan struct_plan_of_class(const SpaceArgs &sa)
         pl.lanes = 2;
         return pl;
     }
-    // eight rows per wave step (8 lanes per row, the rest of a long row in
-    // further steps of 32 positions): measured fastest for Q2-Q3 rows
+    // vector patterns and order 4: x of each 32-row chunk staged per block
+    // (measured on 2.6-4.0 M-row systems: elasticity Q2 / Q3 / Q4 996 / 1769 /
+    // 2889 us against 1033 / 1850 / 3080 us for the best lanes-per-row plan,
+    // scalar Q4 1910 against 2073 us)
+    if (sa.ncomp >= 2 || sa.k >= 4) {
+        pl.mode = 6;
+        pl.rpb = 8;
+        pl.lanes = 8;
+        return pl;
+    }
+    // scalar Q2-Q3: eight rows per wave step (8 lanes per row, the rest of a
+    // long row in further steps of 32 positions), measured fastest (the
+    // block-staged plan: 415 / 925 us against 358 / 862 us)
     pl.mode = 2;
     pl.rpb = 8;
     pl.lanes = 8;
@@ -868,7 +979,9 @@ __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const
 template <int MODE, int RPB, int NC, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
 {
-    if constexpr (MODE == 4 || MODE == 5)
+    if constexpr (MODE == 6)
+        for_rows_xblock<NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+    else if constexpr (MODE == 4 || MODE == 5)
         for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 3)
         for_rows_short<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
@@ -968,7 +1081,9 @@ __global__ __launch_bounds__(rows_block(MODE)) void spmv_struct_kernel(SpaceArgs
                                                                         const double *__restrict__ x,
                                                                         double *__restrict__ y)
 {
-    if constexpr (MODE == 4 || MODE == 5)
+    if constexpr (MODE == 6)
+        for_rows_xblock<NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
+    else if constexpr (MODE == 4 || MODE == 5)
         for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(sa, val, x, blockIdx.x, gridDim.x,
                                                   [&](int64_t row, double s) { y[row] = s; });
     else if constexpr (MODE == 3)
@@ -1039,10 +1154,10 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgPro
     double v = 0.0;
     const FE_GLOBAL double *__restrict__ p = as_global(P.w.p);
     FE_GLOBAL double *__restrict__ q = as_global(P.w.q);
-    // the Q1 traversal hands over p[row] from its LDS copy of p
+    // the Q1 traversal (modes 4, 5) hands over p[row] from its LDS copy of p
     for_rows_p<MODE, RPB, NC, VT>(P, P.w.p, lb, nb, [&](int64_t row, double s, double prow = 0.0) {
                                 q[row] = s;
-                                v += (MODE >= 4 ? prow : p[row]) * s;
+                                v += (MODE == 4 || MODE == 5 ? prow : p[row]) * s;
                             });
     // block partial: wave sums, then wave 0's lane 0 adds them in wave order
     __shared__ double wsum[rows_block(MODE) / 64];
@@ -1193,12 +1308,12 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 // ---------------------------------------------------------------------------
 static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
-    const int rows_per_run = pl.mode >= 3 ? 32 : pl.rpb;
-    const int waves = rows_block(pl.mode) / 64;
+    const int rows_per_run = pl.mode >= 3 ? 32 : pl.rpb;  // mode 6: a block per 32-row chunk
+    const int waves = pl.mode == 6 ? 1 : rows_block(pl.mode) / 64;
     const int64_t runs = (n + rows_per_run - 1) / rows_per_run;
     // the Q1 traversal: up to one block per partial slot (mode 5: exactly one
     // wave per step); the others: at most kGrid blocks
-    const int64_t cap = pl.mode >= 4 ? part_slots(n) : kGrid;
+    const int64_t cap = pl.mode == 4 || pl.mode == 5 ? part_slots(n) : kGrid;
     return int(std::max<int64_t>(1, std::min<int64_t>(cap, (runs + waves - 1) / waves)));
 }
 
@@ -1358,6 +1473,7 @@ static std::vector<SpmvPlan> struct_candidates(const SpaceArgs &sa)
     for (int r : rpws) c.push_back(SpmvPlan{2, nc, r, 64 / r});
     if ((nc == 1 && (L == 27 || L == 9 || L == 25)) || (nc == 2 && L == 18)) c.push_back(SpmvPlan{3, nc, L, 2});
     if (nc == 1 && sa.k == 1) c.push_back(SpmvPlan{4, nc, L, 2});
+    else c.push_back(SpmvPlan{6, nc, 8, 8});
     return c;
 }
 

@@ -247,3 +247,42 @@ def test_q1_staged_traversal_with_wave_strided_steps():
     assert info["status"] == F.FE_OK and infoc["status"] == F.FE_OK
     assert abs(info["iters"] - infoc["iters"]) <= 2
     assert float(torch.linalg.vector_norm(u - uc) / torch.linalg.vector_norm(uc)) <= 1e-6
+
+
+# Orders 2..4 and vector patterns: the block-staged traversal (mode 6) sums
+# every row in the order of the lanes-per-row traversal with eight rows per
+# wave (mode 2), so the products must be bitwise the same.
+@pytest.mark.parametrize("dim,n,k,prob,faces", [(3, [5, 4, 3], 2, "poisson", None), (3, [3, 3, 2], 3, "elasticity", None),
+                                                (3, [2, 3, 2], 4, "poisson", 0b011001), (3, [4, 3, 3], 2, "elasticity", 0),
+                                                (2, [9, 7], 3, "poisson", None), (2, [6, 5], 2, "elasticity", 0b0110),
+                                                (3, [7, 6, 5], 1, "elasticity", None)])
+def test_block_staged_traversal_is_bitwise_the_lanes_per_row_traversal(dim, n, k, prob, faces):
+    pair = Pair(dim, n, k, prob, faces=faces, seed=31)
+    A = pair.gpu_assembly()
+    say(f"[xblock] dim {dim} n {n} k {k} {prob} faces {faces} rows {A.n_rows}")
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(32)).standard_normal(A.n_rows)).cuda()
+    ys = []
+    F.spmv_tuning_reset()
+    try:
+        for mode in (2, 6):
+            F.spmv_plan_set_mesh(pair.mesh, k, pair.coeff, mode, 8)
+            y = torch.empty_like(x)
+            F.spmv_mesh(pair.mesh, k, pair.coeff, A.csr, x, y)
+            torch.cuda.synchronize()
+            ys.append(y)
+        # a PCG solve through the block-staged traversal (faces = 0 leaves the system singular: no solve)
+        if faces != 0:
+            ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+            u = torch.zeros_like(x)
+            info = A.solve(u, 1e-10, 20000, ws)
+            assert info["status"] == F.FE_OK
+    finally:
+        F.spmv_tuning_reset()
+    assert torch.equal(ys[0], ys[1])
+    S = pair.system
+    yo = O.spmv(S.rowptr, S.colind, S.values, x.cpu().numpy())
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x.cpu().numpy()))
+    assert np.all(np.abs(ys[1].cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+    if faces != 0:
+        xd = spla.spsolve(S.scipy().tocsc(), S.rhs)
+        assert rel(u.cpu().numpy(), xd) <= 1e-8
