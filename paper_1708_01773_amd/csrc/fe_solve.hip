@@ -965,6 +965,16 @@ static SpmvPlan launch_form(SpmvPlan pl, int64_t n)
 // The plan an evaluated-pattern system is launched with.
 static SpmvPlan struct_plan(const SpaceArgs &sa) { return launch_form(struct_plan_of_class(sa), sa.n_rows); }
 
+// Modes 4 and 5 stage the values with 16-byte loads from 16-byte boundaries
+// of the array; values not 16-byte aligned take mode 3, the same summation
+// order without wide loads.
+static SpmvPlan aligned_form(SpmvPlan pl, const void *values)
+{
+    if ((reinterpret_cast<uintptr_t>(values) & 15u) == 0) return pl;
+    if (pl.mode == 4 || pl.mode == 5) return SpmvPlan{3, pl.nc, pl.rpb, 2};
+    return pl;
+}
+
 template <int MODE, int RPW, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const VT *val,
                                          const double *x, int64_t lb, int64_t nb, Fn f)
@@ -1495,7 +1505,7 @@ fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int re
     double best_us = 0.0;
     fe_status st = FE_OK;
     for (size_t c = 0; c < cand.size() && st == FE_OK; c++) {
-        const SpmvPlan pl = launch_form(cand[c], n);
+        const SpmvPlan pl = aligned_form(launch_form(cand[c], n), values);
         const int g = grid_rows(n, pl);
         for (int r = -1; r < reps; r++) {
             if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = set_error(FE_EDEVICE, "event record failed");
@@ -1636,7 +1646,7 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
     std::vector<SpmvPlan> plans(njobs);
     for (int i = 0; i < njobs; i++) {
         if (jobs[i].sa && jobs[i].fp32) return set_error(FE_EINVAL, "structured traversal needs FP64 values");
-        plans[i] = jobs[i].sa ? struct_plan(*jobs[i].sa) : plan_for(jobs[i].n, jobs[i].nnz);
+        plans[i] = jobs[i].sa ? aligned_form(struct_plan(*jobs[i].sa), jobs[i].val) : plan_for(jobs[i].n, jobs[i].nnz);
         if (jobs[i].n > 0) order.push_back(i);
     }
     auto key = [&](int i) {
@@ -1916,7 +1926,7 @@ fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, 
 fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s)
 {
     if (sa.n_rows == 0) return FE_OK;
-    const SpmvPlan pl = struct_plan(sa);
+    const SpmvPlan pl = aligned_form(struct_plan(sa), val);
     const int g = grid_rows(sa.n_rows, pl);
     FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(sa, val, x, y)));
     FE_HIP(hipGetLastError());

@@ -251,7 +251,8 @@ def test_q1_staged_traversal_with_wave_strided_steps():
 
 # Orders 2..4 and vector patterns: the block-staged traversal (mode 6) sums
 # every row in the order of the lanes-per-row traversal with eight rows per
-# wave (mode 2), so the products must be bitwise the same.
+# wave (mode 2), so the products must be bitwise the same; also through a PCG
+# solve.
 @pytest.mark.parametrize("dim,n,k,prob,faces", [(3, [5, 4, 3], 2, "poisson", None), (3, [3, 3, 2], 3, "elasticity", None),
                                                 (3, [2, 3, 2], 4, "poisson", 0b011001), (3, [4, 3, 3], 2, "elasticity", 0),
                                                 (2, [9, 7], 3, "poisson", None), (2, [6, 5], 2, "elasticity", 0b0110),
@@ -286,3 +287,31 @@ def test_block_staged_traversal_is_bitwise_the_lanes_per_row_traversal(dim, n, k
     if faces != 0:
         xd = spla.spsolve(S.scipy().tocsc(), S.rhs)
         assert rel(u.cpu().numpy(), xd) <= 1e-8
+
+
+@pytest.mark.parametrize("dim,n,k,prob", [(3, [7, 6, 5], 1, "poisson"), (2, [17, 9], 1, "poisson"),
+                                          (3, [3, 3, 2], 2, "elasticity"), (3, [4, 3, 3], 3, "poisson")])
+def test_mesh_traversals_accept_values_off_16_byte_boundaries(dim, n, k, prob):
+    """The LDS-staged Q1 traversal stages values with 16-byte loads; values 8
+    bytes off a 16-byte boundary run the two-lane traversal (same order)."""
+    pair = Pair(dim, n, k, prob, seed=41)
+    A = pair.gpu_assembly()
+    say(f"[unaligned] dim {dim} n {n} k {k} {prob} rows {A.n_rows}")
+    buf = torch.empty(A.nnz + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = A.values[: A.nnz]
+    vals = buf[1:]
+    assert vals.data_ptr() % 16 == 8
+    C = F.csr_struct(A.n_rows, A.nnz, A.rowptr, A.colind, vals, A.rhs, A.dinv)
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(42)).standard_normal(A.n_rows)).cuda()
+    y = torch.empty_like(x)
+    F.spmv_mesh(pair.mesh, k, pair.coeff, C, x, y)
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    u = torch.zeros_like(x)
+    info = F.pcg_solve_mesh(pair.mesh, k, pair.coeff, C, A.rhs, u, 1e-10, 20000, ws)
+    torch.cuda.synchronize()
+    S = pair.system
+    yo = O.spmv(S.rowptr, S.colind, S.values, x.cpu().numpy())
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x.cpu().numpy()))
+    assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+    assert info["status"] == F.FE_OK
+    assert rel(u.cpu().numpy(), spla.spsolve(S.scipy().tocsc(), S.rhs)) <= 1e-8
