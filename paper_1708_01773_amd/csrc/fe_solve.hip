@@ -1017,26 +1017,45 @@ __device__ __forceinline__ int find_problem(const int32_t *__restrict__ boff, in
     return lo;
 }
 
-// Vector access in pairs of neighbours (16-byte loads and stores); m = 2, or
-// 1 for the last, odd element of a range.
+// Vector access in pairs of neighbours: W, 16-byte loads and stores (every
+// vector of the kernel 16-byte aligned, the kernel decides once per block),
+// else one element at a time (a caller's vector only 8-byte aligned); m = 2,
+// or 1 for the last, odd element of a range.
+__device__ __forceinline__ bool pair_aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+template <bool W>
 __device__ __forceinline__ void load_pair(const double *__restrict__ ga, int64_t i, int m, double (&o)[2])
 {
     const FE_GLOBAL double *__restrict__ a = as_global(ga);
-    if (m == 2) {
+    if (W && m == 2) {
         const fe_dpair t = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(a + i);
         o[0] = t.x;
         o[1] = t.y;
     } else {
         o[0] = a[i];
-        o[1] = 0.0;
+        o[1] = m == 2 ? a[i + 1] : 0.0;
     }
 }
 
+template <bool W>
 __device__ __forceinline__ void store_pair(double *__restrict__ ga, int64_t i, int m, const double (&v)[2])
 {
     FE_GLOBAL double *__restrict__ a = as_global(ga);
-    if (m == 2) *reinterpret_cast<FE_GLOBAL fe_dpair *>(a + i) = fe_dpair{v[0], v[1]};
-    else a[i] = v[0];
+    if (W && m == 2) {
+        *reinterpret_cast<FE_GLOBAL fe_dpair *>(a + i) = fe_dpair{v[0], v[1]};
+    } else {
+        a[i] = v[0];
+        if (m == 2) a[i + 1] = v[1];
+    }
+}
+
+// body(std::true_type) when every pointer is 16-byte aligned, else
+// body(std::false_type).
+template <typename Body>
+__device__ __forceinline__ void with_pair_width(bool aligned, Body body)
+{
+    if (aligned) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 // Visits the pairs (i, i + 1) of [lo, hi) (lo even) owned by this thread:
@@ -1212,27 +1231,32 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__res
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ r = P.w.r;
     double *__restrict__ x = P.x;
-    for_pairs(lo, hi, [&](int64_t i, int m) {
-        double pp[2], qq[2], rr[2], xx[2], dd[2];
-        load_pair(p, i, m, pp);
-        load_pair(q, i, m, qq);
-        load_pair(r, i, m, rr);
-        load_pair(x, i, m, xx);
-        load_pair(dinv, i, m, dd);
-        return [=, &v]() {
-            double xn[2], rn[2];
+    // the workspace vectors are 256-byte aligned; the caller's x and dinv may not be
+    with_pair_width(pair_aligned(x) && pair_aligned(dinv), [&](auto wide) {
+        constexpr bool W = decltype(wide)::value;
+        for_pairs(lo, hi, [&](int64_t i, int m) {
+            double pp[2], qq[2], rr[2], xx[2], dd[2];
+            load_pair<W>(p, i, m, pp);
+            load_pair<W>(q, i, m, qq);
+            load_pair<W>(r, i, m, rr);
+            load_pair<W>(x, i, m, xx);
+            load_pair<W>(dinv, i, m, dd);
+            return [=, &v]() {
+                double xn[2], rn[2];
 #pragma unroll
-            for (int e = 0; e < 2; e++) {
-                xn[e] = xx[e] + alpha * pp[e];
-                rn[e] = rr[e] - alpha * qq[e];
-                if (e < m) {
-                    v[0] += rn[e] * (dd[e] * rn[e]);
-                    v[1] += rn[e] * rn[e];
+                for (int e = 0; e < 2; e++) {
+                    // explicit fused operations: every instantiation rounds alike
+                    xn[e] = fma(alpha, pp[e], xx[e]);
+                    rn[e] = fma(-alpha, qq[e], rr[e]);
+                    if (e < m) {
+                        v[0] = fma(rn[e], dd[e] * rn[e], v[0]);
+                        v[1] = fma(rn[e], rn[e], v[1]);
+                    }
                 }
-            }
-            store_pair(x, i, m, xn);
-            store_pair(r, i, m, rn);
-        };
+                store_pair<W>(x, i, m, xn);
+                store_pair<W>(r, i, m, rn);
+            };
+        });
     });
     block_sum_all<2>(v);
     if (threadIdx.x == 0) {
@@ -1274,17 +1298,20 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
     const double *__restrict__ r = P.w.r;
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ p = P.w.p;
-    for_pairs(lo, hi, [&](int64_t i, int m) {
-        double rr[2], dd[2], pp[2];
-        load_pair(r, i, m, rr);
-        load_pair(dinv, i, m, dd);
-        load_pair(p, i, m, pp);
-        return [=]() {
-            double pn[2];
+    with_pair_width(pair_aligned(dinv), [&](auto wide) {
+        constexpr bool W = decltype(wide)::value;
+        for_pairs(lo, hi, [&](int64_t i, int m) {
+            double rr[2], dd[2], pp[2];
+            load_pair<W>(r, i, m, rr);
+            load_pair<W>(dinv, i, m, dd);
+            load_pair<W>(p, i, m, pp);
+            return [=]() {
+                double pn[2];
 #pragma unroll
-            for (int e = 0; e < 2; e++) pn[e] = dd[e] * rr[e] + beta * pp[e];
-            store_pair(p, i, m, pn);
-        };
+                for (int e = 0; e < 2; e++) pn[e] = fma(beta, pp[e], dd[e] * rr[e]);
+                store_pair<W>(p, i, m, pn);
+            };
+        });
     });
 }
 

@@ -315,3 +315,18 @@ def test_mesh_traversals_accept_values_off_16_byte_boundaries(dim, n, k, prob):
     assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
     assert info["status"] == F.FE_OK
     assert rel(u.cpu().numpy(), spla.spsolve(S.scipy().tocsc(), S.rhs)) <= 1e-8
+    # solution and Jacobi diagonal 8 bytes off 16-byte boundaries: the vector
+    # kernels fall back to single accesses, same arithmetic, bitwise the same
+    ua = torch.zeros_like(x)
+    ia = F.pcg_solve_mesh(pair.mesh, k, pair.coeff, A.csr, A.rhs, ua, 1e-10, 20000, ws)
+    xb = torch.zeros(A.n_rows + 1, dtype=torch.float64, device="cuda")
+    db = torch.empty(A.n_rows + 1, dtype=torch.float64, device="cuda")
+    db[1:] = A.dinv[: A.n_rows]
+    um, dm = xb[1:], db[1:]
+    assert um.data_ptr() % 16 == 8 and dm.data_ptr() % 16 == 8
+    Cm = F.csr_struct(A.n_rows, A.nnz, A.rowptr, A.colind, A.values, A.rhs, dm)
+    im = F.pcg_solve_mesh(pair.mesh, k, pair.coeff, Cm, A.rhs, um, 1e-10, 20000, ws)
+    ic = F.pcg_solve(Cm, A.rhs, torch.zeros_like(x), 1e-10, 20000, ws)
+    torch.cuda.synchronize()
+    assert ia["status"] == im["status"] == ic["status"] == F.FE_OK and ia["iters"] == im["iters"]
+    assert torch.equal(ua, um)
