@@ -225,7 +225,11 @@ fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes);
  * entry and the solution on exit (device, n_rows).  Stops when
  * ||r_j||_2 <= rtol ||b||_2 or after maxit iterations.  Reductions are
  * deterministic (fixed-order two-stage sums, no float atomics).  Synchronizes
- * before returning (info is host memory).  Returns info->status. */
+ * before returning (info is host memory).  Returns info->status.
+ * Alignment: device arrays need the alignment of their element type; the
+ * workspace 8 bytes (FE_EINVAL otherwise).  Vectors and workspace that are
+ * 16-byte aligned (any device allocation is) get 16-byte vector accesses,
+ * others single accesses with the same results. */
 fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
                        size_t ws_bytes, fe_solve_info *info, fe_stream stream);
 

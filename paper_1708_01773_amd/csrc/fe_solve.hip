@@ -1231,8 +1231,9 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__res
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ r = P.w.r;
     double *__restrict__ x = P.x;
-    // the workspace vectors are 256-byte aligned; the caller's x and dinv may not be
-    with_pair_width(pair_aligned(x) && pair_aligned(dinv), [&](auto wide) {
+    // vectors of the caller (x, dinv) and of its workspace (p, q, r) may each be only 8-byte aligned
+    with_pair_width(pair_aligned(x) && pair_aligned(dinv) && pair_aligned(p) && pair_aligned(q) && pair_aligned(r),
+                    [&](auto wide) {
         constexpr bool W = decltype(wide)::value;
         for_pairs(lo, hi, [&](int64_t i, int m) {
             double pp[2], qq[2], rr[2], xx[2], dd[2];
@@ -1298,7 +1299,7 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
     const double *__restrict__ r = P.w.r;
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ p = P.w.p;
-    with_pair_width(pair_aligned(dinv), [&](auto wide) {
+    with_pair_width(pair_aligned(dinv) && pair_aligned(r) && pair_aligned(p), [&](auto wide) {
         constexpr bool W = decltype(wide)::value;
         for_pairs(lo, hi, [&](int64_t i, int m) {
             double rr[2], dd[2], pp[2];
@@ -1433,6 +1434,7 @@ fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe
 {
     const int64_t n = A->n_rows;
     if (ws_bytes < autotune_ws_bytes(n)) return set_error(FE_EINVAL, "autotune workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     double *x = static_cast<double *>(ws);
     double *y = reinterpret_cast<double *>(static_cast<char *>(ws) + align256(size_t(std::max<int64_t>(n, 1)) * 8));
     if (n_tried) *n_tried = 0;
@@ -1521,6 +1523,7 @@ fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int re
     if (n_tried) *n_tried = 0;
     if (n == 0) return set_error(FE_EINVAL, "empty system");
     if (ws_bytes < autotune_ws_bytes(n)) return set_error(FE_EINVAL, "autotune workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     double *x = static_cast<double *>(ws);
     double *y = reinterpret_cast<double *>(static_cast<char *>(ws) + align256(size_t(n) * 8));
     FE_HIP(hipMemsetAsync(x, 0, sizeof(double) * size_t(n), s));
@@ -1928,6 +1931,7 @@ static fe_status pcg_run(int64_t n, int64_t nnz, const int64_t *rowptr, const in
                          size_t ws_bytes, fe_solve_info *info, hipStream_t s, const SpaceArgs *sa = nullptr)
 {
     if (ws_bytes < pcg_ws_bytes(n) + engine_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     std::vector<PcgJob> jobs(1);
     jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit, sa};
     void *table = static_cast<char *>(ws) + pcg_ws_bytes(n);
@@ -1969,6 +1973,7 @@ fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, do
     size_t need = engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) need += pcg_ws_bytes(A[i].n_rows);
     if (ws_bytes < need) return set_error(FE_EINVAL, "batch pcg workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     std::vector<PcgJob> jobs(nprob);
     char *p = static_cast<char *>(ws) + engine_table_bytes(nprob);
     for (int i = 0; i < nprob; i++) {
@@ -2051,6 +2056,7 @@ fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values
     const int64_t n = Ahi->n_rows;
     std::memset(info, 0, sizeof(*info));
     if (ws_bytes < refine_ws_bytes(n)) return set_error(FE_EINVAL, "refinement workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     if (Alo->n_rows != n || Alo->nnz != Ahi->nnz) return set_error(FE_EINVAL, "A_lo must have the pattern of A_hi");
     if (n == 0) return FE_OK;
     static thread_local PinnedState pin;

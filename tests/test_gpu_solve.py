@@ -330,3 +330,14 @@ def test_mesh_traversals_accept_values_off_16_byte_boundaries(dim, n, k, prob):
     torch.cuda.synchronize()
     assert ia["status"] == im["status"] == ic["status"] == F.FE_OK and ia["iters"] == im["iters"]
     assert torch.equal(ua, um)
+    # workspace 8 bytes off a 16-byte boundary (its p, q, r with it): same
+    # arithmetic, bitwise the same; 4 bytes off: refused before any launch
+    wb = torch.empty(ws.numel() + 16, dtype=torch.uint8, device="cuda")
+    w8 = wb[8 : 8 + ws.numel()]
+    assert w8.data_ptr() % 16 == 8
+    uw = torch.zeros_like(x)
+    iw = F.pcg_solve_mesh(pair.mesh, k, pair.coeff, A.csr, A.rhs, uw, 1e-10, 20000, w8)
+    torch.cuda.synchronize()
+    assert iw["status"] == F.FE_OK and iw["iters"] == ia["iters"] and torch.equal(ua, uw)
+    with pytest.raises(F.FeError, match="8-byte"):
+        F.pcg_solve_mesh(pair.mesh, k, pair.coeff, A.csr, A.rhs, uw, 1e-10, 20000, wb[4 : 4 + ws.numel()])
