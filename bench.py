@@ -52,7 +52,10 @@ def spmv_bytes(n, nnz, mode="csr"):
     """Algorithmic HBM bytes of one SpMV.  csr: values + column indices, row
     pointers, the input vector once and the output vector.  mesh (pattern
     evaluated from the mesh): values, the input vector once and the output
-    vector."""
+    vector.  sym (symmetric storage): the upper triangle's values (diagonal
+    included) once, the input vector once and the output vector."""
+    if mode == "sym":
+        return (nnz + n) // 2 * 8 + 16 * n
     if mode == "mesh":
         return nnz * 8 + 16 * n
     return nnz * 12 + (n + 1) * 8 + 16 * n
@@ -327,9 +330,11 @@ def main():
     ap.add_argument("--phase", default="step", choices=["step", "assemble"],
                     help="step = assemble + PCG (default); assemble = assembly only, K3 against the matrix-core peak")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--spmv", default="mesh", choices=["mesh", "csr"],
-                    help="mesh: pattern evaluated from the mesh (fe_pcg_solve_mesh); csr: row pointers and column "
-                         "indices read (fe_pcg_solve)")
+    ap.add_argument("--spmv", default="sym", choices=["sym", "mesh", "csr"],
+                    help="sym: Q1 scalar systems in symmetric storage, filled from the assembled CSR inside the "
+                         "step (fe_sym_from_csr + fe_pcg_solve_sym; other spaces fall back to mesh); mesh: pattern "
+                         "evaluated from the mesh (fe_pcg_solve_mesh); csr: row pointers and column indices read "
+                         "(fe_pcg_solve)")
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="problems of the 512-problem batch run by the batching form (0 = skip)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0, help="device memory per batch wave")
@@ -390,6 +395,11 @@ def main():
     coeff = F.make_coeff(wl["problem"], wl["precision"], source_kind=wl.get("source_kind", 1), source=src, dim=dim)
     A = F.Assembly(mesh, k, coeff)
     A.pattern()
+    if args.spmv == "sym" and not (k == 1 and wl["problem"] == "poisson"):
+        args.spmv = "mesh"
+    sym = None
+    if args.spmv == "sym" and args.phase == "step":
+        sym = torch.empty(F.sym_query(mesh, k, coeff) // 8, dtype=torch.float64, device="cuda")
     ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
     x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -401,30 +411,37 @@ def main():
     def step():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         A.assemble(stream)
         e1.record(stream)
+        if sym is not None:
+            F.sym_from_csr(mesh, k, coeff, A.csr, sym, stream)
+        e2.record(stream)
         x.zero_()
-        if args.spmv == "mesh":
+        if sym is not None:
+            info = F.pcg_solve_sym(mesh, k, coeff, A.csr, sym, A.rhs, x, wl["rtol"], 100000, ws, stream)
+        elif args.spmv == "mesh":
             info = A.solve(x, wl["rtol"], 100000, ws, stream)
         else:
             info = F.pcg_solve(A.csr, A.rhs, x, wl["rtol"], 100000, ws, stream)
-        return info, e0, e1
+        return info, e0, e1, e2
 
     for i in range(args.warmup):
-        info, _, _ = step()
+        info, _, _, _ = step()
         print(f"[bench] warmup {i}: iters={info['iters']} relres={info['relres']:.2e}", file=sys.stderr, flush=True)
     F.set_timing(True)
     F.get_timing(reset=True)
     torch.cuda.synchronize()
-    lat, asm_ms, iters = [], [], []
+    lat, asm_ms, fill_ms, iters = [], [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        info, e0, e1 = step()
+        info, e0, e1, e2 = step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         asm_ms.append(e0.elapsed_time(e1))
+        fill_ms.append(e1.elapsed_time(e2))
         iters.append(info["iters"])
         if info["status"] != F.FE_OK:
             print(f"[bench] step {i}: solver status {info['status']}", file=sys.stderr, flush=True)
@@ -438,7 +455,7 @@ def main():
     spmv_avg_s = tm["spmv_ms"] / max(tm["spmv_calls"], 1) * 1e-3
     sb = spmv_bytes(A.n_rows, A.nnz, args.spmv)
     achieved = sb / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
-    kname = "pcg_spmv_kernel/mesh" if args.spmv == "mesh" else "pcg_spmv_kernel/csr"
+    kname = "pcg_spmv_kernel/" + args.spmv
     traffic = traffic_for(kname, args.workload)
     lat_sorted = sorted(lat)
     p99 = lat_sorted[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
@@ -455,17 +472,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["text"], "cells": ncells, "order": k, "dofs": A.n_rows, "nnz": A.nnz},
+        "config": {"workload": wl["text"], "cells": ncells, "order": k, "dofs": A.n_rows, "nnz": A.nnz,
+                   "operator_storage": {"sym": "symmetric (upper triangle)", "mesh": "CSR values",
+                                        "csr": "CSR"}[args.spmv]},
         "assembly": {"ms_mean": statistics.mean(asm_ms),
                      "elements_per_s": ncells / (statistics.mean(asm_ms) * 1e-3),
                      "integrate_ms": tm["integrate_ms"] / max(tm["integrate_calls"], 1),
-                     "scatter_ms": tm["scatter_ms"] / max(tm["scatter_calls"], 1)},
+                     "scatter_ms": tm["scatter_ms"] / max(tm["scatter_calls"], 1),
+                     "sym_fill_ms": statistics.mean(fill_ms) if sym is not None else None},
         "solve": {"pcg_iters": statistics.mean(iters), "relres": info["relres"],
                   "true_relres": info["true_relres"], "solves_per_s": args.steps / total,
                   "p50_ms": statistics.median(lat) * 1e3, "p99_ms": p99 * 1e3,
                   "kappa_est": info["lambda_max_est"] / info["lambda_min_est"] if info["lambda_min_est"] else None},
-        "roofline": {"kernel": kname, "traversal": "pattern evaluated from the mesh" if args.spmv == "mesh" else
-                     "CSR row pointers and column indices read", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": kname, "traversal": {
+                         "sym": "symmetric storage (upper triangle, slot-major), pattern evaluated from the mesh",
+                         "mesh": "CSR values, pattern evaluated from the mesh",
+                         "csr": "CSR row pointers and column indices read"}[args.spmv], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": sb, "avg_launch_us": spmv_avg_s * 1e6,
                      "launches": tm["spmv_calls"]},
@@ -474,7 +496,7 @@ def main():
         print("[bench] mixed-precision form", file=sys.stderr, flush=True)
         out["forms"] = {"mixed_refine": mixed_form(args, wl, mesh, A, x, F, torch, stream, ncells)}
         if args.batch_sample > 0 and args.workload == "c2":
-            del A, ws, x
+            del A, ws, x, sym
             torch.cuda.empty_cache()
             out["forms"]["batch"] = batch_form(args, F, torch)
         if args.serve_requests > 0 and args.workload == "c2":

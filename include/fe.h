@@ -281,6 +281,46 @@ fe_status fe_pcg_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const in
                                   int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, fe_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* Symmetric storage (Q1 scalar systems)                                     */
+/* ------------------------------------------------------------------------ */
+/* The FE operator may keep only the upper triangle of a symmetric matrix
+ * (Sect. 11.3; the driver of Sect. 12 asks for it).  For a Q1 scalar system
+ * assembled on a structured brick (order 1, Poisson) the upper triangle is
+ * kept slot-major: with g = 9 (dz + 1) + 3 (dy + 1) + (dx + 1) the code of a
+ * neighbour offset (g = 3 (dy + 1) + (dx + 1) in 2D) and C = 13 (4 in 2D),
+ * slot s = g - C of row r holds A[r, r + dx + f0 dy + f0 f1 dz] at
+ * sym[s * stride + r], stride = n_rows rounded up to a multiple of 64, f0, f1
+ * the free nodes per line and per plane; slot 0 is the diagonal; 14 slots in
+ * 3D, 5 in 2D; an entry whose neighbour is not a free node holds 0.  A lower
+ * entry is read as the upper entry of the neighbour's row, so the operator is
+ * the symmetric matrix with A's upper triangle: half the value bytes of the
+ * CSR per SpMV.
+ *   fe_sym_query: *bytes of the storage of (mesh, order, coeff); FE_EINVAL
+ *     unless order 1 and a scalar problem.
+ *   fe_sym_from_csr: sym (device, >= fe_sym_query bytes, 8-byte aligned,
+ *     owned by the caller) = the upper triangle of A, assembled by this
+ *     library on (mesh, order, coeff) (values read, rowptr / colind not);
+ *     asynchronous on stream.
+ *   fe_spmv_sym: y = A x from sym (x, y device, n_rows each).  Each row is
+ *     summed in the order of the Q1 traversal of fe_spmv_mesh, so for a
+ *     bitwise symmetric A (as assembled here) y is bitwise that of
+ *     fe_spmv_mesh.  Asynchronous.
+ *   fe_pcg_solve_sym: Jacobi-PCG of A x = b with A applied from sym and the
+ *     diagonal inverse read from A->dinv (A->values, rowptr, colind not
+ *     read); workspace of fe_pcg_query(n_rows) bytes; for a bitwise symmetric
+ *     A the iterates are bitwise those of fe_pcg_solve_mesh.  Synchronizes.
+ * Errors (FE_EINVAL, nothing launched): not Q1 scalar, sym too small, null
+ * or not 8-byte aligned, csr sizes not those of fe_assemble_query. */
+fe_status fe_sym_query(fe_mesh mesh, int32_t order, const fe_coeff *coeff, size_t *bytes);
+fe_status fe_sym_from_csr(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A, double *sym,
+                          size_t sym_bytes, fe_stream stream);
+fe_status fe_spmv_sym(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const double *sym, size_t sym_bytes,
+                      const double *x, double *y, fe_stream stream);
+fe_status fe_pcg_solve_sym(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A, const double *sym,
+                           size_t sym_bytes, const double *b, double *x, double rtol, int32_t maxit, void *ws,
+                           size_t ws_bytes, fe_solve_info *info, fe_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* SpMV plans and their autotuner                                            */
 /* ------------------------------------------------------------------------ */
 /* A plan is how the CSR SpMV of fe_spmv / fe_pcg_solve / fe_pcg_solve_batch

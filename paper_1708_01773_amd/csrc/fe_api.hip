@@ -734,6 +734,69 @@ fe_status fe_spmv_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr
     return launch_spmv_struct(m->space.args, A->values, x, y, as_stream(stream));
 }
 
+fe_status fe_sym_query(fe_mesh m, int32_t order, const fe_coeff *c, size_t *bytes)
+{
+    if (!bytes) return set_error(FE_EINVAL, "null argument");
+    *bytes = 0;
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    if (!sym_supported(m->space.args)) return set_error(FE_EINVAL, "symmetric storage needs a Q1 scalar space");
+    *bytes = sym_bytes(m->space.args);
+    return FE_OK;
+}
+
+// The symmetric-storage calls share their checks: a Q1 scalar space, a buffer
+// of fe_sym_query's size, 8-byte aligned.
+static fe_status check_sym(fe_mesh m, int32_t order, const fe_coeff *c, const void *sym, size_t sym_bytes_given)
+{
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    const SpaceArgs &sa = m->space.args;
+    if (!sym_supported(sa)) return set_error(FE_EINVAL, "symmetric storage needs a Q1 scalar space");
+    if (sym_bytes_given < sym_bytes(sa)) return set_error(FE_EINVAL, "symmetric storage buffer too small");
+    if (sa.n_rows > 0 && !sym) return set_error(FE_EINVAL, "null symmetric storage");
+    if (reinterpret_cast<uintptr_t>(sym) & 7u) return set_error(FE_EINVAL, "symmetric storage not 8-byte aligned");
+    return FE_OK;
+}
+
+fe_status fe_sym_from_csr(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, double *sym,
+                          size_t sym_bytes_given, fe_stream stream)
+{
+    if (!A) return set_error(FE_EINVAL, "null argument");
+    fe_status st = check_sym(m, order, c, sym, sym_bytes_given);
+    if (st != FE_OK) return st;
+    st = check_csr(A, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (A->nnz > 0 && !A->values) return set_error(FE_EINVAL, "null csr values");
+    m->last_stream = as_stream(stream);
+    return launch_sym_fill(m->space.args, A->values, sym, as_stream(stream));
+}
+
+fe_status fe_spmv_sym(fe_mesh m, int32_t order, const fe_coeff *c, const double *sym, size_t sym_bytes_given,
+                      const double *x, double *y, fe_stream stream)
+{
+    fe_status st = check_sym(m, order, c, sym, sym_bytes_given);
+    if (st != FE_OK) return st;
+    if (m->space.args.n_rows > 0 && (!x || !y)) return set_error(FE_EINVAL, "null argument");
+    m->last_stream = as_stream(stream);
+    return launch_spmv_sym(m->space.args, sym, x, y, as_stream(stream));
+}
+
+fe_status fe_pcg_solve_sym(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, const double *sym,
+                           size_t sym_bytes_given, const double *b, double *x, double rtol, int32_t maxit, void *ws,
+                           size_t ws_bytes, fe_solve_info *info, fe_stream stream)
+{
+    if (!A || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    fe_status st = check_sym(m, order, c, sym, sym_bytes_given);
+    if (st != FE_OK) return st;
+    st = check_csr(A, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (A->n_rows > 0 && !A->dinv) return set_error(FE_EINVAL, "null csr dinv");
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    m->last_stream = as_stream(stream);
+    return pcg_solve_sym(A, m->space.args, sym, b, x, rtol, maxit, ws, ws_bytes, info, as_stream(stream));
+}
+
 fe_status fe_pcg_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const int32_t *orders, const fe_coeff *coeffs,
                                   const fe_csr *A, const double *const *b, double *const *x, double rtol,
                                   int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *infos, fe_stream stream)

@@ -187,6 +187,7 @@ struct PcgJob {
     double rtol;
     int maxit;
     const SpaceArgs *sa = nullptr;  // structured pattern of a mesh-assembled system (FP64 values), or null
+    bool sym = false;               // val is the symmetric storage of a Q1 scalar system on sa
 };
 struct EngineSet;
 EngineSet *engine_create();
@@ -214,6 +215,12 @@ fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, do
 fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,
                          void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s);
 fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s);
+bool sym_supported(const SpaceArgs &sa);
+size_t sym_bytes(const SpaceArgs &sa);
+fe_status launch_sym_fill(const SpaceArgs &sa, const double *val, double *sym, hipStream_t s);
+fe_status launch_spmv_sym(const SpaceArgs &sa, const double *sym, const double *x, double *y, hipStream_t s);
+fe_status pcg_solve_sym(const fe_csr *A, const SpaceArgs &sa, const double *sym, const double *b, double *x,
+                        double rtol, int maxit, void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s);
 size_t autotune_ws_bytes(int64_t n);
 fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe_spmv_plan *tried, int max_tried,
                         int *n_tried, fe_spmv_plan *chosen, hipStream_t s);

@@ -96,7 +96,9 @@ struct SpmvPlan {
                // 3: structured short rows, two lanes per row (rpb = longest row),
                // 4: structured Q1 scalar rows, values and x runs staged in LDS (rpb = longest row),
                // 5: mode 4 with one wave step per wave (launch form only),
-               // 6: structured rows, x of a 32-row chunk's column box staged per block (rpb 8)
+               // 6: structured rows, x of a 32-row chunk's column box staged per block (rpb 8),
+               // 7: Q1 scalar rows of a system in symmetric storage (rpb = longest row),
+               // 8: mode 7 with one wave step per wave (launch form only)
     int nc = 1;  // components (mode 2)
     int rpb;   // rows per wave-iteration (stream mode)
     int lanes; // lanes per row
@@ -107,7 +109,8 @@ struct SpmvPlan {
 // block of the Q1 traversal (128 rows each) up to kPartMax.
 static int32_t part_slots(int64_t n)
 {
-    return int32_t(std::max<int64_t>(kGrid, std::min<int64_t>(kPartMax, (n + 127) / 128)));
+    // a multiple of 8: the symmetric Q1 traversal pads its grid to one
+    return int32_t(std::max<int64_t>(kGrid, std::min<int64_t>(kPartMax, ((n + 127) / 128 + 7) / 8 * 8)));
 }
 
 size_t pcg_ws_bytes(int64_t n)
@@ -763,6 +766,214 @@ __device__ __forceinline__ void for_rows_q1(const SpaceArgs &s, const double *__
     }
 }
 
+// Symmetric storage of a Q1 scalar system (the paper's option of keeping
+// only the upper triangle of a symmetric matrix): with g(d) = 9 (dz + 1) +
+// 3 (dy + 1) + (dx + 1) the code of a neighbour offset, the columns of a row
+// in ascending order are the offsets in ascending g, and those with g >= C
+// (C = 13, or 4 in 2D; C is the row's own node) form the upper triangle.
+// Slot s = g - C of row r holds A[r, r + off(d)] at sym[s * stride + r]
+// (slot-major, stride = n rounded up to 64; slot 0 is the diagonal, an entry
+// whose neighbour is not free holds 0 and is never read).  A lower entry
+// A[r, r + off(d)], g < C, is the upper entry of row r + off(d) at slot C - g.
+constexpr int sym_slots(int dim) { return dim == 3 ? 14 : 5; }
+__host__ __device__ constexpr int64_t sym_stride(int64_t n) { return (n + 63) / 64 * 64; }
+
+// Rows of a Q1 scalar system in symmetric storage (plan mode 7; mode 8 is
+// its instantiation with one step per wave).  The steps, rows, lanes and x
+// runs of the Q1 traversal, its positions in the same order and the same
+// products, so both give bitwise the same sums of a symmetric matrix; each
+// lane loads the values of its positions straight from the slots: for a
+// position shared by the rows of a step the 32 loads are consecutive, as a
+// slot holds its rows in order.
+template <int DIM, bool ONE, typename Fn>
+__device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double *__restrict__ gval,
+                                               const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+{
+    using S = Q1Step<DIM>;
+    constexpr int C = DIM == 3 ? 13 : 4;
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
+    __shared__ double xst[kQ1Waves][S::XS];
+    double *mx = xst[threadIdx.x / 64];
+    const int lane = threadIdx.x % 64, rl = lane % S::RW, h = lane / S::RW;
+    const int64_t n = s.n_rows, ns = sym_stride(n);
+    const int64_t nw = nb * kQ1Waves, lw = lb * kQ1Waves + threadIdx.x / 64;
+    const int64_t runs = (n + S::RW - 1) / S::RW;
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * 2 + A[r].lo;
+    }
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const double f0inv = s.ax[0].finv, f1inv = s.ax[1].finv;
+    const int64_t plane = int64_t(f0) * f1;
+    auto step = [&](int64_t run) {
+        const int64_t r0 = run * S::RW, row = r0 + rl;
+        const bool live = row < n;
+        int32_t len = 0, wx = 1, w1 = 1, e0 = 0, e1 = 0, e2 = 0;
+        if (live) {
+            const int32_t r32 = int32_t(row);
+            const int32_t q = div_exact(r32, f0, f0inv), t0 = r32 - q * f0;
+            const int32_t t2 = div_exact(q, f1, f1inv), t1 = q - t2 * f1;
+            int32_t w0, w2, cl0, cl1, cl2, P0, P1, P2;
+            axis_row(A[0], 1, 1.0, A[0].lo + t0, w0, cl0, P0);
+            axis_row(A[1], 1, 1.0, A[1].lo + t1, w1, cl1, P1);
+            axis_row(A[2], 1, 1.0, A[2].lo + t2, w2, cl2, P2);
+            wx = w0;
+            len = w0 * w1 * w2;
+            e0 = cl0 - (A[0].lo + t0) + 1;
+            e1 = cl1 - (A[1].lo + t1) + 1;
+            e2 = DIM == 3 ? cl2 - (A[2].lo + t2) + 1 : 0;
+        }
+        double xs[S::XCH];
+#pragma unroll
+        for (int u = 0; u < S::XCH; u++) {
+            const int i = lane + 64 * u;
+            const int sg = i / S::SEG, kk = i - sg * S::SEG;
+            const int dy = sg % 3 - 1, dz = sg / 3 - 1;
+            int64_t a = r0 + kk - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0);
+            a = a < 0 ? 0 : (a >= n ? n - 1 : a);  // slots past either end are never read
+            xs[u] = x[a];
+        }
+        double vv[S::H];
+        int32_t xi[S::H];
+        if (__all(len == S::L)) {
+            // every row of the step has its full box: position p is code g = p,
+            // so a lane's loads are its row plus offsets common to the wave
+#pragma unroll
+            for (int t = 0; t < S::H; t++) {
+                const int ga = t, gb = S::H + t < S::L ? S::H + t : 0;
+                const int oa0 = ga % 3 - 1, oa1 = (ga / 3) % 3 - 1, oa2 = DIM == 3 ? ga / 9 - 1 : 0;
+                const int ob0 = gb % 3 - 1, ob1 = (gb / 3) % 3 - 1, ob2 = DIM == 3 ? gb / 9 - 1 : 0;
+                const int64_t ka = ga >= C ? int64_t(ga - C) * ns
+                                           : int64_t(C - ga) * ns + oa0 + int64_t(oa1) * f0 + int64_t(oa2) * plane;
+                const int64_t kb = int64_t(gb - C) * ns;
+                const int xa = (DIM == 3 ? (oa1 + 1) + 3 * (oa2 + 1) : oa1 + 1) * S::SEG + oa0 + 1;
+                const int xb = (DIM == 3 ? (ob1 + 1) + 3 * (ob2 + 1) : ob1 + 1) * S::SEG + ob0 + 1;
+                const bool ok = h == 0 || S::H + t < S::L;
+                xi[t] = (h ? xb : xa) + rl;
+                vv[t] = ok ? val[row + (h ? kb : ka)] : 0.0;
+            }
+        } else {
+            const uint32_t m0 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
+            const uint32_t m1 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
+#pragma unroll
+            for (int t = 0; t < S::H; t++) {
+                const int32_t pos = h * S::H + t;
+                const bool ok = pos < len;
+                const int32_t pc = ok ? pos : 0;
+                const int32_t qy = int32_t((uint32_t(pc) * m0) >> 20);
+                const int32_t j0 = pc - qy * wx;
+                const int32_t j2 = int32_t((uint32_t(qy) * m1) >> 20);
+                const int32_t j1 = qy - j2 * w1;
+                const int32_t o0 = e0 + j0 - 1, o1 = e1 + j1 - 1, o2 = DIM == 3 ? e2 + j2 - 1 : 0;
+                const int32_t g = DIM == 3 ? 9 * (o2 + 1) + 3 * (o1 + 1) + (o0 + 1) : 3 * (o1 + 1) + (o0 + 1);
+                const int32_t sg = DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1;
+                xi[t] = sg * S::SEG + rl + o0 + 1;
+                const int64_t at = g >= C ? int64_t(g - C) * ns + row
+                                          : int64_t(C - g) * ns + row + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
+                vv[t] = ok ? val[at] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < S::XCH; u++)
+            if (lane + 64 * u < S::XS) mx[lane + 64 * u] = xs[u];
+        wave_lds_sync();
+        double sum = 0.0;
+#pragma unroll
+        for (int t = 0; t < S::H; t++) sum += vv[t] * mx[xi[t]];
+        const double upper = __shfl(sum, (lane + S::RW) % 64);
+        if (h == 0 && live) {
+            if constexpr (std::is_invocable_v<Fn, int64_t, double, double>)
+                f(row, sum + upper, mx[(DIM == 3 ? 4 : 1) * S::SEG + rl + 1]);
+            else
+                f(row, sum + upper);
+        }
+        wave_lds_sync();
+    };
+    if constexpr (ONE) {
+        if (lw < runs) step(lw);
+    } else {
+        for (int64_t run = lw; run < runs; run += nw) step(run);
+    }
+}
+
+// sym = the upper triangle of a Q1 scalar system assembled on the mesh, in the
+// symmetric storage above.  A wave takes 32 consecutive rows (of the slot
+// stride): their values, contiguous in CSR, are loaded into LDS with
+// coalesced loads; then each half-wave writes half of the slots, one row per
+// lane (rows past n and neighbours that are not free get 0).
+template <int DIM>
+__global__ __launch_bounds__(kQ1Block) void sym_fill_kernel(SpaceArgs s, const double *__restrict__ gval,
+                                                            double *__restrict__ gsym)
+{
+    using S = Q1Step<DIM>;
+    constexpr int C = DIM == 3 ? 13 : 4, NS = C + 1, SH = (NS + 1) / 2;
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    FE_GLOBAL double *__restrict__ sym = as_global(gsym);
+    __shared__ double vst[kQ1Waves][S::CAP];
+    double *mv = vst[threadIdx.x / 64];
+    const int lane = threadIdx.x % 64, rl = lane % S::RW, h = lane / S::RW;
+    const int64_t n = s.n_rows, ns = sym_stride(n);
+    const int64_t run = int64_t(blockIdx.x) * kQ1Waves + threadIdx.x / 64;
+    const int64_t r0 = run * S::RW, row = r0 + rl;
+    if (r0 >= ns) return;
+    AxisClosed A[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A[r].lo = int32_t(s.ax[r].lo);
+        A[r].hi = int32_t(s.ax[r].lo + s.ax[r].f - 1);
+        A[r].N = int32_t(s.ax[r].N);
+        A[r].swlo = A[r].lo * 2 + A[r].lo;
+    }
+    const int32_t f0 = int32_t(s.ax[0].f), f1 = int32_t(s.ax[1].f);
+    const int64_t T0 = s.ax[0].T, T1 = s.ax[1].T;
+    const bool live = row < n;
+    int64_t start = 0;
+    int32_t len = 0, w[3] = {1, 1, 1}, e[3] = {0, 0, 0};
+    if (live) {
+        const int32_t r32 = int32_t(row);
+        const int32_t q = r32 / f0, t0 = r32 - q * f0;
+        const int32_t t2 = q / f1, t1 = q - t2 * f1;
+        int32_t cl[3], P[3];
+        axis_row(A[0], 1, 1.0, A[0].lo + t0, w[0], cl[0], P[0]);
+        axis_row(A[1], 1, 1.0, A[1].lo + t1, w[1], cl[1], P[1]);
+        axis_row(A[2], 1, 1.0, A[2].lo + t2, w[2], cl[2], P[2]);
+        start = int64_t(P[2]) * T1 * T0 + int64_t(w[2]) * P[1] * T0 + int64_t(w[2] * w[1]) * P[0];
+        len = w[0] * w[1] * w[2];
+        e[0] = cl[0] - (A[0].lo + t0) + 1;
+        e[1] = cl[1] - (A[1].lo + t1) + 1;
+        e[2] = DIM == 3 ? cl[2] - (A[2].lo + t2) + 1 : 0;
+    }
+    const int nv = int(n - r0 <= 0 ? 0 : (n - r0 < S::RW ? n - r0 : S::RW));
+    int64_t base = 0;
+    int total = 0;
+    if (nv > 0) {
+        base = __shfl(start, 0);
+        total = int(__shfl(start, nv - 1) - base) + __shfl(len, nv - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < (S::CAP + 63) / 64; u++) {
+        const int i = lane + 64 * u;
+        if (i < total) mv[i] = val[base + i];
+    }
+    wave_lds_sync();
+    const int off = int(start - base);
+#pragma unroll
+    for (int t = 0; t < SH; t++) {
+        const int sl = h * SH + t;
+        if (sl >= NS) continue;
+        const int g = C + sl;
+        const int32_t o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
+        const int32_t j0 = o0 + 1 - e[0], j1 = o1 + 1 - e[1], j2 = DIM == 3 ? o2 + 1 - e[2] : 0;
+        const bool ok = live && j0 >= 0 && j0 < w[0] && j1 >= 0 && j1 < w[1] && j2 >= 0 && j2 < w[2];
+        sym[sl * ns + row] = ok ? mv[off + (j2 * w[1] + j1) * w[0] + j0] : 0.0;
+    }
+}
+
 // Rows of any evaluated pattern, x staged per block (plan mode 6).  A block
 // takes a chunk of kXbRows consecutive rows of one line of nodes (t1, t2
 // fixed): their column boxes share the y and z ranges, and their x ranges lie
@@ -863,6 +1074,10 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double
 // structured plans (FP64 values only).
 #define FE_SPLAN_DISPATCH(PL, BODY)                                                            \
     switch ((PL).mode * 1000 + (PL).nc * 100 + (PL).rpb) {                                     \
+        case 8127: FE_PLAN_CASE(8, 27, 1, BODY)                                                \
+        case 8109: FE_PLAN_CASE(8, 9, 1, BODY)                                                 \
+        case 7127: FE_PLAN_CASE(7, 27, 1, BODY)                                                \
+        case 7109: FE_PLAN_CASE(7, 9, 1, BODY)                                                 \
         case 6108: FE_PLAN_CASE(6, 8, 1, BODY)                                                 \
         case 6208: FE_PLAN_CASE(6, 8, 2, BODY)                                                 \
         case 6308: FE_PLAN_CASE(6, 8, 3, BODY)                                                 \
@@ -954,11 +1169,11 @@ static SpmvPlan struct_plan_of_class(const SpaceArgs &sa)
     return pl;
 }
 
-// The launch form of a plan: mode 4 becomes its one-step-per-wave
-// instantiation (mode 5) when the partial slots hold a block per 128 rows.
+// The launch form of a plan: mode 4 (7) becomes its one-step-per-wave
+// instantiation, mode 5 (8), when the partial slots hold a block per 128 rows.
 static SpmvPlan launch_form(SpmvPlan pl, int64_t n)
 {
-    if (pl.mode == 4 && (n + 127) / 128 <= part_slots(n)) pl.mode = 5;
+    if ((pl.mode == 4 || pl.mode == 7) && (n + 127) / 128 <= part_slots(n)) pl.mode++;
     return pl;
 }
 
@@ -989,7 +1204,9 @@ __device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const
 template <int MODE, int RPB, int NC, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
 {
-    if constexpr (MODE == 6)
+    if constexpr (MODE == 7 || MODE == 8)
+        for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+    else if constexpr (MODE == 6)
         for_rows_xblock<NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 4 || MODE == 5)
         for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
@@ -1015,6 +1232,21 @@ __device__ __forceinline__ int find_problem(const int32_t *__restrict__ boff, in
     nb = boff[lo + 1] - boff[lo];
     lb = b - boff[lo];
     return lo;
+}
+
+// Block order of the symmetric Q1 traversal (modes 7, 8; nb a multiple of 8):
+// workgroups are dealt to the eight XCDs in turn, so block b runs on XCD
+// b mod 8; b takes the logical block (b mod 8) nb / 8 + b / 8, which gives each
+// XCD one contiguous slab of rows, taken in ascending order.  A row's lower
+// entries are read from rows up to a plane of nodes back, which its own XCD
+// read as upper entries shortly before: they are served by that XCD's L2.
+// The partial of a block goes to its logical slot, so the slots hold what the
+// blocks of the unpermuted order hold (and blocks past the rows add zeros).
+template <int MODE>
+__device__ __forceinline__ int64_t xcd_block(int64_t lb, int64_t nb)
+{
+    if constexpr (MODE == 7 || MODE == 8) return (lb % 8) * (nb / 8) + lb / 8;
+    else return lb;
 }
 
 // Vector access in pairs of neighbours: W, 16-byte loads and stores (every
@@ -1110,7 +1342,10 @@ __global__ __launch_bounds__(rows_block(MODE)) void spmv_struct_kernel(SpaceArgs
                                                                         const double *__restrict__ x,
                                                                         double *__restrict__ y)
 {
-    if constexpr (MODE == 6)
+    if constexpr (MODE == 7 || MODE == 8)
+        for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(sa, val, x, xcd_block<MODE>(blockIdx.x, gridDim.x), gridDim.x,
+                                                     [&](int64_t row, double s) { y[row] = s; });
+    else if constexpr (MODE == 6)
         for_rows_xblock<NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
     else if constexpr (MODE == 4 || MODE == 5)
         for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(sa, val, x, blockIdx.x, gridDim.x,
@@ -1128,6 +1363,7 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_init_kernel(const PcgPro
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
+    lb = xcd_block<MODE>(lb, nb);
     double v[3] = {0.0, 0.0, 0.0};
     const FE_GLOBAL double *__restrict__ b = as_global(P.b);
     const FE_GLOBAL double *__restrict__ dinv = as_global(P.dinv);
@@ -1180,13 +1416,14 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgPro
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     if (P.w.st->done) return;
+    lb = xcd_block<MODE>(lb, nb);
     double v = 0.0;
     const FE_GLOBAL double *__restrict__ p = as_global(P.w.p);
     FE_GLOBAL double *__restrict__ q = as_global(P.w.q);
-    // the Q1 traversal (modes 4, 5) hands over p[row] from its LDS copy of p
+    // the Q1 traversals (modes 4, 5, 7, 8) hand over p[row] from their LDS copy of p
     for_rows_p<MODE, RPB, NC, VT>(P, P.w.p, lb, nb, [&](int64_t row, double s, double prow = 0.0) {
                                 q[row] = s;
-                                v += (MODE == 4 || MODE == 5 ? prow : p[row]) * s;
+                                v += (MODE == 4 || MODE == 5 || MODE >= 7 ? prow : p[row]) * s;
                             });
     // block partial: wave sums, then wave 0's lane 0 adds them in wave order
     __shared__ double wsum[rows_block(MODE) / 64];
@@ -1323,6 +1560,7 @@ __global__ __launch_bounds__(rows_block(MODE)) void resid_kernel(const PcgProb *
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
+    lb = xcd_block<MODE>(lb, nb);
     double v[1] = {0.0};
     const FE_GLOBAL double *__restrict__ b = as_global(P.b);
     for_rows_p<MODE, RPB, NC, VT>(P, P.x, lb, nb, [&](int64_t row, double ax) {
@@ -1349,10 +1587,12 @@ static int grid_rows(int64_t n, const SpmvPlan &pl)
     const int rows_per_run = pl.mode >= 3 ? 32 : pl.rpb;  // mode 6: a block per 32-row chunk
     const int waves = pl.mode == 6 ? 1 : rows_block(pl.mode) / 64;
     const int64_t runs = (n + rows_per_run - 1) / rows_per_run;
-    // the Q1 traversal: up to one block per partial slot (mode 5: exactly one
-    // wave per step); the others: at most kGrid blocks
-    const int64_t cap = pl.mode == 4 || pl.mode == 5 ? part_slots(n) : kGrid;
-    return int(std::max<int64_t>(1, std::min<int64_t>(cap, (runs + waves - 1) / waves)));
+    // the Q1 traversals: up to one block per partial slot (modes 5 and 8:
+    // exactly one wave per step); the others: at most kGrid blocks
+    const int64_t cap = pl.mode == 4 || pl.mode == 5 || pl.mode >= 7 ? part_slots(n) : kGrid;
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(cap, (runs + waves - 1) / waves));
+    // modes 7, 8: a multiple of the XCD count (cap is one), see xcd_block
+    return int(pl.mode >= 7 ? (g + 7) / 8 * 8 : g);
 }
 
 // Blocks of the vector kernels of an n-row problem: at most kGridE, since
@@ -1676,7 +1916,10 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
     std::vector<SpmvPlan> plans(njobs);
     for (int i = 0; i < njobs; i++) {
         if (jobs[i].sa && jobs[i].fp32) return set_error(FE_EINVAL, "structured traversal needs FP64 values");
-        plans[i] = jobs[i].sa ? aligned_form(struct_plan(*jobs[i].sa), jobs[i].val) : plan_for(jobs[i].n, jobs[i].nnz);
+        if (jobs[i].sym)
+            plans[i] = launch_form(SpmvPlan{7, 1, jobs[i].sa->dim == 3 ? 27 : 9, 2}, jobs[i].n);
+        else
+            plans[i] = jobs[i].sa ? aligned_form(struct_plan(*jobs[i].sa), jobs[i].val) : plan_for(jobs[i].n, jobs[i].nnz);
         if (jobs[i].n > 0) order.push_back(i);
     }
     auto key = [&](int i) {
@@ -1928,12 +2171,14 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_gra
 template <typename VT>
 static fe_status pcg_run(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind, const VT *val,
                          const double *dinv, const double *b, double *x, double rtol, int maxit, void *ws,
-                         size_t ws_bytes, fe_solve_info *info, hipStream_t s, const SpaceArgs *sa = nullptr)
+                         size_t ws_bytes, fe_solve_info *info, hipStream_t s, const SpaceArgs *sa = nullptr,
+                         bool sym = false)
 {
     if (ws_bytes < pcg_ws_bytes(n) + engine_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
     if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     std::vector<PcgJob> jobs(1);
-    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit, sa};
+    jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit, sa,
+                     sym};
     void *table = static_cast<char *>(ws) + pcg_ws_bytes(n);
     // small systems are launch-bound: replay the iterations from a HIP graph
     const bool graph = n < (int64_t(1) << 18);
@@ -1952,6 +2197,41 @@ fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, 
 {
     return pcg_run<double>(A->n_rows, A->nnz, A->rowptr, A->colind, A->values, A->dinv, b, x, rtol, maxit, ws,
                            ws_bytes, info, s, &sa);
+}
+
+bool sym_supported(const SpaceArgs &sa) { return sa.k == 1 && sa.ncomp == 1 && (sa.dim == 2 || sa.dim == 3); }
+
+size_t sym_bytes(const SpaceArgs &sa)
+{
+    return size_t(sym_slots(sa.dim)) * size_t(sym_stride(sa.n_rows)) * sizeof(double);
+}
+
+fe_status launch_sym_fill(const SpaceArgs &sa, const double *val, double *sym, hipStream_t s)
+{
+    const int64_t ns = sym_stride(sa.n_rows);
+    if (ns == 0) return FE_OK;
+    const dim3 grid(unsigned((ns / 32 + kQ1Waves - 1) / kQ1Waves));  // a wave per 32 rows of the stride
+    if (sa.dim == 3) hipLaunchKernelGGL(sym_fill_kernel<3>, grid, dim3(kQ1Block), 0, s, sa, val, sym);
+    else hipLaunchKernelGGL(sym_fill_kernel<2>, grid, dim3(kQ1Block), 0, s, sa, val, sym);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+fe_status launch_spmv_sym(const SpaceArgs &sa, const double *sym, const double *x, double *y, hipStream_t s)
+{
+    if (sa.n_rows == 0) return FE_OK;
+    const SpmvPlan pl = launch_form(SpmvPlan{7, 1, sa.dim == 3 ? 27 : 9, 2}, sa.n_rows);
+    const int g = grid_rows(sa.n_rows, pl);
+    FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(sa, sym, x, y)));
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+fe_status pcg_solve_sym(const fe_csr *A, const SpaceArgs &sa, const double *sym, const double *b, double *x,
+                        double rtol, int maxit, void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s)
+{
+    return pcg_run<double>(A->n_rows, A->nnz, A->rowptr, A->colind, sym, A->dinv, b, x, rtol, maxit, ws, ws_bytes,
+                           info, s, &sa, true);
 }
 
 fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s)

@@ -30,7 +30,7 @@ EXPORTS = [
     "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_wait", "fe_server_solution",
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
-    "fe_spmv_plan_set_mesh",
+    "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -161,6 +161,11 @@ def lib():
                                       _c.POINTER(SpmvPlan), _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
             "fe_spmv_plan_of_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
             "fe_spmv_plan_set_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan)],
+            "fe_sym_query": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_size_t)],
+            "fe_sym_from_csr": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_spmv_sym": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _c.c_size_t, _P, _P, _P],
+            "fe_pcg_solve_sym": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P, _P,
+                                 _c.c_double, _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
             "fe_server_create": [_c.c_size_t, _c.c_int32, _c.POINTER(_P)],
             "fe_server_submit": [_P, _c.POINTER(Request), _c.POINTER(_c.c_uint64)],
             "fe_server_poll": [_P, _c.c_uint64, _c.POINTER(Result)],
@@ -438,6 +443,39 @@ def pcg_solve_mesh(mesh, order, coeff, csr, b, x, rtol, maxit, ws, stream=None, 
 def spmv_mesh(mesh, order, coeff, csr, x, y, stream=None):
     _check(lib().fe_spmv_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(x), _ptr(y),
                               _stream(stream)), "fe_spmv_mesh")
+
+
+def sym_query(mesh, order, coeff):
+    """Bytes of the symmetric storage (upper triangle, slot-major) of a Q1 scalar system."""
+    nb = _c.c_size_t()
+    _check(lib().fe_sym_query(mesh.handle, int(order), _c.byref(coeff), _c.byref(nb)), "fe_sym_query")
+    return nb.value
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def sym_from_csr(mesh, order, coeff, csr, sym, stream=None):
+    """sym (float64 device tensor of sym_query bytes) = upper triangle of csr."""
+    _check(lib().fe_sym_from_csr(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(sym), _nbytes(sym),
+                                 _stream(stream)), "fe_sym_from_csr")
+
+
+def spmv_sym(mesh, order, coeff, sym, x, y, stream=None):
+    _check(lib().fe_spmv_sym(mesh.handle, int(order), _c.byref(coeff), _ptr(sym), _nbytes(sym), _ptr(x), _ptr(y),
+                             _stream(stream)), "fe_spmv_sym")
+
+
+def pcg_solve_sym(mesh, order, coeff, csr, sym, b, x, rtol, maxit, ws, stream=None, check=True):
+    """Jacobi-PCG with the operator applied from its symmetric storage."""
+    info = SolveInfo()
+    st = lib().fe_pcg_solve_sym(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(sym), _nbytes(sym),
+                                _ptr(b), _ptr(x), float(rtol), int(maxit), _ptr(ws), _nbytes(ws), _c.byref(info),
+                                _stream(stream))
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_pcg_solve_sym")
+    return _info_dict(info)
 
 
 def pcg_solve_batch_mesh(meshes, orders, coeffs, csrs, bs, xs, rtol, maxit, ws, stream=None, check=True):

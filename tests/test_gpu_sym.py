@@ -1,0 +1,159 @@
+"""GPU parity of the symmetric storage of Q1 scalar systems (upper triangle,
+slot-major): its layout against the oracle's pattern, its SpMV and PCG
+against the CSR value traversal of the same matrix and against the oracle."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle as O
+from paper_1708_01773_amd import fe as F
+from tests.gpu_util import Pair, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# (dim, cells per axis, Dirichlet faces): all-Dirichlet, mixed Neumann faces
+# (rows on a Neumann face keep their outer neighbours' slots empty), ragged
+# row counts (not multiples of 32 or 64), and a single free line.
+CASES = [(3, [7, 6, 5], None), (3, [9, 4, 6], 0b011010), (3, [5, 5, 5], 0b000001), (2, [33, 17], None),
+         (2, [5, 40], 0b0110), (3, [40, 2, 2], None), (2, [64, 3], 0b1111)]
+
+
+def _free_coords(dim, n, faces):
+    """Lattice coordinates of the oracle's free nodes, by free index."""
+    code, nfree, _ = O.number_nodes(dim, n, 1, faces)
+    N = [c + 1 for c in n] + [1] * (3 - dim)
+    ids = np.nonzero(code >= 0)[0]
+    out = np.zeros((nfree, 3), dtype=np.int64)
+    out[code[ids]] = np.stack([ids % N[0], (ids // N[0]) % N[1], ids // (N[0] * N[1])], axis=1)
+    return out
+
+
+def _expected_sym(S, coords, dim, values):
+    """The slot-major upper triangle built from the oracle's pattern: slot
+    g - C of row r holds the entry of the column whose node sits at offset d
+    (g = 9 (dz+1) + 3 (dy+1) + (dx+1), C = 13; 2D: g = 3 (dy+1) + (dx+1), C = 4)."""
+    n = S.nfree
+    ns = (n + 63) // 64 * 64
+    C = 13 if dim == 3 else 4
+    out = np.zeros((C + 1) * ns)
+    for r in range(n):
+        for p in range(S.rowptr[r], S.rowptr[r + 1]):
+            c = S.colind[p]
+            if c < r:
+                continue
+            d = coords[c] - coords[r]
+            assert np.all(np.abs(d) <= 1)
+            g = 9 * (d[2] + 1) + 3 * (d[1] + 1) + (d[0] + 1) if dim == 3 else 3 * (d[1] + 1) + (d[0] + 1)
+            assert g >= C
+            out[(g - C) * ns + r] = values[p]
+    return out
+
+
+def _sym_of(pair, A):
+    nb = F.sym_query(pair.mesh, 1, pair.coeff)
+    sym = torch.full((nb // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    F.sym_from_csr(pair.mesh, 1, pair.coeff, A.csr, sym)
+    return sym
+
+
+@pytest.mark.parametrize("dim,n,faces", CASES)
+def test_symmetric_storage_layout_and_spmv(dim, n, faces):
+    pair = Pair(dim, n, 1, faces=faces, seed=51)
+    A = pair.gpu_assembly()
+    say(f"[sym] dim {dim} n {n} faces {faces} rows {A.n_rows}")
+    S = pair.system
+    coords = _free_coords(dim, n, pair.P.faces)
+    vals = A.values[: A.nnz].cpu().numpy()
+    # the assembled matrix is bitwise symmetric (same element entries, same cell order)
+    M = S.scipy().tocsr()
+    M.data = vals.copy()
+    assert (M != M.T).nnz == 0
+    sym = _sym_of(pair, A)
+    torch.cuda.synchronize()
+    got = sym.cpu().numpy()
+    # placement: bit-exact against the layout built from the oracle's pattern
+    # and the assembled values; every slot entry written (empty ones are 0)
+    assert np.array_equal(got, _expected_sym(S, coords, dim, vals))
+    # values: the oracle's upper triangle to 1e-12
+    want = _expected_sym(S, coords, dim, S.values)
+    assert np.all(np.abs(got - want) <= 1e-12 * np.abs(want).max())
+    # SpMV: bitwise the Q1 value traversal, and the oracle's product to 1e-12
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(52)).standard_normal(A.n_rows)).cuda()
+    y = torch.empty_like(x)
+    ym = torch.empty_like(x)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym, x, y)
+    F.spmv_mesh(pair.mesh, 1, pair.coeff, A.csr, x, ym)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ym)
+    xo = x.cpu().numpy()
+    yo = O.spmv(S.rowptr, S.colind, S.values, xo)
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(xo))
+    assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("dim,n,faces", CASES)
+def test_symmetric_storage_pcg_is_bitwise_the_mesh_pcg(dim, n, faces):
+    pair = Pair(dim, n, 1, faces=faces, seed=53)
+    A = pair.gpu_assembly()
+    say(f"[sym pcg] dim {dim} n {n} faces {faces} rows {A.n_rows}")
+    sym = _sym_of(pair, A)
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    u = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    info = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym, A.rhs, u, 1e-10, 20000, ws)
+    um = torch.zeros_like(u)
+    im = A.solve(um, 1e-10, 20000, ws)
+    torch.cuda.synchronize()
+    say(f"   iters sym {info['iters']} mesh {im['iters']}")
+    assert info["status"] == im["status"] == F.FE_OK
+    assert info["iters"] == im["iters"] and info["relres"] == im["relres"]
+    assert torch.equal(u, um)
+    S = pair.system
+    assert rel(u.cpu().numpy(), spla.spsolve(S.scipy().tocsc(), S.rhs)) <= 1e-8
+
+
+def test_symmetric_storage_with_wave_strided_steps():
+    """Above 128 x 32768 rows the blocks take several steps each (mode 7, the
+    looping form): SpMV and PCG bitwise those of the Q1 value traversal."""
+    n = 163  # 162^3 = 4.25M free nodes
+    pair = Pair(3, [n, n, n], 1, seed=13)
+    A = pair.gpu_assembly()
+    assert A.n_rows > 128 * 32768
+    say(f"[sym strided] rows {A.n_rows} nnz {A.nnz}")
+    sym = _sym_of(pair, A)
+    g = torch.Generator(device="cuda").manual_seed(54)
+    x = torch.rand(A.n_rows, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    y = torch.empty_like(x)
+    ym = torch.empty_like(x)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym, x, y)
+    F.spmv_mesh(pair.mesh, 1, pair.coeff, A.csr, x, ym)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ym)
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    u = torch.zeros_like(x)
+    info = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym, A.rhs, u, 1e-8, 20000, ws)
+    um = torch.zeros_like(x)
+    im = A.solve(um, 1e-8, 20000, ws)
+    torch.cuda.synchronize()
+    say(f"   iters sym {info['iters']} mesh {im['iters']}")
+    assert info["status"] == im["status"] == F.FE_OK and info["iters"] == im["iters"]
+    assert torch.equal(u, um)
+
+
+def test_symmetric_storage_refuses_other_spaces_and_bad_buffers():
+    q2 = Pair(3, [3, 3, 2], 2, seed=55)
+    with pytest.raises(F.FeError, match="Q1 scalar"):
+        F.sym_query(q2.mesh, 2, q2.coeff)
+    el = Pair(3, [3, 3, 2], 1, "elasticity", seed=56)
+    with pytest.raises(F.FeError, match="Q1 scalar"):
+        F.sym_query(el.mesh, 1, el.coeff)
+    pair = Pair(3, [4, 4, 4], 1, seed=57)
+    A = pair.gpu_assembly()
+    nb = F.sym_query(pair.mesh, 1, pair.coeff)
+    assert nb == 14 * ((A.n_rows + 63) // 64 * 64) * 8
+    small = torch.empty(nb // 8 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FeError, match="too small"):
+        F.sym_from_csr(pair.mesh, 1, pair.coeff, A.csr, small)
+    raw = torch.empty(nb + 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(F.FeError, match="8-byte"):
+        F.sym_from_csr(pair.mesh, 1, pair.coeff, A.csr, raw[4: 4 + nb])
