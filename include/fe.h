@@ -307,8 +307,10 @@ fe_status fe_pcg_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const in
  *     fe_spmv_mesh.  Asynchronous.
  *   fe_pcg_solve_sym: Jacobi-PCG of A x = b with A applied from sym and the
  *     diagonal inverse read from A->dinv (A->values, rowptr, colind not
- *     read); workspace of fe_pcg_query(n_rows) bytes; for a bitwise symmetric
- *     A the iterates are bitwise those of fe_pcg_solve_mesh.  Synchronizes.
+ *     read); workspace of fe_pcg_query(n_rows) bytes.  The same rows and
+ *     products as fe_pcg_solve_mesh; its fused p.q partials group 256 rows
+ *     instead of 128, so the iterates agree to rounding, and they are bitwise
+ *     reproducible from run to run.  Synchronizes.
  * Errors (FE_EINVAL, nothing launched): not Q1 scalar, sym too small, null
  * or not 8-byte aligned, csr sizes not those of fe_assemble_query. */
 fe_status fe_sym_query(fe_mesh mesh, int32_t order, const fe_coeff *coeff, size_t *bytes);

@@ -779,26 +779,30 @@ constexpr int sym_slots(int dim) { return dim == 3 ? 14 : 5; }
 __host__ __device__ constexpr int64_t sym_stride(int64_t n) { return (n + 63) / 64 * 64; }
 
 // Rows of a Q1 scalar system in symmetric storage (plan mode 7; mode 8 is
-// its instantiation with one step per wave).  The steps, rows, lanes and x
-// runs of the Q1 traversal, its positions in the same order and the same
-// products, so both give bitwise the same sums of a symmetric matrix; each
-// lane loads the values of its positions straight from the slots: for a
-// position shared by the rows of a step the 32 loads are consecutive, as a
-// slot holds its rows in order.
+// its instantiation with one step per wave).  A wave step takes 64
+// consecutive rows, one lane per row; x is staged in LDS as 3^(d-1) runs of
+// 66 unknowns (as in the Q1 traversal, one run per neighbour line), and each
+// lane loads the values of its row's positions straight from the slots, all
+// in flight at once: for a position shared by the rows of a step the 64 loads
+// are consecutive.  When every row of the step has its full box (most steps),
+// position p is code g = p and each load is the row plus an offset common to
+// the wave.  A lane sums positions [0, H) and [H, 2H) apart (H = (3^d + 1) / 2)
+// and adds the two, the order in which the two-lane Q1 traversal sums a row,
+// so both give bitwise the same row sums of a symmetric matrix.
 template <int DIM, bool ONE, typename Fn>
 __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double *__restrict__ gval,
-                                               const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+                                                const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
-    using S = Q1Step<DIM>;
-    constexpr int C = DIM == 3 ? 13 : 4;
+    constexpr int L = DIM == 3 ? 27 : 9, H = (L + 1) / 2, C = (L - 1) / 2;
+    constexpr int RW = 64, SEG = RW + 2, NSEG = DIM == 3 ? 9 : 3, XS = NSEG * SEG, XCH = (XS + 63) / 64;
     const FE_GLOBAL double *__restrict__ val = as_global(gval);
     const FE_GLOBAL double *__restrict__ x = as_global(gx);
-    __shared__ double xst[kQ1Waves][S::XS];
+    __shared__ double xst[kQ1Waves][XS];
     double *mx = xst[threadIdx.x / 64];
-    const int lane = threadIdx.x % 64, rl = lane % S::RW, h = lane / S::RW;
+    const int lane = threadIdx.x % 64;
     const int64_t n = s.n_rows, ns = sym_stride(n);
     const int64_t nw = nb * kQ1Waves, lw = lb * kQ1Waves + threadIdx.x / 64;
-    const int64_t runs = (n + S::RW - 1) / S::RW;
+    const int64_t runs = (n + RW - 1) / RW;
     AxisClosed A[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) {
@@ -811,7 +815,7 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double 
     const double f0inv = s.ax[0].finv, f1inv = s.ax[1].finv;
     const int64_t plane = int64_t(f0) * f1;
     auto step = [&](int64_t run) {
-        const int64_t r0 = run * S::RW, row = r0 + rl;
+        const int64_t r0 = run * RW, row = r0 + lane;
         const bool live = row < n;
         int32_t len = 0, wx = 1, w1 = 1, e0 = 0, e1 = 0, e2 = 0;
         if (live) {
@@ -828,69 +832,74 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double 
             e1 = cl1 - (A[1].lo + t1) + 1;
             e2 = DIM == 3 ? cl2 - (A[2].lo + t2) + 1 : 0;
         }
-        double xs[S::XCH];
+        double xs[XCH];
 #pragma unroll
-        for (int u = 0; u < S::XCH; u++) {
+        for (int u = 0; u < XCH; u++) {
             const int i = lane + 64 * u;
-            const int sg = i / S::SEG, kk = i - sg * S::SEG;
+            const int sg = i / SEG, kk = i - sg * SEG;
             const int dy = sg % 3 - 1, dz = sg / 3 - 1;
             int64_t a = r0 + kk - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0);
-            a = a < 0 ? 0 : (a >= n ? n - 1 : a);  // slots past either end are never read
+            a = a < 0 ? 0 : (a >= n ? n - 1 : a);
             xs[u] = x[a];
         }
-        double vv[S::H];
-        int32_t xi[S::H];
-        if (__all(len == S::L)) {
-            // every row of the step has its full box: position p is code g = p,
-            // so a lane's loads are its row plus offsets common to the wave
+        double vv[2 * H];
+        const bool full = __all(len == L);
+        const uint32_t m0 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
+        const uint32_t m1 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
+        // LDS slot of x for position t (the column of a position past the row: its first)
+        auto xslot = [&](int t) {
+            if (full) {
+                const int g = t < L ? t : 0;
+                const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
+                return (DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1) * SEG + o0 + 1 + lane;
+            }
+            const int32_t pc = t < len ? t : 0;
+            const int32_t qy = int32_t((uint32_t(pc) * m0) >> 20);
+            const int32_t j0 = pc - qy * wx;
+            const int32_t j2 = int32_t((uint32_t(qy) * m1) >> 20);
+            const int32_t j1 = qy - j2 * w1;
+            const int32_t sg = DIM == 3 ? (e1 + j1) + 3 * (e2 + j2) : e1 + j1;
+            return int(sg * SEG + lane + e0 + j0);
+        };
+        if (full) {
 #pragma unroll
-            for (int t = 0; t < S::H; t++) {
-                const int ga = t, gb = S::H + t < S::L ? S::H + t : 0;
-                const int oa0 = ga % 3 - 1, oa1 = (ga / 3) % 3 - 1, oa2 = DIM == 3 ? ga / 9 - 1 : 0;
-                const int ob0 = gb % 3 - 1, ob1 = (gb / 3) % 3 - 1, ob2 = DIM == 3 ? gb / 9 - 1 : 0;
-                const int64_t ka = ga >= C ? int64_t(ga - C) * ns
-                                           : int64_t(C - ga) * ns + oa0 + int64_t(oa1) * f0 + int64_t(oa2) * plane;
-                const int64_t kb = int64_t(gb - C) * ns;
-                const int xa = (DIM == 3 ? (oa1 + 1) + 3 * (oa2 + 1) : oa1 + 1) * S::SEG + oa0 + 1;
-                const int xb = (DIM == 3 ? (ob1 + 1) + 3 * (ob2 + 1) : ob1 + 1) * S::SEG + ob0 + 1;
-                const bool ok = h == 0 || S::H + t < S::L;
-                xi[t] = (h ? xb : xa) + rl;
-                vv[t] = ok ? val[row + (h ? kb : ka)] : 0.0;
+            for (int t = 0; t < 2 * H; t++) {
+                const int g = t < L ? t : 0;
+                const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
+                const int64_t k = g >= C ? int64_t(g - C) * ns
+                                         : int64_t(C - g) * ns + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
+                vv[t] = t < L ? val[row + k] : 0.0;
             }
         } else {
-            const uint32_t m0 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
-            const uint32_t m1 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
 #pragma unroll
-            for (int t = 0; t < S::H; t++) {
-                const int32_t pos = h * S::H + t;
-                const bool ok = pos < len;
-                const int32_t pc = ok ? pos : 0;
+            for (int t = 0; t < 2 * H; t++) {
+                const bool ok = t < len;
+                const int32_t pc = ok ? t : 0;
                 const int32_t qy = int32_t((uint32_t(pc) * m0) >> 20);
                 const int32_t j0 = pc - qy * wx;
                 const int32_t j2 = int32_t((uint32_t(qy) * m1) >> 20);
                 const int32_t j1 = qy - j2 * w1;
                 const int32_t o0 = e0 + j0 - 1, o1 = e1 + j1 - 1, o2 = DIM == 3 ? e2 + j2 - 1 : 0;
                 const int32_t g = DIM == 3 ? 9 * (o2 + 1) + 3 * (o1 + 1) + (o0 + 1) : 3 * (o1 + 1) + (o0 + 1);
-                const int32_t sg = DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1;
-                xi[t] = sg * S::SEG + rl + o0 + 1;
                 const int64_t at = g >= C ? int64_t(g - C) * ns + row
                                           : int64_t(C - g) * ns + row + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
                 vv[t] = ok ? val[at] : 0.0;
             }
         }
 #pragma unroll
-        for (int u = 0; u < S::XCH; u++)
-            if (lane + 64 * u < S::XS) mx[lane + 64 * u] = xs[u];
+        for (int u = 0; u < XCH; u++)
+            if (lane + 64 * u < XS) mx[lane + 64 * u] = xs[u];
         wave_lds_sync();
-        double sum = 0.0;
+        double lo = 0.0, hi = 0.0;
 #pragma unroll
-        for (int t = 0; t < S::H; t++) sum += vv[t] * mx[xi[t]];
-        const double upper = __shfl(sum, (lane + S::RW) % 64);
-        if (h == 0 && live) {
+        for (int t = 0; t < H; t++) lo += vv[t] * mx[xslot(t)];
+#pragma unroll
+        for (int t = 0; t < H; t++) hi += vv[H + t] * mx[xslot(H + t)];
+        if (live) {
             if constexpr (std::is_invocable_v<Fn, int64_t, double, double>)
-                f(row, sum + upper, mx[(DIM == 3 ? 4 : 1) * S::SEG + rl + 1]);
+                f(row, lo + hi, mx[(DIM == 3 ? 4 : 1) * SEG + lane + 1]);
             else
-                f(row, sum + upper);
+                f(row, lo + hi);
         }
         wave_lds_sync();
     };
@@ -1170,10 +1179,12 @@ static SpmvPlan struct_plan_of_class(const SpaceArgs &sa)
 }
 
 // The launch form of a plan: mode 4 (7) becomes its one-step-per-wave
-// instantiation, mode 5 (8), when the partial slots hold a block per 128 rows.
+// instantiation, mode 5 (8), when the partial slots hold a block per 128
+// (256) rows.
 static SpmvPlan launch_form(SpmvPlan pl, int64_t n)
 {
-    if ((pl.mode == 4 || pl.mode == 7) && (n + 127) / 128 <= part_slots(n)) pl.mode++;
+    if (pl.mode == 4 && (n + 127) / 128 <= part_slots(n)) pl.mode = 5;
+    if (pl.mode == 7 && ((n + 255) / 256 + 7) / 8 * 8 <= part_slots(n)) pl.mode = 8;
     return pl;
 }
 
@@ -1584,7 +1595,7 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 // ---------------------------------------------------------------------------
 static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
-    const int rows_per_run = pl.mode >= 3 ? 32 : pl.rpb;  // mode 6: a block per 32-row chunk
+    const int rows_per_run = pl.mode >= 7 ? 64 : pl.mode >= 3 ? 32 : pl.rpb;  // mode 6: a block per 32-row chunk
     const int waves = pl.mode == 6 ? 1 : rows_block(pl.mode) / 64;
     const int64_t runs = (n + rows_per_run - 1) / rows_per_run;
     // the Q1 traversals: up to one block per partial slot (modes 5 and 8:
