@@ -781,14 +781,16 @@ __host__ __device__ constexpr int64_t sym_stride(int64_t n) { return (n + 63) / 
 // Rows of a Q1 scalar system in symmetric storage (plan mode 7; mode 8 is
 // its instantiation with one step per wave).  A wave step takes 64
 // consecutive rows, one lane per row; x is staged in LDS as 3^(d-1) runs of
-// 66 unknowns (as in the Q1 traversal, one run per neighbour line), and each
-// lane loads the values of its row's positions straight from the slots, all
-// in flight at once: for a position shared by the rows of a step the 64 loads
-// are consecutive.  When every row of the step has its full box (most steps),
-// position p is code g = p and each load is the row plus an offset common to
-// the wave.  A lane sums positions [0, H) and [H, 2H) apart (H = (3^d + 1) / 2)
-// and adds the two, the order in which the two-lane Q1 traversal sums a row,
-// so both give bitwise the same row sums of a symmetric matrix.
+// 66 unknowns (as in the Q1 traversal, one run per neighbour line).  The value
+// of the neighbour with code g sits at the row plus an offset that depends on
+// g only (slot |g - C|, and the mirrored row for g < C), so each lane walks the
+// 3^d codes with a mask of the free ones (per axis, the offsets inside the
+// row's box) and issues all its value loads at once, with no position decode:
+// for a code shared by the rows of a step the 64 loads are consecutive.  The
+// row's columns in ascending order are its free codes in ascending order; the
+// first H = (3^d + 1) / 2 are summed into one partial, the rest into another,
+// and the row is their sum: the order in which the two-lane Q1 traversal sums
+// a row, so both give bitwise the same row sums of a symmetric matrix.
 template <int DIM, bool ONE, typename Fn>
 __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double *__restrict__ gval,
                                                 const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
@@ -817,20 +819,19 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double 
     auto step = [&](int64_t run) {
         const int64_t r0 = run * RW, row = r0 + lane;
         const bool live = row < n;
-        int32_t len = 0, wx = 1, w1 = 1, e0 = 0, e1 = 0, e2 = 0;
+        // allowed neighbour offsets o of the row per axis: bit o + 1 (none for a row past n)
+        uint32_t mk0 = 0, mk1 = 0, mk2 = 0;
         if (live) {
             const int32_t r32 = int32_t(row);
             const int32_t q = div_exact(r32, f0, f0inv), t0 = r32 - q * f0;
             const int32_t t2 = div_exact(q, f1, f1inv), t1 = q - t2 * f1;
-            int32_t w0, w2, cl0, cl1, cl2, P0, P1, P2;
+            int32_t w0, w1, w2, cl0, cl1, cl2, P0, P1, P2;
             axis_row(A[0], 1, 1.0, A[0].lo + t0, w0, cl0, P0);
             axis_row(A[1], 1, 1.0, A[1].lo + t1, w1, cl1, P1);
             axis_row(A[2], 1, 1.0, A[2].lo + t2, w2, cl2, P2);
-            wx = w0;
-            len = w0 * w1 * w2;
-            e0 = cl0 - (A[0].lo + t0) + 1;
-            e1 = cl1 - (A[1].lo + t1) + 1;
-            e2 = DIM == 3 ? cl2 - (A[2].lo + t2) + 1 : 0;
+            mk0 = ((1u << w0) - 1u) << (cl0 - (A[0].lo + t0) + 1);
+            mk1 = ((1u << w1) - 1u) << (cl1 - (A[1].lo + t1) + 1);
+            mk2 = DIM == 3 ? ((1u << w2) - 1u) << (cl2 - (A[2].lo + t2) + 1) : 2u;
         }
         double xs[XCH];
 #pragma unroll
@@ -839,62 +840,41 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double 
             const int sg = i / SEG, kk = i - sg * SEG;
             const int dy = sg % 3 - 1, dz = sg / 3 - 1;
             int64_t a = r0 + kk - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0);
-            a = a < 0 ? 0 : (a >= n ? n - 1 : a);
+            a = a < 0 ? 0 : (a >= n ? n - 1 : a);  // slots past either end are never read
             xs[u] = x[a];
         }
-        double vv[2 * H];
-        const bool full = __all(len == L);
-        const uint32_t m0 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
-        const uint32_t m1 = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(w1))) + 2u;
-        // LDS slot of x for position t (the column of a position past the row: its first)
-        auto xslot = [&](int t) {
-            if (full) {
-                const int g = t < L ? t : 0;
-                const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
-                return (DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1) * SEG + o0 + 1 + lane;
-            }
-            const int32_t pc = t < len ? t : 0;
-            const int32_t qy = int32_t((uint32_t(pc) * m0) >> 20);
-            const int32_t j0 = pc - qy * wx;
-            const int32_t j2 = int32_t((uint32_t(qy) * m1) >> 20);
-            const int32_t j1 = qy - j2 * w1;
-            const int32_t sg = DIM == 3 ? (e1 + j1) + 3 * (e2 + j2) : e1 + j1;
-            return int(sg * SEG + lane + e0 + j0);
+        // code g = 9 (o2 + 1) + 3 (o1 + 1) + (o0 + 1): the value of a free
+        // neighbour is the row plus an offset common to the wave
+        auto code_ok = [&](int g) {
+            const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
+            return ((mk0 >> (o0 + 1)) & (mk1 >> (o1 + 1)) & (mk2 >> (o2 + 1)) & 1u) != 0u;
         };
-        if (full) {
+        double vv[L];
 #pragma unroll
-            for (int t = 0; t < 2 * H; t++) {
-                const int g = t < L ? t : 0;
-                const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
-                const int64_t k = g >= C ? int64_t(g - C) * ns
-                                         : int64_t(C - g) * ns + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
-                vv[t] = t < L ? val[row + k] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < 2 * H; t++) {
-                const bool ok = t < len;
-                const int32_t pc = ok ? t : 0;
-                const int32_t qy = int32_t((uint32_t(pc) * m0) >> 20);
-                const int32_t j0 = pc - qy * wx;
-                const int32_t j2 = int32_t((uint32_t(qy) * m1) >> 20);
-                const int32_t j1 = qy - j2 * w1;
-                const int32_t o0 = e0 + j0 - 1, o1 = e1 + j1 - 1, o2 = DIM == 3 ? e2 + j2 - 1 : 0;
-                const int32_t g = DIM == 3 ? 9 * (o2 + 1) + 3 * (o1 + 1) + (o0 + 1) : 3 * (o1 + 1) + (o0 + 1);
-                const int64_t at = g >= C ? int64_t(g - C) * ns + row
-                                          : int64_t(C - g) * ns + row + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
-                vv[t] = ok ? val[at] : 0.0;
-            }
+        for (int g = 0; g < L; g++) {
+            const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
+            const int64_t k = g >= C ? int64_t(g - C) * ns
+                                     : int64_t(C - g) * ns + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
+            vv[g] = code_ok(g) ? val[row + k] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < XCH; u++)
             if (lane + 64 * u < XS) mx[lane + 64 * u] = xs[u];
         wave_lds_sync();
+        // the row's columns in ascending order are its free codes in ascending
+        // order: the first H go to lo, the rest to hi
         double lo = 0.0, hi = 0.0;
+        int c = 0;
 #pragma unroll
-        for (int t = 0; t < H; t++) lo += vv[t] * mx[xslot(t)];
-#pragma unroll
-        for (int t = 0; t < H; t++) hi += vv[H + t] * mx[xslot(H + t)];
+        for (int g = 0; g < L; g++) {
+            const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
+            const double xg = mx[(DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1) * SEG + o0 + 1 + lane];
+            if (code_ok(g)) {
+                if (c < H) lo += vv[g] * xg;
+                else hi += vv[g] * xg;
+                c++;
+            }
+        }
         if (live) {
             if constexpr (std::is_invocable_v<Fn, int64_t, double, double>)
                 f(row, lo + hi, mx[(DIM == 3 ? 4 : 1) * SEG + lane + 1]);
