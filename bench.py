@@ -490,7 +490,8 @@ def main():
                          "csr": "CSR row pointers and column indices read"}[args.spmv], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": sb, "avg_launch_us": spmv_avg_s * 1e6,
-                     "launches": tm["spmv_calls"]},
+                     "timed_launches": tm["spmv_calls"],
+                     "timing": "HIP events around the SpMV launch of every 16th CG iteration of the timed steps"},
     }
     if not args.no_forms and wl["precision"] == "fp64":
         print("[bench] mixed-precision form", file=sys.stderr, flush=True)

@@ -476,10 +476,13 @@ fe_status fe_server_destroy(fe_server server);
 /* Kernel timing (for benchmarks)                                            */
 /* ------------------------------------------------------------------------ */
 /* When enabled (process-wide), fe_integrate / fe_scatter record HIP events
- * around their kernels and fe_pcg_solve around every SpMV launch, on the
- * call's own stream.  fe_get_timing waits for the recorded events, returns
- * the accumulated kernel times (milliseconds) and launch counts, and clears
- * them when reset != 0. */
+ * around their kernels and the single-system solves (fe_pcg_solve,
+ * fe_pcg_solve_mesh, fe_pcg_solve_sym; not those replayed from a graph)
+ * around the SpMV launch of every 16th CG iteration before convergence, on
+ * the call's own stream (an event pair costs a few microseconds of device
+ * time).  fe_get_timing waits for the recorded events, returns the
+ * accumulated kernel times (milliseconds) and counts of timed launches, and
+ * clears them when reset != 0. */
 typedef struct {
     double integrate_ms, scatter_ms, spmv_ms;
     int64_t integrate_calls, scatter_calls, spmv_calls;

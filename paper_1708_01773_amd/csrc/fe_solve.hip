@@ -60,10 +60,19 @@ __device__ __forceinline__ FE_GLOBAL T *as_global(T *p)
 struct PcgState {
     double rho[2];  // rho_j in slot j & 1
     double bb, rr, true_rr;
+    double alpha;      // alpha_j, from the update kernel to the dir kernel (x += alpha p there)
     int32_t iter;      // current iteration j (advanced by the dir kernel)
     int32_t iter_upd;  // j as seen by the update kernel, read by the dir kernel
-    int32_t done, status;
+    int32_t done;      // stopped before any iteration, or by a breakdown
+    int32_t stop_at;   // the iteration whose dir kernel stopped the solve (converged or maxit)
+    int32_t status;
 };
+
+// The solve has stopped for kernels of iteration j: the dir kernel of an
+// earlier iteration stopped it (the dir kernel of iteration j itself records
+// stop_at = j, which its other blocks read as still running), or it stopped
+// before the first iteration or at a breakdown.
+__host__ __device__ inline bool pcg_stopped(const PcgState &s, int32_t j) { return s.done || s.stop_at < j; }
 
 struct PcgWs {
     PcgState *st;
@@ -1390,6 +1399,8 @@ __global__ __launch_bounds__(kBlock) void pcg_init_finish_kernel(const PcgProb *
         st->iter_upd = 0;
         st->status = FE_OK;
         st->done = 0;
+        st->stop_at = INT32_MAX;
+        st->alpha = 0.0;
         if (t[1] <= P.rtol2 * t[2]) {
             st->done = 1;
         } else if (P.maxit <= 0) {
@@ -1406,7 +1417,7 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgPro
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
-    if (P.w.st->done) return;
+    if (pcg_stopped(*P.w.st, P.w.st->iter)) return;
     lb = xcd_block<MODE>(lb, nb);
     double v = 0.0;
     const FE_GLOBAL double *__restrict__ p = as_global(P.w.p);
@@ -1428,15 +1439,18 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgPro
     }
 }
 
-// alpha = rho_j / p.q; x += alpha p; r -= alpha q; partials of r.z, r.r
+// alpha = rho_j / p.q; r -= alpha q; partials of r.z, r.r (x += alpha p is
+// left to the dir kernel, which reads p anyway)
 __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__restrict__ probs,
                                                              const int32_t *__restrict__ boff, int nprob)
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     PcgState *st = P.w.st;
-    if (st->done) return;
     const int j = st->iter;
+    // the dir kernel's iteration, also when this one has stopped
+    if (lb == 0 && threadIdx.x == 0) st->iter_upd = j;
+    if (pcg_stopped(*st, j)) return;
     double pq[1];
     reduce_partials<1>(P.w.p1, P.nbr, P.w.ps, pq);
     if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
@@ -1448,41 +1462,34 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__res
     }
     const double alpha = st->rho[j & 1] / pq[0];
     if (lb == 0 && threadIdx.x == 0) {
-        st->iter_upd = j;
+        st->alpha = alpha;
         if (j < kHist) P.w.hist[j] = alpha;
     }
     int64_t lo, hi;
     owned_elems(P.n, lb, nb, lo, hi);
     double v[2] = {0.0, 0.0};
-    const double *__restrict__ p = P.w.p;
     const double *__restrict__ q = P.w.q;
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ r = P.w.r;
-    double *__restrict__ x = P.x;
-    // vectors of the caller (x, dinv) and of its workspace (p, q, r) may each be only 8-byte aligned
-    with_pair_width(pair_aligned(x) && pair_aligned(dinv) && pair_aligned(p) && pair_aligned(q) && pair_aligned(r),
-                    [&](auto wide) {
+    // vectors of the caller (dinv) and of its workspace (q, r) may each be only 8-byte aligned
+    with_pair_width(pair_aligned(dinv) && pair_aligned(q) && pair_aligned(r), [&](auto wide) {
         constexpr bool W = decltype(wide)::value;
         for_pairs(lo, hi, [&](int64_t i, int m) {
-            double pp[2], qq[2], rr[2], xx[2], dd[2];
-            load_pair<W>(p, i, m, pp);
+            double qq[2], rr[2], dd[2];
             load_pair<W>(q, i, m, qq);
             load_pair<W>(r, i, m, rr);
-            load_pair<W>(x, i, m, xx);
             load_pair<W>(dinv, i, m, dd);
             return [=, &v]() {
-                double xn[2], rn[2];
+                double rn[2];
 #pragma unroll
                 for (int e = 0; e < 2; e++) {
                     // explicit fused operations: every instantiation rounds alike
-                    xn[e] = fma(alpha, pp[e], xx[e]);
                     rn[e] = fma(-alpha, qq[e], rr[e]);
                     if (e < m) {
                         v[0] = fma(rn[e], dd[e] * rn[e], v[0]);
                         v[1] = fma(rn[e], rn[e], v[1]);
                     }
                 }
-                store_pair<W>(x, i, m, xn);
                 store_pair<W>(r, i, m, rn);
             };
         });
@@ -1494,15 +1501,15 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(const PcgProb *__res
     }
 }
 
-// beta = rho_{j+1} / rho_j; stop test; p = z + beta p
+// beta = rho_{j+1} / rho_j; stop test; x += alpha_j p; p = z + beta p
 __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restrict__ probs,
                                                           const int32_t *__restrict__ boff, int nprob)
 {
     int64_t lb, nb;
     const PcgProb &P = probs[find_problem(boff, nprob, lb, nb)];
     PcgState *st = P.w.st;
-    if (st->done) return;
     const int j = st->iter_upd;
+    if (pcg_stopped(*st, j)) return;
     double t[2];
     reduce_partials<2>(P.w.p2, P.nbe, kGrid, t);
     const double rho_old = st->rho[j & 1];
@@ -1513,31 +1520,54 @@ __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(const PcgProb *__restri
         st->rr = t[1];
         st->iter = j + 1;
         if (j < kHist) P.w.hist[kHist + j] = beta;
+        // stop_at, not done: the other blocks of this kernel still read the solve as running
         if (conv) {
-            st->done = 1;
+            st->stop_at = j;
             st->status = FE_OK;
         } else if (j + 1 >= P.maxit) {
-            st->done = 1;
+            st->stop_at = j;
             st->status = FE_ENOTCONV;
         }
     }
-    if (conv) return;
+    const double alpha = st->alpha;
     int64_t lo, hi;
     owned_elems(P.n, lb, nb, lo, hi);
     const double *__restrict__ r = P.w.r;
     const double *__restrict__ dinv = P.dinv;
     double *__restrict__ p = P.w.p;
-    with_pair_width(pair_aligned(dinv) && pair_aligned(r) && pair_aligned(p), [&](auto wide) {
+    double *__restrict__ x = P.x;
+    // vectors of the caller (x, dinv) and of its workspace (p, r) may each be only 8-byte aligned
+    with_pair_width(pair_aligned(x) && pair_aligned(dinv) && pair_aligned(r) && pair_aligned(p), [&](auto wide) {
         constexpr bool W = decltype(wide)::value;
+        if (conv) {  // the last x update; p is no longer needed
+            for_pairs(lo, hi, [&](int64_t i, int m) {
+                double pp[2], xx[2];
+                load_pair<W>(p, i, m, pp);
+                load_pair<W>(x, i, m, xx);
+                return [=]() {
+                    double xn[2];
+#pragma unroll
+                    for (int e = 0; e < 2; e++) xn[e] = fma(alpha, pp[e], xx[e]);
+                    store_pair<W>(x, i, m, xn);
+                };
+            });
+            return;
+        }
         for_pairs(lo, hi, [&](int64_t i, int m) {
-            double rr[2], dd[2], pp[2];
+            double rr[2], dd[2], pp[2], xx[2];
             load_pair<W>(r, i, m, rr);
             load_pair<W>(dinv, i, m, dd);
             load_pair<W>(p, i, m, pp);
+            load_pair<W>(x, i, m, xx);
             return [=]() {
-                double pn[2];
+                double pn[2], xn[2];
 #pragma unroll
-                for (int e = 0; e < 2; e++) pn[e] = fma(beta, pp[e], dd[e] * rr[e]);
+                for (int e = 0; e < 2; e++) {
+                    // explicit fused operations: every instantiation rounds alike
+                    xn[e] = fma(alpha, pp[e], xx[e]);
+                    pn[e] = fma(beta, pp[e], dd[e] * rr[e]);
+                }
+                store_pair<W>(x, i, m, xn);
                 store_pair<W>(p, i, m, pn);
             };
         });
@@ -1826,7 +1856,7 @@ __global__ __launch_bounds__(kBlock) void count_active_kernel(const PcgProb *__r
 {
     __shared__ int32_t cnt[kBlock];
     int32_t c = 0;
-    for (int i = threadIdx.x; i < nprob; i += kBlock) c += probs[i].w.st->done ? 0 : 1;
+    for (int i = threadIdx.x; i < nprob; i += kBlock) c += pcg_stopped(*probs[i].w.st, probs[i].w.st->iter) ? 0 : 1;
     cnt[threadIdx.x] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -2041,7 +2071,7 @@ fe_status engine_finish(EngineSet &E, hipStream_t s)
         fe_solve_info *info = E.jobs[t].info;
         if (!info) continue;
         info->iters = h.iter;
-        info->status = h.done ? h.status : FE_ENOTCONV;
+        info->status = pcg_stopped(h, h.iter) ? h.status : FE_ENOTCONV;
         const double bn = std::sqrt(h.bb);
         info->relres = bn > 0 ? std::sqrt(h.rr) / bn : std::sqrt(h.rr);
         info->true_relres = bn > 0 ? std::sqrt(h.true_rr) / bn : std::sqrt(h.true_rr);
@@ -2049,7 +2079,7 @@ fe_status engine_finish(EngineSet &E, hipStream_t s)
     return FE_OK;
 }
 
-bool engine_done(const EngineSet &E, int t) { return E.hs[t].done != 0; }
+bool engine_done(const EngineSet &E, int t) { return pcg_stopped(E.hs[t], E.hs[t].iter); }
 
 // Stream on which iteration chunks are captured (one per thread and device):
 // capture only records launches, and the caller's stream may be the null
@@ -2086,7 +2116,12 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_gra
     if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
     int32_t *h_active = reinterpret_cast<int32_t *>(pin.h);
     const bool timed = timing_on() && !use_graph && np == 1;
+    // SpMV launches timed: every kTimeEvery-th iteration (an event pair costs a
+    // few microseconds of device time, which around every launch lengthened
+    // the solve by about 6%); marks[i] belongs to iteration mark_iter[i]
+    constexpr int kTimeEvery = 16;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+    std::vector<int> mark_iter;
     struct GraphHold {
         hipGraph_t g = nullptr;
         hipGraphExec_t e = nullptr;
@@ -2114,7 +2149,11 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_gra
             FE_HIP(hipGraphLaunch(hold.e, s));
             j += gchunk;
         } else {
-            for (int i = 0; i < chunk && j < maxit; i++, j++) engine_iteration(E, s, timed ? &marks : nullptr);
+            for (int i = 0; i < chunk && j < maxit; i++, j++) {
+                const bool mark = timed && j % kTimeEvery == 0;
+                engine_iteration(E, s, mark ? &marks : nullptr);
+                mark_iter.resize(marks.size(), j);
+            }
             hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, s, E.d_probs, np, E.d_active);
             if (chunk < 128) chunk *= 2;
         }
@@ -2126,7 +2165,7 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_gra
     st = engine_finish(E, s);
     if (st != FE_OK) return st;
     for (size_t i = 0; i < marks.size(); i++) {
-        if (int(i) < E.hs[0].iter) {
+        if (mark_iter[i] < E.hs[0].iter) {
             timing_commit(marks[i].first, marks[i].second, kTimeSpmv);
         } else {
             timing_release(marks[i].first);
