@@ -152,21 +152,31 @@ def assemble_only(args, wl, A, ncells, F, torch):
 def mixed_form(args, wl, mesh, A, x_fp64, F, torch, stream, ncells, lo="fp32"):
     """Same workload solved by iterative refinement: A_hi assembled in FP64
     (outer residual), A_lo with FP32 element integration and FP32-stored values
-    (inner Jacobi-PCG at 8 B per nonzero).  Reports the step time and the
-    solution's distance to the plain FP64 solve on this GPU."""
+    (inner Jacobi-PCG; Q1 scalar systems in FP32 symmetric storage, 4 B per
+    upper-triangle entry, else FP32 CSR at 8 B per nonzero).  Reports the step
+    time and the solution's distance to the plain FP64 solve on this GPU."""
     src = (0.0, 0.0, -1.0) if wl["problem"] == "elasticity" else (1.0,)
     coeff_lo = F.make_coeff(wl["problem"], lo, source_kind=wl.get("source_kind", 1), source=src, dim=wl["dim"])
     A_lo = F.Assembly(mesh, wl["k"], coeff_lo)
     A_lo.pattern()
-    v32 = torch.empty(A_lo.nnz, dtype=torch.float32, device="cuda")
+    # Q1 scalar systems: the inner operator in FP32 symmetric storage; else FP32 CSR values
+    sym = wl["k"] == 1 and wl["problem"] == "poisson"
+    if sym:
+        v32 = torch.empty(F.sym_query(mesh, wl["k"], coeff_lo) // 8, dtype=torch.float32, device="cuda")
+    else:
+        v32 = torch.empty(A_lo.nnz, dtype=torch.float32, device="cuda")
     ws = torch.empty(F.refine_query(A.n_rows), dtype=torch.uint8, device="cuda")
     x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
 
     def step():
         A.assemble(stream)
         A_lo.assemble(stream)
-        F.csr_to_fp32(A_lo.csr, v32, stream)
         x.zero_()
+        if sym:
+            F.sym_fp32_from_csr(mesh, wl["k"], coeff_lo, A_lo.csr, v32, stream)
+            return F.refine_solve_sym(mesh, wl["k"], coeff_lo, A.csr, A_lo.csr, v32, A.rhs, x, wl["rtol"], 1e-5, 50,
+                                      100000, ws, stream=stream)
+        F.csr_to_fp32(A_lo.csr, v32, stream)
         return F.refine_solve(A.csr, A_lo.csr, A.rhs, x, wl["rtol"], 1e-5, 50, 100000, ws, values32=v32, stream=stream)
 
     step()
@@ -178,7 +188,8 @@ def mixed_form(args, wl, mesh, A, x_fp64, F, torch, stream, ncells, lo="fp32"):
     total = time.perf_counter() - t0
     err = (torch.linalg.vector_norm(x - x_fp64) / torch.linalg.vector_norm(x_fp64)).item()
     return {"elements_per_s": ncells * args.steps / total, "ms_per_step": total / args.steps * 1e3,
-            "lo_precision": lo, "value_storage_lo": "fp32", "inner_rtol": 1e-5,
+            "lo_precision": lo, "value_storage_lo": "fp32 symmetric (upper triangle)" if sym else "fp32 CSR",
+            "inner_rtol": 1e-5,
             "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"], "relres": info["relres"],
             "rel_error_vs_fp64_solution": err}
 

@@ -401,6 +401,25 @@ fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *v
                           double rtol, double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws,
                           size_t ws_bytes, fe_refine_info *info, fe_stream stream);
 
+/* Iterative refinement with the inner solve on the symmetric storage of A_lo
+ * in FP32 (Q1 scalar systems; the layout of fe_sym_query with float slots):
+ *   fe_sym_fp32_from_csr: sym32 (device, >= fe_sym_query / 2 bytes, 4-byte
+ *     aligned) = the upper triangle of A, rounded to FP32 (as fe_csr_to_fp32
+ *     rounds); asynchronous.
+ *   fe_refine_solve_sym: fe_refine_solve with the inner Jacobi-PCG applying
+ *     A_lo from sym32 (its FP32 values widened to FP64 in each product; every
+ *     vector, dot and the outer residual with A_hi stay FP64) and A_lo->dinv
+ *     as its diagonal; (mesh, order, coeff) those A_hi and A_lo were
+ *     assembled with (either coeff; their patterns are one).  The workspace
+ *     is fe_refine_query's.  Synchronizes; returns info->status.
+ * Errors: as for fe_sym_from_csr and fe_refine_solve. */
+fe_status fe_sym_fp32_from_csr(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A, float *sym32,
+                               size_t sym32_bytes, fe_stream stream);
+fe_status fe_refine_solve_sym(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A_hi,
+                              const fe_csr *A_lo, const float *sym32, size_t sym32_bytes, const double *b, double *x,
+                              double rtol, double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws,
+                              size_t ws_bytes, fe_refine_info *info, fe_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: a request loop with admission by device-memory budget            */
 /* ------------------------------------------------------------------------ */

@@ -746,8 +746,9 @@ fe_status fe_sym_query(fe_mesh m, int32_t order, const fe_coeff *c, size_t *byte
 }
 
 // The symmetric-storage calls share their checks: a Q1 scalar space, a buffer
-// of fe_sym_query's size, 8-byte aligned.
-static fe_status check_sym(fe_mesh m, int32_t order, const fe_coeff *c, const void *sym, size_t sym_bytes_given)
+// of fe_sym_query's size (FP64 slots), aligned to its element size.
+static fe_status check_sym(fe_mesh m, int32_t order, const fe_coeff *c, const void *sym, size_t sym_bytes_given,
+                           size_t elem = sizeof(double))
 {
     fe_status st = prepare_space(m, order, c, nullptr);
     if (st != FE_OK) return st;
@@ -755,7 +756,8 @@ static fe_status check_sym(fe_mesh m, int32_t order, const fe_coeff *c, const vo
     if (!sym_supported(sa)) return set_error(FE_EINVAL, "symmetric storage needs a Q1 scalar space");
     if (sym_bytes_given < sym_bytes(sa)) return set_error(FE_EINVAL, "symmetric storage buffer too small");
     if (sa.n_rows > 0 && !sym) return set_error(FE_EINVAL, "null symmetric storage");
-    if (reinterpret_cast<uintptr_t>(sym) & 7u) return set_error(FE_EINVAL, "symmetric storage not 8-byte aligned");
+    if (reinterpret_cast<uintptr_t>(sym) & (elem - 1))
+        return set_error(FE_EINVAL, elem == 8 ? "symmetric storage not 8-byte aligned" : "symmetric storage not 4-byte aligned");
     return FE_OK;
 }
 
@@ -850,6 +852,39 @@ fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *v
         return set_error(FE_EINVAL, "bad tolerances or iteration limits");
     return refine_solve(A_hi, A_lo, values32, b, x, rtol, inner_rtol, max_outer, max_inner, ws, ws_bytes, info,
                         as_stream(stream));
+}
+
+fe_status fe_sym_fp32_from_csr(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, float *sym32,
+                               size_t sym32_bytes, fe_stream stream)
+{
+    if (!A) return set_error(FE_EINVAL, "null argument");
+    fe_status st = check_sym(m, order, c, sym32, 2 * sym32_bytes, sizeof(float));
+    if (st != FE_OK) return st;
+    st = check_csr(A, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (A->nnz > 0 && !A->values) return set_error(FE_EINVAL, "null csr values");
+    m->last_stream = as_stream(stream);
+    return launch_sym_fill_fp32(m->space.args, A->values, sym32, as_stream(stream));
+}
+
+fe_status fe_refine_solve_sym(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A_hi, const fe_csr *A_lo,
+                              const float *sym32, size_t sym32_bytes, const double *b, double *x, double rtol,
+                              double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws, size_t ws_bytes,
+                              fe_refine_info *info, fe_stream stream)
+{
+    if (!A_hi || !A_lo || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    fe_status st = check_sym(m, order, c, sym32, 2 * sym32_bytes, sizeof(float));
+    if (st != FE_OK) return st;
+    st = check_csr(A_hi, m->space.args, true);
+    if (st != FE_OK) return st;
+    st = check_csr(A_lo, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (!A_hi->rowptr || !A_hi->colind || (A_lo->n_rows > 0 && !A_lo->dinv)) return set_error(FE_EINVAL, "incomplete csr");
+    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || max_outer < 0 || max_inner < 1)
+        return set_error(FE_EINVAL, "bad tolerances or iteration limits");
+    m->last_stream = as_stream(stream);
+    return refine_solve(A_hi, A_lo, nullptr, b, x, rtol, inner_rtol, max_outer, max_inner, ws, ws_bytes, info,
+                        as_stream(stream), &m->space.args, sym32);
 }
 
 fe_status fe_set_timing(int32_t enable)

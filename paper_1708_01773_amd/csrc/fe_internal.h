@@ -218,6 +218,7 @@ fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const doubl
 bool sym_supported(const SpaceArgs &sa);
 size_t sym_bytes(const SpaceArgs &sa);
 fe_status launch_sym_fill(const SpaceArgs &sa, const double *val, double *sym, hipStream_t s);
+fe_status launch_sym_fill_fp32(const SpaceArgs &sa, const double *val, float *sym, hipStream_t s);
 fe_status launch_spmv_sym(const SpaceArgs &sa, const double *sym, const double *x, double *y, hipStream_t s);
 fe_status pcg_solve_sym(const fe_csr *A, const SpaceArgs &sa, const double *sym, const double *b, double *x,
                         double rtol, int maxit, void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s);
@@ -234,7 +235,8 @@ size_t refine_ws_bytes(int64_t n);
 fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s);
 fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,
                        double rtol, double inner_rtol, int max_outer, int max_inner, void *ws, size_t ws_bytes,
-                       fe_refine_info *info, hipStream_t s);
+                       fe_refine_info *info, hipStream_t s, const SpaceArgs *sa = nullptr,
+                       const float *sym32 = nullptr);
 
 // Kernel timing (fe_set_timing / fe_get_timing): event pairs recorded on the
 // launching stream around timed kernels.

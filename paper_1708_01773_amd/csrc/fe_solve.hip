@@ -800,13 +800,13 @@ __host__ __device__ constexpr int64_t sym_stride(int64_t n) { return (n + 63) / 
 // first H = (3^d + 1) / 2 are summed into one partial, the rest into another,
 // and the row is their sum: the order in which the two-lane Q1 traversal sums
 // a row, so both give bitwise the same row sums of a symmetric matrix.
-template <int DIM, bool ONE, typename Fn>
-__device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double *__restrict__ gval,
-                                                const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+template <int DIM, bool ONE, typename VT, typename Fn>
+__device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__restrict__ gval,
+                                               const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
     constexpr int L = DIM == 3 ? 27 : 9, H = (L + 1) / 2, C = (L - 1) / 2;
     constexpr int RW = 64, SEG = RW + 2, NSEG = DIM == 3 ? 9 : 3, XS = NSEG * SEG, XCH = (XS + 63) / 64;
-    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL VT *__restrict__ val = as_global(gval);
     const FE_GLOBAL double *__restrict__ x = as_global(gx);
     __shared__ double xst[kQ1Waves][XS];
     double *mx = xst[threadIdx.x / 64];
@@ -864,7 +864,7 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double 
             const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
             const int64_t k = g >= C ? int64_t(g - C) * ns
                                      : int64_t(C - g) * ns + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
-            vv[g] = code_ok(g) ? val[row + k] : 0.0;
+            vv[g] = code_ok(g) ? double(val[row + k]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < XCH; u++)
@@ -904,14 +904,14 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const double 
 // stride): their values, contiguous in CSR, are loaded into LDS with
 // coalesced loads; then each half-wave writes half of the slots, one row per
 // lane (rows past n and neighbours that are not free get 0).
-template <int DIM>
+template <int DIM, typename OT>
 __global__ __launch_bounds__(kQ1Block) void sym_fill_kernel(SpaceArgs s, const double *__restrict__ gval,
-                                                            double *__restrict__ gsym)
+                                                            OT *__restrict__ gsym)
 {
     using S = Q1Step<DIM>;
     constexpr int C = DIM == 3 ? 13 : 4, NS = C + 1, SH = (NS + 1) / 2;
     const FE_GLOBAL double *__restrict__ val = as_global(gval);
-    FE_GLOBAL double *__restrict__ sym = as_global(gsym);
+    FE_GLOBAL OT *__restrict__ sym = as_global(gsym);
     __shared__ double vst[kQ1Waves][S::CAP];
     double *mv = vst[threadIdx.x / 64];
     const int lane = threadIdx.x % 64, rl = lane % S::RW, h = lane / S::RW;
@@ -968,7 +968,7 @@ __global__ __launch_bounds__(kQ1Block) void sym_fill_kernel(SpaceArgs s, const d
         const int32_t o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
         const int32_t j0 = o0 + 1 - e[0], j1 = o1 + 1 - e[1], j2 = DIM == 3 ? o2 + 1 - e[2] : 0;
         const bool ok = live && j0 >= 0 && j0 < w[0] && j1 >= 0 && j1 < w[1] && j2 >= 0 && j2 < w[2];
-        sym[sl * ns + row] = ok ? mv[off + (j2 * w[1] + j1) * w[0] + j0] : 0.0;
+        sym[sl * ns + row] = OT(ok ? mv[off + (j2 * w[1] + j1) * w[0] + j0] : 0.0);
     }
 }
 
@@ -1101,6 +1101,22 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double
         case 2302: FE_PLAN_CASE(2, 2, 3, BODY)                                                 \
         default: FE_PLAN_CASE(2, 1, 3, BODY)                                                   \
     }
+// Plans of FP32 values: the CSR plans and the symmetric-storage ones
+#define FE_SYM_DISPATCH(PL, BODY)                                                              \
+    switch ((PL).mode * 1000 + (PL).rpb) {                                                     \
+        case 8027: FE_PLAN_CASE(8, 27, 1, BODY)                                                \
+        case 8009: FE_PLAN_CASE(8, 9, 1, BODY)                                                 \
+        case 7027: FE_PLAN_CASE(7, 27, 1, BODY)                                                \
+        default: FE_PLAN_CASE(7, 9, 1, BODY)                                                   \
+    }
+#define FE_PLAN_DISPATCH_FP32(PL, BODY)                                                        \
+    do {                                                                                       \
+        if ((PL).mode >= 7) {                                                                  \
+            FE_SYM_DISPATCH(PL, BODY)                                                          \
+        } else {                                                                               \
+            FE_PLAN_DISPATCH(PL, BODY);                                                        \
+        }                                                                                      \
+    } while (0)
 #define FE_PLAN_DISPATCH_ALL(PL, BODY)                                                         \
     do {                                                                                       \
         if ((PL).mode >= 2) {                                                                  \
@@ -1205,7 +1221,7 @@ template <int MODE, int RPB, int NC, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
 {
     if constexpr (MODE == 7 || MODE == 8)
-        for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+        for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(P.sa, static_cast<const VT *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 6)
         for_rows_xblock<NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 4 || MODE == 5)
@@ -1925,7 +1941,7 @@ static void launch_rows(int which, const Group &g, const PcgProb *probs, hipStre
 {
     const PcgProb *tp = probs + g.first;
     if (g.fp32) {
-        FE_ROWS_KERNELS(FE_PLAN_DISPATCH, float)
+        FE_ROWS_KERNELS(FE_PLAN_DISPATCH_FP32, float)
     } else {
         FE_ROWS_KERNELS(FE_PLAN_DISPATCH_ALL, double)
     }
@@ -1936,7 +1952,8 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
     std::vector<int> order;
     std::vector<SpmvPlan> plans(njobs);
     for (int i = 0; i < njobs; i++) {
-        if (jobs[i].sa && jobs[i].fp32) return set_error(FE_EINVAL, "structured traversal needs FP64 values");
+        if (jobs[i].sa && jobs[i].fp32 && !jobs[i].sym)
+            return set_error(FE_EINVAL, "structured traversal needs FP64 values");
         if (jobs[i].sym)
             plans[i] = launch_form(SpmvPlan{7, 1, jobs[i].sa->dim == 3 ? 27 : 9, 2}, jobs[i].n);
         else
@@ -2236,15 +2253,26 @@ size_t sym_bytes(const SpaceArgs &sa)
     return size_t(sym_slots(sa.dim)) * size_t(sym_stride(sa.n_rows)) * sizeof(double);
 }
 
-fe_status launch_sym_fill(const SpaceArgs &sa, const double *val, double *sym, hipStream_t s)
+template <typename OT>
+static fe_status sym_fill(const SpaceArgs &sa, const double *val, OT *sym, hipStream_t s)
 {
     const int64_t ns = sym_stride(sa.n_rows);
     if (ns == 0) return FE_OK;
     const dim3 grid(unsigned((ns / 32 + kQ1Waves - 1) / kQ1Waves));  // a wave per 32 rows of the stride
-    if (sa.dim == 3) hipLaunchKernelGGL(sym_fill_kernel<3>, grid, dim3(kQ1Block), 0, s, sa, val, sym);
-    else hipLaunchKernelGGL(sym_fill_kernel<2>, grid, dim3(kQ1Block), 0, s, sa, val, sym);
+    if (sa.dim == 3) hipLaunchKernelGGL((sym_fill_kernel<3, OT>), grid, dim3(kQ1Block), 0, s, sa, val, sym);
+    else hipLaunchKernelGGL((sym_fill_kernel<2, OT>), grid, dim3(kQ1Block), 0, s, sa, val, sym);
     FE_HIP(hipGetLastError());
     return FE_OK;
+}
+
+fe_status launch_sym_fill(const SpaceArgs &sa, const double *val, double *sym, hipStream_t s)
+{
+    return sym_fill(sa, val, sym, s);
+}
+
+fe_status launch_sym_fill_fp32(const SpaceArgs &sa, const double *val, float *sym, hipStream_t s)
+{
+    return sym_fill(sa, val, sym, s);
 }
 
 fe_status launch_spmv_sym(const SpaceArgs &sa, const double *sym, const double *x, double *y, hipStream_t s)
@@ -2361,7 +2389,7 @@ fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s)
 
 fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,
                        double rtol, double inner_rtol, int max_outer, int max_inner, void *ws, size_t ws_bytes,
-                       fe_refine_info *info, hipStream_t s)
+                       fe_refine_info *info, hipStream_t s, const SpaceArgs *sa, const float *sym32)
 {
     const int64_t n = Ahi->n_rows;
     std::memset(info, 0, sizeof(*info));
@@ -2399,7 +2427,10 @@ fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values
         FE_HIP(hipMemsetAsync(d, 0, sizeof(double) * size_t(n), s));
         fe_solve_info inner;
         fe_status st;
-        if (values32)
+        if (sym32)
+            st = pcg_run<float>(n, Alo->nnz, Alo->rowptr, Alo->colind, sym32, Alo->dinv, r, d, inner_rtol,
+                                max_inner, pws, inner_bytes, &inner, s, sa, true);
+        else if (values32)
             st = pcg_run<float>(n, Alo->nnz, Alo->rowptr, Alo->colind, values32, Alo->dinv, r, d, inner_rtol,
                                 max_inner, pws, inner_bytes, &inner, s);
         else

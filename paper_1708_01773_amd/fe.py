@@ -31,6 +31,7 @@ EXPORTS = [
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
+    "fe_sym_fp32_from_csr", "fe_refine_solve_sym",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -162,6 +163,10 @@ def lib():
             "fe_spmv_plan_of_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
             "fe_spmv_plan_set_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan)],
             "fe_sym_query": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_size_t)],
+            "fe_sym_fp32_from_csr": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_refine_solve_sym": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _c.POINTER(Csr), _P,
+                                    _c.c_size_t, _P, _P, _c.c_double, _c.c_double, _c.c_int32, _c.c_int32, _P,
+                                    _c.c_size_t, _c.POINTER(RefineInfo), _P],
             "fe_sym_from_csr": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
             "fe_spmv_sym": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _c.c_size_t, _P, _P, _P],
             "fe_pcg_solve_sym": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P, _P,
@@ -516,6 +521,25 @@ def refine_solve(A_hi, A_lo, b, x, rtol, inner_rtol, max_outer, max_inner, ws, v
                                ws.numel() * ws.element_size(), _c.byref(info), _stream(stream))
     if st not in (FE_OK, FE_ENOTCONV):
         _check(st, "fe_refine_solve")
+    return dict(outer_iters=info.outer_iters, inner_iters=info.inner_iters, status=info.status, relres=info.relres)
+
+
+def sym_fp32_from_csr(mesh, order, coeff, csr, sym32, stream=None):
+    """sym32 (float32 device tensor of sym_query / 2 bytes) = upper triangle of csr in FP32."""
+    _check(lib().fe_sym_fp32_from_csr(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), _ptr(sym32),
+                                      _nbytes(sym32), _stream(stream)), "fe_sym_fp32_from_csr")
+
+
+def refine_solve_sym(mesh, order, coeff, A_hi, A_lo, sym32, b, x, rtol, inner_rtol, max_outer, max_inner, ws,
+                     stream=None):
+    """Iterative refinement with the inner PCG on the FP32 symmetric storage of A_lo."""
+    info = RefineInfo()
+    st = lib().fe_refine_solve_sym(mesh.handle, int(order), _c.byref(coeff), _c.byref(A_hi), _c.byref(A_lo),
+                                   _ptr(sym32), _nbytes(sym32), _ptr(b), _ptr(x), float(rtol), float(inner_rtol),
+                                   int(max_outer), int(max_inner), _ptr(ws), _nbytes(ws), _c.byref(info),
+                                   _stream(stream))
+    if st not in (FE_OK, FE_ENOTCONV):
+        _check(st, "fe_refine_solve_sym")
     return dict(outer_iters=info.outer_iters, inner_iters=info.inner_iters, status=info.status, relres=info.relres)
 
 

@@ -59,3 +59,48 @@ def test_refinement_limits():
     # with the FP64 matrix itself as the inner operator one tight correction suffices
     info = F.refine_solve(A.csr, A.csr, A.rhs, x, 1e-10, 1e-12, 5, 2000, ws)
     assert info["status"] == F.FE_OK and info["outer_iters"] == 1
+
+
+@pytest.mark.parametrize("dim,n,lo_prec,faces", [(3, [12, 10, 8], "fp32", None), (3, [9, 7, 11], "fp64", 0b011010),
+                                                 (2, [40, 33], "fp32", None)])
+def test_refinement_on_fp32_symmetric_storage(dim, n, lo_prec, faces):
+    """The inner PCG on the FP32 symmetric storage of A_lo: the storage is the
+    FP32 rounding of the FP64 one entry by entry, and the refined solution
+    reaches FP64 accuracy like the CSR-stored FP32 inner solve."""
+    say(f"[refine sym32] dim={dim} n={n} A_lo integrated in {lo_prec} faces={faces}")
+    src = (1.0,)
+    hi = Pair(dim, n, 1, source=src, faces=faces, seed=61)
+    A_hi = hi.gpu_assembly()
+    lo = Pair(dim, n, 1, source=src, faces=faces, seed=61, precision=lo_prec)
+    A_lo = lo.gpu_assembly()
+    nb = F.sym_query(lo.mesh, 1, lo.coeff)
+    sym64 = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+    sym32 = torch.full((nb // 8,), float("nan"), dtype=torch.float32, device="cuda")
+    F.sym_from_csr(lo.mesh, 1, lo.coeff, A_lo.csr, sym64)
+    F.sym_fp32_from_csr(lo.mesh, 1, lo.coeff, A_lo.csr, sym32)
+    torch.cuda.synchronize()
+    assert torch.equal(sym32, sym64.float())
+    ws = torch.empty(F.refine_query(A_hi.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A_hi.n_rows, dtype=torch.float64, device="cuda")
+    info = F.refine_solve_sym(hi.mesh, 1, hi.coeff, A_hi.csr, A_lo.csr, sym32, A_hi.rhs, x, 1e-12, 1e-4, 50, 5000, ws)
+    x2 = torch.zeros_like(x)
+    info2 = F.refine_solve_sym(hi.mesh, 1, hi.coeff, A_hi.csr, A_lo.csr, sym32, A_hi.rhs, x2, 1e-12, 1e-4, 50, 5000,
+                               ws)
+    v32 = torch.empty(A_lo.nnz, dtype=torch.float32, device="cuda")
+    F.csr_to_fp32(A_lo.csr, v32)
+    xc = torch.zeros_like(x)
+    infoc = F.refine_solve(A_hi.csr, A_lo.csr, A_hi.rhs, xc, 1e-12, 1e-4, 50, 5000, ws, values32=v32)
+    torch.cuda.synchronize()
+    say(f"   sym32 {info}  csr32 {infoc}")
+    assert info["status"] == infoc["status"] == F.FE_OK and info["relres"] <= 1e-12
+    assert info2 == info and torch.equal(x, x2)
+    assert abs(info["outer_iters"] - infoc["outer_iters"]) <= 1
+    xr, _ = _fp64_solution(A_hi)
+    assert rel(x.cpu().numpy(), xr.cpu().numpy()) <= 1e-10
+    # a float buffer only 4-byte aligned is accepted; one too small is refused
+    raw = torch.empty(nb // 8 + 1, dtype=torch.float32, device="cuda")
+    F.sym_fp32_from_csr(lo.mesh, 1, lo.coeff, A_lo.csr, raw[1:])
+    torch.cuda.synchronize()
+    assert torch.equal(raw[1:], sym32)
+    with pytest.raises(F.FeError, match="too small"):
+        F.sym_fp32_from_csr(lo.mesh, 1, lo.coeff, A_lo.csr, raw[2:])
