@@ -160,3 +160,32 @@ def test_symmetric_storage_refuses_other_spaces_and_bad_buffers():
     raw = torch.empty(nb + 8, dtype=torch.uint8, device="cuda")
     with pytest.raises(F.FeError, match="8-byte"):
         F.sym_from_csr(pair.mesh, 1, pair.coeff, A.csr, raw[4: 4 + nb])
+
+
+@pytest.mark.parametrize("dim,n", [(3, [1, 1, 1]), (3, [2, 2, 2]), (2, [2, 2]), (2, [1, 3])])
+def test_symmetric_storage_of_empty_and_single_row_systems(dim, n):
+    """All-Dirichlet meshes with no free node (nothing launched, FE_OK) or one
+    free node (a 1 x 1 system: the diagonal slot only)."""
+    pair = Pair(dim, n, 1, seed=58)
+    A = pair.gpu_assembly()
+    say(f"[sym edge] dim {dim} n {n} rows {A.n_rows}")
+    nb = F.sym_query(pair.mesh, 1, pair.coeff)
+    assert nb == (14 if dim == 3 else 5) * ((A.n_rows + 63) // 64 * 64) * 8
+    sym = torch.full((max(nb // 8, 1),), float("nan"), dtype=torch.float64, device="cuda")
+    F.sym_from_csr(pair.mesh, 1, pair.coeff, A.csr, sym)
+    x = torch.ones(max(A.n_rows, 1), dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym, x, y)
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    u = torch.zeros_like(x)
+    info = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym, A.rhs, u, 1e-10, 100, ws)
+    torch.cuda.synchronize()
+    assert info["status"] == F.FE_OK
+    if A.n_rows == 0:
+        assert nb == 0 and info["iters"] == 0
+    else:
+        assert A.n_rows == 1
+        d = float(A.values[0])
+        assert float(sym[0]) == d and bool(torch.all(sym[1:] == 0.0))
+        assert float(y[0]) == d
+        assert abs(float(u[0]) - float(A.rhs[0]) / d) <= 1e-14 * abs(float(A.rhs[0]) / d)
