@@ -46,6 +46,7 @@ constexpr int kWaveCap = 256;   // products staged in LDS per wave (2 KB)
 // count against the LDS counter the way flat accesses do.
 #define FE_GLOBAL __attribute__((address_space(1)))
 typedef double fe_dpair __attribute__((ext_vector_type(2)));  // 16-byte access of two doubles
+__device__ __forceinline__ bool pair_aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 template <typename T>
 __device__ __forceinline__ const FE_GLOBAL T *as_global(const T *p)
 {
@@ -241,24 +242,44 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *part, in
 
 // Grand totals of partials part[t * stride + b], b < nparts, written by a
 // previous kernel of `nparts` blocks; identical in every thread of every
-// block.  A thread sums its partials b = tid + j kBlock into accumulator
-// j mod 8 (eight loads in flight) and adds the eight in a fixed tree.
+// block.  A thread sums the pairs of partials b = tid + j kBlock into
+// accumulator j mod 8 (eight pair loads in flight; an odd last partial goes
+// to thread 0's last accumulator) and adds the eight in a fixed tree.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double *gpart, int nparts, int stride, double (&tot)[NV])
 {
     const FE_GLOBAL double *__restrict__ part = as_global(gpart);
 #pragma unroll
     for (int t = 0; t < NV; t++) {
+        const FE_GLOBAL double *__restrict__ pt = part + int64_t(t) * stride;
         double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int b = threadIdx.x;
-        for (; b + 7 * kBlock < nparts; b += 8 * kBlock) {
-            double v[8];
+        const int np2 = nparts / 2;
+        // pair b (partials 2b, 2b + 1) goes to accumulator (b / kBlock) mod 8;
+        // 16-byte loads when the array is 16-byte aligned, else two 8-byte
+        // loads: the same sums either way (decided once, outside the loops)
+        auto sum_pairs = [&](auto wide) {
+            constexpr bool W = decltype(wide)::value;
+            auto pair = [&](int b) -> double {
+                if constexpr (W) {
+                    const fe_dpair v = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(pt + 2 * b);
+                    return v.x + v.y;
+                } else {
+                    return pt[2 * b] + pt[2 * b + 1];
+                }
+            };
+            int b = threadIdx.x;
+            for (; b + 7 * kBlock < np2; b += 8 * kBlock) {
+                double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; u++) v[u] = part[t * stride + b + u * kBlock];
+                for (int u = 0; u < 8; u++) v[u] = pair(b + u * kBlock);
 #pragma unroll
-            for (int u = 0; u < 8; u++) a[u] += v[u];
-        }
-        for (int u = 0; b < nparts; b += kBlock, u++) a[u] += part[t * stride + b];
+                for (int u = 0; u < 8; u++) a[u] += v[u];
+            }
+            for (int u = 0; b < np2; b += kBlock, u++) a[u] += pair(b);
+        };
+        if (pair_aligned(gpart + int64_t(t) * stride)) sum_pairs(std::true_type{});
+        else sum_pairs(std::false_type{});
+        if ((nparts & 1) && threadIdx.x == 0) a[7] += pt[nparts - 1];
         tot[t] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     block_sum_all<NV>(tot);
@@ -1269,7 +1290,6 @@ __device__ __forceinline__ int64_t xcd_block(int64_t lb, int64_t nb)
 // vector of the kernel 16-byte aligned, the kernel decides once per block),
 // else one element at a time (a caller's vector only 8-byte aligned); m = 2,
 // or 1 for the last, odd element of a range.
-__device__ __forceinline__ bool pair_aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 template <bool W>
 __device__ __forceinline__ void load_pair(const double *__restrict__ ga, int64_t i, int m, double (&o)[2])
