@@ -171,7 +171,9 @@ __device__ __forceinline__ void k3_q1_body(const SpaceArgs &s, const MeshArgs &m
 #pragma unroll
     for (int a = 0; a < NN; a++) fl[a] = 0.0;
     bool bad = false;
-#pragma unroll
+    // the points one at a time: unrolled, every point's operands stayed live
+    // at once (366 VGPRs, one wave per SIMD; 224 and two waves this way)
+#pragma unroll 1
     for (int q = 0; q < NN; q++) {
         const int q0 = q & 1, q1 = (q >> 1) & 1, q2 = (q >> 2) & 1;
         const double xi[3] = {rt.gx[q0], rt.gx[q1], DIM == 3 ? rt.gx[q2] : 0.0};
