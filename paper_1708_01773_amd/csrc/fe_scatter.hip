@@ -107,6 +107,35 @@ __device__ __forceinline__ void wave_lds_fence()
 // ascending id, which is the summation order of every entry (as in the
 // cell-major traversal); contributions to fixed columns are accumulated and
 // dropped.
+// Work units of the Q1 scatter: line-aligned chunks of at most 64 rows (a
+// line of nodes along x holds ceil(f0 / 64) of them), taken in strips of
+// kQ1Strip lines along y through every plane: strip, then plane, then line
+// in the strip, then chunk in the line.  A cell plane's element matrices are
+// read again by the next plane of nodes a strip later, not a whole plane of
+// nodes later, so the second read finds them in L2.
+constexpr int kQ1Strip = 16;
+
+__host__ __device__ inline int64_t q1_chunks(const SpaceArgs &s)
+{
+    const int64_t f0 = s.ax[0].f;
+    return f0 == 0 ? 0 : (s.n_rows / f0) * ((f0 + 63) / 64);
+}
+
+// First row and row count of chunk c < q1_chunks(s).
+__device__ __forceinline__ void q1_chunk_rows(const SpaceArgs &s, int64_t c, int64_t &r0, int &nrows)
+{
+    const int64_t f0 = s.ax[0].f, f1 = s.ax[1].f, f2 = s.n_rows / f0 / f1;
+    const int64_t cpl = (f0 + 63) / 64, full = kQ1Strip * f2 * cpl;
+    const int64_t nstrip = (f1 + kQ1Strip - 1) / kQ1Strip;
+    const int64_t st = c / full < nstrip - 1 ? c / full : nstrip - 1;
+    const int64_t rem = c - st * full;
+    const int64_t sy = st == nstrip - 1 ? f1 - st * kQ1Strip : kQ1Strip;  // lines of this strip
+    const int64_t z = rem / (sy * cpl), rem2 = rem - z * (sy * cpl);
+    const int64_t y = st * kQ1Strip + rem2 / cpl, part = rem2 - (rem2 / cpl) * cpl;
+    r0 = (z * f1 + y) * f0 + part * 64;
+    nrows = int(f0 - part * 64 < 64 ? f0 - part * 64 : 64);
+}
+
 template <int DIM, typename ET>
 __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restrict__ E,
                                            const double *__restrict__ F, double *__restrict__ values,
@@ -119,9 +148,11 @@ __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restr
     __shared__ double stage[4][64 * NS];
     double *my = stage[threadIdx.x / 64];
     const int lane = threadIdx.x % 64;
-    const int64_t r0 = (bid * 4 + threadIdx.x / 64) * 64;
-    if (r0 >= s.n_rows) return;  // the whole wave leaves together
-    const int nvalid = int(s.n_rows - r0 < 64 ? s.n_rows - r0 : 64);
+    const int64_t chunk = bid * 4 + threadIdx.x / 64;
+    if (chunk >= q1_chunks(s)) return;  // the whole wave leaves together
+    int64_t r0;
+    int nvalid;
+    q1_chunk_rows(s, chunk, r0, nvalid);
     const int64_t row = r0 + lane;
     RowGeom g{};
     int len = 0;
@@ -418,8 +449,8 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
     if (sa.n_rows == 0) return FE_OK;
     const double *F = reinterpret_cast<const double *>(static_cast<const char *>(ws) + el.f_offset);
     if (el.cb > 1) {
-        // thread per row: 4 waves of 64 rows per block
-        const int64_t grid = (sa.n_rows + 255) / 256;
+        // thread per row: 4 waves of one chunk each per block
+        const int64_t grid = (q1_chunks(sa) + 3) / 4;
         if (el.cb != 64) return set_error(FE_EINVAL, "unexpected element layout");
 #define FE_K5Q(D, T)                                                                                           \
     hipLaunchKernelGGL((k5_q1_kernel<D, T>), dim3(grid), dim3(256), 0, s, sa, static_cast<const T *>(ws), F, values, \
@@ -458,7 +489,7 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
 int64_t scatter_blocks(const SpaceArgs &sa, const ElemLayout &el)
 {
     if (sa.n_rows == 0) return 0;
-    if (el.cb > 1) return (sa.n_rows + 255) / 256;
+    if (el.cb > 1) return (q1_chunks(sa) + 3) / 4;
     return std::min<int64_t>((sa.n_rows + 3) / 4, 8192);
 }
 
