@@ -114,6 +114,7 @@ __device__ __forceinline__ void wave_lds_fence()
 // read again by the next plane of nodes a strip later, not a whole plane of
 // nodes later, so the second read finds them in L2.
 constexpr int kQ1Strip = 16;
+constexpr int kQ1Win = 864;  // staged output values per wave (half of 64 full 3D rows)
 
 __host__ __device__ inline int64_t q1_chunks(const SpaceArgs &s)
 {
@@ -145,7 +146,8 @@ __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restr
     constexpr int NT = NN * (NN + 1) / 2;       // stored entries per cell (upper triangle)
     constexpr int NS = DIM == 3 ? 27 : 9;       // stencil entries
     constexpr int CB = 64;                      // cells per block of E
-    __shared__ double stage[4][64 * NS];
+    constexpr int WIN = DIM == 3 ? kQ1Win : 64 * NS;  // 2D: one window holds 64 rows
+    __shared__ double stage[4][WIN];
     double *my = stage[threadIdx.x / 64];
     const int lane = threadIdx.x % 64;
     const int64_t chunk = bid * 4 + threadIdx.x / 64;
@@ -189,22 +191,33 @@ __device__ __forceinline__ void k5_q1_body(const SpaceArgs &s, const ET *__restr
     const int64_t last_start = __shfl(g.start, nvalid - 1);
     const int last_len = __shfl(len, nvalid - 1);
     const int total = int(last_start - base) + last_len;
+    const int o0 = int(g.cl0 - (g.I0 - 1)), o1 = int(g.cl1 - (g.I1 - 1));
+    const int o2 = DIM == 3 ? int(g.cl2 - (g.I2 - 1)) : 0;
     if (lane < nvalid) {
-        double *out = my + (g.start - base);
-        const int o0 = int(g.cl0 - (g.I0 - 1)), o1 = int(g.cl1 - (g.I1 - 1));
-        const int o2 = DIM == 3 ? int(g.cl2 - (g.I2 - 1)) : 0;
-#pragma unroll
-        for (int t = 0; t < NS; t++) {
-            const int s0 = t % 3, s1 = (t / 3) % 3, s2 = t / 9;
-            const int j0 = s0 - o0, j1 = s1 - o1, j2 = s2 - o2;
-            if (j0 >= 0 && j0 < g.w0 && j1 >= 0 && j1 < g.w1 && j2 >= 0 && j2 < g.w2)
-                out[(j2 * g.w1 + j1) * g.w0 + j0] = acc[t];
-        }
         dinv[row] = 1.0 / acc[NS / 2];
         rhs[row] = fsum;
     }
-    wave_lds_fence();
-    for (int t = lane; t < total; t += 64) values[base + t] = my[t];
+    // the wave's output [base, base + total) goes out through windows of WIN
+    // values: each row places the entries that fall in the window, then the
+    // window is written contiguously
+    for (int w = 0; w < total; w += WIN) {
+        if (lane < nvalid) {
+            const int rel = int(g.start - base) - w;
+#pragma unroll
+            for (int t = 0; t < NS; t++) {
+                const int s0 = t % 3, s1 = (t / 3) % 3, s2 = t / 9;
+                const int j0 = s0 - o0, j1 = s1 - o1, j2 = s2 - o2;
+                const int pos = rel + (j2 * g.w1 + j1) * g.w0 + j0;
+                if (j0 >= 0 && j0 < g.w0 && j1 >= 0 && j1 < g.w1 && j2 >= 0 && j2 < g.w2 && pos >= 0 &&
+                    pos < WIN)
+                    my[pos] = acc[t];
+            }
+        }
+        wave_lds_fence();
+        const int cnt = total - w < WIN ? total - w : WIN;
+        for (int t = lane; t < cnt; t += 64) values[base + w + t] = my[t];
+        wave_lds_fence();
+    }
 }
 
 template <int DIM, typename ET>
