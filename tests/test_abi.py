@@ -99,3 +99,18 @@ def test_batch_and_tuning_entry_points_validate_on_host():
     assert mode == 0 and rpw * 27 <= 256 and rpw * 2 * 27 > 256
     mode, rpw, cls2 = F.spmv_plan_of(1000, 343000)
     assert mode == 1 and cls2 > cls
+
+
+def test_symmetric_storage_entry_points_validate_on_host():
+    L = F.lib()
+    c = F.make_coeff()
+    nb = ctypes.c_size_t(123)
+    assert L.fe_sym_query(None, 1, ctypes.byref(c), None) == F.FE_EINVAL
+    assert L.fe_sym_query(None, 1, ctypes.byref(c), ctypes.byref(nb)) == F.FE_EINVAL and nb.value == 0
+    assert L.fe_sym_from_csr(None, 1, ctypes.byref(c), None, None, 0, None) == F.FE_EINVAL
+    assert L.fe_sym_fp32_from_csr(None, 1, ctypes.byref(c), None, None, 0, None) == F.FE_EINVAL
+    assert L.fe_spmv_sym(None, 1, ctypes.byref(c), None, 0, None, None, None) == F.FE_EINVAL
+    assert L.fe_pcg_solve_sym(None, 1, ctypes.byref(c), None, None, 0, None, None, 1e-8, 10, None, 0, None,
+                              None) == F.FE_EINVAL
+    assert L.fe_refine_solve_sym(None, 1, ctypes.byref(c), None, None, None, 0, None, None, 1e-10, 1e-5, 5, 100,
+                                 None, 0, None, None) == F.FE_EINVAL
