@@ -826,10 +826,13 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
                                                const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
     constexpr int L = DIM == 3 ? 27 : 9, H = (L + 1) / 2, C = (L - 1) / 2;
-    constexpr int RW = 64, SEG = RW + 2, NSEG = DIM == 3 ? 9 : 3, XS = NSEG * SEG, XCH = (XS + 63) / 64;
+    // x runs staged from the even index at or below their start (16-byte pairs):
+    // SEG2 = 68 slots per run, the run's first unknown at slot lead (0 or 1)
+    constexpr int RW = 64, SEG = RW + 2, NSEG = DIM == 3 ? 9 : 3, SEG2 = SEG + 2, NP = SEG2 / 2;
+    constexpr int XS = NSEG * SEG2, XCH = (NSEG * NP + 63) / 64;
     const FE_GLOBAL VT *__restrict__ val = as_global(gval);
     const FE_GLOBAL double *__restrict__ x = as_global(gx);
-    __shared__ double xst[kQ1Waves][XS];
+    __shared__ __align__(16) double xst[kQ1Waves][XS];
     double *mx = xst[threadIdx.x / 64];
     const int lane = threadIdx.x % 64;
     const int64_t n = s.n_rows, ns = sym_stride(n);
@@ -849,6 +852,11 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
     auto step = [&](int64_t run) {
         const int64_t r0 = run * RW, row = r0 + lane;
         const bool live = row < n;
+        // slot of run sg's first unknown: 1 when it starts at an odd index
+        auto lead = [&](int sgi) {
+            const int dy = sgi % 3 - 1, dz = sgi / 3 - 1;
+            return int((r0 - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0)) & 1);
+        };
         // allowed neighbour offsets o of the row per axis: bit o + 1 (none for a row past n)
         uint32_t mk0 = 0, mk1 = 0, mk2 = 0;
         if (live) {
@@ -863,15 +871,24 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             mk1 = ((1u << w1) - 1u) << (cl1 - (A[1].lo + t1) + 1);
             mk2 = DIM == 3 ? ((1u << w2) - 1u) << (cl2 - (A[2].lo + t2) + 1) : 2u;
         }
-        double xs[XCH];
+        const bool xw = pair_aligned(gx);
+        fe_dpair xs[XCH];
 #pragma unroll
         for (int u = 0; u < XCH; u++) {
-            const int i = lane + 64 * u;
-            const int sg = i / SEG, kk = i - sg * SEG;
+            const int i = lane + 64 * u;  // pair i of the staged runs
+            const int sg = i / NP, kk = 2 * (i - sg * NP);
             const int dy = sg % 3 - 1, dz = sg / 3 - 1;
-            int64_t a = r0 + kk - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0);
-            a = a < 0 ? 0 : (a >= n ? n - 1 : a);  // slots past either end are never read
-            xs[u] = x[a];
+            const int64_t st = r0 - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0);
+            int64_t a = (st & ~int64_t(1)) + kk;
+            // pairs past either end (and lanes past the staged pairs) are never
+            // read: clamped into the vector; the last unknown may start a pair
+            a = a < 0 ? 0 : a;
+            if (xw && a + 1 < n) {
+                xs[u] = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(x + a);
+            } else {
+                const int64_t b = a < n ? a : n - 1, c = a + 1 < n ? a + 1 : n - 1;
+                xs[u] = fe_dpair{x[b], x[c]};
+            }
         }
         // code g = 9 (o2 + 1) + 3 (o1 + 1) + (o0 + 1): the value of a free
         // neighbour is the row plus an offset common to the wave
@@ -889,7 +906,7 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
         }
 #pragma unroll
         for (int u = 0; u < XCH; u++)
-            if (lane + 64 * u < XS) mx[lane + 64 * u] = xs[u];
+            if (lane + 64 * u < NSEG * NP) reinterpret_cast<fe_dpair *>(mx)[lane + 64 * u] = xs[u];
         wave_lds_sync();
         // the row's columns in ascending order are its free codes in ascending
         // order: the first H go to lo, the rest to hi
@@ -898,7 +915,8 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
 #pragma unroll
         for (int g = 0; g < L; g++) {
             const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
-            const double xg = mx[(DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1) * SEG + o0 + 1 + lane];
+            const int sgi = DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1;
+            const double xg = mx[sgi * SEG2 + lead(sgi) + o0 + 1 + lane];
             if (code_ok(g)) {
                 if (c < H) lo += vv[g] * xg;
                 else hi += vv[g] * xg;
@@ -907,7 +925,7 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
         }
         if (live) {
             if constexpr (std::is_invocable_v<Fn, int64_t, double, double>)
-                f(row, lo + hi, mx[(DIM == 3 ? 4 : 1) * SEG + lane + 1]);
+                f(row, lo + hi, mx[(DIM == 3 ? 4 : 1) * SEG2 + lead(DIM == 3 ? 4 : 1) + lane + 1]);
             else
                 f(row, lo + hi);
         }

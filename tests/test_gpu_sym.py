@@ -189,3 +189,33 @@ def test_symmetric_storage_of_empty_and_single_row_systems(dim, n):
         assert float(sym[0]) == d and bool(torch.all(sym[1:] == 0.0))
         assert float(y[0]) == d
         assert abs(float(u[0]) - float(A.rhs[0]) / d) <= 1e-14 * abs(float(A.rhs[0]) / d)
+
+
+@pytest.mark.parametrize("dim,n", [(3, [7, 6, 5]), (2, [33, 17])])
+def test_symmetric_storage_with_vectors_off_16_byte_boundaries(dim, n):
+    """x is staged with 16-byte loads when it is 16-byte aligned, else with
+    8-byte loads into the same slots: an x (and a workspace, which holds the
+    PCG's direction) 8 bytes off a 16-byte boundary give bitwise the same."""
+    pair = Pair(dim, n, 1, seed=59)
+    A = pair.gpu_assembly()
+    say(f"[sym unaligned] dim {dim} n {n} rows {A.n_rows}")
+    sym = _sym_of(pair, A)
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(60)).standard_normal(A.n_rows)).cuda()
+    xb = torch.empty(A.n_rows + 1, dtype=torch.float64, device="cuda")
+    xb[1:] = x
+    xm = xb[1:]
+    assert xm.data_ptr() % 16 == 8
+    y, ym = torch.empty_like(x), torch.empty_like(x)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym, x, y)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym, xm, ym)
+    nbw = F.pcg_query(A.n_rows)
+    ws = torch.empty(nbw, dtype=torch.uint8, device="cuda")
+    wb = torch.empty(nbw + 16, dtype=torch.uint8, device="cuda")
+    w8 = wb[8: 8 + nbw]
+    assert w8.data_ptr() % 16 == 8
+    u, u8 = torch.zeros_like(x), torch.zeros_like(x)
+    info = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym, A.rhs, u, 1e-10, 20000, ws)
+    info8 = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym, A.rhs, u8, 1e-10, 20000, w8)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ym)
+    assert info["status"] == info8["status"] == F.FE_OK and info["iters"] == info8["iters"] and torch.equal(u, u8)
