@@ -52,6 +52,18 @@ __device__ __forceinline__ const FE_GLOBAL T *as_global(const T *p)
 {
     return (const FE_GLOBAL T *)p;
 }
+// A pointer that is the same in every lane, moved to scalar registers, so
+// loads take it as their base with a 32-bit offset per lane.  The builtin
+// reads an int: both halves go back through uint32_t, or the low half would
+// be sign-extended into the high one.
+template <typename T>
+__device__ __forceinline__ const FE_GLOBAL char *wave_base(const T *p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a >> 32))));
+    return reinterpret_cast<const FE_GLOBAL char *>((uint64_t(hi) << 32) | uint64_t(lo));
+}
 template <typename T>
 __device__ __forceinline__ FE_GLOBAL T *as_global(T *p)
 {
@@ -831,6 +843,7 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
     constexpr int RW = 64, SEG = RW + 2, NSEG = DIM == 3 ? 9 : 3, SEG2 = SEG + 2, NP = SEG2 / 2;
     constexpr int XS = NSEG * SEG2, XCH = (NSEG * NP + 63) / 64;
     const FE_GLOBAL VT *__restrict__ val = as_global(gval);
+    const FE_GLOBAL char *__restrict__ vbase = wave_base(gval);
     const FE_GLOBAL double *__restrict__ x = as_global(gx);
     __shared__ __align__(16) double xst[kQ1Waves][XS];
     double *mx = xst[threadIdx.x / 64];
@@ -902,7 +915,13 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
             const int64_t k = g >= C ? int64_t(g - C) * ns
                                      : int64_t(C - g) * ns + o0 + int64_t(o1) * f0 + int64_t(o2) * plane;
-            vv[g] = code_ok(g) ? double(val[row + k]) : 0.0;
+            if constexpr (ONE) {
+                // one step per wave (at most 8.4 M rows): byte offsets fit in 32 bits
+                const uint32_t boff = uint32_t(row + k) * uint32_t(sizeof(VT));
+                vv[g] = code_ok(g) ? double(*reinterpret_cast<const FE_GLOBAL VT *>(vbase + boff)) : 0.0;
+            } else {
+                vv[g] = code_ok(g) ? double(val[row + k]) : 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < XCH; u++)

@@ -219,3 +219,62 @@ def test_symmetric_storage_with_vectors_off_16_byte_boundaries(dim, n):
     torch.cuda.synchronize()
     assert torch.equal(y, ym)
     assert info["status"] == info8["status"] == F.FE_OK and info["iters"] == info8["iters"] and torch.equal(u, u8)
+
+
+def _views_above_bit_31(sizes):
+    """Byte views of one allocation of 4 GiB and a little more, each starting
+    at an address whose low 32 bits have the top bit set (256-byte aligned).
+    Kernels that take a buffer's base in scalar registers rebuild it from two
+    32-bit halves; a low half read back as a signed int would corrupt the
+    high half exactly at such addresses."""
+    spans = [(s + 255) // 256 * 256 for s in sizes]
+    assert sum(spans) <= 2**30
+    buf = torch.empty(2**32 + sum(spans) + 256, dtype=torch.uint8, device="cuda")
+    off = ((2**31 + 2**20) - (buf.data_ptr() & 0xFFFFFFFF)) % 2**32
+    views = []
+    for s, sp in zip(sizes, spans):
+        v = buf[off: off + s]
+        assert v.data_ptr() & 0x80000000 and (v.data_ptr() & 0xFFFFFFFF) + s < 2**32
+        views.append(v)
+        off += sp
+    return buf, views
+
+
+@pytest.mark.parametrize("dim,n", [(3, [7, 6, 5]), (2, [33, 17])])
+def test_symmetric_storage_at_addresses_with_bit_31_set(dim, n):
+    """The symmetric storage (FP64 and FP32), x and the workspace placed where
+    the low word of the address has its top bit set: the same storage, the
+    same products and bitwise the same solves as at ordinary addresses."""
+    pair = Pair(dim, n, 1, seed=62)
+    A = pair.gpu_assembly()
+    say(f"[sym bit 31] dim {dim} n {n} rows {A.n_rows}")
+    nb = F.sym_query(pair.mesh, 1, pair.coeff)
+    nbw, nbr = F.pcg_query(A.n_rows), F.refine_query(A.n_rows)
+    buf, (b64, b32, bx, bw, br) = _views_above_bit_31([nb, nb // 2, 8 * A.n_rows, nbw, nbr])
+    sym, sym_h = _sym_of(pair, A), b64.view(torch.float64)
+    F.sym_from_csr(pair.mesh, 1, pair.coeff, A.csr, sym_h)
+    sym32 = torch.empty(nb // 8, dtype=torch.float32, device="cuda")
+    sym32_h = b32.view(torch.float32)
+    F.sym_fp32_from_csr(pair.mesh, 1, pair.coeff, A.csr, sym32)
+    F.sym_fp32_from_csr(pair.mesh, 1, pair.coeff, A.csr, sym32_h)
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(63)).standard_normal(A.n_rows)).cuda()
+    x_h = bx.view(torch.float64)
+    x_h.copy_(x)
+    y, y_h = torch.empty_like(x), torch.empty_like(x)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym, x, y)
+    F.spmv_sym(pair.mesh, 1, pair.coeff, sym_h, x_h, y_h)
+    ws, wr = (torch.empty(k, dtype=torch.uint8, device="cuda") for k in (nbw, nbr))
+    u, u_h = torch.zeros_like(x), torch.zeros_like(x)
+    info = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym, A.rhs, u, 1e-10, 20000, ws)
+    info_h = F.pcg_solve_sym(pair.mesh, 1, pair.coeff, A.csr, sym_h, A.rhs, u_h, 1e-10, 20000, bw)
+    v, v_h = torch.zeros_like(x), torch.zeros_like(x)
+    rinfo = F.refine_solve_sym(pair.mesh, 1, pair.coeff, A.csr, A.csr, sym32, A.rhs, v, 1e-12, 1e-4, 50, 5000, wr)
+    rinfo_h = F.refine_solve_sym(pair.mesh, 1, pair.coeff, A.csr, A.csr, sym32_h, A.rhs, v_h, 1e-12, 1e-4, 50, 5000,
+                                 br)
+    torch.cuda.synchronize()
+    assert torch.equal(sym_h, sym) and torch.equal(sym32_h, sym32) and torch.equal(y_h, y)
+    assert info["status"] == info_h["status"] == F.FE_OK and info_h["iters"] == info["iters"]
+    assert torch.equal(u_h, u)
+    assert rinfo["status"] == F.FE_OK and rinfo_h == rinfo and torch.equal(v_h, v)
+    del buf
+    torch.cuda.empty_cache()
