@@ -40,7 +40,7 @@ def test_spmv_matches_oracle(dim, n, k, prob):
 
 
 def test_c1_solution_matches_oracle():
-    """configs[0]: 2D Poisson, 32x32 Q1, k = 1, sin-product load, u = 0 on the
+    """The small 2D case: Poisson, 32x32 Q1, k = 1, sin-product load, u = 0 on the
     boundary, FP64 CSR + Jacobi-PCG to rtol 1e-10; then both solved to
     stagnation (rtol 1e-14) must agree to 1e-12."""
     say("[pcg] C1")
