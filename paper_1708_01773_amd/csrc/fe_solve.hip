@@ -823,7 +823,8 @@ __host__ __device__ constexpr int64_t sym_stride(int64_t n) { return (n + 63) / 
 // Rows of a Q1 scalar system in symmetric storage (plan mode 7; mode 8 is
 // its instantiation with one step per wave).  A wave step takes 64
 // consecutive rows, one lane per row; x is staged in LDS as 3^(d-1) runs of
-// 66 unknowns (as in the Q1 traversal, one run per neighbour line).  The value
+// 66 unknowns (as in the Q1 traversal, one run per neighbour line), loaded
+// straight into LDS in the one-step form.  The value
 // of the neighbour with code g sits at the row plus an offset that depends on
 // g only (slot |g - C|, and the mirrored row for g < C), so each lane walks the
 // 3^d codes with a mask of the free ones (per axis, the offsets inside the
@@ -885,9 +886,37 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             mk2 = DIM == 3 ? ((1u << w2) - 1u) << (cl2 - (A[2].lo + t2) + 1) : 2u;
         }
         const bool xw = pair_aligned(gx);
+        // One-step form with x 16-byte aligned: each lane's pair goes from
+        // memory straight to LDS (a load-to-LDS instruction writes lane l's 16
+        // bytes at the wave's LDS base + 16 l, which is pair slot 64 u + l), so
+        // no registers are held for x across the value loads (82 instead of 96
+        // VGPRs).  A pair that would run past the vector's end (the last
+        // unknown starting a pair, or a clamped lane) is written by the lane.
+        const bool dma = ONE && xw;
+        if (dma) {
+#pragma unroll
+            for (int u = 0; u < XCH; u++) {
+                const int i = lane + 64 * u;
+                if (i < NSEG * NP) {
+                    const int sg = i / NP, kk = 2 * (i - sg * NP);
+                    const int dy = sg % 3 - 1, dz = sg / 3 - 1;
+                    const int64_t st = r0 - 1 + dy * f0 + (DIM == 3 ? dz * plane : 0);
+                    int64_t a = (st & ~int64_t(1)) + kk;
+                    a = a < 0 ? 0 : a;
+                    if (a + 1 < n) {
+                        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(x + a),
+                                                         (__attribute__((address_space(3))) void *)(mx + 128 * u), 16,
+                                                         0, 0);
+                    } else {
+                        const int64_t bb = a < n ? a : n - 1;
+                        reinterpret_cast<fe_dpair *>(mx)[i] = fe_dpair{x[bb], x[bb]};
+                    }
+                }
+            }
+        }
         fe_dpair xs[XCH];
 #pragma unroll
-        for (int u = 0; u < XCH; u++) {
+        for (int u = 0; u < XCH && !dma; u++) {
             const int i = lane + 64 * u;  // pair i of the staged runs
             const int sg = i / NP, kk = 2 * (i - sg * NP);
             const int dy = sg % 3 - 1, dz = sg / 3 - 1;
@@ -909,6 +938,12 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
             return ((mk0 >> (o0 + 1)) & (mk1 >> (o1 + 1)) & (mk2 >> (o2 + 1)) & 1u) != 0u;
         };
+        if (ONE && !dma) {
+            // x only 8-byte aligned: staged through registers before the value loads
+#pragma unroll
+            for (int u = 0; u < XCH; u++)
+                if (lane + 64 * u < NSEG * NP) reinterpret_cast<fe_dpair *>(mx)[lane + 64 * u] = xs[u];
+        }
         double vv[L];
 #pragma unroll
         for (int g = 0; g < L; g++) {
@@ -923,9 +958,15 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
                 vv[g] = code_ok(g) ? double(val[row + k]) : 0.0;
             }
         }
+        if (!ONE) {
 #pragma unroll
-        for (int u = 0; u < XCH; u++)
-            if (lane + 64 * u < NSEG * NP) reinterpret_cast<fe_dpair *>(mx)[lane + 64 * u] = xs[u];
+            for (int u = 0; u < XCH; u++)
+                if (lane + 64 * u < NSEG * NP) reinterpret_cast<fe_dpair *>(mx)[lane + 64 * u] = xs[u];
+        }
+        // the load-to-LDS writes complete with the vector memory counter, which
+        // the compiler does not wait on before LDS reads: wait for it here
+        // (immediate 0x0F70: vmcnt 0, expcnt and lgkmcnt not waited on)
+        if (dma) __builtin_amdgcn_s_waitcnt(0x0F70);
         wave_lds_sync();
         // the row's columns in ascending order are its free codes in ascending
         // order: the first H go to lo, the rest to hi
