@@ -194,6 +194,41 @@ def mixed_form(args, wl, mesh, A, x_fp64, F, torch, stream, ncells, lo="fp32"):
             "rel_error_vs_fp64_solution": err}
 
 
+def peak_probe(torch):
+    """Achievable rates of this GPU, measured, to set the published peaks the
+    roofline uses in context: a 1 GiB device copy and a 4 GiB read (a sum) in
+    GB/s, and library GEMMs (torch.matmul, 8192^3 in FP64 and FP32, 16384^3 in
+    BF16) in TFLOP/s.  Median of 5 timed runs after 2 warm-ups, HIP events."""
+    def timed(fn, reps=5):
+        for _ in range(2):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return sorted(ts)[len(ts) // 2]
+    out = {}
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out["copy_GBps"] = 2 * a.numel() * 8 / timed(lambda: b.copy_(a)) / 1e9
+    del a, b
+    r = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    out["read_GBps"] = r.numel() * 8 / timed(lambda: r.sum()) / 1e9
+    del r
+    for name, dt, m in (("fp64", torch.float64, 8192), ("fp32", torch.float32, 8192), ("bf16", torch.bfloat16, 16384)):
+        x = torch.rand(m, m, dtype=dt, device="cuda")
+        y = torch.rand(m, m, dtype=dt, device="cuda")
+        out[f"gemm_{name}_TFLOPs"] = 2 * m ** 3 / timed(lambda: torch.matmul(x, y)) / 1e12
+        del x, y
+    torch.cuda.empty_cache()
+    out["published"] = {"hbm_GBps": 8000, "fp64_matrix_TFLOPs": 78.6, "fp32_TFLOPs": 157.3, "bf16_matrix_TFLOPs": 2500}
+    return out
+
+
 def batch_form(args, F, torch):
     """Batching form: a sample of the 512-problem batch (3D Poisson, n uniform
     in [8, 64], order uniform in {1, 2, 3}) with FP32 element integration and
@@ -359,6 +394,8 @@ def main():
     ap.add_argument("--form", default=None, choices=["batch", "serve"], help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only measure this GPU's achievable rates (copy, read, library GEMMs) for context")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard as "
@@ -375,6 +412,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read_per_launch": a.numel() * 8, "launches": 3}))
+        return
+
+    if args.peak_probe:
+        print(json.dumps(peak_probe(torch)), flush=True)
         return
 
     from fe_inputs import lognormal_coefficients, structured_vertices
