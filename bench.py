@@ -330,10 +330,14 @@ def serve_form(args, F, torch):
             srv.solution(ticket, x)
             probes[j] = x
 
-    results, makespan = SV.run_stream(srv, stream, rtol=rtol, maxit=maxit, on_done=keep)
+    results, makespan = SV.run_stream(srv, stream, rtol=rtol, maxit=maxit, on_done=keep,
+                                      progress=max(1, len(stream) // 10))
     stats = srv.stats()
     srv.close()
     summary = SV.summarize(results, makespan)
+    failed = [{"request": stream[j][3], "n": stream[j][1], "k": stream[j][2], "state": r["state"],
+               "status": r["status"], "iters": r["iters"], "relres": r["relres"], "error": r["error"]}
+              for j, r in enumerate(results) if not (r["state"] == F.FE_REQ_DONE and r["status"] == F.FE_OK)]
     same = True
     for j, x_mix in probes.items():
         _, n, k, i = stream[j]
@@ -359,6 +363,7 @@ def serve_form(args, F, torch):
         "peak_in_flight": stats["peak_solving"], "peak_bytes": stats["peak_in_use"],
         "admission_waits": stats["admission_waits"], "chunks": stats["chunks"],
         "bitwise_equal_alone_vs_mix": bool(same), "checked_alone": len(probes),
+        "not_converged": failed[:20],
     }
 
 

@@ -5,6 +5,7 @@ Each request is a 3D Poisson assemble-and-solve on an n^3 brick (interior
 vertices jittered by +-0.2 h, lognormal per-cell coefficients, f = 1, u = 0 on
 the boundary) of order k; request i draws its mesh from its own seeds.
 """
+import sys
 import threading
 import time
 
@@ -31,12 +32,16 @@ def percentile(values, q):
     return s[min(r, len(s)) - 1]
 
 
-def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=None, timeout=1200.0):
+def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=None, timeout=1200.0,
+               progress=None):
     """Submits stream[j] = (arrival_s, n, k, index) at its arrival time
     (scaled by time_scale) from a client thread and waits for all results.
-    on_done(j, ticket, result) runs before the request is released.  Returns
-    the per-request results and the makespan."""
+    on_done(j, ticket, result) runs before the request is released; with
+    progress = m, a line on stderr after every m-th result.  Returns the
+    per-request results and the makespan."""
     inputs = [request_inputs(i, n, k) for (_, n, k, i) in stream]
+    if progress:
+        print(f"[serve] inputs of {len(stream)} requests built", file=sys.stderr, flush=True)
     tickets = [None] * len(stream)
     errors = []
     submitted = threading.Event()
@@ -70,6 +75,8 @@ def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=
         if on_done is not None:
             on_done(j, tickets[j], r)
         server.release(tickets[j])
+        if progress and (j + 1) % progress == 0:
+            print(f"[serve] {j + 1}/{len(stream)} results", file=sys.stderr, flush=True)
     th.join()
     if errors:
         raise errors[0]
