@@ -532,14 +532,15 @@ def main():
         "config": {"workload": wl["text"], "cells": ncells, "order": k, "dofs": A.n_rows, "nnz": A.nnz,
                    "operator_storage": {"sym": "symmetric (upper triangle)", "mesh": "CSR values",
                                         "csr": "CSR"}[args.spmv]},
-        "assembly": {"ms_mean": statistics.mean(asm_ms),
+        "assembly": {"ms_mean": statistics.mean(asm_ms), "ms_median": statistics.median(asm_ms),
+                     "ms_min": min(asm_ms),
                      "elements_per_s": ncells / (statistics.mean(asm_ms) * 1e-3),
                      "integrate_ms": tm["integrate_ms"] / max(tm["integrate_calls"], 1),
                      "scatter_ms": tm["scatter_ms"] / max(tm["scatter_calls"], 1),
                      "sym_fill_ms": statistics.mean(fill_ms) if sym is not None else None},
         "solve": {"pcg_iters": statistics.mean(iters), "relres": info["relres"],
                   "true_relres": info["true_relres"], "solves_per_s": args.steps / total,
-                  "p50_ms": statistics.median(lat) * 1e3, "p99_ms": p99 * 1e3,
+                  "p50_ms": statistics.median(lat) * 1e3, "p99_ms": p99 * 1e3, "min_ms": min(lat) * 1e3,
                   "kappa_est": info["lambda_max_est"] / info["lambda_min_est"] if info["lambda_min_est"] else None},
         "roofline": {"kernel": kname, "traversal": {
                          "sym": "symmetric storage (upper triangle, slot-major), pattern evaluated from the mesh",
