@@ -944,7 +944,9 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             for (int u = 0; u < XCH; u++)
                 if (lane + 64 * u < NSEG * NP) reinterpret_cast<fe_dpair *>(mx)[lane + 64 * u] = xs[u];
         }
-        double vv[L];
+        // kept in the storage's type until the product: a conversion at the load
+        // would wait for each load in turn
+        VT vv[L];
 #pragma unroll
         for (int g = 0; g < L; g++) {
             const int o0 = g % 3 - 1, o1 = (g / 3) % 3 - 1, o2 = DIM == 3 ? g / 9 - 1 : 0;
@@ -953,9 +955,17 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             if constexpr (ONE) {
                 // one step per wave (at most 8.4 M rows): byte offsets fit in 32 bits
                 const uint32_t boff = uint32_t(row + k) * uint32_t(sizeof(VT));
-                vv[g] = code_ok(g) ? double(*reinterpret_cast<const FE_GLOBAL VT *>(vbase + boff)) : 0.0;
+                if constexpr (sizeof(VT) == 4) {
+                    // FP32 storage: loaded unconditionally (a lane whose code is not
+                    // free reads its own diagonal, in range for every lane of the step;
+                    // the sums skip it), or the widening to FP64 is folded into a
+                    // conditional load and waits for each load in turn
+                    vv[g] = *reinterpret_cast<const FE_GLOBAL VT *>(vbase + (code_ok(g) ? boff : uint32_t(row) * 4u));
+                } else {
+                    vv[g] = code_ok(g) ? *reinterpret_cast<const FE_GLOBAL VT *>(vbase + boff) : VT(0);
+                }
             } else {
-                vv[g] = code_ok(g) ? double(val[row + k]) : 0.0;
+                vv[g] = code_ok(g) ? val[row + k] : VT(0);
             }
         }
         if (!ONE) {
@@ -978,8 +988,8 @@ __device__ __forceinline__ void for_rows_q1sym(const SpaceArgs &s, const VT *__r
             const int sgi = DIM == 3 ? (o1 + 1) + 3 * (o2 + 1) : o1 + 1;
             const double xg = mx[sgi * SEG2 + lead(sgi) + o0 + 1 + lane];
             if (code_ok(g)) {
-                if (c < H) lo += vv[g] * xg;
-                else hi += vv[g] * xg;
+                if (c < H) lo += double(vv[g]) * xg;
+                else hi += double(vv[g]) * xg;
                 c++;
             }
         }
