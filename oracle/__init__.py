@@ -337,6 +337,97 @@ class System:
         return sp.csr_matrix((self.values, self.colind, self.rowptr), shape=(self.nfree, self.nfree))
 
 
+def _cell_vefs(dim, k):
+    """The vefs (vertices, edges, faces, the cell itself) of a Q_k cell and the
+    local nodes each one owns (the nodes in its relative interior).
+
+    A vef is given per axis by a side: 0 or 1 (the vef lies on that side of
+    the cell) or None (the vef spans the axis).  Local vef order: by
+    dimension (vertices first), then by the set of spanned axes in binary
+    order, then by the sides in the vertex order v0 + 2 v1 + 4 v2 of the paper's
+    hexahedron (Sect. 3.14).  Within a vef, nodes keep their local
+    lexicographic order.  Returns a list of (sides, local node list)."""
+    vefs = []
+    for vdim in range(dim + 1):
+        for mask in range(1 << dim):
+            if bin(mask).count("1") != vdim:
+                continue
+            fixed_axes = [r for r in range(dim) if not (mask >> r) & 1]
+            for code in range(1 << len(fixed_axes)):
+                sides = [None] * dim
+                for t, r in enumerate(fixed_axes):
+                    sides[r] = (code >> t) & 1
+                nodes = []
+                for a in range((k + 1) ** dim):
+                    ar = [(a // (k + 1) ** r) % (k + 1) for r in range(dim)]
+                    on = True
+                    for r in range(dim):
+                        if sides[r] is None:
+                            on = on and 0 < ar[r] < k
+                        else:
+                            on = on and ar[r] == sides[r] * k
+                    if on:
+                        nodes.append(a)
+                vefs.append((tuple(sides), nodes))
+    return vefs
+
+
+def owner_cell_numbering(P: Problem):
+    """Cell-to-DOF map in the paper's owner-cell numbering (Sect. 10.3).
+
+    One sweep over the cells in the iterator's order (lexicographic): a cell
+    first numbers the DOFs in its own interior, then visits its vefs; the
+    first cell that reaches a vef owning at least one DOF becomes its owner
+    and numbers the DOFs on it from the next free identifier, and every later
+    cell fetches the identifiers of that vef from its owner.  Free and fixed
+    DOFs are numbered separately (Sect. 10.4): free ones 0, 1, ..., fixed ones
+    -1, -2, ... (a DOF is fixed if its node lies on a Dirichlet face).  Vector
+    fields number the components of a node consecutively.
+
+    On the structured brick the vefs of neighbouring cells are aligned, so the
+    fetch from the owner maps a node of the vef to the same lattice node; it is
+    done here through a table from lattice node to the identifier its owner
+    gave it.  Pure Python: small meshes only.  Returns (cell_dofs, nfree,
+    nfixed) with cell_dofs[cell, ncomp*a + c]."""
+    dim, k, nc = P.dim, P.k, P.ncomp
+    n = P.n[:dim]
+    N = [n[r] * k + 1 for r in range(dim)]
+    vefs = _cell_vefs(dim, k)
+    # the cell interior (its last vef) is numbered first, then the others
+    order = [vefs[-1]] + vefs[:-1]
+    out = np.zeros((P.ncells, P.nloc), dtype=np.int64)
+    owner_ids = {}  # lattice node -> list of ncomp identifiers from its owner
+    visited = set()  # global vefs that already have an owner
+    nfree = nfixed = 0
+    for cell in range(P.ncells):
+        ci = [(cell // int(np.prod(n[:r]))) % n[r] for r in range(dim)]
+        for sides, nodes in order:
+            if not nodes:
+                continue  # a vef with no DOF gets no owner
+            gvef = (tuple(ci[r] if sides[r] is None else ci[r] + sides[r] for r in range(dim)),
+                    tuple(s is None for s in sides))
+            first = gvef not in visited
+            visited.add(gvef)
+            for a in nodes:
+                ar = [(a // (k + 1) ** r) % (k + 1) for r in range(dim)]
+                I = tuple(ci[r] * k + ar[r] for r in range(dim))
+                if first:
+                    fixed = any((I[r] == 0 and (P.faces >> (2 * r)) & 1) or
+                                (I[r] == N[r] - 1 and (P.faces >> (2 * r + 1)) & 1) for r in range(dim))
+                    ids = []
+                    for c in range(nc):
+                        if fixed:
+                            ids.append(-1 - nfixed)
+                            nfixed += 1
+                        else:
+                            ids.append(nfree)
+                            nfree += 1
+                    owner_ids[I] = ids
+                for c in range(nc):
+                    out[cell, nc * a + c] = owner_ids[I][c]
+    return out, nfree, nfixed
+
+
 def coo_compress(rows, cols, vals, n):
     """The paper's COO build-up followed by compression (Sect. 11.1): sort the
     pushed-back (row, col, value) triplets and sum duplicates, giving CSR."""

@@ -30,6 +30,11 @@ MUTANTS = {
     "load_without_shape_function": ("f[a * ncomp + c] += wd * fc * phi[a];", "f[a * ncomp + c] += wd * fc;"),
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
     "geometry_derivative_sign": ("if (r == s) g *= vr ? 1.0 : -1.0;", "if (r == s) g *= vr ? -1.0 : 1.0;"),
+    "l2_error_without_sqrt": ("return sqrt(err2);", "return err2;"),
+    "l2_error_dropped_weight": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
+                                "err2 += fabs(qp.detJ) * (ue - uh) * (ue - uh);"),
+    "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
+                                  "err2 += w * (ue - uh) * (ue - uh);"),
 }
 
 # the pins run against each mutant (small, fast parametrizations)
@@ -44,6 +49,9 @@ PIN_CALLS = [
     lambda: PINS.test_linear_patch_test(2, 3, 3, "poisson"),
     lambda: PINS.test_linear_patch_test(3, 1, 3, "elasticity"),
     lambda: PINS.test_pcg_matches_direct_solve_and_lanczos_bounds(2, 2, "poisson"),
+    lambda: PINS.test_l2_norm_of_sine_product_closed_form(2, 2, 6, 0.2),
+    lambda: PINS.test_l2_norm_of_affine_field_is_exact(3, 1, 3, 0.2),
+    lambda: PINS.test_l2_norm_of_vector_field_sums_components(),
 ]
 
 
