@@ -369,6 +369,11 @@ fe_status fe_spmv_plan_of_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coef
 fe_status fe_spmv_plan_set_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_spmv_plan *plan);
 /* The plan a matrix of n_rows rows and nnz entries gets now, and its class. */
 fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32_t *row_class);
+/* Makes `plan` (mode and rows_per_wave of one of the CSR plans fe_spmv_autotune
+ * times; us is ignored) the plan of the row-length class of a matrix of n_rows
+ * rows and nnz entries, without timing.  Host only, no device work.
+ * FE_EINVAL for a null plan, negative sizes or any other plan. */
+fe_status fe_spmv_plan_set(int64_t n_rows, int64_t nnz, const fe_spmv_plan *plan);
 
 /* y = A x (device vectors).  Enqueues only. */
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream);

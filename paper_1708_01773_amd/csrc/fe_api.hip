@@ -707,6 +707,13 @@ fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32
     return FE_OK;
 }
 
+fe_status fe_spmv_plan_set(int64_t n_rows, int64_t nnz, const fe_spmv_plan *plan)
+{
+    if (!plan) return set_error(FE_EINVAL, "null plan");
+    if (n_rows < 0 || nnz < 0) return set_error(FE_EINVAL, "negative size");
+    return spmv_plan_set(n_rows, nnz, *plan);
+}
+
 fe_status fe_pcg_solve_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, const double *b, double *x,
                             double rtol, int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *info,
                             fe_stream stream)

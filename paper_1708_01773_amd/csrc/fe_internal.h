@@ -227,6 +227,7 @@ fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe
                         int *n_tried, fe_spmv_plan *chosen, hipStream_t s);
 void spmv_tuning_reset();
 void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls);
+fe_status spmv_plan_set(int64_t n, int64_t nnz, const fe_spmv_plan &plan);
 fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int reps, void *ws, size_t ws_bytes,
                                fe_spmv_plan *tried, int max_tried, int *n_tried, fe_spmv_plan *chosen, hipStream_t s);
 void spmv_plan_of_struct(const SpaceArgs &sa, fe_spmv_plan *plan, int32_t *cls);

@@ -1093,6 +1093,15 @@ __global__ __launch_bounds__(kQ1Block) void sym_fill_kernel(SpaceArgs s, const d
 constexpr int kXbRows = 32;   // rows per chunk: 4 waves x 8 rows
 constexpr int kXbCap = 4864;  // staged doubles: (2k+1)^2 runs of NC (nodes of a chunk + 2k), k <= 4
 
+// The staged box of a chunk: its kXbRows rows cover at most (kXbRows - 1) / NC + 2
+// nodes of the line (a chunk may start inside a node's components), whose
+// column boxes along x reach k nodes beyond each end, and (2k + 1)^2 node
+// lines across; every supported component count and order must fit.
+constexpr int xblock_staged_max(int nc, int k) { return nc * ((kXbRows - 1) / nc + 2 + 2 * k) * (2 * k + 1) * (2 * k + 1); }
+static_assert(xblock_staged_max(1, 4) <= kXbCap && xblock_staged_max(2, 4) <= kXbCap &&
+                  xblock_staged_max(3, 4) <= kXbCap,
+              "the staged x box of a mode-6 chunk exceeds its LDS buffer");
+
 template <int NC, typename Fn>
 __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double *__restrict__ gval,
                                                 const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
@@ -1810,7 +1819,9 @@ struct PinnedState {
 // SpMV autotuner: times every plan on a matrix and keeps the fastest for the
 // matrix's row-length class.
 // ---------------------------------------------------------------------------
-static const SpmvPlan kCandidates[] = {{0, 1, 64}, {0, 2, 32}, {0, 4, 16}, {0, 8, 8}, {0, 16, 4}, {0, 32, 2}, {1, 1, 64}};
+// {mode, nc, rows per wave, lanes per row}
+static const SpmvPlan kCandidates[] = {{0, 1, 1, 64}, {0, 1, 2, 32}, {0, 1, 4, 16}, {0, 1, 8, 8},
+                                       {0, 1, 16, 4}, {0, 1, 32, 2}, {1, 1, 1, 64}};
 
 size_t autotune_ws_bytes(int64_t n) { return 2 * align256(size_t(std::max<int64_t>(n, 1)) * sizeof(double)); }
 
@@ -1874,6 +1885,17 @@ void spmv_tuning_reset()
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
     g_stuned.clear();
+}
+
+fe_status spmv_plan_set(int64_t n, int64_t nnz, const fe_spmv_plan &plan)
+{
+    for (const SpmvPlan &c : kCandidates)
+        if (c.mode == plan.mode && c.rpb == plan.rows_per_wave) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[plan_class(n, nnz)] = c;
+            return FE_OK;
+        }
+    return set_error(FE_EINVAL, "not a CSR plan the autotuner times");
 }
 
 void spmv_plan_of(int64_t n, int64_t nnz, fe_spmv_plan *plan, int32_t *cls)

@@ -31,7 +31,7 @@ EXPORTS = [
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
-    "fe_sym_fp32_from_csr", "fe_refine_solve_sym",
+    "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -152,6 +152,7 @@ def lib():
                                  _c.POINTER(_c.c_int32), _c.POINTER(SpmvPlan), _P],
             "fe_spmv_tuning_reset": [],
             "fe_spmv_plan_of": [_c.c_int64, _c.c_int64, _c.POINTER(SpmvPlan), _c.POINTER(_c.c_int32)],
+            "fe_spmv_plan_set": [_c.c_int64, _c.c_int64, _c.POINTER(SpmvPlan)],
             "fe_spmv_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _P, _P],
             "fe_pcg_solve_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _P, _c.c_double,
                                   _c.c_int32, _P, _c.c_size_t, _c.POINTER(SolveInfo), _P],
@@ -427,6 +428,12 @@ def spmv_plan_of(n_rows, nnz):
     c = _c.c_int32()
     _check(lib().fe_spmv_plan_of(int(n_rows), int(nnz), _c.byref(p), _c.byref(c)), "fe_spmv_plan_of")
     return p.mode, p.rows_per_wave, c.value
+
+
+def spmv_plan_set(n_rows, nnz, mode, rows_per_wave):
+    """Make (mode, rows_per_wave) the CSR plan of the row-length class of an n_rows x nnz matrix."""
+    p = SpmvPlan(int(mode), int(rows_per_wave), 0.0)
+    _check(lib().fe_spmv_plan_set(int(n_rows), int(nnz), _c.byref(p)), "fe_spmv_plan_set")
 
 
 def _info_dict(info):

@@ -114,3 +114,20 @@ def test_symmetric_storage_entry_points_validate_on_host():
                               None) == F.FE_EINVAL
     assert L.fe_refine_solve_sym(None, 1, ctypes.byref(c), None, None, None, 0, None, None, 1e-10, 1e-5, 5, 100,
                                  None, 0, None, None) == F.FE_EINVAL
+
+
+def test_csr_plans_can_be_pinned_per_row_class_on_host():
+    # the CSR plans the autotuner times: stream runs of 1..32 rows per wave,
+    # and one wave per row; each can be made the plan of a row-length class
+    plans = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (0, 32), (1, 1)]
+    try:
+        for mode, rpw in plans:
+            F.spmv_plan_set(1000, 250000, mode, rpw)
+            assert F.spmv_plan_of(1000, 250000)[:2] == (mode, rpw)
+            assert F.spmv_plan_of(1000, 251000)[:2] == (mode, rpw)  # same half-octave class
+        for mode, rpw in [(0, 3), (0, 64), (1, 2), (2, 8)]:
+            with pytest.raises(F.FeError, match="not a CSR plan"):
+                F.spmv_plan_set(1000, 250000, mode, rpw)
+    finally:
+        F.spmv_tuning_reset()
+    assert F.spmv_plan_of(1000, 250000)[:2] == (1, 1)  # the heuristic again: long rows, wave per row

@@ -1,0 +1,190 @@
+"""Parity of the SpMV traversals at the shapes of 3D elasticity on Q2-Q4
+hexahedra: lines of more than 32 rows for the block-staged traversal (chunks
+that start inside a line and inside a node's components), CSR rows of the
+lengths those systems have (hundreds to 2187 entries) for every CSR plan, and
+the full 24^3 Q4 elasticity system in the configuration the benchmark runs."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle as O
+from paper_1708_01773_amd import fe as F
+from tests.gpu_util import MATRIX_RTOL, Pair, element_matrices, rel, say
+
+pytestmark = pytest.mark.gpu
+
+CSR_PLANS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (0, 32), (1, 1)]
+
+
+def _check_rows(S, x, y, tol=1e-12):
+    yo = O.spmv(S.rowptr, S.colind, S.values, x)
+    scale = O.spmv(S.rowptr, S.colind, np.abs(S.values), np.abs(x))
+    bad = np.abs(y - yo) > tol * scale + 1e-300
+    assert not bad.any(), (int(bad.sum()), np.flatnonzero(bad)[:8])
+
+
+# rows per line of nodes: 75 (Q2, no Dirichlet face), 69 (Q4 clamped: chunk 1
+# starts inside node 10's components), 36 and 37 (Q3 and scalar Q4, one or
+# two x faces fixed), 93 (Q2 elasticity, x faces free, y/z clamped)
+LONG_LINES = [(3, [12, 3, 3], 2, "elasticity", 0), (3, [6, 2, 2], 4, "elasticity", None),
+              (3, [4, 3, 2], 3, "elasticity", 0b000001), (3, [9, 2, 2], 4, "poisson", 0b010110),
+              (3, [15, 2, 2], 2, "elasticity", 0b111100)]
+
+
+@pytest.mark.parametrize("dim,n,k,prob,faces", LONG_LINES)
+def test_block_staged_traversal_on_long_lines(dim, n, k, prob, faces):
+    pair = Pair(dim, n, k, prob, faces=faces, seed=61, source=(0.3, -0.2, -1.0))
+    A = pair.gpu_assembly()
+    P = pair.P
+    f0 = P.n[0] * k + 1 - bin(P.faces & 3).count("1")
+    say(f"[c3 lines] n {n} k {k} {prob} faces {faces} rows {A.n_rows} rows/line {P.ncomp * f0}")
+    assert P.ncomp * f0 > 32
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(62)).standard_normal(A.n_rows)).cuda()
+    ys = []
+    F.spmv_tuning_reset()
+    try:
+        for mode in (2, 6):
+            F.spmv_plan_set_mesh(pair.mesh, k, pair.coeff, mode, 8)
+            y = torch.empty_like(x)
+            F.spmv_mesh(pair.mesh, k, pair.coeff, A.csr, x, y)
+            torch.cuda.synchronize()
+            ys.append(y)
+        if faces != 0:
+            ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+            u = torch.zeros_like(x)
+            info = A.solve(u, 1e-12, 50000, ws)
+            assert info["status"] == F.FE_OK
+    finally:
+        F.spmv_tuning_reset()
+    assert torch.equal(ys[0], ys[1])
+    S = pair.system
+    _check_rows(S, x.cpu().numpy(), ys[1].cpu().numpy())
+    if faces != 0:
+        xd = spla.spsolve(S.scipy().tocsc(), S.rhs)
+        assert rel(u.cpu().numpy(), xd) <= 1e-8
+
+
+# longest rows (a vertex node whose column box is complete: the face x = 0
+# clamped, the others free): 375 (Q2 elasticity), 1029 (Q3), 2187 (Q4), 729
+# (scalar Q4); mean row lengths 116 to 474
+LONG_ROWS = [(3, [3, 2, 2], 2, "elasticity", 1), (3, [3, 2, 2], 3, "elasticity", 1),
+             (3, [3, 2, 2], 4, "elasticity", 1), (3, [3, 3, 2], 4, "poisson", 1)]
+
+
+@pytest.mark.parametrize("dim,n,k,prob,faces", LONG_ROWS)
+def test_every_csr_plan_at_long_rows(dim, n, k, prob, faces):
+    pair = Pair(dim, n, k, prob, faces=faces, seed=63, source=(0.3, -0.2, -1.0))
+    A = pair.gpu_assembly()
+    S = pair.system
+    lens = np.diff(S.rowptr)
+    say(f"[c3 csr] n {n} k {k} {prob} rows {A.n_rows} row length {lens.min()}..{lens.max()} "
+        f"mean {lens.mean():.0f}")
+    assert lens.max() == pair.P.ncomp * (2 * k + 1) ** 3
+    x = np.random.Generator(np.random.PCG64(64)).standard_normal(A.n_rows)
+    xd = torch.from_numpy(x).cuda()
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    xs = spla.spsolve(S.scipy().tocsc(), S.rhs)
+    F.spmv_tuning_reset()
+    try:
+        for mode, rpw in CSR_PLANS:
+            F.spmv_plan_set(A.n_rows, A.nnz, mode, rpw)
+            assert F.spmv_plan_of(A.n_rows, A.nnz)[:2] == (mode, rpw)
+            y = torch.empty_like(xd)
+            F.spmv(A.csr, xd, y)
+            u = torch.zeros_like(xd)
+            info = F.pcg_solve(A.csr, A.rhs, u, 1e-12, 50000, ws)
+            torch.cuda.synchronize()
+            _check_rows(S, x, y.cpu().numpy())
+            assert info["status"] == F.FE_OK, (mode, rpw, info)
+            assert rel(u.cpu().numpy(), xs) <= 1e-8, (mode, rpw)
+        with pytest.raises(F.FeError):
+            F.spmv_plan_set(A.n_rows, A.nnz, 0, 3)
+    finally:
+        F.spmv_tuning_reset()
+
+
+# --------------------------------------------------------------------------
+# Full size: 3D elasticity, 24^3 Q4, jittered, f = (0, 0, -1), clamped
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c3q4():
+    say("[c3 fullsize] 3D elasticity 24^3 Q4 jittered, f = (0,0,-1), clamped")
+    pair = Pair(3, [24, 24, 24], 4, "elasticity", lognormal=False, source=(0.0, 0.0, -1.0))
+    A = pair.gpu_assembly()
+    code, nf, nx = O.number_nodes(3, pair.n, 4, pair.P.faces)
+    cdofs = O.cell_dofs(pair.P, code)
+    return pair, A, cdofs
+
+
+def test_c3q4_sizes_and_default_plan(c3q4):
+    pair, A, _ = c3q4
+    assert A.n_rows == 3 * 95 ** 3 == 2572125
+    assert A.nnz == 9 * 559 ** 3 == 1572091911
+    assert F.spmv_plan_of_mesh(pair.mesh, 4, pair.coeff)[0] == 6
+
+
+def test_c3q4_sampled_element_matrices(c3q4):
+    pair, A, _ = c3q4
+    cells = np.random.Generator(np.random.PCG64(5)).integers(0, pair.P.ncells, 12)
+    Es, _ = element_matrices(pair, A, cells)
+    worst = max(rel(E, pair.oracle_element(int(c))) for c, E in zip(cells, Es))
+    say(f"   worst sampled element rel err {worst:.2e}")
+    assert worst <= MATRIX_RTOL
+
+
+def _sample_rows(A):
+    # random rows plus the three components of an interior vertex node (the
+    # longest rows, 2187 entries) and of the last free node
+    rows = list(np.random.Generator(np.random.PCG64(6)).integers(0, A.n_rows, 8))
+    t = 4 * 12 - 1  # lattice index 48 is a vertex node; free index = 47
+    node = t + 95 * (t + 95 * t)
+    rows += [3 * node, 3 * node + 1, 3 * node + 2, A.n_rows - 1]
+    return [int(r) for r in rows]
+
+
+def test_c3q4_sampled_rows_and_products(c3q4):
+    """Sampled CSR rows against the oracle's rows; y = A x through the
+    block-staged traversal (9 chunks per line of 285 rows) and through the CSR
+    SpMV against the oracle's row products."""
+    pair, A, cdofs = c3q4
+    rowptr = A.rowptr.cpu().numpy()
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.rand(A.n_rows, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    ym, yc = torch.empty_like(x), torch.empty_like(x)
+    F.spmv_mesh(pair.mesh, 4, pair.coeff, A.csr, x, ym)
+    F.spmv(A.csr, x, yc)
+    torch.cuda.synchronize()
+    xh, ymh, ych = x.cpu().numpy(), ym.cpu().numpy(), yc.cpu().numpy()
+    for r in _sample_rows(A):
+        cols, vals, rhs = O.assemble_row(pair.P, pair.v, pair.coef, cdofs, r)
+        lo, hi = rowptr[r], rowptr[r + 1]
+        np.testing.assert_array_equal(A.colind[lo:hi].cpu().numpy(), cols)
+        assert rel(A.values[lo:hi].cpu().numpy(), vals) <= MATRIX_RTOL
+        assert abs(A.rhs[r].item() - rhs) <= MATRIX_RTOL * max(abs(rhs), 1e-300)
+        want = float(np.dot(vals, xh[cols]))
+        scale = float(np.dot(np.abs(vals), np.abs(xh[cols])))
+        assert abs(ymh[r] - want) <= 1e-12 * scale and abs(ych[r] - want) <= 1e-12 * scale, r
+    # the two traversals agree on every row
+    Cabs = F.csr_struct(A.n_rows, A.nnz, A.rowptr, A.colind, A.values.abs(), A.rhs, A.dinv)
+    scale = torch.empty_like(x)
+    F.spmv(Cabs, x.abs(), scale)
+    torch.cuda.synchronize()
+    assert bool(torch.all((ym - yc).abs() <= 1e-12 * scale))
+
+
+def test_c3q4_solve_residual_by_csr_spmv(c3q4):
+    """The benchmark's solve (block-staged traversal, rtol 1e-10); its true
+    residual recomputed with the CSR SpMV, a different traversal."""
+    pair, A, _ = c3q4
+    n = A.n_rows
+    ws = torch.empty(F.pcg_query(n), dtype=torch.uint8, device="cuda")
+    u = torch.zeros(n, dtype=torch.float64, device="cuda")
+    info = A.solve(u, 1e-10, 20000, ws)
+    res = torch.empty_like(u)
+    F.spmv(A.csr, u, res)
+    torch.cuda.synchronize()
+    tr = float(torch.linalg.vector_norm(A.rhs[:n] - res) / torch.linalg.vector_norm(A.rhs[:n]))
+    say(f"   pcg iters {info['iters']} relres {info['relres']:.2e} true (CSR SpMV) {tr:.2e}")
+    assert info["status"] == F.FE_OK and info["relres"] <= 1e-10
+    assert tr <= 2e-10 and abs(tr - info["true_relres"]) <= 1e-12
