@@ -233,6 +233,26 @@ fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes);
 fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
                        size_t ws_bytes, fe_solve_info *info, fe_stream stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fe_pcg_solve without a
+ * workspace argument.  The workspace lives in a static device array of
+ * FE_PCG_NOALLOC_BYTES (64 MiB) inside the library, one copy per device,
+ * held from the first call on that device until the process ends; the call
+ * itself allocates no device, pinned-host or graph memory and creates no
+ * stream or event (iterations are launched directly on `stream`, the stop
+ * test is read into pageable host memory).  Arguments, results and
+ * alignment rules as for fe_pcg_solve; the caller still owns A, b and x.
+ * Systems of more than FE_PCG_NOALLOC_MAX_ROWS rows are refused with
+ * FE_EINVAL before any device work.  Every call on a device uses that
+ * device's one array: calls that overlap on one device (other host threads,
+ * other streams) race and must be serialized by the caller.  Nothing in the
+ * array needs to start cleared, so the previous call's contents are harmless.
+ * Synchronizes before returning. */
+#define FE_PCG_NOALLOC_BYTES (64u << 20)
+#define FE_PCG_NOALLOC_MAX_ROWS 2700000
+fe_status fe_pcg_solve_noalloc(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit,
+                               fe_solve_info *info, fe_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched solve: many independent systems in one sequence of launches       */
 /* ------------------------------------------------------------------------ */

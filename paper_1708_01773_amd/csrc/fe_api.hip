@@ -617,6 +617,19 @@ fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol,
     return pcg_solve(A, b, x, rtol, maxit, ws, ws_bytes, info, as_stream(stream));
 }
 
+fe_status fe_pcg_solve_noalloc(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit,
+                               fe_solve_info *info, fe_stream stream)
+{
+    static_assert(FE_PCG_NOALLOC_BYTES == (64u << 20), "header and library disagree on the scratch size");
+    if (!A || !b || !x || !info) return set_error(FE_EINVAL, "null argument");
+    if (!A->rowptr || !A->colind || !A->values || !A->dinv) return set_error(FE_EINVAL, "incomplete csr");
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    if (A->n_rows < 0 || A->nnz < 0) return set_error(FE_EINVAL, "negative size");
+    if (A->n_rows > FE_PCG_NOALLOC_MAX_ROWS)
+        return set_error(FE_EINVAL, "system too large for the allocation-free solve (at most 2,700,000 rows)");
+    return pcg_solve_noalloc(A, b, x, rtol, maxit, info, as_stream(stream));
+}
+
 fe_status fe_pcg_batch_query(int32_t nprob, const int64_t *n_rows, size_t *ws_bytes)
 {
     if (nprob < 0 || (nprob > 0 && !n_rows) || !ws_bytes) return set_error(FE_EINVAL, "bad argument");

@@ -206,6 +206,9 @@ fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, c
 size_t pcg_solve_ws_bytes(int64_t n);
 fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
                     fe_solve_info *info, hipStream_t s);
+size_t pcg_noalloc_bytes();
+fe_status pcg_solve_noalloc(const fe_csr *A, const double *b, double *x, double rtol, int maxit, fe_solve_info *info,
+                            hipStream_t s);
 size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows);
 // sas: per system, the space whose closed-form pattern the SpMV evaluates
 // instead of reading column indices (null array or entry: generic CSR).

@@ -2243,7 +2243,11 @@ static fe_status capture_stream(hipStream_t &out)
     return FE_OK;
 }
 
-static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_graph, hipStream_t s)
+// no_alloc: direct launches only (no graph, no timing events) and the stop
+// counter read into pageable host memory, so the solve creates no device,
+// pinned or graph resource of its own.
+static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_graph, hipStream_t s,
+                            bool no_alloc = false)
 {
     for (PcgJob &jb : jobs) {
         std::memset(jb.info, 0, sizeof(fe_solve_info));
@@ -2260,9 +2264,15 @@ static fe_status pcg_engine(std::vector<PcgJob> &jobs, void *table, bool use_gra
     for (const PcgJob &jb : E.jobs) maxit = std::max(maxit, jb.maxit);
 
     static thread_local PinnedState pin;
-    if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
-    int32_t *h_active = reinterpret_cast<int32_t *>(pin.h);
-    const bool timed = timing_on() && !use_graph && np == 1;
+    int32_t pageable_active = 0;
+    int32_t *h_active = &pageable_active;
+    if (no_alloc) {
+        use_graph = false;
+    } else {
+        if (!pin.h) FE_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), sizeof(PcgState), hipHostMallocDefault));
+        h_active = reinterpret_cast<int32_t *>(pin.h);
+    }
+    const bool timed = timing_on() && !use_graph && !no_alloc && np == 1;
     // SpMV launches timed: every kTimeEvery-th iteration (an event pair costs a
     // few microseconds of device time, which around every launch lengthened
     // the solve by about 6%); marks[i] belongs to iteration mark_iter[i]
@@ -2367,6 +2377,55 @@ fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, in
 {
     return pcg_run<double>(A->n_rows, A->nnz, A->rowptr, A->colind, A->values, A->dinv, b, x, rtol, maxit, ws,
                            ws_bytes, info, s);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-PCG without allocation: the workspace of fe_pcg_solve lives in a
+// file-scope device array, one copy per device, instead of the caller's
+// buffer.  Host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in).
+// Every call on a device shares its copy: overlapping calls on one device
+// race.  Nothing in the workspace has to start at zero (the init kernels write
+// every state field before it is read), so the previous call's contents are
+// harmless.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;  // per device: the array's device address
+
+static fe_status scratch_address(void *&out)
+{
+    int dev = 0;
+    FE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (int(g_scratch_ptr.size()) <= dev) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(FE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    out = g_scratch_ptr[dev];
+    return FE_OK;
+}
+
+size_t pcg_noalloc_bytes() { return kScratchBytes; }
+
+fe_status pcg_solve_noalloc(const fe_csr *A, const double *b, double *x, double rtol, int maxit, fe_solve_info *info,
+                            hipStream_t s)
+{
+    const int64_t n = A->n_rows;
+    if (pcg_ws_bytes(n) + engine_table_bytes(1) > kScratchBytes)
+        return set_error(FE_EINVAL, "system too large for the allocation-free solve (at most 2,700,000 rows)");
+    void *ws = nullptr;
+    const fe_status st = scratch_address(ws);
+    if (st != FE_OK) return st;
+    std::vector<PcgJob> jobs(1);
+    jobs[0] = PcgJob{n, A->nnz, A->rowptr, A->colind, A->values, false, A->dinv, b, x, ws, info, rtol, maxit,
+                     nullptr, false};
+    return pcg_engine(jobs, static_cast<char *>(ws) + pcg_ws_bytes(n), false, s, true);
 }
 
 fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,

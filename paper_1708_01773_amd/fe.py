@@ -31,7 +31,7 @@ EXPORTS = [
     "fe_server_release", "fe_server_get_stats", "fe_server_clock", "fe_server_destroy",
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
-    "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set",
+    "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set", "fe_pcg_solve_noalloc",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -136,6 +136,7 @@ def lib():
             "fe_pcg_query": [_c.c_int64, _c.POINTER(_c.c_size_t)],
             "fe_pcg_solve": [_c.POINTER(Csr), _P, _P, _c.c_double, _c.c_int32, _P, _c.c_size_t,
                              _c.POINTER(SolveInfo), _P],
+            "fe_pcg_solve_noalloc": [_c.POINTER(Csr), _P, _P, _c.c_double, _c.c_int32, _c.POINTER(SolveInfo), _P],
             "fe_spmv": [_c.POINTER(Csr), _P, _P, _P],
             "fe_set_timing": [_c.c_int32],
             "fe_csr_to_fp32": [_c.POINTER(Csr), _P, _P],
@@ -345,6 +346,20 @@ def pcg_solve(csr, b, x, rtol, maxit, ws, stream=None, check=True):
     if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
         _check(st, "fe_pcg_solve")
     return out
+
+
+def pcg_solve_noalloc(csr, b, x, rtol, maxit, stream=None, check=True):
+    """fe_pcg_solve with the library's static device workspace (no allocation)."""
+    info = SolveInfo()
+    st = lib().fe_pcg_solve_noalloc(_c.byref(csr), _ptr(b), _ptr(x), float(rtol), int(maxit), _c.byref(info),
+                                    _stream(stream))
+    out = _info_dict(info)
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_pcg_solve_noalloc")
+    return out
+
+
+PCG_NOALLOC_MAX_ROWS = 2700000
 
 
 def pcg_batch_query(n_rows):
