@@ -79,38 +79,183 @@ def traffic_for(kernel, workload):
     return e["bytes_per_launch"]
 
 
-def cpu_baseline(wl, gpu_iters, ncells_full, nnz_full):
-    """The oracle timed on this host on a bounded sample of the same workload:
-    a 64^3 mesh with the same recipe.  The step time of the full workload is
-    scaled from it: per-cell assembly time x cells, plus per-iteration PCG time
-    scaled by nnz x the iteration count the GPU needed."""
+def cpu_model():
+    """The host CPU's model name (lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
+
+
+def cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=64, cg_its=60):
+    """The oracle timed on this host on a bounded sample of the same workload
+    (an n^d mesh of the same recipe), single-threaded (the parity build) and on
+    all cores (its OpenMP build: element matrices per cell in parallel, then
+    row-parallel accumulation in the serial order; row-parallel SpMV, dot
+    products over fixed chunks).  Symbolic assembly (CSR pattern), numeric
+    assembly and CG iterations are timed separately.  The step of the full
+    workload is scaled from the sample as cells x numeric time per cell +
+    the GPU's iteration count x CG time per iteration x nnz ratio; the symbolic
+    phase is set-up on both sides and excluded from the step, as on the GPU."""
     import numpy as np
     import oracle as O
     from fe_inputs import lognormal_coefficients, structured_vertices
 
-    n = 64
     dim, k = wl["dim"], wl["k"]
     P = O.Problem(dim, [n] * dim, k, source_kind=wl.get("source_kind", 1), source=(1.0,))
     v = structured_vertices(dim, n, jitter=wl.get("jitter", 0.2))
     coef = lognormal_coefficients(P.ncells) if wl.get("lognormal", True) else None
-    t0 = time.perf_counter()
-    S = O.System(P, v, coef)  # numbering + symbolic + numeric assembly
-    t_asm = time.perf_counter() - t0
-    its = 100
-    t0 = time.perf_counter()
-    res = O.pcg(S.rowptr, S.colind, S.values, S.rhs, 0.0, its)
-    t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
-    step = t_asm / P.ncells * ncells_full + t_it * (nnz_full / S.nnz) * gpu_iters
+    code, nf, _ = O.number_nodes(dim, P.n, k, P.faces)
+    cd = O.cell_dofs(P, code)
+    nfree = nf * P.ncomp
+    legs = {}
+    for name, pat, asm, cg in (("single_thread", O.csr_pattern, O.assemble,
+                                lambda rp, ci, va, b: O.pcg(rp, ci, va, b, 0.0, cg_its)),
+                               ("all_cores", O.omp_csr_pattern, O.omp_assemble,
+                                lambda rp, ci, va, b: O.omp_pcg(rp, ci, va, b, 0.0, cg_its))):
+        t0 = time.perf_counter()
+        rp, ci = pat(cd, nfree)
+        t_sym = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        vals, rhs, _ = asm(P, v, coef, cd, nfree, rp, ci)
+        t_num = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        res = cg(rp, ci, vals, rhs)
+        t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
+        nnz = int(rp[-1])
+        step = t_num / P.ncells * ncells_full + t_it * (nnz_full / nnz) * gpu_iters
+        legs[name] = {"value": ncells_full / step, "unit": "elements/s",
+                      "cores": 1 if name == "single_thread" else O.omp_threads(),
+                      "symbolic_s": t_sym, "numeric_s": t_num, "cg_ms_per_iteration": t_it * 1e3,
+                      "cg_iterations_timed": res["iters"], "step_s_scaled": step}
+    omp = legs["all_cores"]
     return {
-        "value": ncells_full / step, "unit": "elements/s", "cores": 1, "kind": "oracle",
-        "sample": f"oracle (single-threaded C, FP64) on the same recipe at {n}^{dim} cells: assembly "
-                  f"{t_asm:.2f} s for {P.ncells} cells, PCG {t_it * 1e3:.2f} ms/iteration at nnz={S.nnz}; "
-                  f"scaled to the full workload as cells x per-cell assembly + {gpu_iters} iterations x "
-                  f"per-iteration time x nnz ratio ({nnz_full}/{S.nnz})",
+        "value": omp["value"], "unit": "elements/s", "cores": omp["cores"], "kind": "oracle",
+        "sample": f"oracle (C, FP64) on the same recipe at {n}^{dim} cells ({P.ncells} cells, {nfree} unknowns, "
+                  f"nnz {int(rp[-1])}): symbolic, numeric and {cg_its} CG iterations timed; the full step scaled as "
+                  f"cells x numeric time per cell + {gpu_iters:.0f} iterations x per-iteration time x nnz ratio "
+                  f"({nnz_full}/{int(rp[-1])}); value from the all-cores (OpenMP) build",
+        "cpu_model": cpu_model(), "affinity_cores": len(os.sched_getaffinity(0)),
+        "single_thread": legs["single_thread"], "all_cores": omp,
     }
 
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+E_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4, "bf16": 4}  # element-matrix storage (FP32 for the reduced GEMMs)
+
+
+def ne_ff(dim, n, k, ncomp):
+    """Free-free element entries of a brick with every face clamped: the sum
+    over cells of (free local DOFs)^2, which factors per axis into the sum over
+    the cells along the axis of (free local nodes along it)^2."""
+    tot = 1
+    for _ in range(dim):
+        tot *= sum(((k + 1) - (i == 0) - (i == n - 1)) ** 2 for i in range(n))
+    return tot * ncomp * ncomp
+
+
+def timed_launches(fn, stream, torch, reps):
+    """Average duration of fn() from HIP events recorded on `stream` around
+    `reps` back-to-back launches (after 3 warm-up launches)."""
+    for _ in range(3):
+        fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def csr_roofline(A, F, torch, stream, reps=30):
+    """The CSR SpMV (row pointers, column indices and values read; the K7 of the
+    method's accounting: 12 nnz + 8 (n + 1) + 16 n bytes) of the assembled
+    system, timed alone on the step's stream."""
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.rand(A.n_rows, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    t = timed_launches(lambda: F.spmv(A.csr, x, y, stream), stream, torch, reps)
+    sb = spmv_bytes(A.n_rows, A.nnz, "csr")
+    mode, rpw, _ = F.spmv_plan_of(A.n_rows, A.nnz)
+    return {"kernel": "spmv_kernel/csr", "plan": {"mode": mode, "rows_per_wave": rpw}, "bound": "hbm",
+            "achieved": sb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sb / t / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": sb, "avg_launch_us": t * 1e6, "timed_launches": reps,
+            "traffic": traffic_for("spmv_kernel/csr", "c2"),
+            "timing": f"HIP events around {reps} back-to-back launches on the step's stream"}
+
+
+def c3_assembly(F, torch, reps=5, precisions=("fp64", "bf16", "fp16")):
+    """3D elasticity on Q2 48^3, Q3 32^3, Q4 24^3 (jittered, f = (0,0,-1),
+    clamped): assembly (K3 + K5) per precision with event-timed kernels, the
+    K3 fraction of the matrix-core peak on 18 nn^2 nq flops per cell and of HBM
+    on its element-matrix bytes, the K5 fraction of HBM on NE_ff (8 + 4) + 8 nnz
+    + 8 n bytes (element entries and their positions read, values and rhs
+    written); then the SpMV of the FP64 system through the block-staged
+    traversal and through the CSR."""
+    from fe_inputs import structured_vertices
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for key in ("c3q2", "c3q3", "c3q4"):
+        wl = WORKLOADS[key]
+        dim, n, k = wl["dim"], wl["n"], wl["k"]
+        ncells, nn = n ** dim, (k + 1) ** dim
+        v = structured_vertices(dim, n, jitter=0.2)
+        mesh = F.create_mesh(dim, [n] * dim, v, None)
+        res = {"workload": wl["text"], "cells": ncells}
+        for prec in precisions:
+            coeff = F.make_coeff("elasticity", prec, source_kind=1, source=(0.0, 0.0, -1.0), dim=dim)
+            A = F.Assembly(mesh, k, coeff)
+            A.pattern()
+            A.assemble()
+            torch.cuda.synchronize()
+            F.set_timing(True)
+            F.get_timing(reset=True)
+            for _ in range(reps):
+                A.assemble(stream)
+            torch.cuda.synchronize()
+            tm = F.get_timing(reset=True)
+            F.set_timing(False)
+            k3 = tm["integrate_ms"] / max(tm["integrate_calls"], 1) * 1e-3
+            k5 = tm["scatter_ms"] / max(tm["scatter_calls"], 1) * 1e-3
+            nloc = 3 * nn
+            fl = k3_flops(wl, ncells)
+            e_bytes = ncells * (8 + nloc * nloc * E_BYTES[prec]) + (n + 1) ** dim * dim * 8
+            k5_bytes = ne_ff(dim, n, k, 3) * (E_BYTES[prec] + 4) + 8 * A.nnz + 8 * A.n_rows
+            r = {"elements_per_s": ncells / (k3 + k5), "k3_ms": k3 * 1e3, "k5_ms": k5 * 1e3,
+                 "k3_algorithmic_tflops": fl / k3 / 1e12, "k3_mfma_frac": fl / k3 / 1e12 / PEAK_TFLOPS[prec],
+                 "k3_hbm_frac": e_bytes / k3 / 1e9 / HBM_PEAK_GBS, "k5_hbm_frac": k5_bytes / k5 / 1e9 / HBM_PEAK_GBS,
+                 "k3_bytes": e_bytes, "k5_bytes": k5_bytes}
+            if prec == "fp64":
+                res["dofs"], res["nnz"] = A.n_rows, A.nnz
+                g = torch.Generator(device="cuda").manual_seed(6)
+                x = torch.rand(A.n_rows, dtype=torch.float64, device="cuda", generator=g)
+                y = torch.empty_like(x)
+                tb = timed_launches(lambda: F.spmv_mesh(mesh, k, coeff, A.csr, x, y, stream), stream, torch, 10)
+                tc = timed_launches(lambda: F.spmv(A.csr, x, y, stream), stream, torch, 10)
+                k7 = spmv_bytes(A.n_rows, A.nnz, "csr")
+                own = spmv_bytes(A.n_rows, A.nnz, "mesh")
+                res["spmv"] = {
+                    "block_staged_us": tb * 1e6, "block_staged_frac_own_bytes": own / tb / 1e9 / HBM_PEAK_GBS,
+                    "csr_us": tc * 1e6, "csr_frac": k7 / tc / 1e9 / HBM_PEAK_GBS, "csr_bytes": k7,
+                    "own_bytes": own, "csr_plan": list(F.spmv_plan_of(A.n_rows, A.nnz)[:2])}
+                del x, y
+            res[prec] = r
+            print(f"[bench] {key} {prec}: K3 {k3 * 1e3:.2f} ms ({r['k3_mfma_frac']:.2f} of MFMA, "
+                  f"{r['k3_hbm_frac']:.2f} of HBM), K5 {k5 * 1e3:.2f} ms ({r['k5_hbm_frac']:.2f} of HBM)",
+                  file=sys.stderr, flush=True)
+            del A
+            torch.cuda.empty_cache()
+        out[key] = res
+        del mesh
+    return out
 
 
 def k3_flops(wl, ncells):
@@ -381,6 +526,7 @@ def main():
     ap.add_argument("--phase", default="step", choices=["step", "assemble"],
                     help="step = assemble + PCG (default); assemble = assembly only, K3 against the matrix-core peak")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3D elasticity Q2-Q4 assembly figures")
     ap.add_argument("--spmv", default="sym", choices=["sym", "mesh", "csr"],
                     help="sym: Q1 scalar systems in symmetric storage, filled from the assembled CSR inside the "
                          "step (fe_sym_from_csr + fe_pcg_solve_sym; other spaces fall back to mesh); mesh: pattern "
@@ -551,14 +697,22 @@ def main():
                      "timed_launches": tm["spmv_calls"],
                      "timing": "HIP events around the SpMV launch of every 16th CG iteration of the timed steps"},
     }
-    if not args.no_forms and wl["precision"] == "fp64":
+    if args.workload == "c2" and wl["precision"] == "fp64":
+        out["roofline_csr"] = csr_roofline(A, F, torch, stream)
+        print(f"[bench] CSR SpMV {out['roofline_csr']['avg_launch_us']:.1f} us "
+              f"({out['roofline_csr']['frac']:.3f} of HBM)", file=sys.stderr, flush=True)
+    forms = not args.no_forms and wl["precision"] == "fp64"
+    if forms:
         print("[bench] mixed-precision form", file=sys.stderr, flush=True)
         out["forms"] = {"mixed_refine": mixed_form(args, wl, mesh, A, x, F, torch, stream, ncells)}
-        if args.batch_sample > 0 and args.workload == "c2":
-            del A, ws, x, sym
-            torch.cuda.empty_cache()
+    del A, ws, x, sym
+    torch.cuda.empty_cache()
+    if args.workload == "c2" and not args.no_c3:
+        out["c3_assembly"] = c3_assembly(F, torch)
+    if forms and args.workload == "c2":
+        if args.batch_sample > 0:
             out["forms"]["batch"] = batch_form(args, F, torch)
-        if args.serve_requests > 0 and args.workload == "c2":
+        if args.serve_requests > 0:
             out["forms"]["serve"] = serve_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)

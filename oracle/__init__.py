@@ -88,6 +88,67 @@ def lib():
     return _lib
 
 
+_omp = None
+
+
+def omp_lib():
+    """The all-cores (OpenMP) build of the oracle: the CPU baseline only."""
+    global _omp
+    if _omp is None:
+        if not os.path.exists(_build.LIB_OMP):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB_OMP)
+        L.orc_omp_threads.argtypes = []
+        L.orc_omp_threads.restype = _i
+        L.orc_omp_csr_pattern.argtypes = [_i64, _i, _P, _i64, _P, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+        L.orc_omp_csr_pattern.restype = _i64
+        L.orc_omp_assemble.argtypes = [ctypes.POINTER(OrcProblem), _P, _P, _P, _i64, _P, _P, _P, _P]
+        L.orc_omp_assemble.restype = _i
+        L.orc_omp_pcg.argtypes = [_i64, _P, _P, _P, _P, _P, _d, _i, _P, _P]
+        L.orc_omp_pcg.restype = _i
+        L.orc_free.argtypes = [_P]
+        L.orc_free.restype = None
+        _omp = L
+    return _omp
+
+
+def omp_threads():
+    return omp_lib().orc_omp_threads()
+
+
+def omp_csr_pattern(cdofs, nfree):
+    cdofs = _c(cdofs, np.int64)
+    rowptr = np.zeros(nfree + 1, dtype=np.int64)
+    cptr = ctypes.POINTER(ctypes.c_int32)()
+    L = omp_lib()
+    nnz = L.orc_omp_csr_pattern(cdofs.shape[0], cdofs.shape[1], _ptr(cdofs), nfree, _ptr(rowptr), ctypes.byref(cptr))
+    colind = np.ctypeslib.as_array(cptr, shape=(max(nnz, 1),))[:nnz].copy()
+    L.orc_free(ctypes.cast(cptr, _P))
+    return rowptr, colind
+
+
+def omp_assemble(P, vxyz, coef, cdofs, nfree, rowptr, colind):
+    s = P.c_struct()
+    values = np.zeros(int(rowptr[-1]))
+    rhs = np.zeros(nfree)
+    coef = None if coef is None else _c(coef, np.float64)
+    rc = omp_lib().orc_omp_assemble(ctypes.byref(s), _ptr(_c(vxyz, np.float64)), _ptr(coef),
+                                    _ptr(_c(cdofs, np.int64)), nfree, _ptr(_c(rowptr, np.int64)),
+                                    _ptr(_c(colind, np.int32)), _ptr(values), _ptr(rhs))
+    return values, rhs, rc == 0
+
+
+def omp_pcg(rowptr, colind, values, b, rtol, maxit):
+    n = len(rowptr) - 1
+    x = np.zeros(n)
+    it = _i()
+    rr = _d()
+    st = omp_lib().orc_omp_pcg(n, _ptr(_c(rowptr, np.int64)), _ptr(_c(colind, np.int32)),
+                               _ptr(_c(values, np.float64)), _ptr(_c(b, np.float64)), _ptr(x), float(rtol),
+                               int(maxit), ctypes.byref(it), ctypes.byref(rr))
+    return dict(x=x, status=st, iters=it.value, relres=rr.value)
+
+
 def _ptr(a):
     return a.ctypes.data_as(_P) if a is not None else None
 

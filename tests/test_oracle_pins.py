@@ -548,3 +548,26 @@ def test_owner_cell_numbering_gives_the_same_system(dim, n, k, prob, faces):
     # contributions are summed in the same (cell, a, b) order: bitwise equal
     assert np.array_equal(A_own[np.ix_(perm, perm)], S.dense())
     assert np.array_equal(rhs[perm], S.rhs)
+
+
+# --------------------------------------------------------------------------
+# The all-cores build of the oracle (the CPU baseline's OpenMP leg) computes
+# the same system as the serial oracle
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n,k,prob", [(3, [5, 4, 3], 1, "poisson"), (3, [3, 2, 2], 2, "elasticity"),
+                                          (2, [6, 5], 3, "poisson")])
+def test_openmp_oracle_matches_serial_oracle(dim, n, k, prob):
+    P = O.Problem(dim, n, k, problem=prob, source_kind=1, source=(1.0, -0.5, 0.25), faces=0b000101 if dim == 3
+                  else 0b0101, dirichlet_kind=1, dirichlet_affine=[0.2, 1.0, -0.5, 0.3] * 3)
+    v = structured_vertices(dim, n, jitter=0.2, seed=95)
+    coef = lognormal_coefficients(P.ncells, seed=96)
+    S = O.System(P, v, coef)
+    rp, ci = O.omp_csr_pattern(S.cell_dofs, S.nfree)
+    assert np.array_equal(rp, S.rowptr) and np.array_equal(ci, S.colind)
+    vals, rhs, ok = O.omp_assemble(P, v, coef, S.cell_dofs, S.nfree, rp, ci)
+    # same per-entry summation order: bitwise the serial assembly
+    assert ok and np.array_equal(vals, S.values) and np.array_equal(rhs, S.rhs)
+    res = O.omp_pcg(S.rowptr, S.colind, S.values, S.rhs, 1e-12, 20000)
+    ref = O.pcg(S.rowptr, S.colind, S.values, S.rhs, 1e-12, 20000)
+    assert res["status"] == 0 and abs(res["iters"] - ref["iters"]) <= 2
+    assert np.linalg.norm(res["x"] - ref["x"]) <= 1e-9 * np.linalg.norm(ref["x"])
