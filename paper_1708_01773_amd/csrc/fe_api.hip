@@ -843,8 +843,8 @@ fe_status fe_pcg_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const in
 fe_status fe_spmv(const fe_csr *A, const double *x, double *y, fe_stream stream)
 {
     if (!A || !x || !y || !A->rowptr || !A->colind || !A->values) return set_error(FE_EINVAL, "null argument");
-    const double npr = A->n_rows > 0 ? double(A->nnz) / double(A->n_rows) : 1.0;
-    return launch_spmv(A->n_rows, A->rowptr, A->colind, A->values, x, y, npr, as_stream(stream));
+    if (A->n_rows < 0 || A->nnz < 0) return set_error(FE_EINVAL, "negative size");
+    return launch_spmv(A->n_rows, A->rowptr, A->colind, A->values, x, y, A->nnz, as_stream(stream));
 }
 
 fe_status fe_csr_to_fp32(const fe_csr *A, float *values32, fe_stream stream)

@@ -202,7 +202,7 @@ fe_status engine_states(EngineSet &E, hipStream_t s);  // synchronizes
 bool engine_done(const EngineSet &E, int t);           // from the last engine_states / engine_finish
 fe_status engine_finish(EngineSet &E, hipStream_t s);  // true residuals + infos; synchronizes
 fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
-                      double *y, double nnz_per_row, hipStream_t s);
+                      double *y, int64_t nnz, hipStream_t s);
 size_t pcg_solve_ws_bytes(int64_t n);
 fe_status pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int maxit, void *ws, size_t ws_bytes,
                     fe_solve_info *info, hipStream_t s);

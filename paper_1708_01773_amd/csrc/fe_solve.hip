@@ -166,7 +166,8 @@ static PcgWs carve(void *ws, int64_t n)
 }
 
 // Device slot for the problem table of a single-problem solve (inside its workspace).
-static SpmvPlan heuristic_plan(double avg)
+// Wave-level plans (modes 0 and 1) by average row length.
+static SpmvPlan stream_plan(double avg)
 {
     SpmvPlan pl{};
     if (avg >= 96.0) {
@@ -189,6 +190,31 @@ static SpmvPlan heuristic_plan(double avg)
 // changed in between.
 static std::mutex g_tune_mu;
 static std::map<int, SpmvPlan> g_tuned;
+
+// The default CSR plan: block tiles (mode 9) of R rows, R the largest power of
+// two in [4, 256] with R avg <= kTileRowsTarget entries (three passes; the
+// fastest tile sizes of the autotuner on the 128^3 Q1 and the Q2-Q4
+// elasticity matrices, 27 to 611 entries per row, lie at 3000-9000 entries).
+constexpr double kTileRowsTarget = 6144.0;
+static SpmvPlan heuristic_plan(double avg)
+{
+    int R = 256;
+    while (R > 4 && R * avg > kTileRowsTarget) R /= 2;
+    SpmvPlan pl{};
+    pl.mode = 9;
+    pl.rpb = R;
+    pl.lanes = 256 / R;
+    return pl;
+}
+
+// Mode 9 loads column indices and values 16 bytes at a time; a matrix whose
+// arrays are not 16-byte aligned takes the wave-level plan of its row length.
+static SpmvPlan csr_launch_form(SpmvPlan pl, int64_t n, int64_t nnz, const int32_t *colind, const void *val)
+{
+    if (pl.mode == 9 && ((reinterpret_cast<uintptr_t>(colind) | reinterpret_cast<uintptr_t>(val)) & 15u))
+        return stream_plan(n > 0 ? double(nnz) / double(n) : 1.0);
+    return pl;
+}
 
 static int plan_class(int64_t n, int64_t nnz)
 {
@@ -243,10 +269,10 @@ __device__ __forceinline__ void block_sum_all(double (&v)[NV])
 }
 
 // Block partials of v -> part[t * stride + blockIdx.x].
-template <int NV>
+template <int NV, int B = kBlock>
 __device__ __forceinline__ void write_partials(double (&v)[NV], double *part, int stride)
 {
-    block_sum_all<NV>(v);
+    block_sum_all<NV, B>(v);
     if (threadIdx.x == 0)
 #pragma unroll
         for (int t = 0; t < NV; t++) part[t * stride + blockIdx.x] = v[t];
@@ -416,6 +442,124 @@ __device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restri
     }
 }
 
+// CSR rows in block tiles (plan mode 9; R rows per tile, 4 <= R <= 256).  A
+// block of kTileThreads threads takes a tile of R consecutive rows and streams
+// its entries in passes of kTileCap: each thread loads four consecutive
+// column indices with one 16-byte load and their values with 16-byte loads
+// (two groups of four per thread, every load of a pass issued before the
+// first gather of x), multiplies and stages the products in LDS; then the
+// LPR = kTileThreads / R lanes of each row sum its staged entries of the pass
+// in lane order, and a butterfly over the LPR lanes ends the row.  The
+// streamed range starts at the row pointer rounded down to a multiple of four
+// entries (the lead is loaded and masked); the last group of the matrix, if
+// it has fewer than four entries, is loaded element by element.  Tiles are
+// dealt XCD-contiguously: block lb runs on XCD lb mod 8 (nb is a multiple of
+// 8), and the blocks of XCD x take the tiles of [x T / 8, (x + 1) T / 8) in
+// turn, so a tile and its neighbours -- which gather much of the same x -- run
+// under one L2.  Needs colind and val 16-byte aligned (checked at launch).
+constexpr int kTileThreads = 256;
+constexpr int kTileCap = 2048;  // products staged per pass (16 KB of LDS)
+constexpr int kTileGroups = kTileCap / (4 * kTileThreads);
+
+template <int R, typename VT, typename Fn>
+__device__ __forceinline__ void for_rows_tiles(int64_t n, int64_t nnz, const int64_t *__restrict__ growptr,
+                                               const int32_t *__restrict__ gcolind, const VT *__restrict__ gval,
+                                               const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+{
+    static_assert(R >= 4 && R <= kTileThreads && kTileThreads % R == 0, "rows per tile");
+    constexpr int LPR = kTileThreads / R;
+    typedef int32_t int4v __attribute__((ext_vector_type(4)));
+    typedef float float4v __attribute__((ext_vector_type(4)));
+    const FE_GLOBAL int64_t *__restrict__ rowptr = as_global(growptr);
+    const FE_GLOBAL int32_t *__restrict__ colind = as_global(gcolind);
+    const FE_GLOBAL VT *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
+    __shared__ double prod[kTileCap];
+    __shared__ int64_t rp[R + 1];
+    const int tid = threadIdx.x, lr = tid / LPR, sub = tid % LPR;
+    const int64_t ntiles = (n + R - 1) / R;
+    const int64_t xcd = lb % 8, per = nb / 8;
+    const int64_t t_hi = (xcd + 1) * ntiles / 8;
+    // the row pointers of a tile: thread tid < nr holds rowptr[r0 + tid],
+    // thread 0 also the tile's end; the next tile's are loaded while this one
+    // streams, so only a block's first tile waits for them
+    int64_t pa = 0, pe = 0;
+    auto fetch_rp = [&](int64_t t) {
+        const int64_t q0 = t * R;
+        const int m = int(n - q0 < R ? n - q0 : R);
+        pa = tid < m ? rowptr[q0 + tid] : 0;
+        pe = tid == 0 ? rowptr[q0 + m] : 0;
+    };
+    int64_t tile = xcd * ntiles / 8 + lb / 8;
+    if (tile < t_hi) fetch_rp(tile);
+    for (; tile < t_hi; tile += per) {
+        const int64_t r0 = tile * R;
+        const int nr = int(n - r0 < R ? n - r0 : R);
+        __syncthreads();  // the previous tile's reads of rp and prod are done
+        if (tid < nr) rp[tid] = pa;
+        if (tid == 0) rp[nr] = pe;
+        __syncthreads();
+        if (tile + per < t_hi) fetch_rp(tile + per);
+        const int64_t base = rp[0], end = rp[nr];
+        const int64_t rb = lr < nr ? rp[lr] : end, re = lr < nr ? rp[lr + 1] : end;
+        double acc = 0.0;
+        for (int64_t p0 = base & ~int64_t(3); p0 < end; p0 += kTileCap) {
+            int32_t c[kTileGroups][4];
+            double a[kTileGroups][4];
+#pragma unroll
+            for (int g = 0; g < kTileGroups; g++) {
+                const int64_t e = p0 + 4 * (tid + kTileThreads * g);
+                if (e < end && e + 4 <= nnz) {
+                    const int4v cv = *reinterpret_cast<const FE_GLOBAL int4v *>(colind + e);
+                    c[g][0] = cv.x;
+                    c[g][1] = cv.y;
+                    c[g][2] = cv.z;
+                    c[g][3] = cv.w;
+                    if constexpr (sizeof(VT) == 8) {
+                        const fe_dpair v0 = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(val + e);
+                        const fe_dpair v1 = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(val + e + 2);
+                        a[g][0] = v0.x;
+                        a[g][1] = v0.y;
+                        a[g][2] = v1.x;
+                        a[g][3] = v1.y;
+                    } else {
+                        const float4v v = *reinterpret_cast<const FE_GLOBAL float4v *>(val + e);
+                        a[g][0] = double(v.x);
+                        a[g][1] = double(v.y);
+                        a[g][2] = double(v.z);
+                        a[g][3] = double(v.w);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const bool ok = e + j < end;
+                        c[g][j] = ok ? colind[e + j] : 0;
+                        a[g][j] = ok ? double(val[e + j]) : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kTileGroups; g++) {
+                const int64_t e = p0 + 4 * (tid + kTileThreads * g);
+                double pr[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const bool in = e + j >= base && e + j < end;
+                    pr[j] = in ? a[g][j] * x[c[g][j]] : 0.0;
+                }
+                reinterpret_cast<fe_dpair *>(prod)[2 * (tid + kTileThreads * g)] = fe_dpair{pr[0], pr[1]};
+                reinterpret_cast<fe_dpair *>(prod)[2 * (tid + kTileThreads * g) + 1] = fe_dpair{pr[2], pr[3]};
+            }
+            __syncthreads();
+            const int64_t s1 = re < p0 + kTileCap ? re : p0 + kTileCap;
+            for (int64_t j = (rb > p0 ? rb : p0) + sub; j < s1; j += LPR) acc += prod[j - p0];
+            __syncthreads();
+        }
+        acc = butterfly<LPR>(acc);
+        if (lr < nr && sub == 0) f(r0 + lr, acc);
+    }
+}
+
 // Dispatch on the plan (mode, rows per wave-iteration) at compile time.
 #define FE_PLAN_CASE(M, R, N, BODY) { constexpr int kMode = M, kRpb = R, kNc = N; (void)kNc; BODY; } break;
 #define FE_PLAN_DISPATCH(PL, BODY)                                 \
@@ -423,6 +567,16 @@ __device__ __forceinline__ void for_rows_wave(int64_t n, const int64_t *__restri
         if ((PL).mode == 1) {                                      \
             constexpr int kMode = 1, kRpb = 1, kNc = 1;            \
             BODY;                                                  \
+        } else if ((PL).mode == 9) {                               \
+            switch ((PL).rpb) {                                    \
+                case 256: FE_PLAN_CASE(9, 256, 1, BODY)            \
+                case 128: FE_PLAN_CASE(9, 128, 1, BODY)            \
+                case 64: FE_PLAN_CASE(9, 64, 1, BODY)              \
+                case 32: FE_PLAN_CASE(9, 32, 1, BODY)              \
+                case 16: FE_PLAN_CASE(9, 16, 1, BODY)              \
+                case 8: FE_PLAN_CASE(9, 8, 1, BODY)                \
+                default: FE_PLAN_CASE(9, 4, 1, BODY)               \
+            }                                                      \
         } else {                                                   \
             switch ((PL).rpb) {                                    \
                 case 32: FE_PLAN_CASE(0, 32, 1, BODY)              \
@@ -1229,7 +1383,7 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double
     }
 #define FE_PLAN_DISPATCH_FP32(PL, BODY)                                                        \
     do {                                                                                       \
-        if ((PL).mode >= 7) {                                                                  \
+        if ((PL).mode == 7 || (PL).mode == 8) {                                                \
             FE_SYM_DISPATCH(PL, BODY)                                                          \
         } else {                                                                               \
             FE_PLAN_DISPATCH(PL, BODY);                                                        \
@@ -1237,7 +1391,7 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double
     } while (0)
 #define FE_PLAN_DISPATCH_ALL(PL, BODY)                                                         \
     do {                                                                                       \
-        if ((PL).mode >= 2) {                                                                  \
+        if ((PL).mode >= 2 && (PL).mode <= 8) {                                                \
             FE_SPLAN_DISPATCH(PL, BODY)                                                        \
         } else {                                                                               \
             FE_PLAN_DISPATCH(PL, BODY);                                                        \
@@ -1325,10 +1479,12 @@ static SpmvPlan aligned_form(SpmvPlan pl, const void *values)
 }
 
 template <int MODE, int RPW, typename VT, typename Fn>
-__device__ __forceinline__ void for_rows(int64_t n, const int64_t *rowptr, const int32_t *colind, const VT *val,
-                                         const double *x, int64_t lb, int64_t nb, Fn f)
+__device__ __forceinline__ void for_rows(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind,
+                                         const VT *val, const double *x, int64_t lb, int64_t nb, Fn f)
 {
-    if constexpr (MODE == 1)
+    if constexpr (MODE == 9)
+        for_rows_tiles<RPW, VT>(n, nnz, rowptr, colind, val, x, lb, nb, f);
+    else if constexpr (MODE == 1)
         for_rows_wave(n, rowptr, colind, val, x, lb, nb, f);
     else
         for_rows_wstream<RPW, VT>(n, rowptr, colind, val, x, lb, nb, f);
@@ -1349,7 +1505,7 @@ __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, in
     else if constexpr (MODE == 2)
         for_rows_struct<RPB, NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else
-        for_rows<MODE, RPB, VT>(P.n, P.rowptr, P.colind, static_cast<const VT *>(P.val), x, lb, nb, f);
+        for_rows<MODE, RPB, VT>(P.n, P.nnz, P.rowptr, P.colind, static_cast<const VT *>(P.val), x, lb, nb, f);
 }
 
 // Problem of block blockIdx.x in a launch whose problem p owns blocks
@@ -1461,12 +1617,13 @@ constexpr int rows_block(int mode) { return mode >= 4 ? kQ1Block : kBlock; }
 // [boff[p], boff[p+1]) of the launch)
 // ---------------------------------------------------------------------------
 template <int MODE, int RPB, typename VT>
-__global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, const int64_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ colind,
-                                                       const VT *__restrict__ val, const double *__restrict__ x,
-                                                       double *__restrict__ y)
+__global__ __launch_bounds__(rows_block(MODE)) void spmv_kernel(int64_t n, int64_t nnz,
+                                                                 const int64_t *__restrict__ rowptr,
+                                                                 const int32_t *__restrict__ colind,
+                                                                 const VT *__restrict__ val,
+                                                                 const double *__restrict__ x, double *__restrict__ y)
 {
-    for_rows<MODE, RPB, VT>(n, rowptr, colind, val, x, blockIdx.x, gridDim.x,
+    for_rows<MODE, RPB, VT>(n, nnz, rowptr, colind, val, x, blockIdx.x, gridDim.x,
                             [&](int64_t row, double s) { y[row] = s; });
 }
 
@@ -1558,7 +1715,7 @@ __global__ __launch_bounds__(rows_block(MODE)) void pcg_spmv_kernel(const PcgPro
     // the Q1 traversals (modes 4, 5, 7, 8) hand over p[row] from their LDS copy of p
     for_rows_p<MODE, RPB, NC, VT>(P, P.w.p, lb, nb, [&](int64_t row, double s, double prow = 0.0) {
                                 q[row] = s;
-                                v += (MODE == 4 || MODE == 5 || MODE >= 7 ? prow : p[row]) * s;
+                                v += (MODE == 4 || MODE == 5 || MODE == 7 || MODE == 8 ? prow : p[row]) * s;
                             });
     // block partial: wave sums, then wave 0's lane 0 adds them in wave order
     __shared__ double wsum[rows_block(MODE) / 64];
@@ -1738,6 +1895,11 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 // ---------------------------------------------------------------------------
 static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
+    if (pl.mode == 9) {  // a block per tile, at most one per partial slot; a multiple of 8 (XCD-contiguous tiles)
+        const int64_t tiles = (n + pl.rpb - 1) / pl.rpb;
+        const int64_t cap = part_slots(n) / 8 * 8;
+        return int((std::max<int64_t>(1, std::min<int64_t>(cap, tiles)) + 7) / 8 * 8);
+    }
     const int rows_per_run = pl.mode >= 7 ? 64 : pl.mode >= 3 ? 32 : pl.rpb;  // mode 6: a block per 32-row chunk
     const int waves = pl.mode == 6 ? 1 : rows_block(pl.mode) / 64;
     const int64_t runs = (n + rows_per_run - 1) / rows_per_run;
@@ -1759,13 +1921,13 @@ static int grid_elems(int64_t n)
 }
 
 fe_status launch_spmv(int64_t n, const int64_t *rowptr, const int32_t *colind, const double *val, const double *x,
-                      double *y, double nnz_per_row, hipStream_t s)
+                      double *y, int64_t nnz, hipStream_t s)
 {
     if (n == 0) return FE_OK;
-    const SpmvPlan pl = plan_for(n, int64_t(nnz_per_row * double(n) + 0.5));
+    const SpmvPlan pl = csr_launch_form(plan_for(n, nnz), n, nnz, colind, val);
     const int g = grid_rows(n, pl);
-    FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb, double><<<dim3(g), dim3(kBlock), 0, s>>>(n, rowptr,
-                                             colind, val, x, y)));
+    FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb, double><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(n, nnz,
+                                             rowptr, colind, val, x, y)));
     FE_HIP(hipGetLastError());
     return FE_OK;
 }
@@ -1820,8 +1982,10 @@ struct PinnedState {
 // matrix's row-length class.
 // ---------------------------------------------------------------------------
 // {mode, nc, rows per wave, lanes per row}
-static const SpmvPlan kCandidates[] = {{0, 1, 1, 64}, {0, 1, 2, 32}, {0, 1, 4, 16}, {0, 1, 8, 8},
-                                       {0, 1, 16, 4}, {0, 1, 32, 2}, {1, 1, 1, 64}};
+static const SpmvPlan kCandidates[] = {{0, 1, 1, 64},   {0, 1, 2, 32},  {0, 1, 4, 16},  {0, 1, 8, 8},
+                                       {0, 1, 16, 4},   {0, 1, 32, 2},  {1, 1, 1, 64},  {9, 1, 256, 1},
+                                       {9, 1, 128, 2},  {9, 1, 64, 4},  {9, 1, 32, 8},  {9, 1, 16, 16},
+                                       {9, 1, 8, 32},   {9, 1, 4, 64}};
 
 size_t autotune_ws_bytes(int64_t n) { return 2 * align256(size_t(std::max<int64_t>(n, 1)) * sizeof(double)); }
 
@@ -1844,12 +2008,12 @@ fe_status spmv_autotune(const fe_csr *A, int reps, void *ws, size_t ws_bytes, fe
     const int ncand = int(sizeof(kCandidates) / sizeof(kCandidates[0]));
     fe_status st = FE_OK;
     for (int c = 0; c < ncand && st == FE_OK; c++) {
-        const SpmvPlan &pl = kCandidates[c];
+        const SpmvPlan pl = csr_launch_form(kCandidates[c], n, A->nnz, A->colind, A->values);
         const int g = grid_rows(n, pl);
         for (int r = -1; r < reps; r++) {
             if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = set_error(FE_EDEVICE, "event record failed");
-            FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb, double><<<dim3(g), dim3(kBlock), 0, s>>>(
-                                     n, A->rowptr, A->colind, A->values, x, y)));
+            FE_PLAN_DISPATCH(pl, (spmv_kernel<kMode, kRpb, double><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(
+                                     n, A->nnz, A->rowptr, A->colind, A->values, x, y)));
         }
         if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
             hipEventSynchronize(e1) != hipSuccess) {
@@ -2087,7 +2251,9 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
         if (jobs[i].sym)
             plans[i] = launch_form(SpmvPlan{7, 1, jobs[i].sa->dim == 3 ? 27 : 9, 2}, jobs[i].n);
         else
-            plans[i] = jobs[i].sa ? aligned_form(struct_plan(*jobs[i].sa), jobs[i].val) : plan_for(jobs[i].n, jobs[i].nnz);
+            plans[i] = jobs[i].sa ? aligned_form(struct_plan(*jobs[i].sa), jobs[i].val)
+                                  : csr_launch_form(plan_for(jobs[i].n, jobs[i].nnz), jobs[i].n, jobs[i].nnz,
+                                                    jobs[i].colind, jobs[i].val);
         if (jobs[i].n > 0) order.push_back(i);
     }
     auto key = [&](int i) {
@@ -2524,21 +2690,22 @@ size_t pcg_batch_ws_bytes(int nprob, const int64_t *n_rows)
 // ---------------------------------------------------------------------------
 // r = b - A x; partials of r.r
 template <int MODE, int RPB>
-__global__ __launch_bounds__(kBlock) void resid_vec_kernel(int64_t n, const int64_t *__restrict__ rowptr,
+__global__ __launch_bounds__(rows_block(MODE)) void resid_vec_kernel(int64_t n, int64_t nnz,
+                                                                      const int64_t *__restrict__ rowptr,
                                                             const int32_t *__restrict__ colind,
                                                             const double *__restrict__ val,
                                                             const double *__restrict__ b, const double *__restrict__ x,
                                                             double *__restrict__ r, PcgWs w)
 {
     double v[2] = {0.0, 0.0};
-    for_rows<MODE, RPB, double>(n, rowptr, colind, val, x, blockIdx.x, gridDim.x,
+    for_rows<MODE, RPB, double>(n, nnz, rowptr, colind, val, x, blockIdx.x, gridDim.x,
                                 [&](int64_t row, double ax) {
         const double d = b[row] - ax;
         r[row] = d;
         v[0] += d * d;
         v[1] += b[row] * b[row];
     });
-    write_partials<2>(v, w.p3, w.ps);
+    write_partials<2, rows_block(MODE)>(v, w.p3, w.ps);
 }
 
 __global__ __launch_bounds__(kBlock) void resid_vec_finish_kernel(PcgWs w, int nparts)
@@ -2594,13 +2761,13 @@ fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values
     double *r = reinterpret_cast<double *>(base + inner_bytes);
     double *d = reinterpret_cast<double *>(base + inner_bytes + align256(size_t(n) * sizeof(double)));
     PcgWs w = carve(pws, n);
-    const SpmvPlan pl = plan_for(n, Ahi->nnz);
+    const SpmvPlan pl = csr_launch_form(plan_for(n, Ahi->nnz), n, Ahi->nnz, Ahi->colind, Ahi->values);
     const int gr = grid_rows(n, pl);
     const int ge = grid_elems(n);
     info->status = FE_ENOTCONV;
     for (int it = 0; it <= max_outer; it++) {
-        FE_PLAN_DISPATCH(pl, (resid_vec_kernel<kMode, kRpb><<<dim3(gr), dim3(kBlock), 0, s>>>(
-                                 n, Ahi->rowptr, Ahi->colind, Ahi->values, b, x, r, w)));
+        FE_PLAN_DISPATCH(pl, (resid_vec_kernel<kMode, kRpb><<<dim3(gr), dim3(rows_block(kMode)), 0, s>>>(
+                                 n, Ahi->nnz, Ahi->rowptr, Ahi->colind, Ahi->values, b, x, r, w)));
         hipLaunchKernelGGL(resid_vec_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr);
         FE_HIP(hipGetLastError());
         FE_HIP(hipMemcpyAsync(pin.h, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));

@@ -391,10 +391,10 @@ def spmv_autotune(csr, reps=20, stream=None):
     q = _c.c_size_t()
     _check(lib().fe_spmv_autotune_query(int(csr.n_rows), _c.byref(q)), "fe_spmv_autotune_query")
     ws = torch.empty(max(q.value, 8), dtype=torch.uint8, device="cuda")
-    tried = (SpmvPlan * 16)()
+    tried = (SpmvPlan * 32)()
     nt = _c.c_int32()
     ch = SpmvPlan()
-    _check(lib().fe_spmv_autotune(_c.byref(csr), int(reps), _ptr(ws), q.value, tried, 16, _c.byref(nt),
+    _check(lib().fe_spmv_autotune(_c.byref(csr), int(reps), _ptr(ws), q.value, tried, 32, _c.byref(nt),
                                   _c.byref(ch), _stream(stream)), "fe_spmv_autotune")
     d = lambda p: dict(mode=p.mode, rows_per_wave=p.rows_per_wave, us=p.us)
     return d(ch), [d(t) for t in tried[: nt.value]]
@@ -407,11 +407,11 @@ def spmv_autotune_mesh(mesh, order, coeff, csr, reps=20, stream=None):
     q = _c.c_size_t()
     _check(lib().fe_spmv_autotune_query(int(csr.n_rows), _c.byref(q)), "fe_spmv_autotune_query")
     ws = torch.empty(max(q.value, 8), dtype=torch.uint8, device="cuda")
-    tried = (SpmvPlan * 16)()
+    tried = (SpmvPlan * 32)()
     nt = _c.c_int32()
     ch = SpmvPlan()
     _check(lib().fe_spmv_autotune_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(csr), int(reps), _ptr(ws),
-                                       q.value, tried, 16, _c.byref(nt), _c.byref(ch), _stream(stream)),
+                                       q.value, tried, 32, _c.byref(nt), _c.byref(ch), _stream(stream)),
            "fe_spmv_autotune_mesh")
     d = lambda p: dict(mode=p.mode, rows_per_wave=p.rows_per_wave, us=p.us)
     return d(ch), [d(t) for t in tried[: nt.value]]

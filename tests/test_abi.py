@@ -93,12 +93,13 @@ def test_batch_and_tuning_entry_points_validate_on_host():
     assert L.fe_assemble_batch_query(2, None, None, None, None, None, ctypes.byref(ws)) == F.FE_EINVAL
     assert L.fe_spmv_autotune(None, 5, None, 0, None, 0, None, None, None) == F.FE_EINVAL
     assert L.fe_spmv_autotune_query(-1, ctypes.byref(ws)) == F.FE_EINVAL
-    # untuned plans follow the row length: short rows share a wave, long rows get one each
+    # untuned plans follow the row length: block tiles of as many rows (a power
+    # of two) as hold at most 6144 entries, 4 rows at least
     assert L.fe_spmv_tuning_reset() == F.FE_OK
     mode, rpw, cls = F.spmv_plan_of(1000, 27000)
-    assert mode == 0 and rpw * 27 <= 256 and rpw * 2 * 27 > 256
+    assert mode == 9 and rpw * 27 <= 6144 and rpw * 2 * 27 > 6144
     mode, rpw, cls2 = F.spmv_plan_of(1000, 343000)
-    assert mode == 1 and cls2 > cls
+    assert mode == 9 and rpw == 16 and cls2 > cls
 
 
 def test_symmetric_storage_entry_points_validate_on_host():
@@ -119,15 +120,20 @@ def test_symmetric_storage_entry_points_validate_on_host():
 def test_csr_plans_can_be_pinned_per_row_class_on_host():
     # the CSR plans the autotuner times: stream runs of 1..32 rows per wave,
     # and one wave per row; each can be made the plan of a row-length class
-    plans = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (0, 32), (1, 1)]
+    plans = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (0, 32), (1, 1), (9, 4), (9, 8), (9, 16), (9, 32), (9, 64),
+             (9, 128), (9, 256)]
     try:
         for mode, rpw in plans:
             F.spmv_plan_set(1000, 250000, mode, rpw)
             assert F.spmv_plan_of(1000, 250000)[:2] == (mode, rpw)
             assert F.spmv_plan_of(1000, 251000)[:2] == (mode, rpw)  # same half-octave class
-        for mode, rpw in [(0, 3), (0, 64), (1, 2), (2, 8)]:
+        for mode, rpw in [(0, 3), (0, 64), (1, 2), (2, 8), (9, 2), (9, 512), (10, 64), (11, 1)]:
             with pytest.raises(F.FeError, match="not a CSR plan"):
                 F.spmv_plan_set(1000, 250000, mode, rpw)
     finally:
         F.spmv_tuning_reset()
-    assert F.spmv_plan_of(1000, 250000)[:2] == (1, 1)  # the heuristic again: long rows, wave per row
+    # the heuristic again: block tiles of the most rows (a power of two, 4..256) with at most 6144 entries
+    assert F.spmv_plan_of(1000, 250000)[:2] == (9, 16)
+    assert F.spmv_plan_of(2048383, 54439939)[:2] == (9, 128)
+    assert F.spmv_plan_of(2572125, 1572091911)[:2] == (9, 8)
+    assert F.spmv_plan_of(1000, 3000)[:2] == (9, 256)

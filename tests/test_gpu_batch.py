@@ -173,7 +173,7 @@ def test_spmv_autotuner_picks_a_measured_plan_and_keeps_results():
         untuned = F.spmv_plan_of(A.n_rows, A.nnz)
         chosen, tried = F.spmv_autotune(A.csr, reps=5)
         say(f"[autotune] untuned {untuned} chosen {chosen}")
-        assert len(tried) == 7 and all(t["us"] > 0 for t in tried)
+        assert len(tried) == 14 and all(t["us"] > 0 for t in tried)
         assert chosen["us"] == min(t["us"] for t in tried)
         mode, rpw, _ = F.spmv_plan_of(A.n_rows, A.nnz)
         assert (mode, rpw) == (chosen["mode"], chosen["rows_per_wave"])

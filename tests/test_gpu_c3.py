@@ -14,7 +14,8 @@ from tests.gpu_util import MATRIX_RTOL, Pair, element_matrices, rel, say
 
 pytestmark = pytest.mark.gpu
 
-CSR_PLANS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (0, 32), (1, 1)]
+CSR_PLANS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (0, 32), (1, 1), (9, 4), (9, 8), (9, 16), (9, 32), (9, 64),
+             (9, 128), (9, 256)]
 
 
 def _check_rows(S, x, y, tol=1e-12):
@@ -188,3 +189,57 @@ def test_c3q4_solve_residual_by_csr_spmv(c3q4):
     say(f"   pcg iters {info['iters']} relres {info['relres']:.2e} true (CSR SpMV) {tr:.2e}")
     assert info["status"] == F.FE_OK and info["relres"] <= 1e-10
     assert tr <= 2e-10 and abs(tr - info["true_relres"]) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# The block-tiled CSR traversal on generic matrices: empty rows, rows longer
+# than a staging pass, entry counts that are not a multiple of four (the last
+# group loaded element by element), arrays off 16-byte boundaries (the
+# wave-level plan of the same row length instead)
+# --------------------------------------------------------------------------
+def _random_csr(n, seed, long_rows=()):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lens = np.minimum(rng.integers(0, 40, n), n)
+    lens[rng.random(n) < 0.15] = 0
+    for r in long_rows:
+        if r < n:
+            lens[r] = min(n, 3000)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(lens)
+    cols = [np.sort(rng.choice(n, size=int(L), replace=False)) for L in lens]
+    colind = np.concatenate(cols).astype(np.int32) if rowptr[-1] else np.zeros(0, dtype=np.int32)
+    vals = rng.standard_normal(int(rowptr[-1]))
+    return rowptr, colind, vals
+
+
+@pytest.mark.parametrize("n,seed,long_rows", [(1, 1, ()), (5, 2, ()), (77, 3, ()), (1000, 4, (3, 500)),
+                                              (4099, 5, (0, 4098, 2048)), (20011, 6, (7,))])
+def test_tiled_csr_traversal_on_irregular_matrices(n, seed, long_rows):
+    rowptr, colind, vals = _random_csr(n, seed, long_rows)
+    nnz = int(rowptr[-1])
+    x = np.random.Generator(np.random.PCG64(seed + 100)).standard_normal(n)
+    want = O.spmv(rowptr, colind, vals, x)
+    scale = O.spmv(rowptr, colind, np.abs(vals), np.abs(x))
+    say(f"[tiled csr] n {n} nnz {nnz} (mod 4 = {nnz % 4}) longest row {np.diff(rowptr).max()}")
+    rp = torch.from_numpy(rowptr).cuda()
+    # column indices and values at 16-byte boundaries, and 4 / 8 bytes off them
+    cbuf = torch.zeros(nnz + 4, dtype=torch.int32, device="cuda")
+    vbuf = torch.zeros(nnz + 2, dtype=torch.float64, device="cuda")
+    xd = torch.from_numpy(x).cuda()
+    F.spmv_tuning_reset()
+    try:
+        for off_c, off_v in ((0, 0), (1, 0), (0, 1)):
+            ci = cbuf[off_c: off_c + nnz]
+            va = vbuf[off_v: off_v + nnz]
+            ci.copy_(torch.from_numpy(colind))
+            va.copy_(torch.from_numpy(vals))
+            C = F.csr_struct(n, nnz, rp, ci, va, None, None)
+            for mode, R in [(9, 4), (9, 8), (9, 16), (9, 32), (9, 64), (9, 128), (9, 256)]:
+                F.spmv_plan_set(n, nnz, mode, R)
+                y = torch.full_like(xd, float("nan"))
+                F.spmv(C, xd, y)
+                torch.cuda.synchronize()
+                got = y.cpu().numpy()
+                assert np.all(np.abs(got - want) <= 1e-13 * scale + 1e-300), (off_c, off_v, mode, R)
+    finally:
+        F.spmv_tuning_reset()
