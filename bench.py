@@ -339,6 +339,77 @@ def mixed_form(args, wl, mesh, A, x_fp64, F, torch, stream, ncells, lo="fp32"):
             "rel_error_vs_fp64_solution": err}
 
 
+def c3_precision(F, torch, orders=("c3q2", "c3q3", "c3q4"), precisions=("fp32", "fp16", "bf16")):
+    """The precision form on 3D elasticity Q2 48^3 / Q3 32^3 / Q4 24^3: the plain
+    FP64 solve (evaluated pattern, rtol 1e-10) against, per element-GEMM
+    precision, (a) the matrix assembled with that precision solved in FP64 (the
+    workload's configuration; its distance to the FP64 solution is the
+    integration error, stated) and (b) iterative refinement to 1e-10: FP64
+    residual with the FP64 matrix, inner Jacobi-PCG on the low-precision matrix
+    stored in FP32 with the pattern evaluated from the mesh (4 B per entry),
+    inner rtol 1e-4.  One solve each, wall clock."""
+    from fe_inputs import structured_vertices
+
+    out = {}
+    for key in orders:
+        wl = WORKLOADS[key]
+        dim, n, k = wl["dim"], wl["n"], wl["k"]
+        v = structured_vertices(dim, n, jitter=0.2)
+        mesh = F.create_mesh(dim, [n] * dim, v, None)
+
+        def assemble(prec):
+            c = F.make_coeff("elasticity", prec, source_kind=1, source=(0.0, 0.0, -1.0), dim=dim)
+            A = F.Assembly(mesh, k, c)
+            A.pattern()
+            A.assemble()
+            return A
+
+        A_hi = assemble("fp64")
+        ws = torch.empty(F.refine_query(A_hi.n_rows), dtype=torch.uint8, device="cuda")
+        x64 = torch.zeros(A_hi.n_rows, dtype=torch.float64, device="cuda")
+        A_hi.solve(x64, wl["rtol"], 100000, ws)  # warm-up
+        x64.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = A_hi.solve(x64, wl["rtol"], 100000, ws)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        nx = torch.linalg.vector_norm(x64)
+        res = {"workload": wl["text"], "fp64": {"s": t64, "iters": info["iters"], "relres": info["relres"]}}
+        for prec in precisions:
+            A_lo = assemble(prec)
+            dA = (torch.linalg.vector_norm(A_lo.values[:A_lo.nnz] - A_hi.values[:A_hi.nnz]) /
+                  torch.linalg.vector_norm(A_hi.values[:A_hi.nnz])).item()
+            xl = torch.zeros_like(x64)
+            il = A_lo.solve(xl, wl["rtol"], 100000, ws)
+            e_plain = (torch.linalg.vector_norm(xl - x64) / nx).item()
+            del xl
+            v32 = torch.empty(A_lo.nnz, dtype=torch.float32, device="cuda")
+            F.csr_to_fp32(A_lo.csr, v32)
+            xr = torch.zeros_like(x64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ri = F.refine_solve_mesh(mesh, k, A_hi.coeff, A_hi.csr, A_lo.csr, A_hi.rhs, xr, wl["rtol"], 1e-4, 50,
+                                     100000, ws, values32=v32)
+            torch.cuda.synchronize()
+            tr = time.perf_counter() - t0
+            e_ref = (torch.linalg.vector_norm(xr - x64) / nx).item()
+            res[prec] = {"matrix_rel_error": dA, "plain_fp64_solve_of_it": {"iters": il["iters"],
+                                                                             "rel_error_vs_fp64": e_plain},
+                         "refined": {"s": tr, "speedup_vs_fp64": t64 / tr, "outer_iters": ri["outer_iters"],
+                                     "inner_iters": ri["inner_iters"], "status_ok": ri["status"] == F.FE_OK,
+                                     "relres": ri["relres"], "rel_error_vs_fp64": e_ref}}
+            print(f"[bench] {key} {prec}: |dA|/|A| {dA:.1e}, its FP64 solve {e_plain:.1e} from FP64; refined "
+                  f"{tr:.2f} s vs {t64:.2f} s ({ri['outer_iters']} outer, {ri['inner_iters']} inner), "
+                  f"{e_ref:.1e} from FP64", file=sys.stderr, flush=True)
+            del A_lo, v32, xr
+            torch.cuda.empty_cache()
+        out[key] = res
+        del A_hi, ws, x64, mesh
+        torch.cuda.empty_cache()
+    return out
+
+
 def peak_probe(torch):
     """Achievable rates of this GPU, measured, to set the published peaks the
     roofline uses in context: a 1 GiB device copy and a 4 GiB read (a sum) in
@@ -542,7 +613,8 @@ def main():
     ap.add_argument("--serve-max-dofs", type=int, default=1000000, help="largest request kept in the sample")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--form", default=None, choices=["batch", "serve"], help="run only this form and print its JSON")
+    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision"],
+                    help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
     ap.add_argument("--peak-probe", action="store_true",
@@ -579,6 +651,10 @@ def main():
     if args.form == "serve":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "serve", **serve_form(args, F, torch)}), flush=True)
+        return
+    if args.form == "precision":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "precision_c3", **c3_precision(F, torch)}), flush=True)
         return
 
     wl = dict(WORKLOADS[args.workload])
@@ -709,6 +785,8 @@ def main():
     torch.cuda.empty_cache()
     if args.workload == "c2" and not args.no_c3:
         out["c3_assembly"] = c3_assembly(F, torch)
+        if forms:
+            out["forms"]["precision_c3"] = c3_precision(F, torch)
     if forms and args.workload == "c2":
         if args.batch_sample > 0:
             out["forms"]["batch"] = batch_form(args, F, torch)

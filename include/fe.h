@@ -426,6 +426,22 @@ fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *v
                           double rtol, double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws,
                           size_t ws_bytes, fe_refine_info *info, fe_stream stream);
 
+/* fe_refine_solve on a system assembled by this library on (mesh, order,
+ * coeff) (either coeff; A_hi and A_lo share the pattern): the inner Jacobi-PCG
+ * evaluates the pattern from the mesh instead of reading column indices, so
+ * an FP32 A_lo (values32) costs 4 bytes per entry per product, each value
+ * widened to FP64 in its product; every vector, dot and the outer residual
+ * with A_hi stay FP64 (the residual through the CSR of A_hi).  values32 (if
+ * not NULL: device, A_lo->nnz floats, 4-byte aligned, e.g. fe_csr_to_fp32 of
+ * A_lo) takes the block-staged traversal; otherwise A_lo->values (FP64) take
+ * the mesh system's plan.  Refinement by the paper's iterative solvers (Sect.
+ * 12) with FP64 residuals; the workspace is fe_refine_query's.  Synchronizes;
+ * returns info->status.  Errors: as for fe_pcg_solve_mesh and fe_refine_solve. */
+fe_status fe_refine_solve_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_csr *A_hi,
+                               const fe_csr *A_lo, const float *values32, const double *b, double *x, double rtol,
+                               double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws, size_t ws_bytes,
+                               fe_refine_info *info, fe_stream stream);
+
 /* Iterative refinement with the inner solve on the symmetric storage of A_lo
  * in FP32 (Q1 scalar systems; the layout of fe_sym_query with float slots):
  *   fe_sym_fp32_from_csr: sym32 (device, >= fe_sym_query / 2 bytes, 4-byte

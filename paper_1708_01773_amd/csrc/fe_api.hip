@@ -874,6 +874,28 @@ fe_status fe_refine_solve(const fe_csr *A_hi, const fe_csr *A_lo, const float *v
                         as_stream(stream));
 }
 
+fe_status fe_refine_solve_mesh(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A_hi, const fe_csr *A_lo,
+                               const float *values32, const double *b, double *x, double rtol, double inner_rtol,
+                               int32_t max_outer, int32_t max_inner, void *ws, size_t ws_bytes, fe_refine_info *info,
+                               fe_stream stream)
+{
+    if (!A_hi || !A_lo || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    fe_status st = prepare_space(m, order, c, nullptr);
+    if (st != FE_OK) return st;
+    st = check_csr(A_hi, m->space.args, true);
+    if (st != FE_OK) return st;
+    st = check_csr(A_lo, m->space.args, false);
+    if (st != FE_OK) return st;
+    if (!A_hi->rowptr || !A_hi->colind || (A_lo->n_rows > 0 && !A_lo->dinv)) return set_error(FE_EINVAL, "incomplete csr");
+    if (A_lo->nnz > 0 && !values32 && !A_lo->values) return set_error(FE_EINVAL, "no A_lo values");
+    if (values32 && (reinterpret_cast<uintptr_t>(values32) & 3u)) return set_error(FE_EINVAL, "values32 not 4-byte aligned");
+    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || max_outer < 0 || max_inner < 1)
+        return set_error(FE_EINVAL, "bad tolerances or iteration limits");
+    m->last_stream = as_stream(stream);
+    return refine_solve(A_hi, A_lo, values32, b, x, rtol, inner_rtol, max_outer, max_inner, ws, ws_bytes, info,
+                        as_stream(stream), &m->space.args, nullptr);
+}
+
 fe_status fe_sym_fp32_from_csr(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, float *sym32,
                                size_t sym32_bytes, fe_stream stream)
 {

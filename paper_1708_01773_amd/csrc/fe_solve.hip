@@ -1256,13 +1256,13 @@ static_assert(xblock_staged_max(1, 4) <= kXbCap && xblock_staged_max(2, 4) <= kX
                   xblock_staged_max(3, 4) <= kXbCap,
               "the staged x box of a mode-6 chunk exceeds its LDS buffer");
 
-template <int NC, typename Fn>
-__device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double *__restrict__ gval,
+template <int NC, typename VT, typename Fn>
+__device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const VT *__restrict__ gval,
                                                 const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
 {
     constexpr int RPW = 8, LW = 64 / RPW;
     __shared__ double sx[kXbCap];
-    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL VT *__restrict__ val = as_global(gval);
     const FE_GLOBAL double *__restrict__ x = as_global(gx);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / LW, sub = lane % LW;
     const int32_t k = s.k;
@@ -1327,7 +1327,10 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double
                     const int32_t xx = pc - qy * wx;
                     const int32_t j2 = int32_t((uint32_t(qy) * my) >> 20);
                     const int32_t j1 = qy - j2 * w1;
-                    a4[t] = ok ? val[start + pc] : 0.0;
+                    // pc = 0 is in the row: an unconditional load, so an FP32 value's widening
+                    // does not make each load wait for the one before
+                    const VT raw = val[start + pc];
+                    a4[t] = ok ? double(raw) : 0.0;
                     x4[t] = sx[(j2 * w1 + j1) * run + xoff + xx];
                 }
 #pragma unroll
@@ -1385,6 +1388,12 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const double
     do {                                                                                       \
         if ((PL).mode == 7 || (PL).mode == 8) {                                                \
             FE_SYM_DISPATCH(PL, BODY)                                                          \
+        } else if ((PL).mode == 6) {                                                           \
+            switch ((PL).nc) {                                                                 \
+                case 1: FE_PLAN_CASE(6, 8, 1, BODY)                                            \
+                case 2: FE_PLAN_CASE(6, 8, 2, BODY)                                            \
+                default: FE_PLAN_CASE(6, 8, 3, BODY)                                           \
+            }                                                                                  \
         } else {                                                                               \
             FE_PLAN_DISPATCH(PL, BODY);                                                        \
         }                                                                                      \
@@ -1497,7 +1506,7 @@ __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, in
     if constexpr (MODE == 7 || MODE == 8)
         for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(P.sa, static_cast<const VT *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 6)
-        for_rows_xblock<NC>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+        for_rows_xblock<NC, VT>(P.sa, static_cast<const VT *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 4 || MODE == 5)
         for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 3)
@@ -1636,7 +1645,7 @@ __global__ __launch_bounds__(rows_block(MODE)) void spmv_struct_kernel(SpaceArgs
         for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(sa, val, x, xcd_block<MODE>(blockIdx.x, gridDim.x), gridDim.x,
                                                      [&](int64_t row, double s) { y[row] = s; });
     else if constexpr (MODE == 6)
-        for_rows_xblock<NC>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
+        for_rows_xblock<NC, double>(sa, val, x, blockIdx.x, gridDim.x, [&](int64_t row, double s) { y[row] = s; });
     else if constexpr (MODE == 4 || MODE == 5)
         for_rows_q1<RPB == 27 ? 3 : 2, MODE == 5>(sa, val, x, blockIdx.x, gridDim.x,
                                                   [&](int64_t row, double s) { y[row] = s; });
@@ -2246,9 +2255,9 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
     std::vector<int> order;
     std::vector<SpmvPlan> plans(njobs);
     for (int i = 0; i < njobs; i++) {
-        if (jobs[i].sa && jobs[i].fp32 && !jobs[i].sym)
-            return set_error(FE_EINVAL, "structured traversal needs FP64 values");
-        if (jobs[i].sym)
+        if (jobs[i].sa && jobs[i].fp32 && !jobs[i].sym)  // FP32 values: the block-staged traversal
+            plans[i] = SpmvPlan{6, jobs[i].sa->ncomp, 8, 8};
+        else if (jobs[i].sym)
             plans[i] = launch_form(SpmvPlan{7, 1, jobs[i].sa->dim == 3 ? 27 : 9, 2}, jobs[i].n);
         else
             plans[i] = jobs[i].sa ? aligned_form(struct_plan(*jobs[i].sa), jobs[i].val)
@@ -2788,10 +2797,10 @@ fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values
                                 max_inner, pws, inner_bytes, &inner, s, sa, true);
         else if (values32)
             st = pcg_run<float>(n, Alo->nnz, Alo->rowptr, Alo->colind, values32, Alo->dinv, r, d, inner_rtol,
-                                max_inner, pws, inner_bytes, &inner, s);
+                                max_inner, pws, inner_bytes, &inner, s, sa);
         else
             st = pcg_run<double>(n, Alo->nnz, Alo->rowptr, Alo->colind, Alo->values, Alo->dinv, r, d, inner_rtol,
-                                 max_inner, pws, inner_bytes, &inner, s);
+                                 max_inner, pws, inner_bytes, &inner, s, sa);
         info->inner_iters += inner.iters;
         info->outer_iters = it + 1;
         if (st == FE_EBREAKDOWN || st == FE_EDEVICE || st == FE_EINVAL) {

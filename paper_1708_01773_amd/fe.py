@@ -32,6 +32,7 @@ EXPORTS = [
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
     "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set", "fe_pcg_solve_noalloc",
+    "fe_refine_solve_mesh",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -166,6 +167,9 @@ def lib():
             "fe_spmv_plan_set_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan)],
             "fe_sym_query": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_size_t)],
             "fe_sym_fp32_from_csr": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_refine_solve_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _c.POINTER(Csr), _P, _P, _P,
+                                     _c.c_double, _c.c_double, _c.c_int32, _c.c_int32, _P, _c.c_size_t,
+                                     _c.POINTER(RefineInfo), _P],
             "fe_refine_solve_sym": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _c.POINTER(Csr), _P,
                                     _c.c_size_t, _P, _P, _c.c_double, _c.c_double, _c.c_int32, _c.c_int32, _P,
                                     _c.c_size_t, _c.POINTER(RefineInfo), _P],
@@ -543,6 +547,20 @@ def refine_solve(A_hi, A_lo, b, x, rtol, inner_rtol, max_outer, max_inner, ws, v
                                ws.numel() * ws.element_size(), _c.byref(info), _stream(stream))
     if st not in (FE_OK, FE_ENOTCONV):
         _check(st, "fe_refine_solve")
+    return dict(outer_iters=info.outer_iters, inner_iters=info.inner_iters, status=info.status, relres=info.relres)
+
+
+def refine_solve_mesh(mesh, order, coeff, A_hi, A_lo, b, x, rtol, inner_rtol, max_outer, max_inner, ws,
+                      values32=None, stream=None):
+    """Iterative refinement whose inner PCG evaluates the pattern from the mesh
+    (FP32 values32, or A_lo's FP64 values); returns dict(outer_iters, inner_iters, status, relres)."""
+    info = RefineInfo()
+    st = lib().fe_refine_solve_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(A_hi), _c.byref(A_lo),
+                                    _ptr(values32), _ptr(b), _ptr(x), float(rtol), float(inner_rtol), int(max_outer),
+                                    int(max_inner), _ptr(ws), ws.numel() * ws.element_size(), _c.byref(info),
+                                    _stream(stream))
+    if st not in (FE_OK, FE_ENOTCONV):
+        _check(st, "fe_refine_solve_mesh")
     return dict(outer_iters=info.outer_iters, inner_iters=info.inner_iters, status=info.status, relres=info.relres)
 
 

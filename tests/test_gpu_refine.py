@@ -104,3 +104,46 @@ def test_refinement_on_fp32_symmetric_storage(dim, n, lo_prec, faces):
     assert torch.equal(raw[1:], sym32)
     with pytest.raises(F.FeError, match="too small"):
         F.sym_fp32_from_csr(lo.mesh, 1, lo.coeff, A_lo.csr, raw[2:])
+
+
+@pytest.mark.parametrize("k,prob,n,lo_prec,demote,faces", [
+    (2, "elasticity", [4, 3, 3], "fp16", True, None),
+    (3, "poisson", [3, 3, 2], "bf16", True, 0b101011),
+    (4, "elasticity", [2, 2, 2], "fp32", True, None),
+    (1, "poisson", [7, 6, 5], "fp32", True, None),
+    (2, "elasticity", [3, 3, 3], "bf16", False, 0b000111),
+    (1, "elasticity", [5, 4, 3], "fp64", True, None),
+])
+def test_refinement_with_the_evaluated_pattern_inner_solve(k, prob, n, lo_prec, demote, faces):
+    """fe_refine_solve_mesh: the inner PCG evaluates the pattern (FP32 values
+    through the block-staged traversal, or A_lo's FP64 values through the mesh
+    plan); the refined solution must reach the FP64 solution as the CSR
+    refinement does."""
+    say(f"[refine mesh] k={k} {prob} n={n} faces={faces} A_lo {lo_prec}, FP32 storage={demote}")
+    hi = Pair(3, n, k, prob, faces=faces, source=(1.0, 0.0, -1.0))
+    A_hi = hi.gpu_assembly()
+    lo = Pair(3, n, k, prob, faces=faces, source=(1.0, 0.0, -1.0), precision=lo_prec)
+    A_lo = lo.gpu_assembly()
+    v32 = None
+    if demote:
+        v32 = torch.empty(A_lo.nnz, dtype=torch.float32, device="cuda")
+        F.csr_to_fp32(A_lo.csr, v32)
+    ws = torch.empty(F.refine_query(A_hi.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A_hi.n_rows, dtype=torch.float64, device="cuda")
+    info = F.refine_solve_mesh(hi.mesh, k, hi.coeff, A_hi.csr, A_lo.csr, A_hi.rhs, x, 1e-12, 1e-4, 50, 20000, ws,
+                               values32=v32)
+    xc = torch.zeros_like(x)
+    infoc = F.refine_solve(A_hi.csr, A_lo.csr, A_hi.rhs, xc, 1e-12, 1e-4, 50, 20000, ws, values32=v32)
+    say(f"   mesh {info}  csr {infoc}")
+    assert info["status"] == F.FE_OK and info["relres"] <= 1e-12
+    xr, _ = _fp64_solution(A_hi)
+    e = rel(x.cpu().numpy(), xr.cpu().numpy())
+    say(f"   |x_refined - x_fp64| / |x_fp64| = {e:.2e}")
+    assert e <= 1e-10 and rel(x.cpu().numpy(), xc.cpu().numpy()) <= 1e-10
+    # the same inner operator: the outer iteration counts agree closely
+    assert abs(info["outer_iters"] - infoc["outer_iters"]) <= 1
+    # a mesh that did not assemble A is refused
+    other = Pair(3, [n[0] + 1] + n[1:], k, prob, faces=faces)
+    with pytest.raises(F.FeError):
+        F.refine_solve_mesh(other.mesh, k, other.coeff, A_hi.csr, A_lo.csr, A_hi.rhs, x, 1e-12, 1e-4, 5, 100, ws,
+                            values32=v32)
