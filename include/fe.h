@@ -442,6 +442,25 @@ fe_status fe_refine_solve_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coef
                                double inner_rtol, int32_t max_outer, int32_t max_inner, void *ws, size_t ws_bytes,
                                fe_refine_info *info, fe_stream stream);
 
+/* Batched iterative refinement: fe_refine_solve_mesh with FP64 A_lo values
+ * for nprob systems at once (the batching form with reduced-precision
+ * integration: A_lo[i] integrated in FP32/FP16/BF16, A_hi[i] in FP64, on
+ * meshes[i], orders[i], coeffs[i] as for fe_pcg_solve_batch_mesh).  Each
+ * correction step forms the residuals of the systems still running with their
+ * A_hi (FP64, CSR) and solves their corrections A_lo d = r together by the
+ * batched Jacobi-PCG (the pattern evaluated from the meshes); a system stops
+ * at ||b - A_hi x|| <= rtol ||b|| or after max_outer corrections.  Every
+ * result is bitwise that of fe_refine_solve_mesh on the system alone.
+ *   fe_refine_batch_query: workspace bytes for nprob systems of n_rows[i] rows.
+ *   infos: host, nprob entries.  Synchronizes; returns FE_OK if every system
+ *   converged, else FE_ENOTCONV or FE_EBREAKDOWN (per system in infos). */
+fe_status fe_refine_batch_query(int32_t nprob, const int64_t *n_rows, size_t *ws_bytes);
+fe_status fe_refine_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const int32_t *orders,
+                                     const fe_coeff *coeffs, const fe_csr *A_hi, const fe_csr *A_lo,
+                                     const double *const *b, double *const *x, double rtol, double inner_rtol,
+                                     int32_t max_outer, int32_t max_inner, void *ws, size_t ws_bytes,
+                                     fe_refine_info *infos, fe_stream stream);
+
 /* Iterative refinement with the inner solve on the symmetric storage of A_lo
  * in FP32 (Q1 scalar systems; the layout of fe_sym_query with float slots):
  *   fe_sym_fp32_from_csr: sym32 (device, >= fe_sym_query / 2 bytes, 4-byte

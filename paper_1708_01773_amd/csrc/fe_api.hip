@@ -896,6 +896,43 @@ fe_status fe_refine_solve_mesh(fe_mesh m, int32_t order, const fe_coeff *c, cons
                         as_stream(stream), &m->space.args, nullptr);
 }
 
+fe_status fe_refine_batch_query(int32_t nprob, const int64_t *n_rows, size_t *ws_bytes)
+{
+    if (nprob < 0 || (nprob > 0 && !n_rows) || !ws_bytes) return set_error(FE_EINVAL, "bad argument");
+    for (int i = 0; i < nprob; i++)
+        if (n_rows[i] < 0) return set_error(FE_EINVAL, "negative n_rows");
+    *ws_bytes = refine_batch_ws_bytes(nprob, n_rows);
+    return FE_OK;
+}
+
+fe_status fe_refine_solve_batch_mesh(int32_t nprob, const fe_mesh *meshes, const int32_t *orders,
+                                     const fe_coeff *coeffs, const fe_csr *A_hi, const fe_csr *A_lo,
+                                     const double *const *b, double *const *x, double rtol, double inner_rtol,
+                                     int32_t max_outer, int32_t max_inner, void *ws, size_t ws_bytes,
+                                     fe_refine_info *infos, fe_stream stream)
+{
+    BatchLayout L;
+    fe_status st = batch_prepare(nprob, meshes, orders, coeffs, L);
+    if (st != FE_OK) return st;
+    if (nprob == 0) return FE_OK;
+    if (!A_hi || !A_lo || !b || !x || !ws || !infos) return set_error(FE_EINVAL, "null argument");
+    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || max_outer < 0 || max_inner < 1)
+        return set_error(FE_EINVAL, "bad tolerances or iteration limits");
+    std::vector<const SpaceArgs *> sas(nprob);
+    for (int i = 0; i < nprob; i++) {
+        st = check_csr(&A_hi[i], meshes[i]->space.args, true);
+        if (st != FE_OK) return st;
+        st = check_csr(&A_lo[i], meshes[i]->space.args, true);
+        if (st != FE_OK) return st;
+        if (A_hi[i].n_rows > 0 && (!b[i] || !x[i] || !A_hi[i].rowptr || !A_hi[i].colind || !A_hi[i].values))
+            return set_error(FE_EINVAL, "null vector or incomplete csr");
+        sas[i] = &meshes[i]->space.args;
+        meshes[i]->last_stream = as_stream(stream);
+    }
+    return refine_solve_batch(nprob, A_hi, A_lo, b, x, rtol, inner_rtol, max_outer, max_inner, ws, ws_bytes, infos,
+                              as_stream(stream), sas.data());
+}
+
 fe_status fe_sym_fp32_from_csr(fe_mesh m, int32_t order, const fe_coeff *c, const fe_csr *A, float *sym32,
                                size_t sym32_bytes, fe_stream stream)
 {

@@ -186,7 +186,7 @@ struct PcgJob {
     fe_solve_info *info;  // filled by engine_finish (may be null)
     double rtol;
     int maxit;
-    const SpaceArgs *sa = nullptr;  // structured pattern of a mesh-assembled system (FP64 values), or null
+    const SpaceArgs *sa = nullptr;  // structured pattern of a mesh-assembled system (FP32 values: block-staged), or null
     bool sym = false;               // val is the symmetric storage of a Q1 scalar system on sa
 };
 struct EngineSet;
@@ -236,6 +236,11 @@ fe_status spmv_autotune_struct(const SpaceArgs &sa, const double *values, int re
 void spmv_plan_of_struct(const SpaceArgs &sa, fe_spmv_plan *plan, int32_t *cls);
 fe_status spmv_plan_set_struct(const SpaceArgs &sa, const fe_spmv_plan &plan);
 size_t refine_ws_bytes(int64_t n);
+size_t refine_batch_ws_bytes(int nprob, const int64_t *n_rows);
+fe_status refine_solve_batch(int nprob, const fe_csr *Ahi, const fe_csr *Alo, const double *const *b,
+                             double *const *x, double rtol, double inner_rtol, int max_outer, int max_inner,
+                             void *ws, size_t ws_bytes, fe_refine_info *infos, hipStream_t s,
+                             const SpaceArgs *const *sas);
 fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s);
 fe_status refine_solve(const fe_csr *Ahi, const fe_csr *Alo, const float *values32, const double *b, double *x,
                        double rtol, double inner_rtol, int max_outer, int max_inner, void *ws, size_t ws_bytes,

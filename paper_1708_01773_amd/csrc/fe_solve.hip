@@ -2743,6 +2743,127 @@ size_t refine_ws_bytes(int64_t n)
     return pcg_ws_bytes(n) + engine_table_bytes(1) + 2 * align256(size_t(n) * sizeof(double));
 }
 
+// Batched refinement: per problem its inner PCG workspace, r and d; plus the
+// inner engine's table, the residual norms and a device array of state pointers.
+size_t refine_batch_ws_bytes(int nprob, const int64_t *n_rows)
+{
+    const size_t np = size_t(std::max(nprob, 1));
+    size_t b = engine_table_bytes(nprob) + align256(2 * np * sizeof(double)) + align256(np * sizeof(PcgState *));
+    for (int i = 0; i < nprob; i++) b += pcg_ws_bytes(n_rows[i]) + 2 * align256(size_t(n_rows[i]) * sizeof(double));
+    return b;
+}
+
+__global__ __launch_bounds__(kBlock) void refine_norms_kernel(PcgState *const *__restrict__ st, int np,
+                                                               double *__restrict__ out)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < np; i += gridDim.x * kBlock) {
+        out[2 * i] = st[i]->bb;
+        out[2 * i + 1] = st[i]->true_rr;
+    }
+}
+
+// Iterative refinement of many systems at once, each step as fe_refine_solve
+// takes it for one system (the FP64 residual through the CSR of A_hi, the
+// inner Jacobi-PCG on A_lo's FP64 values): the residuals of the running
+// systems are formed and their norms read back together, and their
+// corrections solved by one batched PCG (the engine solves each system as it
+// would alone, so every result is bitwise that of the one-system call).
+fe_status refine_solve_batch(int nprob, const fe_csr *Ahi, const fe_csr *Alo, const double *const *b,
+                             double *const *x, double rtol, double inner_rtol, int max_outer, int max_inner,
+                             void *ws, size_t ws_bytes, fe_refine_info *infos, hipStream_t s,
+                             const SpaceArgs *const *sas)
+{
+    std::vector<int64_t> nr(nprob);
+    for (int i = 0; i < nprob; i++) {
+        nr[i] = Ahi[i].n_rows;
+        std::memset(&infos[i], 0, sizeof(fe_refine_info));
+        infos[i].status = nr[i] == 0 ? FE_OK : FE_ENOTCONV;
+        if (Alo[i].n_rows != nr[i] || Alo[i].nnz != Ahi[i].nnz)
+            return set_error(FE_EINVAL, "A_lo must have the pattern of A_hi");
+    }
+    if (ws_bytes < refine_batch_ws_bytes(nprob, nr.data())) return set_error(FE_EINVAL, "refinement workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
+    if (nprob == 0) return FE_OK;
+    char *p = static_cast<char *>(ws);
+    void *table = p;
+    p += engine_table_bytes(nprob);
+    double *d_norms = reinterpret_cast<double *>(p);
+    p += align256(2 * size_t(nprob) * sizeof(double));
+    PcgState **d_st = reinterpret_cast<PcgState **>(p);
+    p += align256(size_t(nprob) * sizeof(PcgState *));
+    std::vector<void *> pws(nprob);
+    std::vector<double *> r(nprob), d(nprob);
+    std::vector<PcgState *> hst(nprob);
+    for (int i = 0; i < nprob; i++) {
+        pws[i] = p;
+        hst[i] = carve(p, nr[i]).st;
+        p += pcg_ws_bytes(nr[i]);
+        r[i] = reinterpret_cast<double *>(p);
+        p += align256(size_t(nr[i]) * sizeof(double));
+        d[i] = reinterpret_cast<double *>(p);
+        p += align256(size_t(nr[i]) * sizeof(double));
+    }
+    FE_HIP(hipMemcpyAsync(d_st, hst.data(), sizeof(PcgState *) * size_t(nprob), hipMemcpyHostToDevice, s));
+    std::vector<int> active;
+    for (int i = 0; i < nprob; i++)
+        if (nr[i] > 0) active.push_back(i);
+    std::vector<double> hn(2 * size_t(nprob));
+    std::vector<fe_solve_info> inner(nprob);
+    fe_status worst = FE_OK;
+    for (int it = 0; it <= max_outer && !active.empty(); it++) {
+        for (int i : active) {
+            const int64_t n = nr[i];
+            const SpmvPlan pl = csr_launch_form(plan_for(n, Ahi[i].nnz), n, Ahi[i].nnz, Ahi[i].colind, Ahi[i].values);
+            const int gr = grid_rows(n, pl);
+            const PcgWs w = carve(pws[i], n);
+            FE_PLAN_DISPATCH(pl, (resid_vec_kernel<kMode, kRpb><<<dim3(gr), dim3(rows_block(kMode)), 0, s>>>(
+                                     n, Ahi[i].nnz, Ahi[i].rowptr, Ahi[i].colind, Ahi[i].values, b[i], x[i], r[i], w)));
+            hipLaunchKernelGGL(resid_vec_finish_kernel, dim3(1), dim3(kBlock), 0, s, w, gr);
+        }
+        hipLaunchKernelGGL(refine_norms_kernel, dim3((nprob + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d_st, nprob,
+                           d_norms);
+        FE_HIP(hipGetLastError());
+        FE_HIP(hipMemcpyAsync(hn.data(), d_norms, sizeof(double) * 2 * size_t(nprob), hipMemcpyDeviceToHost, s));
+        FE_HIP(hipStreamSynchronize(s));
+        std::vector<int> next;
+        for (int i : active) {
+            const double bn = std::sqrt(hn[2 * size_t(i)]), rn = std::sqrt(hn[2 * size_t(i) + 1]);
+            infos[i].relres = bn > 0 ? rn / bn : rn;
+            if (infos[i].relres <= rtol) infos[i].status = FE_OK;
+            else if (it < max_outer) next.push_back(i);
+        }
+        if (next.empty()) break;
+        std::vector<PcgJob> jobs;
+        for (int i : next) {
+            FE_HIP(hipMemsetAsync(d[i], 0, sizeof(double) * size_t(nr[i]), s));
+            jobs.push_back(PcgJob{nr[i], Alo[i].nnz, Alo[i].rowptr, Alo[i].colind, Alo[i].values, false, Alo[i].dinv,
+                                  r[i], d[i], pws[i], &inner[i], inner_rtol, max_inner, sas ? sas[i] : nullptr,
+                                  false});
+        }
+        const fe_status st = pcg_engine(jobs, table, true, s);
+        if (st == FE_EDEVICE || st == FE_EINVAL) return st;
+        active.clear();
+        for (int i : next) {
+            infos[i].inner_iters += inner[i].iters;
+            infos[i].outer_iters = it + 1;
+            if (inner[i].status == FE_EBREAKDOWN) {
+                infos[i].status = FE_EBREAKDOWN;
+                worst = FE_EBREAKDOWN;
+                continue;
+            }
+            hipLaunchKernelGGL(axpy_kernel, dim3(grid_elems(nr[i])), dim3(kBlock), 0, s, nr[i], d[i], x[i]);
+            active.push_back(i);
+        }
+        FE_HIP(hipGetLastError());
+    }
+    FE_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nprob; i++)
+        if (infos[i].status == FE_ENOTCONV && worst == FE_OK) worst = FE_ENOTCONV;
+    if (worst == FE_ENOTCONV) set_error(FE_ENOTCONV, "iterative refinement reached max_outer");
+    if (worst == FE_EBREAKDOWN) set_error(FE_EBREAKDOWN, "inner pcg breakdown");
+    return worst;
+}
+
 fe_status csr_to_fp32(const fe_csr *A, float *values32, hipStream_t s)
 {
     if (A->nnz == 0) return FE_OK;

@@ -32,7 +32,7 @@ EXPORTS = [
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
     "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set", "fe_pcg_solve_noalloc",
-    "fe_refine_solve_mesh",
+    "fe_refine_solve_mesh", "fe_refine_batch_query", "fe_refine_solve_batch_mesh",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -167,6 +167,11 @@ def lib():
             "fe_spmv_plan_set_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan)],
             "fe_sym_query": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_size_t)],
             "fe_sym_fp32_from_csr": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_refine_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
+            "fe_refine_solve_batch_mesh": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
+                                           _c.POINTER(Csr), _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P),
+                                           _c.c_double, _c.c_double, _c.c_int32, _c.c_int32, _P, _c.c_size_t,
+                                           _c.POINTER(RefineInfo), _P],
             "fe_refine_solve_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _c.POINTER(Csr), _P, _P, _P,
                                      _c.c_double, _c.c_double, _c.c_int32, _c.c_int32, _P, _c.c_size_t,
                                      _c.POINTER(RefineInfo), _P],
@@ -562,6 +567,36 @@ def refine_solve_mesh(mesh, order, coeff, A_hi, A_lo, b, x, rtol, inner_rtol, ma
     if st not in (FE_OK, FE_ENOTCONV):
         _check(st, "fe_refine_solve_mesh")
     return dict(outer_iters=info.outer_iters, inner_iters=info.inner_iters, status=info.status, relres=info.relres)
+
+
+def refine_batch_query(n_rows):
+    n = len(n_rows)
+    arr = (_c.c_int64 * max(1, n))(*[int(v) for v in n_rows])
+    ws = _c.c_size_t()
+    _check(lib().fe_refine_batch_query(n, arr, _c.byref(ws)), "fe_refine_batch_query")
+    return ws.value
+
+
+def refine_solve_batch_mesh(meshes, orders, coeffs, csrs_hi, csrs_lo, bs, xs, rtol, inner_rtol, max_outer, max_inner,
+                            ws, stream=None, check=True):
+    """Batched iterative refinement (FP64 residuals with csrs_hi, batched inner
+    PCG on csrs_lo); returns (status, [dict(outer_iters, inner_iters, status, relres)])."""
+    n = len(meshes)
+    M = (_P * max(1, n))(*[m.handle for m in meshes])
+    O = (_c.c_int32 * max(1, n))(*[int(k) for k in orders])
+    C = (Coeff * max(1, n))(*coeffs)
+    H = (Csr * max(1, n))(*csrs_hi)
+    L = (Csr * max(1, n))(*csrs_lo)
+    B = (_P * max(1, n))(*[_ptr(b) for b in bs])
+    X = (_P * max(1, n))(*[_ptr(x) for x in xs])
+    infos = (RefineInfo * max(1, n))()
+    st = lib().fe_refine_solve_batch_mesh(n, M, O, C, H, L, B, X, float(rtol), float(inner_rtol), int(max_outer),
+                                          int(max_inner), _ptr(ws), ws.numel() * ws.element_size(), infos,
+                                          _stream(stream))
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_refine_solve_batch_mesh")
+    return st, [dict(outer_iters=i.outer_iters, inner_iters=i.inner_iters, status=i.status, relres=i.relres)
+                for i in infos[:n]]
 
 
 def sym_fp32_from_csr(mesh, order, coeff, csr, sym32, stream=None):

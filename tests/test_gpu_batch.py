@@ -241,3 +241,33 @@ def test_mesh_spmv_autotuner_picks_a_measured_plan_and_keeps_results():
     finally:
         F.spmv_tuning_reset()
     assert F.spmv_plan_of_mesh(pair.mesh, pair.k, pair.coeff) == untuned
+
+
+def test_batched_refinement_is_bitwise_the_single_refinement_and_reaches_fp64():
+    """Batching with reduced-precision integration: every problem of the batch
+    refined against its FP64 system gives bitwise the one-by-one refinement
+    (fe_refine_solve_mesh) and lies within 1e-10 of the plain FP64 solve."""
+    from paper_1708_01773_amd import batch as BT
+    specs = [(5, 1), (3, 3), (4, 2), (6, 1), (2, 2), (3, 1), (4, 3)]
+    for prec in ("fp32", "fp16"):
+        run = BT.BatchRun(specs, precision=prec, budget=1 << 30, first_index=40)
+        assert run.refine
+        xb, xs, x64 = {}, {}, {}
+        res = run.run(1e-12, 20000, keep=lambda i, x: xb.__setitem__(i, x.clone()))
+        seq = BT.run_sequential(run.problems, 1e-12, 20000, keep=lambda i, x: xs.__setitem__(i, x.clone()),
+                                coeffs_hi=run.coeffs_hi)
+        plain = BT.run_sequential([(m, k, run.coeffs_hi[i]) for i, (m, k, _) in enumerate(run.problems)], 1e-12,
+                                  20000, keep=lambda i, x: x64.__setitem__(i, x.clone()))
+        say(f"[batch refine {prec}] " + ", ".join(f"{i['outer_iters']}/{i['inner_iters']}" for i in res["infos"]))
+        assert res["status"] == F.FE_OK
+        for i in range(len(specs)):
+            bi, si = res["infos"][i], seq["infos"][i]
+            assert bi == si, (i, bi, si)
+            assert torch.equal(xb[i], xs[i]), i
+            if x64[i].numel():
+                assert rel(xb[i].cpu().numpy(), x64[i].cpu().numpy()) <= 1e-10, i
+    # a correction limit stops the problems that need more
+    run = BT.BatchRun(specs, precision="fp16", budget=1 << 30, first_index=40)
+    res = run.run(1e-12, 20000, max_outer=1)
+    assert res["status"] == F.FE_ENOTCONV
+    assert all(i["outer_iters"] <= 1 for i in res["infos"])
