@@ -523,27 +523,34 @@ def batch_form(args, F, torch):
 
 
 def serve_form(args, F, torch):
-    """Serving form: a bounded sample of the seeded Poisson-process request
-    stream (3D Poisson, n log-uniform in [8, 96], order uniform in 1..4, rtol
-    1e-8) replayed against the library's server.  The sample keeps, in arrival
-    order, the requests of at most --serve-max-dofs unknowns (thinning a
-    Poisson process by size keeps it a Poisson process, at the kept fraction of
-    the rate).  Three requests are re-run alone through the plain path and
-    compared bitwise with their result in the mix."""
+    """Serving form: the first --serve-requests requests of the seeded
+    Poisson-process stream (3D Poisson, n log-uniform in [8, 96], order uniform
+    in 1..4, rtol 1e-8), every drawn request submitted to the library's server
+    (a budget near the HBM size; only the server's own admission refuses a
+    request, at submission, if it needs more than the whole budget).  Rate 0:
+    every request arrives at once (the saturated throughput is the capacity).
+    --serve-max-dofs thins the stream to requests of at most that many
+    unknowns (not by default).  Three requests are re-run alone through the
+    plain path and compared bitwise with their result in the mix."""
     from fe_inputs import serving_requests
     from paper_1708_01773_amd import serve as SV
 
     rtol, maxit = 1e-8, 200000
-    drawn = serving_requests(2000, args.serve_rate)
-    kept = [(t, n, k, i) for i, (t, n, k) in enumerate(drawn) if (n * k - 1) ** 3 <= args.serve_max_dofs]
+    drawn = serving_requests(2000, args.serve_rate if args.serve_rate > 0 else 1.0)
+    cap = args.serve_max_dofs
+    kept = [(t if args.serve_rate > 0 else 0.0, n, k, i) for i, (t, n, k) in enumerate(drawn)
+            if cap is None or (n * k - 1) ** 3 <= cap]
     kept = kept[: args.serve_requests]
+    torch.cuda.empty_cache()
     t_first = kept[0][0]
     span = kept[-1][0] - t_first
     stream = [(t - t_first, n, k, i) for (t, n, k, i) in kept]
     print(f"[bench] serving form: {len(stream)} requests over {span:.2f} s of arrivals", file=sys.stderr, flush=True)
     srv = F.Server(int(args.serve_budget_gb * (1 << 30)), max_active=args.serve_slots)
     probes = {}
-    order = sorted(range(len(stream)), key=lambda j: (stream[j][1] * stream[j][2]) ** 3)
+    # probes: the smallest, the median and the largest request of at most 5e6 unknowns
+    order = sorted((j for j in range(len(stream)) if (stream[j][1] * stream[j][2] - 1) ** 3 <= 5e6),
+                   key=lambda j: (stream[j][1] * stream[j][2]) ** 3)
     for j in (order[0], order[len(order) // 2], order[-1]):
         probes[j] = None
 
@@ -553,13 +560,13 @@ def serve_form(args, F, torch):
             srv.solution(ticket, x)
             probes[j] = x
 
-    results, makespan = SV.run_stream(srv, stream, rtol=rtol, maxit=maxit, on_done=keep,
-                                      progress=max(1, len(stream) // 10))
+    results, makespan = SV.run_stream(srv, stream, rtol=rtol, maxit=maxit, on_done=keep, progress=1,
+                                      timeout=3000.0)
     stats = srv.stats()
     srv.close()
     summary = SV.summarize(results, makespan)
     failed = [{"request": stream[j][3], "n": stream[j][1], "k": stream[j][2], "state": r["state"],
-               "status": r["status"], "iters": r["iters"], "relres": r["relres"], "error": r["error"]}
+               "status": r.get("status"), "iters": r.get("iters"), "relres": r.get("relres"), "error": r["error"]}
               for j, r in enumerate(results) if not (r["state"] == F.FE_REQ_DONE and r["status"] == F.FE_OK)]
     same = True
     for j, x_mix in probes.items():
@@ -578,9 +585,12 @@ def serve_form(args, F, torch):
     print(f"[bench] serving form: {summary['solves_per_s']:.1f} solves/s, p50 {summary['p50_ms']:.1f} ms, "
           f"p99 {summary['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
     return {
-        "sample": f"first {len(stream)} requests with at most {args.serve_max_dofs} unknowns of the stream drawn "
-                  f"with seed 17083 at {args.serve_rate}/s (n log-uniform in [8, 96], order uniform in 1..4); "
-                  f"{len(stream)} of {kept[-1][3] + 1} drawn requests kept",
+        "sample": (f"first {len(stream)} requests of the stream drawn with seed 17083 " +
+                   (f"at {args.serve_rate}/s" if args.serve_rate > 0 else "arriving at once") +
+                   " (n log-uniform in [8, 96], order uniform in 1..4), every request submitted" +
+                   ("" if cap is None else f"; thinned to at most {cap} unknowns ({len(stream)} of "
+                                           f"{kept[-1][3] + 1} drawn)")),
+        "largest_request_dofs": max((n * k - 1) ** 3 for _, n, k, _ in stream),
         "arrival_rate_per_s": (len(stream) - 1) / span if span > 0 else None,
         "rtol": rtol, "budget_gb": args.serve_budget_gb, "max_active": args.serve_slots, **summary,
         "peak_in_flight": stats["peak_solving"], "peak_bytes": stats["peak_in_use"],
@@ -615,10 +625,12 @@ def main():
     ap.add_argument("--batch-budget-gb", type=float, default=160.0, help="device memory per batch wave")
     ap.add_argument("--batch-no-sequential", action="store_true",
                     help="batching form: skip the one-by-one comparison runs (for the full 512-problem batch)")
-    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving form (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrival rate of the drawn stream (1/s)")
-    ap.add_argument("--serve-max-dofs", type=int, default=1000000, help="largest request kept in the sample")
-    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-requests", type=int, default=12, help="requests of the serving form (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=0.15,
+                    help="arrival rate of the drawn stream (1/s); 0 = every request at once")
+    ap.add_argument("--serve-max-dofs", type=int, default=None,
+                    help="thin the stream to requests of at most this many unknowns (default: every request)")
+    ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--form", default=None, choices=["batch", "serve", "precision"],
                     help="run only this form and print its JSON")
@@ -793,7 +805,7 @@ def main():
     if args.workload == "c2" and not args.no_c3:
         out["c3_assembly"] = c3_assembly(F, torch)
         if forms:
-            out["forms"]["precision_c3"] = c3_precision(F, torch)
+            out["forms"]["precision_c3"] = c3_precision(F, torch, orders=("c3q2", "c3q4"))
     if forms and args.workload == "c2":
         if args.batch_sample > 0:
             out["forms"]["batch"] = batch_form(args, F, torch)

@@ -37,7 +37,9 @@ def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=
     """Submits stream[j] = (arrival_s, n, k, index) at its arrival time
     (scaled by time_scale) from a client thread and waits for all results.
     on_done(j, ticket, result) runs before the request is released; with
-    progress = m, a line on stderr after every m-th result.  Returns the
+    progress = m, a line on stderr after every m-th result.  A request the
+    server refuses at submission (more device memory than its whole budget)
+    gets the result dict(state="rejected", error=...).  Returns the
     per-request results and the makespan."""
     inputs = [request_inputs(i, n, k) for (_, n, k, i) in stream]
     if progress:
@@ -54,8 +56,13 @@ def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=
                 if delay > 0:
                     time.sleep(delay)
                 a = inputs[j]
-                tickets[j] = server.submit(a["dim"], a["n"], a["order"], a["coeff"], rtol, maxit,
-                                           vertices=a["vertices"], cell_coeff=a["cell_coeff"])
+                try:
+                    tickets[j] = server.submit(a["dim"], a["n"], a["order"], a["coeff"], rtol, maxit,
+                                               vertices=a["vertices"], cell_coeff=a["cell_coeff"])
+                except F.FeError as e:
+                    if e.status != F.FE_ENOMEM:
+                        raise
+                    tickets[j] = ("rejected", str(e))
         except Exception as e:  # reported by the caller
             errors.append(e)
         finally:
@@ -70,6 +77,9 @@ def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=
             time.sleep(0.0005)
         if errors:
             break
+        if isinstance(tickets[j], tuple):
+            results[j] = dict(state="rejected", error=tickets[j][1])
+            continue
         r = server.wait(tickets[j], timeout)
         results[j] = r
         if on_done is not None:
@@ -80,17 +90,22 @@ def run_stream(server, stream, rtol=1e-8, maxit=200000, time_scale=1.0, on_done=
     th.join()
     if errors:
         raise errors[0]
-    makespan = max(r["t_done"] for r in results) - c0
+    makespan = max((r["t_done"] for r in results if r["state"] != "rejected"), default=c0) - c0
     return results, makespan
 
 
 def summarize(results, makespan):
+    """Latency statistics over the served requests (queueing included);
+    requests refused at submission are counted, not timed."""
+    rejected = [r for r in results if r["state"] == "rejected"]
+    results = [r for r in results if r["state"] != "rejected"]
     lat = [r["t_done"] - r["t_submit"] for r in results]
     queue = [r["t_admit"] - r["t_submit"] for r in results]
     setup = [r["t_ready"] - r["t_admit"] for r in results]
     ok = sum(1 for r in results if r["state"] == F.FE_REQ_DONE and r["status"] == F.FE_OK)
-    return {"requests": len(results), "converged": ok, "makespan_s": makespan,
-            "solves_per_s": len(results) / makespan if makespan > 0 else None,
+    return {"requests": len(results) + len(rejected), "served": len(results), "rejected_at_submission": len(rejected),
+            "converged": ok, "makespan_s": makespan,
+            "solves_per_s": ok / makespan if makespan > 0 else None,
             "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
             "max_ms": max(lat) * 1e3, "queue_p50_ms": percentile(queue, 50) * 1e3,
             "queue_p99_ms": percentile(queue, 99) * 1e3, "setup_p50_ms": percentile(setup, 50) * 1e3,

@@ -33,3 +33,15 @@ def test_batch_specs_follow_the_recipe():
 def test_problem_bytes_counts_csr_and_vectors():
     b = problem_bytes(1000, 27000, 4096)
     assert b >= 8 * 1001 + 12 * 27000 + 6 * 8 * 1000 + 4096
+
+
+def test_serving_summary_counts_refused_requests_apart():
+    from paper_1708_01773_amd import fe as F
+    from paper_1708_01773_amd.serve import percentile, summarize
+    done = lambda ts, ta, tr, td: dict(state=F.FE_REQ_DONE, status=F.FE_OK, t_submit=ts, t_admit=ta, t_ready=tr,
+                                       t_done=td, iters=10, n_rows=5, nnz=25)
+    res = [done(0.0, 0.0, 0.1, 1.0), dict(state="rejected", error="budget"), done(0.5, 0.6, 0.7, 3.5)]
+    s = summarize(res, 3.5)
+    assert s["requests"] == 3 and s["served"] == 2 and s["rejected_at_submission"] == 1 and s["converged"] == 2
+    assert s["p50_ms"] == 1000.0 and s["p99_ms"] == 3000.0 and s["solves_per_s"] == 2 / 3.5
+    assert percentile([5, 1, 3], 50) == 3 and percentile([1], 99) == 1

@@ -139,3 +139,18 @@ def test_failures_stay_with_their_request():
         srv.release(tg)  # unknown ticket now
     assert srv.stats()["in_use"] == 0
     srv.close()
+
+
+def test_stream_records_requests_refused_at_submission():
+    """Every drawn request is submitted; one needing more than the whole budget
+    is refused by the server's admission and recorded, the others are served."""
+    srv = F.Server(1 << 30, max_active=8)
+    stream = [(0.0, 6, 2, 50), (0.0, 80, 4, 51), (0.01, 5, 1, 52)]  # the second needs about 100 GB
+    results, makespan = run_stream(srv, stream, rtol=1e-8, maxit=10000)
+    say(f"[serve] refused: {results[1]}")
+    assert results[1]["state"] == "rejected" and "budget" in results[1]["error"]
+    assert results[0]["state"] == F.FE_REQ_DONE and results[2]["state"] == F.FE_REQ_DONE
+    s = summarize(results, makespan)
+    assert s["rejected_at_submission"] == 1 and s["served"] == 2 and s["converged"] == 2
+    assert srv.stats()["rejected"] == 1
+    srv.close()
