@@ -84,6 +84,10 @@ def lib():
         L.orc_l2_error.restype = _d
         L.orc_fixed_values.argtypes = [ctypes.POINTER(OrcProblem), _P, _P, _i64, _P]
         L.orc_fixed_values.restype = None
+        L.orc_dg_pattern.argtypes = [ctypes.POINTER(OrcProblem), _P, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+        L.orc_dg_pattern.restype = _i64
+        L.orc_dg_assemble.argtypes = [ctypes.POINTER(OrcProblem), _P, _d, _d, _P, _P, _P, _P]
+        L.orc_dg_assemble.restype = _i
         _lib = L
     return _lib
 
@@ -487,6 +491,46 @@ def owner_cell_numbering(P: Problem):
                 for c in range(nc):
                     out[cell, nc * a + c] = owner_ids[I][c]
     return out, nfree, nfixed
+
+
+class DGSystem:
+    """The interior-penalty DG system of -Laplace(u) = f (Sect. 3.12) on a
+    mesh: DOF K nn + a, every facet integrated, Dirichlet data weak.  gamma is
+    the penalty parameter, tau = 1 the symmetric method.  The problem's
+    source and Dirichlet datum (kinds as in Problem) are used; its faces are
+    ignored (every boundary facet carries the datum)."""
+
+    def __init__(self, P: Problem, vxyz, gamma, tau=1.0):
+        assert P.problem == "poisson"
+        self.P, self.gamma, self.tau = P, float(gamma), float(tau)
+        self.vxyz = _c(vxyz, np.float64)
+        self.nfree = P.ncells * P.nn
+        s = P.c_struct()
+        self.rowptr = np.zeros(self.nfree + 1, dtype=np.int64)
+        cptr = ctypes.POINTER(ctypes.c_int32)()
+        nnz = lib().orc_dg_pattern(ctypes.byref(s), _ptr(self.rowptr), ctypes.byref(cptr))
+        self.colind = np.ctypeslib.as_array(cptr, shape=(max(nnz, 1),))[:nnz].copy()
+        lib().orc_free(ctypes.cast(cptr, _P))
+        self.values = np.zeros(nnz)
+        self.rhs = np.zeros(self.nfree)
+        rc = lib().orc_dg_assemble(ctypes.byref(s), _ptr(self.vxyz), self.gamma, self.tau, _ptr(self.rowptr),
+                                   _ptr(self.colind), _ptr(self.values), _ptr(self.rhs))
+        self.ok = rc == 0
+        self.cell_dofs = np.arange(self.nfree, dtype=np.int64).reshape(P.ncells, P.nn)
+
+    @property
+    def nnz(self):
+        return int(self.rowptr[-1])
+
+    def dense(self):
+        A = np.zeros((self.nfree, self.nfree))
+        for i in range(self.nfree):
+            A[i, self.colind[self.rowptr[i]:self.rowptr[i + 1]]] = self.values[self.rowptr[i]:self.rowptr[i + 1]]
+        return A
+
+    def scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.values, self.colind, self.rowptr), shape=(self.nfree, self.nfree))
 
 
 def coo_compress(rows, cols, vals, n):

@@ -821,3 +821,256 @@ void orc_fixed_values(const orc_problem *P, const double *vxyz, const int64_t *c
         }
     }
 }
+
+/* ======================================================================== */
+/* Interior-penalty discontinuous Galerkin for -Laplace(u) = f (Sect. 3.12,  */
+/* eq. ip_dg_formulations; the facet matrices of eq. local_to_face_matrix).  */
+/* ======================================================================== */
+/* Readings: tau = 1 (the symmetric member of the family; then the two ways  */
+/* of placing the jump and the mean in the printed facet matrix coincide);   */
+/* the penalty |F|^-1 read as h_F^-1 with h_F = |F|^(1/(d-1)) (the facet      */
+/* length in 2D, as printed; its square root in 3D, so the penalty scales    */
+/* like 1/h in every dimension); coefficient 1; Dirichlet data imposed       */
+/* weakly on every boundary facet.  No DOF is shared: DOF(K, a) = K nn + a.  */
+/* Facet quadrature: Gauss-Legendre with k+1 points per tangential direction */
+/* on the reference face, mapped by the cell's order-1 geometry from either  */
+/* side (the brick's neighbouring faces coincide point by point).            */
+
+/* Cells that share the facet of cell K on side (r, +): K + stride(r), if any */
+static int64_t orc_dg_neighbour(const int *n, int dim, int64_t K, int r, int side)
+{
+    int64_t ci[3] = {K % n[0], (K / n[0]) % n[1], dim == 3 ? K / ((int64_t)n[0] * n[1]) : 0};
+    int64_t st[3] = {1, n[0], (int64_t)n[0] * n[1]};
+    int64_t c = ci[r] + (side ? 1 : -1);
+    if (c < 0 || c >= n[r]) return -1;
+    return K + (side ? st[r] : -st[r]);
+}
+
+/* Pattern: row K nn + a has the columns of K and of its facet neighbours,  */
+/* ascending.  rowptr has nn ncells + 1 entries; *colind_out malloc'ed.     */
+int64_t orc_dg_pattern(const orc_problem *P, int64_t *rowptr, int32_t **colind_out)
+{
+    int dim = P->dim, k = P->k;
+    int nn = ipow(k + 1, dim);
+    int64_t ncells = (int64_t)P->n[0] * P->n[1] * (dim == 3 ? P->n[2] : 1);
+    int64_t nnz = 0;
+    rowptr[0] = 0;
+    int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * 8);
+    for (int64_t K = 0; K < ncells; K++) {
+        int nc = 0;
+        cells[nc++] = K;
+        for (int r = 0; r < dim; r++)
+            for (int side = 0; side < 2; side++) {
+                int64_t L = orc_dg_neighbour(P->n, dim, K, r, side);
+                if (L >= 0) cells[nc++] = L;
+            }
+        for (int a = 0; a < nn; a++) rowptr[K * nn + a + 1] = rowptr[K * nn + a] + (int64_t)nc * nn;
+        nnz += (int64_t)nc * nn * nn;
+    }
+    int32_t *colind = (int32_t *)malloc(sizeof(int32_t) * (nnz > 0 ? nnz : 1));
+    for (int64_t K = 0; K < ncells; K++) {
+        int nc = 0;
+        cells[nc++] = K;
+        for (int r = 0; r < dim; r++)
+            for (int side = 0; side < 2; side++) {
+                int64_t L = orc_dg_neighbour(P->n, dim, K, r, side);
+                if (L >= 0) cells[nc++] = L;
+            }
+        qsort(cells, (size_t)nc, sizeof(int64_t), cmp_i64);
+        for (int a = 0; a < nn; a++) {
+            int64_t p = rowptr[K * nn + a];
+            for (int c = 0; c < nc; c++)
+                for (int b = 0; b < nn; b++) colind[p++] = (int32_t)(cells[c] * nn + b);
+        }
+    }
+    free(cells);
+    *colind_out = colind;
+    return nnz;
+}
+
+/* One side of a facet at reference point xi of cell X: shape values,       */
+/* physical gradients, the physical point, and the area-weighted normal     */
+/* det(J) J^-T e_r (outward for the face xi_r = 1, inward for xi_r = 0).    */
+static int orc_face_side(int dim, int k, const double *X, const double *xi, int r, double *phi, double *grad,
+                         double *x, double *nvec)
+{
+    orc_qp qp;
+    int bad = orc_shape_at(dim, k, X, xi, phi, grad, &qp);
+    double J[9], Ji[9], tmp[3];
+    orc_geometry(dim, X, xi, tmp, J);
+    double det = orc_det_inv(dim, J, Ji);
+    for (int i = 0; i < dim; i++) {
+        x[i] = qp.x[i];
+        nvec[i] = det * Ji[r * dim + i];
+    }
+    return bad;
+}
+
+static double orc_dot_d(int dim, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int i = 0; i < dim; i++) s += a[i] * b[i];
+    return s;
+}
+
+/* Adds v to the entry (row, col) of the DG system. */
+static void orc_dg_add(const int64_t *rowptr, const int32_t *colind, double *values, int64_t row, int64_t col,
+                       double v)
+{
+    values[orc_find(rowptr, colind, row, col)] += v;
+}
+
+/* The facet of cell K on side (r, side) with the tensor rule of k+1 points  */
+/* per tangential direction: for every point, the reference coordinates on   */
+/* K (xi_r = side) and on the neighbour (xi_r = 1 - side), and the weight.   */
+static int orc_face_points(int dim, int k, int r, int side, double (*xiK)[3], double (*xiL)[3], double *wq)
+{
+    double gx[ORC_MAXQ1], gw[ORC_MAXQ1];
+    orc_gauss_legendre(k + 1, gx, gw);
+    int tang[2], nt = 0;
+    for (int s = 0; s < dim; s++)
+        if (s != r) tang[nt++] = s;
+    int np = dim == 3 ? (k + 1) * (k + 1) : k + 1;
+    for (int q = 0; q < np; q++) {
+        int q0 = q % (k + 1), q1 = q / (k + 1);
+        for (int s = 0; s < 3; s++) xiK[q][s] = xiL[q][s] = 0.0;
+        xiK[q][tang[0]] = xiL[q][tang[0]] = gx[q0];
+        wq[q] = gw[q0];
+        if (nt == 2) {
+            xiK[q][tang[1]] = xiL[q][tang[1]] = gx[q1];
+            wq[q] *= gw[q1];
+        }
+        xiK[q][r] = side ? 1.0 : 0.0;
+        xiL[q][r] = side ? 0.0 : 1.0;
+    }
+    return np;
+}
+
+/* DG system of -Laplace(u) = f with weak Dirichlet data on the whole        */
+/* boundary (values and rhs overwritten).  Volume terms: the Poisson element */
+/* matrix with coefficient 1 and the load of the problem.  Interior facet    */
+/* between K- (this cell) and K+ = its neighbour on side (r, +), unit normal */
+/* n outward of K-, sigma = gamma / h_F; with s(K-) = +1, s(K+) = -1 the    */
+/* jump of phi from side i is s_i phi n and the mean of grad phi is half of  */
+/* it, so test row a of side i, trial column b of side j get                 */
+/*   sum_q W_q [ -s_i phi_a (n.grad phi_b)/2 - tau s_j phi_b (n.grad phi_a)/2 */
+/*               + sigma s_i s_j phi_a phi_b ].                              */
+/* Boundary facet of K with outward unit normal n:                           */
+/*   A_ab += sum W [ -phi_a n.grad phi_b - tau phi_b n.grad phi_a + sigma phi_a phi_b ] */
+/*   rhs_a += sum W [ -tau u_D n.grad phi_a + sigma u_D phi_a ].             */
+/* Order: cells ascending (volume), then every cell's interior facets on    */
+/* its + sides (axis ascending), then the boundary facets (cell ascending,  */
+/* face 2r + side).  Returns -1 if a det J <= 0 was met.                     */
+int orc_dg_assemble(const orc_problem *P, const double *vxyz, double gamma, double tau, const int64_t *rowptr,
+                    const int32_t *colind, double *values, double *rhs)
+{
+    int dim = P->dim, k = P->k;
+    int nn = ipow(k + 1, dim);
+    int64_t ncells = (int64_t)P->n[0] * P->n[1] * (dim == 3 ? P->n[2] : 1);
+    int64_t nrows = ncells * nn;
+    double *A = (double *)malloc(sizeof(double) * nn * nn);
+    double *f = (double *)malloc(sizeof(double) * nn);
+    double *phiK = (double *)malloc(sizeof(double) * nn), *phiL = (double *)malloc(sizeof(double) * nn);
+    double *gK = (double *)malloc(sizeof(double) * nn * dim), *gL = (double *)malloc(sizeof(double) * nn * dim);
+    double (*xiK)[3] = malloc(sizeof(double[3]) * ORC_MAXQ1 * ORC_MAXQ1);
+    double (*xiL)[3] = malloc(sizeof(double[3]) * ORC_MAXQ1 * ORC_MAXQ1);
+    double *wq = (double *)malloc(sizeof(double) * ORC_MAXQ1 * ORC_MAXQ1);
+    double X[24], XL[24];
+    int bad = 0;
+    memset(values, 0, sizeof(double) * rowptr[nrows]);
+    memset(rhs, 0, sizeof(double) * nrows);
+    for (int64_t K = 0; K < ncells; K++) {
+        orc_cell_vertices(dim, P->n, vxyz, K, X);
+        if (orc_element_matrix(dim, k, 0, X, 1.0, 0.0, 0.0, A) != 0) bad = 1;
+        orc_element_load(dim, k, 1, X, P->source_kind, P->source, f);
+        for (int a = 0; a < nn; a++) {
+            for (int b = 0; b < nn; b++) orc_dg_add(rowptr, colind, values, K * nn + a, K * nn + b, A[a * nn + b]);
+            rhs[K * nn + a] += f[a];
+        }
+    }
+    /* interior facets */
+    for (int64_t K = 0; K < ncells; K++)
+        for (int r = 0; r < dim; r++) {
+            int64_t L = orc_dg_neighbour(P->n, dim, K, r, 1);
+            if (L < 0) continue;
+            orc_cell_vertices(dim, P->n, vxyz, K, X);
+            orc_cell_vertices(dim, P->n, vxyz, L, XL);
+            int np = orc_face_points(dim, k, r, 1, xiK, xiL, wq);
+            double area = 0.0;
+            for (int q = 0; q < np; q++) {
+                double x[3], nv[3];
+                orc_face_side(dim, k, X, xiK[q], r, phiK, gK, x, nv);
+                area += wq[q] * sqrt(orc_dot_d(dim, nv, nv));
+            }
+            double hF = dim == 3 ? sqrt(area) : area;
+            double sigma = gamma / hF;
+            for (int q = 0; q < np; q++) {
+                double xK[3], xL[3], nvK[3], nvL[3];
+                if (orc_face_side(dim, k, X, xiK[q], r, phiK, gK, xK, nvK)) bad = 1;
+                if (orc_face_side(dim, k, XL, xiL[q], r, phiL, gL, xL, nvL)) bad = 1;
+                double dS = sqrt(orc_dot_d(dim, nvK, nvK));
+                double n[3] = {0, 0, 0};
+                for (int i = 0; i < dim; i++) n[i] = nvK[i] / dS;
+                double W = wq[q] * dS;
+                /* sides: 0 = K (s = +1), 1 = L (s = -1) */
+                const double *ph[2] = {phiK, phiL}, *gr[2] = {gK, gL};
+                int64_t base[2] = {K * nn, L * nn};
+                double sg[2] = {1.0, -1.0};
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 2; j++)
+                        for (int a = 0; a < nn; a++) {
+                            double dna = orc_dot_d(dim, n, gr[i] + a * dim);
+                            for (int b = 0; b < nn; b++) {
+                                double dnb = orc_dot_d(dim, n, gr[j] + b * dim);
+                                double v = -sg[i] * ph[i][a] * dnb * 0.5 - tau * sg[j] * ph[j][b] * dna * 0.5 +
+                                           sigma * sg[i] * sg[j] * ph[i][a] * ph[j][b];
+                                orc_dg_add(rowptr, colind, values, base[i] + a, base[j] + b, W * v);
+                            }
+                        }
+            }
+        }
+    /* boundary facets */
+    for (int64_t K = 0; K < ncells; K++)
+        for (int r = 0; r < dim; r++)
+            for (int side = 0; side < 2; side++) {
+                if (orc_dg_neighbour(P->n, dim, K, r, side) >= 0) continue;
+                orc_cell_vertices(dim, P->n, vxyz, K, X);
+                int np = orc_face_points(dim, k, r, side, xiK, xiL, wq);
+                double area = 0.0;
+                for (int q = 0; q < np; q++) {
+                    double x[3], nv[3];
+                    orc_face_side(dim, k, X, xiK[q], r, phiK, gK, x, nv);
+                    area += wq[q] * sqrt(orc_dot_d(dim, nv, nv));
+                }
+                double hF = dim == 3 ? sqrt(area) : area;
+                double sigma = gamma / hF;
+                for (int q = 0; q < np; q++) {
+                    double x[3], nv[3];
+                    if (orc_face_side(dim, k, X, xiK[q], r, phiK, gK, x, nv)) bad = 1;
+                    double dS = sqrt(orc_dot_d(dim, nv, nv));
+                    double n[3] = {0, 0, 0};
+                    for (int i = 0; i < dim; i++) n[i] = (side ? 1.0 : -1.0) * nv[i] / dS;  /* outward */
+                    double W = wq[q] * dS;
+                    double uD = orc_dirichlet_value(P->dirichlet_kind, P->dirichlet_affine, dim, x, 0);
+                    for (int a = 0; a < nn; a++) {
+                        double dna = orc_dot_d(dim, n, gK + a * dim);
+                        for (int b = 0; b < nn; b++) {
+                            double dnb = orc_dot_d(dim, n, gK + b * dim);
+                            double v = -phiK[a] * dnb - tau * phiK[b] * dna + sigma * phiK[a] * phiK[b];
+                            orc_dg_add(rowptr, colind, values, K * nn + a, K * nn + b, W * v);
+                        }
+                        rhs[K * nn + a] += W * (-tau * uD * dna + sigma * uD * phiK[a]);
+                    }
+                }
+            }
+    free(A);
+    free(f);
+    free(phiK);
+    free(phiL);
+    free(gK);
+    free(gL);
+    free(xiK);
+    free(xiL);
+    free(wq);
+    return bad ? -1 : 0;
+}

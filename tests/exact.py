@@ -121,3 +121,79 @@ def affine_element(dim, k, B, problem="poisson", coef=1.0, lam=0.0, mu=0.0):
 def mass_1d_load(k):
     """int l_i over [0,1] (exact)."""
     return np.array([float(int01(p)) for p in lagrange_polys(k)])
+
+
+def lagrange_end_values(k):
+    """(l_i(0), l_i(1), l_i'(0), l_i'(1)) for the equidistant Lagrange basis, exact."""
+    P = lagrange_polys(k)
+    v0 = [polyval(p, Fr(0)) for p in P]
+    v1 = [polyval(p, Fr(1)) for p in P]
+    d0 = [polyval(polyder(p), Fr(0)) for p in P]
+    d1 = [polyval(polyder(p), Fr(1)) for p in P]
+    return v0, v1, d0, d1
+
+
+def dg_box_matrix(dim, k, n, gamma, tau):
+    """The symmetric-interior-penalty DG matrix of -Laplace on the Cartesian
+    brick of n[r] equal cells per axis of [0,1]^d (cell sides h_r = 1/n_r),
+    DOF K nn + a, assembled from exact per-axis factors: a facet term is the
+    Kronecker product of h_s M over the tangential axes with, across the
+    normal axis r, the 1D endpoint factor of the facet's three terms
+      - s_i l_a(e_i) n.l_b'(e_j) / (2 h_r) - tau s_j l_b(e_j) n.l_a'(e_i) / (2 h_r)
+      + sigma s_i s_j l_a(e_i) l_b(e_j),  sigma = gamma / h_F,
+    e_i the end of cell i at the facet, s = +1 (lower cell) / -1 (upper cell),
+    h_F = h_s (2D) or sqrt(h_s h_t) (3D); boundary facets take s = 1 and the
+    outward sign of the normal derivative, without the halves."""
+    S, M, C = matrices_1d(k)
+    v0, v1, d0, d1 = [np.array([float(t) for t in arr]) for arr in lagrange_end_values(k)]
+    h = [1.0 / n[r] for r in range(dim)]
+    nn = (k + 1) ** dim
+    ncells = int(np.prod(n[:dim]))
+    A = np.zeros((ncells * nn, ncells * nn))
+
+    def cell_index(ci):
+        return ci[0] + n[0] * (ci[1] + (n[1] * ci[2] if dim == 3 else 0))
+
+    def face_block(r, normal_factor):
+        facs = []
+        for s_ in range(dim):
+            facs.append(normal_factor if s_ == r else h[s_] * M)
+        return kron_axes(facs)
+
+    def sigma(r):
+        tang = [h[s_] for s_ in range(dim) if s_ != r]
+        hF = tang[0] if dim == 2 else np.sqrt(tang[0] * tang[1])
+        return gamma / hF
+
+    for K in range(ncells):
+        ci = [K % n[0], (K // n[0]) % n[1], K // (n[0] * n[1]) if dim == 3 else 0][:dim]
+        # volume: sum over axes of (S / h_r^2) on axis r and M on the others, times the cell volume
+        vol = np.zeros((nn, nn))
+        for r in range(dim):
+            facs = [(S / h[r] ** 2 if s_ == r else M) for s_ in range(dim)]
+            vol += kron_axes(facs)
+        A[K * nn:(K + 1) * nn, K * nn:(K + 1) * nn] += vol * np.prod(h)
+        for r in range(dim):
+            sg = sigma(r)
+            # upper side of K along r: interior facet with the neighbour, or boundary
+            if ci[r] + 1 < n[r]:
+                cj = list(ci)
+                cj[r] += 1
+                L = cell_index(cj)
+                ends = {0: (v1, d1), 1: (v0, d0)}  # K sees the facet at 1, L at 0
+                sgn = {0: 1.0, 1: -1.0}
+                idx = {0: K, 1: L}
+                for i in (0, 1):
+                    for j in (0, 1):
+                        vi, di = ends[i]
+                        vj, dj = ends[j]
+                        fac = (-sgn[i] * np.outer(vi, dj) / (2 * h[r]) - tau * sgn[j] * np.outer(di, vj) / (2 * h[r])
+                               + sg * sgn[i] * sgn[j] * np.outer(vi, vj))
+                        A[idx[i] * nn:(idx[i] + 1) * nn, idx[j] * nn:(idx[j] + 1) * nn] += face_block(r, fac)
+            else:
+                fac = -np.outer(v1, d1) / h[r] - tau * np.outer(d1, v1) / h[r] + sg * np.outer(v1, v1)
+                A[K * nn:(K + 1) * nn, K * nn:(K + 1) * nn] += face_block(r, fac)
+            if ci[r] == 0:  # lower boundary: outward normal -e_r
+                fac = np.outer(v0, d0) / h[r] + tau * np.outer(d0, v0) / h[r] + sg * np.outer(v0, v0)
+                A[K * nn:(K + 1) * nn, K * nn:(K + 1) * nn] += face_block(r, fac)
+    return A

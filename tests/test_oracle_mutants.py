@@ -14,6 +14,7 @@ import pytest
 
 import oracle as O
 from oracle import build as OB
+from tests import test_oracle_dg as DG
 from tests import test_oracle_pins as PINS
 
 MUTANTS = {
@@ -31,6 +32,13 @@ MUTANTS = {
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
     "geometry_derivative_sign": ("if (r == s) g *= vr ? 1.0 : -1.0;", "if (r == s) g *= vr ? -1.0 : 1.0;"),
     "l2_error_without_sqrt": ("return sqrt(err2);", "return err2;"),
+    "dg_mean_without_half": ("double v = -sg[i] * ph[i][a] * dnb * 0.5 - tau",
+                             "double v = -sg[i] * ph[i][a] * dnb - tau"),
+    "dg_boundary_normal_inward": ("n[i] = (side ? 1.0 : -1.0) * nv[i] / dS;  /* outward */",
+                                  "n[i] = nv[i] / dS;  /* outward */"),
+    "dg_penalty_not_scaled_by_facet_size": ("            double sigma = gamma / hF;\n            for (int q = 0; q < np; q++) {\n                double xK[3]",
+                                            "            double sigma = gamma;\n            for (int q = 0; q < np; q++) {\n                double xK[3]"),
+    "dg_boundary_load_tau_sign": ("rhs[K * nn + a] += W * (-tau * uD * dna", "rhs[K * nn + a] += W * (tau * uD * dna"),
     "l2_error_dropped_weight": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                 "err2 += fabs(qp.detJ) * (ue - uh) * (ue - uh);"),
     "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
@@ -52,6 +60,8 @@ PIN_CALLS = [
     lambda: PINS.test_l2_norm_of_sine_product_closed_form(2, 2, 6, 0.2),
     lambda: PINS.test_l2_norm_of_affine_field_is_exact(3, 1, 3, 0.2),
     lambda: PINS.test_l2_norm_of_vector_field_sums_components(),
+    lambda: DG.test_dg_box_matrix_closed_form(2, [3, 2], 3, 1.0),
+    lambda: DG.test_dg_linear_patch_test(2, [3, 4], 1),
 ]
 
 
