@@ -410,6 +410,120 @@ def c3_precision(F, torch, orders=("c3q2", "c3q3", "c3q4"), precisions=("fp32", 
     return out
 
 
+DG_WORKLOAD = dict(dim=3, n=48, k=2, gamma=36.0, tau=1.0, rtol=1e-8,
+                   text="interior-penalty DG (symmetric, tau = 1, gamma = 4 (k+1)^2 = 36) for -Laplace(u) = f on "
+                        "the unit cube, 48^3 Q2 hexes jittered +-0.2h (seed 17080), f = 3 pi^2 prod sin(pi x_r), "
+                        "u = 0 imposed weakly on the boundary, FP64 assembly + Jacobi-PCG to rtol 1e-8")
+
+
+def dg_facet_bytes(n_rows, nnz, ncells, nn):
+    """Algorithmic bytes of one launch of the DG cell kernel: the values of
+    every row written once (8 nnz), the volume element matrices and loads read
+    (8 ncells nn^2 + 8 n), rhs and dinv written (16 n), one row pointer per
+    cell read (8 ncells).  The diagonal block's facet updates re-touch bytes
+    the same workgroup has just written (an L2 hit), not counted."""
+    return 8 * nnz + 8 * ncells * nn * nn + 8 * n_rows + 16 * n_rows + 8 * ncells
+
+
+def dg_cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=16, cg_its=100):
+    """The oracle's DG assembly (single thread, the parity build) and its
+    all-cores CG on the DG system of an n^3 mesh of the same recipe, scaled to
+    the full workload like the main baseline: cells x assembly time per cell
+    + the GPU's iterations x CG time per iteration x nnz ratio."""
+    import oracle as O
+    from fe_inputs import structured_vertices
+    dim, k = wl["dim"], wl["k"]
+    P = O.Problem(dim, [n] * dim, k, source_kind=2, source=(1.0,))
+    v = structured_vertices(dim, n, jitter=0.2)
+    t0 = time.perf_counter()
+    D = O.DGSystem(P, v, gamma=wl["gamma"], tau=wl["tau"])
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = O.omp_pcg(D.rowptr, D.colind, D.values, D.rhs, 0.0, cg_its)
+    t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
+    step = t_asm / P.ncells * ncells_full + t_it * (nnz_full / D.nnz) * gpu_iters
+    return {"value": 1.0 / step, "unit": "solves/s", "cores": O.omp_threads(), "kind": "oracle",
+            "sample": f"oracle (C, FP64) DG system at {n}^3 Q{k} ({P.ncells} cells, nnz {D.nnz}): pattern + "
+                      f"assembly single-threaded ({t_asm:.2f} s, the pattern included), {res['iters']} CG "
+                      f"iterations on all cores ({t_it * 1e3:.2f} ms each); the full solve scaled as cells x "
+                      f"assembly time per cell + {gpu_iters:.0f} iterations x per-iteration time x nnz ratio",
+            "step_s_scaled": step}
+
+
+def dg_form(args, F, torch, steps=3, warmup=1):
+    """The DG workload: a step is the DG assembly (volume integration + the
+    cell kernel with the facet terms) + Jacobi-PCG through the CSR SpMV,
+    the pattern built once before timing.  Kernel times from HIP events on
+    the step's stream."""
+    from fe_inputs import structured_vertices
+    wl = DG_WORKLOAD
+    dim, n, k = wl["dim"], wl["n"], wl["k"]
+    v = structured_vertices(dim, n, jitter=0.2)
+    mesh = F.create_mesh(dim, [n] * dim, v)
+    coeff = F.make_coeff("poisson", "fp64", source_kind=2, source=(1.0,), dim=dim)
+    A = F.DGAssembly(mesh, k, coeff, wl["gamma"], wl["tau"])
+    ws = torch.empty(F.pcg_query(A.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ncells, nn = n ** dim, (k + 1) ** dim
+    torch.cuda.synchronize()
+    print(f"[bench] DG form: cells={ncells} rows={A.n_rows} nnz={A.nnz}", file=sys.stderr, flush=True)
+
+    def step():
+        A.assemble(stream)
+        x.zero_()
+        return F.pcg_solve(A.csr, A.rhs, x, wl["rtol"], 100000, ws, stream)
+
+    for _ in range(warmup):
+        info = step()
+    F.set_timing(True)
+    F.get_timing(reset=True)
+    torch.cuda.synchronize()
+    lat, iters = [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        info = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        iters.append(info["iters"])
+        print(f"[bench] DG step {i}: {lat[-1] * 1e3:.1f} ms, {info['iters']} iterations", file=sys.stderr,
+              flush=True)
+    total = time.perf_counter() - t0
+    tm = F.get_timing(reset=True)
+    F.set_timing(False)
+    assert F.get_status(mesh) == F.FE_OK
+    facet_s = tm["scatter_ms"] / max(tm["scatter_calls"], 1) * 1e-3
+    k3_s = tm["integrate_ms"] / max(tm["integrate_calls"], 1) * 1e-3
+    spmv_s = tm["spmv_ms"] / max(tm["spmv_calls"], 1) * 1e-3
+    fb = dg_facet_bytes(A.n_rows, A.nnz, ncells, nn)
+    sb = spmv_bytes(A.n_rows, A.nnz, "csr")
+    mode, rpw, _ = F.spmv_plan_of(A.n_rows, A.nnz)
+    out = {
+        "workload": wl["text"], "cells": ncells, "dofs": A.n_rows, "nnz": A.nnz, "steps": steps,
+        "solves_per_s": steps / total, "ms_per_step": total / steps * 1e3,
+        "p50_ms": statistics.median(lat) * 1e3, "pcg_iters": statistics.mean(iters),
+        "relres": info["relres"], "true_relres": info["true_relres"],
+        "assembly": {"integrate_ms": k3_s * 1e3, "dg_cell_kernel_ms": facet_s * 1e3,
+                     "elements_per_s": ncells / (k3_s + facet_s)},
+        "roofline_dg_cell_kernel": {"kernel": "dg_cell_kernel<3,2>", "bound": "hbm", "achieved": fb / facet_s / 1e9,
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": fb / facet_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": fb,
+                                    "avg_launch_us": facet_s * 1e6, "timed_launches": tm["scatter_calls"],
+                                    "traffic": traffic_for("dg_cell_kernel", "dg_q2_48")},
+        "roofline_spmv": {"kernel": "pcg_spmv_kernel/csr", "plan": {"mode": mode, "rows_per_wave": rpw},
+                          "bound": "hbm", "achieved": sb / spmv_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": sb / spmv_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": sb,
+                          "avg_launch_us": spmv_s * 1e6, "timed_launches": tm["spmv_calls"]},
+    }
+    del A, ws, x
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle's DG system on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = dg_cpu_baseline(wl, statistics.mean(iters), ncells, out["nnz"])
+    return out
+
+
 def peak_probe(torch):
     """Achievable rates of this GPU, measured, to set the published peaks the
     roofline uses in context: a 1 GiB device copy and a 4 GiB read (a sum) in
@@ -632,7 +746,7 @@ def main():
                     help="thin the stream to requests of at most this many unknowns (default: every request)")
     ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision"],
+    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg"],
                     help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -670,6 +784,10 @@ def main():
     if args.form == "serve":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "serve", **serve_form(args, F, torch)}), flush=True)
+        return
+    if args.form == "dg":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "dg", **dg_form(args, F, torch)}), flush=True)
         return
     if args.form == "precision":
         torch.cuda.set_device(0)
@@ -811,6 +929,8 @@ def main():
             out["forms"]["batch"] = batch_form(args, F, torch)
         if args.serve_requests > 0:
             out["forms"]["serve"] = serve_form(args, F, torch)
+        print("[bench] DG form", file=sys.stderr, flush=True)
+        out["forms"]["dg"] = dg_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, out["config"]["nnz"])

@@ -207,6 +207,56 @@ fe_status fe_permutation(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int
 fe_status fe_get_status(fe_mesh mesh);
 
 /* ------------------------------------------------------------------------ */
+/* Interior-penalty discontinuous Galerkin (Sect. 3.12 eq. ip_dg_formulations, */
+/* facet matrices of eq. local_to_face_matrix, facet integration Sect. 3.13) */
+/* ------------------------------------------------------------------------ */
+/* The DG form of -Laplace(u) = f on the brick, with coefficient 1 (the cell
+ * coefficients of the mesh are not used):
+ *   sum_K int_K grad u . grad v
+ *   + sum_F int_F ( -{grad u}.[v] - tau {grad v}.[u] + sigma_F [u].[v] ),
+ * where F runs over interior and boundary facets, [w] = w^- n^- + w^+ n^+
+ * (w n on the boundary), {g} is the mean (g itself on the boundary),
+ * sigma_F = gamma / h_F, h_F = |F|^(1/(d-1)) (facet length in 2D, square
+ * root of the facet area in 3D).  Dirichlet data u_D (coeff->dirichlet_kind,
+ * dirichlet_affine) is imposed weakly on every boundary facet: the rhs holds
+ *   sum_K int_K f v + sum_{F boundary} int_F u_D (-tau grad v . n + sigma_F v).
+ * tau = 1 gives the symmetric method (SPD for gamma large enough, e.g.
+ * 4 (k+1)^2 on a mildly distorted brick), tau = -1 the nonsymmetric one and
+ * tau = 0 the incomplete one.
+ * Space: Q_k per cell (order 1..4), no DOF shared, DOF(K, a) = K nn + a with
+ * nn = (k+1)^d and the local node order of the conforming space; every DOF
+ * is a row (no fixed DOFs).  Row K nn + a holds the nn columns of K and of
+ * each facet neighbour of K, cells in ascending id order.
+ * Quadrature: (k+1)^d Gauss points per cell, (k+1)^(d-1) per facet. */
+
+/* Rows, nonzeros and workspace bytes (volume element matrices and loads) of
+ * the DG system of (mesh, order).  FE_EINVAL for a null mesh, order outside
+ * 1..4 or 2^31 rows or more.  Host only. */
+fe_status fe_dg_query(fe_mesh mesh, int32_t order, int64_t *n_rows, int64_t *nnz, size_t *ws_bytes);
+
+/* Pattern of the DG system into out->rowptr (n_rows + 1, int64) and
+ * out->colind (nnz, int32), device memory owned by the caller; out->n_rows
+ * and out->nnz must equal fe_dg_query's.  Enqueues only. */
+fe_status fe_dg_pattern(fe_mesh mesh, int32_t order, fe_csr *out, fe_stream stream);
+
+/* Numeric phase: volume element matrices and loads into ws (the integration
+ * kernels of fe_integrate, coefficient 1, FP64), then one workgroup per cell
+ * writes the values of the cell's rows: the volume block plus, for each
+ * facet, its two facet matrices with the cell on the row side, and the
+ * facet terms of the rhs; dinv = 1 / diagonal.  No atomics: bitwise
+ * reproducible; for tau = 1 the off-diagonal blocks of the two cells of a
+ * facet are transposes of each other to the last bit.
+ * out->rowptr must hold fe_dg_pattern's pattern (colind is not read).
+ * coeff: problem FE_POISSON, precision FE_FP64, source_kind / source and
+ * dirichlet_kind / dirichlet_affine as for fe_assemble, dirichlet_faces all
+ * 2 dim bits set; young / poisson_ratio unused.  gamma > 0, tau finite.
+ * FE_EINVAL otherwise or for a workspace smaller than fe_dg_query's.
+ * Enqueues only; det J <= 0 at a volume or facet point is reported by the
+ * next fe_get_status.  The system is solved by fe_pcg_solve (tau = 1). */
+fe_status fe_dg_assemble(fe_mesh mesh, int32_t order, const fe_coeff *coeff, double gamma, double tau,
+                         fe_csr *out, void *ws, size_t ws_bytes, fe_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Solve                                                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -387,6 +437,29 @@ fe_status fe_spmv_autotune_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coe
 fe_status fe_spmv_plan_of_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_spmv_plan *plan,
                                int32_t *row_class);
 fe_status fe_spmv_plan_set_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coeff, const fe_spmv_plan *plan);
+/* Tile shapes of the matrix-core element integration (3D, orders 2..4): the
+ * node-tile pairs each wave accumulates (the workgroups per cell follow).
+ * Every shape sums each element-matrix entry over the quadrature points in
+ * the same order, so element matrices are bitwise the same for every shape.
+ * fe_integrate_autotune times each candidate shape of the class (order,
+ * problem, precision) of (mesh, order, coeff) with reps K3 launches into ws
+ * (the workspace of fe_assemble_query, whose element matrices it overwrites)
+ * and makes the fastest the shape of the class in this process (single and
+ * batched assembly).  tried: host, up to max_tried entries (us = mean launch
+ * time); chosen: host.  Synchronizes.  FE_EINVAL for spaces without
+ * matrix-core integration (2D, Q1).  fe_integrate_plan_of reports the shape
+ * a class gets now (pairs_per_wave 0: not a matrix-core class).
+ * fe_spmv_tuning_reset also forgets the tuned shapes. */
+typedef struct {
+    int32_t pairs_per_wave;
+    int32_t parts;  /* workgroups per cell */
+    double us;
+} fe_k3_plan;
+fe_status fe_integrate_autotune(fe_mesh mesh, int32_t order, const fe_coeff *coeff, void *ws, size_t ws_bytes,
+                                int32_t reps, fe_k3_plan *tried, int32_t max_tried, int32_t *n_tried,
+                                fe_k3_plan *chosen, fe_stream stream);
+fe_status fe_integrate_plan_of(fe_mesh mesh, int32_t order, const fe_coeff *coeff, fe_k3_plan *plan);
+
 /* The plan a matrix of n_rows rows and nnz entries gets now, and its class. */
 fe_status fe_spmv_plan_of(int64_t n_rows, int64_t nnz, fe_spmv_plan *plan, int32_t *row_class);
 /* Makes `plan` (mode and rows_per_wave of one of the CSR plans fe_spmv_autotune

@@ -351,6 +351,41 @@ fe_status fe_integrate(fe_mesh m, int32_t order, const fe_coeff *c, void *ws, si
     return st;
 }
 
+fe_status fe_integrate_autotune(fe_mesh m, int32_t order, const fe_coeff *c, void *ws, size_t ws_bytes, int32_t reps,
+                                fe_k3_plan *tried, int32_t max_tried, int32_t *n_tried, fe_k3_plan *chosen,
+                                fe_stream stream)
+{
+    if (reps < 1 || max_tried < 0 || (max_tried > 0 && !tried)) return set_error(FE_EINVAL, "bad reps/max_tried");
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    const SpaceArgs &sa = m->space.args;
+    if (sa.dim != 3 || order < 2) return set_error(FE_EINVAL, "no tile shapes to tune for this space");
+    const ElemLayout el = elem_layout(sa, c->precision);
+    if (!ws || ws_bytes < el.total) return set_error(FE_EINVAL, "workspace too small (see fe_assemble_query)");
+    RefTables rt;
+    ref_tables(order, rt);
+    m->last_stream = as_stream(stream);
+    int nt = 0;
+    st = integrate_autotune(sa, mesh_args(m), problem_args(c), rt, ws,
+                            reinterpret_cast<double *>(static_cast<char *>(ws) + el.f_offset), reps, tried, max_tried,
+                            &nt, chosen, as_stream(stream));
+    if (n_tried) *n_tried = nt;
+    return st;
+}
+
+fe_status fe_integrate_plan_of(fe_mesh m, int32_t order, const fe_coeff *c, fe_k3_plan *plan)
+{
+    if (!plan) return set_error(FE_EINVAL, "null plan");
+    fe_status st = check_coeff(m, order, c);
+    if (st != FE_OK) return st;
+    st = ensure_space(m, order, c);
+    if (st != FE_OK) return st;
+    integrate_plan_of(m->space.args, problem_args(c), plan);
+    return FE_OK;
+}
+
 fe_status fe_scatter(fe_mesh m, int32_t order, const fe_coeff *c, fe_csr *out, const void *ws, size_t ws_bytes,
                      fe_stream stream)
 {
@@ -565,6 +600,83 @@ fe_status fe_assemble_batch(int32_t nprob, const fe_mesh *meshes, const int32_t 
     return FE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Interior-penalty discontinuous Galerkin (fe_dg.hip)
+// ---------------------------------------------------------------------------
+static fe_status dg_check(fe_mesh m, int32_t order, int64_t &n_rows, int64_t &nnz)
+{
+    if (!m) return set_error(FE_EINVAL, "null mesh");
+    if (order < 1 || order > kMaxOrder) return set_error(FE_EINVAL, "order must be in 1..4");
+    dg_sizes(m->dim, m->n, order, n_rows, nnz);
+    if (n_rows >= (int64_t(1) << 31)) return set_error(FE_EINVAL, "too many rows for int32 column indices");
+    return FE_OK;
+}
+
+fe_status fe_dg_query(fe_mesh m, int32_t order, int64_t *n_rows, int64_t *nnz, size_t *ws_bytes)
+{
+    int64_t nr, nz;
+    fe_status st = dg_check(m, order, nr, nz);
+    if (st != FE_OK) return st;
+    if (n_rows) *n_rows = nr;
+    if (nnz) *nnz = nz;
+    if (ws_bytes) *ws_bytes = elem_layout(dg_space(m->dim, m->n, order), FE_FP64).total;
+    return FE_OK;
+}
+
+fe_status fe_dg_pattern(fe_mesh m, int32_t order, fe_csr *out, fe_stream stream)
+{
+    int64_t nr, nz;
+    fe_status st = dg_check(m, order, nr, nz);
+    if (st != FE_OK) return st;
+    if (!out) return set_error(FE_EINVAL, "null csr");
+    if (out->n_rows != nr || out->nnz != nz) return set_error(FE_EINVAL, "csr sizes differ from fe_dg_query");
+    if (!out->rowptr || !out->colind) return set_error(FE_EINVAL, "null rowptr/colind");
+    m->last_stream = as_stream(stream);
+    return launch_dg_pattern(m->dim, m->n, order, out->rowptr, out->colind, as_stream(stream));
+}
+
+fe_status fe_dg_assemble(fe_mesh m, int32_t order, const fe_coeff *c, double gamma, double tau, fe_csr *out,
+                         void *ws, size_t ws_bytes, fe_stream stream)
+{
+    int64_t nr, nz;
+    fe_status st = dg_check(m, order, nr, nz);
+    if (st != FE_OK) return st;
+    if (!c) return set_error(FE_EINVAL, "null coeff");
+    if (c->problem != FE_POISSON) return set_error(FE_EINVAL, "the DG form is built for the Poisson problem only");
+    if (c->precision != FE_FP64) return set_error(FE_EINVAL, "the DG form is assembled in FP64 only");
+    if (c->source_kind < FE_SOURCE_NONE || c->source_kind > FE_SOURCE_SINPROD)
+        return set_error(FE_EINVAL, "unknown source kind");
+    if (c->dirichlet_kind != FE_DIRICHLET_ZERO && c->dirichlet_kind != FE_DIRICHLET_AFFINE)
+        return set_error(FE_EINVAL, "unknown dirichlet kind");
+    if (c->dirichlet_faces != (1u << (2 * m->dim)) - 1u)
+        return set_error(FE_EINVAL, "the DG form imposes Dirichlet data weakly on every boundary face");
+    if (!(gamma > 0.0) || !std::isfinite(gamma) || !std::isfinite(tau))
+        return set_error(FE_EINVAL, "gamma must be positive and finite, tau finite");
+    if (!out) return set_error(FE_EINVAL, "null csr");
+    if (out->n_rows != nr || out->nnz != nz) return set_error(FE_EINVAL, "csr sizes differ from fe_dg_query");
+    if (!out->rowptr || !out->colind || !out->values || !out->rhs || !out->dinv)
+        return set_error(FE_EINVAL, "null csr array");
+    const SpaceArgs sa = dg_space(m->dim, m->n, order);
+    const ElemLayout el = elem_layout(sa, FE_FP64);
+    if (!ws || ws_bytes < el.total) return set_error(FE_EINVAL, "workspace too small (see fe_dg_query)");
+    RefTables rt;
+    ref_tables(order, rt);
+    ProblemArgs pa = problem_args(c);
+    MeshArgs ma = mesh_args(m);
+    ma.coef = nullptr;  // coefficient 1 in the volume term
+    hipStream_t s = as_stream(stream);
+    m->last_stream = s;
+    hipEvent_t t0 = timing_begin(s);
+    st = launch_integrate(sa, ma, pa, rt, el, ws, s);
+    timing_end(t0, kTimeIntegrate, s);
+    if (st != FE_OK) return st;
+    hipEvent_t t1 = timing_begin(s);
+    st = launch_dg_facets(m->dim, m->n, order, gamma, tau, ma, pa, el, ws, out->rowptr, out->values, out->rhs,
+                          out->dinv, s);
+    timing_end(t1, kTimeScatter, s);
+    return st;
+}
+
 fe_status fe_cell_dofs(fe_mesh m, int32_t order, const fe_coeff *c, int32_t *out, fe_stream stream)
 {
     fe_status st = check_coeff(m, order, c);
@@ -710,6 +822,7 @@ fe_status fe_spmv_plan_set_mesh(fe_mesh m, int32_t order, const fe_coeff *c, con
 fe_status fe_spmv_tuning_reset(void)
 {
     spmv_tuning_reset();
+    integrate_tuning_reset();
     return FE_OK;
 }
 

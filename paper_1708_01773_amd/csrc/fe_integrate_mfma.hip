@@ -19,6 +19,10 @@
 // A operand by ~h, the B operand additionally by 1/max_q w_q) so that they
 // sit near 1, and the result is unscaled exactly.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <type_traits>
+#include <vector>
 
 #include "fe_internal.h"
 
@@ -137,6 +141,17 @@ __device__ __forceinline__ void pair_tiles(int p, int NT, int &ta, int &tb)
     tb = ta + p;
 }
 
+// Elasticity entry from the accumulated products: lambda a12 + mu a21, plus
+// mu tr on the diagonal of a component block.  The roundings are fixed by
+// explicit fused multiply-adds, so that every tile shape's instantiation
+// gives the same bits (contraction left to the compiler can differ between
+// instantiations).
+__device__ __forceinline__ double el_value(double lambda, double mu, double a12, double a21, double tr, bool cdiag)
+{
+    const double v = __fma_rn(lambda, a12, mu * a21);
+    return cdiag ? __fma_rn(mu, tr, v) : v;
+}
+
 // One workgroup = 4 waves = (cell, part).  NNP = padded node count (multiple
 // of 16), PPW = max node-tile pairs per wave, QS = quadrature points per slab.
 template <class Pol, int PROB, int NNP, int PPW, int QS>
@@ -189,7 +204,7 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
         sD[tid] = rt.D[tid];
     }
     if (tid == 0) sBad = 0;
-    const double coef = m.coef[cell];
+    const double coef = m.coef ? m.coef[cell] : 1.0;
     __syncthreads();
     for (int q = tid; q < NQ; q += 256) {
         const int a0 = q % K1, a1 = (q / K1) % K1, a2 = q / (K1 * K1);
@@ -348,7 +363,7 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
                         const int b0 = q % K1, b1 = (q / K1) % K1, b2 = q / (K1 * K1);
                         const double phi = sL[n0 * K1 + b0] * sL[n1 * K1 + b1] * sL[n2 * K1 + b2];
                         const double xq[3] = {sXq[q][0], sXq[q][1], sXq[q][2]};
-                        facc[t] += sWd[q] * source_value_mf(p, xq, c) * phi;
+                        facc[t] = __fma_rn(sWd[q] * source_value_mf(p, xq, c), phi, facc[t]);
                     }
                 }
             }
@@ -383,8 +398,8 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
 #pragma unroll
                     for (int c2 = 0; c2 < DIM; c2++) {
                         if (row == col && c1 > c2) continue;
-                        double v = p.lambda * double(acc[t][c1 * DIM + c2][r]) + p.mu * double(acc[t][c2 * DIM + c1][r]);
-                        if (c1 == c2) v += p.mu * tr;
+                        const double v = el_value(p.lambda, p.mu, double(acc[t][c1 * DIM + c2][r]),
+                                                  double(acc[t][c2 * DIM + c1][r]), tr, c1 == c2);
                         const Out o = Out(v * unscale);
                         Ec[int64_t(row * NC + c1) * nloc + col * NC + c2] = o;
                         if (row != col || c1 != c2) Ec[int64_t(col * NC + c2) * nloc + row * NC + c1] = o;
@@ -419,17 +434,58 @@ __global__ __launch_bounds__(256, 2) void k3_mfma_batch_kernel(const AsmJob *__r
 }
 
 // ---------------------------------------------------------------------------
-// Launch: (order, problem) -> padded node count, pairs per wave, parts per cell
-// (measured: Q3 elasticity 3.75 ms with one pair per wave against 5.57 ms with
-// two, Q4 elasticity 9.0 ms with two against 9.7 ms with one; 32^3 and 24^3
-// cells)
+// Launch shapes: node-tile pairs per wave (PPW; parts per cell follow) for
+// (order, problem, precision).  Every shape sums each entry over the
+// quadrature points in the same order, so the element matrices do not depend
+// on it; the autotuner (fe_integrate_autotune) times the candidates of a
+// class and keeps the fastest for the process.  Defaults measured on 32^3 Q3
+// and 24^3 Q4 elasticity (Q3: 3.75 ms with one pair per wave against 5.57 ms
+// with two; Q4 BF16: 7.0 ms with two against 9.6 ms with one).  FP64 Q4
+// elasticity runs one pair per wave (10.0 ms): two need more than 256 VGPRs
+// and spill to private memory, and a variant of that kernel with more spills
+// gave element matrices that differed from run to run, so no kernel here
+// spills.
 // ---------------------------------------------------------------------------
+static std::mutex g_k3_mu;
+static std::map<int, int> g_k3_tuned;  // class -> pairs per wave
+
+static int k3_class(int k, bool el, int prec) { return (k * 2 + (el ? 1 : 0)) * 8 + prec; }
+
+static std::vector<int> k3_candidates(int k, bool el, int prec)
+{
+    if (k == 2) return {1};
+    if (k == 3) return el ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 3};
+    if (el) return prec == FE_FP64 ? std::vector<int>{1} : std::vector<int>{1, 2};
+    return {3, 5, 9};
+}
+
+static int k3_default(int k, bool el, int prec)
+{
+    if (k == 3) return el ? 1 : 3;
+    if (k == 4) return el ? (prec == FE_FP64 ? 1 : 2) : 9;
+    return 1;
+}
+
+static int k3_ppw(int k, bool el, int prec)
+{
+    std::lock_guard<std::mutex> lk(g_k3_mu);
+    auto it = g_k3_tuned.find(k3_class(k, el, prec));
+    return it != g_k3_tuned.end() ? it->second : k3_default(k, el, prec);
+}
+
+static int nnp_of(int k) { return k == 2 ? 32 : (k == 3 ? 64 : 128); }
+
+static int parts_of(int k, int ppw)
+{
+    const int nt = nnp_of(k) / 16, np = nt * (nt + 1) / 2;
+    return (np + 4 * ppw - 1) / (4 * ppw);
+}
+
 template <class Pol, int PROB, int NNP, int PPW, int QS>
 static fe_status launch_one(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
                             void *E, double *F, hipStream_t s)
 {
-    constexpr int NT = NNP / 16, NP = NT * (NT + 1) / 2;
-    const int parts = (NP + 4 * PPW - 1) / (4 * PPW);
+    const int parts = parts_of(sa.k, PPW);
     const int64_t grid = sa.ncells * parts;
     if (grid == 0) return FE_OK;
     hipLaunchKernelGGL((k3_mfma_kernel<Pol, PROB, NNP, PPW, QS>), dim3(grid), dim3(256), 0, s, sa, ma, pa, rt, parts,
@@ -438,32 +494,6 @@ static fe_status launch_one(const SpaceArgs &sa, const MeshArgs &ma, const Probl
     return FE_OK;
 }
 
-template <class Pol>
-static fe_status launch_pol(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
-                            void *E, double *F, hipStream_t s)
-{
-    constexpr int QS = Pol::KFAST ? 32 : 16;
-    const bool el = pa.problem == FE_ELASTICITY;
-    switch (sa.k) {
-        case 2: return el ? launch_one<Pol, 1, 32, 1, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 32, 1, QS>(sa, ma, pa, rt, E, F, s);
-        case 3: return el ? launch_one<Pol, 1, 64, 1, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 64, 3, QS>(sa, ma, pa, rt, E, F, s);
-        case 4: return el ? launch_one<Pol, 1, 128, 2, QS>(sa, ma, pa, rt, E, F, s) : launch_one<Pol, 0, 128, 9, QS>(sa, ma, pa, rt, E, F, s);
-        default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
-    }
-}
-
-fe_status launch_integrate_mfma(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
-                                void *E, double *F, hipStream_t s)
-{
-    switch (pa.precision) {
-        case FE_FP64: return launch_pol<PolF64>(sa, ma, pa, rt, E, F, s);
-        case FE_FP32: return launch_pol<PolF32>(sa, ma, pa, rt, E, F, s);
-        case FE_FP16: return launch_pol<PolF16>(sa, ma, pa, rt, E, F, s);
-        default: return launch_pol<PolBF16>(sa, ma, pa, rt, E, F, s);
-    }
-}
-
-// Batched: the class (precision, order, problem) is that of the host job h.
 template <class Pol, int PROB, int NNP, int PPW, int QS>
 static fe_status launch_batch_one(const AsmJob *jobs, const int32_t *boff, int njobs, int grid, hipStream_t s)
 {
@@ -473,46 +503,168 @@ static fe_status launch_batch_one(const AsmJob *jobs, const int32_t *boff, int n
     return FE_OK;
 }
 
-template <class Pol>
-static fe_status launch_batch_pol(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
-                                  hipStream_t s)
+// Calls body.template operator()<PROB, NNP, PPW>() for the class's shape.
+template <class Body>
+static fe_status with_shape(int k, bool el, int ppw, Body body)
 {
-    constexpr int QS = Pol::KFAST ? 32 : 16;
-    const bool el = h.p.problem == FE_ELASTICITY;
-    switch (h.s.k) {
-        case 2: return el ? launch_batch_one<Pol, 1, 32, 1, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 32, 1, QS>(jobs, boff, njobs, grid, s);
-        case 3: return el ? launch_batch_one<Pol, 1, 64, 1, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 64, 3, QS>(jobs, boff, njobs, grid, s);
-        case 4: return el ? launch_batch_one<Pol, 1, 128, 2, QS>(jobs, boff, njobs, grid, s) : launch_batch_one<Pol, 0, 128, 9, QS>(jobs, boff, njobs, grid, s);
-        default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
+    switch ((k * 2 + (el ? 1 : 0)) * 16 + ppw) {
+        case (2 * 2 + 0) * 16 + 1: return body.template operator()<0, 32, 1>();
+        case (2 * 2 + 1) * 16 + 1: return body.template operator()<1, 32, 1>();
+        case (3 * 2 + 0) * 16 + 1: return body.template operator()<0, 64, 1>();
+        case (3 * 2 + 0) * 16 + 2: return body.template operator()<0, 64, 2>();
+        case (3 * 2 + 0) * 16 + 3: return body.template operator()<0, 64, 3>();
+        case (3 * 2 + 1) * 16 + 1: return body.template operator()<1, 64, 1>();
+        case (3 * 2 + 1) * 16 + 2: return body.template operator()<1, 64, 2>();
+        case (4 * 2 + 0) * 16 + 3: return body.template operator()<0, 128, 3>();
+        case (4 * 2 + 0) * 16 + 5: return body.template operator()<0, 128, 5>();
+        case (4 * 2 + 0) * 16 + 9: return body.template operator()<0, 128, 9>();
+        case (4 * 2 + 1) * 16 + 1: return body.template operator()<1, 128, 1>();
+        case (4 * 2 + 1) * 16 + 2: return body.template operator()<1, 128, 2>();
+        default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4 and a candidate shape");
     }
 }
 
+// The shapes built for a precision: two pairs per wave at Q4 elasticity would
+// need more than 256 VGPRs in FP64 (private-memory spills), so that shape is
+// built for the 32-bit-accumulating precisions only.
+template <class Pol, int PROB, int NNP, int PPW>
+constexpr bool shape_built()
+{
+    return !(std::is_same<Pol, PolF64>::value && PROB == 1 && NNP == 128 && PPW == 2);
+}
+
+template <class Pol>
+struct SingleLaunch {
+    const SpaceArgs &sa;
+    const MeshArgs &ma;
+    const ProblemArgs &pa;
+    const RefTables &rt;
+    void *E;
+    double *F;
+    hipStream_t s;
+    template <int PROB, int NNP, int PPW>
+    fe_status operator()() const
+    {
+        if constexpr (shape_built<Pol, PROB, NNP, PPW>())
+            return launch_one<Pol, PROB, NNP, PPW, Pol::KFAST ? 32 : 16>(sa, ma, pa, rt, E, F, s);
+        else
+            return set_error(FE_EINVAL, "tile shape not built for this precision");
+    }
+};
+
+template <class Pol>
+struct BatchLaunch {
+    const AsmJob *jobs;
+    const int32_t *boff;
+    int njobs, grid;
+    hipStream_t s;
+    template <int PROB, int NNP, int PPW>
+    fe_status operator()() const
+    {
+        if constexpr (shape_built<Pol, PROB, NNP, PPW>())
+            return launch_batch_one<Pol, PROB, NNP, PPW, Pol::KFAST ? 32 : 16>(jobs, boff, njobs, grid, s);
+        else
+            return set_error(FE_EINVAL, "tile shape not built for this precision");
+    }
+};
+
+static fe_status launch_with(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                             void *E, double *F, hipStream_t s, int ppw)
+{
+    const bool el = pa.problem == FE_ELASTICITY;
+    if (sa.k < 2 || sa.k > 4) return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
+    switch (pa.precision) {
+        case FE_FP64: return with_shape(sa.k, el, ppw, SingleLaunch<PolF64>{sa, ma, pa, rt, E, F, s});
+        case FE_FP32: return with_shape(sa.k, el, ppw, SingleLaunch<PolF32>{sa, ma, pa, rt, E, F, s});
+        case FE_FP16: return with_shape(sa.k, el, ppw, SingleLaunch<PolF16>{sa, ma, pa, rt, E, F, s});
+        default: return with_shape(sa.k, el, ppw, SingleLaunch<PolBF16>{sa, ma, pa, rt, E, F, s});
+    }
+}
+
+fe_status launch_integrate_mfma(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                                void *E, double *F, hipStream_t s)
+{
+    return launch_with(sa, ma, pa, rt, E, F, s, k3_ppw(sa.k, pa.problem == FE_ELASTICITY, pa.precision));
+}
+
+// Batched: the class (precision, order, problem) is that of the host job h.
 fe_status launch_mfma_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
                             hipStream_t s)
 {
+    const bool el = h.p.problem == FE_ELASTICITY;
+    const int ppw = k3_ppw(h.s.k, el, h.p.precision);
     switch (h.p.precision) {
-        case FE_FP64: return launch_batch_pol<PolF64>(h, jobs, boff, njobs, grid, s);
-        case FE_FP32: return launch_batch_pol<PolF32>(h, jobs, boff, njobs, grid, s);
-        case FE_FP16: return launch_batch_pol<PolF16>(h, jobs, boff, njobs, grid, s);
-        default: return launch_batch_pol<PolBF16>(h, jobs, boff, njobs, grid, s);
+        case FE_FP64: return with_shape(h.s.k, el, ppw, BatchLaunch<PolF64>{jobs, boff, njobs, grid, s});
+        case FE_FP32: return with_shape(h.s.k, el, ppw, BatchLaunch<PolF32>{jobs, boff, njobs, grid, s});
+        case FE_FP16: return with_shape(h.s.k, el, ppw, BatchLaunch<PolF16>{jobs, boff, njobs, grid, s});
+        default: return with_shape(h.s.k, el, ppw, BatchLaunch<PolBF16>{jobs, boff, njobs, grid, s});
     }
 }
 
-// Workgroups per cell of the matrix-core kernel (same table as launch_pol).
+// Workgroups per cell of the matrix-core kernel (the shape launch_integrate_mfma uses now).
 int64_t mfma_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts)
 {
-    const bool el = pa.problem == FE_ELASTICITY;
-    int nnp = 32, ppw = 1;
-    if (sa.k == 3) {
-        nnp = 64;
-        ppw = el ? 1 : 3;
-    } else if (sa.k == 4) {
-        nnp = 128;
-        ppw = el ? 2 : 9;
-    }
-    const int nt = nnp / 16, np = nt * (nt + 1) / 2;
-    parts = (np + 4 * ppw - 1) / (4 * ppw);
+    parts = parts_of(sa.k, k3_ppw(sa.k, pa.problem == FE_ELASTICITY, pa.precision));
     return sa.ncells * parts;
+}
+
+// Times every candidate shape of the class (reps launches after one warm-up)
+// on this space and keeps the fastest.
+fe_status integrate_autotune(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                             void *E, double *F, int reps, fe_k3_plan *tried, int max_tried, int *n_tried,
+                             fe_k3_plan *chosen, hipStream_t s)
+{
+    if (sa.dim != 3 || sa.k < 2 || sa.k > 4) return set_error(FE_EINVAL, "no tile shapes to tune for this space");
+    const bool el = pa.problem == FE_ELASTICITY;
+    const std::vector<int> cand = k3_candidates(sa.k, el, pa.precision);
+    hipEvent_t e0, e1;
+    FE_HIP(hipEventCreate(&e0));
+    FE_HIP(hipEventCreate(&e1));
+    int best = -1;
+    double best_us = 0.0;
+    fe_status st = FE_OK;
+    for (size_t c = 0; c < cand.size() && st == FE_OK; c++) {
+        for (int r = -1; r < reps && st == FE_OK; r++) {
+            if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = set_error(FE_EDEVICE, "event record failed");
+            if (st == FE_OK) st = launch_with(sa, ma, pa, rt, E, F, s, cand[c]);
+        }
+        if (st != FE_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = set_error(FE_EDEVICE, "autotune timing failed");
+            break;
+        }
+        const double us = 1000.0 * double(ms) / double(reps);
+        if (tried && int(c) < max_tried) tried[c] = fe_k3_plan{cand[c], parts_of(sa.k, cand[c]), us};
+        if (n_tried) *n_tried = std::min(int(c) + 1, max_tried);
+        if (best < 0 || us < best_us) {
+            best = int(c);
+            best_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FE_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_k3_mu);
+        g_k3_tuned[k3_class(sa.k, el, pa.precision)] = cand[best];
+    }
+    if (chosen) *chosen = fe_k3_plan{cand[best], parts_of(sa.k, cand[best]), best_us};
+    return FE_OK;
+}
+
+void integrate_plan_of(const SpaceArgs &sa, const ProblemArgs &pa, fe_k3_plan *plan)
+{
+    const bool el = pa.problem == FE_ELASTICITY;
+    const int ppw = (sa.dim == 3 && sa.k >= 2 && sa.k <= 4) ? k3_ppw(sa.k, el, pa.precision) : 0;
+    *plan = fe_k3_plan{ppw, ppw ? parts_of(sa.k, ppw) : 0, 0.0};
+}
+
+void integrate_tuning_reset()
+{
+    std::lock_guard<std::mutex> lk(g_k3_mu);
+    g_k3_tuned.clear();
 }
 
 }  // namespace fe

@@ -57,7 +57,7 @@ struct SpaceArgs {
 // Device-side view of the mesh.
 struct MeshArgs {
     const double *x, *y, *z;  // vertex coordinates (SoA)
-    const double *coef;       // per cell
+    const double *coef;       // per cell (nullptr: 1 on every cell)
     int32_t n0, n1, n2;       // cells per axis (n2 = 1 in 2D)
     int32_t *status;          // device status word (bit 0: det J <= 0 seen)
 };
@@ -140,6 +140,17 @@ fe_status launch_pattern(const SpaceArgs &sa, int64_t *rowptr, int32_t *colind, 
 fe_status launch_cell_dofs(const SpaceArgs &sa, const MeshArgs &ma, int32_t *out, hipStream_t s);
 fe_status launch_permutation(const SpaceArgs &sa, const MeshArgs &ma, int64_t *perm, hipStream_t s);
 void ref_tables(int k, RefTables &t);
+// Value and derivative at x of the 1D Lagrange polynomial of node i/k of the
+// equidistant order-k basis on [0,1] (Sect. 3.4 eq. lagbas).
+void lagrange_1d(int k, int i, double x, double &val, double &der);
+// Interior-penalty DG (fe_dg.hip): sizes, the space the volume integration
+// runs on (scalar, nloc = nn, no shared DOFs), pattern and facet kernels.
+void dg_sizes(int dim, const int32_t *n, int k, int64_t &n_rows, int64_t &nnz);
+SpaceArgs dg_space(int dim, const int32_t *n, int k);
+fe_status launch_dg_pattern(int dim, const int32_t *n, int k, int64_t *rowptr, int32_t *colind, hipStream_t s);
+fe_status launch_dg_facets(int dim, const int32_t *n, int k, double gamma, double tau, const MeshArgs &ma,
+                           const ProblemArgs &pa, const ElemLayout &el, const void *ws, const int64_t *rowptr,
+                           double *values, double *rhs, double *dinv, hipStream_t s);
 
 // Integration (fe_integrate.hip)
 ElemLayout elem_layout(const SpaceArgs &sa, int precision);
@@ -155,6 +166,11 @@ fe_status launch_lift(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs
 bool integrate_batchable(const SpaceArgs &sa, const ProblemArgs &pa);
 int64_t integrate_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts);
 int64_t mfma_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts);
+fe_status integrate_autotune(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
+                             void *E, double *F, int reps, fe_k3_plan *tried, int max_tried, int *n_tried,
+                             fe_k3_plan *chosen, hipStream_t s);
+void integrate_plan_of(const SpaceArgs &sa, const ProblemArgs &pa, fe_k3_plan *plan);
+void integrate_tuning_reset();
 fe_status launch_mfma_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,
                             hipStream_t s);
 fe_status launch_integrate_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *boff, int njobs, int grid,

@@ -50,28 +50,29 @@ static void gauss_legendre_01(int n, double *x, double *w)
     }
 }
 
+void lagrange_1d(int k, int i, double x, double &val, double &der)
+{
+    const double xi = double(i) / k;
+    double den = 1.0;
+    for (int s = 0; s <= k; s++)
+        if (s != i) den *= xi - double(s) / k;
+    double v = 1.0, d = 0.0;
+    for (int s = 0; s <= k; s++) {
+        if (s == i) continue;
+        // product rule: d/dx prod (x - x_s) accumulated on the fly
+        d = d * (x - double(s) / k) + v;
+        v *= x - double(s) / k;
+    }
+    val = v / den;
+    der = d / den;
+}
+
 void ref_tables(int k, RefTables &t)
 {
     const int nq = k + 1;
     gauss_legendre_01(nq, t.gx, t.gw);
-    for (int i = 0; i <= k; i++) {
-        const double xi = double(i) / k;
-        double den = 1.0;
-        for (int s = 0; s <= k; s++)
-            if (s != i) den *= xi - double(s) / k;
-        for (int q = 0; q < nq; q++) {
-            const double x = t.gx[q];
-            double val = 1.0, der = 0.0;
-            for (int s = 0; s <= k; s++) {
-                if (s == i) continue;
-                // product rule: d/dx prod (x - x_s) accumulated on the fly
-                der = der * (x - double(s) / k) + val;
-                val *= x - double(s) / k;
-            }
-            t.L[i * nq + q] = val / den;
-            t.D[i * nq + q] = der / den;
-        }
-    }
+    for (int i = 0; i <= k; i++)
+        for (int q = 0; q < nq; q++) lagrange_1d(k, i, t.gx[q], t.L[i * nq + q], t.D[i * nq + q]);
 }
 
 // ---------------------------------------------------------------------------

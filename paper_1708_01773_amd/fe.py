@@ -32,7 +32,8 @@ EXPORTS = [
     "fe_spmv_mesh", "fe_pcg_solve_mesh", "fe_pcg_solve_batch_mesh", "fe_spmv_autotune_mesh", "fe_spmv_plan_of_mesh",
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
     "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set", "fe_pcg_solve_noalloc",
-    "fe_refine_solve_mesh", "fe_refine_batch_query", "fe_refine_solve_batch_mesh",
+    "fe_refine_solve_mesh", "fe_refine_batch_query", "fe_refine_solve_batch_mesh", "fe_integrate_autotune",
+    "fe_integrate_plan_of", "fe_dg_query", "fe_dg_pattern", "fe_dg_assemble",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -91,6 +92,10 @@ class ServerStats(_c.Structure):
 
 class SpmvPlan(_c.Structure):
     _fields_ = [("mode", _c.c_int32), ("rows_per_wave", _c.c_int32), ("us", _c.c_double)]
+
+
+class K3Plan(_c.Structure):
+    _fields_ = [("pairs_per_wave", _c.c_int32), ("parts", _c.c_int32), ("us", _c.c_double)]
 
 
 class RefineInfo(_c.Structure):
@@ -167,6 +172,13 @@ def lib():
             "fe_spmv_plan_set_mesh": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(SpmvPlan)],
             "fe_sym_query": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_c.c_size_t)],
             "fe_sym_fp32_from_csr": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(Csr), _P, _c.c_size_t, _P],
+            "fe_integrate_autotune": [_P, _c.c_int32, _c.POINTER(Coeff), _P, _c.c_size_t, _c.c_int32,
+                                      _c.POINTER(K3Plan), _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(K3Plan), _P],
+            "fe_integrate_plan_of": [_P, _c.c_int32, _c.POINTER(Coeff), _c.POINTER(K3Plan)],
+            "fe_dg_query": [_P, _c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
+            "fe_dg_pattern": [_P, _c.c_int32, _c.POINTER(Csr), _P],
+            "fe_dg_assemble": [_P, _c.c_int32, _c.POINTER(Coeff), _c.c_double, _c.c_double, _c.POINTER(Csr), _P,
+                               _c.c_size_t, _P],
             "fe_refine_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
             "fe_refine_solve_batch_mesh": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
                                            _c.POINTER(Csr), _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P),
@@ -316,6 +328,22 @@ def assemble(mesh, order, coeff, csr, ws, stream=None):
                              ws.numel() * ws.element_size(), _stream(stream)), "fe_assemble")
 
 
+def dg_query(mesh, order):
+    """(n_rows, nnz, workspace bytes) of the interior-penalty DG system."""
+    nr, nz, ws = _c.c_int64(), _c.c_int64(), _c.c_size_t()
+    _check(lib().fe_dg_query(mesh.handle, int(order), _c.byref(nr), _c.byref(nz), _c.byref(ws)), "fe_dg_query")
+    return nr.value, nz.value, ws.value
+
+
+def dg_pattern(mesh, order, csr, stream=None):
+    _check(lib().fe_dg_pattern(mesh.handle, int(order), _c.byref(csr), _stream(stream)), "fe_dg_pattern")
+
+
+def dg_assemble(mesh, order, coeff, gamma, tau, csr, ws, stream=None):
+    _check(lib().fe_dg_assemble(mesh.handle, int(order), _c.byref(coeff), float(gamma), float(tau), _c.byref(csr),
+                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "fe_dg_assemble")
+
+
 def integrate(mesh, order, coeff, ws, stream=None):
     _check(lib().fe_integrate(mesh.handle, int(order), _c.byref(coeff), _ptr(ws), ws.numel() * ws.element_size(),
                               _stream(stream)), "fe_integrate")
@@ -440,6 +468,25 @@ def spmv_plan_of_mesh(mesh, order, coeff):
     _check(lib().fe_spmv_plan_of_mesh(mesh.handle, int(order), _c.byref(coeff), _c.byref(p), _c.byref(c)),
            "fe_spmv_plan_of_mesh")
     return p.mode, p.rows_per_wave, c.value
+
+
+def integrate_autotune(mesh, order, coeff, ws, reps=5, stream=None):
+    """Times every tile shape of the matrix-core integration of this class and
+    keeps the fastest; returns (chosen, tried) as dicts (pairs_per_wave, parts, us)."""
+    tried = (K3Plan * 8)()
+    nt = _c.c_int32()
+    ch = K3Plan()
+    _check(lib().fe_integrate_autotune(mesh.handle, int(order), _c.byref(coeff), _ptr(ws), _nbytes(ws), int(reps),
+                                       tried, 8, _c.byref(nt), _c.byref(ch), _stream(stream)), "fe_integrate_autotune")
+    d = lambda p: dict(pairs_per_wave=p.pairs_per_wave, parts=p.parts, us=p.us)
+    return d(ch), [d(t) for t in tried[: nt.value]]
+
+
+def integrate_plan_of(mesh, order, coeff):
+    """(pairs_per_wave, parts) of the class's matrix-core integration now."""
+    p = K3Plan()
+    _check(lib().fe_integrate_plan_of(mesh.handle, int(order), _c.byref(coeff), _c.byref(p)), "fe_integrate_plan_of")
+    return p.pairs_per_wave, p.parts
 
 
 def spmv_tuning_reset():
@@ -659,6 +706,29 @@ class Assembly:
     def solve(self, x, rtol, maxit, ws, stream=None):
         """Jacobi-PCG with the pattern evaluated from the mesh (fe_pcg_solve_mesh)."""
         return pcg_solve_mesh(self.mesh, self.order, self.coeff, self.csr, self.rhs, x, rtol, maxit, ws, stream)
+
+
+class DGAssembly:
+    """Device buffers (torch tensors) of one interior-penalty DG system plus its
+    workspace; the pattern is written at construction."""
+
+    def __init__(self, mesh, order, coeff, gamma, tau=1.0, device="cuda", stream=None):
+        import torch
+        self.mesh, self.order, self.coeff = mesh, int(order), coeff
+        self.gamma, self.tau = float(gamma), float(tau)
+        self.n_rows, self.nnz, ws_bytes = dg_query(mesh, order)
+        dev = torch.device(device)
+        self.rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=dev)
+        self.colind = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        self.values = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        self.rhs = torch.empty(max(self.n_rows, 1), dtype=torch.float64, device=dev)
+        self.dinv = torch.empty(max(self.n_rows, 1), dtype=torch.float64, device=dev)
+        self.ws = torch.empty(max(ws_bytes, 8), dtype=torch.uint8, device=dev)
+        self.csr = csr_struct(self.n_rows, self.nnz, self.rowptr, self.colind, self.values, self.rhs, self.dinv)
+        dg_pattern(mesh, order, self.csr, stream)
+
+    def assemble(self, stream=None):
+        dg_assemble(self.mesh, self.order, self.coeff, self.gamma, self.tau, self.csr, self.ws, stream)
 
 
 def assemble_batch_query(meshes, orders, coeffs):

@@ -36,6 +36,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(F.MeshDesc) == 32
     assert ctypes.sizeof(F.Csr) == 56
     assert ctypes.sizeof(F.SolveInfo) == 40
+    assert ctypes.sizeof(F.K3Plan) == 16 and ctypes.sizeof(F.SpmvPlan) == 16
     assert F.Coeff.dirichlet_affine.offset + 96 == ctypes.sizeof(F.Coeff)
 
 
@@ -137,3 +138,13 @@ def test_csr_plans_can_be_pinned_per_row_class_on_host():
     assert F.spmv_plan_of(2048383, 54439939)[:2] == (9, 128)
     assert F.spmv_plan_of(2572125, 1572091911)[:2] == (9, 8)
     assert F.spmv_plan_of(1000, 3000)[:2] == (9, 256)
+
+
+def test_dg_entry_points_validate_on_host():
+    L = F.lib()
+    nr, nz, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    assert L.fe_dg_query(None, 2, ctypes.byref(nr), ctypes.byref(nz), ctypes.byref(ws)) == F.FE_EINVAL
+    assert "mesh" in L.fe_last_error().decode()
+    assert L.fe_dg_pattern(None, 2, None, None) == F.FE_EINVAL
+    c = F.make_coeff()
+    assert L.fe_dg_assemble(None, 2, ctypes.byref(c), 36.0, 1.0, None, None, 0, None) == F.FE_EINVAL
