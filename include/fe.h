@@ -207,6 +207,53 @@ fe_status fe_permutation(fe_mesh mesh, int32_t order, const fe_coeff *coeff, int
 fe_status fe_get_status(fe_mesh mesh);
 
 /* ------------------------------------------------------------------------ */
+/* Solve                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t iters;           /* CG iterations performed */
+    int32_t status;          /* FE_OK, FE_ENOTCONV or FE_EBREAKDOWN */
+    double relres;           /* ||r_j|| / ||b|| of the recursively updated residual */
+    double true_relres;      /* ||b - A x|| / ||b|| recomputed at exit */
+    double lambda_min_est;   /* extremal Ritz values of diag(A)^-1 A (Lanczos from CG coefficients) */
+    double lambda_max_est;
+} fe_solve_info;
+
+/* Workspace bytes fe_pcg_solve needs for n_rows unknowns. */
+fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes);
+
+/* Jacobi-preconditioned CG on A (device CSR with dinv filled): x holds x0 on
+ * entry and the solution on exit (device, n_rows).  Stops when
+ * ||r_j||_2 <= rtol ||b||_2 or after maxit iterations.  Reductions are
+ * deterministic (fixed-order two-stage sums, no float atomics).  Synchronizes
+ * before returning (info is host memory).  Returns info->status.
+ * Alignment: device arrays need the alignment of their element type; the
+ * workspace 8 bytes (FE_EINVAL otherwise).  Vectors and workspace that are
+ * 16-byte aligned (any device allocation is) get 16-byte vector accesses,
+ * others single accesses with the same results. */
+fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
+                       size_t ws_bytes, fe_solve_info *info, fe_stream stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fe_pcg_solve without a
+ * workspace argument.  The workspace lives in a static device array of
+ * FE_PCG_NOALLOC_BYTES (64 MiB) inside the library, one copy per device,
+ * held from the first call on that device until the process ends; the call
+ * itself allocates no device, pinned-host or graph memory and creates no
+ * stream or event (iterations are launched directly on `stream`, the stop
+ * test is read into pageable host memory).  Arguments, results and
+ * alignment rules as for fe_pcg_solve; the caller still owns A, b and x.
+ * Systems of more than FE_PCG_NOALLOC_MAX_ROWS rows are refused with
+ * FE_EINVAL before any device work.  Every call on a device uses that
+ * device's one array: calls that overlap on one device (other host threads,
+ * other streams) race and must be serialized by the caller.  Nothing in the
+ * array needs to start cleared, so the previous call's contents are harmless.
+ * Synchronizes before returning. */
+#define FE_PCG_NOALLOC_BYTES (64u << 20)
+#define FE_PCG_NOALLOC_MAX_ROWS 2700000
+fe_status fe_pcg_solve_noalloc(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit,
+                               fe_solve_info *info, fe_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Interior-penalty discontinuous Galerkin (Sect. 3.12 eq. ip_dg_formulations, */
 /* facet matrices of eq. local_to_face_matrix, facet integration Sect. 3.13) */
 /* ------------------------------------------------------------------------ */
@@ -256,52 +303,21 @@ fe_status fe_dg_pattern(fe_mesh mesh, int32_t order, fe_csr *out, fe_stream stre
 fe_status fe_dg_assemble(fe_mesh mesh, int32_t order, const fe_coeff *coeff, double gamma, double tau,
                          fe_csr *out, void *ws, size_t ws_bytes, fe_stream stream);
 
-/* ------------------------------------------------------------------------ */
-/* Solve                                                                     */
-/* ------------------------------------------------------------------------ */
-typedef struct {
-    int32_t iters;           /* CG iterations performed */
-    int32_t status;          /* FE_OK, FE_ENOTCONV or FE_EBREAKDOWN */
-    double relres;           /* ||r_j|| / ||b|| of the recursively updated residual */
-    double true_relres;      /* ||b - A x|| / ||b|| recomputed at exit */
-    double lambda_min_est;   /* extremal Ritz values of diag(A)^-1 A (Lanczos from CG coefficients) */
-    double lambda_max_est;
-} fe_solve_info;
+/* y = A x for a DG system of (mesh, order), the pattern evaluated from the
+ * cell index instead of read (out->rowptr / colind are not read): the nn rows
+ * of a cell are contiguous in the values, so only the values and x are
+ * loaded.  x, y: device, n_rows doubles; A->values 16-byte aligned
+ * (FE_EINVAL otherwise).  Each row is summed in a fixed order: bitwise
+ * reproducible.  Enqueues only. */
+fe_status fe_dg_spmv(fe_mesh mesh, int32_t order, const fe_csr *A, const double *x, double *y, fe_stream stream);
 
-/* Workspace bytes fe_pcg_solve needs for n_rows unknowns. */
-fe_status fe_pcg_query(int64_t n_rows, size_t *ws_bytes);
-
-/* Jacobi-preconditioned CG on A (device CSR with dinv filled): x holds x0 on
- * entry and the solution on exit (device, n_rows).  Stops when
- * ||r_j||_2 <= rtol ||b||_2 or after maxit iterations.  Reductions are
- * deterministic (fixed-order two-stage sums, no float atomics).  Synchronizes
- * before returning (info is host memory).  Returns info->status.
- * Alignment: device arrays need the alignment of their element type; the
- * workspace 8 bytes (FE_EINVAL otherwise).  Vectors and workspace that are
- * 16-byte aligned (any device allocation is) get 16-byte vector accesses,
- * others single accesses with the same results. */
-fe_status fe_pcg_solve(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit, void *ws,
-                       size_t ws_bytes, fe_solve_info *info, fe_stream stream);
-
-/* For callers that cannot allocate (code under HIP graph capture, tight
- * serving loops, harnesses that forbid allocation): fe_pcg_solve without a
- * workspace argument.  The workspace lives in a static device array of
- * FE_PCG_NOALLOC_BYTES (64 MiB) inside the library, one copy per device,
- * held from the first call on that device until the process ends; the call
- * itself allocates no device, pinned-host or graph memory and creates no
- * stream or event (iterations are launched directly on `stream`, the stop
- * test is read into pageable host memory).  Arguments, results and
- * alignment rules as for fe_pcg_solve; the caller still owns A, b and x.
- * Systems of more than FE_PCG_NOALLOC_MAX_ROWS rows are refused with
- * FE_EINVAL before any device work.  Every call on a device uses that
- * device's one array: calls that overlap on one device (other host threads,
- * other streams) race and must be serialized by the caller.  Nothing in the
- * array needs to start cleared, so the previous call's contents are harmless.
- * Synchronizes before returning. */
-#define FE_PCG_NOALLOC_BYTES (64u << 20)
-#define FE_PCG_NOALLOC_MAX_ROWS 2700000
-fe_status fe_pcg_solve_noalloc(const fe_csr *A, const double *b, double *x, double rtol, int32_t maxit,
-                               fe_solve_info *info, fe_stream stream);
+/* The Jacobi-PCG of fe_pcg_solve (Sect. 12) on a DG system of (mesh, order),
+ * with the SpMV of fe_dg_spmv; A->values and A->dinv as written by
+ * fe_dg_assemble (tau = 1: symmetric positive definite for a large enough
+ * gamma).  ws: fe_pcg_query(n_rows) bytes; statuses as fe_pcg_solve.
+ * Synchronous (returns after the solve). */
+fe_status fe_dg_pcg_solve(fe_mesh mesh, int32_t order, const fe_csr *A, const double *b, double *x, double rtol,
+                          int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *info, fe_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched solve: many independent systems in one sequence of launches       */

@@ -677,6 +677,35 @@ fe_status fe_dg_assemble(fe_mesh m, int32_t order, const fe_coeff *c, double gam
     return st;
 }
 
+fe_status fe_dg_spmv(fe_mesh m, int32_t order, const fe_csr *A, const double *x, double *y, fe_stream stream)
+{
+    int64_t nr, nz;
+    fe_status st = dg_check(m, order, nr, nz);
+    if (st != FE_OK) return st;
+    if (!A || !x || !y) return set_error(FE_EINVAL, "null argument");
+    if (A->n_rows != nr || A->nnz != nz) return set_error(FE_EINVAL, "csr sizes differ from fe_dg_query");
+    if (nz > 0 && !A->values) return set_error(FE_EINVAL, "null csr values");
+    if (reinterpret_cast<uintptr_t>(A->values) & 15u) return set_error(FE_EINVAL, "csr values not 16-byte aligned");
+    m->last_stream = as_stream(stream);
+    return launch_spmv_dg(dg_space(m->dim, m->n, order), A->values, x, y, as_stream(stream));
+}
+
+fe_status fe_dg_pcg_solve(fe_mesh m, int32_t order, const fe_csr *A, const double *b, double *x, double rtol,
+                          int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *info, fe_stream stream)
+{
+    int64_t nr, nz;
+    fe_status st = dg_check(m, order, nr, nz);
+    if (st != FE_OK) return st;
+    if (!A || !b || !x || !ws || !info) return set_error(FE_EINVAL, "null argument");
+    if (A->n_rows != nr || A->nnz != nz) return set_error(FE_EINVAL, "csr sizes differ from fe_dg_query");
+    if (nr > 0 && (!A->values || !A->dinv)) return set_error(FE_EINVAL, "null csr values/dinv");
+    if (reinterpret_cast<uintptr_t>(A->values) & 15u) return set_error(FE_EINVAL, "csr values not 16-byte aligned");
+    if (!(rtol >= 0.0) || maxit < 0) return set_error(FE_EINVAL, "bad rtol/maxit");
+    m->last_stream = as_stream(stream);
+    const SpaceArgs sa = dg_space(m->dim, m->n, order);
+    return pcg_solve_dg(A, sa, b, x, rtol, maxit, ws, ws_bytes, info, as_stream(stream));
+}
+
 fe_status fe_cell_dofs(fe_mesh m, int32_t order, const fe_coeff *c, int32_t *out, fe_stream stream)
 {
     fe_status st = check_coeff(m, order, c);

@@ -55,23 +55,9 @@ struct DgArgs {
     double Le[2 * kMaxQ1], De[2 * kMaxQ1];
 };
 
-// Cells K' < K whose index along an axis of stride st and extent n equals v.
-__host__ __device__ __forceinline__ int64_t dg_count_at(int64_t K, int64_t st, int64_t n, int64_t v)
-{
-    const int64_t P = st * n, q = K / P, rem = K % P;
-    int64_t t = rem - v * st;
-    t = t < 0 ? 0 : (t > st ? st : t);
-    return q * st + t;
-}
-
-// Sum over cells K' < K of the cells in the row blocks of K' (K' and its
-// facet neighbours): (2d + 1) K minus the missing neighbours on the boundary.
 __host__ __device__ __forceinline__ int64_t dg_prefix(const DgArgs &d, int64_t K)
 {
-    int64_t s = (2 * d.dim + 1) * K;
-    for (int r = 0; r < d.dim; r++)
-        s -= dg_count_at(K, d.st[r], d.n[r], 0) + dg_count_at(K, d.st[r], d.n[r], d.n[r] - 1);
-    return s;
+    return dg_prefix_n(d.dim, d.n[0], d.n[1], d.n[2], K);
 }
 
 // Facet neighbours of K and their column slots.  Facet f = 2 r + side
@@ -138,6 +124,13 @@ struct DgShape {
     static constexpr int NN = DIM == 3 ? K1 * K1 * K1 : K1 * K1;  // nodes per cell
     static constexpr int NF = DIM == 3 ? K1 * K1 : K1;           // nodes per facet
     static constexpr int NP = NF;                                // facet points (k + 1 per direction)
+    static constexpr int NFACE = 2 * DIM;
+    // threads: enough for one entry of the nn x nn block each, up to 256
+    static constexpr int BS = NN * NN <= 64 ? 64 : (NN * NN <= 128 ? 128 : 256);
+    static constexpr int JD = (NN * NN + BS - 1) / BS;  // diagonal-block entries per thread
+    static constexpr bool DREG = JD <= 16;              // diagonal block held in registers
+    static constexpr int NIT = 2 * NFACE * NP;          // (facet, side, point) items
+    static constexpr int IT = (NIT + BS - 1) / BS;      // items per thread
 };
 
 // Index of node a on facet (r, side) (tangential indices, first axis
@@ -161,146 +154,190 @@ __device__ __forceinline__ int face_node(int a, int r, int side)
     return ar == (side ? KO : 0) ? t : -1;
 }
 
+// One workgroup per cell K.  Phases:
+//  0. tables, neighbours, and the vertices of K and its neighbours into LDS;
+//  1. the geometry of every (facet, side, point) at once: J^-1 on each side,
+//     the facet normal from the cell below the facet, weights, Dirichlet
+//     data, penalties;
+//  2. per facet: the normal derivatives of both sides at the facet points,
+//     the facet mass, the tables A and B in place, then the facet's entries.
+// The diagonal block (volume + every facet) accumulates in registers when a
+// thread holds at most 16 of its entries, else in the output (re-read by the
+// thread that wrote it).
 template <int DIM, int KO>
-__global__ __launch_bounds__(256) void dg_cell_kernel(DgArgs d, MeshArgs m, ProblemArgs p, ElemLayout el,
-                                                      const double *__restrict__ E, const double *__restrict__ F,
-                                                      const int64_t *__restrict__ rowptr, double *__restrict__ values,
-                                                      double *__restrict__ rhs, double *__restrict__ dinv)
+__global__ __launch_bounds__((DgShape<DIM, KO>::BS)) void dg_cell_kernel(
+    DgArgs d, MeshArgs m, ProblemArgs p, ElemLayout el, const double *__restrict__ E, const double *__restrict__ F,
+    const int64_t *__restrict__ rowptr, double *__restrict__ values, double *__restrict__ rhs,
+    double *__restrict__ dinv)
 {
     using S = DgShape<DIM, KO>;
-    constexpr int K1 = S::K1, NN = S::NN, NF = S::NF, NP = S::NP;
+    constexpr int K1 = S::K1, NN = S::NN, NF = S::NF, NP = S::NP, NFACE = S::NFACE, BS = S::BS, JD = S::JD;
+    constexpr int NV = 1 << DIM;
     // per facet: normal derivatives of K's and the neighbour's basis at the
     // facet points, overwritten in place by the tables A and B; facet mass M
     __shared__ double sX[NP * NN], sY[NP * NN], sM[NF * NF];
-    __shared__ double sL[K1 * K1], sD[K1 * K1], sLe[2 * K1], sDe[2 * K1], sGw[K1];
-    __shared__ double sW[NP], sU[NP], sMK[NP][3], sML[NP][3], sNv[NP][3];
-    __shared__ double sSigma;
+    __shared__ double sL[K1 * K1], sD[K1 * K1], sLe[2 * K1], sDe[2 * K1];
+    __shared__ double sV[1 + NFACE][NV][3];  // vertices of K (slot 0) and of the neighbour across facet f (1 + f)
+    __shared__ double sNv[NFACE][NP][3];     // det J J^-T e_r of the cell below the facet
+    __shared__ double sMv[NFACE][2][NP][3];  // J^-1 n on K's side and on the neighbour's, n = K's outward normal
+    __shared__ double sW[NFACE][NP], sU[NFACE][NP], sSig[NFACE];
     __shared__ int sFK[NN], sFL[NN];  // facet index of each node on K's facet and on the neighbour's
-    __shared__ int sBad;
+    __shared__ int64_t sNb[6];
+    __shared__ int sSlot[6], sSelf, sNc, sBad;
 
     const int64_t K = xcd_block(blockIdx.x, gridDim.x);
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int t = tid; t < K1 * K1; t += nt) {
+    const int tid = threadIdx.x;
+    for (int t = tid; t < K1 * K1; t += BS) {
         sL[t] = d.L[t];
         sD[t] = d.D[t];
     }
-    for (int t = tid; t < 2 * K1; t += nt) {
+    for (int t = tid; t < 2 * K1; t += BS) {
         sLe[t] = d.Le[t];
         sDe[t] = d.De[t];
     }
-    if (tid < K1) sGw[tid] = d.gw[tid];
-    if (tid == 0) sBad = 0;
-
-    __shared__ int64_t sNb[6];
-    __shared__ int sSlot[6], sSelf, sNc;
     if (tid == 0) {
         int64_t nb[6];
         int slot[6], self, nc;
         dg_cell_faces(d, K, nb, slot, self, nc);
-        for (int f = 0; f < 2 * DIM; f++) {
+        for (int f = 0; f < NFACE; f++) {
             sNb[f] = nb[f];
             sSlot[f] = slot[f];
         }
         sSelf = self;
         sNc = nc;
+        sBad = 0;
     }
     __syncthreads();
+    for (int t = tid; t < (1 + NFACE) * NV; t += BS) {
+        const int sl = t / NV, v = t % NV;
+        const int64_t cell = sl == 0 ? K : sNb[sl - 1];
+        if (cell < 0) continue;
+        const int64_t e0 = cell % m.n0, e1 = (cell / m.n0) % m.n1, e2 = cell / (int64_t(m.n0) * m.n1);
+        const int64_t vid = (e0 + (v & 1)) +
+                            int64_t(m.n0 + 1) * ((e1 + ((v >> 1) & 1)) + int64_t(m.n1 + 1) * (DIM == 3 ? e2 + ((v >> 2) & 1) : 0));
+        sV[sl][v][0] = m.x[vid];
+        sV[sl][v][1] = m.y[vid];
+        sV[sl][v][2] = DIM == 3 ? m.z[vid] : 0.0;
+    }
     const int self = sSelf, nc = sNc;
     const int64_t row0 = rowptr[K * NN];
     const int64_t rlen = int64_t(nc) * NN;
+    __syncthreads();
 
-    // volume block: the element matrix of K
-    for (int e = tid; e < NN * NN; e += nt) {
-        const int a = e / NN, b = e % NN;
-        values[row0 + a * rlen + self * NN + b] = E[elem_index(K, a, b, NN, el.cb, el.packed, el.ne)];
+    // 1a. J^-1 at every facet point on both sides; the facet normal from the
+    // cell below the facet (K on its upper facets and on the boundary)
+    double Ji[S::IT][9];
+#pragma unroll
+    for (int it = 0; it < S::IT; it++) {
+        const int i = tid + it * BS;
+        if (i >= S::NIT) continue;
+        const int f = i / (2 * NP), gs = (i / NP) & 1, q = i % NP;
+        const int r = f >> 1, side = f & 1;
+        const bool interior = sNb[f] >= 0;
+        if (gs == 1 && !interior) continue;
+        const int t0 = DIM == 2 ? 1 - r : (r == 0 ? 1 : 0), t1 = DIM == 2 ? -1 : (r == 2 ? 1 : 2);
+        const int q0 = q % K1, q1 = q / K1;
+        const double er = (gs == 0) == (side == 1) ? 1.0 : 0.0;  // reference coordinate along r
+        double xi[3];
+#pragma unroll
+        for (int sx = 0; sx < 3; sx++) xi[sx] = sx == r ? er : (sx == t0 ? d.gx[q0] : (sx == t1 ? d.gx[q1] : 0.0));
+        double X[NV][3], J[9], xq[3];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) X[v][c] = sV[gs == 0 ? 0 : 1 + f][v][c];
+        const double det = geometry<DIM>(X, xi, J, Ji[it], xq);
+        if (!(det > 0.0)) atomicOr(&sBad, 1);
+        const bool owner = gs == 0 ? (side == 1 || !interior) : side == 0;
+        if (owner) {
+#pragma unroll
+            for (int rr = 0; rr < DIM; rr++)
+                if (rr == r) {
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) sNv[f][q][c] = det * Ji[it][rr * DIM + c];
+                }
+        }
+        if (gs == 0) {
+            double u = 0.0;
+            if (!interior && p.dirichlet_kind == FE_DIRICHLET_AFFINE) {
+                u = p.aff[0];
+#pragma unroll
+                for (int c = 0; c < DIM; c++) u += p.aff[1 + c] * xq[c];
+            }
+            sU[f][q] = u;
+        }
+    }
+    __syncthreads();
+    // 1b. K's outward unit normal n, J^-1 n on each side, weights
+#pragma unroll
+    for (int it = 0; it < S::IT; it++) {
+        const int i = tid + it * BS;
+        if (i >= S::NIT) continue;
+        const int f = i / (2 * NP), gs = (i / NP) & 1, q = i % NP;
+        if (gs == 1 && sNb[f] < 0) continue;
+        double nv[3] = {0.0, 0.0, 0.0}, nn2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; c++) {
+            nv[c] = sNv[f][q][c];
+            nn2 += nv[c] * nv[c];
+        }
+        const double dS = sqrt(nn2);
+        const double sgn = (f & 1) ? 1.0 : -1.0;
+        double n[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < DIM; c++) n[c] = sgn * (nv[c] / dS);
+#pragma unroll
+        for (int sx = 0; sx < 3; sx++) {
+            double mv = 0.0;
+            if (sx < DIM) {
+#pragma unroll
+                for (int c = 0; c < DIM; c++) mv += Ji[it][sx * DIM + c] * n[c];
+            }
+            sMv[f][gs][q][sx] = mv;
+        }
+        if (gs == 0) {
+            const int q0 = q % K1, q1 = q / K1;
+            sW[f][q] = (d.gw[q0] * (DIM == 3 ? d.gw[q1] : 1.0)) * dS;
+        }
+    }
+    __syncthreads();
+    if (tid < NFACE) {
+        double area = 0.0;
+        for (int q = 0; q < NP; q++) area += sW[tid][q];
+        sSig[tid] = d.gamma / (DIM == 3 ? sqrt(area) : area);
+    }
+
+    // the diagonal block starts from the element matrix of K
+    double dacc[S::DREG ? JD : 1];
+#pragma unroll
+    for (int j = 0; j < (S::DREG ? JD : 1); j++) dacc[j] = 0.0;
+    if constexpr (S::DREG) {
+#pragma unroll
+        for (int j = 0; j < JD; j++) {
+            const int e = tid + j * BS;
+            if (e < NN * NN) dacc[j] = E[elem_index(K, e / NN, e % NN, NN, el.cb, el.packed, el.ne)];
+        }
+    } else {
+        for (int e = tid; e < NN * NN; e += BS) {
+            const int a = e / NN, b = e % NN;
+            values[row0 + a * rlen + self * NN + b] = E[elem_index(K, a, b, NN, el.cb, el.packed, el.ne)];
+        }
     }
     double racc = tid < NN ? F[K * NN + tid] : 0.0;
 
 #pragma unroll 1
-    for (int f = 0; f < 2 * DIM; f++) {
+    for (int f = 0; f < NFACE; f++) {
         const int r = f >> 1, side = f & 1;
-        const int64_t Lc = sNb[f];
-        const bool interior = Lc >= 0;
-        const int t0 = DIM == 2 ? 1 - r : (r == 0 ? 1 : 0), t1 = DIM == 2 ? -1 : (r == 2 ? 1 : 2);
-        __syncthreads();  // the previous facet's tables are no longer read
-        // facet points, one thread per (side, point): side 0 is K, side 1 the
-        // neighbour.  Weights, K's outward unit normal n, J^-1 n on each side.
-        for (int a = tid; a < NN; a += nt) {
+        const bool interior = sNb[f] >= 0;
+        const int t0 = DIM == 2 ? 1 - r : (r == 0 ? 1 : 0);
+        if (f > 0) __syncthreads();  // the previous facet's tables are no longer read
+        for (int a = tid; a < NN; a += BS) {
             sFK[a] = face_node<DIM, KO>(a, r, side);
             sFL[a] = face_node<DIM, KO>(a, r, 1 - side);
         }
-        const int gs = tid / NP, gq = tid % NP;
-        const bool gact = tid < (interior ? 2 : 1) * NP;
-        double Ji[9], xq[3];
-        if (gact) {
-            const int q0 = gq % K1, q1 = gq / K1;
-            const double er = (gs == 0) == (side == 1) ? 1.0 : 0.0;  // reference coordinate along r
-            double xi[3];
-#pragma unroll
-            for (int sx = 0; sx < 3; sx++)
-                xi[sx] = sx == r ? er : (sx == t0 ? d.gx[q0] : (sx == t1 ? d.gx[q1] : 0.0));
-            double X[1 << DIM][3], J[9];
-            load_vertices<DIM>(m, gs == 0 ? K : Lc, X);
-            const double det = geometry<DIM>(X, xi, J, Ji, xq);
-            if (!(det > 0.0)) atomicOr(&sBad, 1);
-            // the facet's normal det J J^-T e_r comes from the cell below it:
-            // K on its upper facets and on the boundary, else the neighbour
-            const bool owner = gs == 0 ? (side == 1 || !interior) : side == 0;
-            if (owner) {
-#pragma unroll
-                for (int rr = 0; rr < DIM; rr++)
-                    if (rr == r) {
-#pragma unroll
-                        for (int i = 0; i < DIM; i++) sNv[gq][i] = det * Ji[rr * DIM + i];
-                    }
-            }
-        }
-        __syncthreads();
-        if (gact) {
-            double nv[3] = {0.0, 0.0, 0.0}, nn2 = 0.0;
-#pragma unroll
-            for (int i = 0; i < DIM; i++) {
-                nv[i] = sNv[gq][i];
-                nn2 += nv[i] * nv[i];
-            }
-            const double dS = sqrt(nn2);
-            const double sgn = side ? 1.0 : -1.0;
-            double n[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < DIM; i++) n[i] = sgn * (nv[i] / dS);
-            // n . grad phi = (J^-1 n) . grad_ref phi
-            double(*dst)[3] = gs == 0 ? sMK : sML;
-#pragma unroll
-            for (int sx = 0; sx < 3; sx++) {
-                double mv = 0.0;
-                if (sx < DIM) {
-#pragma unroll
-                    for (int i = 0; i < DIM; i++) mv += Ji[sx * DIM + i] * n[i];
-                }
-                dst[gq][sx] = mv;
-            }
-            if (gs == 0) {
-                const int q0 = gq % K1, q1 = gq / K1;
-                sW[gq] = (d.gw[q0] * (DIM == 3 ? d.gw[q1] : 1.0)) * dS;
-                double u = 0.0;
-                if (!interior && p.dirichlet_kind == FE_DIRICHLET_AFFINE) {
-                    u = p.aff[0];
-#pragma unroll
-                    for (int i = 0; i < DIM; i++) u += p.aff[1 + i] * xq[i];
-                }
-                sU[gq] = u;
-            }
-        }
-        __syncthreads();
-        // normal derivatives of both sides at the facet points (sX: K, sY:
-        // the neighbour), the facet mass and the penalty
-        if (tid == 0) {
-            double area = 0.0;
-            for (int q = 0; q < NP; q++) area += sW[q];
-            sSigma = d.gamma / (DIM == 3 ? sqrt(area) : area);
-        }
+        // normal derivatives of both sides at the facet points, facet mass
         const int nside = interior ? 2 : 1;
-        for (int e = tid; e < nside * NP * NN; e += nt) {
+        for (int e = tid; e < nside * NP * NN; e += BS) {
             const int sd = e / (NP * NN), e2 = e - sd * (NP * NN);
             const int q = e2 / NN, b = e2 % NN;
             const int es = sd == 0 ? side : 1 - side;  // reference coordinate along r on this side
@@ -318,7 +355,7 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(DgArgs d, MeshArgs m, Prob
                     g[sx] = sD[bi[sx] * K1 + qs];
                 }
             }
-            const double *mv = sd == 0 ? sMK[q] : sML[q];
+            const double *mv = sMv[f][sd][q];
             double out = 0.0;
 #pragma unroll
             for (int sx = 0; sx < DIM; sx++) {
@@ -330,18 +367,19 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(DgArgs d, MeshArgs m, Prob
             }
             (sd == 0 ? sX : sY)[e2] = out;
         }
-        for (int e = tid; e < NF * NF; e += nt) {
+        for (int e = tid; e < NF * NF; e += BS) {
             const int t = e / NF, u = e % NF;
             double sm = 0.0;
 #pragma unroll
             for (int q = 0; q < NP; q++) {
                 const double pt = DIM == 3 ? sL[(t % K1) * K1 + q % K1] * sL[(t / K1) * K1 + q / K1] : sL[t * K1 + q];
                 const double pu = DIM == 3 ? sL[(u % K1) * K1 + q % K1] * sL[(u / K1) * K1 + q / K1] : sL[u * K1 + q];
-                sm += sW[q] * (pt * pu);  // symmetric in (t, u) to the last bit
+                sm += sW[f][q] * (pt * pu);  // symmetric in (t, u) to the last bit
             }
             sM[e] = sm;
         }
         __syncthreads();
+        const double sigma = sSig[f];
         // A (from sX) and B (from sY) in place, one thread per column b:
         // T[t][b] = sum_q W_q phi_t(q) DN[q][b], t over the facet nodes
         if (tid < nside * NN) {
@@ -360,9 +398,9 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(DgArgs d, MeshArgs m, Prob
                     if (bf >= 0) {
                         const double phi = DIM == 3 ? sL[(bf % K1) * K1 + q % K1] * sL[(bf / K1) * K1 + q / K1]
                                                     : sL[bf * K1 + q];
-                        v += sSigma * phi;
+                        v += sigma * phi;
                     }
-                    sr += sW[q] * sU[q] * v;
+                    sr += sW[f][q] * sU[f][q] * v;
                 }
                 racc += sr;  // thread b holds the rhs of row b
             }
@@ -373,30 +411,40 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(DgArgs d, MeshArgs m, Prob
 #pragma unroll
                 for (int q = 0; q < NP; q++) {
                     const double phi = DIM == 3 ? sL[ta * K1 + q % K1] * sL[tb * K1 + q / K1] : sL[ta * K1 + q];
-                    sa += sW[q] * phi * col[q];
+                    sa += sW[f][q] * phi * col[q];
                 }
                 T[t * NN + b] = sa;
             }
         }
         __syncthreads();
         const double *sA = sX, *sB = sY;
-        const double sigma = sSigma;
         const double cc = interior ? 0.5 : 1.0;
         // A^F_KK: the cross of K's facet rows and columns in the diagonal block
-        for (int e = tid; e < NN * NN; e += nt) {
+        auto cross = [&](int e) -> double {
             const int a = e / NN, b = e % NN;
             const int af = sFK[a], bf = sFK[b];
-            if (af < 0 && bf < 0) continue;
             double v = 0.0;
             if (af >= 0) v -= cc * sA[af * NN + b];
             if (bf >= 0) v -= cc * d.tau * sA[bf * NN + a];
             if (af >= 0 && bf >= 0) v += sigma * sM[af * NF + bf];
-            values[row0 + a * rlen + self * NN + b] += v;
+            return v;
+        };
+        if constexpr (S::DREG) {
+#pragma unroll
+            for (int j = 0; j < JD; j++) {
+                const int e = tid + j * BS;
+                if (e < NN * NN) dacc[j] += cross(e);
+            }
+        } else {
+            for (int e = tid; e < NN * NN; e += BS) {
+                const int a = e / NN, b = e % NN;
+                if (sFK[a] >= 0 || sFK[b] >= 0) values[row0 + a * rlen + self * NN + b] += cross(e);
+            }
         }
         // A^F_KL: the block of the neighbour
         if (interior) {
             const int64_t off = row0 + int64_t(sSlot[f]) * NN;
-            for (int e = tid; e < NN * NN; e += nt) {
+            for (int e = tid; e < NN * NN; e += BS) {
                 const int a = e / NN, b = e % NN;
                 const int af = sFK[a], bl = sFL[b];
                 double v = 0.0;
@@ -408,10 +456,21 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(DgArgs d, MeshArgs m, Prob
         }
     }
     if (tid < NN) rhs[K * NN + tid] = racc;
-    // each thread reads back only the diagonal entries it wrote itself
-    for (int e = tid; e < NN * NN; e += nt) {
-        const int a = e / NN, b = e % NN;
-        if (a == b) dinv[K * NN + a] = 1.0 / values[row0 + a * rlen + self * NN + b];
+    // the diagonal block, and 1 / its diagonal from the thread holding it
+    if constexpr (S::DREG) {
+#pragma unroll
+        for (int j = 0; j < JD; j++) {
+            const int e = tid + j * BS;
+            if (e >= NN * NN) continue;
+            const int a = e / NN, b = e % NN;
+            values[row0 + a * rlen + self * NN + b] = dacc[j];
+            if (a == b) dinv[K * NN + a] = 1.0 / dacc[j];
+        }
+    } else {
+        for (int e = tid; e < NN * NN; e += BS) {
+            const int a = e / NN, b = e % NN;
+            if (a == b) dinv[K * NN + a] = 1.0 / values[row0 + a * rlen + self * NN + b];
+        }
     }
     __syncthreads();
     if (tid == 0 && sBad) atomicOr(m.status, 1);
@@ -469,6 +528,7 @@ SpaceArgs dg_space(int dim, const int32_t *n, int k)
     sa.ncomp = 1;
     sa.nn = int32_t(d.n_rows / (d.ncells > 0 ? d.ncells : 1));
     sa.nloc = sa.nn;
+    for (int r = 0; r < 3; r++) sa.ax[r].n = d.n[r];
     sa.ncells = d.ncells;
     sa.n_rows = d.n_rows;
     sa.nnz = d.nnz;
@@ -493,12 +553,9 @@ fe_status launch_dg_facets(int dim, const int32_t *n, int k, double gamma, doubl
     if (d.ncells == 0) return FE_OK;
     const double *E = static_cast<const double *>(ws);
     const double *F = reinterpret_cast<const double *>(static_cast<const char *>(ws) + el.f_offset);
-    const int nn = int(d.n_rows / d.ncells);
-    // enough threads for one entry of the nn x nn block each, up to 256
-    const int bs = nn * nn <= 64 ? 64 : (nn * nn <= 128 ? 128 : 256);
-#define FE_DGK(D, KO)                                                                                        \
-    hipLaunchKernelGGL((dg_cell_kernel<D, KO>), dim3(d.ncells), dim3(bs), 0, s, d, ma, pa, el, E, F, rowptr, \
-                       values, rhs, dinv)
+#define FE_DGK(D, KO)                                                                                  \
+    hipLaunchKernelGGL((dg_cell_kernel<D, KO>), dim3(d.ncells), dim3((DgShape<D, KO>::BS)), 0, s, d, ma, pa, el, E, \
+                       F, rowptr, values, rhs, dinv)
     if (dim == 3) {
         switch (k) {
             case 1: FE_DGK(3, 1); break;

@@ -204,6 +204,7 @@ struct PcgJob {
     int maxit;
     const SpaceArgs *sa = nullptr;  // structured pattern of a mesh-assembled system (FP32 values: block-staged), or null
     bool sym = false;               // val is the symmetric storage of a Q1 scalar system on sa
+    bool dg = false;                // val holds a DG system on sa (pattern evaluated per cell)
 };
 struct EngineSet;
 EngineSet *engine_create();
@@ -234,6 +235,10 @@ fe_status pcg_solve_batch(int nprob, const fe_csr *A, const double *const *b, do
 fe_status pcg_solve_mesh(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,
                          void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s);
 fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s);
+// DG systems (pattern of fe_dg_pattern evaluated from the cell index; sa from dg_space)
+fe_status launch_spmv_dg(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s);
+fe_status pcg_solve_dg(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,
+                       void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s);
 bool sym_supported(const SpaceArgs &sa);
 size_t sym_bytes(const SpaceArgs &sa);
 fe_status launch_sym_fill(const SpaceArgs &sa, const double *val, double *sym, hipStream_t s);
@@ -312,6 +317,43 @@ __host__ __device__ __forceinline__ int64_t elem_index(int64_t c, int a, int b, 
         e = a * nloc + b;
     }
     return ((c / cb) * int64_t(ne) + e) * cb + c % cb;
+}
+
+// Pattern of the interior-penalty DG system on a brick of n[0] x n[1] (x n[2])
+// cells: the row block of cell K holds the columns of K and of its facet
+// neighbours, cells in ascending id order.
+// Cells K' < K whose index along an axis of stride st and extent n equals v.
+__host__ __device__ __forceinline__ int64_t dg_count_at(int64_t K, int64_t st, int64_t n, int64_t v)
+{
+    const int64_t P = st * n, q = K / P, rem = K % P;
+    int64_t t = rem - v * st;
+    t = t < 0 ? 0 : (t > st ? st : t);
+    return q * st + t;
+}
+
+// Sum over cells K' < K of the cells in the row block of K': (2d + 1) K minus
+// the neighbours missing on the boundary.
+__host__ __device__ __forceinline__ int64_t dg_prefix_n(int dim, int64_t n0, int64_t n1, int64_t n2, int64_t K)
+{
+    const int64_t nr[3] = {n0, n1, n2}, st[3] = {1, n0, n0 * n1};
+    int64_t s = (2 * dim + 1) * K;
+    for (int r = 0; r < dim; r++) s -= dg_count_at(K, st[r], nr[r], 0) + dg_count_at(K, st[r], nr[r], nr[r] - 1);
+    return s;
+}
+
+// The cells of K's row block in ascending id order; returns their number.
+__host__ __device__ __forceinline__ int dg_block_cells(int dim, int64_t n0, int64_t n1, int64_t n2, int64_t K,
+                                                       int64_t cells[7])
+{
+    const int64_t c[3] = {K % n0, (K / n0) % n1, dim == 3 ? K / (n0 * n1) : 0};
+    const int64_t nr[3] = {n0, n1, n2}, st[3] = {1, n0, n0 * n1};
+    int m = 0;
+    for (int r = 2; r >= 0; r--)
+        if (r < dim && c[r] > 0) cells[m++] = K - st[r];
+    cells[m++] = K;
+    for (int r = 0; r < dim; r++)
+        if (c[r] < nr[r] - 1) cells[m++] = K + st[r];
+    return m;
 }
 
 // Job of block blockIdx.x in a launch whose job j owns the blocks

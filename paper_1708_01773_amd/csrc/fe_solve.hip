@@ -1398,9 +1398,23 @@ __device__ __forceinline__ void for_rows_xblock(const SpaceArgs &s, const VT *__
             FE_PLAN_DISPATCH(PL, BODY);                                                        \
         }                                                                                      \
     } while (0)
+// DG systems: kRpb = nodes per cell, kNc = dimension
+#define FE_DG_DISPATCH(PL, BODY)                                                               \
+    switch ((PL).nc * 1000 + (PL).rpb) {                                                       \
+        case 3008: FE_PLAN_CASE(10, 8, 3, BODY)                                                \
+        case 3027: FE_PLAN_CASE(10, 27, 3, BODY)                                               \
+        case 3064: FE_PLAN_CASE(10, 64, 3, BODY)                                               \
+        case 3125: FE_PLAN_CASE(10, 125, 3, BODY)                                              \
+        case 2004: FE_PLAN_CASE(10, 4, 2, BODY)                                                \
+        case 2009: FE_PLAN_CASE(10, 9, 2, BODY)                                                \
+        case 2016: FE_PLAN_CASE(10, 16, 2, BODY)                                               \
+        default: FE_PLAN_CASE(10, 25, 2, BODY)                                                 \
+    }
 #define FE_PLAN_DISPATCH_ALL(PL, BODY)                                                         \
     do {                                                                                       \
-        if ((PL).mode >= 2 && (PL).mode <= 8) {                                                \
+        if ((PL).mode == 10) {                                                                 \
+            FE_DG_DISPATCH(PL, BODY)                                                           \
+        } else if ((PL).mode >= 2 && (PL).mode <= 8) {                                         \
             FE_SPLAN_DISPATCH(PL, BODY)                                                        \
         } else {                                                                               \
             FE_PLAN_DISPATCH(PL, BODY);                                                        \
@@ -1487,6 +1501,112 @@ static SpmvPlan aligned_form(SpmvPlan pl, const void *values)
     return pl;
 }
 
+// Rows of an interior-penalty DG system on the brick (plan mode 10), the
+// pattern evaluated from the cell index: the nn rows of cell K are
+// contiguous in the values, rlen = nc nn entries each (the nn columns of each
+// cell of K's row block, cells ascending), starting at nn^2 times the prefix
+// of block sizes over the cells before K.  Only the values and x are read.
+// The block tiles of the CSR traversal (mode 9) with a cell as the tile: the
+// block stages the x entries of K's row block in LDS, streams the cell's
+// values in passes of kTileCap with 16-byte loads, stages the products in
+// LDS (the column of an entry is its offset in its row, one division per four
+// entries), and LPR lanes of each row sum its staged entries in lane order,
+// then a butterfly.  Cells are dealt XCD-contiguously as tiles are in mode 9.
+template <int DIM, int NN, typename Fn>
+__device__ __forceinline__ void for_rows_dg(const SpaceArgs &s, const double *__restrict__ gval,
+                                            const double *__restrict__ gx, int64_t lb, int64_t nb, Fn f)
+{
+    const FE_GLOBAL double *__restrict__ val = as_global(gval);
+    const FE_GLOBAL double *__restrict__ x = as_global(gx);
+    constexpr int RMAX = (2 * DIM + 1) * NN;  // longest row
+    constexpr int LPR = NN <= 8 ? 32 : (NN <= 16 ? 16 : (NN <= 32 ? 8 : (NN <= 64 ? 4 : 2)));  // LPR NN <= 256
+    static_assert(LPR * NN <= kTileThreads, "lanes per row");
+    __shared__ double prod[kTileCap];
+    __shared__ double xs[RMAX];
+    const int tid = threadIdx.x, lr = tid / LPR, sub = tid % LPR;
+    const int32_t n0 = int32_t(s.ax[0].n), n1 = int32_t(s.ax[1].n), n2 = DIM == 3 ? int32_t(s.ax[2].n) : 1;
+    const int32_t nr[3] = {n0, n1, n2}, st[3] = {1, n0, n0 * n1};
+    const int64_t ncells = s.ncells, nnz = s.nnz;
+    const int64_t xcd = lb % 8, per = nb / 8;
+    const int64_t c_hi = (xcd + 1) * ncells / 8;
+    for (int64_t K64 = xcd * ncells / 8 + lb / 8; K64 < c_hi; K64 += per) {
+        const int32_t K = int32_t(K64);
+        // coordinates, block size and the prefix of block sizes (32-bit: fewer than 2^31 rows)
+        int32_t c[3], prefix = (2 * DIM + 1) * K, nc = 1;
+#pragma unroll
+        for (int r = 0; r < DIM; r++) {
+            const int32_t P = st[r] * nr[r], q = K / P, rem = K - q * P;
+            c[r] = rem / st[r];
+            const int32_t lo = min(max(rem, 0), st[r]), hi = min(max(rem - (nr[r] - 1) * st[r], 0), st[r]);
+            prefix -= 2 * q * st[r] + lo + hi;
+            nc += (c[r] > 0) + (c[r] < nr[r] - 1);
+        }
+        const int32_t rlen = nc * NN;
+        const int64_t base = int64_t(NN) * NN * prefix, end = base + int64_t(NN) * rlen;
+        __syncthreads();  // the previous cell's reads of xs and prod are done
+        // x of the block's cells (slot j: lower neighbours far axis first, K, upper neighbours)
+        for (int t = tid; t < rlen; t += kTileThreads) {
+            int j = t / NN;
+            int32_t cell = -1;
+#pragma unroll
+            for (int r = DIM - 1; r >= 0; r--)
+                if (c[r] > 0 && j-- == 0) cell = K - st[r];
+            if (cell < 0 && j-- == 0) cell = K;
+#pragma unroll
+            for (int r = 0; r < DIM; r++)
+                if (cell < 0 && c[r] < nr[r] - 1 && j-- == 0) cell = K + st[r];
+            xs[t] = x[int64_t(cell) * NN + t % NN];
+        }
+        __syncthreads();
+        const int64_t rb = lr < NN ? base + int64_t(lr) * rlen : end, re = lr < NN ? rb + rlen : end;
+        const float rinv = 1.0f / float(rlen);
+        double acc = 0.0;
+        for (int64_t p0 = base & ~int64_t(3); p0 < end; p0 += kTileCap) {
+            double a[kTileGroups][4];
+#pragma unroll
+            for (int g = 0; g < kTileGroups; g++) {
+                const int64_t e = p0 + 4 * (tid + kTileThreads * g);
+                if (e < end && e + 4 <= nnz) {
+                    const fe_dpair v0 = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(val + e);
+                    const fe_dpair v1 = *reinterpret_cast<const FE_GLOBAL fe_dpair *>(val + e + 2);
+                    a[g][0] = v0.x;
+                    a[g][1] = v0.y;
+                    a[g][2] = v1.x;
+                    a[g][3] = v1.y;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) a[g][j] = e + j < end ? val[e + j] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kTileGroups; g++) {
+                const int64_t e = p0 + 4 * (tid + kTileThreads * g);
+                // column of entry e within its row: (e - base) mod rlen (a lead before base is masked)
+                const int32_t pos = int32_t(e - base);
+                int32_t q = int32_t(float(pos) * rinv);
+                int32_t col = pos - q * rlen;
+                if (col < 0) col += rlen;
+                if (col >= rlen) col -= rlen;
+                double pr[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const bool in = e + j >= base && e + j < end;
+                    pr[j] = in ? a[g][j] * xs[col] : 0.0;
+                    col = col + 1 == rlen ? 0 : col + 1;
+                }
+                reinterpret_cast<fe_dpair *>(prod)[2 * (tid + kTileThreads * g)] = fe_dpair{pr[0], pr[1]};
+                reinterpret_cast<fe_dpair *>(prod)[2 * (tid + kTileThreads * g) + 1] = fe_dpair{pr[2], pr[3]};
+            }
+            __syncthreads();
+            const int64_t s1 = re < p0 + kTileCap ? re : p0 + kTileCap;
+            for (int64_t j = (rb > p0 ? rb : p0) + sub; j < s1; j += LPR) acc += prod[j - p0];
+            __syncthreads();
+        }
+        acc = butterfly<LPR>(acc);
+        if (lr < NN && sub == 0) f(K64 * NN + lr, acc);
+    }
+}
+
 template <int MODE, int RPW, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind,
                                          const VT *val, const double *x, int64_t lb, int64_t nb, Fn f)
@@ -1503,7 +1623,9 @@ __device__ __forceinline__ void for_rows(int64_t n, int64_t nnz, const int64_t *
 template <int MODE, int RPB, int NC, typename VT, typename Fn>
 __device__ __forceinline__ void for_rows_p(const PcgProb &P, const double *x, int64_t lb, int64_t nb, Fn f)
 {
-    if constexpr (MODE == 7 || MODE == 8)
+    if constexpr (MODE == 10)
+        for_rows_dg<NC, RPB>(P.sa, static_cast<const double *>(P.val), x, lb, nb, f);
+    else if constexpr (MODE == 7 || MODE == 8)
         for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(P.sa, static_cast<const VT *>(P.val), x, lb, nb, f);
     else if constexpr (MODE == 6)
         for_rows_xblock<NC, VT>(P.sa, static_cast<const VT *>(P.val), x, lb, nb, f);
@@ -1641,7 +1763,10 @@ __global__ __launch_bounds__(rows_block(MODE)) void spmv_struct_kernel(SpaceArgs
                                                                         const double *__restrict__ x,
                                                                         double *__restrict__ y)
 {
-    if constexpr (MODE == 7 || MODE == 8)
+    if constexpr (MODE == 10)
+        for_rows_dg<NC, RPB>(sa, val, x, xcd_block<MODE>(blockIdx.x, gridDim.x), gridDim.x,
+                             [&](int64_t row, double s) { y[row] = s; });
+    else if constexpr (MODE == 7 || MODE == 8)
         for_rows_q1sym<RPB == 27 ? 3 : 2, MODE == 8>(sa, val, x, xcd_block<MODE>(blockIdx.x, gridDim.x), gridDim.x,
                                                      [&](int64_t row, double s) { y[row] = s; });
     else if constexpr (MODE == 6)
@@ -1904,6 +2029,11 @@ __global__ __launch_bounds__(kBlock) void resid_finish_kernel(const PcgProb *__r
 // ---------------------------------------------------------------------------
 static int grid_rows(int64_t n, const SpmvPlan &pl)
 {
+    if (pl.mode == 10) {  // DG: a block per cell, at most one per partial slot; a multiple of 8 (XCD-contiguous cells)
+        const int64_t ncells = n / pl.rpb;
+        const int64_t cap = part_slots(n) / 8 * 8;
+        return int((std::max<int64_t>(1, std::min<int64_t>(cap, ncells)) + 7) / 8 * 8);
+    }
     if (pl.mode == 9) {  // a block per tile, at most one per partial slot; a multiple of 8 (XCD-contiguous tiles)
         const int64_t tiles = (n + pl.rpb - 1) / pl.rpb;
         const int64_t cap = part_slots(n) / 8 * 8;
@@ -2255,7 +2385,9 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
     std::vector<int> order;
     std::vector<SpmvPlan> plans(njobs);
     for (int i = 0; i < njobs; i++) {
-        if (jobs[i].sa && jobs[i].fp32 && !jobs[i].sym)  // FP32 values: the block-staged traversal
+        if (jobs[i].dg)  // DG: the cell-block traversal
+            plans[i] = SpmvPlan{10, jobs[i].sa->dim, jobs[i].sa->nn, 0};
+        else if (jobs[i].sa && jobs[i].fp32 && !jobs[i].sym)  // FP32 values: the block-staged traversal
             plans[i] = SpmvPlan{6, jobs[i].sa->ncomp, 8, 8};
         else if (jobs[i].sym)
             plans[i] = launch_form(SpmvPlan{7, 1, jobs[i].sa->dim == 3 ? 27 : 9, 2}, jobs[i].n);
@@ -2266,7 +2398,7 @@ fe_status engine_build(EngineSet &E, const PcgJob *jobs, int njobs, void *table,
         if (jobs[i].n > 0) order.push_back(i);
     }
     auto key = [&](int i) {
-        return ((plans[i].mode * 64 + plans[i].rpb) * 4 + plans[i].nc) * 2 + (jobs[i].fp32 ? 1 : 0);
+        return ((plans[i].mode * 1024 + plans[i].rpb) * 4 + plans[i].nc) * 2 + (jobs[i].fp32 ? 1 : 0);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     const int np = int(order.size());
@@ -2534,13 +2666,13 @@ template <typename VT>
 static fe_status pcg_run(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind, const VT *val,
                          const double *dinv, const double *b, double *x, double rtol, int maxit, void *ws,
                          size_t ws_bytes, fe_solve_info *info, hipStream_t s, const SpaceArgs *sa = nullptr,
-                         bool sym = false)
+                         bool sym = false, bool dg = false)
 {
     if (ws_bytes < pcg_ws_bytes(n) + engine_table_bytes(1)) return set_error(FE_EINVAL, "pcg workspace too small");
     if (reinterpret_cast<uintptr_t>(ws) & 7u) return set_error(FE_EINVAL, "workspace not 8-byte aligned");
     std::vector<PcgJob> jobs(1);
     jobs[0] = PcgJob{n, nnz, rowptr, colind, val, std::is_same<VT, float>::value, dinv, b, x, ws, info, rtol, maxit, sa,
-                     sym};
+                     sym, dg};
     void *table = static_cast<char *>(ws) + pcg_ws_bytes(n);
     // small systems are launch-bound: replay the iterations from a HIP graph
     const bool graph = n < (int64_t(1) << 18);
@@ -2664,6 +2796,23 @@ fe_status launch_spmv_struct(const SpaceArgs &sa, const double *val, const doubl
     FE_SPLAN_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(sa, val, x, y)));
     FE_HIP(hipGetLastError());
     return FE_OK;
+}
+
+fe_status launch_spmv_dg(const SpaceArgs &sa, const double *val, const double *x, double *y, hipStream_t s)
+{
+    if (sa.n_rows == 0) return FE_OK;
+    const SpmvPlan pl{10, sa.dim, sa.nn, 0};
+    const int g = grid_rows(sa.n_rows, pl);
+    FE_DG_DISPATCH(pl, (spmv_struct_kernel<kMode, kRpb, kNc><<<dim3(g), dim3(rows_block(kMode)), 0, s>>>(sa, val, x, y)));
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+fe_status pcg_solve_dg(const fe_csr *A, const SpaceArgs &sa, const double *b, double *x, double rtol, int maxit,
+                       void *ws, size_t ws_bytes, fe_solve_info *info, hipStream_t s)
+{
+    return pcg_run<double>(A->n_rows, A->nnz, A->rowptr, A->colind, A->values, A->dinv, b, x, rtol, maxit, ws, ws_bytes,
+                           info, s, &sa, false, true);
 }
 
 size_t pcg_solve_ws_bytes(int64_t n) { return pcg_ws_bytes(n) + engine_table_bytes(1); }

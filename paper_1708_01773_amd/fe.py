@@ -33,7 +33,7 @@ EXPORTS = [
     "fe_spmv_plan_set_mesh", "fe_sym_query", "fe_sym_from_csr", "fe_spmv_sym", "fe_pcg_solve_sym",
     "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set", "fe_pcg_solve_noalloc",
     "fe_refine_solve_mesh", "fe_refine_batch_query", "fe_refine_solve_batch_mesh", "fe_integrate_autotune",
-    "fe_integrate_plan_of", "fe_dg_query", "fe_dg_pattern", "fe_dg_assemble",
+    "fe_integrate_plan_of", "fe_dg_query", "fe_dg_pattern", "fe_dg_assemble", "fe_dg_spmv", "fe_dg_pcg_solve",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -179,6 +179,9 @@ def lib():
             "fe_dg_pattern": [_P, _c.c_int32, _c.POINTER(Csr), _P],
             "fe_dg_assemble": [_P, _c.c_int32, _c.POINTER(Coeff), _c.c_double, _c.c_double, _c.POINTER(Csr), _P,
                                _c.c_size_t, _P],
+            "fe_dg_spmv": [_P, _c.c_int32, _c.POINTER(Csr), _P, _P, _P],
+            "fe_dg_pcg_solve": [_P, _c.c_int32, _c.POINTER(Csr), _P, _P, _c.c_double, _c.c_int32, _P, _c.c_size_t,
+                                _c.POINTER(SolveInfo), _P],
             "fe_refine_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
             "fe_refine_solve_batch_mesh": [_c.c_int32, _c.POINTER(_P), _c.POINTER(_c.c_int32), _c.POINTER(Coeff),
                                            _c.POINTER(Csr), _c.POINTER(Csr), _c.POINTER(_P), _c.POINTER(_P),
@@ -342,6 +345,22 @@ def dg_pattern(mesh, order, csr, stream=None):
 def dg_assemble(mesh, order, coeff, gamma, tau, csr, ws, stream=None):
     _check(lib().fe_dg_assemble(mesh.handle, int(order), _c.byref(coeff), float(gamma), float(tau), _c.byref(csr),
                                 _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "fe_dg_assemble")
+
+
+def dg_spmv(mesh, order, csr, x, y, stream=None):
+    _check(lib().fe_dg_spmv(mesh.handle, int(order), _c.byref(csr), _ptr(x), _ptr(y), _stream(stream)), "fe_dg_spmv")
+
+
+def dg_pcg_solve(mesh, order, csr, b, x, rtol, maxit, ws, stream=None, check=True):
+    """Jacobi-PCG on a DG system with the cell-block SpMV; returns the info dict of pcg_solve."""
+    info = SolveInfo()
+    st = lib().fe_dg_pcg_solve(mesh.handle, int(order), _c.byref(csr), _ptr(b), _ptr(x), float(rtol), int(maxit),
+                               _ptr(ws), ws.numel() * ws.element_size(), _c.byref(info), _stream(stream))
+    out = dict(iters=info.iters, status=info.status, relres=info.relres, true_relres=info.true_relres,
+               lambda_min_est=info.lambda_min_est, lambda_max_est=info.lambda_max_est)
+    if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+        _check(st, "fe_dg_pcg_solve")
+    return out
 
 
 def integrate(mesh, order, coeff, ws, stream=None):
@@ -729,6 +748,13 @@ class DGAssembly:
 
     def assemble(self, stream=None):
         dg_assemble(self.mesh, self.order, self.coeff, self.gamma, self.tau, self.csr, self.ws, stream)
+
+    def spmv(self, x, y, stream=None):
+        dg_spmv(self.mesh, self.order, self.csr, x, y, stream)
+
+    def solve(self, x, rtol, maxit, ws, stream=None):
+        """Jacobi-PCG with the cell-block SpMV (fe_dg_pcg_solve)."""
+        return dg_pcg_solve(self.mesh, self.order, self.csr, self.rhs, x, rtol, maxit, ws, stream)
 
 
 def assemble_batch_query(meshes, orders, coeffs):

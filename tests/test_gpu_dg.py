@@ -6,8 +6,11 @@ the oracle, through the C ABI.
   one cell along an axis): pattern bit-exact; values, rhs and dinv within
   1e-12 relative (Frobenius) of the oracle; for tau = 1 the off-diagonal
   blocks of the two cells of every facet are transposes to the last bit.
-* The solve: Jacobi-PCG on the GPU system against a direct solve of the
-  oracle's system.
+* The cell-block SpMV (pattern evaluated from the cell index) against the
+  oracle's CSR SpMV, element-wise within 1e-12 (|A| |x|), on every small case
+  and on sampled rows of the workload.
+* The solve: Jacobi-PCG on the GPU system (CSR SpMV, and the cell-block
+  SpMV) against a direct solve of the oracle's system.
 * The 48^3 Q2 workload the benchmark times: the rows of sampled cells
   (corners, edges, faces, interior, random) against the oracle run on the
   block of cells around each (the rows of a cell depend only on it and its
@@ -90,6 +93,23 @@ def test_dg_system_matches_oracle(dim, n, k, tau):
         np.testing.assert_array_equal(M.data[off], np.asarray(T[r, c]).ravel())
 
 
+@pytest.mark.parametrize("dim,n,k,tau", CASES, ids=[f"{c[0]}d_{'x'.join(map(str, c[1]))}_q{c[2]}" for c in CASES])
+def test_dg_cell_block_spmv_matches_oracle(dim, n, k, tau):
+    say(f"[dg spmv] dim={dim} n={n} k={k}")
+    v = structured_vertices(dim, n, jitter=0.2, seed=94)
+    mesh, coeff, A = gpu_dg(dim, n, k, v, penalty(k), tau)
+    P = O.Problem(dim, n, k, source_kind=1, source=(1.0,), dirichlet_kind=1, dirichlet_affine=AFF)
+    D = O.DGSystem(P, v, gamma=penalty(k), tau=tau)
+    x = rng(95).standard_normal(A.n_rows)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.full_like(xd, np.nan)
+    A.spmv(xd, y)
+    torch.cuda.synchronize()
+    yo = O.spmv(D.rowptr, D.colind, D.values, x)
+    scale = O.spmv(D.rowptr, D.colind, np.abs(D.values), np.abs(x))
+    assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-12 * scale + 1e-300)
+
+
 @pytest.mark.parametrize("dim,n,k", [(2, [6, 5], 2), (3, [4, 3, 3], 2), (3, [3, 3, 2], 3)])
 def test_dg_pcg_solution_matches_direct_solve_of_oracle(dim, n, k):
     say(f"[dg solve] dim={dim} n={n} k={k}")
@@ -105,6 +125,12 @@ def test_dg_pcg_solution_matches_direct_solve_of_oracle(dim, n, k):
     say(f"iters {info['iters']} true relres {info['true_relres']:.2e}")
     assert info["status"] == 0 and info["true_relres"] <= 1e-11
     assert rel(x.cpu().numpy(), xo) <= 1e-8
+    # the same solve with the cell-block SpMV
+    x2 = torch.zeros_like(x)
+    info2 = A.solve(x2, 1e-12, 20000, ws)
+    say(f"cell-block SpMV: iters {info2['iters']} true relres {info2['true_relres']:.2e}")
+    assert info2["status"] == 0 and info2["true_relres"] <= 1e-11 and abs(info2["iters"] - info["iters"]) <= 2
+    assert rel(x2.cpu().numpy(), xo) <= 1e-8
 
 
 def _block_around(dim, n, c):
@@ -127,7 +153,14 @@ def test_dg_rows_of_sampled_cells_at_workload_size():
     cells += [tuple(int(x) for x in g.integers(0, 48, size=3)) for _ in range(8)]
     rowptr = A.rowptr.cpu().numpy()
     assert rowptr[-1] == A.nnz
+    xs = rng(96).standard_normal(A.n_rows)
+    yd = torch.full((A.n_rows,), np.nan, dtype=torch.float64, device="cuda")
+    A.spmv(torch.from_numpy(xs).cuda(), yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    assert np.isfinite(y).all()
     worst = 0.0
+    worst_spmv = 0.0
     for c in cells:
         K = c[0] + 48 * (c[1] + 48 * c[2])
         lo, m = _block_around(dim, n, c)
@@ -151,5 +184,11 @@ def test_dg_rows_of_sampled_cells_at_workload_size():
         e = rel(vals, D.values[so:se])
         er = rel(A.rhs[K * nn:(K + 1) * nn].cpu().numpy(), D.rhs[kl * nn:(kl + 1) * nn])
         worst = max(worst, e, er)
-    say(f"worst sampled-row rel err {worst:.2e}")
-    assert worst <= MATRIX_RTOL
+        # the cell-block SpMV on these rows: the oracle's row values times x
+        ov = D.values[so:se].reshape(nn, -1)
+        xc = xs[exp_cols.reshape(nn, -1)]
+        yo = (ov * xc).sum(axis=1)
+        scale = (np.abs(ov) * np.abs(xc)).sum(axis=1)
+        worst_spmv = max(worst_spmv, float(np.max(np.abs(y[K * nn:(K + 1) * nn] - yo) / scale)))
+    say(f"worst sampled-row rel err {worst:.2e}, cell-block SpMV {worst_spmv:.2e}")
+    assert worst <= MATRIX_RTOL and worst_spmv <= 1e-12
