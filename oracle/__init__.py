@@ -88,6 +88,8 @@ def lib():
         L.orc_dg_pattern.restype = _i64
         L.orc_dg_assemble.argtypes = [ctypes.POINTER(OrcProblem), _P, _d, _d, _P, _P, _P, _P]
         L.orc_dg_assemble.restype = _i
+        L.orc_stokes_b_element.argtypes = [_i, _i, _P, _P, _P]
+        L.orc_stokes_b_element.restype = _i
         _lib = L
     return _lib
 
@@ -531,6 +533,89 @@ class DGSystem:
     def scipy(self):
         import scipy.sparse as sp
         return sp.csr_matrix((self.values, self.colind, self.rowptr), shape=(self.nfree, self.nfree))
+
+
+def stokes_b_element(dim, k, X):
+    """Divergence block (pressure order k, velocity order k+1; rows pressure
+    nodes, columns local velocity DOFs dim b + c) and pressure mass diagonal
+    of one cell.  Returns (B, md, ok)."""
+    X = _c(X, np.float64).reshape(-1)
+    nnp, nlu = (k + 1) ** dim, dim * (k + 2) ** dim
+    B = np.zeros((nnp, nlu))
+    md = np.zeros(nnp)
+    rc = lib().orc_stokes_b_element(dim, k, _ptr(X), _ptr(B), _ptr(md))
+    if rc == -2:
+        raise ValueError("unsupported dim/order")
+    return B, md, rc == 0
+
+
+class StokesSystem:
+    """Taylor-Hood Stokes on a mesh (the Stokes example of Sect. 3.1):
+    velocity Q_{k+1}^d with zero Dirichlet data on the whole boundary,
+    pressure Q_k with every node free, viscous term mu eps(u):eps(v) (the
+    elasticity system with lambda = 0, its mu = mu / 2: Young's modulus mu,
+    Poisson ratio 0), b(v, q) = -int q div v, body force from source_kind /
+    source.  The system [[A, B^T], [B, 0]] [u; p] = [f; 0] is symmetric and
+    indefinite; the pressure is fixed up to a constant."""
+
+    def __init__(self, dim, n, k, vxyz, mu=1.0, source_kind=1, source=(1.0, 0.0, 0.0)):
+        import scipy.sparse as sp
+        self.dim, self.k, self.mu = int(dim), int(k), float(mu)
+        self.vxyz = _c(vxyz, np.float64)
+        self.Pu = Problem(dim, n, k + 1, problem="elasticity", young=mu, nu=0.0, source_kind=source_kind,
+                          source=source)
+        self.A = System(self.Pu, self.vxyz)
+        self.Pp = Problem(dim, n, k, problem="poisson", faces=0)
+        code, nfp, _ = number_nodes(dim, self.Pp.n, k, 0)
+        self.cdp = cell_dofs(self.Pp, code)
+        self.nu, self.np = self.A.nfree, nfp
+        rows, cols, vals = [], [], []
+        self.md = np.zeros(self.np)
+        self.ok = self.A.ok
+        for K in range(self.Pp.ncells):
+            X = cell_vertices(dim, self.Pp.n, self.vxyz, K)
+            Bk, mdk, ok = stokes_b_element(dim, k, X)
+            self.ok &= ok
+            gp, gu = self.cdp[K], self.A.cell_dofs[K]
+            np.add.at(self.md, gp, mdk)
+            free = gu >= 0
+            R, C = np.meshgrid(gp, gu[free], indexing="ij")
+            rows.append(R.ravel())
+            cols.append(C.ravel())
+            vals.append(Bk[:, free].ravel())
+        self.B = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                               shape=(self.np, self.nu)).tocsr()
+        self.B.sort_indices()
+
+    def matrix(self):
+        import scipy.sparse as sp
+        return sp.bmat([[self.A.scipy(), self.B.T], [self.B, None]]).tocsr()
+
+    def rhs(self):
+        return np.concatenate([self.A.rhs, np.zeros(self.np)])
+
+    def solve(self):
+        """Direct solve with the pressure's DOF sum set to zero (a bordered
+        system).  Returns (u, p)."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        e = np.concatenate([np.zeros(self.nu), np.ones(self.np)])[:, None]
+        Kb = sp.bmat([[self.matrix(), sp.csr_matrix(e)], [sp.csr_matrix(e.T), None]]).tocsc()
+        x = spla.spsolve(Kb, np.concatenate([self.rhs(), [0.0]]))
+        return x[:self.nu], x[self.nu:self.nu + self.np]
+
+    def pressure_nodes(self):
+        """Physical coordinates of the pressure nodes (order-1 map of each cell)."""
+        k, dim = self.k, self.dim
+        out = np.zeros((self.np, dim))
+        for K in range(self.Pp.ncells):
+            X = cell_vertices(dim, self.Pp.n, self.vxyz, K)
+            for a in range(self.Pp.nn):
+                xi = [((a // (k + 1) ** r) % (k + 1)) / k for r in range(dim)]
+                w = np.array([np.prod([xi[r] if (v >> r) & 1 else 1 - xi[r] for r in range(dim)])
+                              for v in range(1 << dim)])
+                out[self.cdp[K][a]] = w @ X
+        return out
 
 
 def coo_compress(rows, cols, vals, n):

@@ -1074,3 +1074,54 @@ int orc_dg_assemble(const orc_problem *P, const double *vxyz, double gamma, doub
     free(wq);
     return bad ? -1 : 0;
 }
+
+/* ======================================================================== */
+/* Taylor-Hood Stokes (the Stokes example of Sect. 3.1; Q_{k+1}^d x Q_k, the */
+/* mixed pair of Sect. 3.8).  Readings: viscous term mu eps(u):eps(v), which  */
+/* is the elasticity element matrix of orc_element_matrix with lambda = 0    */
+/* and its mu set to mu / 2; the continuity equation multiplied by -1, so     */
+/* that the system [[A, B^T], [B, 0]] is symmetric (same solution), with      */
+/* b(v, q) = - int q div v.                                                  */
+/* ======================================================================== */
+/* Divergence block of one cell: B[a * nlu + dim * b + c] =                  */
+/*   - sum_q w_q |det J_q| psi_a(q) d_c phi_b(q)                             */
+/* for the (k+1)^d pressure nodes a (order k) and the (k+2)^d velocity nodes */
+/* b (order k+1), nlu = dim (k+2)^d, on the velocity order's Gauss rule      */
+/* ((k+2)^d points: exact for psi d_c phi on affine cells).  Also            */
+/* md[a] = sum_q w_q |det J_q| psi_a(q)^2, the pressure mass diagonal.       */
+/* Returns -1 if det J <= 0 at a quadrature point, -2 for a bad order.       */
+int orc_stokes_b_element(int dim, int k, const double *X, double *B, double *md)
+{
+    int ku = k + 1, nq1 = ku + 1;
+    if (dim < 2 || dim > 3 || k < 1 || ku > ORC_MAXK) return -2;
+    int nnp = ipow(k + 1, dim), nnu = ipow(ku + 1, dim), nlu = nnu * dim;
+    double gx[ORC_MAXQ1], gw[ORC_MAXQ1];
+    orc_gauss_legendre(nq1, gx, gw);
+    double *phiu = (double *)malloc(sizeof(double) * nnu), *gu = (double *)malloc(sizeof(double) * nnu * dim);
+    double *psi = (double *)malloc(sizeof(double) * nnp), *gp = (double *)malloc(sizeof(double) * nnp * dim);
+    memset(B, 0, sizeof(double) * (size_t)nnp * nlu);
+    memset(md, 0, sizeof(double) * (size_t)nnp);
+    int nq = ipow(nq1, dim), bad = 0;
+    for (int q = 0; q < nq; q++) {
+        int qi[3] = {q % nq1, (q / nq1) % nq1, q / (nq1 * nq1)};
+        double xi[3] = {0, 0, 0}, w = 1.0;
+        for (int r = 0; r < dim; r++) {
+            xi[r] = gx[qi[r]];
+            w *= gw[qi[r]];
+        }
+        orc_qp qu, qpp;
+        if (orc_shape_at(dim, ku, X, xi, phiu, gu, &qu)) bad = 1;
+        orc_shape_at(dim, k, X, xi, psi, gp, &qpp);
+        double wd = w * fabs(qu.detJ);
+        for (int a = 0; a < nnp; a++) {
+            md[a] += wd * psi[a] * psi[a];
+            for (int b = 0; b < nnu; b++)
+                for (int c = 0; c < dim; c++) B[a * nlu + dim * b + c] -= wd * psi[a] * gu[b * dim + c];
+        }
+    }
+    free(phiu);
+    free(gu);
+    free(psi);
+    free(gp);
+    return bad ? -1 : 0;
+}

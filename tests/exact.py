@@ -197,3 +197,38 @@ def dg_box_matrix(dim, k, n, gamma, tau):
                 fac = np.outer(v0, d0) / h[r] + tau * np.outer(d0, v0) / h[r] + sg * np.outer(v0, v0)
                 A[K * nn:(K + 1) * nn, K * nn:(K + 1) * nn] += face_block(r, fac)
     return A
+
+
+def mixed_matrices_1d(kp, ku):
+    """1D matrices between the order-kp basis (rows) and the order-ku basis
+    (columns), computed exactly: Mx_ij = int l^kp_i l^ku_j and
+    Gx_ij = int l^kp_i (l^ku_j)'."""
+    Lp, Lu = lagrange_polys(kp), lagrange_polys(ku)
+    Du = [polyder(p) for p in Lu]
+    Mx = np.array([[float(int01(polymul(Lp[i], Lu[j]))) for j in range(ku + 1)] for i in range(kp + 1)])
+    Gx = np.array([[float(int01(polymul(Lp[i], Du[j]))) for j in range(ku + 1)] for i in range(kp + 1)])
+    return Mx, Gx
+
+
+def stokes_box_b_element(dim, k, h):
+    """Divergence block -int psi_a d_c phi_b of an axis-aligned box cell with
+    sides h (pressure order k, velocity order k+1, local velocity DOF
+    dim b + c), and the pressure mass diagonal, as Kronecker products of the
+    exact 1D matrices: the derivative along c brings 1/h_c, the measure h_c."""
+    Mx, Gx = mixed_matrices_1d(k, k + 1)
+    _, Mp, _ = matrices_1d(k)
+    kp1, ku1 = k + 1, k + 2
+    nnp, nnu = kp1 ** dim, ku1 ** dim
+    B = np.zeros((nnp, dim * nnu))
+    md = np.zeros(nnp)
+    for a in range(nnp):
+        ai = [(a // kp1 ** r) % kp1 for r in range(dim)]
+        md[a] = np.prod([h[r] * Mp[ai[r], ai[r]] for r in range(dim)])
+        for b in range(nnu):
+            bi = [(b // ku1 ** r) % ku1 for r in range(dim)]
+            for c in range(dim):
+                v = 1.0
+                for r in range(dim):
+                    v *= Gx[ai[r], bi[r]] if r == c else h[r] * Mx[ai[r], bi[r]]
+                B[a, dim * b + c] = -v
+    return B, md

@@ -16,6 +16,7 @@ import oracle as O
 from oracle import build as OB
 from tests import test_oracle_dg as DG
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_stokes as ST
 
 MUTANTS = {
     "transposed_inverse_jacobian": ("g += Ji[s * dim + i] * gref[s];", "g += Ji[i * dim + s] * gref[s];"),
@@ -41,6 +42,11 @@ MUTANTS = {
     "dg_boundary_load_tau_sign": ("rhs[K * nn + a] += W * (-tau * uD * dna", "rhs[K * nn + a] += W * (tau * uD * dna"),
     "l2_error_dropped_weight": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                 "err2 += fabs(qp.detJ) * (ue - uh) * (ue - uh);"),
+    "stokes_divergence_sign": ("B[a * nlu + dim * b + c] -= wd * psi[a] * gu[b * dim + c];",
+                               "B[a * nlu + dim * b + c] += wd * psi[a] * gu[b * dim + c];"),
+    "stokes_dropped_jacobian": ("double wd = w * fabs(qu.detJ);\n        for (int a = 0; a < nnp; a++) {\n            md[a]",
+                                "double wd = w;\n        for (int a = 0; a < nnp; a++) {\n            md[a]"),
+    "stokes_wrong_velocity_component": ("wd * psi[a] * gu[b * dim + c];", "wd * psi[a] * gu[b * dim + (c + 1) % dim];"),
     "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                   "err2 += w * (ue - uh) * (ue - uh);"),
 }
@@ -62,6 +68,8 @@ PIN_CALLS = [
     lambda: PINS.test_l2_norm_of_vector_field_sums_components(),
     lambda: DG.test_dg_box_matrix_closed_form(2, [3, 2], 3, 1.0),
     lambda: DG.test_dg_linear_patch_test(2, [3, 4], 1),
+    lambda: ST.test_b_element_box_closed_form(2, 2),
+    lambda: ST.test_constant_force_is_balanced_by_an_affine_pressure(2, [3, 4], 1),
 ]
 
 
