@@ -320,6 +320,59 @@ fe_status fe_dg_pcg_solve(fe_mesh mesh, int32_t order, const fe_csr *A, const do
                           int32_t maxit, void *ws, size_t ws_bytes, fe_solve_info *info, fe_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* Taylor-Hood Stokes (the Stokes example of Sect. 3.1; the mixed pair       */
+/* Q_{k+1}^d x Q_k from the scalar spaces of Sect. 3.8)                      */
+/* ------------------------------------------------------------------------ */
+/* Find velocity u (order k+1, d components, zero on the whole boundary) and
+ * pressure p (order k, every node free) with
+ *   int mu eps(u):eps(v) - int p div v = int f . v,   - int q div u = 0
+ * for all v, q: the symmetric indefinite system [[A, B^T], [B, 0]] [u; p] =
+ * [f; 0], A the elasticity matrix of order k+1 with lambda = 0, B_(a),(b,c) =
+ * -int psi_a d_c phi_b on the velocity order's Gauss rule.  The pressure is
+ * fixed up to a constant (the solve returns one solution).
+ * DOFs: velocity as the vector space of fe.h's numbering with every face
+ * fixed (dim components interleaved), pressure as the scalar lattice with no
+ * fixed node. */
+typedef struct fe_stokes_s *fe_stokes; /* opaque, library-owned */
+
+/* Builds both spaces, the patterns of A, B and B^T and the gather maps of
+ * B's entries (made once on the host: every CSR entry's element
+ * contributions in ascending cell order), and allocates the system and
+ * solver storage on the device (owned by the handle).  order = k, the
+ * pressure order, in 1..3; mu > 0; force: source_kind / source as in
+ * fe_coeff (NULL: no force).  Synchronous.  The mesh must outlive the handle. */
+fe_status fe_stokes_create(fe_mesh mesh, int32_t order, double mu, const fe_coeff *force, fe_stokes *out);
+fe_status fe_stokes_destroy(fe_stokes s);
+
+/* Velocity unknowns, pressure unknowns, nonzeros of A and of B.  Host only. */
+fe_status fe_stokes_query(fe_stokes s, int64_t *n_u, int64_t *n_p, int64_t *nnz_a, int64_t *nnz_b);
+
+/* Numeric phase: A (the integration and scatter kernels), the element
+ * blocks of B, B and B^T by deterministic gathers (bitwise reproducible), the
+ * pressure mass diagonal, the rhs [f; 0] and the preconditioner.  Enqueues
+ * only; det J <= 0 is reported by the next fe_get_status of the mesh. */
+fe_status fe_stokes_assemble(fe_stokes s, fe_stream stream);
+
+/* Device views of the assembled system (owned by the handle, valid until it
+ * is destroyed): A (rows n_u, with rhs = the first n_u entries of the
+ * system's rhs and dinv), B (n_p x n_u; rhs and dinv NULL), B^T (n_u x n_p),
+ * the pressure mass diagonal md (n_p) and the whole rhs (n_u + n_p).  Any
+ * pointer may be NULL. */
+fe_status fe_stokes_system(fe_stokes s, fe_csr *A, fe_csr *B, fe_csr *Bt, const double **md, const double **rhs);
+
+/* MINRES on the Stokes system (a Lanczos process on the preconditioned
+ * operator, its tridiagonal reduced by Givens rotations), preconditioned by
+ * diag(A)^-1 on the velocity and mu / md on the pressure.  u (n_u) and p
+ * (n_p), device: the initial guess on entry, the solution on exit.  Stops when
+ * ||r||_{M^-1} <= rtol ||b||_{M^-1} (the recurrence's estimate; info->relres)
+ * or after maxit iterations; info->true_relres recomputes it from K x.
+ * Dot products are deterministic (fixed partials summed in a fixed order).
+ * Synchronous.  FE_ENOTCONV at maxit, FE_EBREAKDOWN if the preconditioned
+ * Lanczos process breaks down. */
+fe_status fe_stokes_solve(fe_stokes s, double rtol, int32_t maxit, double *u, double *p, fe_solve_info *info,
+                          fe_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched solve: many independent systems in one sequence of launches       */
 /* ------------------------------------------------------------------------ */
 /* Workspace bytes fe_pcg_solve_batch needs for nprob systems of n_rows[i]

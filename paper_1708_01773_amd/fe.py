@@ -34,6 +34,8 @@ EXPORTS = [
     "fe_sym_fp32_from_csr", "fe_refine_solve_sym", "fe_spmv_plan_set", "fe_pcg_solve_noalloc",
     "fe_refine_solve_mesh", "fe_refine_batch_query", "fe_refine_solve_batch_mesh", "fe_integrate_autotune",
     "fe_integrate_plan_of", "fe_dg_query", "fe_dg_pattern", "fe_dg_assemble", "fe_dg_spmv", "fe_dg_pcg_solve",
+    "fe_stokes_create", "fe_stokes_destroy", "fe_stokes_query", "fe_stokes_assemble", "fe_stokes_system",
+    "fe_stokes_solve",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -180,6 +182,14 @@ def lib():
             "fe_dg_assemble": [_P, _c.c_int32, _c.POINTER(Coeff), _c.c_double, _c.c_double, _c.POINTER(Csr), _P,
                                _c.c_size_t, _P],
             "fe_dg_spmv": [_P, _c.c_int32, _c.POINTER(Csr), _P, _P, _P],
+            "fe_stokes_create": [_P, _c.c_int32, _c.c_double, _c.POINTER(Coeff), _c.POINTER(_P)],
+            "fe_stokes_destroy": [_P],
+            "fe_stokes_query": [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                _c.POINTER(_c.c_int64)],
+            "fe_stokes_assemble": [_P, _P],
+            "fe_stokes_system": [_P, _c.POINTER(Csr), _c.POINTER(Csr), _c.POINTER(Csr), _c.POINTER(_P),
+                                 _c.POINTER(_P)],
+            "fe_stokes_solve": [_P, _c.c_double, _c.c_int32, _P, _P, _c.POINTER(SolveInfo), _P],
             "fe_dg_pcg_solve": [_P, _c.c_int32, _c.POINTER(Csr), _P, _P, _c.c_double, _c.c_int32, _P, _c.c_size_t,
                                 _c.POINTER(SolveInfo), _P],
             "fe_refine_batch_query": [_c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_size_t)],
@@ -755,6 +765,73 @@ class DGAssembly:
     def solve(self, x, rtol, maxit, ws, stream=None):
         """Jacobi-PCG with the cell-block SpMV (fe_dg_pcg_solve)."""
         return dg_pcg_solve(self.mesh, self.order, self.csr, self.rhs, x, rtol, maxit, ws, stream)
+
+
+def _copy_to_host(out, ptr):
+    """Copies device memory at ptr into the numpy array out (hipMemcpy through
+    the HIP runtime libfe.so is linked against)."""
+    L = lib()
+    f = L.hipMemcpy
+    f.argtypes = [_P, _P, _c.c_size_t, _c.c_int]
+    f.restype = _c.c_int
+    if f(out.ctypes.data_as(_P), _c.c_void_p(ptr), out.nbytes, 2) != 0:  # hipMemcpyDeviceToHost
+        raise FeError(FE_EDEVICE, "hipMemcpy", "copy to the host failed")
+
+
+class Stokes:
+    """Owning wrapper of an fe_stokes handle (Taylor-Hood Q_{k+1}^d x Q_k on a
+    mesh): assemble(), system() device views as torch tensors, solve()."""
+
+    def __init__(self, mesh, order, mu=1.0, source_kind=FE_SOURCE_NONE, source=(0.0, 0.0, 0.0)):
+        self.mesh, self.order, self.mu = mesh, int(order), float(mu)
+        c = make_coeff("elasticity", "fp64", source_kind=source_kind, source=source, dim=mesh.dim)
+        h = _P()
+        _check(lib().fe_stokes_create(mesh.handle, self.order, self.mu, _c.byref(c), _c.byref(h)),
+               "fe_stokes_create")
+        self.handle = h
+        nu, np_, na, nb = _c.c_int64(), _c.c_int64(), _c.c_int64(), _c.c_int64()
+        _check(lib().fe_stokes_query(h, _c.byref(nu), _c.byref(np_), _c.byref(na), _c.byref(nb)), "fe_stokes_query")
+        self.n_u, self.n_p, self.nnz_a, self.nnz_b = nu.value, np_.value, na.value, nb.value
+
+    def assemble(self, stream=None):
+        _check(lib().fe_stokes_assemble(self.handle, _stream(stream)), "fe_stokes_assemble")
+
+    def system(self):
+        """Host copies (numpy) of A (CSR arrays), B, B^T, md and the rhs."""
+        import numpy as np
+        import torch
+        A, B, Bt = Csr(), Csr(), Csr()
+        md, rhs = _P(), _P()
+        _check(lib().fe_stokes_system(self.handle, _c.byref(A), _c.byref(B), _c.byref(Bt), _c.byref(md),
+                                      _c.byref(rhs)), "fe_stokes_system")
+        torch.cuda.synchronize()
+
+        def dev(ptr, n, dtype):
+            out = np.empty(n, dtype=dtype)
+            if n > 0:
+                _copy_to_host(out, ptr)
+            return out
+
+        def csr(C):
+            return (dev(C.rowptr, C.n_rows + 1, np.int64), dev(C.colind, C.nnz, np.int32),
+                    dev(C.values, C.nnz, np.float64))
+        return dict(A=csr(A), B=csr(B), Bt=csr(Bt), md=dev(md.value, self.n_p, np.float64),
+                    rhs=dev(rhs.value, self.n_u + self.n_p, np.float64), dinv=dev(A.dinv, self.n_u, np.float64))
+
+    def solve(self, u, p, rtol, maxit, stream=None, check=True):
+        info = SolveInfo()
+        st = lib().fe_stokes_solve(self.handle, float(rtol), int(maxit), _ptr(u), _ptr(p), _c.byref(info),
+                                   _stream(stream))
+        out = dict(iters=info.iters, status=info.status, relres=info.relres, true_relres=info.true_relres)
+        if check and st not in (FE_OK, FE_ENOTCONV, FE_EBREAKDOWN):
+            _check(st, "fe_stokes_solve")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            lib().fe_stokes_destroy(h)
+            self.handle = None
 
 
 def assemble_batch_query(meshes, orders, coeffs):
