@@ -538,6 +538,123 @@ def dg_form(args, F, torch, steps=3, warmup=1):
     return out
 
 
+STOKES_WORKLOAD = dict(dim=3, n=24, k=1, mu=1.0, rtol=1e-8,
+                       text="Taylor-Hood Stokes (Q2^3 velocity x Q1 pressure) on the unit cube, 24^3 hexes jittered "
+                            "+-0.2h (seed 17080), mu = 1, f = 3 pi^2 prod sin(pi x_r) (1, -0.5, 0.25), u = 0 on the "
+                            "boundary, FP64 assembly + block-Jacobi-preconditioned MINRES to rtol 1e-8")
+
+
+def stokes_iteration_bytes(nu, np_, nnz_a, nnz_b):
+    """Algorithmic bytes of one MINRES iteration: the A SpMV (pattern
+    evaluated: 8 nnz + 16 n_u), the B^T and B SpMVs (CSR: 12 nnz + row
+    pointers + x + y each), the B^T product added to A x (24 n_u), the dot
+    product (16 n), the Lanczos update (48 n), the solution update (48 n) and
+    the rescaling (32 n), n = n_u + n_p."""
+    n = nu + np_
+    spmv_b = 12 * nnz_b + 8 * (nu + 1) + 8 * np_ + 8 * nu + 12 * nnz_b + 8 * (np_ + 1) + 8 * nu + 8 * np_
+    return 8 * nnz_a + 16 * nu + spmv_b + 24 * nu + (16 + 48 + 48 + 32) * n
+
+
+def stokes_cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=8, its=100):
+    """The oracle's Stokes system on an n^3 mesh of the same recipe (its
+    assembly, single-threaded) and MINRES on it (scipy's, the library
+    routine, with the same block-diagonal preconditioner; a fixed number of
+    iterations), scaled to the full workload like the other baselines."""
+    import numpy as np
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    import oracle as O
+    from fe_inputs import structured_vertices
+    v = structured_vertices(3, n, jitter=0.2)
+    t0 = time.perf_counter()
+    S = O.StokesSystem(3, [n] * 3, wl["k"], v, mu=wl["mu"], source_kind=2, source=(1.0, -0.5, 0.25))
+    t_asm = time.perf_counter() - t0
+    K = S.matrix()
+    d = np.concatenate([1.0 / S.A.scipy().diagonal(), wl["mu"] / S.md])
+    M = sp.diags(d)
+    t0 = time.perf_counter()
+    spla.minres(K, S.rhs(), M=M, maxiter=its, rtol=0.0)
+    t_it = (time.perf_counter() - t0) / its
+    step = t_asm / S.Pp.ncells * ncells_full + t_it * (nnz_full / K.nnz) * gpu_iters
+    return {"value": 1.0 / step, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle Stokes system at {n}^3 Q{wl['k'] + 1}-Q{wl['k']} ({S.Pp.ncells} cells, nnz {K.nnz}): "
+                      f"assembly single-threaded ({t_asm:.2f} s), {its} iterations of scipy's MINRES with the same "
+                      f"preconditioner ({t_it * 1e3:.2f} ms each); the full solve scaled as cells x assembly time "
+                      f"per cell + {gpu_iters:.0f} iterations x per-iteration time x nnz ratio",
+            "step_s_scaled": step}
+
+
+def stokes_form(args, F, torch, steps=3, warmup=1):
+    """The Stokes workload: a step is the block assembly (velocity block,
+    divergence blocks, gathers) + MINRES, set-up (spaces, patterns, gather
+    maps) once before timing.  The MINRES iteration's roofline counts the
+    bytes of all its kernels over its wall-clock time."""
+    from fe_inputs import structured_vertices
+    wl = STOKES_WORKLOAD
+    dim, n, k = wl["dim"], wl["n"], wl["k"]
+    v = structured_vertices(dim, n, jitter=0.2)
+    mesh = F.create_mesh(dim, [n] * dim, v)
+    t0 = time.perf_counter()
+    S = F.Stokes(mesh, k, mu=wl["mu"], source_kind=2, source=(1.0, -0.5, 0.25))
+    t_setup = time.perf_counter() - t0
+    u = torch.zeros(S.n_u, dtype=torch.float64, device="cuda")
+    p = torch.zeros(S.n_p, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    print(f"[bench] Stokes form: cells={n ** dim} velocity={S.n_u} pressure={S.n_p} nnz A={S.nnz_a} B={S.nnz_b}",
+          file=sys.stderr, flush=True)
+
+    def step():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.assemble(stream)
+        e1.record(stream)
+        u.zero_()
+        p.zero_()
+        ts = time.perf_counter()
+        info = S.solve(u, p, wl["rtol"], 20000, stream)
+        return info, e0, e1, time.perf_counter() - ts
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, asm, solve_s, iters = [], [], [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        info, e0, e1, ds = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        asm.append(e0.elapsed_time(e1))
+        solve_s.append(ds)
+        iters.append(info["iters"])
+        print(f"[bench] Stokes step {i}: {lat[-1] * 1e3:.1f} ms, {info['iters']} MINRES iterations", file=sys.stderr,
+              flush=True)
+    total = time.perf_counter() - t0
+    assert F.get_status(mesh) == F.FE_OK
+    it_s = statistics.mean(solve_s) / max(statistics.mean(iters), 1)
+    ib = stokes_iteration_bytes(S.n_u, S.n_p, S.nnz_a, S.nnz_b)
+    out = {
+        "workload": wl["text"], "cells": n ** dim, "velocity_dofs": S.n_u, "pressure_dofs": S.n_p,
+        "nnz_a": S.nnz_a, "nnz_b": S.nnz_b, "steps": steps, "solves_per_s": steps / total,
+        "ms_per_step": total / steps * 1e3, "minres_iters": statistics.mean(iters), "relres": info["relres"],
+        "true_relres": info["true_relres"], "setup_s": t_setup,
+        "assembly_ms": statistics.mean(asm),
+        "roofline_minres_iteration": {"kernels": "A SpMV (evaluated pattern), B and B^T SpMVs (CSR), vector kernels",
+                                      "bound": "hbm", "achieved": ib / it_s / 1e9, "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": ib / it_s / 1e9 / HBM_PEAK_GBS,
+                                      "algorithmic_bytes_per_iteration": ib, "avg_iteration_us": it_s * 1e6,
+                                      "timing": "wall clock of the solve over its iterations (two host reads of "
+                                                "scalars per iteration included)"},
+    }
+    del S, u, p
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle's Stokes system on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = stokes_cpu_baseline(wl, statistics.mean(iters), n ** dim, out["nnz_a"] + 2 * out["nnz_b"])
+    return out
+
+
 def peak_probe(torch):
     """Achievable rates of this GPU, measured, to set the published peaks the
     roofline uses in context: a 1 GiB device copy and a 4 GiB read (a sum) in
@@ -760,7 +877,7 @@ def main():
                     help="thin the stream to requests of at most this many unknowns (default: every request)")
     ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg"],
+    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg", "stokes"],
                     help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -798,6 +915,10 @@ def main():
     if args.form == "serve":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "serve", **serve_form(args, F, torch)}), flush=True)
+        return
+    if args.form == "stokes":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "stokes", **stokes_form(args, F, torch)}), flush=True)
         return
     if args.form == "dg":
         torch.cuda.set_device(0)
@@ -945,6 +1066,8 @@ def main():
             out["forms"]["serve"] = serve_form(args, F, torch)
         print("[bench] DG form", file=sys.stderr, flush=True)
         out["forms"]["dg"] = dg_form(args, F, torch)
+        print("[bench] Stokes form", file=sys.stderr, flush=True)
+        out["forms"]["stokes"] = stokes_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, out["config"]["nnz"])
