@@ -12,6 +12,13 @@ returns.  Recipe (stated once here, used everywhere):
   (not on the boundary) moves by ``rng.uniform(-jitter, jitter, size=(n_int, d)) * h``
   drawn in vertex-lexicographic order, one row per interior vertex; boundary
   vertices stay put.  The workloads use jitter 0.2 (i.e. +-0.2 h).
+* Simplicial mesh (``simplex_mesh``): the Kuhn (Freudenthal) subdivision of
+  the brick above, with the jittered vertices: every cell (lexicographic
+  order) splits into d! simplices, one per permutation pi of the axes (in
+  ``itertools.permutations`` order), with vertices c, c + e_pi0,
+  c + e_pi0 + e_pi1, ... (the cell's lower corner c).  With ``shuffle`` the
+  vertex labels, the cell order and each cell's local vertex order are
+  permuted at random (seed 17084): the same mesh as general connectivity.
 * Coefficients: per-cell ``exp(rng.standard_normal(ncells))`` (lognormal,
   cell-lexicographic order), or all ones.
 * Seeds: jitter 17080, coefficients 17081, batch sampling 17082, arrivals
@@ -24,6 +31,7 @@ SEED_JITTER = 17080
 SEED_COEF = 17081
 SEED_BATCH = 17082
 SEED_ARRIVALS = 17083
+SEED_SHUFFLE = 17084
 
 
 def rng(seed):
@@ -98,3 +106,39 @@ def serving_requests(nreq, rate, seed=SEED_ARRIVALS, nmin=8, nmax=96, kmax=4):
     ns = np.rint(np.exp(g.uniform(np.log(nmin), np.log(nmax), size=nreq))).astype(int)
     ks = g.integers(1, kmax + 1, size=nreq)
     return [(float(a), int(b), int(c)) for a, b, c in zip(t, ns, ks)]
+
+
+def simplex_mesh(dim, n, jitter=0.0, seed=SEED_JITTER, shuffle=False, shuffle_seed=SEED_SHUFFLE):
+    """(vertices (nverts x dim) float64, cells (ncells x (dim+1)) int32) of the
+    Kuhn subdivision of the n^d brick."""
+    import itertools
+    n = _dims(dim, n)
+    v = structured_vertices(dim, n, jitter, seed)
+    perms = list(itertools.permutations(range(dim)))
+    if dim == 2:
+        j, i = np.meshgrid(np.arange(n[1]), np.arange(n[0]), indexing="ij")
+        base = (i + (n[0] + 1) * j).ravel()
+        stride = [1, n[0] + 1]
+    else:
+        l, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+        base = (i + (n[0] + 1) * (j + (n[1] + 1) * l)).ravel()
+        stride = [1, n[0] + 1, (n[0] + 1) * (n[1] + 1)]
+    cells = np.zeros((base.size, len(perms), dim + 1), dtype=np.int64)
+    for p, pi in enumerate(perms):
+        off = 0
+        cells[:, p, 0] = base
+        for t, axis in enumerate(pi):
+            off += stride[axis]
+            cells[:, p, t + 1] = base + off
+    cells = cells.reshape(-1, dim + 1)
+    if shuffle:
+        g = rng(shuffle_seed)
+        relabel = g.permutation(v.shape[0])
+        v2 = np.empty_like(v)
+        v2[relabel] = v
+        v = v2
+        cells = relabel[cells]
+        cells = cells[g.permutation(cells.shape[0])]
+        order = np.argsort(g.random(cells.shape), axis=1)
+        cells = np.take_along_axis(cells, order, axis=1)
+    return np.ascontiguousarray(v), np.ascontiguousarray(cells.astype(np.int32))

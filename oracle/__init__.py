@@ -47,6 +47,20 @@ class OrcProblem(ctypes.Structure):
     ]
 
 
+class OrcSxProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", _i),
+        ("k", _i),
+        ("problem", _i),
+        ("lam", _d),
+        ("mu", _d),
+        ("source_kind", _i),
+        ("source", _d * 3),
+        ("dirichlet_kind", _i),
+        ("dirichlet_affine", _d * 12),
+    ]
+
+
 def lib():
     """Load (building on first use) the oracle shared library."""
     global _lib
@@ -90,6 +104,28 @@ def lib():
         L.orc_dg_assemble.restype = _i
         L.orc_stokes_b_element.argtypes = [_i, _i, _P, _P, _P]
         L.orc_stokes_b_element.restype = _i
+        L.orc_sx_nodes.argtypes = [_i, _i, _P]
+        L.orc_sx_nodes.restype = _i
+        L.orc_sx_basis.argtypes = [_i, _i, _P]
+        L.orc_sx_basis.restype = _i
+        L.orc_sx_shape.argtypes = [_i, _i, _P, _P, _P]
+        L.orc_sx_shape.restype = _i
+        L.orc_sx_quadrature.argtypes = [_i, _i, _P, _P]
+        L.orc_sx_quadrature.restype = _i
+        L.orc_sx_element_matrix.argtypes = [_i, _i, _i, _P, _d, _d, _d, _P]
+        L.orc_sx_element_matrix.restype = _i
+        L.orc_sx_element_load.argtypes = [_i, _i, _i, _P, _i, _P, _P]
+        L.orc_sx_element_load.restype = _i
+        L.orc_sx_number.argtypes = [_i, _i, _i64, _i64, _P, _i, _P, _P, _P, _P, _P]
+        L.orc_sx_number.restype = _i
+        L.orc_sx_cell_dofs.argtypes = [_i, _i, _i, _i64, _P, _P, _P]
+        L.orc_sx_cell_dofs.restype = None
+        L.orc_sx_node_positions.argtypes = [_i, _i, _i64, _P, _P, _P, _P]
+        L.orc_sx_node_positions.restype = None
+        L.orc_sx_assemble.argtypes = [ctypes.POINTER(OrcSxProblem), _P, _i64, _P, _P, _P, _i64, _P, _P, _P, _P]
+        L.orc_sx_assemble.restype = _i
+        L.orc_sx_l2_error.argtypes = [ctypes.POINTER(OrcSxProblem), _P, _i64, _P, _P, _P, _i, _i, _P]
+        L.orc_sx_l2_error.restype = _d
         _lib = L
     return _lib
 
@@ -655,3 +691,161 @@ def lanczos_extremes(alphas, betas):
             T[j, j + 1] = T[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
     ev = np.linalg.eigvalsh(T)
     return float(ev[0]), float(ev[-1])
+
+
+# ---------------------------------------------------------------------------
+# Lagrangian P_k on simplicial meshes (fe_oracle_simplex.c)
+# ---------------------------------------------------------------------------
+def simplex_nn(dim, k):
+    """Number of nodes of P_k on the d-simplex."""
+    return (k + 1) * (k + 2) // 2 if dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
+
+
+def simplex_nodes(dim, k):
+    """Lattice points s (nn x dim, integers) of the local nodes, in local order."""
+    s = np.zeros(3 * 64, dtype=np.int32)
+    nn = lib().orc_sx_nodes(dim, k, _ptr(s))
+    return s[: 3 * nn].reshape(nn, 3)[:, :dim].copy()
+
+
+def simplex_basis(dim, k):
+    """Change-of-basis matrix Phi (nn x nn): phi_a = sum_b Phi_ab xi^(alpha_b)."""
+    nn = simplex_nn(dim, k)
+    Phi = np.zeros((nn, nn))
+    if lib().orc_sx_basis(dim, k, _ptr(Phi)) != nn:
+        raise ValueError("unsupported dim/order")
+    return Phi
+
+
+def simplex_shape(dim, k, xi):
+    """Reference shape values (nn) and gradients (nn x dim) at xi."""
+    nn = simplex_nn(dim, k)
+    x = _c(list(xi) + [0.0] * (3 - len(xi)), np.float64)
+    phi = np.zeros(nn)
+    d = np.zeros((nn, dim))
+    lib().orc_sx_shape(dim, k, _ptr(x), _ptr(phi), _ptr(d))
+    return phi, d
+
+
+def simplex_quadrature(dim, n):
+    """Collapsed Gauss rule: points (n^d x dim) and weights on the reference simplex."""
+    nq = n ** dim
+    xi = np.zeros((nq, 3))
+    w = np.zeros(nq)
+    lib().orc_sx_quadrature(dim, n, _ptr(xi), _ptr(w))
+    return xi[:, :dim].copy(), w
+
+
+def simplex_element_matrix(dim, k, X, coef=1.0, problem="poisson", young=1.0, nu=0.3):
+    """Element matrix on the simplex with vertices X ((d+1) x d); (A, ok)."""
+    X = _c(X, np.float64).reshape(-1)
+    ncomp = dim if problem == "elasticity" else 1
+    nloc = simplex_nn(dim, k) * ncomp
+    A = np.zeros((nloc, nloc))
+    lam, mu = lame(young, nu) if problem == "elasticity" else (0.0, 0.0)
+    rc = lib().orc_sx_element_matrix(dim, k, 1 if problem == "elasticity" else 0, _ptr(X), float(coef), lam, mu,
+                                     _ptr(A))
+    if rc == -2:
+        raise ValueError("unsupported dim/order")
+    return A, rc == 0
+
+
+def simplex_element_load(dim, k, ncomp, X, source_kind, source):
+    X = _c(X, np.float64).reshape(-1)
+    src = _c(list(source) + [0.0] * (3 - len(source)), np.float64)
+    f = np.zeros(simplex_nn(dim, k) * ncomp)
+    lib().orc_sx_element_load(dim, k, ncomp, _ptr(X), int(source_kind), _ptr(src), _ptr(f))
+    return f
+
+
+def simplex_number(dim, k, nverts, cells, dirichlet=True):
+    """(node_of (ncells x nn), node_code (nnodes), nfree, nfixed)."""
+    cells = _c(cells, np.int32)
+    nc = cells.shape[0]
+    nn = simplex_nn(dim, k)
+    node_of = np.zeros((nc, nn), dtype=np.int64)
+    code = np.zeros(max(nc * nn, 1), dtype=np.int64)
+    nnodes, nf, nx = _i64(), _i64(), _i64()
+    rc = lib().orc_sx_number(dim, k, int(nverts), nc, _ptr(cells), 1 if dirichlet else 0, _ptr(node_of),
+                             _ptr(code), ctypes.byref(nnodes), ctypes.byref(nf), ctypes.byref(nx))
+    if rc != 0:
+        raise ValueError(f"orc_sx_number failed ({rc})")
+    return node_of, code[: nnodes.value].copy(), nf.value, nx.value
+
+
+class SimplexSystem:
+    """The oracle's free-free system of P_k on a simplicial mesh.
+
+    verts (nverts x dim), cells (ncells x (dim+1)) int; coef per cell or None;
+    problem 'poisson' / 'elasticity'; dirichlet: fix every boundary node;
+    dirichlet_kind 0 zero, 1 affine (u_D,c = aff[4c] + sum_r aff[4c+1+r] x_r)."""
+
+    def __init__(self, dim, k, verts, cells, coef=None, problem="poisson", young=1.0, nu=0.3, source_kind=0,
+                 source=(0.0, 0.0, 0.0), dirichlet=True, dirichlet_kind=0, dirichlet_affine=None):
+        self.dim, self.k, self.problem = int(dim), int(k), problem
+        self.verts = _c(verts, np.float64)
+        self.cells = _c(cells, np.int32)
+        self.coef = None if coef is None else _c(coef, np.float64)
+        self.ncomp = dim if problem == "elasticity" else 1
+        self.nn = simplex_nn(dim, k)
+        self.nloc = self.nn * self.ncomp
+        self.node_of, self.node_code, self.nfree_nodes, self.nfixed_nodes = simplex_number(
+            dim, k, self.verts.shape[0], self.cells, dirichlet)
+        self.nnodes = len(self.node_code)
+        nc = self.cells.shape[0]
+        self.cell_dofs = np.zeros((nc, self.nloc), dtype=np.int64)
+        lib().orc_sx_cell_dofs(dim, k, self.ncomp, nc, _ptr(_c(self.node_of, np.int64)), _ptr(self.node_code),
+                               _ptr(self.cell_dofs))
+        self.nfree = self.nfree_nodes * self.ncomp
+        self.rowptr, self.colind = csr_pattern(self.cell_dofs, self.nfree)
+        self.nnz = int(self.rowptr[-1])
+        s = OrcSxProblem()
+        s.dim, s.k = self.dim, self.k
+        s.problem = 1 if problem == "elasticity" else 0
+        s.lam, s.mu = lame(young, nu) if problem == "elasticity" else (0.0, 0.0)
+        s.source_kind = int(source_kind)
+        src = list(source) + [0.0] * (3 - len(source))
+        for r in range(3):
+            s.source[r] = float(src[r])
+        s.dirichlet_kind = int(dirichlet_kind)
+        aff = list(dirichlet_affine) if dirichlet_affine is not None else []
+        aff = aff + [0.0] * (12 - len(aff))
+        for r in range(12):
+            s.dirichlet_affine[r] = float(aff[r])
+        self._s = s
+        self.values = np.zeros(self.nnz)
+        self.rhs = np.zeros(self.nfree)
+        rc = lib().orc_sx_assemble(ctypes.byref(s), _ptr(self.verts), nc, _ptr(self.cells), _ptr(self.coef),
+                                   _ptr(self.cell_dofs), self.nfree, _ptr(self.rowptr), _ptr(_c(self.colind, np.int32)),
+                                   _ptr(self.values), _ptr(self.rhs))
+        self.ok = rc == 0
+        diag = np.zeros(self.nfree)
+        for i in range(self.nfree):
+            lo, hi = self.rowptr[i], self.rowptr[i + 1]
+            j = lo + np.searchsorted(self.colind[lo:hi], i)
+            diag[i] = self.values[j]
+        self.dinv = 1.0 / diag if self.nfree else diag
+
+    def node_positions(self):
+        xyz = np.zeros((self.nnodes, self.dim))
+        lib().orc_sx_node_positions(self.dim, self.k, self.cells.shape[0], _ptr(self.cells), _ptr(self.verts),
+                                    _ptr(_c(self.node_of, np.int64)), _ptr(xyz))
+        return xyz
+
+    def scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.values, self.colind, self.rowptr), shape=(self.nfree, self.nfree))
+
+    def dense(self):
+        return self.scipy().toarray()
+
+    def solve(self):
+        import scipy.sparse.linalg as spla
+        return spla.spsolve(self.scipy().tocsc(), self.rhs)
+
+    def l2_error(self, x, exact_kind, exact, nq1=None):
+        nq1 = nq1 or self.k + 3
+        ex = _c(list(exact) + [0.0] * (12 - len(exact)), np.float64)
+        return lib().orc_sx_l2_error(ctypes.byref(self._s), _ptr(self.verts), self.cells.shape[0], _ptr(self.cells),
+                                     _ptr(self.cell_dofs), _ptr(_c(x, np.float64)), int(nq1), int(exact_kind),
+                                     _ptr(ex))

@@ -1125,3 +1125,6 @@ int orc_stokes_b_element(int dim, int k, const double *X, double *B, double *md)
     free(gp);
     return bad ? -1 : 0;
 }
+
+/* Lagrangian P_k on simplicial meshes (same oracle, same translation unit). */
+#include "fe_oracle_simplex.c"

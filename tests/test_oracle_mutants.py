@@ -16,7 +16,11 @@ import oracle as O
 from oracle import build as OB
 from tests import test_oracle_dg as DG
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_simplex as SX
 from tests import test_oracle_stokes as ST
+
+# the oracle's sources: fe_oracle.c includes the simplex part
+ORACLE_FILES = ("fe_oracle.c", "fe_oracle_simplex.c")
 
 MUTANTS = {
     "transposed_inverse_jacobian": ("g += Ji[s * dim + i] * gref[s];", "g += Ji[i * dim + s] * gref[s];"),
@@ -47,6 +51,19 @@ MUTANTS = {
     "stokes_dropped_jacobian": ("double wd = w * fabs(qu.detJ);\n        for (int a = 0; a < nnp; a++) {\n            md[a]",
                                 "double wd = w;\n        for (int a = 0; a < nnp; a++) {\n            md[a]"),
     "stokes_wrong_velocity_component": ("wd * psi[a] * gu[b * dim + c];", "wd * psi[a] * gu[b * dim + (c + 1) % dim];"),
+    "simplex_basis_untransposed": ("Phi[a * nn + b] = Ci[b * nn + a];", "Phi[a * nn + b] = Ci[a * nn + b];"),
+    "simplex_collapsed_jacobian_power": ("jac = (1.0 - u0) * (1.0 - u0) * (1.0 - u1);", "jac = (1.0 - u0) * (1.0 - u1);"),
+    "simplex_gradient_untransposed_jacobian": ("g += Ji[r * dim + i] * dref[a * dim + r];",
+                                               "g += Ji[i * dim + r] * dref[a * dim + r];"),
+    "simplex_barycentric_vertex_shift": ("lam[r + 1] = s[3 * a + r];", "lam[r + 1] = s[3 * a + (r + 1) % dim];"),
+    "simplex_boundary_facet_vertex": ("lj = s[3 * a + j - 1];", "lj = s[3 * a + j % dim];"),
+    "simplex_node_position_axis": ("(X[(t + 1) * dim + r] - X[r]) * s[3 * a + t] / k;",
+                                   "(X[(t + 1) * dim + r] - X[r]) * s[3 * a + r] / k;"),
+    "simplex_load_without_jacobian": ("double wd = qw[q] * fabs(det);\n        for (int c = 0; c < ncomp; c++) {\n            double fc",
+                                      "double wd = qw[q];\n        for (int c = 0; c < ncomp; c++) {\n            double fc"),
+    "simplex_lifting_sign": ("else rhs[g[i]] -= A[i * nloc + j] * ud[j];", "else rhs[g[i]] += A[i * nloc + j] * ud[j];"),
+    "simplex_l2_error_without_sqrt": ("double norm = sqrt(err2);", "double norm = err2;"),
+    "simplex_numbering_not_first_appearance": ("qsort(grp, ng, sizeof(sx_first), sx_first_cmp);", ""),
     "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                   "err2 += w * (ue - uh) * (ue - uh);"),
 }
@@ -70,18 +87,27 @@ PIN_CALLS = [
     lambda: DG.test_dg_linear_patch_test(2, [3, 4], 1),
     lambda: ST.test_b_element_box_closed_form(2, 2),
     lambda: ST.test_constant_force_is_balanced_by_an_affine_pressure(2, [3, 4], 1),
+    lambda: SX.test_local_nodes_and_basis_match_silvester(2, 2),
+    lambda: SX.test_collapsed_rule_integrates_monomials_exactly(3, 3),
+    lambda: SX.test_poisson_element_matches_exact_reference_tensor(3, 2),
+    lambda: SX.test_load_of_constant_source_is_exact_moment(3, 2),
+    lambda: SX.test_numbering_matches_brute_force_by_position(3, 2, 2, True),
+    lambda: SX.test_linear_patch_test(3, 1, "poisson", 3),
+    lambda: SX.test_linear_patch_test(3, 2, "elasticity", 2),
+    lambda: SX.test_l2_error_magnitude_closed_forms(2, 2),
 ]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, monkeypatch):
     old, new = MUTANTS[name]
-    src = open(OB.SRC).read()
-    assert src.count(old) == 1, "mutation site not found exactly once"
+    srcs = {f: open(os.path.join(os.path.dirname(OB.SRC), f)).read() for f in ORACLE_FILES}
+    assert sum(s.count(old) for s in srcs.values()) == 1, "mutation site not found exactly once"
     with tempfile.TemporaryDirectory() as td:
-        path = os.path.join(td, "mut.c")
-        with open(path, "w") as f:
-            f.write(src.replace(old, new))
+        for f, s in srcs.items():
+            with open(os.path.join(td, f), "w") as out:
+                out.write(s.replace(old, new))
+        path = os.path.join(td, "fe_oracle.c")
         so = os.path.join(td, "libmut.so")
         subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", so, path, "-lm"], check=True)
         real = O.lib()
