@@ -538,6 +538,129 @@ def dg_form(args, F, torch, steps=3, warmup=1):
     return out
 
 
+SIMPLEX_WORKLOAD = dict(dim=3, n=64, k=2, rtol=1e-10,
+                        text="P2 Lagrange on tetrahedra: the Kuhn subdivision of the 64^3 unit-cube brick "
+                             "(1,572,864 tetrahedra as general connectivity), interior vertices jittered +-0.2h "
+                             "(seed 17080), lognormal per-cell coefficient (seed 17081), f = 1, u = 0 on the "
+                             "boundary; FP64 assembly + Jacobi-PCG (CSR SpMV) to rtol 1e-10")
+
+
+def simplex_element_bytes(ncells, ntri, nloc, nverts, dim):
+    """Algorithmic bytes of the element kernel: the element matrices' upper
+    triangles and the loads written, connectivity, coefficients and vertex
+    coordinates read once."""
+    return 8 * ncells * (ntri + nloc) + 4 * (dim + 1) * ncells + 8 * ncells + 8 * dim * nverts
+
+
+def simplex_gather_bytes(nnz, ncontrib):
+    """Algorithmic bytes of the value gather: the contribution list (4 B per
+    entry) and the element entry it names (8 B) in list order, the entry
+    offsets and the values written."""
+    return 12 * ncontrib + 8 * (nnz + 1) + 8 * nnz
+
+
+def simplex_cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=12, cg_its=100):
+    """The oracle's P_k system on the Kuhn mesh of an n^3 brick of the same
+    recipe (numbering, pattern and assembly single-threaded) and its
+    all-cores CG, scaled to the full workload like the other baselines."""
+    import oracle as O
+    from fe_inputs import lognormal_coefficients, simplex_mesh
+    v, c = simplex_mesh(wl["dim"], n, jitter=0.2)
+    coef = lognormal_coefficients(c.shape[0])
+    S = O.SimplexSystem(wl["dim"], wl["k"], v, c, coef=coef, source_kind=1, source=(1.0,))
+    t_asm = S.t_assemble
+    t0 = time.perf_counter()
+    res = O.omp_pcg(S.rowptr, S.colind, S.values, S.rhs, 0.0, cg_its)
+    t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
+    step = t_asm / c.shape[0] * ncells_full + t_it * (nnz_full / S.nnz) * gpu_iters
+    return {"value": ncells_full / step, "unit": "elements/s", "cores": O.omp_threads(), "kind": "oracle",
+            "sample": f"oracle (C, FP64) P{wl['k']} system on the Kuhn mesh of {n}^3 ({c.shape[0]} tetrahedra, "
+                      f"nnz {S.nnz}): numeric assembly single-threaded ({t_asm:.2f} s; numbering and pattern "
+                      f"{S.t_setup:.2f} s, outside the step as on the GPU), "
+                      f"{res['iters']} CG iterations on all cores ({t_it * 1e3:.2f} ms each); the full step scaled "
+                      f"as cells x assembly time per cell + {gpu_iters:.0f} iterations x per-iteration "
+                      f"time x nnz ratio",
+            "step_s_scaled": step}
+
+
+def simplex_form(args, F, torch, steps=3, warmup=1):
+    """The simplicial workload: a step is the assembly (element kernel +
+    gathers through the stored map) + Jacobi-PCG on the CSR, the numbering,
+    pattern and gather map built once before timing (Sect. 11.1)."""
+    from fe_inputs import lognormal_coefficients, simplex_mesh
+    wl = SIMPLEX_WORKLOAD
+    dim, n, k = wl["dim"], wl["n"], wl["k"]
+    v, c = simplex_mesh(dim, n, jitter=0.2)
+    coef = lognormal_coefficients(c.shape[0])
+    coeff = F.make_coeff("poisson", "fp64", source_kind=1, source=(1.0,), dim=dim)
+    t0 = time.perf_counter()
+    G = F.Simplex(dim, v, c, k, coeff, cell_coeff=coef)
+    t_setup = time.perf_counter() - t0
+    ncells = c.shape[0]
+    ws = torch.empty(F.pcg_query(G.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(G.n_rows, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    print(f"[bench] simplex form: cells={ncells} rows={G.n_rows} nnz={G.nnz} contributions={G.n_contrib} "
+          f"set-up {t_setup:.1f} s", file=sys.stderr, flush=True)
+
+    def step():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        G.assemble(stream)
+        e1.record(stream)
+        x.zero_()
+        return F.pcg_solve(G.csr, G.rhs, x, wl["rtol"], 100000, ws, stream), e0, e1
+
+    for _ in range(warmup):
+        step()
+    F.set_timing(True)
+    F.get_timing(reset=True)
+    torch.cuda.synchronize()
+    lat, iters, asm = [], [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        info, e0, e1 = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        iters.append(info["iters"])
+        asm.append(e0.elapsed_time(e1) * 1e-3)
+        print(f"[bench] simplex step {i}: {lat[-1] * 1e3:.1f} ms, {info['iters']} iterations", file=sys.stderr,
+              flush=True)
+    total = time.perf_counter() - t0
+    tm = F.get_timing(reset=True)
+    F.set_timing(False)
+    spmv_s = tm["spmv_ms"] / max(tm["spmv_calls"], 1) * 1e-3
+    sb = spmv_bytes(G.n_rows, G.nnz, "csr")
+    mode, rpw, _ = F.spmv_plan_of(G.n_rows, G.nnz)
+    t_asm = statistics.mean(asm)
+    eb = simplex_element_bytes(ncells, G.ntri, G.nloc, len(v), dim)
+    gb = simplex_gather_bytes(G.nnz, G.n_contrib)
+    out = {
+        "workload": wl["text"], "cells": ncells, "dofs": G.n_rows, "nnz": G.nnz, "contributions": G.n_contrib,
+        "steps": steps, "elements_per_s": ncells * steps / total, "ms_per_step": total / steps * 1e3,
+        "p50_ms": statistics.median(lat) * 1e3, "pcg_iters": statistics.mean(iters), "relres": info["relres"],
+        "true_relres": info["true_relres"], "setup_s": t_setup,
+        "assembly": {"ms": t_asm * 1e3, "elements_per_s": ncells / t_asm,
+                     "algorithmic_bytes": {"element_kernel": eb, "value_gather": gb},
+                     "hbm_frac_of_assembly_bytes": (eb + gb) / t_asm / 1e9 / HBM_PEAK_GBS,
+                     "timing": "HIP events around fe_simplex_assemble (element kernel, value gather, rhs/dinv)"},
+        "roofline_spmv": {"kernel": f"pcg_spmv_kernel/csr (plan mode {mode}, {rpw} rows per tile)", "bound": "hbm",
+                          "achieved": sb / spmv_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": sb / spmv_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": sb,
+                          "avg_launch_us": spmv_s * 1e6, "timed_launches": tm["spmv_calls"],
+                          "bytes": "12 nnz + 8 (n + 1) + 16 n: values, column indices, row pointers, x once, y"},
+    }
+    del G, ws, x
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle's simplex system on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = simplex_cpu_baseline(wl, statistics.mean(iters), ncells, out["nnz"])
+    return out
+
+
 STOKES_WORKLOAD = dict(dim=3, n=24, k=1, mu=1.0, rtol=1e-8,
                        text="Taylor-Hood Stokes (Q2^3 velocity x Q1 pressure) on the unit cube, 24^3 hexes jittered "
                             "+-0.2h (seed 17080), mu = 1, f = 3 pi^2 prod sin(pi x_r) (1, -0.5, 0.25), u = 0 on the "
@@ -877,7 +1000,7 @@ def main():
                     help="thin the stream to requests of at most this many unknowns (default: every request)")
     ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg", "stokes"],
+    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg", "stokes", "simplex"],
                     help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -915,6 +1038,10 @@ def main():
     if args.form == "serve":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "serve", **serve_form(args, F, torch)}), flush=True)
+        return
+    if args.form == "simplex":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "simplex", **simplex_form(args, F, torch)}), flush=True)
         return
     if args.form == "stokes":
         torch.cuda.set_device(0)
@@ -1068,6 +1195,8 @@ def main():
         out["forms"]["dg"] = dg_form(args, F, torch)
         print("[bench] Stokes form", file=sys.stderr, flush=True)
         out["forms"]["stokes"] = stokes_form(args, F, torch)
+        print("[bench] simplex form", file=sys.stderr, flush=True)
+        out["forms"]["simplex"] = simplex_form(args, F, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, out["config"]["nnz"])

@@ -373,6 +373,65 @@ fe_status fe_stokes_solve(fe_stokes s, double rtol, int32_t maxit, double *u, do
                           fe_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* Lagrangian P_k on simplicial meshes (Sect. 3.3 truncated spaces and node  */
+/* sets, Sect. 3.5 shape functions by a change of basis, Sect. 3.7 collapsed */
+/* quadrature on simplices; triangles and tetrahedra of a general mesh)      */
+/* ------------------------------------------------------------------------ */
+/* A simplicial mesh: vertex coordinates and cell-to-vertex connectivity,
+ * with no structure assumed.  Local nodes are the lattice points s/k with
+ * |s| <= k of the reference simplex (x fastest); global nodes are numbered
+ * by first appearance over (cell ascending, local node ascending); a node is
+ * on the boundary when it lies on a facet of one cell only.  DOFs follow
+ * fe.h's conventions (free ranks in node order, components interleaved,
+ * fixed DOFs -1 - fixed rank in cell_dofs). */
+typedef struct fe_simplex_s *fe_simplex; /* opaque, library-owned */
+
+typedef struct {
+    int32_t dim;              /* 2 (triangles) or 3 (tetrahedra) */
+    int64_t nverts, ncells;
+    const double *vertex_xyz; /* host, nverts x dim (AoS) */
+    const int32_t *cells;     /* host, ncells x (dim+1) vertex ids; either orientation */
+    const double *cell_coeff; /* host, ncells; NULL = 1.0 */
+} fe_simplex_desc;
+
+/* Builds the space of P_order (1..4; elasticity 1..3) on the mesh: the
+ * reference element (change of basis, collapsed Gauss rule with
+ * order + ceil(dim/2) points per direction), the global numbering, the CSR
+ * pattern and the stored cell-to-nnz gather map (every entry's element
+ * contributions in ascending cell order), on the host; copies the mesh and
+ * those maps to the device (owned by the handle).  coeff: problem, FP64
+ * precision only, source, dirichlet_faces != 0 fixes every boundary node
+ * (0: none), Dirichlet kind and affine datum.  Synchronous.  FE_EMESH for a
+ * vertex id out of range, a degenerate cell (det J = 0) or a facet of more
+ * than two cells; FE_EINVAL for 2^31 or more free DOFs or 2^32 or more
+ * element entries. */
+fe_status fe_simplex_create(const fe_simplex_desc *desc, int32_t order, const fe_coeff *coeff, fe_simplex *out);
+fe_status fe_simplex_destroy(fe_simplex s);
+
+/* Free DOFs (rows), nonzeros, global nodes and element contributions to the
+ * nonzeros (the gather map's length).  Host only. */
+fe_status fe_simplex_query(fe_simplex s, int64_t *n_rows, int64_t *nnz, int64_t *n_nodes, int64_t *n_contrib);
+
+/* The cell-to-DOF map into cell_dofs (device, ncells x nloc int32). */
+fe_status fe_simplex_cell_dofs(fe_simplex s, int32_t *cell_dofs, fe_stream stream);
+
+/* Symbolic phase: A->rowptr and A->colind (device, caller-owned, sizes from
+ * fe_simplex_query) from the pattern built at creation.  Synchronous. */
+fe_status fe_simplex_pattern(fe_simplex s, const fe_csr *A, fe_stream stream);
+
+/* Numeric phase (Sect. 3.6, 3.7, 10.4): the element matrices (upper
+ * triangles) and loads with Dirichlet lifting of every cell, then A->values
+ * by the gather map, A->rhs and A->dinv.  Bitwise reproducible.  Enqueues
+ * only. */
+fe_status fe_simplex_assemble(fe_simplex s, const fe_csr *A, fe_stream stream);
+
+/* Device views of the last assembly's element data (owned by the handle):
+ * E[K ntri + t], t = I nloc - I (I - 1) / 2 + (J - I) for local DOFs I <= J
+ * (nloc = nodes x components, ntri = nloc (nloc + 1) / 2), and the loads with
+ * lifting F[K nloc + I]. */
+fe_status fe_simplex_elements(fe_simplex s, const double **E, const double **F);
+
+/* ------------------------------------------------------------------------ */
 /* Batched solve: many independent systems in one sequence of launches       */
 /* ------------------------------------------------------------------------ */
 /* Workspace bytes fe_pcg_solve_batch needs for nprob systems of n_rows[i]

@@ -19,6 +19,7 @@ numpy arrays to it through ctypes and adds two pure-Python pieces:
 """
 import ctypes
 import os
+import time
 
 import numpy as np
 
@@ -789,6 +790,7 @@ class SimplexSystem:
         self.ncomp = dim if problem == "elasticity" else 1
         self.nn = simplex_nn(dim, k)
         self.nloc = self.nn * self.ncomp
+        t0 = time.perf_counter()
         self.node_of, self.node_code, self.nfree_nodes, self.nfixed_nodes = simplex_number(
             dim, k, self.verts.shape[0], self.cells, dirichlet)
         self.nnodes = len(self.node_code)
@@ -799,6 +801,7 @@ class SimplexSystem:
         self.nfree = self.nfree_nodes * self.ncomp
         self.rowptr, self.colind = csr_pattern(self.cell_dofs, self.nfree)
         self.nnz = int(self.rowptr[-1])
+        self.t_setup = time.perf_counter() - t0  # numbering and pattern (seconds)
         s = OrcSxProblem()
         s.dim, s.k = self.dim, self.k
         s.problem = 1 if problem == "elasticity" else 0
@@ -815,15 +818,14 @@ class SimplexSystem:
         self._s = s
         self.values = np.zeros(self.nnz)
         self.rhs = np.zeros(self.nfree)
+        t0 = time.perf_counter()
         rc = lib().orc_sx_assemble(ctypes.byref(s), _ptr(self.verts), nc, _ptr(self.cells), _ptr(self.coef),
                                    _ptr(self.cell_dofs), self.nfree, _ptr(self.rowptr), _ptr(_c(self.colind, np.int32)),
                                    _ptr(self.values), _ptr(self.rhs))
+        self.t_assemble = time.perf_counter() - t0  # numeric assembly (seconds)
         self.ok = rc == 0
-        diag = np.zeros(self.nfree)
-        for i in range(self.nfree):
-            lo, hi = self.rowptr[i], self.rowptr[i + 1]
-            j = lo + np.searchsorted(self.colind[lo:hi], i)
-            diag[i] = self.values[j]
+        rows = np.repeat(np.arange(self.nfree), np.diff(self.rowptr))
+        diag = self.values[self.colind == rows]
         self.dinv = 1.0 / diag if self.nfree else diag
 
     def node_positions(self):

@@ -140,6 +140,8 @@ fe_status launch_pattern(const SpaceArgs &sa, int64_t *rowptr, int32_t *colind, 
 fe_status launch_cell_dofs(const SpaceArgs &sa, const MeshArgs &ma, int32_t *out, hipStream_t s);
 fe_status launch_permutation(const SpaceArgs &sa, const MeshArgs &ma, int64_t *perm, hipStream_t s);
 void ref_tables(int k, RefTables &t);
+// Gauss-Legendre rule of n points on [0,1] (nodes ascending).
+void gauss_legendre_01(int n, double *x, double *w);
 // Value and derivative at x of the 1D Lagrange polynomial of node i/k of the
 // equidistant order-k basis on [0,1] (Sect. 3.4 eq. lagbas).
 void lagrange_1d(int k, int i, double x, double &val, double &der);

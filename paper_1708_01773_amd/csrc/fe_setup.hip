@@ -18,7 +18,7 @@ namespace fe {
 // Reference tables (Sect. 3.7 Gauss-Legendre rule; Sect. 3.4 eq. lagbas on the
 // equidistant nodes of Sect. 3.15)
 // ---------------------------------------------------------------------------
-static void gauss_legendre_01(int n, double *x, double *w)
+void gauss_legendre_01(int n, double *x, double *w)
 {
     // Legendre roots by Newton's method from the cosine initial guess, then
     // mapped from [-1,1] to [0,1].

@@ -1,0 +1,1004 @@
+// fe_simplex.hip -- Lagrangian P_k elements on simplicial meshes: triangles
+// and tetrahedra of a general mesh given by vertex coordinates and
+// cell-to-vertex connectivity (Sect. 3.3 truncated polynomial spaces and
+// node sets, Sect. 3.5 shape functions by a change of basis, Sect. 3.7
+// quadrature on simplices through the collapsed (Duffy) map; Sect. 3.6 and
+// 10.3 global DOFs; Sect. 11.1 a pattern built once and reused).
+//
+// Set-up on the host, once per mesh and order:
+//  * the reference element: nodes s/k with |s| <= k (x fastest), shape
+//    functions from the monomial pre-basis by the change of basis, the
+//    collapsed Gauss rule with k + ceil(d/2) points per direction and the
+//    reference gradient tensor S^{rs}_ab = int d_r phi_a d_s phi_b on it;
+//  * global nodes: a local node is named by the sub-simplex its barycentric
+//    support spans (vertex, edge, face or the cell) and its weights there;
+//    edges and faces are found by sorting their vertex keys, so the cells
+//    around a node name it alike whatever their local vertex order.  Global
+//    ids by first appearance over (cell, local node); boundary facets are the
+//    facets of one cell only; free and fixed ranks; the cell-to-DOF map;
+//  * the stored pattern and permutation: each free row's columns (the free
+//    nodes of the cells around it, ascending) and, per entry, its element
+//    contributions in ascending cell order (the gather map).
+// Numeric phase on the device:
+//  * sx_element_kernel: per cell the affine geometry, then each entry of the
+//    element matrix's upper triangle as a contraction of the cell's
+//    coefficient tensor (|det J| J^-1 J^-T, or its elasticity analogue) with
+//    the reference tensor -- the map is affine, so the quadrature sum does not
+//    depend on the cell and is carried out once on the reference element --
+//    and the load vector (with Dirichlet lifting) on the collapsed rule;
+//  * gathers: each CSR entry sums its contributions in list order, each rhs
+//    entry the loads of its node's occurrences; dinv from the diagonal.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+constexpr int kSxMaxK = 4;
+constexpr int kSxMaxNN = 35;  // P4 on the tetrahedron
+
+struct SxArgs {
+    int32_t problem, source_kind, dirichlet_kind;
+    double lambda, mu;
+    double source[3];
+    double aff[12];
+    int64_t ncells;
+    int8_t s[3 * kSxMaxNN];  // lattice point of every local node
+};
+
+__host__ __device__ constexpr int sx_nn(int dim, int k)
+{
+    return dim == 2 ? (k + 1) * (k + 2) / 2 : (k + 1) * (k + 2) * (k + 3) / 6;
+}
+
+template <int DIM, int K, int PROB>
+struct SxShape {
+    static constexpr int NN = sx_nn(DIM, K);
+    static constexpr int NC = PROB == FE_ELASTICITY ? DIM : 1;
+    static constexpr int NLOC = NN * NC;
+    static constexpr int NTRI = NLOC * (NLOC + 1) / 2;
+    // per-cell coefficients: the symmetric DIM x DIM tensor (Poisson) or
+    // C^{ij}_{rs} (elasticity)
+    static constexpr int NP = PROB == FE_ELASTICITY ? DIM * DIM * DIM * DIM : DIM * (DIM + 1) / 2;
+    // reference table: per coefficient pair, every upper-triangle entry
+    // (Poisson), or S^{rs}_{ab} over the full nn x nn (elasticity)
+    static constexpr int NTAB = PROB == FE_ELASTICITY ? DIM * DIM * NN * NN : NP * NTRI;
+    static constexpr int NQ1 = K + (DIM + 1) / 2;
+    static constexpr int NQ = DIM == 3 ? NQ1 * NQ1 * NQ1 : NQ1 * NQ1;
+    static constexpr int CPB = NTRI <= 16 ? 64 : NTRI <= 64 ? 32 : NTRI <= 256 ? 8 : 4;
+};
+
+// One workgroup per CPB consecutive cells.  Writes the upper triangle of
+// every element matrix, E[K ntri + t] with t = I nloc - I (I - 1) / 2 + (J - I)
+// for I <= J, and the load with lifting, F[K nloc + I].
+template <int DIM, int K, int PROB>
+__global__ __launch_bounds__(256) void sx_element_kernel(SxArgs sa, const double *__restrict__ vxyz,
+                                                         const int32_t *__restrict__ cells,
+                                                         const double *__restrict__ coef,
+                                                         const int32_t *__restrict__ cell_dofs,
+                                                         const double *__restrict__ tab, const int32_t *__restrict__ tri,
+                                                         const double *__restrict__ phiq,
+                                                         const double *__restrict__ qxw, double *__restrict__ E,
+                                                         double *__restrict__ F)
+{
+    using S = SxShape<DIM, K, PROB>;
+    constexpr int NV = DIM + 1;
+    __shared__ double sTab[S::NTAB];
+    __shared__ int32_t sTri[S::NTRI];
+    __shared__ double sC[S::CPB][S::NP];
+    __shared__ double sX[S::CPB][NV * DIM];
+    __shared__ double sG[S::CPB][S::NQ];
+    __shared__ double sDet[S::CPB];
+    __shared__ int32_t sDofs[S::CPB * S::NLOC];
+    const int tid = threadIdx.x;
+    const int64_t K0 = xcd_block(blockIdx.x, gridDim.x) * S::CPB;
+    const int ncl = sa.ncells - K0 < S::CPB ? int(sa.ncells - K0) : S::CPB;
+    for (int t = tid; t < S::NTAB; t += blockDim.x) sTab[t] = tab[t];
+    for (int t = tid; t < S::NTRI; t += blockDim.x) sTri[t] = tri[t];
+    if (sa.dirichlet_kind == FE_DIRICHLET_AFFINE)
+        for (int t = tid; t < ncl * S::NLOC; t += blockDim.x) sDofs[t] = cell_dofs[K0 * S::NLOC + t];
+    // geometry and coefficients of the block's cells
+    for (int c = tid; c < ncl; c += blockDim.x) {
+        const int64_t Kc = K0 + c;
+        double X[NV][DIM];
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            const int64_t v = cells[Kc * NV + j];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) X[j][r] = vxyz[v * DIM + r];
+        }
+        double J[DIM][DIM], Ji[DIM][DIM], det;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) J[r][s] = X[s + 1][r] - X[0][r];
+        if constexpr (DIM == 2) {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double id = 1.0 / det;
+            Ji[0][0] = J[1][1] * id;
+            Ji[0][1] = -J[0][1] * id;
+            Ji[1][0] = -J[1][0] * id;
+            Ji[1][1] = J[0][0] * id;
+        } else {
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+            const double id = 1.0 / det;
+            Ji[0][0] = c00 * id;
+            Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+            Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+            Ji[1][0] = c01 * id;
+            Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+            Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+            Ji[2][0] = c02 * id;
+            Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+            Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        }
+        const double ad = fabs(det);
+        const double w = ad * (coef ? coef[Kc] : 1.0);
+        if constexpr (PROB == FE_ELASTICITY) {
+            // C^{ij}_{rs} = w [lambda Ji_ri Ji_sj + mu Ji_rj Ji_si + mu delta_ij sum_l Ji_rl Ji_sl]
+#pragma unroll
+            for (int i = 0; i < DIM; i++)
+#pragma unroll
+                for (int j = 0; j < DIM; j++)
+#pragma unroll
+                    for (int r = 0; r < DIM; r++)
+#pragma unroll
+                        for (int s = 0; s < DIM; s++) {
+                            double v = sa.lambda * Ji[r][i] * Ji[s][j] + sa.mu * Ji[r][j] * Ji[s][i];
+                            if (i == j) {
+                                double g = 0.0;
+#pragma unroll
+                                for (int l = 0; l < DIM; l++) g += Ji[r][l] * Ji[s][l];
+                                v += sa.mu * g;
+                            }
+                            sC[c][((i * DIM + j) * DIM + r) * DIM + s] = w * v;
+                        }
+        } else {
+            // (J^-1 J^-T)_{rs}, r <= s, pairs in the order (0,0),(0,1),..,(1,1),..
+            int p = 0;
+#pragma unroll
+            for (int r = 0; r < DIM; r++)
+#pragma unroll
+                for (int s = r; s < DIM; s++) {
+                    double g = 0.0;
+#pragma unroll
+                    for (int l = 0; l < DIM; l++) g += Ji[r][l] * Ji[s][l];
+                    sC[c][p++] = w * g;
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NV; j++)
+#pragma unroll
+            for (int r = 0; r < DIM; r++) sX[c][j * DIM + r] = X[j][r];
+        sDet[c] = ad;
+    }
+    __syncthreads();
+    // load weights at the quadrature points, w_q |det J| f(x_q) (the
+    // component factor source[c] is applied below), over (cell, point) pairs
+    if (sa.source_kind != FE_SOURCE_NONE)
+        for (int e = tid; e < ncl * S::NQ; e += blockDim.x) {
+            const int c = e / S::NQ, q = e - c * S::NQ;
+            double g = 1.0;
+            if (sa.source_kind == FE_SOURCE_SINPROD) {
+                g = DIM * M_PI * M_PI;
+#pragma unroll
+                for (int r = 0; r < DIM; r++) {
+                    double x = sX[c][r];
+#pragma unroll
+                    for (int t = 0; t < DIM; t++) x += (sX[c][(t + 1) * DIM + r] - sX[c][r]) * qxw[q * (DIM + 1) + t];
+                    g *= sin(M_PI * x);
+                }
+            }
+            sG[c][q] = g * qxw[q * (DIM + 1) + DIM] * sDet[c];
+        }
+    __syncthreads();
+    // element matrices: contiguous over the block's cells
+    for (int e = tid; e < ncl * S::NTRI; e += blockDim.x) {
+        const int c = e / S::NTRI, t = e - c * S::NTRI;
+        double v = 0.0;
+        if (PROB == FE_ELASTICITY) {
+            const int IJ = sTri[t], I = IJ >> 16, Jx = IJ & 0xffff;
+            const int a = I / S::NC, i = I % S::NC, b = Jx / S::NC, j = Jx % S::NC;
+#pragma unroll
+            for (int rs = 0; rs < DIM * DIM; rs++)
+                v = __fma_rn(sC[c][(i * DIM + j) * DIM * DIM + rs], sTab[rs * S::NN * S::NN + a * S::NN + b], v);
+        } else {
+#pragma unroll
+            for (int p = 0; p < S::NP; p++) v = __fma_rn(sC[c][p], sTab[p * S::NTRI + t], v);
+        }
+        E[(K0 + c) * S::NTRI + t] = v;
+    }
+    // loads and lifting
+    for (int e = tid; e < ncl * S::NLOC; e += blockDim.x) {
+        const int c = e / S::NLOC, I = e - c * S::NLOC;
+        const int a = I / S::NC, i = I % S::NC;
+        const int64_t Kc = K0 + c;
+        double f = 0.0;
+        if (sa.source_kind != FE_SOURCE_NONE) {
+            for (int q = 0; q < S::NQ; q++) f = __fma_rn(sG[c][q], phiq[q * S::NN + a], f);
+            f *= sa.source[i];
+        }
+        if (sa.dirichlet_kind == FE_DIRICHLET_AFFINE) {
+            for (int Jx = 0; Jx < S::NLOC; Jx++) {
+                if (sDofs[c * S::NLOC + Jx] >= 0) continue;
+                const int b = Jx / S::NC, j = Jx % S::NC;
+                // entry (I, Jx) of the element matrix
+                double A = 0.0;
+                if (PROB == FE_ELASTICITY) {
+#pragma unroll
+                    for (int rs = 0; rs < DIM * DIM; rs++)
+                        A = __fma_rn(sC[c][(i * DIM + j) * DIM * DIM + rs], sTab[rs * S::NN * S::NN + a * S::NN + b], A);
+                } else {
+                    const int lo = I < Jx ? I : Jx, hi = I < Jx ? Jx : I;
+                    const int t = lo * S::NLOC - lo * (lo - 1) / 2 + (hi - lo);
+#pragma unroll
+                    for (int p = 0; p < S::NP; p++) A = __fma_rn(sC[c][p], sTab[p * S::NTRI + t], A);
+                }
+                // u_D,j at the node: x_b = X_0 + sum_t (X_{t+1} - X_0) s_t / k
+                double u = sa.aff[4 * j];
+#pragma unroll
+                for (int r = 0; r < DIM; r++) {
+                    double x = sX[c][r];
+#pragma unroll
+                    for (int t = 0; t < DIM; t++)
+                        x += (sX[c][(t + 1) * DIM + r] - sX[c][r]) * (double(sa.s[3 * b + t]) / K);
+                    u += sa.aff[4 * j + 1 + r] * x;
+                }
+                f -= A * u;
+            }
+        }
+        F[Kc * S::NLOC + I] = f;
+    }
+}
+
+// values[j] = sum of E over the contributions of entry j, in list order.
+__global__ __launch_bounds__(256) void sx_gather_kernel(int64_t nnz, const int64_t *__restrict__ gptr,
+                                                        const uint32_t *__restrict__ gsrc,
+                                                        const double *__restrict__ E, double *__restrict__ values)
+{
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j >= nnz) return;
+    const int64_t t0 = gptr[j], t1 = gptr[j + 1];
+    double s = 0.0;
+    for (int64_t t = t0; t < t1; t++) s += E[gsrc[t]];
+    values[j] = s;
+}
+
+// rhs[row] = sum of the loads of the row's node occurrences (ascending cell);
+// dinv[row] = 1 / values[diag[row]].
+__global__ __launch_bounds__(256) void sx_rhs_kernel(int64_t n_rows, int ncomp, const int64_t *__restrict__ optr,
+                                                     const uint32_t *__restrict__ oidx, const double *__restrict__ F,
+                                                     const int64_t *__restrict__ diag,
+                                                     const double *__restrict__ values, double *__restrict__ rhs,
+                                                     double *__restrict__ dinv)
+{
+    const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (row >= n_rows) return;
+    const int64_t node = row / ncomp;
+    const int comp = int(row - node * ncomp);
+    double s = 0.0;
+    for (int64_t t = optr[node]; t < optr[node + 1]; t++) s += F[int64_t(oidx[t]) * ncomp + comp];
+    if (rhs) rhs[row] = s;
+    if (dinv) dinv[row] = 1.0 / values[diag[row]];
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+struct fe_simplex_s {
+    int dim = 0, k = 0, nn = 0, ncomp = 0, nloc = 0, ntri = 0;
+    bool fix_boundary = false;
+    int64_t nverts = 0, ncells = 0, nnodes = 0, nfree_nodes = 0, n_rows = 0, nnz = 0, ncontrib = 0;
+    SxArgs args{};
+    std::vector<int64_t> h_rowptr;
+    std::vector<int32_t> h_colind;
+    double *vxyz = nullptr, *coef = nullptr, *tab = nullptr, *phiq = nullptr, *qxw = nullptr, *E = nullptr,
+           *F = nullptr;
+    int32_t *cells = nullptr, *cell_dofs = nullptr, *tri = nullptr;
+    int64_t *gptr = nullptr, *diag = nullptr, *optr = nullptr;
+    uint32_t *gsrc = nullptr, *oidx = nullptr;
+};
+
+namespace {
+
+template <typename T>
+fe_status sx_alloc(T *&p, size_t count)
+{
+    FE_HIP(hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)));
+    return FE_OK;
+}
+
+template <typename T>
+fe_status sx_upload(T *&d, const T *h, size_t count)
+{
+    fe_status st = sx_alloc(d, count);
+    if (st != FE_OK) return st;
+    if (count) FE_HIP(hipMemcpy(d, h, sizeof(T) * count, hipMemcpyHostToDevice));
+    return FE_OK;
+}
+
+void sx_free(fe_simplex S)
+{
+    void *ptrs[] = {S->vxyz, S->coef, S->tab, S->phiq, S->qxw, S->E,    S->F,    S->cells,
+                    S->cell_dofs, S->tri, S->gptr, S->diag, S->optr, S->gsrc, S->oidx};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete S;
+}
+
+// ---------------------------------------------------------------------------
+// Reference element (host)
+// ---------------------------------------------------------------------------
+struct SxRef {
+    int nn = 0;
+    std::vector<int> s;        // nn x 3 lattice points
+    std::vector<double> Phi;   // nn x nn: phi_a = sum_b Phi_ab xi^(s_b)
+};
+
+void sx_lattice(int dim, int k, std::vector<int> &s)
+{
+    s.clear();
+    for (int s2 = 0; s2 <= (dim == 3 ? k : 0); s2++)
+        for (int s1 = 0; s1 <= k; s1++)
+            for (int s0 = 0; s0 <= k; s0++)
+                if (s0 + s1 + s2 <= k) {
+                    s.push_back(s0);
+                    s.push_back(s1);
+                    s.push_back(s2);
+                }
+}
+
+double ipowd(double x, int e)
+{
+    double r = 1.0;
+    while (e-- > 0) r *= x;
+    return r;
+}
+
+// The change of basis: C_ab = (s_a / k)^(s_b) (the pre-basis monomial b at
+// node a); Phi = C^-T, by Gauss-Jordan elimination with partial pivoting.
+bool sx_reference(int dim, int k, SxRef &R)
+{
+    sx_lattice(dim, k, R.s);
+    const int n = int(R.s.size() / 3);
+    R.nn = n;
+    std::vector<double> M(static_cast<size_t>(n) * 2 * n, 0.0);
+    for (int a = 0; a < n; a++) {
+        for (int b = 0; b < n; b++) {
+            double v = 1.0;
+            for (int r = 0; r < dim; r++) v *= ipowd(double(R.s[3 * a + r]) / k, R.s[3 * b + r]);
+            M[a * 2 * n + b] = v;
+        }
+        M[a * 2 * n + n + a] = 1.0;
+    }
+    for (int c = 0; c < n; c++) {
+        int p = c;
+        for (int i = c + 1; i < n; i++)
+            if (std::fabs(M[i * 2 * n + c]) > std::fabs(M[p * 2 * n + c])) p = i;
+        if (M[p * 2 * n + c] == 0.0) return false;
+        if (p != c)
+            for (int j = 0; j < 2 * n; j++) std::swap(M[c * 2 * n + j], M[p * 2 * n + j]);
+        const double piv = M[c * 2 * n + c];
+        for (int j = 0; j < 2 * n; j++) M[c * 2 * n + j] /= piv;
+        for (int i = 0; i < n; i++) {
+            if (i == c) continue;
+            const double f = M[i * 2 * n + c];
+            if (f != 0.0)
+                for (int j = 0; j < 2 * n; j++) M[i * 2 * n + j] -= f * M[c * 2 * n + j];
+        }
+    }
+    R.Phi.assign(size_t(n) * n, 0.0);
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) R.Phi[a * n + b] = M[b * 2 * n + n + a];  // (C^-1)_{ba}
+    return true;
+}
+
+void sx_eval(int dim, const SxRef &R, const double *xi, double *phi, double *dphi)
+{
+    const int n = R.nn;
+    std::vector<double> psi(n), dpsi(size_t(n) * 3);
+    for (int b = 0; b < n; b++) {
+        double v = 1.0;
+        for (int r = 0; r < dim; r++) v *= ipowd(xi[r], R.s[3 * b + r]);
+        psi[b] = v;
+        for (int r = 0; r < dim; r++) {
+            const int e = R.s[3 * b + r];
+            double g = e == 0 ? 0.0 : e * ipowd(xi[r], e - 1);
+            for (int t = 0; t < dim; t++)
+                if (t != r) g *= ipowd(xi[t], R.s[3 * b + t]);
+            dpsi[b * 3 + r] = g;
+        }
+    }
+    for (int a = 0; a < n; a++) {
+        double v = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < n; b++) {
+            v += R.Phi[a * n + b] * psi[b];
+            for (int r = 0; r < dim; r++) g[r] += R.Phi[a * n + b] * dpsi[b * 3 + r];
+        }
+        phi[a] = v;
+        for (int r = 0; r < dim; r++) dphi[a * dim + r] = g[r];
+    }
+}
+
+// Collapsed Gauss rule: nq1 points per direction, u_0 fastest.  Output
+// qxw[q (dim + 1) + r] = xi_r, qxw[q (dim + 1) + dim] = weight.
+void sx_rule(int dim, int nq1, std::vector<double> &qxw)
+{
+    double gx[16], gw[16];
+    gauss_legendre_01(nq1, gx, gw);
+    const int nq = dim == 3 ? nq1 * nq1 * nq1 : nq1 * nq1;
+    qxw.assign(size_t(nq) * (dim + 1), 0.0);
+    for (int q = 0; q < nq; q++) {
+        const int i0 = q % nq1, i1 = (q / nq1) % nq1, i2 = q / (nq1 * nq1);
+        const double u0 = gx[i0], u1 = gx[i1];
+        double *o = &qxw[size_t(q) * (dim + 1)];
+        o[0] = u0;
+        o[1] = (1.0 - u0) * u1;
+        if (dim == 3) {
+            o[2] = (1.0 - u0) * (1.0 - u1) * gx[i2];
+            o[3] = gw[i0] * gw[i1] * gw[i2] * (1.0 - u0) * (1.0 - u0) * (1.0 - u1);
+        } else {
+            o[2] = gw[i0] * gw[i1] * (1.0 - u0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Global numbering (host)
+// ---------------------------------------------------------------------------
+struct Facet {
+    std::array<int32_t, 3> v;  // ascending; v[2] = -1 for an edge
+    int64_t cell;
+    int32_t j;  // local vertex opposite (facets), or local edge index
+};
+
+bool facet_less(const Facet &x, const Facet &y)
+{
+    if (x.v != y.v) return x.v < y.v;
+    if (x.cell != y.cell) return x.cell < y.cell;
+    return x.j < y.j;
+}
+
+// Unique keys of the given records (sorted in place), and the multiplicity
+// of each.
+void unique_keys(std::vector<Facet> &rec, std::vector<std::array<int32_t, 3>> &keys, std::vector<int32_t> &count)
+{
+    std::sort(rec.begin(), rec.end(), facet_less);
+    keys.clear();
+    count.clear();
+    for (size_t t = 0; t < rec.size(); t++) {
+        if (t == 0 || rec[t].v != rec[t - 1].v) {
+            keys.push_back(rec[t].v);
+            count.push_back(0);
+        }
+        count.back()++;
+    }
+}
+
+int64_t key_index(const std::vector<std::array<int32_t, 3>> &keys, const std::array<int32_t, 3> &k)
+{
+    return int64_t(std::lower_bound(keys.begin(), keys.end(), k) - keys.begin());
+}
+
+int worker_count(int64_t work)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t by_work = std::max<int64_t>(1, work / 4096);
+    return int(std::min<int64_t>(std::min<unsigned>(hw, 16u), by_work));
+}
+
+template <typename Fn>
+void parallel_chunks(int64_t n, Fn fn)
+{
+    const int nt = worker_count(n);
+    if (nt <= 1) {
+        fn(int64_t(0), n);
+        return;
+    }
+    // interleaved chunks of 2048 for balance
+    const int64_t chunk = 2048;
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; w++)
+        th.emplace_back([&, w]() {
+            for (int64_t lo = int64_t(w) * chunk; lo < n; lo += int64_t(nt) * chunk) fn(lo, std::min(n, lo + chunk));
+        });
+    for (auto &t : th) t.join();
+}
+
+struct Cand {
+    int32_t cn;   // column node (free rank)
+    int32_t a, b;
+    int64_t K;
+};
+
+fe_status sx_setup(fe_simplex S, const int32_t *cells, const double *vxyz)
+{
+    const int dim = S->dim, k = S->k, nn = S->nn, nv = dim + 1, nc = S->ncomp;
+    const int64_t ncells = S->ncells;
+    std::vector<int> sl;
+    sx_lattice(dim, k, sl);
+    // barycentric weights of every local node
+    std::vector<std::array<int, 4>> beta(nn);
+    for (int a = 0; a < nn; a++) {
+        int sum = 0;
+        for (int r = 0; r < dim; r++) {
+            beta[a][r + 1] = sl[3 * a + r];
+            sum += sl[3 * a + r];
+        }
+        beta[a][0] = k - sum;
+        for (int r = dim + 1; r < 4; r++) beta[a][r] = 0;
+    }
+    // edges (3D: 6 per cell) and facets (2D: the 3 edges; 3D: the 4 faces)
+    std::vector<Facet> frec(static_cast<size_t>(ncells) * nv);
+    for (int64_t K = 0; K < ncells; K++)
+        for (int j = 0; j < nv; j++) {
+            Facet &f = frec[K * nv + j];
+            int m = 0;
+            for (int i = 0; i < nv; i++)
+                if (i != j) f.v[m++] = cells[K * nv + i];
+            std::sort(f.v.begin(), f.v.begin() + m);
+            if (m == 2) f.v[2] = -1;
+            f.cell = K;
+            f.j = j;
+        }
+    std::vector<std::array<int32_t, 3>> fkeys, ekeys;
+    std::vector<int32_t> fcount, ecount;
+    unique_keys(frec, fkeys, fcount);
+    for (int32_t c : fcount)
+        if (c > 2) return set_error(FE_EMESH, "a facet is shared by more than two cells");
+    if (dim == 3) {
+        std::vector<Facet> erec(static_cast<size_t>(ncells) * 6);
+        for (int64_t K = 0; K < ncells; K++) {
+            int e = 0;
+            for (int i = 0; i < 4; i++)
+                for (int j = i + 1; j < 4; j++, e++) {
+                    Facet &f = erec[K * 6 + e];
+                    const int32_t x = cells[K * 4 + i], y = cells[K * 4 + j];
+                    f.v = {std::min(x, y), std::max(x, y), -1};
+                    f.cell = K;
+                    f.j = e;
+                }
+        }
+        unique_keys(erec, ekeys, ecount);
+    }
+    const std::vector<std::array<int32_t, 3>> &edges = dim == 3 ? ekeys : fkeys;
+    // sub-simplex slot counts: nodes strictly inside an edge, face, tetrahedron
+    const int64_t ne = int64_t(edges.size()), nf = dim == 3 ? int64_t(fkeys.size()) : 0;
+    const int64_t se = k - 1, sf = int64_t(std::max(k - 2, 0)) * std::max(k - 2, 0),
+                  sc = dim == 3 ? int64_t(std::max(k - 3, 0)) * std::max(k - 3, 0) * std::max(k - 3, 0) : sf;
+    const int64_t base_e = S->nverts, base_f = base_e + ne * se, base_c = base_f + nf * sf;
+    const int64_t nprelim = base_c + ncells * sc;
+    // preliminary node names of every (cell, local node)
+    std::vector<int64_t> pre(static_cast<size_t>(ncells) * nn);
+    parallel_chunks(ncells, [&](int64_t lo, int64_t hi) {
+        for (int64_t K = lo; K < hi; K++)
+            for (int a = 0; a < nn; a++) {
+                int32_t vv[4];
+                int ww[4], m = 0;
+                for (int j = 0; j < nv; j++)
+                    if (beta[a][j] > 0) {
+                        vv[m] = cells[K * nv + j];
+                        ww[m] = beta[a][j];
+                        m++;
+                    }
+                // ascending vertex ids
+                for (int i = 1; i < m; i++)
+                    for (int j = i; j > 0 && vv[j - 1] > vv[j]; j--) {
+                        std::swap(vv[j - 1], vv[j]);
+                        std::swap(ww[j - 1], ww[j]);
+                    }
+                int64_t p;
+                if (m == 1) {
+                    p = vv[0];
+                } else if (m == 2) {
+                    p = base_e + key_index(edges, {vv[0], vv[1], -1}) * se + (ww[1] - 1);
+                } else if (m == 3 && dim == 3) {
+                    p = base_f + key_index(fkeys, {vv[0], vv[1], vv[2]}) * sf + (ww[0] - 1) * (k - 2) + (ww[1] - 1);
+                } else if (m == 3) {  // interior of a triangle
+                    p = base_c + K * sc + (ww[0] - 1) * (k - 2) + (ww[1] - 1);
+                } else {  // interior of a tetrahedron
+                    p = base_c + K * sc + ((ww[0] - 1) * (k - 3) + (ww[1] - 1)) * (k - 3) + (ww[2] - 1);
+                }
+                pre[K * nn + a] = p;
+            }
+    });
+    // global ids by first appearance
+    std::vector<int64_t> gid(static_cast<size_t>(nprelim), -1);
+    int64_t nnodes = 0;
+    for (int64_t t = 0; t < ncells * nn; t++) {
+        int64_t &g = gid[pre[t]];
+        if (g < 0) g = nnodes++;
+        pre[t] = g;
+    }
+    std::vector<int64_t>().swap(gid);
+    S->nnodes = nnodes;
+    // boundary nodes: the nodes of facets of one cell
+    std::vector<char> bnd(static_cast<size_t>(nnodes), 0);
+    if (S->fix_boundary) {
+        for (size_t t = 0; t < frec.size();) {
+            size_t u = t + 1;
+            while (u < frec.size() && frec[u].v == frec[t].v) u++;
+            if (u - t == 1) {
+                const int64_t K = frec[t].cell;
+                const int j = frec[t].j;
+                for (int a = 0; a < nn; a++)
+                    if (beta[a][j] == 0) bnd[pre[K * nn + a]] = 1;
+            }
+            t = u;
+        }
+    }
+    std::vector<Facet>().swap(frec);
+    // free / fixed ranks
+    std::vector<int64_t> code(static_cast<size_t>(nnodes));
+    int64_t nfree = 0, nfixed = 0;
+    for (int64_t g = 0; g < nnodes; g++) code[g] = bnd[g] ? -1 - nfixed++ : nfree++;
+    S->nfree_nodes = nfree;
+    S->n_rows = nfree * nc;
+    if (S->n_rows >= (int64_t(1) << 31)) return set_error(FE_EINVAL, "2^31 or more free DOFs");
+    // cell-to-DOF map
+    std::vector<int32_t> cdofs(static_cast<size_t>(ncells) * S->nloc);
+    for (int64_t K = 0; K < ncells; K++)
+        for (int a = 0; a < nn; a++) {
+            const int64_t cd = code[pre[K * nn + a]];
+            for (int c = 0; c < nc; c++)
+                cdofs[(K * nn + a) * nc + c] = int32_t(cd >= 0 ? nc * cd + c : -1 - (nc * (-1 - cd) + c));
+        }
+    // occurrences of the free nodes, ascending cell
+    std::vector<int64_t> optr(static_cast<size_t>(nfree) + 1, 0);
+    for (int64_t t = 0; t < ncells * nn; t++) {
+        const int64_t cd = code[pre[t]];
+        if (cd >= 0) optr[cd + 1]++;
+    }
+    for (int64_t r = 0; r < nfree; r++) optr[r + 1] += optr[r];
+    std::vector<uint32_t> oidx(static_cast<size_t>(optr[nfree]));
+    {
+        std::vector<int64_t> fill(optr.begin(), optr.end() - 1);
+        for (int64_t t = 0; t < ncells * nn; t++) {
+            const int64_t cd = code[pre[t]];
+            if (cd >= 0) oidx[fill[cd]++] = uint32_t(t);
+        }
+    }
+    // pattern and gather map: per free node, the candidates (column node,
+    // cell, a, b) sorted by (column node, cell)
+    const int ntri = S->ntri, nloc = S->nloc;
+    auto candidates = [&](int64_t r, std::vector<Cand> &cd) {
+        cd.clear();
+        for (int64_t t = optr[r]; t < optr[r + 1]; t++) {
+            const int64_t K = oidx[t] / nn;
+            const int a = int(oidx[t] % nn);
+            for (int b = 0; b < nn; b++) {
+                const int64_t cb = code[pre[K * nn + b]];
+                if (cb >= 0) cd.push_back({int32_t(cb), a, b, K});
+            }
+        }
+        std::sort(cd.begin(), cd.end(), [](const Cand &x, const Cand &y) {
+            return x.cn != y.cn ? x.cn < y.cn : x.K < y.K;
+        });
+    };
+    std::vector<int64_t> ncol(static_cast<size_t>(nfree)), ncand(static_cast<size_t>(nfree));
+    parallel_chunks(nfree, [&](int64_t lo, int64_t hi) {
+        std::vector<Cand> cd;
+        for (int64_t r = lo; r < hi; r++) {
+            candidates(r, cd);
+            int64_t m = 0;
+            for (size_t u = 0; u < cd.size(); u++)
+                if (u == 0 || cd[u].cn != cd[u - 1].cn) m++;
+            ncol[r] = m;
+            ncand[r] = int64_t(cd.size());
+        }
+    });
+    const int64_t nrows = S->n_rows;
+    std::vector<int64_t> rowptr(static_cast<size_t>(nrows) + 1, 0), cbase(size_t(nrows) + 1, 0);
+    for (int64_t r = 0; r < nfree; r++)
+        for (int i = 0; i < nc; i++) {
+            rowptr[r * nc + i + 1] = ncol[r] * nc;
+            cbase[r * nc + i + 1] = ncand[r] * nc;
+        }
+    for (int64_t row = 0; row < nrows; row++) {
+        rowptr[row + 1] += rowptr[row];
+        cbase[row + 1] += cbase[row];
+    }
+    const int64_t nnz = rowptr[nrows], ncontrib = cbase[nrows];
+    if (ncells * int64_t(ntri) >= (int64_t(1) << 32) || ncells * int64_t(nn) >= (int64_t(1) << 32))
+        return set_error(FE_EINVAL, "element storage of 2^32 or more entries");
+    std::vector<int32_t> colind(static_cast<size_t>(nnz));
+    std::vector<int64_t> gptr(static_cast<size_t>(nnz) + 1), diag(size_t(nrows), -1);
+    std::vector<uint32_t> gsrc(static_cast<size_t>(ncontrib));
+    parallel_chunks(nfree, [&](int64_t lo, int64_t hi) {
+        std::vector<Cand> cd;
+        for (int64_t r = lo; r < hi; r++) {
+            candidates(r, cd);
+            for (int i = 0; i < nc; i++) {
+                const int64_t row = r * nc + i;
+                int64_t pos = rowptr[row], cpos = cbase[row];
+                for (size_t u0 = 0; u0 < cd.size();) {
+                    size_t u1 = u0 + 1;
+                    while (u1 < cd.size() && cd[u1].cn == cd[u0].cn) u1++;
+                    for (int j = 0; j < nc; j++) {
+                        const int64_t col = int64_t(cd[u0].cn) * nc + j;
+                        colind[pos] = int32_t(col);
+                        gptr[pos] = cpos;
+                        if (col == row) diag[row] = pos;
+                        for (size_t u = u0; u < u1; u++) {
+                            const int I = cd[u].a * nc + i, J = cd[u].b * nc + j;
+                            const int lo2 = std::min(I, J), hi2 = std::max(I, J);
+                            const int t = lo2 * nloc - lo2 * (lo2 - 1) / 2 + (hi2 - lo2);
+                            gsrc[cpos++] = uint32_t(cd[u].K * ntri + t);
+                        }
+                        pos++;
+                    }
+                    u0 = u1;
+                }
+            }
+        }
+    });
+    gptr[nnz] = ncontrib;
+    S->nnz = nnz;
+    S->ncontrib = ncontrib;
+    S->h_rowptr.swap(rowptr);
+    S->h_colind.swap(colind);
+    // device copies
+    fe_status st = sx_upload(S->cell_dofs, cdofs.data(), cdofs.size());
+    if (st == FE_OK) st = sx_upload(S->gptr, gptr.data(), gptr.size());
+    if (st == FE_OK) st = sx_upload(S->gsrc, gsrc.data(), gsrc.size());
+    if (st == FE_OK) st = sx_upload(S->diag, diag.data(), diag.size());
+    if (st == FE_OK) st = sx_upload(S->optr, optr.data(), optr.size());
+    if (st == FE_OK) st = sx_upload(S->oidx, oidx.data(), oidx.size());
+    return st;
+}
+
+// Reference tables for the element kernel: the coefficient-pair table and the
+// entry table, the shape values at the rule's points and the rule itself.
+fe_status sx_tables(fe_simplex S)
+{
+    const int dim = S->dim, k = S->k, nn = S->nn, nc = S->ncomp, nloc = S->nloc, ntri = S->ntri;
+    SxRef R;
+    if (!sx_reference(dim, k, R) || R.nn != nn) return set_error(FE_EINVAL, "singular change of basis");
+    const int nq1 = k + (dim + 1) / 2;
+    std::vector<double> qxw;
+    sx_rule(dim, nq1, qxw);
+    const int nq = int(qxw.size() / (dim + 1));
+    std::vector<double> phiq(static_cast<size_t>(nq) * nn), dphi(size_t(nq) * nn * dim);
+    for (int q = 0; q < nq; q++) sx_eval(dim, R, &qxw[size_t(q) * (dim + 1)], &phiq[size_t(q) * nn], &dphi[size_t(q) * nn * dim]);
+    // S^{rs}_ab = sum_q w_q d_r phi_a d_s phi_b
+    std::vector<double> Sg(static_cast<size_t>(dim) * dim * nn * nn, 0.0);
+    for (int q = 0; q < nq; q++) {
+        const double w = qxw[size_t(q) * (dim + 1) + dim];
+        const double *g = &dphi[size_t(q) * nn * dim];
+        for (int r = 0; r < dim; r++)
+            for (int s = 0; s < dim; s++)
+                for (int a = 0; a < nn; a++)
+                    for (int b = 0; b < nn; b++)
+                        Sg[((size_t(r) * dim + s) * nn + a) * nn + b] += w * g[a * dim + r] * g[b * dim + s];
+    }
+    std::vector<double> tab;
+    std::vector<int32_t> tri(ntri);
+    {
+        int t = 0;
+        for (int I = 0; I < nloc; I++)
+            for (int J = I; J < nloc; J++) tri[t++] = (I << 16) | J;
+    }
+    if (S->args.problem == FE_ELASTICITY) {
+        tab = Sg;
+    } else {
+        const int np = dim * (dim + 1) / 2;
+        tab.assign(size_t(np) * ntri, 0.0);
+        int p = 0;
+        for (int r = 0; r < dim; r++)
+            for (int s = r; s < dim; s++, p++)
+                for (int t = 0; t < ntri; t++) {
+                    const int a = tri[t] >> 16, b = tri[t] & 0xffff;
+                    double v = Sg[((size_t(r) * dim + s) * nn + a) * nn + b];
+                    if (s != r) v += Sg[((size_t(s) * dim + r) * nn + a) * nn + b];
+                    tab[size_t(p) * ntri + t] = v;
+                }
+    }
+    (void)nc;
+    fe_status st = sx_upload(S->tab, tab.data(), tab.size());
+    if (st == FE_OK) st = sx_upload(S->tri, tri.data(), tri.size());
+    if (st == FE_OK) st = sx_upload(S->phiq, phiq.data(), phiq.size());
+    if (st == FE_OK) st = sx_upload(S->qxw, qxw.data(), qxw.size());
+    return st;
+}
+
+template <int DIM, int K, int PROB>
+fe_status launch_sx_elements(fe_simplex S, hipStream_t s)
+{
+    using Sh = SxShape<DIM, K, PROB>;
+    const int64_t nb = (S->ncells + Sh::CPB - 1) / Sh::CPB;
+    if (nb == 0) return FE_OK;
+    hipLaunchKernelGGL((sx_element_kernel<DIM, K, PROB>), dim3(unsigned(nb)), dim3(256), 0, s, S->args, S->vxyz,
+                       S->cells, S->coef, S->cell_dofs, S->tab, S->tri, S->phiq, S->qxw, S->E, S->F);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+fe_status launch_elements(fe_simplex S, hipStream_t s)
+{
+    const bool el = S->args.problem == FE_ELASTICITY;
+#define FE_SXL(D, KK)                                                                              \
+    return el ? launch_sx_elements<D, KK, FE_ELASTICITY>(S, s) : launch_sx_elements<D, KK, FE_POISSON>(S, s)
+    if (S->dim == 2) {
+        switch (S->k) {
+            case 1: FE_SXL(2, 1);
+            case 2: FE_SXL(2, 2);
+            case 3: FE_SXL(2, 3);
+            default: return launch_sx_elements<2, 4, FE_POISSON>(S, s);
+        }
+    }
+    switch (S->k) {
+        case 1: FE_SXL(3, 1);
+        case 2: FE_SXL(3, 2);
+        case 3: FE_SXL(3, 3);
+        default: return launch_sx_elements<3, 4, FE_POISSON>(S, s);
+    }
+#undef FE_SXL
+}
+
+unsigned blocks_of(int64_t n) { return unsigned(std::max<int64_t>(1, (n + 255) / 256)); }
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_simplex_create(const fe_simplex_desc *desc, int32_t order, const fe_coeff *coeff, fe_simplex *out)
+{
+    if (!desc || !coeff || !out) return set_error(FE_EINVAL, "null argument");
+    *out = nullptr;
+    const int dim = desc->dim;
+    if (dim != 2 && dim != 3) return set_error(FE_EINVAL, "dim must be 2 or 3");
+    if (order < 1 || order > kSxMaxK) return set_error(FE_EINVAL, "order must be in 1..4");
+    if (coeff->problem != FE_POISSON && coeff->problem != FE_ELASTICITY)
+        return set_error(FE_EINVAL, "unknown problem");
+    if (coeff->problem == FE_ELASTICITY && order > 3)
+        return set_error(FE_EINVAL, "elasticity on simplices supports orders 1..3");
+    if (coeff->precision != FE_FP64) return set_error(FE_EINVAL, "simplices integrate in FP64 only");
+    if (coeff->source_kind < FE_SOURCE_NONE || coeff->source_kind > FE_SOURCE_SINPROD)
+        return set_error(FE_EINVAL, "unknown source kind");
+    if (coeff->dirichlet_kind != FE_DIRICHLET_ZERO && coeff->dirichlet_kind != FE_DIRICHLET_AFFINE)
+        return set_error(FE_EINVAL, "unknown Dirichlet kind");
+    if (desc->nverts < 0 || desc->ncells < 0) return set_error(FE_EINVAL, "negative sizes");
+    if (desc->ncells > 0 && (!desc->cells || !desc->vertex_xyz)) return set_error(FE_EINVAL, "null mesh arrays");
+    if (desc->nverts >= (int64_t(1) << 31)) return set_error(FE_EINVAL, "2^31 or more vertices");
+    const int nv = dim + 1;
+    for (int64_t t = 0; t < desc->ncells * nv; t++)
+        if (desc->cells[t] < 0 || desc->cells[t] >= desc->nverts) return set_error(FE_EMESH, "vertex id out of range");
+    // degenerate cells (det J = 0) are rejected; either orientation is accepted
+    for (int64_t K = 0; K < desc->ncells; K++) {
+        double J[3][3];
+        const double *x0 = desc->vertex_xyz + int64_t(desc->cells[K * nv]) * dim;
+        for (int s = 0; s < dim; s++) {
+            const double *xs = desc->vertex_xyz + int64_t(desc->cells[K * nv + s + 1]) * dim;
+            for (int r = 0; r < dim; r++) J[r][s] = xs[r] - x0[r];
+        }
+        const double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                    : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det != 0.0) || !std::isfinite(det)) return set_error(FE_EMESH, "degenerate simplex (det J = 0)");
+    }
+    fe_simplex S = new fe_simplex_s();
+    S->dim = dim;
+    S->k = order;
+    S->nn = sx_nn(dim, order);
+    S->ncomp = coeff->problem == FE_ELASTICITY ? dim : 1;
+    S->nloc = S->nn * S->ncomp;
+    S->ntri = S->nloc * (S->nloc + 1) / 2;
+    S->nverts = desc->nverts;
+    S->ncells = desc->ncells;
+    SxArgs &a = S->args;
+    a.problem = coeff->problem;
+    a.source_kind = coeff->source_kind;
+    a.dirichlet_kind = coeff->dirichlet_kind;
+    for (int i = 0; i < 3; i++) a.source[i] = coeff->source[i];
+    for (int i = 0; i < 12; i++) a.aff[i] = coeff->dirichlet_affine[i];
+    if (coeff->problem == FE_ELASTICITY) {
+        const double E = coeff->young, nu = coeff->poisson_ratio;
+        if (!(nu > -1.0 && nu < 0.5)) {
+            delete S;
+            return set_error(FE_EINVAL, "poisson_ratio must be in (-1, 0.5)");
+        }
+        a.lambda = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        a.mu = E / (2.0 * (1.0 + nu));
+    }
+    a.ncells = desc->ncells;
+    {
+        std::vector<int> sl;
+        sx_lattice(dim, order, sl);
+        for (size_t t = 0; t < sl.size(); t++) a.s[t] = int8_t(sl[t]);
+    }
+    // every node of a boundary facet is fixed when dirichlet_faces != 0
+    S->fix_boundary = coeff->dirichlet_faces != 0;
+    fe_status st = sx_setup(S, desc->cells, desc->vertex_xyz);
+    if (st == FE_OK) st = sx_tables(S);
+    if (st == FE_OK) st = sx_upload(S->vxyz, desc->vertex_xyz, size_t(desc->nverts) * dim);
+    if (st == FE_OK) st = sx_upload(S->cells, desc->cells, size_t(desc->ncells) * nv);
+    if (st == FE_OK && desc->cell_coeff) st = sx_upload(S->coef, desc->cell_coeff, size_t(desc->ncells));
+    if (st == FE_OK) st = sx_alloc(S->E, size_t(S->ncells) * S->ntri);
+    if (st == FE_OK) st = sx_alloc(S->F, size_t(S->ncells) * S->nloc);
+    if (st != FE_OK) {
+        sx_free(S);
+        return st;
+    }
+    *out = S;
+    return FE_OK;
+}
+
+fe_status fe_simplex_destroy(fe_simplex S)
+{
+    if (!S) return set_error(FE_EINVAL, "null handle");
+    (void)hipDeviceSynchronize();
+    sx_free(S);
+    return FE_OK;
+}
+
+fe_status fe_simplex_query(fe_simplex S, int64_t *n_rows, int64_t *nnz, int64_t *n_nodes, int64_t *n_contrib)
+{
+    if (!S) return set_error(FE_EINVAL, "null handle");
+    if (n_rows) *n_rows = S->n_rows;
+    if (nnz) *nnz = S->nnz;
+    if (n_nodes) *n_nodes = S->nnodes;
+    if (n_contrib) *n_contrib = S->ncontrib;
+    return FE_OK;
+}
+
+fe_status fe_simplex_cell_dofs(fe_simplex S, int32_t *cell_dofs, fe_stream stream)
+{
+    if (!S || !cell_dofs) return set_error(FE_EINVAL, "null argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (S->ncells > 0)
+        FE_HIP(hipMemcpyAsync(cell_dofs, S->cell_dofs, sizeof(int32_t) * size_t(S->ncells) * S->nloc,
+                              hipMemcpyDeviceToDevice, s));
+    return FE_OK;
+}
+
+fe_status fe_simplex_pattern(fe_simplex S, const fe_csr *A, fe_stream stream)
+{
+    if (!S || !A || !A->rowptr || (S->nnz > 0 && !A->colind)) return set_error(FE_EINVAL, "null argument");
+    if (A->n_rows != S->n_rows || A->nnz != S->nnz) return set_error(FE_EINVAL, "CSR sizes do not match the space");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    FE_HIP(hipMemcpyAsync(A->rowptr, S->h_rowptr.data(), sizeof(int64_t) * S->h_rowptr.size(), hipMemcpyHostToDevice,
+                          s));
+    if (S->nnz > 0)
+        FE_HIP(hipMemcpyAsync(A->colind, S->h_colind.data(), sizeof(int32_t) * S->h_colind.size(),
+                              hipMemcpyHostToDevice, s));
+    FE_HIP(hipStreamSynchronize(s));
+    return FE_OK;
+}
+
+fe_status fe_simplex_assemble(fe_simplex S, const fe_csr *A, fe_stream stream)
+{
+    if (!S || !A || (S->nnz > 0 && !A->values) || (S->n_rows > 0 && (!A->rhs || !A->dinv)))
+        return set_error(FE_EINVAL, "null argument");
+    if (A->n_rows != S->n_rows || A->nnz != S->nnz) return set_error(FE_EINVAL, "CSR sizes do not match the space");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    fe_status st = launch_elements(S, s);
+    if (st != FE_OK) return st;
+    if (S->nnz > 0)
+        hipLaunchKernelGGL(sx_gather_kernel, dim3(blocks_of(S->nnz)), dim3(256), 0, s, S->nnz, S->gptr, S->gsrc, S->E,
+                           A->values);
+    if (S->n_rows > 0)
+        hipLaunchKernelGGL(sx_rhs_kernel, dim3(blocks_of(S->n_rows)), dim3(256), 0, s, S->n_rows, S->ncomp, S->optr,
+                           S->oidx, S->F, S->diag, A->values, A->rhs, A->dinv);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+fe_status fe_simplex_elements(fe_simplex S, const double **E, const double **F)
+{
+    if (!S) return set_error(FE_EINVAL, "null handle");
+    if (E) *E = S->E;
+    if (F) *F = S->F;
+    return FE_OK;
+}
+
+}  // extern "C"

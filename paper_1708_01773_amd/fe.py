@@ -35,7 +35,8 @@ EXPORTS = [
     "fe_refine_solve_mesh", "fe_refine_batch_query", "fe_refine_solve_batch_mesh", "fe_integrate_autotune",
     "fe_integrate_plan_of", "fe_dg_query", "fe_dg_pattern", "fe_dg_assemble", "fe_dg_spmv", "fe_dg_pcg_solve",
     "fe_stokes_create", "fe_stokes_destroy", "fe_stokes_query", "fe_stokes_assemble", "fe_stokes_system",
-    "fe_stokes_solve",
+    "fe_stokes_solve", "fe_simplex_create", "fe_simplex_destroy", "fe_simplex_query", "fe_simplex_cell_dofs",
+    "fe_simplex_pattern", "fe_simplex_assemble", "fe_simplex_elements",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -59,6 +60,11 @@ class Coeff(_c.Structure):
                 ("poisson_ratio", _c.c_double), ("source_kind", _c.c_int32), ("source", _c.c_double * 3),
                 ("dirichlet_faces", _c.c_uint32), ("dirichlet_kind", _c.c_int32),
                 ("dirichlet_affine", _c.c_double * 12)]
+
+
+class SimplexDesc(_c.Structure):
+    _fields_ = [("dim", _c.c_int32), ("nverts", _c.c_int64), ("ncells", _c.c_int64), ("vertex_xyz", _P),
+                ("cells", _P), ("cell_coeff", _P)]
 
 
 class Csr(_c.Structure):
@@ -184,6 +190,14 @@ def lib():
             "fe_dg_spmv": [_P, _c.c_int32, _c.POINTER(Csr), _P, _P, _P],
             "fe_stokes_create": [_P, _c.c_int32, _c.c_double, _c.POINTER(Coeff), _c.POINTER(_P)],
             "fe_stokes_destroy": [_P],
+            "fe_simplex_create": [_c.POINTER(SimplexDesc), _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_P)],
+            "fe_simplex_destroy": [_P],
+            "fe_simplex_query": [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                 _c.POINTER(_c.c_int64)],
+            "fe_simplex_cell_dofs": [_P, _P, _P],
+            "fe_simplex_pattern": [_P, _c.POINTER(Csr), _P],
+            "fe_simplex_assemble": [_P, _c.POINTER(Csr), _P],
+            "fe_simplex_elements": [_P, _c.POINTER(_P), _c.POINTER(_P)],
             "fe_stokes_query": [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
                                 _c.POINTER(_c.c_int64)],
             "fe_stokes_assemble": [_P, _P],
@@ -969,6 +983,81 @@ class Server:
         if self.handle:
             _check(lib().fe_server_destroy(self.handle), "fe_server_destroy")
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Simplex:
+    """Owning wrapper of an fe_simplex handle (P_k on a simplicial mesh) with
+    the device CSR of its free-free system (torch tensors); the pattern is
+    written at construction."""
+
+    def __init__(self, dim, vertices, cells, order, coeff, cell_coeff=None, device="cuda", stream=None):
+        import numpy as np
+        import torch
+        self.dim, self.order = int(dim), int(order)
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        k = None if cell_coeff is None else np.ascontiguousarray(cell_coeff, dtype=np.float64)
+        d = SimplexDesc()
+        d.dim = self.dim
+        d.nverts, d.ncells = v.shape[0], c.shape[0]
+        d.vertex_xyz = v.ctypes.data_as(_P)
+        d.cells = c.ctypes.data_as(_P)
+        d.cell_coeff = None if k is None else k.ctypes.data_as(_P)
+        h = _P()
+        _check(lib().fe_simplex_create(_c.byref(d), self.order, _c.byref(coeff), _c.byref(h)), "fe_simplex_create")
+        self.handle = h
+        self.ncells = c.shape[0]
+        nr, nz, nn, nc = _c.c_int64(), _c.c_int64(), _c.c_int64(), _c.c_int64()
+        _check(lib().fe_simplex_query(h, _c.byref(nr), _c.byref(nz), _c.byref(nn), _c.byref(nc)), "fe_simplex_query")
+        self.n_rows, self.nnz, self.n_nodes, self.n_contrib = nr.value, nz.value, nn.value, nc.value
+        ncomp = self.dim if coeff.problem == FE_ELASTICITY else 1
+        nnode = (order + 1) * (order + 2) // 2 if dim == 2 else (order + 1) * (order + 2) * (order + 3) // 6
+        self.nloc = nnode * ncomp
+        self.ntri = self.nloc * (self.nloc + 1) // 2
+        dev = torch.device(device)
+        self.rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=dev)
+        self.colind = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        self.values = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        self.rhs = torch.empty(max(self.n_rows, 1), dtype=torch.float64, device=dev)
+        self.dinv = torch.empty(max(self.n_rows, 1), dtype=torch.float64, device=dev)
+        self.csr = csr_struct(self.n_rows, self.nnz, self.rowptr, self.colind, self.values, self.rhs, self.dinv)
+        _check(lib().fe_simplex_pattern(h, _c.byref(self.csr), _stream(stream)), "fe_simplex_pattern")
+
+    def assemble(self, stream=None):
+        _check(lib().fe_simplex_assemble(self.handle, _c.byref(self.csr), _stream(stream)), "fe_simplex_assemble")
+
+    def cell_dofs(self, stream=None):
+        import torch
+        out = torch.empty((self.ncells, self.nloc), dtype=torch.int32, device="cuda")
+        _check(lib().fe_simplex_cell_dofs(self.handle, _ptr(out), _stream(stream)), "fe_simplex_cell_dofs")
+        return out
+
+    def elements(self):
+        """Host copies (numpy) of the last assembly's element upper triangles
+        (ncells x ntri) and loads (ncells x nloc)."""
+        import numpy as np
+        import torch
+        torch.cuda.synchronize()
+        e, f = _P(), _P()
+        _check(lib().fe_simplex_elements(self.handle, _c.byref(e), _c.byref(f)), "fe_simplex_elements")
+        E = np.empty((self.ncells, self.ntri))
+        F = np.empty((self.ncells, self.nloc))
+        if self.ncells:
+            _copy_to_host(E, e.value)
+            _copy_to_host(F, f.value)
+        return E, F
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            lib().fe_simplex_destroy(h)
+        self.handle = None
 
     def __del__(self):
         try:

@@ -148,3 +148,47 @@ def test_dg_entry_points_validate_on_host():
     assert L.fe_dg_pattern(None, 2, None, None) == F.FE_EINVAL
     c = F.make_coeff()
     assert L.fe_dg_assemble(None, 2, ctypes.byref(c), 36.0, 1.0, None, None, 0, None) == F.FE_EINVAL
+
+
+def _simplex_create(dim, verts, cells, order=2, problem="poisson", precision="fp64"):
+    L = F.lib()
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    d = F.SimplexDesc()
+    d.dim, d.nverts, d.ncells = dim, v.shape[0], c.shape[0]
+    d.vertex_xyz = v.ctypes.data_as(ctypes.c_void_p)
+    d.cells = c.ctypes.data_as(ctypes.c_void_p)
+    d.cell_coeff = None
+    h = ctypes.c_void_p()
+    coeff = F.make_coeff(problem, precision, dim=dim)
+    st = L.fe_simplex_create(ctypes.byref(d), order, ctypes.byref(coeff), ctypes.byref(h))
+    return st, L.fe_last_error().decode()
+
+
+def test_simplex_entry_points_validate_on_host():
+    """Argument and mesh checks of fe_simplex_create run before any device
+    call: bad dimension or order, reduced precision, vertex ids out of range,
+    degenerate cells, a facet shared by three cells."""
+    L = F.lib()
+    h = ctypes.c_void_p()
+    c = F.make_coeff()
+    assert L.fe_simplex_create(None, 1, ctypes.byref(c), ctypes.byref(h)) == F.FE_EINVAL
+    tet = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    assert _simplex_create(4, tet, [[0, 1, 2, 3]])[0] == F.FE_EINVAL
+    assert _simplex_create(3, tet, [[0, 1, 2, 3]], order=5)[0] == F.FE_EINVAL
+    assert _simplex_create(3, tet, [[0, 1, 2, 3]], order=4, problem="elasticity")[0] == F.FE_EINVAL
+    assert _simplex_create(3, tet, [[0, 1, 2, 3]], precision="fp32")[0] == F.FE_EINVAL
+    st, msg = _simplex_create(3, tet, [[0, 1, 2, 4]])
+    assert st == F.FE_EMESH and "range" in msg
+    flat = tet.copy()
+    flat[3] = [0.5, 0.5, 0.0]  # coplanar with the first three
+    st, msg = _simplex_create(3, flat, [[0, 1, 2, 3]])
+    assert st == F.FE_EMESH and "degenerate" in msg
+    tri = np.array([[0, 0], [1, 0], [0, 1], [1, 1], [-1, -1]], dtype=np.float64)
+    st, msg = _simplex_create(2, tri, [[0, 1, 2], [1, 2, 3], [2, 1, 4]])
+    assert st == F.FE_EMESH and "more than two" in msg
+    for name in ("fe_simplex_destroy",):
+        assert getattr(L, name)(None) == F.FE_EINVAL
+    assert L.fe_simplex_query(None, None, None, None, None) == F.FE_EINVAL
+    assert L.fe_simplex_pattern(None, None, None) == F.FE_EINVAL
+    assert L.fe_simplex_assemble(None, None, None) == F.FE_EINVAL
