@@ -127,6 +127,18 @@ def lib():
         L.orc_sx_assemble.restype = _i
         L.orc_sx_l2_error.argtypes = [ctypes.POINTER(OrcSxProblem), _P, _i64, _P, _P, _P, _i, _i, _P]
         L.orc_sx_l2_error.restype = _d
+        L.orc_vx_basis.argtypes = [_i, _i, _P]
+        L.orc_vx_basis.restype = _i
+        L.orc_vx_shape.argtypes = [_i, _i, _P, _P, _P, _P]
+        L.orc_vx_shape.restype = _i
+        L.orc_vx_element.argtypes = [_i, _i, _P, _P, _d, _d, _i, _P, _P, _P]
+        L.orc_vx_element.restype = _i
+        L.orc_vx_number.argtypes = [_i, _i, _i64, _i64, _P, _i, _P, _P, _P, _P, _P]
+        L.orc_vx_number.restype = _i
+        L.orc_vx_assemble.argtypes = [_i, _i, _P, _i64, _P, _P, _d, _i, _P, _P, _i64, _P, _P, _P, _P]
+        L.orc_vx_assemble.restype = _i
+        L.orc_vx_l2_error.argtypes = [_i, _i, _P, _i64, _P, _P, _P, _d, _i]
+        L.orc_vx_l2_error.restype = _d
         _lib = L
     return _lib
 
@@ -851,3 +863,105 @@ class SimplexSystem:
         return lib().orc_sx_l2_error(ctypes.byref(self._s), _ptr(self.verts), self.cells.shape[0], _ptr(self.cells),
                                      _ptr(self.cell_dofs), _ptr(_c(x, np.float64)), int(nq1), int(exact_kind),
                                      _ptr(ex))
+
+
+# ---------------------------------------------------------------------------
+# Lowest-order Nedelec (edges, covariant Piola) and Raviart-Thomas (facets,
+# contravariant Piola) elements on simplices (fe_oracle_simplex.c)
+# ---------------------------------------------------------------------------
+FAMILIES = {"nedelec": 1, "raviart_thomas": 2}
+
+
+def vector_ndof(family, dim):
+    return (6 if dim == 3 else 3) if family == "nedelec" else dim + 1
+
+
+def vector_basis(family, dim):
+    nd = vector_ndof(family, dim)
+    Phi = np.zeros((nd, nd))
+    if lib().orc_vx_basis(FAMILIES[family], dim, _ptr(Phi)) != nd:
+        raise ValueError("unsupported family/dim")
+    return Phi
+
+
+def vector_shape(family, dim, xi):
+    """Reference shape functions (nd x dim), curls (nd x 3 in 3D, nd in 2D), divergences (nd)."""
+    nd = vector_ndof(family, dim)
+    x = _c(list(xi) + [0.0] * (3 - len(xi)), np.float64)
+    phi = np.zeros((nd, dim))
+    curl = np.zeros((nd, 3)) if dim == 3 else np.zeros(nd)
+    div = np.zeros(nd)
+    lib().orc_vx_shape(FAMILIES[family], dim, _ptr(x), _ptr(phi), _ptr(curl), _ptr(div))
+    return phi, curl, div
+
+
+def vector_element(family, dim, X, g, coef=1.0, kappa=1.0, source_kind=0, source=(0.0, 0.0, 0.0)):
+    """Element matrix and load (global orientation signs applied); (A, f, ok)."""
+    nd = vector_ndof(family, dim)
+    A = np.zeros((nd, nd))
+    f = np.zeros(nd)
+    src = _c(list(source) + [0.0] * (3 - len(source)), np.float64)
+    rc = lib().orc_vx_element(FAMILIES[family], dim, _ptr(_c(X, np.float64).reshape(-1)), _ptr(_c(g, np.int32)),
+                              float(coef), float(kappa), int(source_kind), _ptr(src), _ptr(A), _ptr(f))
+    return A, f, rc == 0
+
+
+def vector_number(family, dim, nverts, cells, dirichlet=True):
+    cells = _c(cells, np.int32)
+    nc = cells.shape[0]
+    nd = vector_ndof(family, dim)
+    dof_of = np.zeros((nc, nd), dtype=np.int64)
+    code = np.zeros(max(nc * nd, 1), dtype=np.int64)
+    ne, nf, nx = _i64(), _i64(), _i64()
+    rc = lib().orc_vx_number(FAMILIES[family], dim, int(nverts), nc, _ptr(cells), 1 if dirichlet else 0,
+                             _ptr(dof_of), _ptr(code), ctypes.byref(ne), ctypes.byref(nf), ctypes.byref(nx))
+    if rc != 0:
+        raise ValueError(f"orc_vx_number failed ({rc})")
+    return dof_of, code[: ne.value].copy(), nf.value, nx.value
+
+
+class VectorSystem:
+    """The oracle's free-free system of a lowest-order vector element on a
+    simplicial mesh: int coef curl.curl (div div) + kappa u.v, zero
+    tangential (normal) trace on the boundary when dirichlet."""
+
+    def __init__(self, family, dim, verts, cells, coef=None, kappa=1.0, source_kind=0, source=(0.0, 0.0, 0.0),
+                 dirichlet=True):
+        self.family, self.dim = family, int(dim)
+        self.verts = _c(verts, np.float64)
+        self.cells = _c(cells, np.int32)
+        self.coef = None if coef is None else _c(coef, np.float64)
+        self.kappa = float(kappa)
+        self.nd = vector_ndof(family, dim)
+        self.dof_of, self.code, self.nfree, self.nfixed = vector_number(family, dim, self.verts.shape[0], self.cells,
+                                                                        dirichlet)
+        self.nent = len(self.code)
+        self.cell_dofs = self.code[self.dof_of]
+        self.rowptr, self.colind = csr_pattern(self.cell_dofs, self.nfree)
+        self.nnz = int(self.rowptr[-1])
+        self.values = np.zeros(self.nnz)
+        self.rhs = np.zeros(self.nfree)
+        src = _c(list(source) + [0.0] * (3 - len(source)), np.float64)
+        t0 = time.perf_counter()
+        rc = lib().orc_vx_assemble(FAMILIES[family], self.dim, _ptr(self.verts), self.cells.shape[0], _ptr(self.cells),
+                                   _ptr(self.coef), self.kappa, int(source_kind), _ptr(src), _ptr(self.cell_dofs),
+                                   self.nfree, _ptr(self.rowptr), _ptr(_c(self.colind, np.int32)), _ptr(self.values),
+                                   _ptr(self.rhs))
+        self.t_assemble = time.perf_counter() - t0
+        self.ok = rc == 0
+        rows = np.repeat(np.arange(self.nfree), np.diff(self.rowptr))
+        diag = self.values[self.colind == rows]
+        self.dinv = 1.0 / diag if self.nfree else diag
+
+    def scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.values, self.colind, self.rowptr), shape=(self.nfree, self.nfree))
+
+    def solve(self):
+        import scipy.sparse.linalg as spla
+        return spla.spsolve(self.scipy().tocsc(), self.rhs)
+
+    def l2_error(self, x, scale, nq1=4):
+        return lib().orc_vx_l2_error(FAMILIES[self.family], self.dim, _ptr(self.verts), self.cells.shape[0],
+                                     _ptr(self.cells), _ptr(_c(self.cell_dofs, np.int64)), _ptr(_c(x, np.float64)),
+                                     float(scale), int(nq1))

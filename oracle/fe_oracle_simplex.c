@@ -619,3 +619,484 @@ double orc_sx_l2_error(const orc_sx_problem *P, const double *vxyz, int64_t ncel
     double norm = sqrt(err2);
     return norm;
 }
+
+/* ======================================================================== */
+/* Lowest-order vector elements on simplices (Sect. 3.9 div-conforming,      */
+/* Sect. 3.10 curl-conforming): family 1 = Nedelec edge elements (space      */
+/* [P_0]^d + S, S = {W x : W skew}, one tangential moment per edge,          */
+/* covariant Piola map), family 2 = Raviart-Thomas (space [P_0]^d + x P_0,   */
+/* one flux moment per facet, contravariant Piola map).  Shape functions by  */
+/* the change of basis of Sect. 3.5 from that pre-basis.                     */
+/*                                                                          */
+/* Moments on the reference simplex (the readings taken):                   */
+/*  - edge (i, j), i < j local: int_0^1 v(x_i + t (x_j - x_i)) . (x_j - x_i) */
+/*    dt (the tangent not normalized: the line integral, which the          */
+/*    covariant map preserves);                                             */
+/*  - facet opposite local vertex j, its vertices i0 < i1 (< i2) local:     */
+/*    int over the reference (d-1)-simplex of v(phi_F(s)) . N ds with       */
+/*    phi_F(s) = x_i0 + s_1 (x_i1 - x_i0) (+ s_2 (x_i2 - x_i0)) and         */
+/*    N = (x_i1 - x_i0) x (x_i2 - x_i0) in 3D, N = rot(x_i1 - x_i0) =       */
+/*    (t_y, -t_x) in 2D (the flux, which the contravariant map preserves).  */
+/*  - Global orientation: an edge runs from its lower to its higher global  */
+/*    vertex id; a facet's normal is N taken over its vertices in ascending */
+/*    global id.  A local DOF whose local orientation differs has sign -1:  */
+/*    the cell's matrix and load are multiplied by the signs.               */
+/* Local DOF order: edges (0,1),(0,2),(1,2) in 2D and (0,1),(0,2),(0,3),    */
+/* (1,2),(1,3),(2,3) in 3D; facets by the opposite local vertex.            */
+/* ======================================================================== */
+static int vx_ndof(int family, int dim) { return family == 1 ? (dim == 3 ? 6 : 3) : dim + 1; }
+
+static void vx_edge(int dim, int a, int *i, int *j)
+{
+    static const int e2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    static const int e3[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    *i = dim == 3 ? e3[a][0] : e2[a][0];
+    *j = dim == 3 ? e3[a][1] : e2[a][1];
+}
+
+/* vertex r of the reference simplex */
+static void vx_ref_vertex(int dim, int r, double *x)
+{
+    for (int t = 0; t < dim; t++) x[t] = (r > 0 && t == r - 1) ? 1.0 : 0.0;
+}
+
+/* pre-basis function b at x: value v[dim], derivative dv[c*dim + r] = d v_c / d x_r */
+static void vx_prebasis(int family, int dim, int b, const double *x, double *v, double *dv)
+{
+    for (int c = 0; c < dim; c++) {
+        v[c] = 0.0;
+        for (int r = 0; r < dim; r++) dv[c * dim + r] = 0.0;
+    }
+    if (b < dim) { /* constants e_b */
+        v[b] = 1.0;
+        return;
+    }
+    if (family == 2) { /* x */
+        for (int c = 0; c < dim; c++) {
+            v[c] = x[c];
+            dv[c * dim + c] = 1.0;
+        }
+        return;
+    }
+    /* Nedelec: rotations W x.  2D: (-y, x).  3D: b = 3: (0, -z, y), 4: (z, 0, -x), 5: (-y, x, 0) */
+    if (dim == 2) {
+        v[0] = -x[1];
+        v[1] = x[0];
+        dv[0 * 2 + 1] = -1.0;
+        dv[1 * 2 + 0] = 1.0;
+        return;
+    }
+    int m = b - 3; /* rotation about axis m: v = e_m x x */
+    int p = (m + 1) % 3, q = (m + 2) % 3;
+    v[p] = -x[q];
+    v[q] = x[p];
+    dv[p * 3 + q] = -1.0;
+    dv[q * 3 + p] = 1.0;
+}
+
+/* moment a of the function f (given as a pre-basis index b) */
+static double vx_moment(int family, int dim, int a, int b)
+{
+    double gx[ORC_MAXQ1], gw[ORC_MAXQ1];
+    double v[3], dv[9], p[3], xi[3], xj[3];
+    double s = 0.0;
+    if (family == 1) {
+        int i, j;
+        vx_edge(dim, a, &i, &j);
+        vx_ref_vertex(dim, i, xi);
+        vx_ref_vertex(dim, j, xj);
+        orc_gauss_legendre(2, gx, gw);
+        for (int q = 0; q < 2; q++) {
+            for (int t = 0; t < dim; t++) p[t] = xi[t] + gx[q] * (xj[t] - xi[t]);
+            vx_prebasis(family, dim, b, p, v, dv);
+            double d = 0.0;
+            for (int t = 0; t < dim; t++) d += v[t] * (xj[t] - xi[t]);
+            s += gw[q] * d;
+        }
+        return s;
+    }
+    /* facet opposite vertex a */
+    int iv[3], m = 0;
+    for (int r = 0; r <= dim; r++)
+        if (r != a) iv[m++] = r;
+    double x0[3], x1[3], x2[3] = {0, 0, 0}, N[3];
+    vx_ref_vertex(dim, iv[0], x0);
+    vx_ref_vertex(dim, iv[1], x1);
+    if (dim == 3) vx_ref_vertex(dim, iv[2], x2);
+    if (dim == 2) {
+        N[0] = x1[1] - x0[1];
+        N[1] = -(x1[0] - x0[0]);
+    } else {
+        double t1[3], t2[3];
+        for (int t = 0; t < 3; t++) {
+            t1[t] = x1[t] - x0[t];
+            t2[t] = x2[t] - x0[t];
+        }
+        N[0] = t1[1] * t2[2] - t1[2] * t2[1];
+        N[1] = t1[2] * t2[0] - t1[0] * t2[2];
+        N[2] = t1[0] * t2[1] - t1[1] * t2[0];
+    }
+    if (dim == 2) {
+        orc_gauss_legendre(2, gx, gw);
+        for (int q = 0; q < 2; q++) {
+            for (int t = 0; t < 2; t++) p[t] = x0[t] + gx[q] * (x1[t] - x0[t]);
+            vx_prebasis(family, dim, b, p, v, dv);
+            s += gw[q] * (v[0] * N[0] + v[1] * N[1]);
+        }
+        return s;
+    }
+    double sq[3 * 9], sw[9];
+    int nq = orc_sx_quadrature(2, 3, sq, sw);
+    for (int q = 0; q < nq; q++) {
+        for (int t = 0; t < 3; t++) p[t] = x0[t] + sq[3 * q] * (x1[t] - x0[t]) + sq[3 * q + 1] * (x2[t] - x0[t]);
+        vx_prebasis(family, dim, b, p, v, dv);
+        s += sw[q] * (v[0] * N[0] + v[1] * N[1] + v[2] * N[2]);
+    }
+    return s;
+}
+
+/* Change-of-basis matrix Phi (nd x nd) of the family.  Returns nd or -1. */
+int orc_vx_basis(int family, int dim, double *Phi)
+{
+    if ((family != 1 && family != 2) || dim < 2 || dim > 3) return -1;
+    int nd = vx_ndof(family, dim);
+    double C[36], Ci[36];
+    for (int a = 0; a < nd; a++)
+        for (int b = 0; b < nd; b++) C[a * nd + b] = vx_moment(family, dim, a, b);
+    if (sx_invert(nd, C, Ci) != 0) return -1;
+    for (int a = 0; a < nd; a++)
+        for (int b = 0; b < nd; b++) Phi[a * nd + b] = Ci[b * nd + a];
+    return nd;
+}
+
+/* Shape functions phi_a = sum_b Phi_ab psi_b at xi from a change-of-basis
+ * matrix: phi[a*dim + c], their curl (3D: curl[a*3 + c]; 2D: the scalar
+ * curl[a]) and divergence div[a]. */
+static void vx_shape_with(int family, int dim, int nd, const double *Phi, const double *xi, double *phi, double *curl,
+                          double *div)
+{
+    for (int a = 0; a < nd; a++) {
+        double v[3] = {0, 0, 0}, dv[9] = {0};
+        for (int b = 0; b < nd; b++) {
+            double pv[3], pdv[9];
+            vx_prebasis(family, dim, b, xi, pv, pdv);
+            for (int c = 0; c < dim; c++) v[c] += Phi[a * nd + b] * pv[c];
+            for (int t = 0; t < dim * dim; t++) dv[t] += Phi[a * nd + b] * pdv[t];
+        }
+        for (int c = 0; c < dim; c++) phi[a * dim + c] = v[c];
+        if (dim == 3) {
+            curl[a * 3 + 0] = dv[2 * 3 + 1] - dv[1 * 3 + 2];
+            curl[a * 3 + 1] = dv[0 * 3 + 2] - dv[2 * 3 + 0];
+            curl[a * 3 + 2] = dv[1 * 3 + 0] - dv[0 * 3 + 1];
+        } else {
+            curl[a] = dv[1 * 2 + 0] - dv[0 * 2 + 1];
+        }
+        div[a] = 0.0;
+        for (int c = 0; c < dim; c++) div[a] += dv[c * dim + c];
+    }
+}
+
+/* Reference shape functions at xi (the family's basis; for tests). */
+int orc_vx_shape(int family, int dim, const double *xi, double *phi, double *curl, double *div)
+{
+    double Phi[36];
+    int nd = orc_vx_basis(family, dim, Phi);
+    if (nd < 0) return -1;
+    vx_shape_with(family, dim, nd, Phi, xi, phi, curl, div);
+    return nd;
+}
+
+/* Orientation signs of the local DOFs from the cell's global vertex ids. */
+static void vx_signs(int family, int dim, const int32_t *g, double *sgn)
+{
+    int nd = vx_ndof(family, dim);
+    for (int a = 0; a < nd; a++) {
+        if (family == 1) {
+            int i, j;
+            vx_edge(dim, a, &i, &j);
+            sgn[a] = g[i] < g[j] ? 1.0 : -1.0;
+        } else {
+            int iv[3], m = 0;
+            for (int r = 0; r <= dim; r++)
+                if (r != a) iv[m++] = g[r];
+            /* parity of the permutation sorting the facet's vertex ids */
+            int inv = 0;
+            for (int x = 0; x < m; x++)
+                for (int y = x + 1; y < m; y++)
+                    if (iv[x] > iv[y]) inv++;
+            sgn[a] = (inv % 2) ? -1.0 : 1.0;
+        }
+    }
+}
+
+/* The family's manufactured field m(x): Nedelec 3D (sin pi y sin pi z,
+ * sin pi z sin pi x, sin pi x sin pi y), 2D (sin pi y, sin pi x);
+ * Raviart-Thomas (sin pi x_r)_r. */
+static void vx_field(int family, int dim, const double *x, double *m)
+{
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < dim; r++) s[r] = sin(M_PI * x[r]);
+    if (family == 2) {
+        for (int r = 0; r < dim; r++) m[r] = s[r];
+    } else if (dim == 2) {
+        m[0] = s[1];
+        m[1] = s[0];
+    } else {
+        m[0] = s[1] * s[2];
+        m[1] = s[2] * s[0];
+        m[2] = s[0] * s[1];
+    }
+}
+
+/* load f_c(x): kind 1 constant source[c], kind 2 source[c] m_c(x) */
+static void vx_source(int family, int dim, int kind, const double *src, const double *x, double *f)
+{
+    double m[3] = {0, 0, 0};
+    if (kind == 2) vx_field(family, dim, x, m);
+    for (int c = 0; c < dim; c++) f[c] = kind == 1 ? src[c] : kind == 2 ? src[c] * m[c] : 0.0;
+}
+
+/* Element matrix and load of the form
+ *   a(u, v) = int coef (curl u . curl v) + kappa u . v     (family 1)
+ *   a(u, v) = int coef (div u div v) + kappa u . v         (family 2)
+ * on a simplex with vertices X and global vertex ids g (for the signs),
+ * by the collapsed rule with 1 + ceil(d/2) points per direction; physical
+ * shape functions J^-T phi (family 1, curl J curl / det J in 3D, curl / det J
+ * in 2D) or J phi / det J (family 2, div / det J).  A nd x nd, f nd. */
+int orc_vx_element(int family, int dim, const double *X, const int32_t *g, double coef, double kappa,
+                   int source_kind, const double *source, double *A, double *f)
+{
+    int nd = vx_ndof(family, dim);
+    int n = 1 + (dim + 1) / 2;
+    int nq = ipow(n, dim);
+    double qx[3 * 27], qw[27];
+    orc_sx_quadrature(dim, n, qx, qw);
+    double J[9], Ji[9];
+    double det = sx_jacobian(dim, X, J, Ji);
+    double sgn[6], Phi[36];
+    vx_signs(family, dim, g, sgn);
+    orc_vx_basis(family, dim, Phi);
+    memset(A, 0, sizeof(double) * nd * nd);
+    memset(f, 0, sizeof(double) * nd);
+    for (int q = 0; q < nq; q++) {
+        double phi[18], curl[18], div[6];
+        vx_shape_with(family, dim, nd, Phi, qx + 3 * q, phi, curl, div);
+        double P[18], Cp[18], Dp[6]; /* physical values */
+        for (int a = 0; a < nd; a++) {
+            for (int c = 0; c < dim; c++) {
+                double v = 0.0;
+                for (int r = 0; r < dim; r++)
+                    v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;
+                P[a * dim + c] = v;
+            }
+            if (dim == 3) {
+                for (int c = 0; c < 3; c++) {
+                    double v = 0.0;
+                    for (int r = 0; r < 3; r++) v += J[c * 3 + r] * curl[a * 3 + r];
+                    Cp[a * 3 + c] = v / det;
+                }
+            } else {
+                Cp[a] = curl[a] / det;
+            }
+            Dp[a] = div[a] / det;
+        }
+        double x[3] = {0, 0, 0};
+        for (int r = 0; r < dim; r++) {
+            x[r] = X[r];
+            for (int t = 0; t < dim; t++) x[r] += J[r * dim + t] * qx[3 * q + t];
+        }
+        double fx[3];
+        vx_source(family, dim, source_kind, source, x, fx);
+        double wd = qw[q] * fabs(det);
+        int nc = dim == 3 ? 3 : 1;
+        for (int a = 0; a < nd; a++) {
+            double fa = 0.0;
+            for (int c = 0; c < dim; c++) fa += fx[c] * P[a * dim + c];
+            f[a] += wd * fa;
+            for (int b = 0; b < nd; b++) {
+                double st = 0.0, ms = 0.0;
+                if (family == 1)
+                    for (int c = 0; c < nc; c++) st += Cp[a * nc + c] * Cp[b * nc + c];
+                else
+                    st = Dp[a] * Dp[b];
+                for (int c = 0; c < dim; c++) ms += P[a * dim + c] * P[b * dim + c];
+                A[a * nd + b] += wd * (coef * st + kappa * ms);
+            }
+        }
+    }
+    for (int a = 0; a < nd; a++) {
+        f[a] *= sgn[a];
+        for (int b = 0; b < nd; b++) A[a * nd + b] *= sgn[a] * sgn[b];
+    }
+    return det == 0.0 ? -1 : 0;
+}
+
+/* Numbering of the DOF entities (edges for family 1, facets for family 2):
+ * ids by first appearance over (cell, local DOF); dirichlet != 0 fixes the
+ * entities on the boundary (facets of one cell, and their edges).
+ * dof_of[K*nd + a], code[entity] as orc_sx_number.  Returns 0, -1, -2. */
+int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int32_t *cells, int dirichlet,
+                  int64_t *dof_of, int64_t *code, int64_t *nent_out, int64_t *nfree_out, int64_t *nfixed_out)
+{
+    if ((family != 1 && family != 2) || dim < 2 || dim > 3) return -1;
+    int nd = vx_ndof(family, dim), nv = dim + 1;
+    for (int64_t t = 0; t < ncells * nv; t++)
+        if (cells[t] < 0 || cells[t] >= nverts) return -1;
+    /* entity keys as sx_facet records (vertex triple, padded) */
+    int64_t nrec = ncells * nd;
+    sx_facet *rec = (sx_facet *)malloc(sizeof(sx_facet) * (nrec > 0 ? nrec : 1));
+    for (int64_t K = 0; K < ncells; K++)
+        for (int a = 0; a < nd; a++) {
+            sx_facet *r = rec + K * nd + a;
+            int m = 0;
+            if (family == 1) {
+                int i, j;
+                vx_edge(dim, a, &i, &j);
+                r->v[m++] = cells[K * nv + i];
+                r->v[m++] = cells[K * nv + j];
+            } else {
+                for (int t = 0; t < nv; t++)
+                    if (t != a) r->v[m++] = cells[K * nv + t];
+            }
+            sx_sort_small(r->v, NULL, m);
+            for (int t = m; t < 3; t++) r->v[t] = INT32_MAX;
+            r->cell = K;
+            r->j = a;
+        }
+    qsort(rec, nrec, sizeof(sx_facet), sx_facet_cmp);
+    sx_first *first_of = (sx_first *)malloc(sizeof(sx_first) * (nrec > 0 ? nrec : 1));
+    int64_t ng = 0;
+    for (int64_t t = 0; t < nrec; t++)
+        if (t == 0 || memcmp(rec[t].v, rec[t - 1].v, sizeof(rec[t].v)) != 0) {
+            first_of[ng].first = rec[t].cell * nd + rec[t].j;
+            first_of[ng].group = t;
+            ng++;
+        }
+    qsort(first_of, ng, sizeof(sx_first), sx_first_cmp);
+    for (int64_t g2 = 0; g2 < ng; g2++) {
+        int64_t t = first_of[g2].group;
+        do {
+            dof_of[rec[t].cell * nd + rec[t].j] = g2;
+            t++;
+        } while (t < nrec && memcmp(rec[t].v, rec[t - 1].v, sizeof(rec[t].v)) == 0);
+    }
+    free(first_of);
+    free(rec);
+    /* boundary facets */
+    int64_t nfac = ncells * nv;
+    sx_facet *fac = (sx_facet *)malloc(sizeof(sx_facet) * (nfac > 0 ? nfac : 1));
+    for (int64_t K = 0; K < ncells; K++)
+        for (int j = 0; j < nv; j++) {
+            sx_facet *f = fac + K * nv + j;
+            int m = 0;
+            for (int i = 0; i < nv; i++)
+                if (i != j) f->v[m++] = cells[K * nv + i];
+            sx_sort_small(f->v, NULL, m);
+            if (m < 3) f->v[2] = INT32_MAX;
+            f->cell = K;
+            f->j = j;
+        }
+    qsort(fac, nfac, sizeof(sx_facet), sx_facet_cmp);
+    char *bnd = (char *)calloc(ng > 0 ? ng : 1, 1);
+    int bad = 0;
+    for (int64_t t = 0; t < nfac;) {
+        int64_t u = t + 1;
+        while (u < nfac && memcmp(fac[u].v, fac[t].v, sizeof(fac[t].v)) == 0) u++;
+        if (u - t > 2) bad = 1;
+        if (u - t == 1) {
+            int64_t K = fac[t].cell;
+            int j = fac[t].j;
+            for (int a = 0; a < nd; a++) {
+                int on;
+                if (family == 2) {
+                    on = a == j;
+                } else {
+                    int i1, j1;
+                    vx_edge(dim, a, &i1, &j1);
+                    on = i1 != j && j1 != j; /* the edge avoids the opposite vertex */
+                }
+                if (on) bnd[dof_of[K * nd + a]] = 1;
+            }
+        }
+        t = u;
+    }
+    free(fac);
+    int64_t nfree = 0, nfixed = 0;
+    for (int64_t g2 = 0; g2 < ng; g2++) code[g2] = (dirichlet && bnd[g2]) ? -1 - nfixed++ : nfree++;
+    free(bnd);
+    *nent_out = ng;
+    *nfree_out = nfree;
+    *nfixed_out = nfixed;
+    return bad ? -2 : 0;
+}
+
+/* Assembly of the vector-element system (zero boundary data: fixed DOFs are
+ * dropped), cells ascending, as orc_sx_assemble. */
+int orc_vx_assemble(int family, int dim, const double *vxyz, int64_t ncells, const int32_t *cells, const double *coef,
+                    double kappa, int source_kind, const double *source, const int64_t *cell_dofs, int64_t nfree,
+                    const int64_t *rowptr, const int32_t *colind, double *values, double *rhs)
+{
+    int nd = vx_ndof(family, dim), nv = dim + 1;
+    memset(values, 0, sizeof(double) * rowptr[nfree]);
+    memset(rhs, 0, sizeof(double) * nfree);
+    double A[36], f[6], X[12];
+    int bad = 0;
+    for (int64_t K = 0; K < ncells; K++) {
+        sx_cell_vertices(dim, cells, vxyz, K, X);
+        if (orc_vx_element(family, dim, X, cells + K * nv, coef ? coef[K] : 1.0, kappa, source_kind, source, A, f))
+            bad = 1;
+        const int64_t *g = cell_dofs + K * nd;
+        for (int a = 0; a < nd; a++) {
+            if (g[a] < 0) continue;
+            rhs[g[a]] += f[a];
+            for (int b = 0; b < nd; b++)
+                if (g[b] >= 0) values[orc_find(rowptr, colind, g[a], g[b])] += A[a * nd + b];
+        }
+    }
+    return bad ? -1 : 0;
+}
+
+/* L2 error of the discrete field (free DOF values x, fixed DOFs zero)
+ * against scale * m(x), the family's manufactured field, on the collapsed
+ * rule with nq1 points per direction. */
+double orc_vx_l2_error(int family, int dim, const double *vxyz, int64_t ncells, const int32_t *cells,
+                       const int64_t *cell_dofs, const double *x, double scale, int nq1)
+{
+    int nd = vx_ndof(family, dim), nv = dim + 1;
+    int nq = ipow(nq1, dim);
+    double *qx = (double *)malloc(sizeof(double) * 3 * nq), *qw = (double *)malloc(sizeof(double) * nq);
+    orc_sx_quadrature(dim, nq1, qx, qw);
+    double X[12], J[9], Ji[9], err2 = 0.0, Phi[36];
+    orc_vx_basis(family, dim, Phi);
+    for (int64_t K = 0; K < ncells; K++) {
+        sx_cell_vertices(dim, cells, vxyz, K, X);
+        double det = sx_jacobian(dim, X, J, Ji);
+        double sgn[6], u[6];
+        vx_signs(family, dim, cells + K * nv, sgn);
+        for (int a = 0; a < nd; a++) {
+            int64_t gd = cell_dofs[K * nd + a];
+            u[a] = gd >= 0 ? sgn[a] * x[gd] : 0.0;
+        }
+        for (int q = 0; q < nq; q++) {
+            double phi[18], curl[18], div[6], uh[3] = {0, 0, 0}, p[3], m[3];
+            vx_shape_with(family, dim, nd, Phi, qx + 3 * q, phi, curl, div);
+            for (int a = 0; a < nd; a++)
+                for (int c = 0; c < dim; c++)
+                    for (int r = 0; r < dim; r++) {
+                        /* covariant J^-T phi, or contravariant J phi / det J */
+                        double m1 = family == 1 ? Ji[r * dim + c] : J[c * dim + r] / det;
+                        uh[c] += u[a] * m1 * phi[a * dim + r];
+                    }
+            for (int r = 0; r < dim; r++) {
+                p[r] = X[r];
+                for (int t = 0; t < dim; t++) p[r] += J[r * dim + t] * qx[3 * q + t];
+            }
+            vx_field(family, dim, p, m);
+            for (int c = 0; c < dim; c++) err2 += qw[q] * fabs(det) * (uh[c] - scale * m[c]) * (uh[c] - scale * m[c]);
+        }
+    }
+    free(qx);
+    free(qw);
+    double e = sqrt(err2);
+    return e;
+}

@@ -18,6 +18,7 @@ from tests import test_oracle_dg as DG
 from tests import test_oracle_pins as PINS
 from tests import test_oracle_simplex as SX
 from tests import test_oracle_stokes as ST
+from tests import test_oracle_vector as VX
 
 # the oracle's sources: fe_oracle.c includes the simplex part
 ORACLE_FILES = ("fe_oracle.c", "fe_oracle_simplex.c")
@@ -64,6 +65,18 @@ MUTANTS = {
     "simplex_lifting_sign": ("else rhs[g[i]] -= A[i * nloc + j] * ud[j];", "else rhs[g[i]] += A[i * nloc + j] * ud[j];"),
     "simplex_l2_error_without_sqrt": ("double norm = sqrt(err2);", "double norm = err2;"),
     "simplex_numbering_not_first_appearance": ("qsort(grp, ng, sizeof(sx_first), sx_first_cmp);", ""),
+    "vector_edge_orientation_ignored": ("sgn[a] = g[i] < g[j] ? 1.0 : -1.0;", "sgn[a] = 1.0;"),
+    "vector_facet_orientation_ignored": ("sgn[a] = (inv % 2) ? -1.0 : 1.0;", "sgn[a] = 1.0;"),
+    "vector_covariant_map_untransposed": (
+        "v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
+        "v += family == 1 ? Ji[c * dim + r] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;"),
+    "vector_contravariant_map_without_det": (
+        "v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
+        "v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r];"),
+    "vector_curl_map_without_det": ("Cp[a * 3 + c] = v / det;", "Cp[a * 3 + c] = v;"),
+    "vector_edge_tangent_reversed": ("d += v[t] * (xj[t] - xi[t]);", "d += v[t] * (xi[t] - xj[t]);"),
+    "vector_boundary_edge_test": ("on = i1 != j && j1 != j;", "on = i1 != j || j1 != j;"),
+    "vector_mass_without_kappa": ("A[a * nd + b] += wd * (coef * st + kappa * ms);", "A[a * nd + b] += wd * (coef * st + ms);"),
     "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                   "err2 += w * (ue - uh) * (ue - uh);"),
 }
@@ -95,6 +108,15 @@ PIN_CALLS = [
     lambda: SX.test_linear_patch_test(3, 1, "poisson", 3),
     lambda: SX.test_linear_patch_test(3, 2, "elasticity", 2),
     lambda: SX.test_l2_error_magnitude_closed_forms(2, 2),
+    lambda: VX.test_shape_functions_are_whitney_forms("nedelec", 3),
+    lambda: VX.test_shape_functions_are_whitney_forms("raviart_thomas", 3),
+    lambda: VX.test_element_matrix_matches_exact_whitney_integrals("nedelec", 3),
+    lambda: VX.test_element_matrix_matches_exact_whitney_integrals("raviart_thomas", 2),
+    lambda: VX.test_curl_curl_annihilates_discrete_gradients(3),
+    lambda: VX.test_div_div_annihilates_discrete_curls_3d(),
+    lambda: VX.test_constant_field_patch_test("nedelec", 3),
+    lambda: VX.test_constant_field_patch_test("raviart_thomas", 3),
+    lambda: VX.test_l2_convergence_to_manufactured_field("nedelec", 2, (8, 16)),
 ]
 
 

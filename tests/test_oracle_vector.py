@@ -1,0 +1,258 @@
+"""Pins of the oracle's lowest-order Nedelec (curl-conforming, Sect. 3.10) and
+Raviart-Thomas (div-conforming, Sect. 3.9) elements on simplices, against
+what the mathematics fixes independently of the change-of-basis code:
+
+* the shape functions against the Whitney forms: lambda_i grad(lambda_j) -
+  lambda_j grad(lambda_i) for the edge (i, j), and (d-1)! (x - p_j) / ((x_i0 -
+  p_j) . N) for the facet opposite vertex j; their curls and divergences;
+* element matrices (with the global orientation signs) on random cells
+  against the same Whitney forms integrated exactly through barycentric
+  moments;
+* the de Rham complex on assembled meshes: the curl-curl matrix annihilates
+  discrete gradients, the div-div matrix annihilates discrete curls (3D) and
+  rotated gradients (2D) -- which holds only if every cell orients every
+  shared edge and facet alike;
+* patch tests (constant fields reproduced on jittered, shuffled meshes) and
+  first-order L2 convergence to a manufactured solution.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fe_inputs import rng, simplex_mesh
+
+EDGES = {2: [(0, 1), (0, 2), (1, 2)], 3: [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]}
+
+
+def bary(X):
+    """Barycentric gradients (rows) and volume of the simplex X ((d+1) x d)."""
+    d = X.shape[1]
+    T = np.hstack([np.ones((d + 1, 1)), X])
+    return np.linalg.inv(T)[1:].T, abs(np.linalg.det(T)) / math.factorial(d)
+
+
+def facet_normal(P):
+    """N of a facet from its vertices in the given order."""
+    if P.shape[1] == 2:
+        t = P[1] - P[0]
+        return np.array([t[1], -t[0]])
+    return np.cross(P[1] - P[0], P[2] - P[0])
+
+
+def whitney(family, X, x):
+    """Whitney forms of the simplex X at the point x (local orientation)."""
+    d = X.shape[1]
+    G, _ = bary(X)
+    lam = np.linalg.solve(np.hstack([np.ones((d + 1, 1)), X]).T, np.concatenate([[1.0], x]))
+    if family == "nedelec":
+        return np.array([lam[i] * G[j] - lam[j] * G[i] for i, j in EDGES[d]])
+    out = []
+    for j in range(d + 1):
+        P = X[[r for r in range(d + 1) if r != j]]
+        out.append(math.factorial(d - 1) * (x - X[j]) / ((P[0] - X[j]) @ facet_normal(P)))
+    return np.array(out)
+
+
+def crs(a, b):
+    """Cross product; the scalar a_x b_y - a_y b_x for plane vectors."""
+    if len(a) == 2:
+        return a[0] * b[1] - a[1] * b[0]
+    return np.cross(a, b)
+
+
+def random_simplex(dim, seed):
+    g = rng(seed)
+    while True:
+        X = np.vstack([np.zeros(dim), np.eye(dim)]) + 0.3 * g.standard_normal((dim + 1, dim))
+        if abs(np.linalg.det(X[1:] - X[0])) > 0.2:
+            return X
+
+
+REF = {d: np.vstack([np.zeros(d), np.eye(d)]) for d in (2, 3)}
+
+
+@pytest.mark.parametrize("family,dim", [("nedelec", 2), ("nedelec", 3), ("raviart_thomas", 2), ("raviart_thomas", 3)])
+def test_shape_functions_are_whitney_forms(family, dim):
+    g = rng(11)
+    Gr, _ = bary(REF[dim])
+    for _ in range(5):
+        xi = g.dirichlet(np.ones(dim + 1))[:dim]
+        phi, curl, div = O.vector_shape(family, dim, xi)
+        np.testing.assert_allclose(phi, whitney(family, REF[dim], xi), atol=1e-13)
+        if family == "nedelec":
+            for a, (i, j) in enumerate(EDGES[dim]):
+                c = 2 * crs(Gr[i], Gr[j])
+                np.testing.assert_allclose(curl[a], c, atol=1e-13)
+            np.testing.assert_allclose(div, 0.0, atol=1e-13)
+        else:
+            for j in range(dim + 1):
+                P = REF[dim][[r for r in range(dim + 1) if r != j]]
+                den = (P[0] - REF[dim][j]) @ facet_normal(P)
+                assert abs(div[j] - math.factorial(dim) / den) <= 1e-13
+
+
+def exact_element(family, X, gids, coef, kappa):
+    """Whitney-form element matrix with the global orientation signs, from
+    exact barycentric moments: int lam_i lam_j = |K| (1 + delta_ij) / ((d+1)(d+2))."""
+    d = X.shape[1]
+    G, vol = bary(X)
+    M = vol * (np.ones((d + 1, d + 1)) + np.eye(d + 1)) / ((d + 1) * (d + 2))
+    if family == "nedelec":
+        E = EDGES[d]
+        n = len(E)
+        A = np.zeros((n, n))
+        for a, (i, j) in enumerate(E):
+            for b, (k, l) in enumerate(E):
+                mass = (M[i, k] * G[j] @ G[l] - M[i, l] * G[j] @ G[k] - M[j, k] * G[i] @ G[l] + M[j, l] * G[i] @ G[k])
+                ca, cb = 2 * crs(G[i], G[j]), 2 * crs(G[k], G[l])
+                A[a, b] = coef * vol * np.dot(np.atleast_1d(ca), np.atleast_1d(cb)) + kappa * mass
+        s = np.array([1.0 if gids[i] < gids[j] else -1.0 for i, j in E])
+    else:
+        n = d + 1
+        A = np.zeros((n, n))
+        den = []
+        for j in range(n):
+            P = X[[r for r in range(n) if r != j]]
+            den.append((P[0] - X[j]) @ facet_normal(P))
+        f = math.factorial(d - 1)
+        for a in range(n):
+            for b in range(n):
+                # int (x - p_a) . (x - p_b) with x - p = sum_i lam_i (x_i - p)
+                mass = sum(M[i, k] * (X[i] - X[a]) @ (X[k] - X[b]) for i in range(n) for k in range(n))
+                A[a, b] = (coef * vol * (d * f) ** 2 + kappa * f * f * mass) / (den[a] * den[b])
+        s = []
+        for j in range(n):
+            ids = [gids[r] for r in range(n) if r != j]
+            inv = sum(1 for x in range(len(ids)) for y in range(x + 1, len(ids)) if ids[x] > ids[y])
+            s.append(-1.0 if inv % 2 else 1.0)
+        s = np.array(s)
+    return A * np.outer(s, s)
+
+
+@pytest.mark.parametrize("family,dim", [("nedelec", 2), ("nedelec", 3), ("raviart_thomas", 2), ("raviart_thomas", 3)])
+def test_element_matrix_matches_exact_whitney_integrals(family, dim):
+    for seed in (1, 2, 3):
+        X = random_simplex(dim, seed)
+        gids = rng(seed + 10).permutation(100)[: dim + 1].astype(np.int32)
+        A, f, ok = O.vector_element(family, dim, X, gids, coef=1.3, kappa=0.7)
+        assert ok
+        ref = exact_element(family, X, gids, 1.3, 0.7)
+        assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _edge_vertices(S):
+    """Global edge -> (lower, higher) global vertex id."""
+    ev = np.zeros((S.nent, 2), dtype=np.int64)
+    for K, row in enumerate(S.dof_of):
+        for a, (i, j) in enumerate(EDGES[S.dim]):
+            x, y = S.cells[K, i], S.cells[K, j]
+            ev[row[a]] = (min(x, y), max(x, y))
+    return ev
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_curl_curl_annihilates_discrete_gradients(dim):
+    v, c = simplex_mesh(dim, 3, jitter=0.2, shuffle=True)
+    S = O.VectorSystem("nedelec", dim, v, c, kappa=0.0, dirichlet=False)
+    ev = _edge_vertices(S)
+    Gd = np.zeros((S.nent, len(v)))
+    Gd[np.arange(S.nent), ev[:, 1]] = 1.0
+    Gd[np.arange(S.nent), ev[:, 0]] = -1.0
+    A = S.scipy()
+    assert S.nfree == S.nent
+    res = A @ Gd
+    assert np.abs(res).max() <= 1e-12 * np.abs(S.values).max()
+    # with the mass term the kernel is gone (positive definite)
+    S2 = O.VectorSystem("nedelec", dim, v, c, kappa=1.0, dirichlet=False)
+    assert np.linalg.eigvalsh(S2.scipy().toarray()).min() > 0
+
+
+def test_div_div_annihilates_discrete_curls_3d():
+    v, c = simplex_mesh(3, 2, jitter=0.2, shuffle=True)
+    N = O.VectorSystem("nedelec", 3, v, c, kappa=0.0, dirichlet=False)
+    R = O.VectorSystem("raviart_thomas", 3, v, c, kappa=0.0, dirichlet=False)
+    ev = _edge_vertices(N)
+    eid = {tuple(e): k for k, e in enumerate(ev)}
+    C = np.zeros((R.nent, N.nent))
+    for K, row in enumerate(R.dof_of):
+        for j in range(4):
+            g0, g1, g2 = sorted(int(R.cells[K, r]) for r in range(4) if r != j)
+            f = row[j]
+            C[f, :] = 0.0
+            C[f, eid[(g0, g1)]] = 1.0
+            C[f, eid[(g1, g2)]] = 1.0
+            C[f, eid[(g0, g2)]] = -1.0
+    A = R.scipy()
+    assert np.abs(A @ C).max() <= 1e-12 * np.abs(R.values).max()
+
+
+def test_div_div_annihilates_rotated_gradients_2d():
+    v, c = simplex_mesh(2, 4, jitter=0.2, shuffle=True)
+    R = O.VectorSystem("raviart_thomas", 2, v, c, kappa=0.0, dirichlet=False)
+    N = O.VectorSystem("nedelec", 2, v, c, kappa=0.0, dirichlet=False)
+    ev = _edge_vertices(N)  # 2D facets are the edges; number them the RT way
+    Gd = np.zeros((R.nent, len(v)))
+    for K, row in enumerate(R.dof_of):
+        for j in range(3):
+            a, b = sorted(int(R.cells[K, r]) for r in range(3) if r != j)
+            Gd[row[j]] = 0.0
+            Gd[row[j], b] = 1.0
+            Gd[row[j], a] = -1.0
+    assert np.abs(R.scipy() @ Gd).max() <= 1e-12 * np.abs(R.values).max()
+
+
+@pytest.mark.parametrize("family,dim", [("nedelec", 2), ("nedelec", 3), ("raviart_thomas", 2), ("raviart_thomas", 3)])
+def test_constant_field_patch_test(family, dim):
+    v, c = simplex_mesh(dim, 3, jitter=0.2, shuffle=True)
+    cvec = np.array([0.7, -1.3, 0.4][:dim])
+    kappa = 2.5
+    S = O.VectorSystem(family, dim, v, c, kappa=kappa, source_kind=1, source=list(kappa * cvec), dirichlet=False)
+    x = S.solve()
+    exact = np.zeros(S.nent)
+    for K, row in enumerate(S.dof_of):
+        for a in range(S.nd):
+            if family == "nedelec":
+                i, j = EDGES[dim][a]
+                lo, hi = sorted((int(c[K, i]), int(c[K, j])))
+                exact[row[a]] = cvec @ (v[hi] - v[lo])
+            else:
+                ids = sorted(int(c[K, r]) for r in range(dim + 1) if r != a)
+                exact[row[a]] = cvec @ facet_normal(v[ids]) / math.factorial(dim - 1)
+    assert np.abs(x - exact).max() <= 1e-10 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("family,dim,ns", [("nedelec", 2, (8, 16)), ("nedelec", 3, (4, 8)),
+                                           ("raviart_thomas", 2, (8, 16)), ("raviart_thomas", 3, (4, 8))])
+def test_l2_convergence_to_manufactured_field(family, dim, ns):
+    kappa = 1.0
+    lap = (2.0 if (family == "nedelec" and dim == 3) else 1.0) * math.pi ** 2
+    scale = 1.0
+    errs = []
+    for n in ns:
+        v, c = simplex_mesh(dim, n, jitter=0.15)
+        S = O.VectorSystem(family, dim, v, c, kappa=kappa, source_kind=2, source=[(lap + kappa) * scale] * dim)
+        errs.append(S.l2_error(S.solve(), scale, nq1=4))
+    rate = math.log(errs[0] / errs[1]) / math.log(ns[1] / ns[0])
+    assert 0.8 <= rate <= 1.4, (errs, rate)
+    # the error is a fraction of the field's norm (each component's square integrates to 2^-(number of sines))
+    sines = 2 if (family == "nedelec" and dim == 3) else 1
+    norm = math.sqrt(dim * 0.5 ** sines)
+    assert errs[1] < 0.25 * norm
+
+
+@pytest.mark.parametrize("family,dim", [("nedelec", 3), ("raviart_thomas", 3)])
+def test_boundary_dofs_and_definiteness(family, dim):
+    n = 2
+    v, c = simplex_mesh(dim, n)
+    S = O.VectorSystem(family, dim, v, c, kappa=1.0)
+    Sf = O.VectorSystem(family, dim, v, c, kappa=1.0, dirichlet=False)
+    # Kuhn subdivision of the n^3 brick: boundary edges 3 per boundary square x 6 n^2 squares
+    # + ... counted directly: a DOF is fixed iff all of its entity's vertices are on the boundary face set
+    if family == "raviart_thomas":
+        assert S.nfixed == 2 * 6 * n * n  # two triangles per boundary square
+    assert S.nfree + S.nfixed == Sf.nfree
+    A = S.scipy().toarray()
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    assert np.linalg.eigvalsh(A).min() > 0
