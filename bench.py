@@ -13,6 +13,7 @@ Prints one JSON line.  Run ``python bench.py`` (1 GPU, 10 timed steps).
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -545,6 +546,14 @@ SIMPLEX_WORKLOAD = dict(dim=3, n=64, k=2, rtol=1e-10,
                              "boundary; FP64 assembly + Jacobi-PCG (CSR SpMV) to rtol 1e-10")
 
 
+NEDELEC_WORKLOAD = dict(dim=3, n=64, kappa=1.0, rtol=1e-8,
+                        text="lowest-order Nedelec edge elements on tetrahedra: the Kuhn subdivision of the 64^3 "
+                             "unit-cube brick (1,572,864 tetrahedra as general connectivity, jittered +-0.2h, seed "
+                             "17080), curl(k curl u) + u = f with lognormal k per cell (seed 17081), f = (2 pi^2 + 1) "
+                             "(sin pi y sin pi z, sin pi z sin pi x, sin pi x sin pi y), zero tangential trace; FP64 "
+                             "assembly + Jacobi-PCG (CSR SpMV) to rtol 1e-8")
+
+
 def simplex_element_bytes(ncells, ntri, nloc, nverts, dim):
     """Algorithmic bytes of the element kernel: the element matrices' upper
     triangles and the loads written, connectivity, coefficients and vertex
@@ -583,25 +592,32 @@ def simplex_cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=12, cg_its=100)
             "step_s_scaled": step}
 
 
-def simplex_form(args, F, torch, steps=3, warmup=1):
-    """The simplicial workload: a step is the assembly (element kernel +
+def simplex_form(args, F, torch, steps=3, warmup=1, family=None):
+    """The simplicial workload (Lagrange P2, or with family "nedelec" the
+    lowest-order edge elements): a step is the assembly (element kernel +
     gathers through the stored map) + Jacobi-PCG on the CSR, the numbering,
     pattern and gather map built once before timing (Sect. 11.1)."""
     from fe_inputs import lognormal_coefficients, simplex_mesh
-    wl = SIMPLEX_WORKLOAD
-    dim, n, k = wl["dim"], wl["n"], wl["k"]
+    wl = SIMPLEX_WORKLOAD if family is None else NEDELEC_WORKLOAD
+    dim, n = wl["dim"], wl["n"]
     v, c = simplex_mesh(dim, n, jitter=0.2)
     coef = lognormal_coefficients(c.shape[0])
-    coeff = F.make_coeff("poisson", "fp64", source_kind=1, source=(1.0,), dim=dim)
     t0 = time.perf_counter()
-    G = F.Simplex(dim, v, c, k, coeff, cell_coeff=coef)
+    if family is None:
+        coeff = F.make_coeff("poisson", "fp64", source_kind=1, source=(1.0,), dim=dim)
+        G = F.Simplex(dim, v, c, wl["k"], coeff, cell_coeff=coef)
+    else:
+        src = (2 * math.pi ** 2 + wl["kappa"],) * 3
+        coeff = F.make_coeff("poisson", "fp64", source_kind=2, source=src, dim=dim)
+        G = F.Simplex(dim, v, c, 0, coeff, cell_coeff=coef, family=family, kappa=wl["kappa"])
     t_setup = time.perf_counter() - t0
     ncells = c.shape[0]
     ws = torch.empty(F.pcg_query(G.n_rows), dtype=torch.uint8, device="cuda")
     x = torch.zeros(G.n_rows, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    print(f"[bench] simplex form: cells={ncells} rows={G.n_rows} nnz={G.nnz} contributions={G.n_contrib} "
+    print(f"[bench] simplex form ({family or 'lagrange'}): cells={ncells} rows={G.n_rows} nnz={G.nnz} "
+          f"contributions={G.n_contrib} "
           f"set-up {t_setup:.1f} s", file=sys.stderr, flush=True)
 
     def step():
@@ -657,8 +673,34 @@ def simplex_form(args, F, torch, steps=3, warmup=1):
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle's simplex system on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = simplex_cpu_baseline(wl, statistics.mean(iters), ncells, out["nnz"])
+        if family is None:
+            out["cpu_baseline"] = simplex_cpu_baseline(wl, statistics.mean(iters), ncells, out["nnz"])
+        else:
+            out["cpu_baseline"] = vector_cpu_baseline(wl, family, statistics.mean(iters), ncells, out["nnz"])
     return out
+
+
+def vector_cpu_baseline(wl, family, gpu_iters, ncells_full, nnz_full, n=16, cg_its=100):
+    """The oracle's vector-element system on the Kuhn mesh of an n^3 brick of
+    the same recipe (numeric assembly single-threaded) and its all-cores CG,
+    scaled to the full workload like the other baselines."""
+    import oracle as O
+    from fe_inputs import lognormal_coefficients, simplex_mesh
+    v, c = simplex_mesh(wl["dim"], n, jitter=0.2)
+    coef = lognormal_coefficients(c.shape[0])
+    src = (2 * math.pi ** 2 + wl["kappa"],) * 3
+    S = O.VectorSystem(family, wl["dim"], v, c, coef=coef, kappa=wl["kappa"], source_kind=2, source=src)
+    t_asm = S.t_assemble
+    t0 = time.perf_counter()
+    res = O.omp_pcg(S.rowptr, S.colind, S.values, S.rhs, 0.0, cg_its)
+    t_it = (time.perf_counter() - t0) / max(res["iters"], 1)
+    step = t_asm / c.shape[0] * ncells_full + t_it * (nnz_full / S.nnz) * gpu_iters
+    return {"value": ncells_full / step, "unit": "elements/s", "cores": O.omp_threads(), "kind": "oracle",
+            "sample": f"oracle (C, FP64) {family} system on the Kuhn mesh of {n}^3 ({c.shape[0]} tetrahedra, "
+                      f"nnz {S.nnz}): numeric assembly single-threaded ({t_asm:.2f} s), {res['iters']} CG "
+                      f"iterations on all cores ({t_it * 1e3:.2f} ms each); the full step scaled as cells x "
+                      f"assembly time per cell + {gpu_iters:.0f} iterations x per-iteration time x nnz ratio",
+            "step_s_scaled": step}
 
 
 STOKES_WORKLOAD = dict(dim=3, n=24, k=1, mu=1.0, rtol=1e-8,
@@ -1000,7 +1042,7 @@ def main():
                     help="thin the stream to requests of at most this many unknowns (default: every request)")
     ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg", "stokes", "simplex"],
+    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg", "stokes", "simplex", "nedelec"],
                     help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -1042,6 +1084,10 @@ def main():
     if args.form == "simplex":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "simplex", **simplex_form(args, F, torch)}), flush=True)
+        return
+    if args.form == "nedelec":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "nedelec", **simplex_form(args, F, torch, family="nedelec")}), flush=True)
         return
     if args.form == "stokes":
         torch.cuda.set_device(0)
@@ -1197,6 +1243,8 @@ def main():
         out["forms"]["stokes"] = stokes_form(args, F, torch)
         print("[bench] simplex form", file=sys.stderr, flush=True)
         out["forms"]["simplex"] = simplex_form(args, F, torch)
+        print("[bench] Nedelec form", file=sys.stderr, flush=True)
+        out["forms"]["nedelec"] = simplex_form(args, F, torch, family="nedelec")
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, statistics.mean(iters), ncells, out["config"]["nnz"])

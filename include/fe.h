@@ -408,6 +408,30 @@ typedef struct {
 fe_status fe_simplex_create(const fe_simplex_desc *desc, int32_t order, const fe_coeff *coeff, fe_simplex *out);
 fe_status fe_simplex_destroy(fe_simplex s);
 
+/* Lowest-order vector elements on the same meshes (Sect. 3.9, 3.10):
+ * FE_NEDELEC, one tangential moment per edge (the line integral along the
+ * edge), mapped by the covariant Piola map J^-T; FE_RAVIART_THOMAS, one flux
+ * moment per facet, mapped by the contravariant Piola map J / det J.  Shape
+ * functions by the change of basis from the spaces' pre-bases.  Global
+ * orientation: an edge runs from its lower to its higher vertex id, a facet's
+ * normal is taken over its vertices in ascending id.  The form is
+ *   int c curl u . curl v + kappa u . v   (Nedelec)
+ *   int c div u div v + kappa u . v       (Raviart-Thomas)
+ * with c the per-cell coefficient (cell_coeff, NULL = 1).  coeff: FP64;
+ * source_kind CONST (f = source) or SINPROD (f_c = source[c] m_c(x), m the
+ * family's field: Nedelec 3D (sin pi y sin pi z, sin pi z sin pi x,
+ * sin pi x sin pi y), 2D (sin pi y, sin pi x); Raviart-Thomas (sin pi x_r)_r);
+ * dirichlet_faces != 0 fixes the DOFs on the boundary to zero (tangential or
+ * normal trace), FE_DIRICHLET_ZERO only.  A DOF entity (edge, facet) is
+ * numbered by first appearance over (cell, local DOF); local DOFs are the
+ * edges (0,1),(0,2),(1,2) [2D] or (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) [3D],
+ * or the facets by their opposite vertex.  The other fe_simplex_* calls
+ * apply (one DOF per entity: n_nodes counts the entities).  FE_EINVAL for
+ * kappa < 0 or an unknown family; mesh errors as fe_simplex_create. */
+enum { FE_NEDELEC = 1, FE_RAVIART_THOMAS = 2 };
+fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, double kappa, const fe_coeff *coeff,
+                                   fe_simplex *out);
+
 /* Free DOFs (rows), nonzeros, global nodes and element contributions to the
  * nonzeros (the gather map's length).  Host only. */
 fe_status fe_simplex_query(fe_simplex s, int64_t *n_rows, int64_t *nnz, int64_t *n_nodes, int64_t *n_contrib);

@@ -259,6 +259,214 @@ __global__ __launch_bounds__(256) void sx_element_kernel(SxArgs sa, const double
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Lowest-order vector elements on simplices (Sect. 3.9, 3.10): family 1
+// Nedelec (a DOF per edge, covariant map J^-T), family 2 Raviart-Thomas (a
+// DOF per facet, contravariant map J / det J).  The form is
+//   int coef curl u . curl v + kappa u . v   (Nedelec)
+//   int coef div u div v + kappa u . v       (Raviart-Thomas)
+// and for an affine map each term is a contraction of a per-cell symmetric
+// tensor with reference products: curl curl (3D) coef/|det J| J^T J, (2D)
+// coef/|det J|; div div coef/|det J|; mass kappa |det J| J^-1 J^-T
+// (Nedelec) or kappa/|det J| J^T J (Raviart-Thomas).  Entries and loads are
+// multiplied by the orientation signs of the cell's DOFs (edges run from the
+// lower to the higher global vertex id; a facet's normal is taken over its
+// vertices in ascending global id).
+template <int DIM, int FAM>
+struct SxvShape {
+    static constexpr int ND = FAM == 1 ? (DIM == 3 ? 6 : 3) : DIM + 1;
+    static constexpr int NTRI = ND * (ND + 1) / 2;
+    static constexpr int NPS = (FAM == 1 && DIM == 3) ? 6 : 1;
+    static constexpr int NPM = DIM * (DIM + 1) / 2;
+    static constexpr int NP = NPS + NPM;
+    static constexpr int NQ1 = 1 + (DIM + 1) / 2;
+    static constexpr int NQ = DIM == 3 ? NQ1 * NQ1 * NQ1 : NQ1 * NQ1;
+    static constexpr int CPB = 64;
+};
+
+template <int DIM, int FAM>
+__global__ __launch_bounds__(256) void sx_vector_kernel(SxArgs sa, double kappa, const double *__restrict__ vxyz,
+                                                        const int32_t *__restrict__ cells,
+                                                        const double *__restrict__ coef, const double *__restrict__ tab,
+                                                        const int32_t *__restrict__ tri,
+                                                        const double *__restrict__ phq, const double *__restrict__ qxw,
+                                                        double *__restrict__ E, double *__restrict__ F)
+{
+    using S = SxvShape<DIM, FAM>;
+    constexpr int NV = DIM + 1;
+    __shared__ double sTab[S::NP * S::NTRI];
+    __shared__ int32_t sTri[S::NTRI];
+    __shared__ double sC[S::CPB][S::NP];
+    __shared__ double sSg[S::CPB][S::ND];
+    __shared__ double sX[S::CPB][NV * DIM];
+    __shared__ double sM[S::CPB][DIM * DIM];  // pull-back of the load: J^-1 or J^T / det J
+    __shared__ double sDet[S::CPB];
+    __shared__ double sG[S::CPB][S::NQ][DIM];
+    const int tid = threadIdx.x;
+    const int64_t K0 = xcd_block(blockIdx.x, gridDim.x) * S::CPB;
+    const int ncl = sa.ncells - K0 < S::CPB ? int(sa.ncells - K0) : S::CPB;
+    for (int t = tid; t < S::NP * S::NTRI; t += blockDim.x) sTab[t] = tab[t];
+    for (int t = tid; t < S::NTRI; t += blockDim.x) sTri[t] = tri[t];
+    for (int c = tid; c < ncl; c += blockDim.x) {
+        const int64_t Kc = K0 + c;
+        int32_t g[NV];
+        double X[NV][DIM];
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            g[j] = cells[Kc * NV + j];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) X[j][r] = vxyz[int64_t(g[j]) * DIM + r];
+        }
+        double J[DIM][DIM], Ji[DIM][DIM], det;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) J[r][s] = X[s + 1][r] - X[0][r];
+        if constexpr (DIM == 2) {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double id = 1.0 / det;
+            Ji[0][0] = J[1][1] * id;
+            Ji[0][1] = -J[0][1] * id;
+            Ji[1][0] = -J[1][0] * id;
+            Ji[1][1] = J[0][0] * id;
+        } else {
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+            const double id = 1.0 / det;
+            Ji[0][0] = c00 * id;
+            Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+            Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+            Ji[1][0] = c01 * id;
+            Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+            Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+            Ji[2][0] = c02 * id;
+            Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+            Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        }
+        const double ad = fabs(det), k = coef ? coef[Kc] : 1.0;
+        // stiffness coefficients
+        if constexpr (FAM == 1 && DIM == 3) {
+            int p = 0;
+#pragma unroll
+            for (int r = 0; r < DIM; r++)
+#pragma unroll
+                for (int s = r; s < DIM; s++) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int l = 0; l < DIM; l++) v += J[l][r] * J[l][s];
+                    sC[c][p++] = k / ad * v;
+                }
+        } else {
+            sC[c][0] = k / ad;
+        }
+        // mass coefficients
+        int p = S::NPS;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = r; s < DIM; s++) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < DIM; l++) v += FAM == 1 ? Ji[r][l] * Ji[s][l] : J[l][r] * J[l][s];
+                sC[c][p++] = FAM == 1 ? kappa * ad * v : kappa / ad * v;
+            }
+        // orientation signs
+        if constexpr (FAM == 1) {
+#pragma unroll
+            for (int a = 0; a < S::ND; a++) {
+                const int i = DIM == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
+                const int j = DIM == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
+                sSg[c][a] = g[i] < g[j] ? 1.0 : -1.0;
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < S::ND; a++) {
+                int32_t f[3];
+                int m = 0;
+#pragma unroll
+                for (int r = 0; r < NV; r++)
+                    if (r != a) f[m++] = g[r];
+                int inv = f[0] > f[1];
+                if (DIM == 3) inv += (f[0] > f[2]) + (f[1] > f[2]);
+                sSg[c][a] = (inv & 1) ? -1.0 : 1.0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) sM[c][r * DIM + s] = FAM == 1 ? Ji[r][s] : J[s][r] / det;
+#pragma unroll
+        for (int j = 0; j < NV; j++)
+#pragma unroll
+            for (int r = 0; r < DIM; r++) sX[c][j * DIM + r] = X[j][r];
+        sDet[c] = ad;
+    }
+    __syncthreads();
+    // pulled-back load weights at the rule's points: w_q |det J| M f(x_q)
+    if (sa.source_kind != FE_SOURCE_NONE)
+        for (int e = tid; e < ncl * S::NQ; e += blockDim.x) {
+            const int c = e / S::NQ, q = e - c * S::NQ;
+            double x[DIM], f[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) {
+                x[r] = sX[c][r];
+#pragma unroll
+                for (int t = 0; t < DIM; t++) x[r] += (sX[c][(t + 1) * DIM + r] - sX[c][r]) * qxw[q * (DIM + 1) + t];
+            }
+            if (sa.source_kind == FE_SOURCE_SINPROD) {
+                double sn[DIM];
+#pragma unroll
+                for (int r = 0; r < DIM; r++) sn[r] = sin(M_PI * x[r]);
+                double m[DIM];
+                if constexpr (FAM == 2) {
+#pragma unroll
+                    for (int r = 0; r < DIM; r++) m[r] = sn[r];
+                } else if constexpr (DIM == 2) {
+                    m[0] = sn[1];
+                    m[1] = sn[0];
+                } else {
+                    m[0] = sn[1] * sn[2];
+                    m[1] = sn[2] * sn[0];
+                    m[2] = sn[0] * sn[1];
+                }
+#pragma unroll
+                for (int r = 0; r < DIM; r++) f[r] = sa.source[r] * m[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < DIM; r++) f[r] = sa.source[r];
+            }
+            const double w = qxw[q * (DIM + 1) + DIM] * sDet[c];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) {
+                double v = 0.0;
+#pragma unroll
+                for (int t = 0; t < DIM; t++) v += sM[c][r * DIM + t] * f[t];
+                sG[c][q][r] = w * v;
+            }
+        }
+    __syncthreads();
+    for (int e = tid; e < ncl * S::NTRI; e += blockDim.x) {
+        const int c = e / S::NTRI, t = e - c * S::NTRI;
+        const int a = sTri[t] >> 16, b = sTri[t] & 0xffff;
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < S::NP; p++) v = __fma_rn(sC[c][p], sTab[p * S::NTRI + t], v);
+        E[(K0 + c) * S::NTRI + t] = sSg[c][a] * sSg[c][b] * v;
+    }
+    for (int e = tid; e < ncl * S::ND; e += blockDim.x) {
+        const int c = e / S::ND, a = e - c * S::ND;
+        double f = 0.0;
+        if (sa.source_kind != FE_SOURCE_NONE)
+            for (int q = 0; q < S::NQ; q++)
+#pragma unroll
+                for (int r = 0; r < DIM; r++) f = __fma_rn(sG[c][q][r], phq[(q * S::ND + a) * DIM + r], f);
+        F[(K0 + c) * S::ND + a] = sSg[c][a] * f;
+    }
+}
+
 // values[j] = sum of E over the contributions of entry j, in list order.
 __global__ __launch_bounds__(256) void sx_gather_kernel(int64_t nnz, const int64_t *__restrict__ gptr,
                                                         const uint32_t *__restrict__ gsrc,
@@ -296,6 +504,8 @@ using namespace fe;
 
 struct fe_simplex_s {
     int dim = 0, k = 0, nn = 0, ncomp = 0, nloc = 0, ntri = 0;
+    int family = 0;  // 0 Lagrange P_k, 1 Nedelec, 2 Raviart-Thomas
+    double kappa = 0.0;
     bool fix_boundary = false;
     int64_t nverts = 0, ncells = 0, nnodes = 0, nfree_nodes = 0, n_rows = 0, nnz = 0, ncontrib = 0;
     SxArgs args{};
@@ -520,123 +730,15 @@ struct Cand {
     int64_t K;
 };
 
-fe_status sx_setup(fe_simplex S, const int32_t *cells, const double *vxyz)
+// The common tail of the set-up, given every (cell, local DOF)'s global
+// entity id (pre, ids by first appearance), the entity count and the
+// boundary flags: free / fixed ranks, the cell-to-DOF map, each free
+// entity's occurrences, the pattern and the gather map.
+fe_status sx_finish(fe_simplex S, std::vector<int64_t> &pre, int64_t nnodes, const std::vector<char> &bnd)
 {
-    const int dim = S->dim, k = S->k, nn = S->nn, nv = dim + 1, nc = S->ncomp;
+    const int nn = S->nn, nc = S->ncomp;
     const int64_t ncells = S->ncells;
-    std::vector<int> sl;
-    sx_lattice(dim, k, sl);
-    // barycentric weights of every local node
-    std::vector<std::array<int, 4>> beta(nn);
-    for (int a = 0; a < nn; a++) {
-        int sum = 0;
-        for (int r = 0; r < dim; r++) {
-            beta[a][r + 1] = sl[3 * a + r];
-            sum += sl[3 * a + r];
-        }
-        beta[a][0] = k - sum;
-        for (int r = dim + 1; r < 4; r++) beta[a][r] = 0;
-    }
-    // edges (3D: 6 per cell) and facets (2D: the 3 edges; 3D: the 4 faces)
-    std::vector<Facet> frec(static_cast<size_t>(ncells) * nv);
-    for (int64_t K = 0; K < ncells; K++)
-        for (int j = 0; j < nv; j++) {
-            Facet &f = frec[K * nv + j];
-            int m = 0;
-            for (int i = 0; i < nv; i++)
-                if (i != j) f.v[m++] = cells[K * nv + i];
-            std::sort(f.v.begin(), f.v.begin() + m);
-            if (m == 2) f.v[2] = -1;
-            f.cell = K;
-            f.j = j;
-        }
-    std::vector<std::array<int32_t, 3>> fkeys, ekeys;
-    std::vector<int32_t> fcount, ecount;
-    unique_keys(frec, fkeys, fcount);
-    for (int32_t c : fcount)
-        if (c > 2) return set_error(FE_EMESH, "a facet is shared by more than two cells");
-    if (dim == 3) {
-        std::vector<Facet> erec(static_cast<size_t>(ncells) * 6);
-        for (int64_t K = 0; K < ncells; K++) {
-            int e = 0;
-            for (int i = 0; i < 4; i++)
-                for (int j = i + 1; j < 4; j++, e++) {
-                    Facet &f = erec[K * 6 + e];
-                    const int32_t x = cells[K * 4 + i], y = cells[K * 4 + j];
-                    f.v = {std::min(x, y), std::max(x, y), -1};
-                    f.cell = K;
-                    f.j = e;
-                }
-        }
-        unique_keys(erec, ekeys, ecount);
-    }
-    const std::vector<std::array<int32_t, 3>> &edges = dim == 3 ? ekeys : fkeys;
-    // sub-simplex slot counts: nodes strictly inside an edge, face, tetrahedron
-    const int64_t ne = int64_t(edges.size()), nf = dim == 3 ? int64_t(fkeys.size()) : 0;
-    const int64_t se = k - 1, sf = int64_t(std::max(k - 2, 0)) * std::max(k - 2, 0),
-                  sc = dim == 3 ? int64_t(std::max(k - 3, 0)) * std::max(k - 3, 0) * std::max(k - 3, 0) : sf;
-    const int64_t base_e = S->nverts, base_f = base_e + ne * se, base_c = base_f + nf * sf;
-    const int64_t nprelim = base_c + ncells * sc;
-    // preliminary node names of every (cell, local node)
-    std::vector<int64_t> pre(static_cast<size_t>(ncells) * nn);
-    parallel_chunks(ncells, [&](int64_t lo, int64_t hi) {
-        for (int64_t K = lo; K < hi; K++)
-            for (int a = 0; a < nn; a++) {
-                int32_t vv[4];
-                int ww[4], m = 0;
-                for (int j = 0; j < nv; j++)
-                    if (beta[a][j] > 0) {
-                        vv[m] = cells[K * nv + j];
-                        ww[m] = beta[a][j];
-                        m++;
-                    }
-                // ascending vertex ids
-                for (int i = 1; i < m; i++)
-                    for (int j = i; j > 0 && vv[j - 1] > vv[j]; j--) {
-                        std::swap(vv[j - 1], vv[j]);
-                        std::swap(ww[j - 1], ww[j]);
-                    }
-                int64_t p;
-                if (m == 1) {
-                    p = vv[0];
-                } else if (m == 2) {
-                    p = base_e + key_index(edges, {vv[0], vv[1], -1}) * se + (ww[1] - 1);
-                } else if (m == 3 && dim == 3) {
-                    p = base_f + key_index(fkeys, {vv[0], vv[1], vv[2]}) * sf + (ww[0] - 1) * (k - 2) + (ww[1] - 1);
-                } else if (m == 3) {  // interior of a triangle
-                    p = base_c + K * sc + (ww[0] - 1) * (k - 2) + (ww[1] - 1);
-                } else {  // interior of a tetrahedron
-                    p = base_c + K * sc + ((ww[0] - 1) * (k - 3) + (ww[1] - 1)) * (k - 3) + (ww[2] - 1);
-                }
-                pre[K * nn + a] = p;
-            }
-    });
-    // global ids by first appearance
-    std::vector<int64_t> gid(static_cast<size_t>(nprelim), -1);
-    int64_t nnodes = 0;
-    for (int64_t t = 0; t < ncells * nn; t++) {
-        int64_t &g = gid[pre[t]];
-        if (g < 0) g = nnodes++;
-        pre[t] = g;
-    }
-    std::vector<int64_t>().swap(gid);
     S->nnodes = nnodes;
-    // boundary nodes: the nodes of facets of one cell
-    std::vector<char> bnd(static_cast<size_t>(nnodes), 0);
-    if (S->fix_boundary) {
-        for (size_t t = 0; t < frec.size();) {
-            size_t u = t + 1;
-            while (u < frec.size() && frec[u].v == frec[t].v) u++;
-            if (u - t == 1) {
-                const int64_t K = frec[t].cell;
-                const int j = frec[t].j;
-                for (int a = 0; a < nn; a++)
-                    if (beta[a][j] == 0) bnd[pre[K * nn + a]] = 1;
-            }
-            t = u;
-        }
-    }
-    std::vector<Facet>().swap(frec);
     // free / fixed ranks
     std::vector<int64_t> code(static_cast<size_t>(nnodes));
     int64_t nfree = 0, nfixed = 0;
@@ -756,6 +858,393 @@ fe_status sx_setup(fe_simplex S, const int32_t *cells, const double *vxyz)
     return st;
 }
 
+fe_status sx_setup(fe_simplex S, const int32_t *cells, const double *vxyz)
+{
+    const int dim = S->dim, k = S->k, nn = S->nn, nv = dim + 1, nc = S->ncomp;
+    const int64_t ncells = S->ncells;
+    std::vector<int> sl;
+    sx_lattice(dim, k, sl);
+    // barycentric weights of every local node
+    std::vector<std::array<int, 4>> beta(nn);
+    for (int a = 0; a < nn; a++) {
+        int sum = 0;
+        for (int r = 0; r < dim; r++) {
+            beta[a][r + 1] = sl[3 * a + r];
+            sum += sl[3 * a + r];
+        }
+        beta[a][0] = k - sum;
+        for (int r = dim + 1; r < 4; r++) beta[a][r] = 0;
+    }
+    // edges (3D: 6 per cell) and facets (2D: the 3 edges; 3D: the 4 faces)
+    std::vector<Facet> frec(static_cast<size_t>(ncells) * nv);
+    for (int64_t K = 0; K < ncells; K++)
+        for (int j = 0; j < nv; j++) {
+            Facet &f = frec[K * nv + j];
+            int m = 0;
+            for (int i = 0; i < nv; i++)
+                if (i != j) f.v[m++] = cells[K * nv + i];
+            std::sort(f.v.begin(), f.v.begin() + m);
+            if (m == 2) f.v[2] = -1;
+            f.cell = K;
+            f.j = j;
+        }
+    std::vector<std::array<int32_t, 3>> fkeys, ekeys;
+    std::vector<int32_t> fcount, ecount;
+    unique_keys(frec, fkeys, fcount);
+    for (int32_t c : fcount)
+        if (c > 2) return set_error(FE_EMESH, "a facet is shared by more than two cells");
+    if (dim == 3) {
+        std::vector<Facet> erec(static_cast<size_t>(ncells) * 6);
+        for (int64_t K = 0; K < ncells; K++) {
+            int e = 0;
+            for (int i = 0; i < 4; i++)
+                for (int j = i + 1; j < 4; j++, e++) {
+                    Facet &f = erec[K * 6 + e];
+                    const int32_t x = cells[K * 4 + i], y = cells[K * 4 + j];
+                    f.v = {std::min(x, y), std::max(x, y), -1};
+                    f.cell = K;
+                    f.j = e;
+                }
+        }
+        unique_keys(erec, ekeys, ecount);
+    }
+    const std::vector<std::array<int32_t, 3>> &edges = dim == 3 ? ekeys : fkeys;
+    // sub-simplex slot counts: nodes strictly inside an edge, face, tetrahedron
+    const int64_t ne = int64_t(edges.size()), nf = dim == 3 ? int64_t(fkeys.size()) : 0;
+    const int64_t se = k - 1, sf = int64_t(std::max(k - 2, 0)) * std::max(k - 2, 0),
+                  sc = dim == 3 ? int64_t(std::max(k - 3, 0)) * std::max(k - 3, 0) * std::max(k - 3, 0) : sf;
+    const int64_t base_e = S->nverts, base_f = base_e + ne * se, base_c = base_f + nf * sf;
+    const int64_t nprelim = base_c + ncells * sc;
+    // preliminary node names of every (cell, local node)
+    std::vector<int64_t> pre(static_cast<size_t>(ncells) * nn);
+    parallel_chunks(ncells, [&](int64_t lo, int64_t hi) {
+        for (int64_t K = lo; K < hi; K++)
+            for (int a = 0; a < nn; a++) {
+                int32_t vv[4];
+                int ww[4], m = 0;
+                for (int j = 0; j < nv; j++)
+                    if (beta[a][j] > 0) {
+                        vv[m] = cells[K * nv + j];
+                        ww[m] = beta[a][j];
+                        m++;
+                    }
+                // ascending vertex ids
+                for (int i = 1; i < m; i++)
+                    for (int j = i; j > 0 && vv[j - 1] > vv[j]; j--) {
+                        std::swap(vv[j - 1], vv[j]);
+                        std::swap(ww[j - 1], ww[j]);
+                    }
+                int64_t p;
+                if (m == 1) {
+                    p = vv[0];
+                } else if (m == 2) {
+                    p = base_e + key_index(edges, {vv[0], vv[1], -1}) * se + (ww[1] - 1);
+                } else if (m == 3 && dim == 3) {
+                    p = base_f + key_index(fkeys, {vv[0], vv[1], vv[2]}) * sf + (ww[0] - 1) * (k - 2) + (ww[1] - 1);
+                } else if (m == 3) {  // interior of a triangle
+                    p = base_c + K * sc + (ww[0] - 1) * (k - 2) + (ww[1] - 1);
+                } else {  // interior of a tetrahedron
+                    p = base_c + K * sc + ((ww[0] - 1) * (k - 3) + (ww[1] - 1)) * (k - 3) + (ww[2] - 1);
+                }
+                pre[K * nn + a] = p;
+            }
+    });
+    // global ids by first appearance
+    std::vector<int64_t> gid(static_cast<size_t>(nprelim), -1);
+    int64_t nnodes = 0;
+    for (int64_t t = 0; t < ncells * nn; t++) {
+        int64_t &g = gid[pre[t]];
+        if (g < 0) g = nnodes++;
+        pre[t] = g;
+    }
+    std::vector<int64_t>().swap(gid);
+    S->nnodes = nnodes;
+    // boundary nodes: the nodes of facets of one cell
+    std::vector<char> bnd(static_cast<size_t>(nnodes), 0);
+    if (S->fix_boundary) {
+        for (size_t t = 0; t < frec.size();) {
+            size_t u = t + 1;
+            while (u < frec.size() && frec[u].v == frec[t].v) u++;
+            if (u - t == 1) {
+                const int64_t K = frec[t].cell;
+                const int j = frec[t].j;
+                for (int a = 0; a < nn; a++)
+                    if (beta[a][j] == 0) bnd[pre[K * nn + a]] = 1;
+            }
+            t = u;
+        }
+    }
+    std::vector<Facet>().swap(frec);
+    return sx_finish(S, pre, nnodes, bnd);
+}
+
+// Entities of the vector families: edges (family 1) or facets (family 2)
+// named by their sorted vertex keys, ids by first appearance over (cell,
+// local DOF); boundary entities lie on a facet of one cell.
+fe_status sxv_setup(fe_simplex S, const int32_t *cells)
+{
+    const int dim = S->dim, nv = dim + 1, nd = S->nn;
+    const int64_t ncells = S->ncells;
+    std::vector<Facet> erec(static_cast<size_t>(ncells) * nd), frec(static_cast<size_t>(ncells) * nv);
+    for (int64_t K = 0; K < ncells; K++) {
+        for (int a = 0; a < nd; a++) {
+            Facet &f = erec[K * nd + a];
+            int m = 0;
+            if (S->family == 1) {
+                const int i = dim == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
+                const int j = dim == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
+                f.v[m++] = cells[K * nv + i];
+                f.v[m++] = cells[K * nv + j];
+            } else {
+                for (int r = 0; r < nv; r++)
+                    if (r != a) f.v[m++] = cells[K * nv + r];
+            }
+            std::sort(f.v.begin(), f.v.begin() + m);
+            for (int r = m; r < 3; r++) f.v[r] = -1;
+            f.cell = K;
+            f.j = a;
+        }
+        for (int j = 0; j < nv; j++) {
+            Facet &f = frec[K * nv + j];
+            int m = 0;
+            for (int r = 0; r < nv; r++)
+                if (r != j) f.v[m++] = cells[K * nv + r];
+            std::sort(f.v.begin(), f.v.begin() + m);
+            for (int r = m; r < 3; r++) f.v[r] = -1;
+            f.cell = K;
+            f.j = j;
+        }
+    }
+    std::vector<std::array<int32_t, 3>> keys, fkeys;
+    std::vector<int32_t> count, fcount;
+    unique_keys(frec, fkeys, fcount);
+    for (int32_t c : fcount)
+        if (c > 2) return set_error(FE_EMESH, "a facet is shared by more than two cells");
+    unique_keys(erec, keys, count);
+    // group id of every (cell, local DOF), then ids by first appearance
+    std::vector<int64_t> pre(static_cast<size_t>(ncells) * nd), gid(keys.size(), -1);
+    {
+        int64_t grp = -1;
+        for (size_t t = 0; t < erec.size(); t++) {
+            if (t == 0 || erec[t].v != erec[t - 1].v) grp++;
+            pre[erec[t].cell * nd + erec[t].j] = grp;
+        }
+    }
+    int64_t nent = 0;
+    for (int64_t t = 0; t < ncells * nd; t++) {
+        int64_t &g = gid[pre[t]];
+        if (g < 0) g = nent++;
+        pre[t] = g;
+    }
+    std::vector<char> bnd(static_cast<size_t>(nent), 0);
+    if (S->fix_boundary)
+        for (size_t t = 0; t < frec.size();) {
+            size_t u = t + 1;
+            while (u < frec.size() && frec[u].v == frec[t].v) u++;
+            if (u - t == 1) {
+                const int64_t K = frec[t].cell;
+                const int j = frec[t].j;
+                for (int a = 0; a < nd; a++) {
+                    bool on;
+                    if (S->family == 2) {
+                        on = a == j;
+                    } else {
+                        const int i1 = dim == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
+                        const int j1 = dim == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
+                        on = i1 != j && j1 != j;
+                    }
+                    if (on) bnd[pre[K * nd + a]] = 1;
+                }
+            }
+            t = u;
+        }
+    return sx_finish(S, pre, nent, bnd);
+}
+
+// Pre-basis of the vector family at x: value v and Jacobian dv[c dim + r].
+// Constants e_b first; then Nedelec rotations (2D (-y, x); 3D e_m x x) or
+// the Raviart-Thomas field x.
+void sxv_prebasis(int fam, int dim, int b, const double *x, double *v, double *dv)
+{
+    for (int c = 0; c < 3; c++) v[c] = 0.0;
+    for (int t = 0; t < 9; t++) dv[t] = 0.0;
+    if (b < dim) {
+        v[b] = 1.0;
+    } else if (fam == 2) {
+        for (int c = 0; c < dim; c++) {
+            v[c] = x[c];
+            dv[c * dim + c] = 1.0;
+        }
+    } else if (dim == 2) {
+        v[0] = -x[1];
+        v[1] = x[0];
+        dv[1] = -1.0;
+        dv[2] = 1.0;
+    } else {
+        const int m = b - 3, p = (m + 1) % 3, q = (m + 2) % 3;
+        v[p] = -x[q];
+        v[q] = x[p];
+        dv[p * 3 + q] = -1.0;
+        dv[q * 3 + p] = 1.0;
+    }
+}
+
+// Degrees of freedom on the reference simplex: the line integral of v along
+// edge (i, j) with tangent x_j - x_i, or the flux through the facet opposite
+// vertex a with normal N over its vertices in ascending local order.
+double sxv_moment(int fam, int dim, int a, int b)
+{
+    double gx[4], gw[4];
+    gauss_legendre_01(2, gx, gw);
+    auto vert = [dim](int r, double *x) {
+        for (int t = 0; t < dim; t++) x[t] = (r > 0 && t == r - 1) ? 1.0 : 0.0;
+    };
+    double v[3], dv[9], p[3] = {0, 0, 0};
+    double s = 0.0;
+    if (fam == 1) {
+        const int i = dim == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
+        const int j = dim == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
+        double xi[3], xj[3];
+        vert(i, xi);
+        vert(j, xj);
+        for (int q = 0; q < 2; q++) {
+            for (int t = 0; t < dim; t++) p[t] = xi[t] + gx[q] * (xj[t] - xi[t]);
+            sxv_prebasis(fam, dim, b, p, v, dv);
+            double d = 0.0;
+            for (int t = 0; t < dim; t++) d += v[t] * (xj[t] - xi[t]);
+            s += gw[q] * d;
+        }
+        return s;
+    }
+    int iv[3], m = 0;
+    for (int r = 0; r <= dim; r++)
+        if (r != a) iv[m++] = r;
+    double x0[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0}, N[3] = {0, 0, 0};
+    vert(iv[0], x0);
+    vert(iv[1], x1);
+    if (dim == 3) vert(iv[2], x2);
+    if (dim == 2) {
+        N[0] = x1[1] - x0[1];
+        N[1] = x0[0] - x1[0];
+        for (int q = 0; q < 2; q++) {
+            for (int t = 0; t < 2; t++) p[t] = x0[t] + gx[q] * (x1[t] - x0[t]);
+            sxv_prebasis(fam, dim, b, p, v, dv);
+            s += gw[q] * (v[0] * N[0] + v[1] * N[1]);
+        }
+        return s;
+    }
+    double t1[3], t2[3];
+    for (int t = 0; t < 3; t++) {
+        t1[t] = x1[t] - x0[t];
+        t2[t] = x2[t] - x0[t];
+    }
+    N[0] = t1[1] * t2[2] - t1[2] * t2[1];
+    N[1] = t1[2] * t2[0] - t1[0] * t2[2];
+    N[2] = t1[0] * t2[1] - t1[1] * t2[0];
+    // the (linear) integrand on the reference triangle by its centroid rule
+    for (int t = 0; t < 3; t++) p[t] = x0[t] + (t1[t] + t2[t]) / 3.0;
+    sxv_prebasis(fam, dim, b, p, v, dv);
+    return 0.5 * (v[0] * N[0] + v[1] * N[1] + v[2] * N[2]);
+}
+
+fe_status sxv_tables(fe_simplex S)
+{
+    const int dim = S->dim, fam = S->family, nd = S->nn, ntri = S->ntri;
+    // change of basis: C_ab = sigma_a(psi_b), Phi = C^-T (Gauss-Jordan)
+    std::vector<double> M(static_cast<size_t>(nd) * 2 * nd, 0.0);
+    for (int a = 0; a < nd; a++) {
+        for (int b = 0; b < nd; b++) M[a * 2 * nd + b] = sxv_moment(fam, dim, a, b);
+        M[a * 2 * nd + nd + a] = 1.0;
+    }
+    for (int c = 0; c < nd; c++) {
+        int p = c;
+        for (int i = c + 1; i < nd; i++)
+            if (std::fabs(M[i * 2 * nd + c]) > std::fabs(M[p * 2 * nd + c])) p = i;
+        if (M[p * 2 * nd + c] == 0.0) return set_error(FE_EINVAL, "singular change of basis");
+        if (p != c)
+            for (int j = 0; j < 2 * nd; j++) std::swap(M[c * 2 * nd + j], M[p * 2 * nd + j]);
+        const double piv = M[c * 2 * nd + c];
+        for (int j = 0; j < 2 * nd; j++) M[c * 2 * nd + j] /= piv;
+        for (int i = 0; i < nd; i++)
+            if (i != c) {
+                const double f = M[i * 2 * nd + c];
+                if (f != 0.0)
+                    for (int j = 0; j < 2 * nd; j++) M[i * 2 * nd + j] -= f * M[c * 2 * nd + j];
+            }
+    }
+    auto Phi = [&](int a, int b) { return M[b * 2 * nd + nd + a]; };  // (C^-1)_{ba}
+    auto shape = [&](const double *x, double *phi, double *cu, double *dvg) {
+        for (int a = 0; a < nd; a++) {
+            double v[3] = {0, 0, 0}, dv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int b = 0; b < nd; b++) {
+                double pv[3], pdv[9];
+                sxv_prebasis(fam, dim, b, x, pv, pdv);
+                for (int c = 0; c < 3; c++) v[c] += Phi(a, b) * pv[c];
+                for (int t = 0; t < 9; t++) dv[t] += Phi(a, b) * pdv[t];
+            }
+            for (int c = 0; c < dim; c++) phi[a * dim + c] = v[c];
+            if (dim == 3) {
+                cu[a * 3 + 0] = dv[7] - dv[5];
+                cu[a * 3 + 1] = dv[2] - dv[6];
+                cu[a * 3 + 2] = dv[3] - dv[1];
+            } else {
+                cu[a] = dv[2] - dv[1];
+            }
+            dvg[a] = dim == 3 ? dv[0] + dv[4] + dv[8] : dv[0] + dv[3];
+        }
+    };
+    const int nq1 = 1 + (dim + 1) / 2;
+    std::vector<double> qxw;
+    sx_rule(dim, nq1, qxw);
+    const int nq = int(qxw.size() / (dim + 1));
+    std::vector<double> phq(static_cast<size_t>(nq) * nd * dim);
+    std::vector<double> cu(nd * 3), dvg(nd);
+    for (int q = 0; q < nq; q++) shape(&qxw[size_t(q) * (dim + 1)], &phq[size_t(q) * nd * dim], cu.data(), dvg.data());
+    const double xc[3] = {0.25, 0.25, 0.25};
+    shape(xc, std::vector<double>(nd * 3).data(), cu.data(), dvg.data());  // curls and divergences are constant
+    const int nps = (fam == 1 && dim == 3) ? 6 : 1, npm = dim * (dim + 1) / 2;
+    const double vol = dim == 3 ? 1.0 / 6.0 : 0.5;
+    std::vector<int32_t> tri(ntri);
+    {
+        int t = 0;
+        for (int I = 0; I < nd; I++)
+            for (int J = I; J < nd; J++) tri[t++] = (I << 16) | J;
+    }
+    std::vector<double> tab(static_cast<size_t>(nps + npm) * ntri, 0.0);
+    for (int t = 0; t < ntri; t++) {
+        const int a = tri[t] >> 16, b = tri[t] & 0xffff;
+        if (nps == 6) {
+            int p = 0;
+            for (int r = 0; r < 3; r++)
+                for (int s = r; s < 3; s++, p++) {
+                    double v = cu[a * 3 + r] * cu[b * 3 + s];
+                    if (s != r) v += cu[a * 3 + s] * cu[b * 3 + r];
+                    tab[size_t(p) * ntri + t] = vol * v;
+                }
+        } else {
+            tab[t] = vol * (fam == 1 ? cu[a] * cu[b] : dvg[a] * dvg[b]);
+        }
+        int p = nps;
+        for (int r = 0; r < dim; r++)
+            for (int s = r; s < dim; s++, p++) {
+                double v = 0.0;
+                for (int q = 0; q < nq; q++) {
+                    const double w = qxw[size_t(q) * (dim + 1) + dim];
+                    const double *ph = &phq[size_t(q) * nd * dim];
+                    double pr = ph[a * dim + r] * ph[b * dim + s];
+                    if (s != r) pr += ph[a * dim + s] * ph[b * dim + r];
+                    v += w * pr;
+                }
+                tab[size_t(p) * ntri + t] = v;
+            }
+    }
+    fe_status st = sx_upload(S->tab, tab.data(), tab.size());
+    if (st == FE_OK) st = sx_upload(S->tri, tri.data(), tri.size());
+    if (st == FE_OK) st = sx_upload(S->phiq, phq.data(), phq.size());
+    if (st == FE_OK) st = sx_upload(S->qxw, qxw.data(), qxw.size());
+    return st;
+}
+
 // Reference tables for the element kernel: the coefficient-pair table and the
 // entry table, the shape values at the rule's points and the rule itself.
 fe_status sx_tables(fe_simplex S)
@@ -822,8 +1311,22 @@ fe_status launch_sx_elements(fe_simplex S, hipStream_t s)
     return FE_OK;
 }
 
+template <int DIM, int FAM>
+fe_status launch_sx_vector(fe_simplex S, hipStream_t s)
+{
+    using Sh = SxvShape<DIM, FAM>;
+    const int64_t nb = (S->ncells + Sh::CPB - 1) / Sh::CPB;
+    if (nb == 0) return FE_OK;
+    hipLaunchKernelGGL((sx_vector_kernel<DIM, FAM>), dim3(unsigned(nb)), dim3(256), 0, s, S->args, S->kappa, S->vxyz,
+                       S->cells, S->coef, S->tab, S->tri, S->phiq, S->qxw, S->E, S->F);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
 fe_status launch_elements(fe_simplex S, hipStream_t s)
 {
+    if (S->family == 1) return S->dim == 3 ? launch_sx_vector<3, 1>(S, s) : launch_sx_vector<2, 1>(S, s);
+    if (S->family == 2) return S->dim == 3 ? launch_sx_vector<3, 2>(S, s) : launch_sx_vector<2, 2>(S, s);
     const bool el = S->args.problem == FE_ELASTICITY;
 #define FE_SXL(D, KK)                                                                              \
     return el ? launch_sx_elements<D, KK, FE_ELASTICITY>(S, s) : launch_sx_elements<D, KK, FE_POISSON>(S, s)
@@ -842,6 +1345,45 @@ fe_status launch_elements(fe_simplex S, hipStream_t s)
         default: return launch_sx_elements<3, 4, FE_POISSON>(S, s);
     }
 #undef FE_SXL
+}
+
+// Mesh checks shared by the create calls (host only): sizes, vertex ids in
+// range, no degenerate cell (either orientation is accepted).
+fe_status sx_validate(const fe_simplex_desc *desc)
+{
+    const int dim = desc->dim;
+    if (desc->nverts < 0 || desc->ncells < 0) return set_error(FE_EINVAL, "negative sizes");
+    if (desc->ncells > 0 && (!desc->cells || !desc->vertex_xyz)) return set_error(FE_EINVAL, "null mesh arrays");
+    if (desc->nverts >= (int64_t(1) << 31)) return set_error(FE_EINVAL, "2^31 or more vertices");
+    const int nv = dim + 1;
+    for (int64_t t = 0; t < desc->ncells * nv; t++)
+        if (desc->cells[t] < 0 || desc->cells[t] >= desc->nverts) return set_error(FE_EMESH, "vertex id out of range");
+    // degenerate cells (det J = 0) are rejected; either orientation is accepted
+    for (int64_t K = 0; K < desc->ncells; K++) {
+        double J[3][3];
+        const double *x0 = desc->vertex_xyz + int64_t(desc->cells[K * nv]) * dim;
+        for (int s = 0; s < dim; s++) {
+            const double *xs = desc->vertex_xyz + int64_t(desc->cells[K * nv + s + 1]) * dim;
+            for (int r = 0; r < dim; r++) J[r][s] = xs[r] - x0[r];
+        }
+        const double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                    : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det != 0.0) || !std::isfinite(det)) return set_error(FE_EMESH, "degenerate simplex (det J = 0)");
+    }
+    return FE_OK;
+}
+
+// Device copies of the mesh and the element storage.
+fe_status sx_upload_mesh(fe_simplex S, const fe_simplex_desc *desc)
+{
+    fe_status st = sx_upload(S->vxyz, desc->vertex_xyz, size_t(desc->nverts) * S->dim);
+    if (st == FE_OK) st = sx_upload(S->cells, desc->cells, size_t(desc->ncells) * (S->dim + 1));
+    if (st == FE_OK && desc->cell_coeff) st = sx_upload(S->coef, desc->cell_coeff, size_t(desc->ncells));
+    if (st == FE_OK) st = sx_alloc(S->E, size_t(S->ncells) * S->ntri);
+    if (st == FE_OK) st = sx_alloc(S->F, size_t(S->ncells) * S->nloc);
+    return st;
 }
 
 unsigned blocks_of(int64_t n) { return unsigned(std::max<int64_t>(1, (n + 255) / 256)); }
@@ -866,26 +1408,9 @@ fe_status fe_simplex_create(const fe_simplex_desc *desc, int32_t order, const fe
         return set_error(FE_EINVAL, "unknown source kind");
     if (coeff->dirichlet_kind != FE_DIRICHLET_ZERO && coeff->dirichlet_kind != FE_DIRICHLET_AFFINE)
         return set_error(FE_EINVAL, "unknown Dirichlet kind");
-    if (desc->nverts < 0 || desc->ncells < 0) return set_error(FE_EINVAL, "negative sizes");
-    if (desc->ncells > 0 && (!desc->cells || !desc->vertex_xyz)) return set_error(FE_EINVAL, "null mesh arrays");
-    if (desc->nverts >= (int64_t(1) << 31)) return set_error(FE_EINVAL, "2^31 or more vertices");
+    fe_status vst = sx_validate(desc);
+    if (vst != FE_OK) return vst;
     const int nv = dim + 1;
-    for (int64_t t = 0; t < desc->ncells * nv; t++)
-        if (desc->cells[t] < 0 || desc->cells[t] >= desc->nverts) return set_error(FE_EMESH, "vertex id out of range");
-    // degenerate cells (det J = 0) are rejected; either orientation is accepted
-    for (int64_t K = 0; K < desc->ncells; K++) {
-        double J[3][3];
-        const double *x0 = desc->vertex_xyz + int64_t(desc->cells[K * nv]) * dim;
-        for (int s = 0; s < dim; s++) {
-            const double *xs = desc->vertex_xyz + int64_t(desc->cells[K * nv + s + 1]) * dim;
-            for (int r = 0; r < dim; r++) J[r][s] = xs[r] - x0[r];
-        }
-        const double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
-                                    : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                                          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                                          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        if (!(det != 0.0) || !std::isfinite(det)) return set_error(FE_EMESH, "degenerate simplex (det J = 0)");
-    }
     fe_simplex S = new fe_simplex_s();
     S->dim = dim;
     S->k = order;
@@ -920,11 +1445,52 @@ fe_status fe_simplex_create(const fe_simplex_desc *desc, int32_t order, const fe
     S->fix_boundary = coeff->dirichlet_faces != 0;
     fe_status st = sx_setup(S, desc->cells, desc->vertex_xyz);
     if (st == FE_OK) st = sx_tables(S);
-    if (st == FE_OK) st = sx_upload(S->vxyz, desc->vertex_xyz, size_t(desc->nverts) * dim);
-    if (st == FE_OK) st = sx_upload(S->cells, desc->cells, size_t(desc->ncells) * nv);
-    if (st == FE_OK && desc->cell_coeff) st = sx_upload(S->coef, desc->cell_coeff, size_t(desc->ncells));
-    if (st == FE_OK) st = sx_alloc(S->E, size_t(S->ncells) * S->ntri);
-    if (st == FE_OK) st = sx_alloc(S->F, size_t(S->ncells) * S->nloc);
+    if (st == FE_OK) st = sx_upload_mesh(S, desc);
+    if (st != FE_OK) {
+        sx_free(S);
+        return st;
+    }
+    *out = S;
+    return FE_OK;
+}
+
+fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, double kappa, const fe_coeff *coeff,
+                                   fe_simplex *out)
+{
+    if (!desc || !coeff || !out) return set_error(FE_EINVAL, "null argument");
+    *out = nullptr;
+    const int dim = desc->dim;
+    if (dim != 2 && dim != 3) return set_error(FE_EINVAL, "dim must be 2 or 3");
+    if (family != FE_NEDELEC && family != FE_RAVIART_THOMAS) return set_error(FE_EINVAL, "unknown element family");
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return set_error(FE_EINVAL, "kappa must be finite and >= 0");
+    if (coeff->precision != FE_FP64) return set_error(FE_EINVAL, "simplices integrate in FP64 only");
+    if (coeff->source_kind < FE_SOURCE_NONE || coeff->source_kind > FE_SOURCE_SINPROD)
+        return set_error(FE_EINVAL, "unknown source kind");
+    if (coeff->dirichlet_kind != FE_DIRICHLET_ZERO)
+        return set_error(FE_EINVAL, "vector elements take zero boundary traces only");
+    fe_status vst = sx_validate(desc);
+    if (vst != FE_OK) return vst;
+    fe_simplex S = new fe_simplex_s();
+    S->dim = dim;
+    S->k = 0;
+    S->family = family;
+    S->kappa = kappa;
+    S->nn = family == FE_NEDELEC ? (dim == 3 ? 6 : 3) : dim + 1;
+    S->ncomp = 1;
+    S->nloc = S->nn;
+    S->ntri = S->nloc * (S->nloc + 1) / 2;
+    S->nverts = desc->nverts;
+    S->ncells = desc->ncells;
+    SxArgs &a = S->args;
+    a.problem = -1;
+    a.source_kind = coeff->source_kind;
+    a.dirichlet_kind = FE_DIRICHLET_ZERO;
+    for (int i = 0; i < 3; i++) a.source[i] = coeff->source[i];
+    a.ncells = desc->ncells;
+    S->fix_boundary = coeff->dirichlet_faces != 0;
+    fe_status st = sxv_setup(S, desc->cells);
+    if (st == FE_OK) st = sxv_tables(S);
+    if (st == FE_OK) st = sx_upload_mesh(S, desc);
     if (st != FE_OK) {
         sx_free(S);
         return st;

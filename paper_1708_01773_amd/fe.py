@@ -18,6 +18,8 @@ FE_FP64, FE_FP32, FE_FP16, FE_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FE_FP64, "fp32": FE_FP32, "fp16": FE_FP16, "bf16": FE_BF16}
 FE_SOURCE_NONE, FE_SOURCE_CONST, FE_SOURCE_SINPROD = 0, 1, 2
 FE_DIRICHLET_ZERO, FE_DIRICHLET_AFFINE = 0, 1
+FE_NEDELEC, FE_RAVIART_THOMAS = 1, 2
+FAMILIES = {"nedelec": FE_NEDELEC, "raviart_thomas": FE_RAVIART_THOMAS}
 
 # every entry point include/fe.h declares
 EXPORTS = [
@@ -36,7 +38,7 @@ EXPORTS = [
     "fe_integrate_plan_of", "fe_dg_query", "fe_dg_pattern", "fe_dg_assemble", "fe_dg_spmv", "fe_dg_pcg_solve",
     "fe_stokes_create", "fe_stokes_destroy", "fe_stokes_query", "fe_stokes_assemble", "fe_stokes_system",
     "fe_stokes_solve", "fe_simplex_create", "fe_simplex_destroy", "fe_simplex_query", "fe_simplex_cell_dofs",
-    "fe_simplex_pattern", "fe_simplex_assemble", "fe_simplex_elements",
+    "fe_simplex_pattern", "fe_simplex_assemble", "fe_simplex_elements", "fe_simplex_create_vector",
 ]
 
 FE_REQ_QUEUED, FE_REQ_SETUP, FE_REQ_SOLVING, FE_REQ_DONE, FE_REQ_FAILED = 0, 1, 2, 3, 4
@@ -192,6 +194,8 @@ def lib():
             "fe_stokes_destroy": [_P],
             "fe_simplex_create": [_c.POINTER(SimplexDesc), _c.c_int32, _c.POINTER(Coeff), _c.POINTER(_P)],
             "fe_simplex_destroy": [_P],
+            "fe_simplex_create_vector": [_c.POINTER(SimplexDesc), _c.c_int32, _c.c_double, _c.POINTER(Coeff),
+                                         _c.POINTER(_P)],
             "fe_simplex_query": [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
                                  _c.POINTER(_c.c_int64)],
             "fe_simplex_cell_dofs": [_P, _P, _P],
@@ -996,7 +1000,10 @@ class Simplex:
     the device CSR of its free-free system (torch tensors); the pattern is
     written at construction."""
 
-    def __init__(self, dim, vertices, cells, order, coeff, cell_coeff=None, device="cuda", stream=None):
+    def __init__(self, dim, vertices, cells, order, coeff, cell_coeff=None, device="cuda", stream=None, family=None,
+                 kappa=1.0):
+        """family None: Lagrange P_order; "nedelec" / "raviart_thomas": the
+        lowest-order vector element (order ignored) with mass coefficient kappa."""
         import numpy as np
         import torch
         self.dim, self.order = int(dim), int(order)
@@ -1010,15 +1017,22 @@ class Simplex:
         d.cells = c.ctypes.data_as(_P)
         d.cell_coeff = None if k is None else k.ctypes.data_as(_P)
         h = _P()
-        _check(lib().fe_simplex_create(_c.byref(d), self.order, _c.byref(coeff), _c.byref(h)), "fe_simplex_create")
+        if family is None:
+            _check(lib().fe_simplex_create(_c.byref(d), self.order, _c.byref(coeff), _c.byref(h)), "fe_simplex_create")
+        else:
+            _check(lib().fe_simplex_create_vector(_c.byref(d), FAMILIES[family], float(kappa), _c.byref(coeff),
+                                                  _c.byref(h)), "fe_simplex_create_vector")
         self.handle = h
         self.ncells = c.shape[0]
         nr, nz, nn, nc = _c.c_int64(), _c.c_int64(), _c.c_int64(), _c.c_int64()
         _check(lib().fe_simplex_query(h, _c.byref(nr), _c.byref(nz), _c.byref(nn), _c.byref(nc)), "fe_simplex_query")
         self.n_rows, self.nnz, self.n_nodes, self.n_contrib = nr.value, nz.value, nn.value, nc.value
-        ncomp = self.dim if coeff.problem == FE_ELASTICITY else 1
-        nnode = (order + 1) * (order + 2) // 2 if dim == 2 else (order + 1) * (order + 2) * (order + 3) // 6
-        self.nloc = nnode * ncomp
+        if family is None:
+            ncomp = self.dim if coeff.problem == FE_ELASTICITY else 1
+            nnode = (order + 1) * (order + 2) // 2 if dim == 2 else (order + 1) * (order + 2) * (order + 3) // 6
+            self.nloc = nnode * ncomp
+        else:
+            self.nloc = (6 if dim == 3 else 3) if family == "nedelec" else dim + 1
         self.ntri = self.nloc * (self.nloc + 1) // 2
         dev = torch.device(device)
         self.rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=dev)

@@ -194,3 +194,133 @@ def test_simplex_rows_of_sampled_nodes_at_workload_size():
     info = F.pcg_solve(G.csr, G.rhs, xs, 1e-8, 20000, ws)
     say(f"solve: iters {info['iters']} true relres {info['true_relres']:.2e}")
     assert info["status"] == 0 and info["true_relres"] <= 2e-8
+
+
+# ---------------------------------------------------------------------------
+# lowest-order Nedelec and Raviart-Thomas elements (Sect. 3.9, 3.10)
+# ---------------------------------------------------------------------------
+VCASES = [
+    # family, dim, n, shuffle, source_kind, dirichlet
+    ("nedelec", 2, [3, 2], False, 1, True),
+    ("nedelec", 2, [2, 3], True, 2, False),
+    ("nedelec", 3, [2, 2, 1], True, 2, True),
+    ("nedelec", 3, [2, 1, 2], False, 1, False),
+    ("raviart_thomas", 2, [3, 2], True, 2, True),
+    ("raviart_thomas", 2, [2, 2], False, 1, False),
+    ("raviart_thomas", 3, [1, 2, 2], True, 1, True),
+    ("raviart_thomas", 3, [2, 2, 2], True, 2, False),
+]
+
+
+def _vids(c):
+    return f"{c[0][:3]}_{c[1]}d_{'x'.join(map(str, c[2]))}{'_shuf' if c[3] else ''}_f{c[4]}{'_dir' if c[5] else ''}"
+
+
+def build_vector_pair(family, dim, n, shuffle, sk, dirichlet, kappa=0.8, seed=5):
+    v, c = simplex_mesh(dim, n, jitter=0.2, shuffle=shuffle)
+    coef = lognormal_coefficients(c.shape[0], seed=17081 + seed)
+    src = (1.0, -0.5, 0.25)
+    coeff = F.make_coeff("poisson", "fp64", source_kind=sk, source=src, dim=dim, faces=None if dirichlet else 0)
+    G = F.Simplex(dim, v, c, 0, coeff, cell_coeff=coef, family=family, kappa=kappa)
+    G.assemble()
+    torch.cuda.synchronize()
+    S = O.VectorSystem(family, dim, v, c, coef=coef, kappa=kappa, source_kind=sk, source=src, dirichlet=dirichlet)
+    assert S.ok
+    return v, c, coef, G, S
+
+
+@pytest.mark.parametrize("case", VCASES, ids=[_vids(c) for c in VCASES])
+def test_vector_element_system_matches_oracle(case):
+    family, dim, n, shuffle, sk, dirichlet = case
+    say(f"[vector] {_vids(case)}")
+    v, c, coef, G, S = build_vector_pair(family, dim, n, shuffle, sk, dirichlet)
+    assert (G.n_rows, G.nnz, G.n_nodes) == (S.nfree, S.nnz, S.nent)
+    np.testing.assert_array_equal(G.cell_dofs().cpu().numpy(), S.cell_dofs)
+    np.testing.assert_array_equal(G.rowptr.cpu().numpy(), S.rowptr)
+    np.testing.assert_array_equal(G.colind[: G.nnz].cpu().numpy(), S.colind)
+    E, Fl = G.elements()
+    worst = 0.0
+    for K in range(c.shape[0]):
+        A, f, ok = O.vector_element(family, dim, v[c[K]], c[K], coef=coef[K], kappa=0.8, source_kind=sk,
+                                    source=(1.0, -0.5, 0.25))
+        assert ok
+        worst = max(worst, rel(E[K], upper(A)), rel(Fl[K], f))
+    ev = rel(G.values[: G.nnz].cpu().numpy(), S.values)
+    er = rel(G.rhs[: G.n_rows].cpu().numpy(), S.rhs)
+    ed = rel(G.dinv[: G.n_rows].cpu().numpy(), S.dinv)
+    say(f"element {worst:.2e} values {ev:.2e} rhs {er:.2e} dinv {ed:.2e}")
+    assert worst <= MATRIX_RTOL and ev <= MATRIX_RTOL and er <= MATRIX_RTOL and ed <= MATRIX_RTOL
+    v1 = G.values.clone()
+    G.assemble()
+    torch.cuda.synchronize()
+    assert torch.equal(v1, G.values)
+
+
+@pytest.mark.parametrize("family,dim,n", [("nedelec", 3, [3, 3, 2]), ("raviart_thomas", 3, [3, 2, 2]),
+                                          ("nedelec", 2, [6, 5])])
+def test_vector_element_pcg_matches_direct_solve_of_oracle(family, dim, n):
+    say(f"[vector solve] {family} dim={dim} n={n}")
+    v, c, coef, G, S = build_vector_pair(family, dim, n, True, 2, True, kappa=1.0)
+    xo = S.solve()
+    x = torch.zeros(G.n_rows, dtype=torch.float64, device="cuda")
+    ws = torch.empty(F.pcg_query(G.n_rows), dtype=torch.uint8, device="cuda")
+    info = F.pcg_solve(G.csr, G.rhs, x, 1e-12, 20000, ws)
+    say(f"iters {info['iters']} true relres {info['true_relres']:.2e}")
+    assert info["status"] == 0 and info["true_relres"] <= 1e-11
+    assert rel(x.cpu().numpy(), xo) <= 1e-8
+
+
+def test_nedelec_rows_of_sampled_edges_at_workload_size():
+    """Lowest-order Nedelec on the Kuhn subdivision of the jittered 64^3
+    brick (the benchmark's vector workload): curl curl u + u = f with the
+    manufactured field's load, zero tangential trace, lognormal coefficient."""
+    dim, n = 3, 64
+    say("[nedelec workload] 64^3 Kuhn")
+    v, c = simplex_mesh(dim, n, jitter=0.2)
+    coef = lognormal_coefficients(c.shape[0])
+    lap = 2.0 * np.pi ** 2
+    src = (lap + 1.0,) * 3
+    coeff = F.make_coeff("poisson", "fp64", source_kind=2, source=src, dim=dim)
+    G = F.Simplex(dim, v, c, 0, coeff, cell_coeff=coef, family="nedelec", kappa=1.0)
+    G.assemble()
+    torch.cuda.synchronize()
+    say(f"rows {G.n_rows} nnz {G.nnz} contributions {G.n_contrib}")
+    dof_of, code, nfree, _ = O.vector_number("nedelec", dim, len(v), c)
+    cd = G.cell_dofs().cpu().numpy()
+    np.testing.assert_array_equal(cd, code[dof_of])
+    assert G.n_rows == nfree
+    E, Fl = G.elements()
+    g = rng(98)
+    for K in list(g.integers(0, c.shape[0], size=24)) + [0, c.shape[0] - 1]:
+        A, f, _ = O.vector_element("nedelec", dim, v[c[K]], c[K], coef=coef[K], kappa=1.0, source_kind=2, source=src)
+        assert rel(E[K], upper(A)) <= MATRIX_RTOL and rel(Fl[K], f) <= MATRIX_RTOL
+    rowptr = G.rowptr.cpu().numpy()
+    x = g.standard_normal(G.n_rows)
+    y = torch.full((G.n_rows,), np.nan, dtype=torch.float64, device="cuda")
+    F.spmv(G.csr, torch.from_numpy(x).cuda(), y)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    worst, worst_y = 0.0, 0.0
+    for r in list(g.integers(0, G.n_rows, size=30)) + [0, G.n_rows - 1]:
+        Ks, As = np.nonzero(cd == r)
+        acc, rhs = {}, 0.0
+        for K, a in zip(Ks, As):
+            A, f, _ = O.vector_element("nedelec", dim, v[c[K]], c[K], coef=coef[K], kappa=1.0, source_kind=2,
+                                       source=src)
+            rhs += f[a]
+            for b in range(cd.shape[1]):
+                if cd[K, b] >= 0:
+                    acc[cd[K, b]] = acc.get(cd[K, b], 0.0) + A[a, b]
+        cols = np.array(sorted(acc))
+        vals = np.array([acc[j] for j in cols])
+        r0, r1 = rowptr[r], rowptr[r + 1]
+        np.testing.assert_array_equal(G.colind[r0:r1].cpu().numpy(), cols)
+        worst = max(worst, rel(G.values[r0:r1].cpu().numpy(), vals), rel(G.rhs[r:r + 1].cpu().numpy(), [rhs]))
+        worst_y = max(worst_y, abs(y[r] - vals @ x[cols]) / (np.abs(vals) @ np.abs(x[cols])))
+    say(f"worst sampled-row rel err {worst:.2e}, SpMV {worst_y:.2e}")
+    assert worst <= MATRIX_RTOL and worst_y <= 1e-12
+    xs = torch.zeros(G.n_rows, dtype=torch.float64, device="cuda")
+    ws = torch.empty(F.pcg_query(G.n_rows), dtype=torch.uint8, device="cuda")
+    info = F.pcg_solve(G.csr, G.rhs, xs, 1e-8, 20000, ws)
+    say(f"solve: iters {info['iters']} true relres {info['true_relres']:.2e}")
+    assert info["status"] == 0 and info["true_relres"] <= 2e-8
