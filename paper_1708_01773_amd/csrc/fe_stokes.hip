@@ -153,35 +153,6 @@ __device__ __forceinline__ double block_reduce_256(double v)
     return red[0];
 }
 
-__global__ __launch_bounds__(256) void minres_dot_kernel(int64_t n, const double *__restrict__ a,
-                                                         const double *__restrict__ b, double *__restrict__ part)
-{
-    double s = 0.0;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        s += a[i] * b[i];
-    s = block_reduce_256(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// p -= alpha v + beta vold; z = minv p; partial sums of p.z
-__global__ __launch_bounds__(256) void minres_lanczos_kernel(int64_t n, double alpha, double beta,
-                                                             const double *__restrict__ v,
-                                                             const double *__restrict__ vold, double *__restrict__ p,
-                                                             const double *__restrict__ minv, double *__restrict__ z,
-                                                             double *__restrict__ part)
-{
-    double s = 0.0;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const double pi = p[i] - alpha * v[i] - beta * vold[i];
-        const double zi = minv[i] * pi;
-        p[i] = pi;
-        z[i] = zi;
-        s += pi * zi;
-    }
-    s = block_reduce_256(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
 __global__ __launch_bounds__(256) void minres_sum_kernel(int np, const double *__restrict__ part,
                                                          double *__restrict__ out)
 {
@@ -191,23 +162,6 @@ __global__ __launch_bounds__(256) void minres_sum_kernel(int np, const double *_
     if (threadIdx.x == 0) *out = s;
 }
 
-// dnew = (zv - delta d - eps dold) / gamma; x += tau dnew (x split into u | p)
-__global__ __launch_bounds__(256) void minres_update_kernel(int64_t n, int64_t nu, double delta, double eps,
-                                                            double ginv, double tau, const double *__restrict__ zv,
-                                                            const double *__restrict__ d,
-                                                            const double *__restrict__ dold,
-                                                            double *__restrict__ dnew, double *__restrict__ xu,
-                                                            double *__restrict__ xp)
-{
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const double di = (zv[i] - delta * d[i] - eps * dold[i]) * ginv;
-        dnew[i] = di;
-        if (i < nu) xu[i] += tau * di;
-        else xp[i - nu] += tau * di;
-    }
-}
-
-// y = s x (in place allowed), and w = s z
 __global__ __launch_bounds__(256) void minres_scale2_kernel(int64_t n, double s, const double *__restrict__ x,
                                                             double *__restrict__ y, const double *__restrict__ z,
                                                             double *__restrict__ w)
@@ -226,6 +180,116 @@ __global__ __launch_bounds__(256) void minres_axpy_kernel(int64_t n, double a, c
 }
 
 // r = b - y (b: rhs; y: K x), z = minv r, partials of r.z
+// ---------------------------------------------------------------------------
+// MINRES with its scalars on the device.  The Givens state of the QR of the
+// Lanczos tridiagonal lives in two slots (read one, write the other, by
+// iteration parity); every block of a kernel sums the partials it needs in
+// the fixed order of minres_sum_kernel, so all blocks hold the same scalars
+// and the host never waits inside an iteration.  ctrl[0] is the iteration
+// count at which the solve stopped (-1 while running), ctrl[1] the reason
+// (0 converged, 1 breakdown, 2 maxit); kernels queued after a stop return at
+// once, so x is never touched again.
+struct MinresScalars {
+    double beta, c_old, s_old, c, sn, eta;
+};
+
+__device__ __forceinline__ double sum_partials(int np, const double *__restrict__ part)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_reduce_256(s);
+    __syncthreads();  // every thread has read the sum before the buffer is reused
+    return s;
+}
+
+__global__ __launch_bounds__(256) void minres_dot_dev_kernel(int64_t n, const double *__restrict__ a,
+                                                             const double *__restrict__ b, double *__restrict__ part,
+                                                             const int *__restrict__ ctrl)
+{
+    if (ctrl[0] >= 0) return;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        s += a[i] * b[i];
+    s = block_reduce_256(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// w -= alpha v + beta vold; z = minv w; partial sums of w.z
+__global__ __launch_bounds__(256) void minres_lanczos_dev_kernel(int64_t n, int np,
+                                                                 const double *__restrict__ part_dot,
+                                                                 const MinresScalars *__restrict__ sc,
+                                                                 const double *__restrict__ v,
+                                                                 const double *__restrict__ vold,
+                                                                 double *__restrict__ w, const double *__restrict__ minv,
+                                                                 double *__restrict__ z, double *__restrict__ part_bn,
+                                                                 const int *__restrict__ ctrl)
+{
+    if (ctrl[0] >= 0) return;
+    const double alpha = sum_partials(np, part_dot);
+    const double beta = sc->beta;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const double pi = w[i] - alpha * v[i] - beta * vold[i];
+        const double zi = minv[i] * pi;
+        w[i] = pi;
+        z[i] = zi;
+        s += pi * zi;
+    }
+    s = block_reduce_256(s);
+    if (threadIdx.x == 0) part_bn[blockIdx.x] = s;
+}
+
+// Givens step and the vector updates of iteration it:
+//   d_new = (zv - delta d - eps d_old) / gamma   (written over d_old)
+//   x += tau d_new; v_next = w / beta_new (over v_old); zv = z / beta_new
+__global__ __launch_bounds__(256) void minres_update_dev_kernel(
+    int64_t n, int64_t nu, int np, const double *__restrict__ part_dot, const double *__restrict__ part_bn,
+    const MinresScalars *__restrict__ sc_in, MinresScalars *__restrict__ sc_out, double stop_tol, int it, int maxit,
+    int *__restrict__ ctrl, const double *__restrict__ w, const double *__restrict__ z, double *__restrict__ zv,
+    const double *__restrict__ d, double *__restrict__ dold_dnew, double *__restrict__ vold_vnext,
+    double *__restrict__ xu, double *__restrict__ xp)
+{
+    if (ctrl[0] >= 0) return;
+    const double alpha = sum_partials(np, part_dot);
+    const double bn2 = sum_partials(np, part_bn);
+    const MinresScalars S = *sc_in;
+    const double beta_new = sqrt(bn2 > 0.0 ? bn2 : 0.0);
+    const double eps = S.s_old * S.beta;
+    const double t = S.c_old * S.beta;
+    const double delta = S.c * t + S.sn * alpha;
+    const double gbar = -S.sn * t + S.c * alpha;
+    const double gamma = sqrt(gbar * gbar + beta_new * beta_new);
+    const bool bad = !(bn2 >= 0.0) || !isfinite(bn2) || !isfinite(alpha) || !(gamma > 0.0);
+    if (bad) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctrl[0] = it;
+            ctrl[1] = 1;
+        }
+        return;
+    }
+    const double c2 = gbar / gamma, sn2 = beta_new / gamma;
+    const double tau = c2 * S.eta, eta2 = -sn2 * S.eta;
+    const double ginv = 1.0 / gamma, bscale = beta_new > 0.0 ? 1.0 / beta_new : 0.0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const double di = (zv[i] - delta * d[i] - eps * dold_dnew[i]) * ginv;
+        dold_dnew[i] = di;
+        if (i < nu) xu[i] += tau * di;
+        else xp[i - nu] += tau * di;
+        vold_vnext[i] = bscale * w[i];
+        zv[i] = bscale * z[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *sc_out = MinresScalars{beta_new, S.c, S.sn, c2, sn2, eta2};
+        if (fabs(eta2) <= stop_tol) {
+            ctrl[0] = it + 1;
+            ctrl[1] = 0;
+        } else if (it + 1 >= maxit) {
+            ctrl[0] = it + 1;
+            ctrl[1] = 2;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void minres_init_kernel(int64_t n, const double *__restrict__ b,
                                                           const double *__restrict__ y, const double *__restrict__ minv,
                                                           double *__restrict__ r, double *__restrict__ z,
@@ -267,6 +331,8 @@ struct fe_stokes_s {
     double *eb = nullptr, *mdb = nullptr, *md = nullptr, *minv = nullptr;
     double *mv = nullptr;    // MINRES vectors: 8 of n = nu + np
     double *part = nullptr;  // partials (kMinresGrid) and the scalar
+    double *mr = nullptr;    // device MINRES: dot and w.z partials, two scalar slots, control word
+    int *ctrl_host = nullptr; // pinned copies of the control word (two)
 };
 
 namespace {
@@ -283,9 +349,10 @@ void stokes_free(fe_stokes S)
     void *ptrs[] = {S->ws_a,   S->a_rowptr, S->a_colind, S->a_values, S->rhs,     S->dinv,    S->b_rowptr,
                     S->bt_rowptr, S->b_colind, S->bt_colind, S->b_values, S->bt_values, S->gb_ptr,  S->gb_idx,
                     S->gbt_ptr,  S->gbt_idx,  S->gm_ptr,   S->gm_idx,   S->eb,      S->mdb,     S->md,
-                    S->minv,     S->mv,       S->part};
+                    S->minv,     S->mv,       S->part,     S->mr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (S->ctrl_host) (void)hipHostFree(S->ctrl_host);
     free_space(S->su);
     free_space(S->sp);
     delete S;
@@ -502,6 +569,11 @@ fe_status fe_stokes_create(fe_mesh mesh, int32_t order, double mu, const fe_coef
     if (st == FE_OK) st = dmalloc(S->minv, size_t(n));
     if (st == FE_OK) st = dmalloc(S->mv, 8 * size_t(n));
     if (st == FE_OK) st = dmalloc(S->part, kMinresGrid + 8);
+    if (st == FE_OK) st = dmalloc(S->mr, 2 * kMinresGrid + 16);
+    if (st == FE_OK && hipHostMalloc(&S->ctrl_host, 8 * sizeof(int)) != hipSuccess) {
+        S->ctrl_host = nullptr;
+        st = set_error(FE_ENOMEM, "pinned control word");
+    }
     if (st == FE_OK) st = launch_pattern(au, S->a_rowptr, S->a_colind, nullptr);
     if (st == FE_OK && hipDeviceSynchronize() != hipSuccess) st = set_error(FE_EDEVICE, "stokes set-up failed");
     if (st != FE_OK) {
@@ -634,67 +706,78 @@ fe_status fe_stokes_solve(fe_stokes S, double rtol, int32_t maxit, double *u, do
         info->status = FE_EBREAKDOWN;
         return set_error(FE_EBREAKDOWN, "minres: preconditioner not positive");
     }
-    double beta = std::sqrt(b2), beta_old = 0.0;
+    const double beta = std::sqrt(b2);
     const double bnorm = std::sqrt(std::max(bb, 0.0));
-    double eta = beta;  // the rotated right-hand side: |eta| = ||r||_{M^-1}
-    double c_old = 1.0, s_old = 0.0, c = 1.0, sn = 0.0;
     FE_HIP(hipMemsetAsync(vold, 0, sizeof(double) * n, s));
     FE_HIP(hipMemsetAsync(d, 0, sizeof(double) * n, s));
     FE_HIP(hipMemsetAsync(dold, 0, sizeof(double) * n, s));
-    int it = 0;
-    fe_status status = beta <= rtol * bnorm ? FE_OK : FE_ENOTCONV;
     if (beta > 0.0)
         hipLaunchKernelGGL(minres_scale2_kernel, dim3(g), dim3(256), 0, s, n, 1.0 / beta, v, v, z, zv);
-    while (status == FE_ENOTCONV && it < maxit && beta > 0.0) {
-        // Lanczos: w = K zv - alpha v - beta_old vold; z = M^-1 w; beta_new = sqrt(w . z)
-        if ((st = stokes_apply(S, zv, zv + nu, w, w + nu, dnew, s)) != FE_OK) return st;
-        hipLaunchKernelGGL(minres_dot_kernel, dim3(g), dim3(256), 0, s, n, zv, w, S->part);
-        double alpha = 0.0;
-        if ((st = read_scalar(S, g, s, alpha)) != FE_OK) return st;
-        hipLaunchKernelGGL(minres_lanczos_kernel, dim3(g), dim3(256), 0, s, n, alpha, beta, v, vold, w, S->minv, z,
-                           S->part);
-        double bn2 = 0.0;
-        if ((st = read_scalar(S, g, s, bn2)) != FE_OK) return st;
-        if (!(bn2 >= 0.0) || !std::isfinite(bn2) || !std::isfinite(alpha)) {
-            status = FE_EBREAKDOWN;
-            break;
+    // device state: dot partials, w.z partials, two scalar slots, the control word
+    double *part_dot = S->mr, *part_bn = S->mr + kMinresGrid;
+    MinresScalars *slot = reinterpret_cast<MinresScalars *>(S->mr + 2 * kMinresGrid);
+    int *ctrl = reinterpret_cast<int *>(S->mr + 2 * kMinresGrid + 12);
+    const MinresScalars s0{beta, 1.0, 0.0, 1.0, 0.0, beta};  // |eta| = ||r||_{M^-1}
+    const int ctrl0[2] = {-1, 0};
+    FE_HIP(hipMemcpyAsync(slot, &s0, sizeof(s0), hipMemcpyHostToDevice, s));
+    FE_HIP(hipMemcpyAsync(ctrl, ctrl0, sizeof(ctrl0), hipMemcpyHostToDevice, s));
+    const double stop_tol = rtol * bnorm;
+    int iters = 0, reason = 0;
+    if (beta <= stop_tol || !(beta > 0.0)) {
+        reason = 0;  // converged at x0
+    } else if (maxit == 0) {
+        reason = 2;
+    } else {
+        // iterations are queued in chunks; the host reads the control word of
+        // chunk c (copied asynchronously) only after chunk c+1 is queued, so
+        // the device never waits for it
+        constexpr int kChunk = 8;
+        hipEvent_t ev[2];
+        FE_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        FE_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        int chunk = 0;
+        bool stopped = false;
+        for (int it = 0; it < maxit && !stopped; chunk++) {
+            const int end = std::min(maxit, it + kChunk);
+            for (; it < end; it++) {
+                // Lanczos: w = K zv - alpha v - beta vold; z = M^-1 w; beta_new = sqrt(w . z)
+                if ((st = stokes_apply(S, zv, zv + nu, w, w + nu, dnew, s)) != FE_OK) break;
+                hipLaunchKernelGGL(minres_dot_dev_kernel, dim3(g), dim3(256), 0, s, n, zv, w, part_dot, ctrl);
+                hipLaunchKernelGGL(minres_lanczos_dev_kernel, dim3(g), dim3(256), 0, s, n, g, part_dot, slot + (it & 1),
+                                   v, vold, w, S->minv, z, part_bn, ctrl);
+                hipLaunchKernelGGL(minres_update_dev_kernel, dim3(g), dim3(256), 0, s, n, nu, g, part_dot, part_bn,
+                                   slot + (it & 1), slot + ((it + 1) & 1), stop_tol, it, maxit, ctrl, w, z, zv, d,
+                                   dold, vold, u, p);
+                // the new direction was written over dold, the new v over vold
+                std::swap(d, dold);
+                std::swap(v, vold);
+            }
+            if (st != FE_OK) break;
+            FE_HIP(hipGetLastError());
+            int *hc = S->ctrl_host + 2 * (chunk & 1);
+            FE_HIP(hipMemcpyAsync(hc, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            FE_HIP(hipEventRecord(ev[chunk & 1], s));
+            if (chunk > 0) {
+                FE_HIP(hipEventSynchronize(ev[(chunk - 1) & 1]));
+                stopped = S->ctrl_host[2 * ((chunk - 1) & 1)] >= 0;
+            }
         }
-        const double beta_new = std::sqrt(bn2);
-        // QR of the tridiagonal by Givens rotations: column it has beta (row it-1),
-        // alpha (row it), beta_new (row it+1); rotations of the two previous columns first
-        const double eps = s_old * beta;
-        const double t = c_old * beta;
-        const double delta = c * t + sn * alpha;
-        const double gbar = -sn * t + c * alpha;
-        const double gamma = std::sqrt(gbar * gbar + beta_new * beta_new);
-        if (!(gamma > 0.0)) {
-            status = FE_EBREAKDOWN;
-            break;
-        }
-        c_old = c;
-        s_old = sn;
-        c = gbar / gamma;
-        sn = beta_new / gamma;
-        const double tau = c * eta;
-        eta = -sn * eta;
-        // direction and solution update
-        hipLaunchKernelGGL(minres_update_kernel, dim3(g), dim3(256), 0, s, n, nu, delta, eps, 1.0 / gamma, tau, zv, d,
-                           dold, dnew, u, p);
-        std::swap(dold, d);
-        std::swap(d, dnew);
-        // next Lanczos vectors: vold = v, v = w / beta_new, zv = z / beta_new
-        std::swap(vold, v);
-        if (beta_new > 0.0)
-            hipLaunchKernelGGL(minres_scale2_kernel, dim3(g), dim3(256), 0, s, n, 1.0 / beta_new, w, v, z, zv);
-        beta_old = beta;
-        beta = beta_new;
-        it++;
-        if (std::fabs(eta) <= rtol * bnorm) status = FE_OK;
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        if (st != FE_OK) return st;
+        int hc[2];
+        FE_HIP(hipMemcpyAsync(hc, ctrl, sizeof(hc), hipMemcpyDeviceToHost, s));
+        FE_HIP(hipStreamSynchronize(s));
+        iters = hc[0] >= 0 ? hc[0] : maxit;
+        reason = hc[0] >= 0 ? hc[1] : 2;
     }
-    (void)beta_old;
-    FE_HIP(hipGetLastError());
+    MinresScalars fin{};
+    FE_HIP(hipMemcpyAsync(&fin, slot + (iters & 1), sizeof(fin), hipMemcpyDeviceToHost,
+                          s));
     FE_HIP(hipStreamSynchronize(s));
-    info->iters = it;
+    const double eta = fin.eta;
+    const fe_status status = reason == 0 ? FE_OK : reason == 1 ? FE_EBREAKDOWN : FE_ENOTCONV;
+    info->iters = iters;
     info->status = status;
     info->relres = bnorm > 0.0 ? std::fabs(eta) / bnorm : std::fabs(eta);
     // the true residual in the same norm

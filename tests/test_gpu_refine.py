@@ -61,6 +61,35 @@ def test_refinement_limits():
     assert info["status"] == F.FE_OK and info["outer_iters"] == 1
 
 
+def test_refinement_on_fp32_symmetric_storage_with_wave_strided_steps():
+    """Above 256 x 32768 rows the FP32 symmetric SpMV loops over steps (the
+    looping form, mode 7): the refined solution against the refinement whose
+    inner operator is the FP32 CSR of the same system."""
+    n = 205  # 204^3 = 8.49M free nodes
+    say("[refine sym32 strided] 205^3 Q1")
+    hi = Pair(3, [n, n, n], 1, source=(1.0,), seed=13)  # a jitter draw that inverts no cell at 205^3
+    A_hi = hi.gpu_assembly()
+    lo = Pair(3, [n, n, n], 1, source=(1.0,), seed=13, precision="fp32")
+    A_lo = lo.gpu_assembly()
+    assert A_hi.n_rows > 256 * 32768
+    nb = F.sym_query(lo.mesh, 1, lo.coeff)
+    sym32 = torch.full((nb // 8,), float("nan"), dtype=torch.float32, device="cuda")
+    F.sym_fp32_from_csr(lo.mesh, 1, lo.coeff, A_lo.csr, sym32)
+    ws = torch.empty(F.refine_query(A_hi.n_rows), dtype=torch.uint8, device="cuda")
+    x = torch.zeros(A_hi.n_rows, dtype=torch.float64, device="cuda")
+    info = F.refine_solve_sym(hi.mesh, 1, hi.coeff, A_hi.csr, A_lo.csr, sym32, A_hi.rhs, x, 1e-10, 1e-4, 50, 20000,
+                              ws)
+    v32 = torch.empty(A_lo.nnz, dtype=torch.float32, device="cuda")
+    F.csr_to_fp32(A_lo.csr, v32)
+    xc = torch.zeros_like(x)
+    infoc = F.refine_solve(A_hi.csr, A_lo.csr, A_hi.rhs, xc, 1e-10, 1e-4, 50, 20000, ws, values32=v32)
+    torch.cuda.synchronize()
+    say(f"   sym32 {info}  csr32 {infoc}")
+    assert info["status"] == infoc["status"] == F.FE_OK and info["relres"] <= 1e-10
+    assert abs(info["outer_iters"] - infoc["outer_iters"]) <= 1
+    assert rel(x.cpu().numpy(), xc.cpu().numpy()) <= 1e-8
+
+
 @pytest.mark.parametrize("dim,n,lo_prec,faces", [(3, [12, 10, 8], "fp32", None), (3, [9, 7, 11], "fp64", 0b011010),
                                                  (2, [40, 33], "fp32", None)])
 def test_refinement_on_fp32_symmetric_storage(dim, n, lo_prec, faces):
