@@ -869,10 +869,12 @@ class SimplexSystem:
 # Lowest-order Nedelec (edges, covariant Piola) and Raviart-Thomas (facets,
 # contravariant Piola) elements on simplices (fe_oracle_simplex.c)
 # ---------------------------------------------------------------------------
-FAMILIES = {"nedelec": 1, "raviart_thomas": 2}
+FAMILIES = {"nedelec": 1, "raviart_thomas": 2, "nedelec2": 3}
 
 
 def vector_ndof(family, dim):
+    if family == "nedelec2":
+        return 20 if dim == 3 else 8
     return (6 if dim == 3 else 3) if family == "nedelec" else dim + 1
 
 
@@ -900,7 +902,7 @@ def vector_element(family, dim, X, g, coef=1.0, kappa=1.0, source_kind=0, source
     nd = vector_ndof(family, dim)
     A = np.zeros((nd, nd))
     f = np.zeros(nd)
-    src = _c(list(source) + [0.0] * (3 - len(source)), np.float64)
+    src = _c(list(source) + [0.0] * (12 - len(source)), np.float64)
     rc = lib().orc_vx_element(FAMILIES[family], dim, _ptr(_c(X, np.float64).reshape(-1)), _ptr(_c(g, np.int32)),
                               float(coef), float(kappa), int(source_kind), _ptr(src), _ptr(A), _ptr(f))
     return A, f, rc == 0
@@ -921,9 +923,11 @@ def vector_number(family, dim, nverts, cells, dirichlet=True):
 
 
 class VectorSystem:
-    """The oracle's free-free system of a lowest-order vector element on a
-    simplicial mesh: int coef curl.curl (div div) + kappa u.v, zero
-    tangential (normal) trace on the boundary when dirichlet."""
+    """The oracle's free-free system of a vector element on a simplicial mesh
+    ("nedelec", "raviart_thomas": lowest order; "nedelec2": second-order
+    Nedelec): int coef curl.curl (div div) + kappa u.v, zero tangential
+    (normal) trace on the boundary when dirichlet.  source_kind 1 constant,
+    2 the manufactured field, 3 affine (12 coefficients, as a Dirichlet datum)."""
 
     def __init__(self, family, dim, verts, cells, coef=None, kappa=1.0, source_kind=0, source=(0.0, 0.0, 0.0),
                  dirichlet=True):
@@ -941,7 +945,7 @@ class VectorSystem:
         self.nnz = int(self.rowptr[-1])
         self.values = np.zeros(self.nnz)
         self.rhs = np.zeros(self.nfree)
-        src = _c(list(source) + [0.0] * (3 - len(source)), np.float64)
+        src = _c(list(source) + [0.0] * (12 - len(source)), np.float64)
         t0 = time.perf_counter()
         rc = lib().orc_vx_assemble(FAMILIES[family], self.dim, _ptr(self.verts), self.cells.shape[0], _ptr(self.cells),
                                    _ptr(self.coef), self.kappa, int(source_kind), _ptr(src), _ptr(self.cell_dofs),

@@ -621,30 +621,51 @@ double orc_sx_l2_error(const orc_sx_problem *P, const double *vxyz, int64_t ncel
 }
 
 /* ======================================================================== */
-/* Lowest-order vector elements on simplices (Sect. 3.9 div-conforming,      */
-/* Sect. 3.10 curl-conforming): family 1 = Nedelec edge elements (space      */
-/* [P_0]^d + S, S = {W x : W skew}, one tangential moment per edge,          */
-/* covariant Piola map), family 2 = Raviart-Thomas (space [P_0]^d + x P_0,   */
-/* one flux moment per facet, contravariant Piola map).  Shape functions by  */
-/* the change of basis of Sect. 3.5 from that pre-basis.                     */
+/* Vector elements on simplices (Sect. 3.9 div-conforming, Sect. 3.10        */
+/* curl-conforming), shape functions by the change of basis of Sect. 3.5:   */
+/*  family 1: Nedelec of the lowest order, [P_0]^d + {W x : W skew}, one    */
+/*            tangential moment per edge (covariant Piola map);             */
+/*  family 2: Raviart-Thomas of the lowest order, [P_0]^d + x P_0, one flux */
+/*            moment per facet (contravariant Piola map);                   */
+/*  family 3: Nedelec of the second order, [P_1]^d + S_2 with S_2 the       */
+/*            homogeneous quadratic fields orthogonal to x, two moments per */
+/*            edge (against 1 - t and t along it), two per face (against   */
+/*            its two edge tangents, 3D) and two interior ones (2D).       */
 /*                                                                          */
 /* Moments on the reference simplex (the readings taken):                   */
 /*  - edge (i, j), i < j local: int_0^1 v(x_i + t (x_j - x_i)) . (x_j - x_i) */
-/*    dt (the tangent not normalized: the line integral, which the          */
-/*    covariant map preserves);                                             */
+/*    q(t) dt, the tangent not normalized (the line integral, which the     */
+/*    covariant map preserves); q = 1 (family 1) or 1 - t, t (family 3);   */
 /*  - facet opposite local vertex j, its vertices i0 < i1 (< i2) local:     */
-/*    int over the reference (d-1)-simplex of v(phi_F(s)) . N ds with       */
-/*    phi_F(s) = x_i0 + s_1 (x_i1 - x_i0) (+ s_2 (x_i2 - x_i0)) and         */
-/*    N = (x_i1 - x_i0) x (x_i2 - x_i0) in 3D, N = rot(x_i1 - x_i0) =       */
-/*    (t_y, -t_x) in 2D (the flux, which the contravariant map preserves).  */
-/*  - Global orientation: an edge runs from its lower to its higher global  */
-/*    vertex id; a facet's normal is N taken over its vertices in ascending */
-/*    global id.  A local DOF whose local orientation differs has sign -1:  */
-/*    the cell's matrix and load are multiplied by the signs.               */
-/* Local DOF order: edges (0,1),(0,2),(1,2) in 2D and (0,1),(0,2),(0,3),    */
-/* (1,2),(1,3),(2,3) in 3D; facets by the opposite local vertex.            */
+/*    family 2: int over the reference (d-1)-simplex of v(phi_F(s)) . N ds  */
+/*    with N = (x_i1 - x_i0) x (x_i2 - x_i0) (2D: (t_y, -t_x)), the flux;   */
+/*    family 3 (3D): int v(phi_F(s)) . t_m ds, t_0 = x_i1 - x_i0,           */
+/*    t_1 = x_i2 - x_i0;                                                    */
+/*  - family 3 in 2D: the interior moments int_K v . e_m on the reference   */
+/*    cell (local to the cell).                                             */
+/* Global orientation: an edge runs from its lower to its higher global     */
+/* vertex id, a facet's frame is taken over its vertices in ascending      */
+/* global id.  The cell's local moments are T times the global ones (T      */
+/* block diagonal: a sign per DOF for families 1-2; for family 3 a 2 x 2    */
+/* block per edge -- identity, or the two DOFs swapped and negated when the */
+/* edge runs the other way -- and per face, the integer matrix expressing  */
+/* the local tangents in the global ones); so the cell's basis functions in */
+/* the global frame are T^T phi, its matrix T^T A T and its load T^T f.     */
+/* Local DOF order: edges (0,1),(0,2),(1,2) [2D] or (0,1),(0,2),(0,3),(1,2), */
+/* (1,3),(2,3) [3D] (two consecutive DOFs each for family 3), then faces by  */
+/* their opposite vertex, then interior DOFs; facets by their opposite     */
+/* vertex for family 2.                                                     */
 /* ======================================================================== */
-static int vx_ndof(int family, int dim) { return family == 1 ? (dim == 3 ? 6 : 3) : dim + 1; }
+#define VX_MAXND 20
+
+static int vx_ndof(int family, int dim)
+{
+    if (family == 1) return dim == 3 ? 6 : 3;
+    if (family == 2) return dim + 1;
+    return dim == 3 ? 20 : 8;
+}
+
+static int vx_order(int family) { return family == 3 ? 2 : 1; }
 
 static void vx_edge(int dim, int a, int *i, int *j)
 {
@@ -666,6 +687,50 @@ static void vx_prebasis(int family, int dim, int b, const double *x, double *v, 
     for (int c = 0; c < dim; c++) {
         v[c] = 0.0;
         for (int r = 0; r < dim; r++) dv[c * dim + r] = 0.0;
+    }
+    if (family == 3) {
+        if (b < dim * (dim + 1)) { /* [P_1]^d: component b / (d+1) times 1, x_0, .. */
+            int c = b / (dim + 1), m = b % (dim + 1);
+            v[c] = m == 0 ? 1.0 : x[m - 1];
+            if (m > 0) dv[c * dim + m - 1] = 1.0;
+            return;
+        }
+        int j = b - dim * (dim + 1);
+        if (dim == 2) { /* x_m (-y, x) */
+            int m = j;
+            double R[2] = {-x[1], x[0]};
+            v[0] = x[m] * R[0];
+            v[1] = x[m] * R[1];
+            dv[0 * 2 + m] += R[0];
+            dv[1 * 2 + m] += R[1];
+            dv[0 * 2 + 1] += -x[m];
+            dv[1 * 2 + 0] += x[m];
+            return;
+        }
+        /* x_jj (x cross e_i) for the pairs (i, jj) other than (2, 2) */
+        int i = j / 3, jj = j % 3;
+        double R[3] = {0, 0, 0}, dR[9] = {0};
+        if (i == 0) { /* (0, z, -y) */
+            R[1] = x[2];
+            R[2] = -x[1];
+            dR[1 * 3 + 2] = 1.0;
+            dR[2 * 3 + 1] = -1.0;
+        } else if (i == 1) { /* (-z, 0, x) */
+            R[0] = -x[2];
+            R[2] = x[0];
+            dR[0 * 3 + 2] = -1.0;
+            dR[2 * 3 + 0] = 1.0;
+        } else { /* (y, -x, 0) */
+            R[0] = x[1];
+            R[1] = -x[0];
+            dR[0 * 3 + 1] = 1.0;
+            dR[1 * 3 + 0] = -1.0;
+        }
+        for (int c = 0; c < 3; c++) {
+            v[c] = x[jj] * R[c];
+            for (int r = 0; r < 3; r++) dv[c * 3 + r] = (r == jj ? R[c] : 0.0) + x[jj] * dR[c * 3 + r];
+        }
+        return;
     }
     if (b < dim) { /* constants e_b */
         v[b] = 1.0;
@@ -694,47 +759,71 @@ static void vx_prebasis(int family, int dim, int b, const double *x, double *v, 
     dv[q * 3 + p] = 1.0;
 }
 
-/* moment a of the function f (given as a pre-basis index b) */
+/* the vertices of the facet opposite local vertex a, ascending local order */
+static int vx_facet(int dim, int a, int *iv)
+{
+    int m = 0;
+    for (int r = 0; r <= dim; r++)
+        if (r != a) iv[m++] = r;
+    return m;
+}
+
+/* moment a of the pre-basis function b */
 static double vx_moment(int family, int dim, int a, int b)
 {
     double gx[ORC_MAXQ1], gw[ORC_MAXQ1];
     double v[3], dv[9], p[3], xi[3], xj[3];
     double s = 0.0;
-    if (family == 1) {
+    int nedges = dim == 3 ? 6 : 3;
+    if (family == 1 || (family == 3 && a < 2 * nedges)) {
+        int e = family == 1 ? a : a / 2, slot = family == 1 ? -1 : a % 2;
         int i, j;
-        vx_edge(dim, a, &i, &j);
+        vx_edge(dim, e, &i, &j);
         vx_ref_vertex(dim, i, xi);
         vx_ref_vertex(dim, j, xj);
-        orc_gauss_legendre(2, gx, gw);
-        for (int q = 0; q < 2; q++) {
+        orc_gauss_legendre(3, gx, gw);
+        for (int q = 0; q < 3; q++) {
             for (int t = 0; t < dim; t++) p[t] = xi[t] + gx[q] * (xj[t] - xi[t]);
             vx_prebasis(family, dim, b, p, v, dv);
             double d = 0.0;
             for (int t = 0; t < dim; t++) d += v[t] * (xj[t] - xi[t]);
-            s += gw[q] * d;
+            double qv = slot < 0 ? 1.0 : slot == 0 ? 1.0 - gx[q] : gx[q];
+            s += gw[q] * d * qv;
         }
         return s;
     }
-    /* facet opposite vertex a */
-    int iv[3], m = 0;
-    for (int r = 0; r <= dim; r++)
-        if (r != a) iv[m++] = r;
+    if (family == 3 && dim == 2) { /* interior moments on the reference triangle */
+        int m = a - 6;
+        double qx[3 * 9], qw[9];
+        int nq = orc_sx_quadrature(2, 3, qx, qw);
+        for (int q = 0; q < nq; q++) {
+            vx_prebasis(family, dim, b, qx + 3 * q, v, dv);
+            s += qw[q] * v[m];
+        }
+        return s;
+    }
+    /* facet moments: family 2 (flux) or family 3 in 3D (tangents) */
+    int f = family == 2 ? a : (a - 12) / 2, slot = family == 2 ? -1 : (a - 12) % 2;
+    int iv[3];
+    vx_facet(dim, f, iv);
     double x0[3], x1[3], x2[3] = {0, 0, 0}, N[3];
     vx_ref_vertex(dim, iv[0], x0);
     vx_ref_vertex(dim, iv[1], x1);
     if (dim == 3) vx_ref_vertex(dim, iv[2], x2);
+    double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+    for (int t = 0; t < dim; t++) {
+        t1[t] = x1[t] - x0[t];
+        t2[t] = x2[t] - x0[t];
+    }
     if (dim == 2) {
-        N[0] = x1[1] - x0[1];
-        N[1] = -(x1[0] - x0[0]);
-    } else {
-        double t1[3], t2[3];
-        for (int t = 0; t < 3; t++) {
-            t1[t] = x1[t] - x0[t];
-            t2[t] = x2[t] - x0[t];
-        }
+        N[0] = t1[1];
+        N[1] = -t1[0];
+    } else if (slot < 0) {
         N[0] = t1[1] * t2[2] - t1[2] * t2[1];
         N[1] = t1[2] * t2[0] - t1[0] * t2[2];
         N[2] = t1[0] * t2[1] - t1[1] * t2[0];
+    } else {
+        for (int t = 0; t < 3; t++) N[t] = slot == 0 ? t1[t] : t2[t];
     }
     if (dim == 2) {
         orc_gauss_legendre(2, gx, gw);
@@ -758,9 +847,9 @@ static double vx_moment(int family, int dim, int a, int b)
 /* Change-of-basis matrix Phi (nd x nd) of the family.  Returns nd or -1. */
 int orc_vx_basis(int family, int dim, double *Phi)
 {
-    if ((family != 1 && family != 2) || dim < 2 || dim > 3) return -1;
+    if (family < 1 || family > 3 || dim < 2 || dim > 3) return -1;
     int nd = vx_ndof(family, dim);
-    double C[36], Ci[36];
+    double C[VX_MAXND * VX_MAXND], Ci[VX_MAXND * VX_MAXND];
     for (int a = 0; a < nd; a++)
         for (int b = 0; b < nd; b++) C[a * nd + b] = vx_moment(family, dim, a, b);
     if (sx_invert(nd, C, Ci) != 0) return -1;
@@ -799,14 +888,14 @@ static void vx_shape_with(int family, int dim, int nd, const double *Phi, const 
 /* Reference shape functions at xi (the family's basis; for tests). */
 int orc_vx_shape(int family, int dim, const double *xi, double *phi, double *curl, double *div)
 {
-    double Phi[36];
+    double Phi[VX_MAXND * VX_MAXND];
     int nd = orc_vx_basis(family, dim, Phi);
     if (nd < 0) return -1;
     vx_shape_with(family, dim, nd, Phi, xi, phi, curl, div);
     return nd;
 }
 
-/* Orientation signs of the local DOFs from the cell's global vertex ids. */
+/* Orientation signs of the lowest-order families' local DOFs. */
 static void vx_signs(int family, int dim, const int32_t *g, double *sgn)
 {
     int nd = vx_ndof(family, dim);
@@ -829,6 +918,56 @@ static void vx_signs(int family, int dim, const int32_t *g, double *sgn)
     }
 }
 
+/* T (nd x nd, row-major): local moments = T global moments, from the cell's
+ * global vertex ids. */
+static void vx_transform(int family, int dim, const int32_t *g, double *T)
+{
+    int nd = vx_ndof(family, dim);
+    memset(T, 0, sizeof(double) * nd * nd);
+    if (family != 3) {
+        double sgn[6];
+        vx_signs(family, dim, g, sgn);
+        for (int a = 0; a < nd; a++) T[a * nd + a] = sgn[a];
+        return;
+    }
+    int nedges = dim == 3 ? 6 : 3;
+    for (int e = 0; e < nedges; e++) {
+        int i, j, a = 2 * e;
+        vx_edge(dim, e, &i, &j);
+        if (g[i] < g[j]) {
+            T[a * nd + a] = 1.0;
+            T[(a + 1) * nd + a + 1] = 1.0;
+        } else { /* reversed: the two moments swap ends and change sign */
+            T[a * nd + a + 1] = -1.0;
+            T[(a + 1) * nd + a] = -1.0;
+        }
+    }
+    if (dim == 3) {
+        for (int f = 0; f < 4; f++) {
+            int iv[3], a = 12 + 2 * f;
+            vx_facet(dim, f, iv);
+            /* rank of each facet vertex in ascending global id */
+            int rank[3];
+            for (int x = 0; x < 3; x++) {
+                rank[x] = 0;
+                for (int y = 0; y < 3; y++)
+                    if (g[iv[y]] < g[iv[x]]) rank[x]++;
+            }
+            /* position of facet vertex x in the global frame: 0 -> (0,0), 1 -> (1,0), 2 -> (0,1) */
+            double P[3][2];
+            for (int x = 0; x < 3; x++) {
+                P[x][0] = rank[x] == 1 ? 1.0 : 0.0;
+                P[x][1] = rank[x] == 2 ? 1.0 : 0.0;
+            }
+            for (int m = 0; m < 2; m++)
+                for (int b = 0; b < 2; b++) T[(a + m) * nd + a + b] = P[m + 1][b] - P[0][b];
+        }
+    } else {
+        T[6 * nd + 6] = 1.0;
+        T[7 * nd + 7] = 1.0;
+    }
+}
+
 /* The family's manufactured field m(x): Nedelec 3D (sin pi y sin pi z,
  * sin pi z sin pi x, sin pi x sin pi y), 2D (sin pi y, sin pi x);
  * Raviart-Thomas (sin pi x_r)_r. */
@@ -848,45 +987,54 @@ static void vx_field(int family, int dim, const double *x, double *m)
     }
 }
 
-/* load f_c(x): kind 1 constant source[c], kind 2 source[c] m_c(x) */
+/* load f_c(x): kind 1 constant source[c], kind 2 source[c] m_c(x), kind 3
+ * affine: source[4c] + sum_r source[4c+1+r] x_r (source has 12 entries) */
 static void vx_source(int family, int dim, int kind, const double *src, const double *x, double *f)
 {
     double m[3] = {0, 0, 0};
     if (kind == 2) vx_field(family, dim, x, m);
-    for (int c = 0; c < dim; c++) f[c] = kind == 1 ? src[c] : kind == 2 ? src[c] * m[c] : 0.0;
+    for (int c = 0; c < dim; c++) {
+        if (kind == 3) {
+            f[c] = src[4 * c];
+            for (int r = 0; r < dim; r++) f[c] += src[4 * c + 1 + r] * x[r];
+        } else {
+            f[c] = kind == 1 ? src[c] : kind == 2 ? src[c] * m[c] : 0.0;
+        }
+    }
 }
 
 /* Element matrix and load of the form
- *   a(u, v) = int coef (curl u . curl v) + kappa u . v     (family 1)
+ *   a(u, v) = int coef (curl u . curl v) + kappa u . v     (families 1, 3)
  *   a(u, v) = int coef (div u div v) + kappa u . v         (family 2)
- * on a simplex with vertices X and global vertex ids g (for the signs),
- * by the collapsed rule with 1 + ceil(d/2) points per direction; physical
- * shape functions J^-T phi (family 1, curl J curl / det J in 3D, curl / det J
- * in 2D) or J phi / det J (family 2, div / det J).  A nd x nd, f nd. */
+ * on a simplex with vertices X and global vertex ids g (for the
+ * orientation), by the collapsed rule with order + ceil(d/2) points per
+ * direction; physical shape functions J^-T phi (curl J curl / det J in 3D,
+ * curl / det J in 2D) or J phi / det J (div / det J).  Returned in the global
+ * frame: T^T A T and T^T f.  A nd x nd, f nd. */
 int orc_vx_element(int family, int dim, const double *X, const int32_t *g, double coef, double kappa,
                    int source_kind, const double *source, double *A, double *f)
 {
     int nd = vx_ndof(family, dim);
-    int n = 1 + (dim + 1) / 2;
+    int n = vx_order(family) + (dim + 1) / 2;
     int nq = ipow(n, dim);
-    double qx[3 * 27], qw[27];
+    double *qx = (double *)malloc(sizeof(double) * 3 * nq), *qw = (double *)malloc(sizeof(double) * nq);
     orc_sx_quadrature(dim, n, qx, qw);
     double J[9], Ji[9];
     double det = sx_jacobian(dim, X, J, Ji);
-    double sgn[6], Phi[36];
-    vx_signs(family, dim, g, sgn);
+    double T[VX_MAXND * VX_MAXND], Phi[VX_MAXND * VX_MAXND], Al[VX_MAXND * VX_MAXND], fl[VX_MAXND];
+    vx_transform(family, dim, g, T);
     orc_vx_basis(family, dim, Phi);
-    memset(A, 0, sizeof(double) * nd * nd);
-    memset(f, 0, sizeof(double) * nd);
+    memset(Al, 0, sizeof(double) * nd * nd);
+    memset(fl, 0, sizeof(double) * nd);
     for (int q = 0; q < nq; q++) {
-        double phi[18], curl[18], div[6];
+        double phi[3 * VX_MAXND], curl[3 * VX_MAXND], div[VX_MAXND];
         vx_shape_with(family, dim, nd, Phi, qx + 3 * q, phi, curl, div);
-        double P[18], Cp[18], Dp[6]; /* physical values */
+        double P[3 * VX_MAXND], Cp[3 * VX_MAXND], Dp[VX_MAXND]; /* physical values */
         for (int a = 0; a < nd; a++) {
             for (int c = 0; c < dim; c++) {
                 double v = 0.0;
                 for (int r = 0; r < dim; r++)
-                    v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;
+                    v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;
                 P[a * dim + c] = v;
             }
             if (dim == 3) {
@@ -912,63 +1060,83 @@ int orc_vx_element(int family, int dim, const double *X, const int32_t *g, doubl
         for (int a = 0; a < nd; a++) {
             double fa = 0.0;
             for (int c = 0; c < dim; c++) fa += fx[c] * P[a * dim + c];
-            f[a] += wd * fa;
+            fl[a] += wd * fa;
             for (int b = 0; b < nd; b++) {
                 double st = 0.0, ms = 0.0;
-                if (family == 1)
+                if (family != 2)
                     for (int c = 0; c < nc; c++) st += Cp[a * nc + c] * Cp[b * nc + c];
                 else
                     st = Dp[a] * Dp[b];
                 for (int c = 0; c < dim; c++) ms += P[a * dim + c] * P[b * dim + c];
-                A[a * nd + b] += wd * (coef * st + kappa * ms);
+                Al[a * nd + b] += wd * (coef * st + kappa * ms);
             }
         }
     }
-    for (int a = 0; a < nd; a++) {
-        f[a] *= sgn[a];
-        for (int b = 0; b < nd; b++) A[a * nd + b] *= sgn[a] * sgn[b];
+    free(qx);
+    free(qw);
+    /* to the global frame: A = T^T Al T, f = T^T fl */
+    for (int b = 0; b < nd; b++) {
+        double s = 0.0;
+        for (int a = 0; a < nd; a++) s += T[a * nd + b] * fl[a];
+        f[b] = s;
+        for (int d = 0; d < nd; d++) {
+            double v = 0.0;
+            for (int a = 0; a < nd; a++)
+                for (int c = 0; c < nd; c++) v += T[a * nd + b] * Al[a * nd + c] * T[c * nd + d];
+            A[b * nd + d] = v;
+        }
     }
     return det == 0.0 ? -1 : 0;
 }
 
-/* Numbering of the DOF entities (edges for family 1, facets for family 2):
- * ids by first appearance over (cell, local DOF); dirichlet != 0 fixes the
- * entities on the boundary (facets of one cell, and their edges).
- * dof_of[K*nd + a], code[entity] as orc_sx_number.  Returns 0, -1, -2. */
+/* Numbering of the DOFs (an edge's, a facet's, or -- family 3 in 2D -- a
+ * cell's interior ones): a DOF is named by its entity's sorted vertex ids
+ * and its slot in the entity's global frame; ids by first appearance over
+ * (cell, local DOF); dirichlet != 0 fixes the DOFs of entities on the
+ * boundary (facets of one cell, and their edges).  dof_of[K*nd + a],
+ * code[dof] as orc_sx_number.  Returns 0, -1, -2. */
 int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int32_t *cells, int dirichlet,
                   int64_t *dof_of, int64_t *code, int64_t *nent_out, int64_t *nfree_out, int64_t *nfixed_out)
 {
-    if ((family != 1 && family != 2) || dim < 2 || dim > 3) return -1;
-    int nd = vx_ndof(family, dim), nv = dim + 1;
+    if (family < 1 || family > 3 || dim < 2 || dim > 3) return -1;
+    int nd = vx_ndof(family, dim), nv = dim + 1, nedges = dim == 3 ? 6 : 3;
     for (int64_t t = 0; t < ncells * nv; t++)
         if (cells[t] < 0 || cells[t] >= nverts) return -1;
-    /* entity keys as sx_facet records (vertex triple, padded) */
     int64_t nrec = ncells * nd;
-    sx_facet *rec = (sx_facet *)malloc(sizeof(sx_facet) * (nrec > 0 ? nrec : 1));
+    sx_occ *rec = (sx_occ *)malloc(sizeof(sx_occ) * (nrec > 0 ? nrec : 1));
     for (int64_t K = 0; K < ncells; K++)
         for (int a = 0; a < nd; a++) {
-            sx_facet *r = rec + K * nd + a;
-            int m = 0;
-            if (family == 1) {
+            sx_occ *r = rec + K * nd + a;
+            const int32_t *g = cells + K * nv;
+            int m = 0, slot = 0;
+            if (family == 1 || (family == 3 && a < 2 * nedges)) {
                 int i, j;
-                vx_edge(dim, a, &i, &j);
-                r->v[m++] = cells[K * nv + i];
-                r->v[m++] = cells[K * nv + j];
+                vx_edge(dim, family == 1 ? a : a / 2, &i, &j);
+                r->v[m++] = g[i];
+                r->v[m++] = g[j];
+                slot = family == 1 ? 0 : a % 2;
+            } else if (family == 3 && dim == 2) { /* interior: the cell's vertices */
+                for (int t = 0; t < nv; t++) r->v[m++] = g[t];
+                slot = a - 6;
             } else {
-                for (int t = 0; t < nv; t++)
-                    if (t != a) r->v[m++] = cells[K * nv + t];
+                int iv[3];
+                vx_facet(dim, family == 2 ? a : (a - 12) / 2, iv);
+                for (int t = 0; t < dim; t++) r->v[m++] = g[iv[t]];
+                slot = family == 2 ? 0 : (a - 12) % 2;
             }
             sx_sort_small(r->v, NULL, m);
-            for (int t = m; t < 3; t++) r->v[t] = INT32_MAX;
+            for (int t = m; t < 4; t++) r->v[t] = INT32_MAX;
+            r->w[0] = slot;
+            r->w[1] = r->w[2] = r->w[3] = 0;
             r->cell = K;
-            r->j = a;
+            r->a = a;
         }
-    qsort(rec, nrec, sizeof(sx_facet), sx_facet_cmp);
+    qsort(rec, nrec, sizeof(sx_occ), sx_occ_cmp);
     sx_first *first_of = (sx_first *)malloc(sizeof(sx_first) * (nrec > 0 ? nrec : 1));
     int64_t ng = 0;
     for (int64_t t = 0; t < nrec; t++)
-        if (t == 0 || memcmp(rec[t].v, rec[t - 1].v, sizeof(rec[t].v)) != 0) {
-            first_of[ng].first = rec[t].cell * nd + rec[t].j;
+        if (t == 0 || memcmp(rec[t].v, rec[t - 1].v, sizeof(rec[t].v)) != 0 || rec[t].w[0] != rec[t - 1].w[0]) {
+            first_of[ng].first = rec[t].cell * nd + rec[t].a;
             first_of[ng].group = t;
             ng++;
         }
@@ -976,9 +1144,9 @@ int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int
     for (int64_t g2 = 0; g2 < ng; g2++) {
         int64_t t = first_of[g2].group;
         do {
-            dof_of[rec[t].cell * nd + rec[t].j] = g2;
+            dof_of[rec[t].cell * nd + rec[t].a] = g2;
             t++;
-        } while (t < nrec && memcmp(rec[t].v, rec[t - 1].v, sizeof(rec[t].v)) == 0);
+        } while (t < nrec && memcmp(rec[t].v, rec[t - 1].v, sizeof(rec[t].v)) == 0 && rec[t].w[0] == rec[t - 1].w[0]);
     }
     free(first_of);
     free(rec);
@@ -1010,10 +1178,14 @@ int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int
                 int on;
                 if (family == 2) {
                     on = a == j;
-                } else {
+                } else if (family == 1 || a < 2 * nedges) {
                     int i1, j1;
-                    vx_edge(dim, a, &i1, &j1);
+                    vx_edge(dim, family == 1 ? a : a / 2, &i1, &j1);
                     on = i1 != j && j1 != j; /* the edge avoids the opposite vertex */
+                } else if (dim == 3) {
+                    on = (a - 12) / 2 == j;
+                } else {
+                    on = 0; /* interior */
                 }
                 if (on) bnd[dof_of[K * nd + a]] = 1;
             }
@@ -1039,7 +1211,7 @@ int orc_vx_assemble(int family, int dim, const double *vxyz, int64_t ncells, con
     int nd = vx_ndof(family, dim), nv = dim + 1;
     memset(values, 0, sizeof(double) * rowptr[nfree]);
     memset(rhs, 0, sizeof(double) * nfree);
-    double A[36], f[6], X[12];
+    double A[VX_MAXND * VX_MAXND], f[VX_MAXND], X[12];
     int bad = 0;
     for (int64_t K = 0; K < ncells; K++) {
         sx_cell_vertices(dim, cells, vxyz, K, X);
@@ -1066,25 +1238,31 @@ double orc_vx_l2_error(int family, int dim, const double *vxyz, int64_t ncells, 
     int nq = ipow(nq1, dim);
     double *qx = (double *)malloc(sizeof(double) * 3 * nq), *qw = (double *)malloc(sizeof(double) * nq);
     orc_sx_quadrature(dim, nq1, qx, qw);
-    double X[12], J[9], Ji[9], err2 = 0.0, Phi[36];
+    double X[12], J[9], Ji[9], err2 = 0.0, Phi[VX_MAXND * VX_MAXND], T[VX_MAXND * VX_MAXND];
     orc_vx_basis(family, dim, Phi);
     for (int64_t K = 0; K < ncells; K++) {
         sx_cell_vertices(dim, cells, vxyz, K, X);
         double det = sx_jacobian(dim, X, J, Ji);
-        double sgn[6], u[6];
-        vx_signs(family, dim, cells + K * nv, sgn);
+        double ug[VX_MAXND], u[VX_MAXND];
+        vx_transform(family, dim, cells + K * nv, T);
         for (int a = 0; a < nd; a++) {
             int64_t gd = cell_dofs[K * nd + a];
-            u[a] = gd >= 0 ? sgn[a] * x[gd] : 0.0;
+            ug[a] = gd >= 0 ? x[gd] : 0.0;
+        }
+        /* local coefficients u = T ug */
+        for (int a = 0; a < nd; a++) {
+            double s = 0.0;
+            for (int b = 0; b < nd; b++) s += T[a * nd + b] * ug[b];
+            u[a] = s;
         }
         for (int q = 0; q < nq; q++) {
-            double phi[18], curl[18], div[6], uh[3] = {0, 0, 0}, p[3], m[3];
+            double phi[3 * VX_MAXND], curl[3 * VX_MAXND], div[VX_MAXND], uh[3] = {0, 0, 0}, p[3], m[3];
             vx_shape_with(family, dim, nd, Phi, qx + 3 * q, phi, curl, div);
             for (int a = 0; a < nd; a++)
                 for (int c = 0; c < dim; c++)
                     for (int r = 0; r < dim; r++) {
                         /* covariant J^-T phi, or contravariant J phi / det J */
-                        double m1 = family == 1 ? Ji[r * dim + c] : J[c * dim + r] / det;
+                        double m1 = family != 2 ? Ji[r * dim + c] : J[c * dim + r] / det;
                         uh[c] += u[a] * m1 * phi[a * dim + r];
                     }
             for (int r = 0; r < dim; r++) {

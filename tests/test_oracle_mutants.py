@@ -68,15 +68,20 @@ MUTANTS = {
     "vector_edge_orientation_ignored": ("sgn[a] = g[i] < g[j] ? 1.0 : -1.0;", "sgn[a] = 1.0;"),
     "vector_facet_orientation_ignored": ("sgn[a] = (inv % 2) ? -1.0 : 1.0;", "sgn[a] = 1.0;"),
     "vector_covariant_map_untransposed": (
-        "v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
-        "v += family == 1 ? Ji[c * dim + r] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;"),
+        "v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
+        "v += family != 2 ? Ji[c * dim + r] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;"),
     "vector_contravariant_map_without_det": (
-        "v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
-        "v += family == 1 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r];"),
+        "v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
+        "v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r];"),
     "vector_curl_map_without_det": ("Cp[a * 3 + c] = v / det;", "Cp[a * 3 + c] = v;"),
     "vector_edge_tangent_reversed": ("d += v[t] * (xj[t] - xi[t]);", "d += v[t] * (xi[t] - xj[t]);"),
     "vector_boundary_edge_test": ("on = i1 != j && j1 != j;", "on = i1 != j || j1 != j;"),
-    "vector_mass_without_kappa": ("A[a * nd + b] += wd * (coef * st + kappa * ms);", "A[a * nd + b] += wd * (coef * st + ms);"),
+    "vector_mass_without_kappa": ("Al[a * nd + b] += wd * (coef * st + kappa * ms);", "Al[a * nd + b] += wd * (coef * st + ms);"),
+    "nedelec2_edge_reversal_sign": ("T[a * nd + a + 1] = -1.0;", "T[a * nd + a + 1] = 1.0;"),
+    "nedelec2_edge_weights_swapped": ("double qv = slot < 0 ? 1.0 : slot == 0 ? 1.0 - gx[q] : gx[q];",
+                                      "double qv = slot < 0 ? 1.0 : slot == 0 ? gx[q] : 1.0 - gx[q];"),
+    "nedelec2_face_block_transposed": ("T[(a + m) * nd + a + b] = P[m + 1][b] - P[0][b];",
+                                       "T[(a + b) * nd + a + m] = P[m + 1][b] - P[0][b];"),
     "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                   "err2 += w * (ue - uh) * (ue - uh);"),
 }
@@ -117,6 +122,9 @@ PIN_CALLS = [
     lambda: VX.test_constant_field_patch_test("nedelec", 3),
     lambda: VX.test_constant_field_patch_test("raviart_thomas", 3),
     lambda: VX.test_l2_convergence_to_manufactured_field("nedelec", 2, (8, 16)),
+    lambda: VX.test_nedelec2_interpolates_its_space_exactly(3),
+    lambda: VX.test_nedelec2_linear_curl_free_patch_test(3, 2),
+    lambda: VX.test_nedelec2_curl_curl_annihilates_gradients_of_p2(3, 2),
 ]
 
 

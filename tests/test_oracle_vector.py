@@ -256,3 +256,194 @@ def test_boundary_dofs_and_definiteness(family, dim):
     A = S.scipy().toarray()
     assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
     assert np.linalg.eigvalsh(A).min() > 0
+
+
+# ---------------------------------------------------------------------------
+# second-order Nedelec ("nedelec2"): two DOFs per edge and per face (3D), two
+# interior DOFs (2D), local moments = T global moments with 2 x 2 blocks
+# ---------------------------------------------------------------------------
+def _gl(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 + 0.5 * x, 0.5 * w
+
+
+def _tri_rule():
+    """A degree-4 rule on the reference triangle (collapsed Gauss, numpy)."""
+    x, w = _gl(4)
+    pts, wts = [], []
+    for i in range(4):
+        for j in range(4):
+            pts.append((x[i], (1 - x[i]) * x[j]))
+            wts.append(w[i] * w[j] * (1 - x[i]))
+    return np.array(pts), np.array(wts)
+
+
+def edge_moments(u, xa, xb):
+    """int_0^1 u(xa + t (xb - xa)) . (xb - xa) q_s(t) dt for q_0 = 1 - t, q_1 = t."""
+    x, w = _gl(4)
+    out = np.zeros(2)
+    for t, wt in zip(x, w):
+        d = u(xa + t * (xb - xa)) @ (xb - xa)
+        out += wt * d * np.array([1 - t, t])
+    return out
+
+
+def face_moments(u, x0, x1, x2):
+    """int over the reference triangle of u(x0 + s0 t0 + s1 t1) . t_m ds."""
+    t0, t1 = x1 - x0, x2 - x0
+    P, W = _tri_rule()
+    out = np.zeros(2)
+    for (s0, s1), w in zip(P, W):
+        val = u(x0 + s0 * t0 + s1 * t1)
+        out += w * np.array([val @ t0, val @ t1])
+    return out
+
+
+def reference_moments(u, dim):
+    """The second-order Nedelec moments of u on the reference simplex in the
+    local frame (edges, faces or interior, in the element's DOF order)."""
+    X = REF[dim]
+    out = []
+    for i, j in EDGES[dim]:
+        out += list(edge_moments(u, X[i], X[j]))
+    if dim == 3:
+        for f in range(4):
+            iv = [r for r in range(4) if r != f]
+            out += list(face_moments(u, X[iv[0]], X[iv[1]], X[iv[2]]))
+    else:
+        P, W = _tri_rule()
+        out += list(sum(w * u(np.array(p)) for p, w in zip(P, W)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nedelec2_interpolates_its_space_exactly(dim):
+    """The interpolant sum_a sigma_a(v) phi_a reproduces fields of the space:
+    random affine fields ([P_1]^d) and the quadratic fields x_m (x x e_i)
+    (3D) or x_m (-y, x) (2D) orthogonal to x."""
+    g = rng(21)
+    fields = []
+    for _ in range(3):
+        B, c = g.standard_normal((dim, dim)), g.standard_normal(dim)
+        fields.append(lambda x, B=B, c=c: B @ x + c)
+    if dim == 3:
+        for i in range(3):
+            for m in range(3):
+                e = np.eye(3)[i]
+                fields.append(lambda x, e=e, m=m: x[m] * np.cross(x, e))
+    else:
+        for m in range(2):
+            fields.append(lambda x, m=m: x[m] * np.array([-x[1], x[0]]))
+    for u in fields:
+        sig = reference_moments(u, dim)
+        for _ in range(4):
+            xi = g.dirichlet(np.ones(dim + 1))[:dim]
+            phi, _, _ = O.vector_shape("nedelec2", dim, xi)
+            np.testing.assert_allclose(sig @ phi, u(xi), atol=1e-12)
+
+
+def _global_moments(u, v, c, S, dim):
+    """Global-frame DOF values of the field u on the mesh (fixed DOFs dropped):
+    edges lower -> higher id, faces over their vertices in ascending id; the
+    2D interior moments of the covariant pull-back J^T u on the reference cell."""
+    vals = np.full(S.nent, np.nan)
+    for K, row in enumerate(S.dof_of):
+        gids = c[K]
+        for e, (i, j) in enumerate(EDGES[dim]):
+            lo, hi = sorted((int(gids[i]), int(gids[j])))
+            vals[row[2 * e:2 * e + 2]] = edge_moments(u, v[lo], v[hi])
+        if dim == 3:
+            for f in range(4):
+                ids = sorted(int(gids[r]) for r in range(4) if r != f)
+                vals[row[12 + 2 * f:14 + 2 * f]] = face_moments(u, v[ids[0]], v[ids[1]], v[ids[2]])
+        else:
+            X = v[gids]
+            J = (X[1:] - X[0]).T
+            P, W = _tri_rule()
+            vals[row[6:8]] = sum(w * (J.T @ u(X[0] + J @ np.array(p))) for p, w in zip(P, W))
+    return vals
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (3, 2)])
+def test_nedelec2_linear_curl_free_patch_test(dim, n):
+    """u = B x + c with B symmetric has no curl, so curl curl u + kappa u =
+    kappa u and the natural boundary condition holds: the discrete solution
+    is u's interpolant, exactly, on jittered shuffled meshes."""
+    v, c = simplex_mesh(dim, n, jitter=0.2, shuffle=True)
+    g = rng(22)
+    B = g.standard_normal((dim, dim))
+    B = B + B.T
+    cv = g.standard_normal(dim)
+    kappa = 2.5
+    aff = []
+    for comp in range(dim):
+        aff += [kappa * cv[comp]] + list(kappa * B[comp]) + [0.0] * (3 - dim)
+    S = O.VectorSystem("nedelec2", dim, v, c, kappa=kappa, source_kind=3, source=aff, dirichlet=False)
+    x = S.solve()
+    exact = _global_moments(lambda p: B @ p + cv, v, c, S, dim)
+    assert np.abs(x - exact).max() <= 1e-10 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (3, 2)])
+def test_nedelec2_curl_curl_annihilates_gradients_of_p2(dim, n):
+    """Gradients of the global P2 Lagrange functions lie in the second-order
+    Nedelec space; the curl-curl matrix (kappa = 0, no boundary DOFs fixed)
+    times the matrix of their global-frame moments vanishes -- only if every
+    cell maps shared edge and face DOFs to the global frame alike."""
+    v, c = simplex_mesh(dim, n, jitter=0.2, shuffle=True)
+    S = O.VectorSystem("nedelec2", dim, v, c, kappa=0.0, dirichlet=False)
+    node_of, code, _, _ = O.simplex_number(dim, 2, len(v), c, dirichlet=False)
+    nnodes = len(code)
+    G = np.zeros((S.nent, nnodes))
+    for K in range(c.shape[0]):
+        X = v[c[K]]
+        J = (X[1:] - X[0]).T
+        Ji = np.linalg.inv(J)
+        for ln in range(node_of.shape[1]):
+            def grad(p, ln=ln):
+                xi = Ji @ (p - X[0])
+                _, d = O.simplex_shape(dim, 2, xi)
+                return Ji.T @ d[ln]
+            col = _global_moments_cell(grad, v, c, S, dim, K)
+            for pos, val in col.items():
+                G[pos, node_of[K, ln]] = val
+    A = S.scipy()
+    assert np.abs(G).max() > 0.1 and np.abs(A @ np.ones(S.nent)).max() > 1e-3  # neither side is trivial
+    assert np.abs(A @ G).max() <= 1e-10 * np.abs(S.values).max()
+
+
+def _global_moments_cell(u, v, c, S, dim, K):
+    """Global-frame moments of u over the edges and faces of cell K (the
+    interior DOFs of a 2D cell: the pull-back moments on the reference cell)."""
+    out = {}
+    gids = c[K]
+    row = S.dof_of[K]
+    for e, (i, j) in enumerate(EDGES[dim]):
+        lo, hi = sorted((int(gids[i]), int(gids[j])))
+        m = edge_moments(u, v[lo], v[hi])
+        out[row[2 * e]], out[row[2 * e + 1]] = m
+    if dim == 3:
+        for f in range(4):
+            ids = sorted(int(gids[r]) for r in range(4) if r != f)
+            m = face_moments(u, v[ids[0]], v[ids[1]], v[ids[2]])
+            out[row[12 + 2 * f]], out[row[13 + 2 * f]] = m
+    else:
+        X = v[gids]
+        J = (X[1:] - X[0]).T
+        P, W = _tri_rule()
+        m = sum(w * (J.T @ u(X[0] + J @ np.array(p))) for p, w in zip(P, W))
+        out[row[6]], out[row[7]] = m
+    return out
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (4, 8)), (3, (2, 4))])
+def test_nedelec2_second_order_convergence(dim, ns):
+    kappa = 1.0
+    lap = (2.0 if dim == 3 else 1.0) * math.pi ** 2
+    errs = []
+    for n in ns:
+        v, c = simplex_mesh(dim, n, jitter=0.15)
+        S = O.VectorSystem("nedelec2", dim, v, c, kappa=kappa, source_kind=2, source=[lap + kappa] * dim)
+        errs.append(S.l2_error(S.solve(), 1.0, nq1=5))
+    rate = math.log(errs[0] / errs[1]) / math.log(ns[1] / ns[0])
+    assert 1.7 <= rate <= 2.5, (errs, rate)
