@@ -426,9 +426,19 @@ fe_status fe_simplex_destroy(fe_simplex s);
  * numbered by first appearance over (cell, local DOF); local DOFs are the
  * edges (0,1),(0,2),(1,2) [2D] or (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) [3D],
  * or the facets by their opposite vertex.  The other fe_simplex_* calls
- * apply (one DOF per entity: n_nodes counts the entities).  FE_EINVAL for
- * kappa < 0 or an unknown family; mesh errors as fe_simplex_create. */
-enum { FE_NEDELEC = 1, FE_RAVIART_THOMAS = 2 };
+ * apply (n_nodes counts the DOFs).  FE_NEDELEC2: the second-order Nedelec
+ * element ([P_1]^d plus the quadratic fields orthogonal to x): two moments
+ * per edge (against 1 - t and t from its first vertex), two per face against
+ * the face's edge tangents x_i1 - x_i0, x_i2 - x_i0 (3D), two interior
+ * moments on the reference triangle (2D); local DOF order: the edges' pairs,
+ * then the faces' (3D) or the interior pair (2D).  A DOF's global frame is its
+ * entity's vertices in ascending global id; the cell's local moments are T
+ * times the global ones with a 2 x 2 block per edge (identity, or swapped and
+ * negated) and per face (the local tangents in the global ones), and the
+ * element matrix and load are returned in the global frame (T^T A T, T^T f).
+ * FE_EINVAL for kappa < 0 or an unknown family; mesh errors as
+ * fe_simplex_create. */
+enum { FE_NEDELEC = 1, FE_RAVIART_THOMAS = 2, FE_NEDELEC2 = 3 };
 fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, double kappa, const fe_coeff *coeff,
                                    fe_simplex *out);
 

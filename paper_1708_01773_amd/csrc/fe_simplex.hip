@@ -467,6 +467,253 @@ __global__ __launch_bounds__(256) void sx_vector_kernel(SxArgs sa, double kappa,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Second-order Nedelec elements (family 3): two DOFs per edge (moments
+// against 1 - t and t), two per face (against the face's two edge
+// tangents, 3D) and two interior ones (2D).  The cell's local moments are T
+// times the moments in the global frame (edges from the lower to the higher
+// global vertex id, faces over their vertices in ascending id): a 2 x 2 block
+// per edge (identity, or the two DOFs swapped and negated) and per face (the
+// local tangents expressed in the global ones).  The cell's matrix in the
+// global frame is T^T A T and its load T^T f; A's entries are contractions
+// of the cell's stiffness and mass tensors with the reference products, as
+// for the lowest order, so every global entry is a sum of at most four.
+template <int DIM>
+struct Sxn2Shape {
+    static constexpr int ND = DIM == 3 ? 20 : 8;
+    static constexpr int NB = ND / 2;  // 2 x 2 blocks
+    static constexpr int NTRI = ND * (ND + 1) / 2;
+    static constexpr int NPS = DIM == 3 ? 6 : 1;
+    static constexpr int NPM = DIM * (DIM + 1) / 2;
+    static constexpr int NP = NPS + NPM;
+    static constexpr int NQ1 = 2 + (DIM + 1) / 2;
+    static constexpr int NQ = DIM == 3 ? NQ1 * NQ1 * NQ1 : NQ1 * NQ1;
+    static constexpr int CPB = DIM == 3 ? 8 : 32;
+};
+
+template <int DIM>
+__global__ __launch_bounds__(256) void sx_nedelec2_kernel(SxArgs sa, double kappa, const double *__restrict__ vxyz,
+                                                          const int32_t *__restrict__ cells,
+                                                          const double *__restrict__ coef,
+                                                          const double *__restrict__ tab,
+                                                          const int32_t *__restrict__ tri,
+                                                          const double *__restrict__ phq,
+                                                          const double *__restrict__ qxw, double *__restrict__ E,
+                                                          double *__restrict__ F)
+{
+    using S = Sxn2Shape<DIM>;
+    constexpr int NV = DIM + 1;
+    __shared__ double sTab[S::NP * S::NTRI];
+    __shared__ int32_t sTri[S::NTRI];
+    __shared__ double sC[S::CPB][S::NP];
+    __shared__ double sT[S::CPB][S::NB][4];  // block entries T(2B + x, 2B + y) at [x * 2 + y]
+    __shared__ double sX[S::CPB][NV * DIM];
+    __shared__ double sM[S::CPB][DIM * DIM];
+    __shared__ double sDet[S::CPB];
+    __shared__ double sG[S::CPB][S::NQ][DIM];
+    const int tid = threadIdx.x;
+    const int64_t K0 = xcd_block(blockIdx.x, gridDim.x) * S::CPB;
+    const int ncl = sa.ncells - K0 < S::CPB ? int(sa.ncells - K0) : S::CPB;
+    for (int t = tid; t < S::NP * S::NTRI; t += blockDim.x) sTab[t] = tab[t];
+    for (int t = tid; t < S::NTRI; t += blockDim.x) sTri[t] = tri[t];
+    for (int c = tid; c < ncl; c += blockDim.x) {
+        const int64_t Kc = K0 + c;
+        int32_t g[NV];
+        double X[NV][DIM];
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            g[j] = cells[Kc * NV + j];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) X[j][r] = vxyz[int64_t(g[j]) * DIM + r];
+        }
+        double J[DIM][DIM], Ji[DIM][DIM], det;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) J[r][s] = X[s + 1][r] - X[0][r];
+        if constexpr (DIM == 2) {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double id = 1.0 / det;
+            Ji[0][0] = J[1][1] * id;
+            Ji[0][1] = -J[0][1] * id;
+            Ji[1][0] = -J[1][0] * id;
+            Ji[1][1] = J[0][0] * id;
+        } else {
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+            const double id = 1.0 / det;
+            Ji[0][0] = c00 * id;
+            Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+            Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+            Ji[1][0] = c01 * id;
+            Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+            Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+            Ji[2][0] = c02 * id;
+            Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+            Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        }
+        const double ad = fabs(det), k = coef ? coef[Kc] : 1.0;
+        if constexpr (DIM == 3) {
+            int p = 0;
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int s = r; s < 3; s++) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int l = 0; l < 3; l++) v += J[l][r] * J[l][s];
+                    sC[c][p++] = k / ad * v;
+                }
+        } else {
+            sC[c][0] = k / ad;
+        }
+        int p = S::NPS;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = r; s < DIM; s++) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < DIM; l++) v += Ji[r][l] * Ji[s][l];
+                sC[c][p++] = kappa * ad * v;
+            }
+        // frame blocks: edges
+        constexpr int NE = DIM == 3 ? 6 : 3;
+#pragma unroll
+        for (int e = 0; e < NE; e++) {
+            const int i = DIM == 3 ? (e < 3 ? 0 : e < 5 ? 1 : 2) : (e < 2 ? 0 : 1);
+            const int j = DIM == 3 ? (e < 3 ? e + 1 : e < 5 ? e - 1 : 3) : (e < 2 ? e + 1 : 2);
+            const bool fwd = g[i] < g[j];
+            sT[c][e][0] = fwd ? 1.0 : 0.0;
+            sT[c][e][1] = fwd ? 0.0 : -1.0;
+            sT[c][e][2] = fwd ? 0.0 : -1.0;
+            sT[c][e][3] = fwd ? 1.0 : 0.0;
+        }
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                int iv[3], m = 0;
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    if (r != f) iv[m++] = r;
+                double P[3][2];
+#pragma unroll
+                for (int x = 0; x < 3; x++) {
+                    int rank = 0;
+#pragma unroll
+                    for (int y = 0; y < 3; y++) rank += g[iv[y]] < g[iv[x]];
+                    P[x][0] = rank == 1 ? 1.0 : 0.0;
+                    P[x][1] = rank == 2 ? 1.0 : 0.0;
+                }
+#pragma unroll
+                for (int mm = 0; mm < 2; mm++)
+#pragma unroll
+                    for (int b = 0; b < 2; b++) sT[c][NE + f][mm * 2 + b] = P[mm + 1][b] - P[0][b];
+            }
+        } else {
+            sT[c][NE][0] = 1.0;
+            sT[c][NE][1] = 0.0;
+            sT[c][NE][2] = 0.0;
+            sT[c][NE][3] = 1.0;
+        }
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) sM[c][r * DIM + s] = Ji[r][s];
+#pragma unroll
+        for (int j = 0; j < NV; j++)
+#pragma unroll
+            for (int r = 0; r < DIM; r++) sX[c][j * DIM + r] = X[j][r];
+        sDet[c] = ad;
+    }
+    __syncthreads();
+    if (sa.source_kind != FE_SOURCE_NONE)
+        for (int e = tid; e < ncl * S::NQ; e += blockDim.x) {
+            const int c = e / S::NQ, q = e - c * S::NQ;
+            double x[DIM], f[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) {
+                x[r] = sX[c][r];
+#pragma unroll
+                for (int t = 0; t < DIM; t++) x[r] += (sX[c][(t + 1) * DIM + r] - sX[c][r]) * qxw[q * (DIM + 1) + t];
+            }
+            if (sa.source_kind == FE_SOURCE_SINPROD) {
+                double sn[DIM], m[DIM];
+#pragma unroll
+                for (int r = 0; r < DIM; r++) sn[r] = sin(M_PI * x[r]);
+                if constexpr (DIM == 2) {
+                    m[0] = sn[1];
+                    m[1] = sn[0];
+                } else {
+                    m[0] = sn[1] * sn[2];
+                    m[1] = sn[2] * sn[0];
+                    m[2] = sn[0] * sn[1];
+                }
+#pragma unroll
+                for (int r = 0; r < DIM; r++) f[r] = sa.source[r] * m[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < DIM; r++) f[r] = sa.source[r];
+            }
+            const double w = qxw[q * (DIM + 1) + DIM] * sDet[c];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) {
+                double v = 0.0;
+#pragma unroll
+                for (int t = 0; t < DIM; t++) v += sM[c][r * DIM + t] * f[t];
+                sG[c][q][r] = w * v;
+            }
+        }
+    __syncthreads();
+    auto local_entry = [&](int c, int a, int b) {
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        const int t = lo * S::ND - lo * (lo - 1) / 2 + (hi - lo);
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < S::NP; p++) v = __fma_rn(sC[c][p], sTab[p * S::NTRI + t], v);
+        return v;
+    };
+    for (int e = tid; e < ncl * S::NTRI; e += blockDim.x) {
+        const int c = e / S::NTRI, t = e - c * S::NTRI;
+        const int I = sTri[t] >> 16, Jx = sTri[t] & 0xffff;
+        const int bI = I >> 1, rI = I & 1, bJ = Jx >> 1, rJ = Jx & 1;
+        double v = 0.0;
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            const double tI = sT[c][bI][x * 2 + rI];
+            if (tI == 0.0) continue;
+#pragma unroll
+            for (int y = 0; y < 2; y++) {
+                const double tJ = sT[c][bJ][y * 2 + rJ];
+                if (tJ == 0.0) continue;
+                v += tI * tJ * local_entry(c, 2 * bI + x, 2 * bJ + y);
+            }
+        }
+        E[(K0 + c) * S::NTRI + t] = v;
+    }
+    for (int e = tid; e < ncl * S::ND; e += blockDim.x) {
+        const int c = e / S::ND, I = e - c * S::ND;
+        const int bI = I >> 1, rI = I & 1;
+        double f = 0.0;
+        if (sa.source_kind != FE_SOURCE_NONE)
+#pragma unroll
+            for (int x = 0; x < 2; x++) {
+                const double tI = sT[c][bI][x * 2 + rI];
+                if (tI == 0.0) continue;
+                const int a = 2 * bI + x;
+                double fl = 0.0;
+                for (int q = 0; q < S::NQ; q++)
+#pragma unroll
+                    for (int r = 0; r < DIM; r++) fl = __fma_rn(sG[c][q][r], phq[(q * S::ND + a) * DIM + r], fl);
+                f += tI * fl;
+            }
+        F[(K0 + c) * S::ND + I] = f;
+    }
+}
+
 // values[j] = sum of E over the contributions of entry j, in list order.
 __global__ __launch_bounds__(256) void sx_gather_kernel(int64_t nnz, const int64_t *__restrict__ gptr,
                                                         const uint32_t *__restrict__ gsrc,
@@ -978,31 +1225,64 @@ fe_status sx_setup(fe_simplex S, const int32_t *cells, const double *vxyz)
     return sx_finish(S, pre, nnodes, bnd);
 }
 
-// Entities of the vector families: edges (family 1) or facets (family 2)
-// named by their sorted vertex keys, ids by first appearance over (cell,
-// local DOF); boundary entities lie on a facet of one cell.
+// Local DOF a of a vector family: its entity kind (0 edge, 1 facet, 2 the
+// cell's interior), the entity's local index and the DOF's slot in it.
+void sxv_dof(int fam, int dim, int a, int &kind, int &ent, int &slot)
+{
+    const int ne = dim == 3 ? 6 : 3;
+    if (fam == 1) {
+        kind = 0, ent = a, slot = 0;
+    } else if (fam == 2) {
+        kind = 1, ent = a, slot = 0;
+    } else if (a < 2 * ne) {
+        kind = 0, ent = a / 2, slot = a % 2;
+    } else if (dim == 3) {
+        kind = 1, ent = (a - 12) / 2, slot = (a - 12) % 2;
+    } else {
+        kind = 2, ent = 0, slot = a - 6;
+    }
+}
+
+void sxv_edge(int dim, int e, int &i, int &j)
+{
+    i = dim == 3 ? (e < 3 ? 0 : e < 5 ? 1 : 2) : (e < 2 ? 0 : 1);
+    j = dim == 3 ? (e < 3 ? e + 1 : e < 5 ? e - 1 : 3) : (e < 2 ? e + 1 : 2);
+}
+
+// DOF entities of the vector families: a DOF is named by its entity's sorted
+// vertex ids (an edge's, a facet's, or for the interior DOFs of a 2D cell the
+// cell's) and its slot; ids by first appearance over (cell, local DOF);
+// boundary DOFs are those of entities on a facet of one cell.
 fe_status sxv_setup(fe_simplex S, const int32_t *cells)
 {
-    const int dim = S->dim, nv = dim + 1, nd = S->nn;
+    const int dim = S->dim, nv = dim + 1, nd = S->nn, fam = S->family;
     const int64_t ncells = S->ncells;
-    std::vector<Facet> erec(static_cast<size_t>(ncells) * nd), frec(static_cast<size_t>(ncells) * nv);
+    struct DofRec {
+        std::array<int32_t, 4> key;  // sorted vertex ids (padded with -1), slot
+        int64_t cell;
+        int32_t a;
+    };
+    std::vector<DofRec> rec(static_cast<size_t>(ncells) * nd);
+    std::vector<Facet> frec(static_cast<size_t>(ncells) * nv);
     for (int64_t K = 0; K < ncells; K++) {
         for (int a = 0; a < nd; a++) {
-            Facet &f = erec[K * nd + a];
+            int kind, ent, slot;
+            sxv_dof(fam, dim, a, kind, ent, slot);
+            std::array<int32_t, 4> k{-1, -1, -1, slot};
             int m = 0;
-            if (S->family == 1) {
-                const int i = dim == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
-                const int j = dim == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
-                f.v[m++] = cells[K * nv + i];
-                f.v[m++] = cells[K * nv + j];
-            } else {
+            if (kind == 0) {
+                int i, j;
+                sxv_edge(dim, ent, i, j);
+                k[m++] = cells[K * nv + i];
+                k[m++] = cells[K * nv + j];
+            } else if (kind == 1) {
                 for (int r = 0; r < nv; r++)
-                    if (r != a) f.v[m++] = cells[K * nv + r];
+                    if (r != ent) k[m++] = cells[K * nv + r];
+            } else {
+                for (int r = 0; r < nv; r++) k[m++] = cells[K * nv + r];
             }
-            std::sort(f.v.begin(), f.v.begin() + m);
-            for (int r = m; r < 3; r++) f.v[r] = -1;
-            f.cell = K;
-            f.j = a;
+            std::sort(k.begin(), k.begin() + m);
+            rec[K * nd + a] = DofRec{k, K, a};
         }
         for (int j = 0; j < nv; j++) {
             Facet &f = frec[K * nv + j];
@@ -1015,21 +1295,26 @@ fe_status sxv_setup(fe_simplex S, const int32_t *cells)
             f.j = j;
         }
     }
-    std::vector<std::array<int32_t, 3>> keys, fkeys;
-    std::vector<int32_t> count, fcount;
+    std::vector<std::array<int32_t, 3>> fkeys;
+    std::vector<int32_t> fcount;
     unique_keys(frec, fkeys, fcount);
     for (int32_t c : fcount)
         if (c > 2) return set_error(FE_EMESH, "a facet is shared by more than two cells");
-    unique_keys(erec, keys, count);
+    std::sort(rec.begin(), rec.end(), [](const DofRec &x, const DofRec &y) {
+        if (x.key != y.key) return x.key < y.key;
+        if (x.cell != y.cell) return x.cell < y.cell;
+        return x.a < y.a;
+    });
     // group id of every (cell, local DOF), then ids by first appearance
-    std::vector<int64_t> pre(static_cast<size_t>(ncells) * nd), gid(keys.size(), -1);
-    {
-        int64_t grp = -1;
-        for (size_t t = 0; t < erec.size(); t++) {
-            if (t == 0 || erec[t].v != erec[t - 1].v) grp++;
-            pre[erec[t].cell * nd + erec[t].j] = grp;
-        }
+    std::vector<int64_t> pre(static_cast<size_t>(ncells) * nd);
+    int64_t ngrp = 0;
+    for (size_t t = 0; t < rec.size(); t++) {
+        if (t > 0 && rec[t].key != rec[t - 1].key) ngrp++;
+        pre[rec[t].cell * nd + rec[t].a] = ngrp;
     }
+    if (!rec.empty()) ngrp++;
+    std::vector<DofRec>().swap(rec);
+    std::vector<int64_t> gid(static_cast<size_t>(ngrp), -1);
     int64_t nent = 0;
     for (int64_t t = 0; t < ncells * nd; t++) {
         int64_t &g = gid[pre[t]];
@@ -1045,12 +1330,14 @@ fe_status sxv_setup(fe_simplex S, const int32_t *cells)
                 const int64_t K = frec[t].cell;
                 const int j = frec[t].j;
                 for (int a = 0; a < nd; a++) {
-                    bool on;
-                    if (S->family == 2) {
-                        on = a == j;
-                    } else {
-                        const int i1 = dim == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
-                        const int j1 = dim == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
+                    int kind, ent, slot;
+                    sxv_dof(fam, dim, a, kind, ent, slot);
+                    bool on = false;
+                    if (kind == 1) {
+                        on = ent == j;
+                    } else if (kind == 0) {
+                        int i1, j1;
+                        sxv_edge(dim, ent, i1, j1);
                         on = i1 != j && j1 != j;
                     }
                     if (on) bnd[pre[K * nd + a]] = 1;
@@ -1062,12 +1349,46 @@ fe_status sxv_setup(fe_simplex S, const int32_t *cells)
 }
 
 // Pre-basis of the vector family at x: value v and Jacobian dv[c dim + r].
-// Constants e_b first; then Nedelec rotations (2D (-y, x); 3D e_m x x) or
-// the Raviart-Thomas field x.
+// Families 1-2: constants e_b first, then Nedelec rotations (2D (-y, x); 3D
+// e_m x x) or the Raviart-Thomas field x.  Family 3: [P_1]^d (component
+// b / (d+1) times 1, x_0, ..), then the quadratic fields orthogonal to x:
+// 2D x_m (-y, x); 3D x_j (x cross e_i) for the pairs (i, j) but (2, 2).
 void sxv_prebasis(int fam, int dim, int b, const double *x, double *v, double *dv)
 {
     for (int c = 0; c < 3; c++) v[c] = 0.0;
     for (int t = 0; t < 9; t++) dv[t] = 0.0;
+    if (fam == 3) {
+        if (b < dim * (dim + 1)) {
+            const int c = b / (dim + 1), m = b % (dim + 1);
+            v[c] = m == 0 ? 1.0 : x[m - 1];
+            if (m > 0) dv[c * dim + m - 1] = 1.0;
+            return;
+        }
+        const int q = b - dim * (dim + 1);
+        if (dim == 2) {
+            const double R[2] = {-x[1], x[0]};
+            v[0] = x[q] * R[0];
+            v[1] = x[q] * R[1];
+            dv[q] += R[0];
+            dv[2 + q] += R[1];
+            dv[1] += -x[q];
+            dv[2] += x[q];
+            return;
+        }
+        const int i = q / 3, j = q % 3;
+        double R[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // x cross e_i = x_{i+2} e_{i+1} - x_{i+1} e_{i+2}, indices mod 3
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+        R[i1] = x[i2];
+        R[i2] = -x[i1];
+        dR[i1 * 3 + i2] = 1.0;
+        dR[i2 * 3 + i1] = -1.0;
+        for (int c = 0; c < 3; c++) {
+            v[c] = x[j] * R[c];
+            for (int r = 0; r < 3; r++) dv[c * 3 + r] = (r == j ? R[c] : 0.0) + x[j] * dR[c * 3 + r];
+        }
+        return;
+    }
     if (b < dim) {
         v[b] = 1.0;
     } else if (fam == 2) {
@@ -1089,36 +1410,59 @@ void sxv_prebasis(int fam, int dim, int b, const double *x, double *v, double *d
     }
 }
 
-// Degrees of freedom on the reference simplex: the line integral of v along
-// edge (i, j) with tangent x_j - x_i, or the flux through the facet opposite
-// vertex a with normal N over its vertices in ascending local order.
+// Degrees of freedom on the reference simplex: along edge (i, j) the line
+// integral of v with tangent x_j - x_i (family 3: weighted by 1 - t and t);
+// on the facet opposite vertex a (vertices in ascending local order) the flux
+// with N (family 2) or, family 3, the integrals of v against the tangents
+// x_i1 - x_i0 and x_i2 - x_i0; family 3 in 2D: the interior moments of v's
+// components on the reference triangle.
 double sxv_moment(int fam, int dim, int a, int b)
 {
     double gx[4], gw[4];
-    gauss_legendre_01(2, gx, gw);
+    gauss_legendre_01(3, gx, gw);
     auto vert = [dim](int r, double *x) {
         for (int t = 0; t < dim; t++) x[t] = (r > 0 && t == r - 1) ? 1.0 : 0.0;
     };
+    int kind, ent, slot;
+    sxv_dof(fam, dim, a, kind, ent, slot);
     double v[3], dv[9], p[3] = {0, 0, 0};
     double s = 0.0;
-    if (fam == 1) {
-        const int i = dim == 3 ? (a < 3 ? 0 : a < 5 ? 1 : 2) : (a < 2 ? 0 : 1);
-        const int j = dim == 3 ? (a < 3 ? a + 1 : a < 5 ? a - 1 : 3) : (a < 2 ? a + 1 : 2);
+    if (kind == 0) {
+        int i, j;
+        sxv_edge(dim, ent, i, j);
         double xi[3], xj[3];
         vert(i, xi);
         vert(j, xj);
-        for (int q = 0; q < 2; q++) {
+        for (int q = 0; q < 3; q++) {
             for (int t = 0; t < dim; t++) p[t] = xi[t] + gx[q] * (xj[t] - xi[t]);
             sxv_prebasis(fam, dim, b, p, v, dv);
             double d = 0.0;
             for (int t = 0; t < dim; t++) d += v[t] * (xj[t] - xi[t]);
-            s += gw[q] * d;
+            const double w = fam != 3 ? 1.0 : slot == 0 ? 1.0 - gx[q] : gx[q];
+            s += gw[q] * d * w;
         }
         return s;
     }
+    // a degree-4 rule on the reference triangle (the collapsed 3 x 3 Gauss rule)
+    auto triangle = [&](auto &&f) {
+        double acc = 0.0;
+        for (int q0 = 0; q0 < 3; q0++)
+            for (int q1 = 0; q1 < 3; q1++) {
+                const double u0 = gx[q0], u1 = (1.0 - gx[q0]) * gx[q1];
+                acc += gw[q0] * gw[q1] * (1.0 - gx[q0]) * f(u0, u1);
+            }
+        return acc;
+    };
+    if (kind == 2) {
+        return triangle([&](double u0, double u1) {
+            double x[3] = {u0, u1, 0.0};
+            sxv_prebasis(fam, dim, b, x, v, dv);
+            return v[slot];
+        });
+    }
     int iv[3], m = 0;
     for (int r = 0; r <= dim; r++)
-        if (r != a) iv[m++] = r;
+        if (r != ent) iv[m++] = r;
     double x0[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0}, N[3] = {0, 0, 0};
     vert(iv[0], x0);
     vert(iv[1], x1);
@@ -1126,7 +1470,7 @@ double sxv_moment(int fam, int dim, int a, int b)
     if (dim == 2) {
         N[0] = x1[1] - x0[1];
         N[1] = x0[0] - x1[0];
-        for (int q = 0; q < 2; q++) {
+        for (int q = 0; q < 3; q++) {
             for (int t = 0; t < 2; t++) p[t] = x0[t] + gx[q] * (x1[t] - x0[t]);
             sxv_prebasis(fam, dim, b, p, v, dv);
             s += gw[q] * (v[0] * N[0] + v[1] * N[1]);
@@ -1138,13 +1482,18 @@ double sxv_moment(int fam, int dim, int a, int b)
         t1[t] = x1[t] - x0[t];
         t2[t] = x2[t] - x0[t];
     }
-    N[0] = t1[1] * t2[2] - t1[2] * t2[1];
-    N[1] = t1[2] * t2[0] - t1[0] * t2[2];
-    N[2] = t1[0] * t2[1] - t1[1] * t2[0];
-    // the (linear) integrand on the reference triangle by its centroid rule
-    for (int t = 0; t < 3; t++) p[t] = x0[t] + (t1[t] + t2[t]) / 3.0;
-    sxv_prebasis(fam, dim, b, p, v, dv);
-    return 0.5 * (v[0] * N[0] + v[1] * N[1] + v[2] * N[2]);
+    if (fam == 2) {
+        N[0] = t1[1] * t2[2] - t1[2] * t2[1];
+        N[1] = t1[2] * t2[0] - t1[0] * t2[2];
+        N[2] = t1[0] * t2[1] - t1[1] * t2[0];
+    } else {
+        for (int t = 0; t < 3; t++) N[t] = slot == 0 ? t1[t] : t2[t];
+    }
+    return triangle([&](double u0, double u1) {
+        for (int t = 0; t < 3; t++) p[t] = x0[t] + u0 * t1[t] + u1 * t2[t];
+        sxv_prebasis(fam, dim, b, p, v, dv);
+        return v[0] * N[0] + v[1] * N[1] + v[2] * N[2];
+    });
 }
 
 fe_status sxv_tables(fe_simplex S)
@@ -1193,50 +1542,49 @@ fe_status sxv_tables(fe_simplex S)
             dvg[a] = dim == 3 ? dv[0] + dv[4] + dv[8] : dv[0] + dv[3];
         }
     };
-    const int nq1 = 1 + (dim + 1) / 2;
+    const int nq1 = (fam == 3 ? 2 : 1) + (dim + 1) / 2;
     std::vector<double> qxw;
     sx_rule(dim, nq1, qxw);
     const int nq = int(qxw.size() / (dim + 1));
-    std::vector<double> phq(static_cast<size_t>(nq) * nd * dim);
-    std::vector<double> cu(nd * 3), dvg(nd);
-    for (int q = 0; q < nq; q++) shape(&qxw[size_t(q) * (dim + 1)], &phq[size_t(q) * nd * dim], cu.data(), dvg.data());
-    const double xc[3] = {0.25, 0.25, 0.25};
-    shape(xc, std::vector<double>(nd * 3).data(), cu.data(), dvg.data());  // curls and divergences are constant
-    const int nps = (fam == 1 && dim == 3) ? 6 : 1, npm = dim * (dim + 1) / 2;
-    const double vol = dim == 3 ? 1.0 / 6.0 : 0.5;
+    const int ncu = dim == 3 ? 3 : 1;
+    std::vector<double> phq(static_cast<size_t>(nq) * nd * dim), cuq(static_cast<size_t>(nq) * nd * ncu),
+        dvq(static_cast<size_t>(nq) * nd);
+    for (int q = 0; q < nq; q++)
+        shape(&qxw[size_t(q) * (dim + 1)], &phq[size_t(q) * nd * dim], &cuq[size_t(q) * nd * ncu],
+              &dvq[size_t(q) * nd]);
+    const int nps = (fam != 2 && dim == 3) ? 6 : 1, npm = dim * (dim + 1) / 2;
     std::vector<int32_t> tri(ntri);
     {
         int t = 0;
         for (int I = 0; I < nd; I++)
             for (int J = I; J < nd; J++) tri[t++] = (I << 16) | J;
     }
+    // reference products by the rule: stiffness (curl or divergence) then mass
     std::vector<double> tab(static_cast<size_t>(nps + npm) * ntri, 0.0);
     for (int t = 0; t < ntri; t++) {
         const int a = tri[t] >> 16, b = tri[t] & 0xffff;
-        if (nps == 6) {
-            int p = 0;
-            for (int r = 0; r < 3; r++)
-                for (int s = r; s < 3; s++, p++) {
-                    double v = cu[a * 3 + r] * cu[b * 3 + s];
-                    if (s != r) v += cu[a * 3 + s] * cu[b * 3 + r];
-                    tab[size_t(p) * ntri + t] = vol * v;
-                }
-        } else {
-            tab[t] = vol * (fam == 1 ? cu[a] * cu[b] : dvg[a] * dvg[b]);
-        }
-        int p = nps;
-        for (int r = 0; r < dim; r++)
-            for (int s = r; s < dim; s++, p++) {
-                double v = 0.0;
-                for (int q = 0; q < nq; q++) {
-                    const double w = qxw[size_t(q) * (dim + 1) + dim];
-                    const double *ph = &phq[size_t(q) * nd * dim];
+        for (int q = 0; q < nq; q++) {
+            const double w = qxw[size_t(q) * (dim + 1) + dim];
+            const double *cu = &cuq[size_t(q) * nd * ncu], *ph = &phq[size_t(q) * nd * dim], *dg = &dvq[size_t(q) * nd];
+            if (nps == 6) {
+                int p = 0;
+                for (int r = 0; r < 3; r++)
+                    for (int s = r; s < 3; s++, p++) {
+                        double v = cu[a * 3 + r] * cu[b * 3 + s];
+                        if (s != r) v += cu[a * 3 + s] * cu[b * 3 + r];
+                        tab[size_t(p) * ntri + t] += w * v;
+                    }
+            } else {
+                tab[t] += w * (fam != 2 ? cu[a] * cu[b] : dg[a] * dg[b]);
+            }
+            int p = nps;
+            for (int r = 0; r < dim; r++)
+                for (int s = r; s < dim; s++, p++) {
                     double pr = ph[a * dim + r] * ph[b * dim + s];
                     if (s != r) pr += ph[a * dim + s] * ph[b * dim + r];
-                    v += w * pr;
+                    tab[size_t(p) * ntri + t] += w * pr;
                 }
-                tab[size_t(p) * ntri + t] = v;
-            }
+        }
     }
     fe_status st = sx_upload(S->tab, tab.data(), tab.size());
     if (st == FE_OK) st = sx_upload(S->tri, tri.data(), tri.size());
@@ -1323,8 +1671,21 @@ fe_status launch_sx_vector(fe_simplex S, hipStream_t s)
     return FE_OK;
 }
 
+template <int DIM>
+fe_status launch_sx_nedelec2(fe_simplex S, hipStream_t s)
+{
+    using Sh = Sxn2Shape<DIM>;
+    const int64_t nb = (S->ncells + Sh::CPB - 1) / Sh::CPB;
+    if (nb == 0) return FE_OK;
+    hipLaunchKernelGGL((sx_nedelec2_kernel<DIM>), dim3(unsigned(nb)), dim3(256), 0, s, S->args, S->kappa, S->vxyz,
+                       S->cells, S->coef, S->tab, S->tri, S->phiq, S->qxw, S->E, S->F);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
 fe_status launch_elements(fe_simplex S, hipStream_t s)
 {
+    if (S->family == 3) return S->dim == 3 ? launch_sx_nedelec2<3>(S, s) : launch_sx_nedelec2<2>(S, s);
     if (S->family == 1) return S->dim == 3 ? launch_sx_vector<3, 1>(S, s) : launch_sx_vector<2, 1>(S, s);
     if (S->family == 2) return S->dim == 3 ? launch_sx_vector<3, 2>(S, s) : launch_sx_vector<2, 2>(S, s);
     const bool el = S->args.problem == FE_ELASTICITY;
@@ -1461,7 +1822,8 @@ fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, 
     *out = nullptr;
     const int dim = desc->dim;
     if (dim != 2 && dim != 3) return set_error(FE_EINVAL, "dim must be 2 or 3");
-    if (family != FE_NEDELEC && family != FE_RAVIART_THOMAS) return set_error(FE_EINVAL, "unknown element family");
+    if (family != FE_NEDELEC && family != FE_RAVIART_THOMAS && family != FE_NEDELEC2)
+        return set_error(FE_EINVAL, "unknown element family");
     if (!(kappa >= 0.0) || !std::isfinite(kappa)) return set_error(FE_EINVAL, "kappa must be finite and >= 0");
     if (coeff->precision != FE_FP64) return set_error(FE_EINVAL, "simplices integrate in FP64 only");
     if (coeff->source_kind < FE_SOURCE_NONE || coeff->source_kind > FE_SOURCE_SINPROD)
@@ -1475,7 +1837,7 @@ fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, 
     S->k = 0;
     S->family = family;
     S->kappa = kappa;
-    S->nn = family == FE_NEDELEC ? (dim == 3 ? 6 : 3) : dim + 1;
+    S->nn = family == FE_NEDELEC ? (dim == 3 ? 6 : 3) : family == FE_NEDELEC2 ? (dim == 3 ? 20 : 8) : dim + 1;
     S->ncomp = 1;
     S->nloc = S->nn;
     S->ntri = S->nloc * (S->nloc + 1) / 2;
