@@ -603,6 +603,8 @@ fe_status fe_spmv_plan_set_mesh(fe_mesh mesh, int32_t order, const fe_coeff *coe
  * node-tile pairs each wave accumulates (the workgroups per cell follow).
  * Every shape sums each element-matrix entry over the quadrature points in
  * the same order, so element matrices are bitwise the same for every shape.
+ * FP16 / BF16 classes have one shape (a workgroup per cell, parts = 1;
+ * pairs_per_wave the most node-tile pairs one of its waves takes).
  * fe_integrate_autotune times each candidate shape of the class (order,
  * problem, precision) of (mesh, order, coeff) with reps K3 launches into ws
  * (the workspace of fe_assemble_query, whose element matrices it overwrites)

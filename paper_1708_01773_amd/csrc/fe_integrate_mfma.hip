@@ -7,17 +7,13 @@
 //   Poisson     A[a][b]        = sum_(c,q) G[(c,q)][a] w_q G[(c,q)][b]          (K = d nq)
 //   Elasticity  M_ij[a][b]     = sum_q G[(i,q)][a] w_q G[(j,q)][b]              (9 Gram blocks, K = nq)
 //               A[(a,i)][(b,j)] = lambda M_ij + mu (M_ji + delta_ij sum_l M_ll)  (combined per lane)
-// A workgroup owns one cell (or a part of its tile pairs): it stages the
-// physical gradients of a slab of quadrature points in LDS, then every wave
-// accumulates its node-tile pairs (ta <= tb, 16 x 16 each) with MFMA; the
-// lower triangle is written as the mirror of the upper one.
-//
-// Precision policies: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4),
-// FP16 / BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x32).  The
-// gradients are always computed in FP64 and rounded to the input type; for
-// FP16/BF16 the operands are scaled by powers of two chosen per cell (the
-// A operand by ~h, the B operand additionally by 1/max_q w_q) so that they
-// sit near 1, and the result is unscaled exactly.
+// FP64 (v_mfma_f64_16x16x4) and FP32 (v_mfma_f32_16x16x4): a workgroup owns
+// one cell (or a part of its tile pairs); it stages the physical gradients of
+// a slab of quadrature points in LDS, then every wave accumulates its
+// node-tile pairs (ta <= tb, 16 x 16 each) with MFMA; the lower triangle is
+// written as the mirror of the upper one.  FP16 / BF16 inputs with FP32
+// accumulation (v_mfma_f32_16x16x32) run the whole-cell kernel further down.
+// The gradients are always computed in FP64 and rounded to the input type.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -38,9 +34,7 @@ struct PolF64 {
     using Acc = d4_t;
     using Out = double;
     static constexpr int KM = 4;
-    static constexpr bool KFAST = false;       // LDS layout [c][q][node]
     static constexpr bool ROW_INTERLEAVED = true;  // D register r of lane l is row 4 r + l / 16
-    static constexpr bool SCALED = false;
     __device__ static Acc zero() { return Acc{0.0, 0.0, 0.0, 0.0}; }
     __device__ static Acc mma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
@@ -50,9 +44,7 @@ struct PolF32 {
     using Acc = f4_t;
     using Out = float;
     static constexpr int KM = 4;
-    static constexpr bool KFAST = false;
     static constexpr bool ROW_INTERLEAVED = false;  // row 4 (l / 16) + r
-    static constexpr bool SCALED = false;
     __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
     __device__ static Acc mma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
@@ -62,10 +54,7 @@ struct PolF16 {
     using V = h8_t;
     using Acc = f4_t;
     using Out = float;
-    static constexpr int KM = 32;
-    static constexpr bool KFAST = true;  // LDS layout [c][node][q]: a lane reads 8 consecutive q
-    static constexpr bool ROW_INTERLEAVED = false;
-    static constexpr bool SCALED = true;
+    static constexpr int KM = 32;  // a lane reads 8 consecutive points
     __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
     __device__ static Acc mma(V a, V b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 };
@@ -76,9 +65,6 @@ struct PolBF16 {
     using Acc = f4_t;
     using Out = float;
     static constexpr int KM = 32;
-    static constexpr bool KFAST = true;
-    static constexpr bool ROW_INTERLEAVED = false;
-    static constexpr bool SCALED = true;
     __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
     __device__ static Acc mma(V a, V b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
@@ -185,12 +171,10 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
     // geometry of every quadrature point of the cell
     __shared__ double sJi[NQ][9];
     __shared__ double sW[NQ], sWd[NQ], sXq[NQ][3];
-    __shared__ double sScale[2];  // alpha, beta (powers of two)
     __shared__ int sBad;
-    // gradients (and the scaled B operand for FP16/BF16) of a slab of points
-    __shared__ __attribute__((aligned(16))) S sG[DIM][Pol::KFAST ? NNP : QS][Pol::KFAST ? QS : NNP];
-    __shared__ __attribute__((aligned(16))) S sH[Pol::SCALED ? DIM : 1][Pol::SCALED ? NNP : 1][Pol::SCALED ? QS : 1];
-    __shared__ S sWs[Pol::KFAST ? 1 : QS];
+    // gradients of a slab of points, and their weights
+    __shared__ __attribute__((aligned(16))) S sG[DIM][QS][NNP];
+    __shared__ S sWs[QS];
 
     if (tid < 8) {
         const int64_t e0 = cell % m.n0, e1 = (cell / m.n0) % m.n1, e2 = cell / (int64_t(m.n0) * m.n1);
@@ -219,27 +203,8 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
         sW[q] = wd * coef;
         for (int t = 0; t < 9; t++) sJi[q][t] = Ji[t];
         for (int r = 0; r < 3; r++) sXq[q][r] = xq[r];
-        if (q == 0) sScale[0] = det;
     }
     __syncthreads();
-
-    // per-cell operand scaling (FP16/BF16 only): alpha ~ h, beta = alpha / 2^floor(log2 max_q w_q)
-    if (Pol::SCALED) {
-        __syncthreads();
-        if (tid == 0) {
-            double wmax = 0.0;
-            for (int q = 0; q < NQ; q++) wmax = fmax(wmax, sW[q]);
-            const double det0 = sScale[0];
-            const double h = cbrt(fabs(det0) > 0.0 ? fabs(det0) : 1.0);
-            const double alpha = exp2(floor(log2(h)));
-            const double beta = alpha * (wmax > 0.0 ? exp2(-floor(log2(wmax))) : 1.0);
-            sScale[0] = alpha;
-            sScale[1] = beta;
-        }
-        __syncthreads();
-    }
-    const double alpha = Pol::SCALED ? sScale[0] : 1.0;
-    const double beta = Pol::SCALED ? sScale[1] : 1.0;
 
     // tile pairs of this wave
     int pta[PPW], ptb[PPW];
@@ -292,16 +257,9 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
                     for (int c = 0; c < 3; c++) g[c] = Ji[0 * 3 + c] * gr[0] + Ji[1 * 3 + c] * gr[1] + Ji[2 * 3 + c] * gr[2];
                 }
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    if (Pol::KFAST) {
-                        sG[c][node][gq] = S(g[c] * alpha);
-                        if (Pol::SCALED) sH[c][node][gq] = S(g[c] * w * beta);
-                    } else {
-                        sG[c][gq][node] = S(g[c]);
-                    }
-                }
+                for (int c = 0; c < 3; c++) sG[c][gq][node] = S(g[c]);
             }
-            if (!Pol::KFAST && gsub == 0) sWs[gq] = S(w);
+            if (gsub == 0) sWs[gq] = S(w);
         }
         __syncthreads();
         // MFMA over the slab
@@ -310,43 +268,23 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
             if (!pok[t]) continue;
             const int ra = pta[t] * 16 + i16, rb = ptb[t] * 16 + i16;
             for (int k0 = 0; k0 < QS; k0 += Pol::KM) {
-                if constexpr (Pol::KFAST) {
-                    using V = typename Pol::V;
-                    V av[DIM], bv[DIM];
+                const int kq = k0 + g4;
+                const S wk = sWs[kq];
+                S av[DIM], bv[DIM];
 #pragma unroll
-                    for (int c = 0; c < DIM; c++) {
-                        av[c] = *reinterpret_cast<const V *>(&sG[c][ra][k0 + 8 * g4]);
-                        bv[c] = *reinterpret_cast<const V *>(&sH[c][rb][k0 + 8 * g4]);
-                    }
-                    if (PROB == 0) {
+                for (int c = 0; c < DIM; c++) {
+                    av[c] = sG[c][kq][ra];
+                    bv[c] = wk * sG[c][kq][rb];
+                }
+                if (PROB == 0) {
 #pragma unroll
-                        for (int c = 0; c < DIM; c++) acc[t][0] = Pol::mma(av[c], bv[c], acc[t][0]);
-                    } else {
-#pragma unroll
-                        for (int c1 = 0; c1 < DIM; c1++)
-#pragma unroll
-                            for (int c2 = 0; c2 < DIM; c2++)
-                                acc[t][c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[t][c1 * DIM + c2]);
-                    }
+                    for (int c = 0; c < DIM; c++) acc[t][0] = Pol::mma(av[c], bv[c], acc[t][0]);
                 } else {
-                    const int kq = k0 + g4;
-                    const S wk = sWs[kq];
-                    S av[DIM], bv[DIM];
 #pragma unroll
-                    for (int c = 0; c < DIM; c++) {
-                        av[c] = sG[c][kq][ra];
-                        bv[c] = wk * sG[c][kq][rb];
-                    }
-                    if (PROB == 0) {
+                    for (int c1 = 0; c1 < DIM; c1++)
 #pragma unroll
-                        for (int c = 0; c < DIM; c++) acc[t][0] = Pol::mma(av[c], bv[c], acc[t][0]);
-                    } else {
-#pragma unroll
-                        for (int c1 = 0; c1 < DIM; c1++)
-#pragma unroll
-                            for (int c2 = 0; c2 < DIM; c2++)
-                                acc[t][c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[t][c1 * DIM + c2]);
-                    }
+                        for (int c2 = 0; c2 < DIM; c2++)
+                            acc[t][c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[t][c1 * DIM + c2]);
                 }
             }
         }
@@ -371,7 +309,6 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
         __syncthreads();
     }
     if (tid == 0 && sBad) atomicOr(m.status, 1);
-    const double unscale = 1.0 / (alpha * beta);
     Out *Ec = E + cell * int64_t(nloc) * nloc;
 #pragma unroll
     for (int t = 0; t < PPW; t++) {
@@ -386,7 +323,7 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
             const bool diag = pta[t] == ptb[t];
             if (diag && row > col) continue;
             if (PROB == 0) {
-                const Out v = Out(double(acc[t][0][r]) * unscale);
+                const Out v = Out(double(acc[t][0][r]));
                 Ec[int64_t(row) * nloc + col] = v;
                 if (row != col) Ec[int64_t(col) * nloc + row] = v;
             } else {
@@ -400,7 +337,7 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
                         if (row == col && c1 > c2) continue;
                         const double v = el_value(p.lambda, p.mu, double(acc[t][c1 * DIM + c2][r]),
                                                   double(acc[t][c2 * DIM + c1][r]), tr, c1 == c2);
-                        const Out o = Out(v * unscale);
+                        const Out o = Out(v);
                         Ec[int64_t(row * NC + c1) * nloc + col * NC + c2] = o;
                         if (row != col || c1 != c2) Ec[int64_t(col * NC + c2) * nloc + row * NC + c1] = o;
                     }
@@ -434,25 +371,388 @@ __global__ __launch_bounds__(256, 2) void k3_mfma_batch_kernel(const AsmJob *__r
 }
 
 // ---------------------------------------------------------------------------
+// FP16 / BF16 operands: one workgroup per cell.  With the operand
+// sqrt(w_q) G[(c,q)][a] both GEMM operands are the same array, so the scaled
+// gradients of all the cell's points fit in LDS at once (Q4: 3 x 128 nodes x
+// 128 points x 2 bytes, rows padded by 16 bytes so that the 16 rows a
+// quarter-wave reads sit in distinct banks).  They are computed once per cell;
+// then each wave takes whole node-tile pairs in turn, accumulates the pair's
+// blocks over all points and stores them, so no accumulator outlives its pair
+// and no workgroup repeats another's gradients.  At Q4 a pair's block goes
+// out through a per-wave LDS chunk of 8 node rows (16 for Poisson), written
+// as rows of the block and of its mirror, consecutive lanes on consecutive
+// addresses: stored straight from the accumulators, one store instruction
+// touches up to 32 rows and makes some 28 write requests to L2, which then
+// bounds the kernel.  At Q2 and Q3 the staging area would cost workgroups
+// per CU, and the direct stores are faster.  The operand is scaled by a
+// power of two per cell (~ h / sqrt(max_q w_q)) so that it sits near 1; the
+// product is unscaled exactly.  The load vector is the FP64 sum of the slab
+// kernel, in the same order.
+template <int NNP>
+struct Cell16Shape {
+    static constexpr int K1 = NNP == 32 ? 3 : (NNP == 64 ? 4 : 5);
+    static constexpr int NQ = K1 * K1 * K1;
+    static constexpr int NQP = (NQ + 31) / 32 * 32;  // points padded to the MFMA depth
+    static constexpr int PITCH = NQP + 8;            // LDS row pitch (elements)
+    static constexpr int NTH = NNP == 128 ? 512 : 256;
+};
+
+template <class Pol, int PROB, int NNP>
+__device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArgs &m, const ProblemArgs &p,
+                                               const RefTables &rt, typename Pol::Out *__restrict__ E,
+                                               double *__restrict__ F, int64_t cell)
+{
+    constexpr int DIM = 3;
+    using Sh = Cell16Shape<NNP>;
+    constexpr int K1 = Sh::K1, NQ = Sh::NQ, NQP = Sh::NQP, PITCH = Sh::PITCH, NTH = Sh::NTH, NW = NTH / 64;
+    constexpr int NT = NNP / 16;
+    constexpr int NP = NT * (NT + 1) / 2;
+    constexpr int NC = PROB == 1 ? DIM : 1;
+    constexpr int NCP = PROB == 1 ? DIM * DIM : 1;
+    constexpr int TPQ = NTH / NQP;  // threads per point in the gradient stage
+    static_assert(NTH % NQP == 0 && NNP % TPQ == 0, "gradient stage shape");
+    constexpr bool STAGE = NNP == 128;            // output through LDS
+    constexpr int CH = PROB == 1 ? 8 : 16;        // node rows per output chunk
+    constexpr int BC = 16 * NC, BP = BC + 1;      // block columns, staging pitch
+    constexpr int CHR = CH * NC;                  // block rows per chunk
+    using S = typename Pol::S;
+    using V = typename Pol::V;
+    using Acc = typename Pol::Acc;
+    using Out = typename Pol::Out;
+    const int nn = NQ, nloc = s.nloc;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+
+    __shared__ double sX[8][3];
+    __shared__ double sL[K1 * K1], sD[K1 * K1];
+    __shared__ double sJi[NQ][9];
+    __shared__ double sW[NQ], sWd[NQ], sXq[NQ][3];
+    __shared__ double sDet0, sAlpha;
+    __shared__ int sBad;
+    __shared__ __attribute__((aligned(16))) S sG[DIM][NNP][PITCH];
+    __shared__ Out sStage[STAGE ? NW : 1][STAGE ? CHR * BP : 1];
+
+    if (tid < 8) {
+        const int64_t e0 = cell % m.n0, e1 = (cell / m.n0) % m.n1, e2 = cell / (int64_t(m.n0) * m.n1);
+        const int64_t vid = (e0 + (tid & 1)) + int64_t(m.n0 + 1) * ((e1 + ((tid >> 1) & 1)) + int64_t(m.n1 + 1) * (e2 + ((tid >> 2) & 1)));
+        sX[tid][0] = m.x[vid];
+        sX[tid][1] = m.y[vid];
+        sX[tid][2] = m.z[vid];
+    }
+    if (tid < K1 * K1) {
+        sL[tid] = rt.L[tid];
+        sD[tid] = rt.D[tid];
+    }
+    if (tid == 0) sBad = 0;
+    const double coef = m.coef ? m.coef[cell] : 1.0;
+    __syncthreads();
+    for (int q = tid; q < NQ; q += NTH) {
+        const int a0 = q % K1, a1 = (q / K1) % K1, a2 = q / (K1 * K1);
+        const double xi[3] = {rt.gx[a0], rt.gx[a1], rt.gx[a2]};
+        double Xl[8][3], Ji[9], xq[3];
+        for (int v = 0; v < 8; v++)
+            for (int r = 0; r < 3; r++) Xl[v][r] = sX[v][r];
+        const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
+        if (!(det > 0.0)) sBad = 1;
+        const double wd = rt.gw[a0] * rt.gw[a1] * rt.gw[a2] * fabs(det);
+        sWd[q] = wd;
+        sW[q] = wd * coef;
+        for (int t = 0; t < 9; t++) sJi[q][t] = Ji[t];
+        for (int r = 0; r < 3; r++) sXq[q][r] = xq[r];
+        if (q == 0) sDet0 = det;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double wmax = 0.0;
+        for (int q = lane; q < NQ; q += 64) wmax = fmax(wmax, sW[q]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wmax = fmax(wmax, __shfl_xor(wmax, off));
+        if (lane == 0) {
+            const double h = cbrt(fabs(sDet0) > 0.0 ? fabs(sDet0) : 1.0);
+            sAlpha = wmax > 0.0 ? exp2(floor(log2(h / sqrt(wmax)))) : 1.0;
+        }
+    }
+    __syncthreads();
+    const double alpha = sAlpha;
+
+    // scaled gradients of every point: thread -> (point gq, nodes gsub + TPQ j);
+    // consecutive lanes write consecutive points of one node row
+    {
+        const int gq = tid % NQP, gsub = tid / NQP;
+        const bool live = gq < NQ;
+        double Ji[9];
+        double sw = 0.0;
+        int b0 = 0, b1 = 0, b2 = 0;
+        if (live) {
+#pragma unroll
+            for (int t = 0; t < 9; t++) Ji[t] = sJi[gq][t];
+            b0 = gq % K1;
+            b1 = (gq / K1) % K1;
+            b2 = gq / (K1 * K1);
+            sw = sqrt(sW[gq]) * alpha;
+        }
+#pragma unroll 4
+        for (int j = 0; j < NNP / TPQ; j++) {
+            const int node = gsub + TPQ * j;
+            double g[3] = {0.0, 0.0, 0.0};
+            if (live && node < nn) {
+                const int n0 = node % K1, n1 = (node / K1) % K1, n2 = node / (K1 * K1);
+                const double L0 = sL[n0 * K1 + b0], L1 = sL[n1 * K1 + b1], L2 = sL[n2 * K1 + b2];
+                const double gr[3] = {sD[n0 * K1 + b0] * L1 * L2, L0 * sD[n1 * K1 + b1] * L2,
+                                      L0 * L1 * sD[n2 * K1 + b2]};
+#pragma unroll
+                for (int c = 0; c < 3; c++) g[c] = Ji[0 * 3 + c] * gr[0] + Ji[1 * 3 + c] * gr[1] + Ji[2 * 3 + c] * gr[2];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++) sG[c][node][gq] = S(g[c] * sw);
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && sBad) atomicOr(m.status, 1);
+
+    const int i16 = lane % 16, g4 = lane / 16;
+    const double unscale = 1.0 / (alpha * alpha);
+    Out *Ec = E + cell * int64_t(nloc) * nloc;
+    for (int pidx = wave; pidx < NP; pidx += NW) {
+        int ta, tb;
+        pair_tiles(pidx, NT, ta, tb);
+        const int ra = ta * 16 + i16, rb = tb * 16 + i16;
+        Acc acc[NCP];
+#pragma unroll
+        for (int c = 0; c < NCP; c++) acc[c] = Pol::zero();
+#pragma unroll
+        for (int k0 = 0; k0 < NQP; k0 += Pol::KM) {
+            V av[DIM], bv[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; c++) {
+                av[c] = *reinterpret_cast<const V *>(&sG[c][ra][k0 + 8 * g4]);
+                bv[c] = *reinterpret_cast<const V *>(&sG[c][rb][k0 + 8 * g4]);
+            }
+            if (PROB == 0) {
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[0] = Pol::mma(av[c], bv[c], acc[0]);
+            } else {
+#pragma unroll
+                for (int c1 = 0; c1 < DIM; c1++)
+#pragma unroll
+                    for (int c2 = 0; c2 < DIM; c2++)
+                        acc[c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[c1 * DIM + c2]);
+            }
+        }
+        if constexpr (!STAGE) {
+            const int col = tb * 16 + i16;
+            const bool diag = ta == tb;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = ta * 16 + 4 * g4 + r;
+                if (row >= nn || col >= nn) continue;
+                // on a diagonal tile only the upper triangle is taken, and mirrored
+                if (diag && row > col) continue;
+                if (PROB == 0) {
+                    const Out v = Out(double(acc[0][r]) * unscale);
+                    Ec[int64_t(row) * nloc + col] = v;
+                    if (row != col) Ec[int64_t(col) * nloc + row] = v;
+                } else {
+                    double tr = 0.0;
+#pragma unroll
+                    for (int l = 0; l < DIM; l++) tr += double(acc[l * DIM + l][r]);
+#pragma unroll
+                    for (int c1 = 0; c1 < DIM; c1++)
+#pragma unroll
+                        for (int c2 = 0; c2 < DIM; c2++) {
+                            if (row == col && c1 > c2) continue;
+                            const double v = el_value(p.lambda, p.mu, double(acc[c1 * DIM + c2][r]),
+                                                      double(acc[c2 * DIM + c1][r]), tr, c1 == c2);
+                            const Out o = Out(v * unscale);
+                            Ec[int64_t(row * NC + c1) * nloc + col * NC + c2] = o;
+                            if (row != col || c1 != c2) Ec[int64_t(col * NC + c2) * nloc + row * NC + c1] = o;
+                        }
+                }
+            }
+            continue;
+        }
+        // The staged chunk holds block rows (rl - ch0) NC + c1, columns
+        // i16 NC + c2; on a diagonal tile only entries with block row <=
+        // block column are computed (the upper triangle), the rest is their
+        // mirror.  The wave's LDS operations run in order, so fences at
+        // wavefront scope order the lanes' writes and reads.
+        const int col = tb * 16 + i16;
+        const bool diag = ta == tb;
+        Out *stg = sStage[wave];
+#pragma unroll
+        for (int ch0 = 0; ch0 < 16; ch0 += CH) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int rl = 4 * g4 + r, row = ta * 16 + rl;
+                if (rl < ch0 || rl >= ch0 + CH || row >= nn || col >= nn) continue;
+                if (diag && row > col) continue;
+                Out *st = stg + (rl - ch0) * NC * BP + i16 * NC;
+                if (PROB == 0) {
+                    st[0] = Out(double(acc[0][r]) * unscale);
+                } else {
+                    double tr = 0.0;
+#pragma unroll
+                    for (int l = 0; l < DIM; l++) tr += double(acc[l * DIM + l][r]);
+#pragma unroll
+                    for (int c1 = 0; c1 < DIM; c1++)
+#pragma unroll
+                        for (int c2 = 0; c2 < DIM; c2++) {
+                            if (row == col && c1 > c2) continue;
+                            const double v = el_value(p.lambda, p.mu, double(acc[c1 * DIM + c2][r]),
+                                                      double(acc[c2 * DIM + c1][r]), tr, c1 == c2);
+                            st[c1 * BP + c2] = Out(v * unscale);
+                        }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int I0 = (ta * 16 + ch0) * NC, J0 = tb * 16 * NC;
+            for (int e = lane; e < CHR * BC; e += 64) {
+                const int il = e / BC, jl = e - il * BC;
+                const int I = I0 + il, J = J0 + jl;
+                if (I < nloc && J < nloc && !(diag && J < I)) Ec[int64_t(I) * nloc + J] = stg[il * BP + jl];
+            }
+            for (int e = lane; e < CHR * BC; e += 64) {
+                const int jl = e / CHR, il = e - jl * CHR;
+                const int I = I0 + il, J = J0 + jl;
+                if (I < nloc && J < nloc && !(diag && J <= I)) Ec[int64_t(J) * nloc + I] = stg[il * BP + jl];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    // load vector (FP64, VALU): the points in ascending order, as the slab kernel
+    for (int row = tid; row < nloc; row += NTH) {
+        const int a = row / NC, c = row % NC;
+        const int n0 = a % K1, n1 = (a / K1) % K1, n2 = a / (K1 * K1);
+        double f = 0.0;
+        for (int q = 0; q < NQ; q++) {
+            const int b0 = q % K1, b1 = (q / K1) % K1, b2 = q / (K1 * K1);
+            const double phi = sL[n0 * K1 + b0] * sL[n1 * K1 + b1] * sL[n2 * K1 + b2];
+            const double xq[3] = {sXq[q][0], sXq[q][1], sXq[q][2]};
+            f = __fma_rn(sWd[q] * source_value_mf(p, xq, c), phi, f);
+        }
+        F[cell * nloc + row] = f;
+    }
+}
+
+template <class Pol, int PROB, int NNP>
+__global__ __launch_bounds__(Cell16Shape<NNP>::NTH, 1) void k3_cell16_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p,
+                                                                            RefTables rt,
+                                                                            typename Pol::Out *__restrict__ E,
+                                                                            double *__restrict__ F)
+{
+    k3_cell16_body<Pol, PROB, NNP>(s, m, p, rt, E, F, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <class Pol, int PROB, int NNP>
+__global__ __launch_bounds__(Cell16Shape<NNP>::NTH, 1) void k3_cell16_batch_kernel(const AsmJob *__restrict__ jobs,
+                                                                                  const int32_t *__restrict__ boff,
+                                                                                  int njobs)
+{
+    int64_t lb, nb;
+    const AsmJob &J = jobs[find_job(boff, njobs, lb, nb)];
+    k3_cell16_body<Pol, PROB, NNP>(J.s, J.m, J.p, J.rt, static_cast<typename Pol::Out *>(J.E), J.F, lb);
+}
+
+template <class Pol, int PROB, int NNP>
+static fe_status launch_cell16_one(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa,
+                                   const RefTables &rt, void *E, double *F, hipStream_t s)
+{
+    if (sa.ncells == 0) return FE_OK;
+    hipLaunchKernelGGL((k3_cell16_kernel<Pol, PROB, NNP>), dim3(unsigned(sa.ncells)), dim3(Cell16Shape<NNP>::NTH), 0, s,
+                       sa, ma, pa, rt, static_cast<typename Pol::Out *>(E), F);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+template <class Pol, int PROB, int NNP>
+static fe_status launch_cell16_batch_one(const AsmJob *jobs, const int32_t *boff, int njobs, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_cell16_batch_kernel<Pol, PROB, NNP>), dim3(grid), dim3(Cell16Shape<NNP>::NTH), 0, s, jobs,
+                       boff, njobs);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
+// Calls body.template operator()<PROB, NNP>() for (order, problem).
+template <class Body>
+static fe_status with_cell16(int k, bool el, Body body)
+{
+    switch (k * 2 + (el ? 1 : 0)) {
+        case 2 * 2 + 0: return body.template operator()<0, 32>();
+        case 2 * 2 + 1: return body.template operator()<1, 32>();
+        case 3 * 2 + 0: return body.template operator()<0, 64>();
+        case 3 * 2 + 1: return body.template operator()<1, 64>();
+        case 4 * 2 + 0: return body.template operator()<0, 128>();
+        case 4 * 2 + 1: return body.template operator()<1, 128>();
+        default: return set_error(FE_EINVAL, "matrix-core integration needs order 2..4");
+    }
+}
+
+template <class Pol>
+struct Cell16Single {
+    const SpaceArgs &sa;
+    const MeshArgs &ma;
+    const ProblemArgs &pa;
+    const RefTables &rt;
+    void *E;
+    double *F;
+    hipStream_t s;
+    template <int PROB, int NNP>
+    fe_status operator()() const
+    {
+        return launch_cell16_one<Pol, PROB, NNP>(sa, ma, pa, rt, E, F, s);
+    }
+};
+
+template <class Pol>
+struct Cell16Batch {
+    const AsmJob *jobs;
+    const int32_t *boff;
+    int njobs, grid;
+    hipStream_t s;
+    template <int PROB, int NNP>
+    fe_status operator()() const
+    {
+        return launch_cell16_batch_one<Pol, PROB, NNP>(jobs, boff, njobs, grid, s);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Launch shapes: node-tile pairs per wave (PPW; parts per cell follow) for
 // (order, problem, precision).  Every shape sums each entry over the
 // quadrature points in the same order, so the element matrices do not depend
 // on it; the autotuner (fe_integrate_autotune) times the candidates of a
 // class and keeps the fastest for the process.  Defaults measured on 32^3 Q3
 // and 24^3 Q4 elasticity (Q3: 3.75 ms with one pair per wave against 5.57 ms
-// with two; Q4 BF16: 7.0 ms with two against 9.6 ms with one).  FP64 Q4
-// elasticity runs one pair per wave (10.0 ms): two need more than 256 VGPRs
-// and spill to private memory, and a variant of that kernel with more spills
-// gave element matrices that differed from run to run, so no kernel here
-// spills.
+// with two).  FP64 Q4 elasticity runs one pair per wave (10.0 ms): two need
+// more than 256 VGPRs and spill to private memory, and a variant of that
+// kernel with more spills gave element matrices that differed from run to
+// run, so no kernel here spills.  FP16 / BF16 have the one shape of the
+// whole-cell kernel.
 // ---------------------------------------------------------------------------
 static std::mutex g_k3_mu;
 static std::map<int, int> g_k3_tuned;  // class -> pairs per wave
 
 static int k3_class(int k, bool el, int prec) { return (k * 2 + (el ? 1 : 0)) * 8 + prec; }
 
+static bool whole_cell(int prec) { return prec == FE_FP16 || prec == FE_BF16; }
+
+static int nnp_of(int k) { return k == 2 ? 32 : (k == 3 ? 64 : 128); }
+
+// FP16 / BF16 run the whole-cell kernel, one shape per class: its waves take
+// the node-tile pairs in turn (reported as the most pairs a wave takes).
+static int cell16_ppw(int k)
+{
+    const int nt = nnp_of(k) / 16, np = nt * (nt + 1) / 2, nw = (k == 4 ? 512 : 256) / 64;
+    return (np + nw - 1) / nw;
+}
+
 static std::vector<int> k3_candidates(int k, bool el, int prec)
 {
+    if (whole_cell(prec)) return {cell16_ppw(k)};
     if (k == 2) return {1};
     if (k == 3) return el ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 3};
     if (el) return prec == FE_FP64 ? std::vector<int>{1} : std::vector<int>{1, 2};
@@ -461,6 +761,7 @@ static std::vector<int> k3_candidates(int k, bool el, int prec)
 
 static int k3_default(int k, bool el, int prec)
 {
+    if (whole_cell(prec)) return cell16_ppw(k);
     if (k == 3) return el ? 1 : 3;
     if (k == 4) return el ? (prec == FE_FP64 ? 1 : 2) : 9;
     return 1;
@@ -473,13 +774,14 @@ static int k3_ppw(int k, bool el, int prec)
     return it != g_k3_tuned.end() ? it->second : k3_default(k, el, prec);
 }
 
-static int nnp_of(int k) { return k == 2 ? 32 : (k == 3 ? 64 : 128); }
-
 static int parts_of(int k, int ppw)
 {
     const int nt = nnp_of(k) / 16, np = nt * (nt + 1) / 2;
     return (np + 4 * ppw - 1) / (4 * ppw);
 }
+
+// Workgroups per cell of the shape (ppw) of a class.
+static int parts_for(int k, int prec, int ppw) { return whole_cell(prec) ? 1 : parts_of(k, ppw); }
 
 template <class Pol, int PROB, int NNP, int PPW, int QS>
 static fe_status launch_one(const SpaceArgs &sa, const MeshArgs &ma, const ProblemArgs &pa, const RefTables &rt,
@@ -526,7 +828,7 @@ static fe_status with_shape(int k, bool el, int ppw, Body body)
 
 // The shapes built for a precision: two pairs per wave at Q4 elasticity would
 // need more than 256 VGPRs in FP64 (private-memory spills), so that shape is
-// built for the 32-bit-accumulating precisions only.
+// built for FP32 only.
 template <class Pol, int PROB, int NNP, int PPW>
 constexpr bool shape_built()
 {
@@ -546,7 +848,7 @@ struct SingleLaunch {
     fe_status operator()() const
     {
         if constexpr (shape_built<Pol, PROB, NNP, PPW>())
-            return launch_one<Pol, PROB, NNP, PPW, Pol::KFAST ? 32 : 16>(sa, ma, pa, rt, E, F, s);
+            return launch_one<Pol, PROB, NNP, PPW, 16>(sa, ma, pa, rt, E, F, s);
         else
             return set_error(FE_EINVAL, "tile shape not built for this precision");
     }
@@ -562,7 +864,7 @@ struct BatchLaunch {
     fe_status operator()() const
     {
         if constexpr (shape_built<Pol, PROB, NNP, PPW>())
-            return launch_batch_one<Pol, PROB, NNP, PPW, Pol::KFAST ? 32 : 16>(jobs, boff, njobs, grid, s);
+            return launch_batch_one<Pol, PROB, NNP, PPW, 16>(jobs, boff, njobs, grid, s);
         else
             return set_error(FE_EINVAL, "tile shape not built for this precision");
     }
@@ -576,8 +878,8 @@ static fe_status launch_with(const SpaceArgs &sa, const MeshArgs &ma, const Prob
     switch (pa.precision) {
         case FE_FP64: return with_shape(sa.k, el, ppw, SingleLaunch<PolF64>{sa, ma, pa, rt, E, F, s});
         case FE_FP32: return with_shape(sa.k, el, ppw, SingleLaunch<PolF32>{sa, ma, pa, rt, E, F, s});
-        case FE_FP16: return with_shape(sa.k, el, ppw, SingleLaunch<PolF16>{sa, ma, pa, rt, E, F, s});
-        default: return with_shape(sa.k, el, ppw, SingleLaunch<PolBF16>{sa, ma, pa, rt, E, F, s});
+        case FE_FP16: return with_cell16(sa.k, el, Cell16Single<PolF16>{sa, ma, pa, rt, E, F, s});
+        default: return with_cell16(sa.k, el, Cell16Single<PolBF16>{sa, ma, pa, rt, E, F, s});
     }
 }
 
@@ -596,15 +898,15 @@ fe_status launch_mfma_batch(const AsmJob &h, const AsmJob *jobs, const int32_t *
     switch (h.p.precision) {
         case FE_FP64: return with_shape(h.s.k, el, ppw, BatchLaunch<PolF64>{jobs, boff, njobs, grid, s});
         case FE_FP32: return with_shape(h.s.k, el, ppw, BatchLaunch<PolF32>{jobs, boff, njobs, grid, s});
-        case FE_FP16: return with_shape(h.s.k, el, ppw, BatchLaunch<PolF16>{jobs, boff, njobs, grid, s});
-        default: return with_shape(h.s.k, el, ppw, BatchLaunch<PolBF16>{jobs, boff, njobs, grid, s});
+        case FE_FP16: return with_cell16(h.s.k, el, Cell16Batch<PolF16>{jobs, boff, njobs, grid, s});
+        default: return with_cell16(h.s.k, el, Cell16Batch<PolBF16>{jobs, boff, njobs, grid, s});
     }
 }
 
 // Workgroups per cell of the matrix-core kernel (the shape launch_integrate_mfma uses now).
 int64_t mfma_blocks(const SpaceArgs &sa, const ProblemArgs &pa, int32_t &parts)
 {
-    parts = parts_of(sa.k, k3_ppw(sa.k, pa.problem == FE_ELASTICITY, pa.precision));
+    parts = parts_for(sa.k, pa.precision, k3_ppw(sa.k, pa.problem == FE_ELASTICITY, pa.precision));
     return sa.ncells * parts;
 }
 
@@ -636,7 +938,7 @@ fe_status integrate_autotune(const SpaceArgs &sa, const MeshArgs &ma, const Prob
             break;
         }
         const double us = 1000.0 * double(ms) / double(reps);
-        if (tried && int(c) < max_tried) tried[c] = fe_k3_plan{cand[c], parts_of(sa.k, cand[c]), us};
+        if (tried && int(c) < max_tried) tried[c] = fe_k3_plan{cand[c], parts_for(sa.k, pa.precision, cand[c]), us};
         if (n_tried) *n_tried = std::min(int(c) + 1, max_tried);
         if (best < 0 || us < best_us) {
             best = int(c);
@@ -650,7 +952,7 @@ fe_status integrate_autotune(const SpaceArgs &sa, const MeshArgs &ma, const Prob
         std::lock_guard<std::mutex> lk(g_k3_mu);
         g_k3_tuned[k3_class(sa.k, el, pa.precision)] = cand[best];
     }
-    if (chosen) *chosen = fe_k3_plan{cand[best], parts_of(sa.k, cand[best]), best_us};
+    if (chosen) *chosen = fe_k3_plan{cand[best], parts_for(sa.k, pa.precision, cand[best]), best_us};
     return FE_OK;
 }
 
@@ -658,7 +960,7 @@ void integrate_plan_of(const SpaceArgs &sa, const ProblemArgs &pa, fe_k3_plan *p
 {
     const bool el = pa.problem == FE_ELASTICITY;
     const int ppw = (sa.dim == 3 && sa.k >= 2 && sa.k <= 4) ? k3_ppw(sa.k, el, pa.precision) : 0;
-    *plan = fe_k3_plan{ppw, ppw ? parts_of(sa.k, ppw) : 0, 0.0};
+    *plan = fe_k3_plan{ppw, ppw ? parts_for(sa.k, pa.precision, ppw) : 0, 0.0};
 }
 
 void integrate_tuning_reset()
