@@ -415,6 +415,8 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
     constexpr int CH = PROB == 1 ? 8 : 16;        // node rows per output chunk
     constexpr int BC = 16 * NC, BP = BC + 1;      // block columns, staging pitch
     constexpr int CHR = CH * NC;                  // block rows per chunk
+    constexpr int RPI = 64 / BC, MPI = 64 / CHR;  // rows per store instruction (block, mirror)
+    static_assert(CHR % RPI == 0 && BC % MPI == 0, "output chunk shape");
     using S = typename Pol::S;
     using V = typename Pol::V;
     using Acc = typename Pol::Acc;
@@ -606,16 +608,26 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // block rows: RPI rows per store instruction, a lane keeps its
+            // column; mirror rows (block columns): MPI per instruction
             const int I0 = (ta * 16 + ch0) * NC, J0 = tb * 16 * NC;
-            for (int e = lane; e < CHR * BC; e += 64) {
-                const int il = e / BC, jl = e - il * BC;
-                const int I = I0 + il, J = J0 + jl;
-                if (I < nloc && J < nloc && !(diag && J < I)) Ec[int64_t(I) * nloc + J] = stg[il * BP + jl];
+            {
+                const int rsub = lane / BC, jl = lane - rsub * BC, J = J0 + jl;
+                if (rsub < RPI && J < nloc)
+#pragma unroll 4
+                    for (int it = 0; it < CHR / RPI; it++) {
+                        const int il = it * RPI + rsub, I = I0 + il;
+                        if (I < nloc && !(diag && J < I)) Ec[I * nloc + J] = stg[il * BP + jl];
+                    }
             }
-            for (int e = lane; e < CHR * BC; e += 64) {
-                const int jl = e / CHR, il = e - jl * CHR;
-                const int I = I0 + il, J = J0 + jl;
-                if (I < nloc && J < nloc && !(diag && J <= I)) Ec[int64_t(J) * nloc + I] = stg[il * BP + jl];
+            {
+                const int msub = lane / CHR, il = lane - msub * CHR, I = I0 + il;
+                if (msub < MPI && I < nloc)
+#pragma unroll 4
+                    for (int it = 0; it < BC / MPI; it++) {
+                        const int jl = it * MPI + msub, J = J0 + jl;
+                        if (J < nloc && !(diag && J <= I)) Ec[J * nloc + I] = stg[il * BP + jl];
+                    }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
