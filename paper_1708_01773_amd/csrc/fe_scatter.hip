@@ -27,6 +27,7 @@
 //    entry is a sum of per-axis terms, tabulated per row in LDS, and every
 //    contribution of an entry is loaded before any is added.
 #include <algorithm>
+#include <type_traits>
 
 #include "fe_internal.h"
 
@@ -289,8 +290,12 @@ __device__ __forceinline__ void build_row_tables(const SpaceArgs &s, const RowGe
 
 // Entry (row, position pos): contributions of cells u = d0 + 2 d1 + 4 d2
 // (d_r < cnt_r) loaded together and summed in ascending u, which is
-// ascending cell id, the summation order of every CSR entry.
-template <int NC, typename ET>
+// ascending cell id, the summation order of every CSR entry.  RM bit r says
+// whether the row node lies in two cells along axis r; a column shares at
+// most the row node's cells, so u with d_r = 1 where bit r is clear are
+// never loaded (the bit pattern is the same for the whole row, so each
+// pattern is its own instantiation).
+template <int NC, typename ET, int RM = 7>
 __device__ __forceinline__ double entry_from_tables(const RowTables &t, const ET *__restrict__ E, int64_t base,
                                                     int j0, int j1, int j2)
 {
@@ -308,12 +313,14 @@ __device__ __forceinline__ double entry_from_tables(const RowTables &t, const ET
         ET v[8];
 #pragma unroll
         for (int u = 0; u < 8; u++) {
+            if ((u & ~RM) != 0) continue;
             const int d0 = u & 1, d1 = (u >> 1) & 1, d2 = u >> 2;
             const bool ok = d0 < n0 && d1 < n1 && d2 < n2;
             v[u] = E[base + (ok ? (d0 ? a1 : a0) + (d1 ? b1 : b0) + (d2 ? c1 : c0) : a0 + b0 + c0)];
         }
 #pragma unroll
         for (int u = 0; u < 8; u++) {
+            if ((u & ~RM) != 0) continue;
             const int d0 = u & 1, d1 = (u >> 1) & 1, d2 = u >> 2;
             if (d0 < n0 && d1 < n1 && d2 < n2) sum += double(v[u]);
         }
@@ -397,66 +404,99 @@ __device__ __forceinline__ void k5_entries_body(const SpaceArgs &s, const ET *__
         A[r].N = int32_t(s.ax[r].N);
         A[r].swlo = A[r].lo * (k + 1) + k * ((A[r].lo + k - 1) / k);
     }
-    for (int64_t row = lw; row < s.n_rows; row += nw) {
-        const RowGeom g = row_geom_closed<NC>(s, A, kinv, row);
+    // A wave takes a node: its NC rows share the geometry and the tables, and
+    // their CSR values are one contiguous range of NC len positions (row c
+    // starts at c len), streamed as one.
+    const int64_t n_nodes = s.n_rows / NC;
+    for (int64_t node = lw; node < n_nodes; node += nw) {
+        const int64_t row0 = node * NC;
+        const RowGeom g = row_geom_closed<NC>(s, A, kinv, row0);
         build_row_tables(s, g, NC, t, lane);
-        // rhs: lanes u < 8 load the loads of the row node's cells u = d0 + 2 d1 + 4 d2
+        int32_t e0lo, e0hi, e1lo, e1hi, e2lo, e2hi;  // the node's cells along each axis
+        axis_cells(g.I0, g.v0, g.m0, g.I0, s.ax[0].n, e0lo, e0hi);
+        axis_cells(g.I1, g.v1, g.m1, g.I1, s.ax[1].n, e1lo, e1hi);
+        axis_cells(g.I2, g.v2, g.m2, g.I2, s.ax[2].n, e2lo, e2hi);
+        // rhs: lane 8 c + u loads component c of the node's cell u = d0 + 2 d1 + 4 d2
         double fu = 0.0;
         bool fok = false;
-        if (lane < 8) {
-            int32_t e0lo, e0hi, e1lo, e1hi, e2lo, e2hi;
-            axis_cells(g.I0, g.v0, g.m0, g.I0, s.ax[0].n, e0lo, e0hi);
-            axis_cells(g.I1, g.v1, g.m1, g.I1, s.ax[1].n, e1lo, e1hi);
-            axis_cells(g.I2, g.v2, g.m2, g.I2, s.ax[2].n, e2lo, e2hi);
-            const int32_t e0 = e0lo + (lane & 1), e1 = e1lo + ((lane >> 1) & 1), e2 = e2lo + (lane >> 2);
+        if (lane < 8 * NC) {
+            const int u = lane % 8, c = lane / 8;
+            const int32_t e0 = e0lo + (u & 1), e1 = e1lo + ((u >> 1) & 1), e2 = e2lo + (u >> 2);
             fok = e0 <= e0hi && e1 <= e1hi && e2 <= e2hi;
             if (fok) {
                 const int64_t cell = e0 + int64_t(s.ax[0].n) * (e1 + int64_t(s.ax[1].n) * e2);
                 const int la = (int(g.I0 - int64_t(e0) * k) +
-                                k1 * (int(g.I1 - int64_t(e1) * k) + k1 * int(g.I2 - int64_t(e2) * k))) * NC + g.c;
+                                k1 * (int(g.I1 - int64_t(e1) * k) + k1 * int(g.I2 - int64_t(e2) * k))) * NC + c;
                 fu = F[cell * s.nloc + la];
             }
         }
         wave_lds_fence();
         const int wx = g.w0 * NC;   // entries per x-run
         const int len = wx * g.w1 * g.w2;
-        const int64_t base = int64_t(g.c) * s.nloc;
-        // the diagonal's position
-        const int pd = ((int(g.I2 - g.cl2) * g.w1 + int(g.I1 - g.cl1)) * g.w0 + int(g.I0 - g.cl0)) * NC + g.c;
-        // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8] (p < 2^12, d <= 27)
+        // the diagonal node's position in a row (row c's diagonal at c len + pdn + c)
+        const int pdn = ((int(g.I2 - g.cl2) * g.w1 + int(g.I1 - g.cl1)) * g.w0 + int(g.I0 - g.cl0)) * NC;
+        // floor(p / d) = (p m) >> 20 for m in [2^20 / d, 2^20 / d + 8] (p < 2^12, d <= 27;
+        // positions within a row are below len <= 27 * 9 * 9)
         const uint32_t mx = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(wx))) + 2u;
         const uint32_t my = uint32_t(1048576.0f * __builtin_amdgcn_rcpf(float(g.w1))) + 2u;
-        auto decode = [&](int pos, int &j0, int &j1, int &j2, int &cc) {
+        auto decode = [&](int P, int &c, int &j0, int &j1, int &j2, int &cc) {
+            c = NC == 1 ? 0 : (P >= len ? 1 : 0) + (NC == 3 && P >= 2 * len ? 1 : 0);
+            const int pos = P - c * len;
             const int q = int((uint32_t(pos) * mx) >> 20), x = pos - q * wx;
             j2 = int((uint32_t(q) * my) >> 20);
             j1 = q - j2 * g.w1;
             j0 = x / NC;
             cc = x - j0 * NC;
         };
-        // two entries per lane and step (positions pos, pos + 64), their loads in flight together
-        for (int pos = lane; pos < len; pos += 128) {
-            int a0, a1, a2, ac, b0 = 0, b1 = 0, b2 = 0, bc = 0;
-            decode(pos, a0, a1, a2, ac);
-            const bool hb = pos + 64 < len;
-            if (hb) decode(pos + 64, b0, b1, b2, bc);
-            const double va = entry_from_tables<NC>(t, E, base + ac, a0, a1, a2);
-            const double vb = hb ? entry_from_tables<NC>(t, E, base + bc, b0, b1, b2) : 0.0;
-            values[g.start + pos] = va;
-            if (pos == pd) dinv[row] = 1.0 / va;
-            if (hb) {
-                values[g.start + pos + 64] = vb;
-                if (pos + 64 == pd) dinv[row] = 1.0 / vb;
+        const int total = NC * len;
+        // two entries per lane and step (positions P, P + 64), their loads in flight together
+        auto entries = [&](auto rm) {
+            constexpr int RM = decltype(rm)::value;
+            for (int P = lane; P < total; P += 128) {
+                int ca, a0, a1, a2, ac, cb = 0, b0 = 0, b1 = 0, b2 = 0, bc = 0;
+                decode(P, ca, a0, a1, a2, ac);
+                const bool hb = P + 64 < total;
+                if (hb) decode(P + 64, cb, b0, b1, b2, bc);
+                const double va = entry_from_tables<NC, ET, RM>(t, E, int64_t(ca) * s.nloc + ac, a0, a1, a2);
+                const double vb =
+                    hb ? entry_from_tables<NC, ET, RM>(t, E, int64_t(cb) * s.nloc + bc, b0, b1, b2) : 0.0;
+                values[g.start + P] = va;
+                if (P == ca * len + pdn + ca) dinv[row0 + ca] = 1.0 / va;
+                if (hb) {
+                    values[g.start + P + 64] = vb;
+                    if (P + 64 == cb * len + pdn + cb) dinv[row0 + cb] = 1.0 / vb;
+                }
             }
+        };
+        if constexpr (sizeof(ET) == 4) {
+            // FP32 loads are unconditional: bound them by the node's cells
+            const int rm = __builtin_amdgcn_readfirstlane((e0hi > e0lo ? 1 : 0) | (e1hi > e1lo ? 2 : 0) |
+                                                          (e2hi > e2lo ? 4 : 0));
+            switch (rm) {
+                case 0: entries(std::integral_constant<int, 0>{}); break;
+                case 1: entries(std::integral_constant<int, 1>{}); break;
+                case 2: entries(std::integral_constant<int, 2>{}); break;
+                case 3: entries(std::integral_constant<int, 3>{}); break;
+                case 4: entries(std::integral_constant<int, 4>{}); break;
+                case 5: entries(std::integral_constant<int, 5>{}); break;
+                case 6: entries(std::integral_constant<int, 6>{}); break;
+                default: entries(std::integral_constant<int, 7>{}); break;
+            }
+        } else {
+            entries(std::integral_constant<int, 7>{});
         }
-        // rhs summed in ascending cell order
-        double f = 0.0;
+        // rhs of each row summed in ascending cell order
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const double fv = __shfl(fu, u);
-            const bool ok = __shfl(int(fok), u) != 0;
-            if (ok) f += fv;
+        for (int c = 0; c < NC; c++) {
+            double f = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const double fv = __shfl(fu, 8 * c + u);
+                const bool ok = __shfl(int(fok), 8 * c + u) != 0;
+                if (ok) f += fv;
+            }
+            if (lane == 0) rhs[row0 + c] = f;
         }
-        if (lane == 0) rhs[row] = f;
         wave_lds_fence();
     }
 }
@@ -500,7 +540,7 @@ fe_status launch_scatter(const SpaceArgs &sa, const ElemLayout &el, const void *
 #undef FE_K5Q
     } else {
         // wave per row, rows interleaved over a grid that fills the chip
-        const int64_t grid = std::min<int64_t>((sa.n_rows + 3) / 4, 8192);
+        const int64_t grid = std::min<int64_t>((sa.n_rows / sa.ncomp + 3) / 4, 8192);
 #define FE_K5E(NCV, T)                                                                                              \
     hipLaunchKernelGGL((k5_entries_kernel<NCV, T>), dim3(grid), dim3(256), 0, s, sa, static_cast<const T *>(ws), F, \
                        values, rhs, dinv)
@@ -525,7 +565,7 @@ int64_t scatter_blocks(const SpaceArgs &sa, const ElemLayout &el)
 {
     if (sa.n_rows == 0) return 0;
     if (el.cb > 1) return (q1_chunks(sa) + 3) / 4;
-    return std::min<int64_t>((sa.n_rows + 3) / 4, 8192);
+    return std::min<int64_t>((sa.n_rows / sa.ncomp + 3) / 4, 8192);
 }
 
 fe_status launch_scatter_batch(const AsmJob &h, const ElemLayout &el, const AsmJob *jobs, const int32_t *boff,

@@ -61,3 +61,38 @@ def test_fp64_matrix_cores_are_deterministic():
     A.assemble()
     torch.cuda.synchronize()
     assert torch.equal(v1, A.values)
+
+
+@pytest.mark.parametrize("prec,k,prob,n,faces", [("fp32", 2, "elasticity", [3, 3, 3], None),
+                                                 ("bf16", 4, "elasticity", [2, 2, 3], 0),
+                                                 ("fp16", 3, "poisson", [3, 2, 3], 0b010110),
+                                                 ("fp32", 1, "poisson", [4, 3, 3], 0)])
+def test_scatter_of_32bit_element_matrices_is_their_ordered_sum(prec, k, prob, n, faces):
+    """Each CSR value is, bit for bit, the FP64 sum over the cells that share
+    the entry, in ascending cell order, of the GPU's own element-matrix
+    entries (FP32 widened); every dinv entry is 1 / its diagonal value.  Meshes
+    two cells wide or more, so that vertex rows gather from eight cells."""
+    say(f"[scatter fp32] {prec} k={k} {prob} n={n} faces={faces}")
+    pair = Pair(3, n, k, prob, precision=prec, faces=faces, seed=23)
+    A = pair.gpu_assembly()
+    S = pair.system
+    cells = list(range(pair.P.ncells))
+    Es, _ = element_matrices(pair, A, cells)
+    ref = {}
+    for c in cells:
+        d = S.cell_dofs[c]
+        E = Es[c]
+        for a in range(len(d)):
+            if d[a] < 0:
+                continue
+            for b in range(len(d)):
+                if d[b] >= 0:
+                    key = (int(d[a]), int(d[b]))
+                    ref[key] = ref.get(key, 0.0) + float(E[a, b])
+    rowptr, colind = S.rowptr, S.colind
+    vals = A.values.cpu().numpy()
+    want = np.array([ref[(r, int(colind[j]))] for r in range(S.nfree) for j in range(rowptr[r], rowptr[r + 1])])
+    assert len(want) == len(vals)
+    np.testing.assert_array_equal(vals, want)
+    diag = np.array([ref[(r, r)] for r in range(S.nfree)])
+    np.testing.assert_array_equal(A.dinv.cpu().numpy(), 1.0 / diag)
