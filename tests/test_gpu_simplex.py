@@ -262,6 +262,43 @@ def test_vector_element_system_matches_oracle(case):
     assert torch.equal(v1, G.values)
 
 
+@pytest.mark.parametrize("family", ["nedelec", "raviart_thomas", "nedelec2"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_vector_single_cell_with_and_without_free_dofs(family, dim):
+    """One reference-shaped cell with its vertices listed out of order: with a
+    zero trace every edge, facet and face DOF is fixed (second order in 2D keeps
+    its two interior DOFs); without, every DOF is free and the system is the
+    cell's matrix in the global frame."""
+    if dim == 3:
+        v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64) * 0.7
+        c = np.array([[2, 0, 3, 1]], dtype=np.int32)
+    else:
+        v = np.array([[0, 0], [1, 0], [0.2, 0.9]], dtype=np.float64)
+        c = np.array([[1, 2, 0]], dtype=np.int32)
+    say(f"[vector single cell] {family} dim={dim}")
+    for dirichlet in (True, False):
+        coeff = F.make_coeff("poisson", "fp64", source_kind=1, source=(1.0, -0.5, 0.25), dim=dim,
+                             faces=None if dirichlet else 0)
+        G = F.Simplex(dim, v, c, 0, coeff, cell_coeff=np.array([1.3]), family=family, kappa=0.8)
+        G.assemble()
+        torch.cuda.synchronize()
+        S = O.VectorSystem(family, dim, v, c, coef=np.array([1.3]), kappa=0.8, source_kind=1,
+                           source=(1.0, -0.5, 0.25), dirichlet=dirichlet)
+        assert S.ok
+        assert (G.n_rows, G.nnz, G.n_nodes) == (S.nfree, S.nnz, S.nent)
+        np.testing.assert_array_equal(G.cell_dofs().cpu().numpy(), S.cell_dofs)
+        if dirichlet:
+            assert G.n_rows == (2 if (family == "nedelec2" and dim == 2) else 0)
+        else:
+            assert G.n_rows == G.cell_dofs().shape[1]
+        if G.n_rows:
+            np.testing.assert_array_equal(G.rowptr.cpu().numpy(), S.rowptr)
+            np.testing.assert_array_equal(G.colind[: G.nnz].cpu().numpy(), S.colind)
+            assert rel(G.values[: G.nnz].cpu().numpy(), S.values) <= MATRIX_RTOL
+            assert rel(G.rhs[: G.n_rows].cpu().numpy(), S.rhs) <= MATRIX_RTOL
+            assert rel(G.dinv[: G.n_rows].cpu().numpy(), S.dinv) <= MATRIX_RTOL
+
+
 @pytest.mark.parametrize("family,dim,n", [("nedelec", 3, [3, 3, 2]), ("raviart_thomas", 3, [3, 2, 2]),
                                           ("nedelec", 2, [6, 5]), ("nedelec2", 3, [2, 2, 2]),
                                           ("nedelec2", 2, [5, 4])])
