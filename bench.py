@@ -554,6 +554,14 @@ NEDELEC_WORKLOAD = dict(dim=3, n=64, kappa=1.0, rtol=1e-8,
                              "assembly + Jacobi-PCG (CSR SpMV) to rtol 1e-8")
 
 
+NEDELEC2_WORKLOAD = dict(dim=3, n=24, kappa=1.0, rtol=1e-8,
+                         text="second-order Nedelec elements on tetrahedra (two DOFs per edge and per face): the "
+                              "Kuhn subdivision of the 24^3 unit-cube brick (82,944 tetrahedra, jittered +-0.2h, seed "
+                              "17080), curl(k curl u) + u = f with lognormal k per cell (seed 17081), f = (2 pi^2 + 1) "
+                              "(sin pi y sin pi z, sin pi z sin pi x, sin pi x sin pi y), zero tangential trace; FP64 "
+                              "assembly + Jacobi-PCG (CSR SpMV) to rtol 1e-8")
+
+
 def simplex_element_bytes(ncells, ntri, nloc, nverts, dim):
     """Algorithmic bytes of the element kernel: the element matrices' upper
     triangles and the loads written, connectivity, coefficients and vertex
@@ -593,12 +601,13 @@ def simplex_cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=12, cg_its=100)
 
 
 def simplex_form(args, F, torch, steps=3, warmup=1, family=None):
-    """The simplicial workload (Lagrange P2, or with family "nedelec" the
-    lowest-order edge elements): a step is the assembly (element kernel +
-    gathers through the stored map) + Jacobi-PCG on the CSR, the numbering,
-    pattern and gather map built once before timing (Sect. 11.1)."""
+    """The simplicial workload (Lagrange P2, or with family "nedelec" /
+    "nedelec2" the first- / second-order edge elements): a step is the
+    assembly (element kernel + gathers through the stored map) + Jacobi-PCG
+    on the CSR, the numbering, pattern and gather map built once before
+    timing (Sect. 11.1)."""
     from fe_inputs import lognormal_coefficients, simplex_mesh
-    wl = SIMPLEX_WORKLOAD if family is None else NEDELEC_WORKLOAD
+    wl = {None: SIMPLEX_WORKLOAD, "nedelec": NEDELEC_WORKLOAD, "nedelec2": NEDELEC2_WORKLOAD}[family]
     dim, n = wl["dim"], wl["n"]
     v, c = simplex_mesh(dim, n, jitter=0.2)
     coef = lognormal_coefficients(c.shape[0])
@@ -627,7 +636,7 @@ def simplex_form(args, F, torch, steps=3, warmup=1, family=None):
         G.assemble(stream)
         e1.record(stream)
         x.zero_()
-        return F.pcg_solve(G.csr, G.rhs, x, wl["rtol"], 100000, ws, stream), e0, e1
+        return F.pcg_solve(G.csr, G.rhs, x, wl["rtol"], 200000, ws, stream), e0, e1
 
     for _ in range(warmup):
         step()
@@ -1042,7 +1051,8 @@ def main():
                     help="thin the stream to requests of at most this many unknowns (default: every request)")
     ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--form", default=None, choices=["batch", "serve", "precision", "dg", "stokes", "simplex", "nedelec"],
+    ap.add_argument("--form", default=None,
+                    choices=["batch", "serve", "precision", "dg", "stokes", "simplex", "nedelec", "nedelec2"],
                     help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -1088,6 +1098,11 @@ def main():
     if args.form == "nedelec":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "nedelec", **simplex_form(args, F, torch, family="nedelec")}), flush=True)
+        return
+    if args.form == "nedelec2":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "nedelec2", **simplex_form(args, F, torch, steps=2, warmup=1, family="nedelec2")}),
+              flush=True)
         return
     if args.form == "stokes":
         torch.cuda.set_device(0)
