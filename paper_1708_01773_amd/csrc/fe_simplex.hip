@@ -223,6 +223,7 @@ __global__ __launch_bounds__(256) void sx_element_kernel(SxArgs sa, const double
         const int64_t Kc = K0 + c;
         double f = 0.0;
         if (sa.source_kind != FE_SOURCE_NONE) {
+#pragma unroll 4
             for (int q = 0; q < S::NQ; q++) f = __fma_rn(sG[c][q], phiq[q * S::NN + a], f);
             f *= sa.source[i];
         }
@@ -303,11 +304,13 @@ __global__ __launch_bounds__(256) void sx_vector_kernel(SxArgs sa, double kappa,
     __shared__ double sM[S::CPB][DIM * DIM];  // pull-back of the load: J^-1 or J^T / det J
     __shared__ double sDet[S::CPB];
     __shared__ double sG[S::CPB][S::NQ][DIM];
+    __shared__ double sPh[S::NQ * S::ND * DIM];  // reference shape functions at the rule's points
     const int tid = threadIdx.x;
     const int64_t K0 = xcd_block(blockIdx.x, gridDim.x) * S::CPB;
     const int ncl = sa.ncells - K0 < S::CPB ? int(sa.ncells - K0) : S::CPB;
     for (int t = tid; t < S::NP * S::NTRI; t += blockDim.x) sTab[t] = tab[t];
     for (int t = tid; t < S::NTRI; t += blockDim.x) sTri[t] = tri[t];
+    for (int t = tid; t < S::NQ * S::ND * DIM; t += blockDim.x) sPh[t] = phq[t];
     for (int c = tid; c < ncl; c += blockDim.x) {
         const int64_t Kc = K0 + c;
         int32_t g[NV];
@@ -459,10 +462,12 @@ __global__ __launch_bounds__(256) void sx_vector_kernel(SxArgs sa, double kappa,
     for (int e = tid; e < ncl * S::ND; e += blockDim.x) {
         const int c = e / S::ND, a = e - c * S::ND;
         double f = 0.0;
+        // (unrolled over all points the loop held every operand: 256 VGPRs, two waves per SIMD)
         if (sa.source_kind != FE_SOURCE_NONE)
+#pragma unroll 3
             for (int q = 0; q < S::NQ; q++)
 #pragma unroll
-                for (int r = 0; r < DIM; r++) f = __fma_rn(sG[c][q][r], phq[(q * S::ND + a) * DIM + r], f);
+                for (int r = 0; r < DIM; r++) f = __fma_rn(sG[c][q][r], sPh[(q * S::ND + a) * DIM + r], f);
         F[(K0 + c) * S::ND + a] = sSg[c][a] * f;
     }
 }
