@@ -1060,8 +1060,9 @@ def main():
                     help="only measure this GPU's achievable rates (copy, read, library GEMMs) for context")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard as "
-              f"described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard by "
+              f"cells, each GPU owning its rows with one layer of ghost cells, and exchange a halo of p and two "
+              f"scalars per CG iteration)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
