@@ -378,13 +378,12 @@ __global__ __launch_bounds__(256, 2) void k3_mfma_batch_kernel(const AsmJob *__r
 // quarter-wave reads sit in distinct banks).  They are computed once per cell;
 // then each wave takes whole node-tile pairs in turn, accumulates the pair's
 // blocks over all points and stores them, so no accumulator outlives its pair
-// and no workgroup repeats another's gradients.  At Q4 a pair's block goes
-// out through a per-wave LDS chunk of 8 node rows (16 for Poisson), written
-// as rows of the block and of its mirror, consecutive lanes on consecutive
+// and no workgroup repeats another's gradients.  A pair's block goes out
+// through a per-wave LDS chunk of 8 node rows (16 for Poisson), written as
+// rows of the block and of its mirror, consecutive lanes on consecutive
 // addresses: stored straight from the accumulators, one store instruction
 // touches up to 32 rows and makes some 28 write requests to L2, which then
-// bounds the kernel.  At Q2 and Q3 the staging area would cost workgroups
-// per CU, and the direct stores are faster.  The operand is scaled by a
+// bounds the kernel.  The operand is scaled by a
 // power of two per cell (~ h / sqrt(max_q w_q)) so that it sits near 1; the
 // product is unscaled exactly.  The load vector is the FP64 sum of the slab
 // kernel, in the same order.
@@ -411,7 +410,6 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
     constexpr int NCP = PROB == 1 ? DIM * DIM : 1;
     constexpr int TPQ = NTH / NQP;  // threads per point in the gradient stage
     static_assert(NTH % NQP == 0 && NNP % TPQ == 0, "gradient stage shape");
-    constexpr bool STAGE = NNP == 128;            // output through LDS
     constexpr int CH = PROB == 1 ? 8 : 16;        // node rows per output chunk
     constexpr int BC = 16 * NC, BP = BC + 1;      // block columns, staging pitch
     constexpr int CHR = CH * NC;                  // block rows per chunk
@@ -431,7 +429,7 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
     __shared__ double sDet0, sAlpha;
     __shared__ int sBad;
     __shared__ __attribute__((aligned(16))) S sG[DIM][NNP][PITCH];
-    __shared__ Out sStage[STAGE ? NW : 1][STAGE ? CHR * BP : 1];
+    __shared__ Out sStage[NW][CHR * BP];
 
     if (tid < 8) {
         const int64_t e0 = cell % m.n0, e1 = (cell / m.n0) % m.n1, e2 = cell / (int64_t(m.n0) * m.n1);
@@ -539,38 +537,6 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
                     for (int c2 = 0; c2 < DIM; c2++)
                         acc[c1 * DIM + c2] = Pol::mma(av[c1], bv[c2], acc[c1 * DIM + c2]);
             }
-        }
-        if constexpr (!STAGE) {
-            const int col = tb * 16 + i16;
-            const bool diag = ta == tb;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int row = ta * 16 + 4 * g4 + r;
-                if (row >= nn || col >= nn) continue;
-                // on a diagonal tile only the upper triangle is taken, and mirrored
-                if (diag && row > col) continue;
-                if (PROB == 0) {
-                    const Out v = Out(double(acc[0][r]) * unscale);
-                    Ec[int64_t(row) * nloc + col] = v;
-                    if (row != col) Ec[int64_t(col) * nloc + row] = v;
-                } else {
-                    double tr = 0.0;
-#pragma unroll
-                    for (int l = 0; l < DIM; l++) tr += double(acc[l * DIM + l][r]);
-#pragma unroll
-                    for (int c1 = 0; c1 < DIM; c1++)
-#pragma unroll
-                        for (int c2 = 0; c2 < DIM; c2++) {
-                            if (row == col && c1 > c2) continue;
-                            const double v = el_value(p.lambda, p.mu, double(acc[c1 * DIM + c2][r]),
-                                                      double(acc[c2 * DIM + c1][r]), tr, c1 == c2);
-                            const Out o = Out(v * unscale);
-                            Ec[int64_t(row * NC + c1) * nloc + col * NC + c2] = o;
-                            if (row != col || c1 != c2) Ec[int64_t(col * NC + c2) * nloc + row * NC + c1] = o;
-                        }
-                }
-            }
-            continue;
         }
         // The staged chunk holds block rows (rl - ch0) NC + c1, columns
         // i16 NC + c2; on a diagonal tile only entries with block row <=
