@@ -869,12 +869,14 @@ class SimplexSystem:
 # Lowest-order Nedelec (edges, covariant Piola) and Raviart-Thomas (facets,
 # contravariant Piola) elements on simplices (fe_oracle_simplex.c)
 # ---------------------------------------------------------------------------
-FAMILIES = {"nedelec": 1, "raviart_thomas": 2, "nedelec2": 3}
+FAMILIES = {"nedelec": 1, "raviart_thomas": 2, "nedelec2": 3, "raviart_thomas2": 4}
 
 
 def vector_ndof(family, dim):
     if family == "nedelec2":
         return 20 if dim == 3 else 8
+    if family == "raviart_thomas2":
+        return 15 if dim == 3 else 8
     return (6 if dim == 3 else 3) if family == "nedelec" else dim + 1
 
 
@@ -924,8 +926,8 @@ def vector_number(family, dim, nverts, cells, dirichlet=True):
 
 class VectorSystem:
     """The oracle's free-free system of a vector element on a simplicial mesh
-    ("nedelec", "raviart_thomas": lowest order; "nedelec2": second-order
-    Nedelec): int coef curl.curl (div div) + kappa u.v, zero tangential
+    ("nedelec", "raviart_thomas": lowest order; "nedelec2", "raviart_thomas2":
+    second order): int coef curl.curl (div div) + kappa u.v, zero tangential
     (normal) trace on the boundary when dirichlet.  source_kind 1 constant,
     2 the manufactured field, 3 affine (12 coefficients, as a Dirichlet datum)."""
 

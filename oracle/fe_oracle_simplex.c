@@ -662,10 +662,14 @@ static int vx_ndof(int family, int dim)
 {
     if (family == 1) return dim == 3 ? 6 : 3;
     if (family == 2) return dim + 1;
+    if (family == 4) return dim == 3 ? 15 : 8;
     return dim == 3 ? 20 : 8;
 }
 
-static int vx_order(int family) { return family == 3 ? 2 : 1; }
+static int vx_order(int family) { return family >= 3 ? 2 : 1; }
+
+/* the H(div) families (contravariant map, divergence) */
+static int vx_contra(int family) { return family == 2 || family == 4; }
 
 static void vx_edge(int dim, int a, int *i, int *j)
 {
@@ -732,6 +736,21 @@ static void vx_prebasis(int family, int dim, int b, const double *x, double *v, 
         }
         return;
     }
+    if (family == 4) {
+        if (b < dim * (dim + 1)) { /* [P_1]^d as family 3 */
+            int c = b / (dim + 1), m = b % (dim + 1);
+            v[c] = m == 0 ? 1.0 : x[m - 1];
+            if (m > 0) dv[c * dim + m - 1] = 1.0;
+            return;
+        }
+        int m = b - dim * (dim + 1); /* x times x_m */
+        for (int c = 0; c < dim; c++) {
+            v[c] = x[c] * x[m];
+            dv[c * dim + c] += x[m];
+            dv[c * dim + m] += x[c];
+        }
+        return;
+    }
     if (b < dim) { /* constants e_b */
         v[b] = 1.0;
         return;
@@ -792,13 +811,62 @@ static double vx_moment(int family, int dim, int a, int b)
         }
         return s;
     }
-    if (family == 3 && dim == 2) { /* interior moments on the reference triangle */
-        int m = a - 6;
-        double qx[3 * 9], qw[9];
-        int nq = orc_sx_quadrature(2, 3, qx, qw);
+    if ((family == 3 && dim == 2) || (family == 4 && a >= dim * (dim + 1))) {
+        /* interior moments: the components' integrals over the reference cell */
+        int m = family == 3 ? a - 6 : a - dim * (dim + 1);
+        double qx[3 * 27], qw[27];
+        int nq = orc_sx_quadrature(dim, 3, qx, qw);
         for (int q = 0; q < nq; q++) {
             vx_prebasis(family, dim, b, qx + 3 * q, v, dv);
             s += qw[q] * v[m];
+        }
+        return s;
+    }
+    if (family == 4) { /* flux through facet a / d against the barycentric of its vertex a % d */
+        int iv[3], k = a % dim;
+        vx_facet(dim, a / dim, iv);
+        double y[3][3] = {{0}};
+        for (int t = 0; t < dim; t++) vx_ref_vertex(dim, iv[t], y[t]);
+        double Nf[3] = {0, 0, 0};
+        if (dim == 2) {
+            Nf[0] = y[1][1] - y[0][1];
+            Nf[1] = y[0][0] - y[1][0];
+        } else {
+            double e1[3], e2[3];
+            for (int t = 0; t < 3; t++) {
+                e1[t] = y[1][t] - y[0][t];
+                e2[t] = y[2][t] - y[0][t];
+            }
+            Nf[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            Nf[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            Nf[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        }
+        double fx[3 * 9], fw[9];
+        int nf;
+        if (dim == 2) {
+            orc_gauss_legendre(2, gx, gw);
+            for (int q = 0; q < 2; q++) {
+                fx[3 * q] = gx[q];
+                fw[q] = gw[q];
+            }
+            nf = 2;
+        } else {
+            nf = orc_sx_quadrature(2, 3, fx, fw);
+        }
+        for (int q = 0; q < nf; q++) {
+            /* barycentrics of the facet's vertices at the point */
+            double lam[3];
+            lam[1] = fx[3 * q];
+            lam[2] = dim == 3 ? fx[3 * q + 1] : 0.0;
+            lam[0] = 1.0 - lam[1] - lam[2];
+            for (int t = 0; t < dim; t++) {
+                p[t] = 0.0;
+                for (int r = 0; r < dim; r++) p[t] += lam[r] * y[r][t];
+            }
+            vx_prebasis(family, dim, b, p, v, dv);
+            double d = 0.0;
+            for (int t = 0; t < dim; t++) d += v[t] * Nf[t];
+            s += fw[q] * d * lam[k];
         }
         return s;
     }
@@ -847,7 +915,7 @@ static double vx_moment(int family, int dim, int a, int b)
 /* Change-of-basis matrix Phi (nd x nd) of the family.  Returns nd or -1. */
 int orc_vx_basis(int family, int dim, double *Phi)
 {
-    if (family < 1 || family > 3 || dim < 2 || dim > 3) return -1;
+    if (family < 1 || family > 4 || dim < 2 || dim > 3) return -1;
     int nd = vx_ndof(family, dim);
     double C[VX_MAXND * VX_MAXND], Ci[VX_MAXND * VX_MAXND];
     for (int a = 0; a < nd; a++)
@@ -924,6 +992,26 @@ static void vx_transform(int family, int dim, const int32_t *g, double *T)
 {
     int nd = vx_ndof(family, dim);
     memset(T, 0, sizeof(double) * nd * nd);
+    if (family == 4) {
+        /* a facet's moments: against the barycentric of each of its vertices,
+         * flux with N over the vertices in ascending global id; a local moment
+         * is the global one of the same vertex, times the parity of the
+         * permutation that sorts the facet's ids (the orientation of N) */
+        for (int f = 0; f <= dim; f++) {
+            int iv[3], rank[3], inv = 0;
+            vx_facet(dim, f, iv);
+            for (int x = 0; x < dim; x++) {
+                rank[x] = 0;
+                for (int y = 0; y < dim; y++) {
+                    if (g[iv[y]] < g[iv[x]]) rank[x]++;
+                    if (y > x && g[iv[x]] > g[iv[y]]) inv++;
+                }
+            }
+            for (int x = 0; x < dim; x++) T[(f * dim + x) * nd + f * dim + rank[x]] = (inv % 2) ? -1.0 : 1.0;
+        }
+        for (int a = dim * (dim + 1); a < nd; a++) T[a * nd + a] = 1.0; /* interior */
+        return;
+    }
     if (family != 3) {
         double sgn[6];
         vx_signs(family, dim, g, sgn);
@@ -975,7 +1063,7 @@ static void vx_field(int family, int dim, const double *x, double *m)
 {
     double s[3] = {0.0, 0.0, 0.0};
     for (int r = 0; r < dim; r++) s[r] = sin(M_PI * x[r]);
-    if (family == 2) {
+    if (vx_contra(family)) {
         for (int r = 0; r < dim; r++) m[r] = s[r];
     } else if (dim == 2) {
         m[0] = s[1];
@@ -1034,7 +1122,7 @@ int orc_vx_element(int family, int dim, const double *X, const int32_t *g, doubl
             for (int c = 0; c < dim; c++) {
                 double v = 0.0;
                 for (int r = 0; r < dim; r++)
-                    v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;
+                    v += !vx_contra(family) ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;
                 P[a * dim + c] = v;
             }
             if (dim == 3) {
@@ -1063,7 +1151,7 @@ int orc_vx_element(int family, int dim, const double *X, const int32_t *g, doubl
             fl[a] += wd * fa;
             for (int b = 0; b < nd; b++) {
                 double st = 0.0, ms = 0.0;
-                if (family != 2)
+                if (!vx_contra(family))
                     for (int c = 0; c < nc; c++) st += Cp[a * nc + c] * Cp[b * nc + c];
                 else
                     st = Dp[a] * Dp[b];
@@ -1098,7 +1186,7 @@ int orc_vx_element(int family, int dim, const double *X, const int32_t *g, doubl
 int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int32_t *cells, int dirichlet,
                   int64_t *dof_of, int64_t *code, int64_t *nent_out, int64_t *nfree_out, int64_t *nfixed_out)
 {
-    if (family < 1 || family > 3 || dim < 2 || dim > 3) return -1;
+    if (family < 1 || family > 4 || dim < 2 || dim > 3) return -1;
     int nd = vx_ndof(family, dim), nv = dim + 1, nedges = dim == 3 ? 6 : 3;
     for (int64_t t = 0; t < ncells * nv; t++)
         if (cells[t] < 0 || cells[t] >= nverts) return -1;
@@ -1115,9 +1203,15 @@ int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int
                 r->v[m++] = g[i];
                 r->v[m++] = g[j];
                 slot = family == 1 ? 0 : a % 2;
-            } else if (family == 3 && dim == 2) { /* interior: the cell's vertices */
+            } else if ((family == 3 && dim == 2) || (family == 4 && a >= dim * (dim + 1))) {
+                /* interior: the cell's vertices */
                 for (int t = 0; t < nv; t++) r->v[m++] = g[t];
-                slot = a - 6;
+                slot = family == 3 ? a - 6 : a - dim * (dim + 1);
+            } else if (family == 4) { /* facet a / d, slot a % d of its global frame */
+                int iv[3];
+                vx_facet(dim, a / dim, iv);
+                for (int t = 0; t < dim; t++) r->v[m++] = g[iv[t]];
+                slot = a % dim;
             } else {
                 int iv[3];
                 vx_facet(dim, family == 2 ? a : (a - 12) / 2, iv);
@@ -1178,6 +1272,8 @@ int orc_vx_number(int family, int dim, int64_t nverts, int64_t ncells, const int
                 int on;
                 if (family == 2) {
                     on = a == j;
+                } else if (family == 4) {
+                    on = a < dim * (dim + 1) && a / dim == j;
                 } else if (family == 1 || a < 2 * nedges) {
                     int i1, j1;
                     vx_edge(dim, family == 1 ? a : a / 2, &i1, &j1);
@@ -1262,7 +1358,7 @@ double orc_vx_l2_error(int family, int dim, const double *vxyz, int64_t ncells, 
                 for (int c = 0; c < dim; c++)
                     for (int r = 0; r < dim; r++) {
                         /* covariant J^-T phi, or contravariant J phi / det J */
-                        double m1 = family != 2 ? Ji[r * dim + c] : J[c * dim + r] / det;
+                        double m1 = !vx_contra(family) ? Ji[r * dim + c] : J[c * dim + r] / det;
                         uh[c] += u[a] * m1 * phi[a * dim + r];
                     }
             for (int r = 0; r < dim; r++) {

@@ -271,6 +271,7 @@ int main(void)
         run_vector(1, dim);
         run_vector(2, dim);
         run_vector(3, dim);
+        run_vector(4, dim);
     }
     for (int dim = 2; dim <= 3; dim++)
         for (int k = 1; k <= 3; k++) {

@@ -68,11 +68,11 @@ MUTANTS = {
     "vector_edge_orientation_ignored": ("sgn[a] = g[i] < g[j] ? 1.0 : -1.0;", "sgn[a] = 1.0;"),
     "vector_facet_orientation_ignored": ("sgn[a] = (inv % 2) ? -1.0 : 1.0;", "sgn[a] = 1.0;"),
     "vector_covariant_map_untransposed": (
-        "v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
-        "v += family != 2 ? Ji[c * dim + r] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;"),
+        "v += !vx_contra(family) ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
+        "v += !vx_contra(family) ? Ji[c * dim + r] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;"),
     "vector_contravariant_map_without_det": (
-        "v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
-        "v += family != 2 ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r];"),
+        "v += !vx_contra(family) ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r] / det;",
+        "v += !vx_contra(family) ? Ji[r * dim + c] * phi[a * dim + r] : J[c * dim + r] * phi[a * dim + r];"),
     "vector_curl_map_without_det": ("Cp[a * 3 + c] = v / det;", "Cp[a * 3 + c] = v;"),
     "vector_edge_tangent_reversed": ("d += v[t] * (xj[t] - xi[t]);", "d += v[t] * (xi[t] - xj[t]);"),
     "vector_boundary_edge_test": ("on = i1 != j && j1 != j;", "on = i1 != j || j1 != j;"),
@@ -82,6 +82,12 @@ MUTANTS = {
                                       "double qv = slot < 0 ? 1.0 : slot == 0 ? gx[q] : 1.0 - gx[q];"),
     "nedelec2_face_block_transposed": ("T[(a + m) * nd + a + b] = P[m + 1][b] - P[0][b];",
                                        "T[(a + b) * nd + a + m] = P[m + 1][b] - P[0][b];"),
+    "rt2_facet_parity_ignored": ("T[(f * dim + x) * nd + f * dim + rank[x]] = (inv % 2) ? -1.0 : 1.0;",
+                                 "T[(f * dim + x) * nd + f * dim + rank[x]] = 1.0;"),
+    "rt2_facet_vertex_order_ignored": ("T[(f * dim + x) * nd + f * dim + rank[x]] = (inv % 2) ? -1.0 : 1.0;",
+                                       "T[(f * dim + x) * nd + f * dim + x] = (inv % 2) ? -1.0 : 1.0;"),
+    "rt2_flux_weight_of_first_vertex": ("s += fw[q] * d * lam[k];", "s += fw[q] * d * lam[0];"),
+    "rt2_interior_key_slot": ("slot = family == 3 ? a - 6 : a - dim * (dim + 1);", "slot = family == 3 ? a - 6 : 0;"),
     "l2_error_dropped_jacobian": ("err2 += w * fabs(qp.detJ) * (ue - uh) * (ue - uh);",
                                   "err2 += w * (ue - uh) * (ue - uh);"),
 }
@@ -125,6 +131,9 @@ PIN_CALLS = [
     lambda: VX.test_nedelec2_interpolates_its_space_exactly(3),
     lambda: VX.test_nedelec2_linear_curl_free_patch_test(3, 2),
     lambda: VX.test_nedelec2_curl_curl_annihilates_gradients_of_p2(3, 2),
+    lambda: VX.test_rt2_interpolates_its_space_exactly(3),
+    lambda: VX.test_rt2_divergence_free_affine_patch_test(3, 2),
+    lambda: VX.test_rt2_div_div_kernel_is_the_discrete_curls(3, [2, 1, 1]),
 ]
 
 

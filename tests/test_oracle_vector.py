@@ -447,3 +447,181 @@ def test_nedelec2_second_order_convergence(dim, ns):
         errs.append(S.l2_error(S.solve(), 1.0, nq1=5))
     rate = math.log(errs[0] / errs[1]) / math.log(ns[1] / ns[0])
     assert 1.7 <= rate <= 2.5, (errs, rate)
+
+
+# ---------------------------------------------------------------------------
+# second-order Raviart-Thomas ("raviart_thomas2"): per facet the flux against
+# the barycentric of each of its vertices (N over the facet's vertices, in
+# ascending global id in the global frame), the components' integrals inside;
+# local moments = the global ones of the same vertex times the facet's parity
+# ---------------------------------------------------------------------------
+def _tet_rule():
+    """A degree-5 rule on the reference tetrahedron (collapsed Gauss, numpy)."""
+    x, w = _gl(4)
+    pts, wts = [], []
+    for i in range(4):
+        for j in range(4):
+            for k in range(4):
+                a = x[i]
+                b = (1 - a) * x[j]
+                c = (1 - a) * (1 - x[j]) * x[k]
+                pts.append((a, b, c))
+                wts.append(w[i] * w[j] * w[k] * (1 - a) ** 2 * (1 - x[j]))
+    return np.array(pts), np.array(wts)
+
+
+def flux_moments(u, ys):
+    """int over the facet with vertices ys (in the given order) of u . N times
+    the barycentric of each vertex, in the facet's parameter measure; N the
+    rotated edge (2D) or the cross product of the edges from ys[0] (3D)."""
+    ys = [np.asarray(y, dtype=np.float64) for y in ys]
+    if len(ys) == 2:
+        t = ys[1] - ys[0]
+        N = np.array([t[1], -t[0]])
+        x, w = _gl(4)
+        return sum(wt * (u(ys[0] + s * t) @ N) * np.array([1 - s, s]) for s, wt in zip(x, w))
+    N = np.cross(ys[1] - ys[0], ys[2] - ys[0])
+    P, W = _tri_rule()
+    out = np.zeros(3)
+    for (s0, s1), wt in zip(P, W):
+        out += wt * (u(ys[0] + s0 * (ys[1] - ys[0]) + s1 * (ys[2] - ys[0])) @ N) * np.array([1 - s0 - s1, s0, s1])
+    return out
+
+
+def _cell_rule(dim):
+    return _tri_rule() if dim == 2 else _tet_rule()
+
+
+def rt2_reference_moments(u, dim):
+    X = REF[dim]
+    out = []
+    for f in range(dim + 1):
+        out += list(flux_moments(u, [X[r] for r in range(dim + 1) if r != f]))
+    P, W = _cell_rule(dim)
+    out += list(sum(w * u(np.array(p)) for p, w in zip(P, W)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rt2_interpolates_its_space_exactly(dim):
+    """The interpolant sum_a sigma_a(v) phi_a reproduces fields of the space:
+    random affine fields ([P_1]^d) and x x_m."""
+    g = rng(31)
+    fields = []
+    for _ in range(3):
+        B, c = g.standard_normal((dim, dim)), g.standard_normal(dim)
+        fields.append(lambda x, B=B, c=c: B @ x + c)
+    for m in range(dim):
+        fields.append(lambda x, m=m: x * x[m])
+    for u in fields:
+        sig = rt2_reference_moments(u, dim)
+        for _ in range(4):
+            xi = g.dirichlet(np.ones(dim + 1))[:dim]
+            phi, _, _ = O.vector_shape("raviart_thomas2", dim, xi)
+            np.testing.assert_allclose(sig @ phi, u(xi), atol=1e-12)
+
+
+def _rt2_global_moments(u, v, c, S, dim):
+    """Global-frame DOF values of u: facets over their vertices in ascending
+    id; a cell's interior moments of the contravariant pull-back
+    det J J^-1 u on the reference cell."""
+    vals = np.full(S.nent, np.nan)
+    P, W = _cell_rule(dim)
+    for K, row in enumerate(S.dof_of):
+        gids = c[K]
+        for f in range(dim + 1):
+            ids = sorted(int(gids[r]) for r in range(dim + 1) if r != f)
+            vals[row[f * dim:(f + 1) * dim]] = flux_moments(u, [v[i] for i in ids])
+        X = v[gids]
+        J = (X[1:] - X[0]).T
+        pull = np.linalg.det(J) * np.linalg.inv(J)
+        vals[row[dim * (dim + 1):]] = sum(w * (pull @ u(X[0] + J @ np.array(p))) for p, w in zip(P, W))
+    return vals
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (3, 2)])
+def test_rt2_divergence_free_affine_patch_test(dim, n):
+    """u = B x + c with trace B = 0 has no divergence, so -grad(k div u) +
+    kappa u = kappa u and the natural boundary term vanishes: the discrete
+    solution is u's interpolant, exactly, on jittered shuffled meshes."""
+    v, c = simplex_mesh(dim, n, jitter=0.2, shuffle=True)
+    g = rng(32)
+    B = g.standard_normal((dim, dim))
+    B -= np.trace(B) / dim * np.eye(dim)
+    cv = g.standard_normal(dim)
+    kappa = 1.7
+    aff = []
+    for comp in range(dim):
+        aff += [kappa * cv[comp]] + list(kappa * B[comp]) + [0.0] * (3 - dim)
+    S = O.VectorSystem("raviart_thomas2", dim, v, c, kappa=kappa, source_kind=3, source=aff, dirichlet=False)
+    x = S.solve()
+    exact = _rt2_global_moments(lambda p: B @ p + cv, v, c, S, dim)
+    assert np.abs(x - exact).max() <= 1e-10 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("dim,n", [(2, [3, 2]), (3, [2, 1, 1])])
+def test_rt2_div_div_kernel_is_the_discrete_curls(dim, n):
+    """With no DOF fixed and kappa = 0, the div-div matrix's null space is the
+    divergence-free part of the space, which the exact sequence makes the
+    curls of the second-order Nedelec space (3D) or the rotated gradients of
+    P2 (2D): its rank is #RT2 - (#N2 - (#P2 - 1)) (3D), #RT2 - (#P2 - 1) (2D).
+    A facet whose two cells disagree on its orientation or vertex order breaks
+    the count."""
+    v, c = simplex_mesh(dim, n, jitter=0.2, shuffle=True)
+    S = O.VectorSystem("raviart_thomas2", dim, v, c, kappa=0.0, dirichlet=False)
+    _, code, _, _ = O.simplex_number(dim, 2, len(v), c, dirichlet=False)
+    npk = len(code)
+    if dim == 3:
+        _, ncode, nfree, _ = O.vector_number("nedelec2", dim, len(v), c, dirichlet=False)
+        kernel = nfree - (npk - 1)
+    else:
+        kernel = npk - 1
+    ev = np.linalg.eigvalsh(S.scipy().toarray())
+    rank = int((ev > 1e-9 * ev.max()).sum())
+    assert rank == S.nent - kernel, (S.nent, kernel, rank)
+    gap = ev[ev > 1e-9 * ev.max()].min() / ev.max()
+    assert gap > 1e-6 and np.abs(ev[: S.nent - rank]).max() < 1e-12 * ev.max()
+
+
+def test_rt2_div_div_annihilates_rotated_gradients_2d():
+    """The rotated gradients (d_y phi, -d_x phi) of the global P2 Lagrange
+    functions lie in the second-order Raviart-Thomas space; the div-div matrix
+    times the matrix of their global-frame moments vanishes."""
+    dim = 2
+    v, c = simplex_mesh(dim, [3, 2], jitter=0.2, shuffle=True)
+    S = O.VectorSystem("raviart_thomas2", dim, v, c, kappa=0.0, dirichlet=False)
+    node_of, code, _, _ = O.simplex_number(dim, 2, len(v), c, dirichlet=False)
+    G = np.zeros((S.nent, len(code)))
+    P, W = _cell_rule(dim)
+    for K in range(c.shape[0]):
+        X = v[c[K]]
+        J = (X[1:] - X[0]).T
+        Ji = np.linalg.inv(J)
+        pull = np.linalg.det(J) * Ji
+        gids = c[K]
+        row = S.dof_of[K]
+        for ln in range(node_of.shape[1]):
+            def rot(p, ln=ln):
+                _, d = O.simplex_shape(dim, 2, Ji @ (p - X[0]))
+                gr = Ji.T @ d[ln]
+                return np.array([gr[1], -gr[0]])
+            for f in range(3):
+                ids = sorted(int(gids[r]) for r in range(3) if r != f)
+                G[row[2 * f:2 * f + 2], node_of[K, ln]] = flux_moments(rot, [v[i] for i in ids])
+            G[row[6:8], node_of[K, ln]] = sum(w * (pull @ rot(X[0] + J @ np.array(p))) for p, w in zip(P, W))
+    A = S.scipy()
+    assert np.abs(G).max() > 0.1 and np.abs(A @ np.ones(S.nent)).max() > 1e-3
+    assert np.abs(A @ G).max() <= 1e-10 * np.abs(S.values).max()
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (4, 8)), (3, (2, 4))])
+def test_rt2_second_order_convergence(dim, ns):
+    kappa = 1.0
+    errs = []
+    for n in ns:
+        v, c = simplex_mesh(dim, n, jitter=0.15)
+        S = O.VectorSystem("raviart_thomas2", dim, v, c, kappa=kappa, source_kind=2,
+                           source=[math.pi ** 2 + kappa] * dim)
+        errs.append(S.l2_error(S.solve(), 1.0, nq1=5))
+    rate = math.log(errs[0] / errs[1]) / math.log(ns[1] / ns[0])
+    assert 1.7 <= rate <= 2.5, (errs, rate)
