@@ -436,9 +436,17 @@ fe_status fe_simplex_destroy(fe_simplex s);
  * times the global ones with a 2 x 2 block per edge (identity, or swapped and
  * negated) and per face (the local tangents in the global ones), and the
  * element matrix and load are returned in the global frame (T^T A T, T^T f).
+ * FE_RAVIART_THOMAS2: the second-order Raviart-Thomas element ([P_1]^d plus
+ * x times the linear monomials): per facet the fluxes (N as for
+ * FE_RAVIART_THOMAS) against the barycentric of each of its vertices, then
+ * the integrals of the d components over the reference cell (15 DOFs in 3D,
+ * 8 in 2D; local order: facet by facet, its vertices ascending, then the
+ * interior).  A facet's global frame lists its vertices in ascending global id;
+ * a local moment is the global moment of the same vertex times the parity of
+ * the facet's vertex order; matrix and load in the global frame as above.
  * FE_EINVAL for kappa < 0 or an unknown family; mesh errors as
  * fe_simplex_create. */
-enum { FE_NEDELEC = 1, FE_RAVIART_THOMAS = 2, FE_NEDELEC2 = 3 };
+enum { FE_NEDELEC = 1, FE_RAVIART_THOMAS = 2, FE_NEDELEC2 = 3, FE_RAVIART_THOMAS2 = 4 };
 fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, double kappa, const fe_coeff *coeff,
                                    fe_simplex *out);
 

@@ -719,6 +719,172 @@ __global__ __launch_bounds__(256) void sx_nedelec2_kernel(SxArgs sa, double kapp
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Second-order Raviart-Thomas elements (family 4): per facet the fluxes
+// against the barycentrics of its vertices, then the interior moments of the
+// components.  A facet's global frame lists its vertices in ascending global
+// id (N over them); the cell's moment against local vertex x is the global
+// one of the same vertex times the parity of the facet's vertex order, so
+// each global DOF I is one local DOF loc(I) with a sign: the cell's matrix in
+// the global frame has entries s_I s_J A(loc(I), loc(J)) and loads
+// s_I f(loc(I)).  A is the contraction of k / |det J| (div-div) and
+// kappa / |det J| J^T J (mass, contravariant map) with the reference products.
+template <int DIM>
+struct SxRt2Shape {
+    static constexpr int ND = DIM == 3 ? 15 : 8;
+    static constexpr int NTRI = ND * (ND + 1) / 2;
+    static constexpr int NPM = DIM * (DIM + 1) / 2;
+    static constexpr int NP = 1 + NPM;
+    static constexpr int NQ1 = 2 + (DIM + 1) / 2;
+    static constexpr int NQ = DIM == 3 ? NQ1 * NQ1 * NQ1 : NQ1 * NQ1;
+    static constexpr int CPB = DIM == 3 ? 16 : 32;
+};
+
+template <int DIM>
+__global__ __launch_bounds__(256) void sx_rt2_kernel(SxArgs sa, double kappa, const double *__restrict__ vxyz,
+                                                     const int32_t *__restrict__ cells,
+                                                     const double *__restrict__ coef,
+                                                     const double *__restrict__ tab,
+                                                     const int32_t *__restrict__ tri,
+                                                     const double *__restrict__ phq,
+                                                     const double *__restrict__ qxw, double *__restrict__ E,
+                                                     double *__restrict__ F)
+{
+    using S = SxRt2Shape<DIM>;
+    constexpr int NV = DIM + 1;
+    __shared__ double sTab[S::NP * S::NTRI];
+    __shared__ int32_t sTri[S::NTRI];
+    __shared__ double sC[S::CPB][S::NP];
+    __shared__ int32_t sLoc[S::CPB][S::ND];  // local DOF of global-frame DOF I
+    __shared__ double sSg[S::CPB][S::ND];    // and its sign
+    __shared__ double sX[S::CPB][NV * DIM];
+    __shared__ double sM[S::CPB][DIM * DIM];  // pull-back of the load: J^T / det J
+    __shared__ double sDet[S::CPB];
+    __shared__ double sG[S::CPB][S::NQ][DIM];
+    const int tid = threadIdx.x;
+    const int64_t K0 = xcd_block(blockIdx.x, gridDim.x) * S::CPB;
+    const int ncl = sa.ncells - K0 < S::CPB ? int(sa.ncells - K0) : S::CPB;
+    for (int t = tid; t < S::NP * S::NTRI; t += blockDim.x) sTab[t] = tab[t];
+    for (int t = tid; t < S::NTRI; t += blockDim.x) sTri[t] = tri[t];
+    for (int c = tid; c < ncl; c += blockDim.x) {
+        const int64_t Kc = K0 + c;
+        int32_t g[NV];
+        double X[NV][DIM];
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            g[j] = cells[Kc * NV + j];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) X[j][r] = vxyz[int64_t(g[j]) * DIM + r];
+        }
+        double J[DIM][DIM], det;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) J[r][s] = X[s + 1][r] - X[0][r];
+        if constexpr (DIM == 2) {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        } else {
+            det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) + J[0][1] * (J[1][2] * J[2][0] - J[1][0] * J[2][2]) +
+                  J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        }
+        const double ad = fabs(det), k = coef ? coef[Kc] : 1.0;
+        sC[c][0] = k / ad;
+        int p = 1;
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = r; s < DIM; s++) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < DIM; l++) v += J[l][r] * J[l][s];
+                sC[c][p++] = kappa / ad * v;
+            }
+        // facet frames: local vertex x of facet f -> global slot rank(x), sign the parity
+#pragma unroll
+        for (int f = 0; f < NV; f++) {
+            int iv[DIM], m = 0;
+#pragma unroll
+            for (int r = 0; r < NV; r++)
+                if (r != f) iv[m++] = r;
+            int inv = 0;
+#pragma unroll
+            for (int x = 0; x < DIM; x++)
+#pragma unroll
+                for (int y = x + 1; y < DIM; y++) inv += g[iv[x]] > g[iv[y]];
+            const double sg = (inv & 1) ? -1.0 : 1.0;
+#pragma unroll
+            for (int x = 0; x < DIM; x++) {
+                int rank = 0;
+#pragma unroll
+                for (int y = 0; y < DIM; y++) rank += g[iv[y]] < g[iv[x]];
+                sLoc[c][f * DIM + rank] = f * DIM + x;
+                sSg[c][f * DIM + rank] = sg;
+            }
+        }
+#pragma unroll
+        for (int a = DIM * NV; a < S::ND; a++) {
+            sLoc[c][a] = a;
+            sSg[c][a] = 1.0;
+        }
+#pragma unroll
+        for (int r = 0; r < DIM; r++)
+#pragma unroll
+            for (int s = 0; s < DIM; s++) sM[c][r * DIM + s] = J[s][r] / det;
+#pragma unroll
+        for (int j = 0; j < NV; j++)
+#pragma unroll
+            for (int r = 0; r < DIM; r++) sX[c][j * DIM + r] = X[j][r];
+        sDet[c] = ad;
+    }
+    __syncthreads();
+    if (sa.source_kind != FE_SOURCE_NONE)
+        for (int e = tid; e < ncl * S::NQ; e += blockDim.x) {
+            const int c = e / S::NQ, q = e - c * S::NQ;
+            double x[DIM], f[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) {
+                x[r] = sX[c][r];
+#pragma unroll
+                for (int t = 0; t < DIM; t++) x[r] += (sX[c][(t + 1) * DIM + r] - sX[c][r]) * qxw[q * (DIM + 1) + t];
+            }
+#pragma unroll
+            for (int r = 0; r < DIM; r++)
+                f[r] = sa.source_kind == FE_SOURCE_SINPROD ? sa.source[r] * sin(M_PI * x[r]) : sa.source[r];
+            const double w = qxw[q * (DIM + 1) + DIM] * sDet[c];
+#pragma unroll
+            for (int r = 0; r < DIM; r++) {
+                double v = 0.0;
+#pragma unroll
+                for (int t = 0; t < DIM; t++) v += sM[c][r * DIM + t] * f[t];
+                sG[c][q][r] = w * v;
+            }
+        }
+    __syncthreads();
+    for (int e = tid; e < ncl * S::NTRI; e += blockDim.x) {
+        const int c = e / S::NTRI, t = e - c * S::NTRI;
+        const int I = sTri[t] >> 16, Jx = sTri[t] & 0xffff;
+        const int a = sLoc[c][I], b = sLoc[c][Jx];
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        const int tl = lo * S::ND - lo * (lo - 1) / 2 + (hi - lo);
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < S::NP; p++) v = __fma_rn(sC[c][p], sTab[p * S::NTRI + tl], v);
+        E[(K0 + c) * S::NTRI + t] = sSg[c][I] * sSg[c][Jx] * v;
+    }
+    for (int e = tid; e < ncl * S::ND; e += blockDim.x) {
+        const int c = e / S::ND, I = e - c * S::ND;
+        const int a = sLoc[c][I];
+        double f = 0.0;
+        if (sa.source_kind != FE_SOURCE_NONE)
+#pragma unroll 4
+            for (int q = 0; q < S::NQ; q++)
+#pragma unroll
+                for (int r = 0; r < DIM; r++) f = __fma_rn(sG[c][q][r], phq[(q * S::ND + a) * DIM + r], f);
+        F[(K0 + c) * S::ND + I] = sSg[c][I] * f;
+    }
+}
+
 // values[j] = sum of E over the contributions of entry j, in list order.
 __global__ __launch_bounds__(256) void sx_gather_kernel(int64_t nnz, const int64_t *__restrict__ gptr,
                                                         const uint32_t *__restrict__ gsrc,
@@ -1112,7 +1278,7 @@ fe_status sx_finish(fe_simplex S, std::vector<int64_t> &pre, int64_t nnodes, con
 
 fe_status sx_setup(fe_simplex S, const int32_t *cells, const double *vxyz)
 {
-    const int dim = S->dim, k = S->k, nn = S->nn, nv = dim + 1, nc = S->ncomp;
+    const int dim = S->dim, k = S->k, nn = S->nn, nv = dim + 1;
     const int64_t ncells = S->ncells;
     std::vector<int> sl;
     sx_lattice(dim, k, sl);
@@ -1239,6 +1405,11 @@ void sxv_dof(int fam, int dim, int a, int &kind, int &ent, int &slot)
         kind = 0, ent = a, slot = 0;
     } else if (fam == 2) {
         kind = 1, ent = a, slot = 0;
+    } else if (fam == 4) {  // facet a / d, slot a % d (its vertices); then the interior
+        if (a < dim * (dim + 1))
+            kind = 1, ent = a / dim, slot = a % dim;
+        else
+            kind = 2, ent = 0, slot = a - dim * (dim + 1);
     } else if (a < 2 * ne) {
         kind = 0, ent = a / 2, slot = a % 2;
     } else if (dim == 3) {
@@ -1263,7 +1434,7 @@ fe_status sxv_setup(fe_simplex S, const int32_t *cells)
     const int dim = S->dim, nv = dim + 1, nd = S->nn, fam = S->family;
     const int64_t ncells = S->ncells;
     struct DofRec {
-        std::array<int32_t, 4> key;  // sorted vertex ids (padded with -1), slot
+        std::array<int32_t, 5> key;  // sorted vertex ids (up to a tetrahedron's four, padded with -1), slot
         int64_t cell;
         int32_t a;
     };
@@ -1273,7 +1444,7 @@ fe_status sxv_setup(fe_simplex S, const int32_t *cells)
         for (int a = 0; a < nd; a++) {
             int kind, ent, slot;
             sxv_dof(fam, dim, a, kind, ent, slot);
-            std::array<int32_t, 4> k{-1, -1, -1, slot};
+            std::array<int32_t, 5> k{-1, -1, -1, -1, slot};
             int m = 0;
             if (kind == 0) {
                 int i, j;
@@ -1362,7 +1533,16 @@ void sxv_prebasis(int fam, int dim, int b, const double *x, double *v, double *d
 {
     for (int c = 0; c < 3; c++) v[c] = 0.0;
     for (int t = 0; t < 9; t++) dv[t] = 0.0;
-    if (fam == 3) {
+    if (fam == 4 && b >= dim * (dim + 1)) {  // x times x_m
+        const int m = b - dim * (dim + 1);
+        for (int c = 0; c < dim; c++) {
+            v[c] = x[c] * x[m];
+            dv[c * dim + c] += x[m];
+            dv[c * dim + m] += x[c];
+        }
+        return;
+    }
+    if (fam == 3 || fam == 4) {
         if (b < dim * (dim + 1)) {
             const int c = b / (dim + 1), m = b % (dim + 1);
             v[c] = m == 0 ? 1.0 : x[m - 1];
@@ -1458,6 +1638,15 @@ double sxv_moment(int fam, int dim, int a, int b)
             }
         return acc;
     };
+    if (kind == 2 && dim == 3) {  // interior moments on the reference tetrahedron (degree 5)
+        std::vector<double> r;
+        sx_rule(3, 3, r);
+        for (size_t q = 0; q < r.size() / 4; q++) {
+            sxv_prebasis(fam, dim, b, &r[q * 4], v, dv);
+            s += r[q * 4 + 3] * v[slot];
+        }
+        return s;
+    }
     if (kind == 2) {
         return triangle([&](double u0, double u1) {
             double x[3] = {u0, u1, 0.0};
@@ -1478,7 +1667,9 @@ double sxv_moment(int fam, int dim, int a, int b)
         for (int q = 0; q < 3; q++) {
             for (int t = 0; t < 2; t++) p[t] = x0[t] + gx[q] * (x1[t] - x0[t]);
             sxv_prebasis(fam, dim, b, p, v, dv);
-            s += gw[q] * (v[0] * N[0] + v[1] * N[1]);
+            // family 4: against the barycentric of the facet's vertex `slot`
+            const double lam = fam != 4 ? 1.0 : slot == 0 ? 1.0 - gx[q] : gx[q];
+            s += gw[q] * (v[0] * N[0] + v[1] * N[1]) * lam;
         }
         return s;
     }
@@ -1487,7 +1678,7 @@ double sxv_moment(int fam, int dim, int a, int b)
         t1[t] = x1[t] - x0[t];
         t2[t] = x2[t] - x0[t];
     }
-    if (fam == 2) {
+    if (fam == 2 || fam == 4) {
         N[0] = t1[1] * t2[2] - t1[2] * t2[1];
         N[1] = t1[2] * t2[0] - t1[0] * t2[2];
         N[2] = t1[0] * t2[1] - t1[1] * t2[0];
@@ -1497,7 +1688,8 @@ double sxv_moment(int fam, int dim, int a, int b)
     return triangle([&](double u0, double u1) {
         for (int t = 0; t < 3; t++) p[t] = x0[t] + u0 * t1[t] + u1 * t2[t];
         sxv_prebasis(fam, dim, b, p, v, dv);
-        return v[0] * N[0] + v[1] * N[1] + v[2] * N[2];
+        const double lam = fam != 4 ? 1.0 : slot == 0 ? 1.0 - u0 - u1 : slot == 1 ? u0 : u1;
+        return (v[0] * N[0] + v[1] * N[1] + v[2] * N[2]) * lam;
     });
 }
 
@@ -1547,7 +1739,7 @@ fe_status sxv_tables(fe_simplex S)
             dvg[a] = dim == 3 ? dv[0] + dv[4] + dv[8] : dv[0] + dv[3];
         }
     };
-    const int nq1 = (fam == 3 ? 2 : 1) + (dim + 1) / 2;
+    const int nq1 = (fam >= 3 ? 2 : 1) + (dim + 1) / 2;
     std::vector<double> qxw;
     sx_rule(dim, nq1, qxw);
     const int nq = int(qxw.size() / (dim + 1));
@@ -1557,7 +1749,8 @@ fe_status sxv_tables(fe_simplex S)
     for (int q = 0; q < nq; q++)
         shape(&qxw[size_t(q) * (dim + 1)], &phq[size_t(q) * nd * dim], &cuq[size_t(q) * nd * ncu],
               &dvq[size_t(q) * nd]);
-    const int nps = (fam != 2 && dim == 3) ? 6 : 1, npm = dim * (dim + 1) / 2;
+    const bool hdiv = fam == 2 || fam == 4;
+    const int nps = (!hdiv && dim == 3) ? 6 : 1, npm = dim * (dim + 1) / 2;
     std::vector<int32_t> tri(ntri);
     {
         int t = 0;
@@ -1580,7 +1773,7 @@ fe_status sxv_tables(fe_simplex S)
                         tab[size_t(p) * ntri + t] += w * v;
                     }
             } else {
-                tab[t] += w * (fam != 2 ? cu[a] * cu[b] : dg[a] * dg[b]);
+                tab[t] += w * (!hdiv ? cu[a] * cu[b] : dg[a] * dg[b]);
             }
             int p = nps;
             for (int r = 0; r < dim; r++)
@@ -1688,9 +1881,22 @@ fe_status launch_sx_nedelec2(fe_simplex S, hipStream_t s)
     return FE_OK;
 }
 
+template <int DIM>
+fe_status launch_sx_rt2(fe_simplex S, hipStream_t s)
+{
+    using Sh = SxRt2Shape<DIM>;
+    const int64_t nb = (S->ncells + Sh::CPB - 1) / Sh::CPB;
+    if (nb == 0) return FE_OK;
+    hipLaunchKernelGGL((sx_rt2_kernel<DIM>), dim3(unsigned(nb)), dim3(256), 0, s, S->args, S->kappa, S->vxyz, S->cells,
+                       S->coef, S->tab, S->tri, S->phiq, S->qxw, S->E, S->F);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+}
+
 fe_status launch_elements(fe_simplex S, hipStream_t s)
 {
     if (S->family == 3) return S->dim == 3 ? launch_sx_nedelec2<3>(S, s) : launch_sx_nedelec2<2>(S, s);
+    if (S->family == 4) return S->dim == 3 ? launch_sx_rt2<3>(S, s) : launch_sx_rt2<2>(S, s);
     if (S->family == 1) return S->dim == 3 ? launch_sx_vector<3, 1>(S, s) : launch_sx_vector<2, 1>(S, s);
     if (S->family == 2) return S->dim == 3 ? launch_sx_vector<3, 2>(S, s) : launch_sx_vector<2, 2>(S, s);
     const bool el = S->args.problem == FE_ELASTICITY;
@@ -1776,7 +1982,6 @@ fe_status fe_simplex_create(const fe_simplex_desc *desc, int32_t order, const fe
         return set_error(FE_EINVAL, "unknown Dirichlet kind");
     fe_status vst = sx_validate(desc);
     if (vst != FE_OK) return vst;
-    const int nv = dim + 1;
     fe_simplex S = new fe_simplex_s();
     S->dim = dim;
     S->k = order;
@@ -1827,7 +2032,7 @@ fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, 
     *out = nullptr;
     const int dim = desc->dim;
     if (dim != 2 && dim != 3) return set_error(FE_EINVAL, "dim must be 2 or 3");
-    if (family != FE_NEDELEC && family != FE_RAVIART_THOMAS && family != FE_NEDELEC2)
+    if (family != FE_NEDELEC && family != FE_RAVIART_THOMAS && family != FE_NEDELEC2 && family != FE_RAVIART_THOMAS2)
         return set_error(FE_EINVAL, "unknown element family");
     if (!(kappa >= 0.0) || !std::isfinite(kappa)) return set_error(FE_EINVAL, "kappa must be finite and >= 0");
     if (coeff->precision != FE_FP64) return set_error(FE_EINVAL, "simplices integrate in FP64 only");
@@ -1842,7 +2047,10 @@ fe_status fe_simplex_create_vector(const fe_simplex_desc *desc, int32_t family, 
     S->k = 0;
     S->family = family;
     S->kappa = kappa;
-    S->nn = family == FE_NEDELEC ? (dim == 3 ? 6 : 3) : family == FE_NEDELEC2 ? (dim == 3 ? 20 : 8) : dim + 1;
+    S->nn = family == FE_NEDELEC        ? (dim == 3 ? 6 : 3)
+            : family == FE_NEDELEC2       ? (dim == 3 ? 20 : 8)
+            : family == FE_RAVIART_THOMAS2 ? (dim == 3 ? 15 : 8)
+                                           : dim + 1;
     S->ncomp = 1;
     S->nloc = S->nn;
     S->ntri = S->nloc * (S->nloc + 1) / 2;

@@ -18,8 +18,9 @@ FE_FP64, FE_FP32, FE_FP16, FE_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FE_FP64, "fp32": FE_FP32, "fp16": FE_FP16, "bf16": FE_BF16}
 FE_SOURCE_NONE, FE_SOURCE_CONST, FE_SOURCE_SINPROD = 0, 1, 2
 FE_DIRICHLET_ZERO, FE_DIRICHLET_AFFINE = 0, 1
-FE_NEDELEC, FE_RAVIART_THOMAS, FE_NEDELEC2 = 1, 2, 3
-FAMILIES = {"nedelec": FE_NEDELEC, "raviart_thomas": FE_RAVIART_THOMAS, "nedelec2": FE_NEDELEC2}
+FE_NEDELEC, FE_RAVIART_THOMAS, FE_NEDELEC2, FE_RAVIART_THOMAS2 = 1, 2, 3, 4
+FAMILIES = {"nedelec": FE_NEDELEC, "raviart_thomas": FE_RAVIART_THOMAS, "nedelec2": FE_NEDELEC2,
+            "raviart_thomas2": FE_RAVIART_THOMAS2}
 
 # every entry point include/fe.h declares
 EXPORTS = [
@@ -1032,7 +1033,8 @@ class Simplex:
             nnode = (order + 1) * (order + 2) // 2 if dim == 2 else (order + 1) * (order + 2) * (order + 3) // 6
             self.nloc = nnode * ncomp
         else:
-            self.nloc = {"nedelec": 6 if dim == 3 else 3, "nedelec2": 20 if dim == 3 else 8}.get(family, dim + 1)
+            self.nloc = {"nedelec": 6 if dim == 3 else 3, "nedelec2": 20 if dim == 3 else 8,
+                         "raviart_thomas2": 15 if dim == 3 else 8}.get(family, dim + 1)
         self.ntri = self.nloc * (self.nloc + 1) // 2
         dev = torch.device(device)
         self.rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=dev)

@@ -215,6 +215,11 @@ VCASES = [
     ("nedelec2", 3, [2, 2, 1], True, 2, True),
     ("nedelec2", 3, [1, 2, 2], True, 1, False),
     ("nedelec2", 3, [2, 1, 2], False, 2, False),
+    ("raviart_thomas2", 2, [3, 2], True, 2, True),
+    ("raviart_thomas2", 2, [2, 3], False, 1, False),
+    ("raviart_thomas2", 3, [2, 2, 1], True, 2, True),
+    ("raviart_thomas2", 3, [1, 2, 2], True, 1, False),
+    ("raviart_thomas2", 3, [2, 1, 2], False, 2, False),
 ]
 
 
@@ -262,13 +267,14 @@ def test_vector_element_system_matches_oracle(case):
     assert torch.equal(v1, G.values)
 
 
-@pytest.mark.parametrize("family", ["nedelec", "raviart_thomas", "nedelec2"])
+@pytest.mark.parametrize("family", ["nedelec", "raviart_thomas", "nedelec2", "raviart_thomas2"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_vector_single_cell_with_and_without_free_dofs(family, dim):
     """One reference-shaped cell with its vertices listed out of order: with a
-    zero trace every edge, facet and face DOF is fixed (second order in 2D keeps
-    its two interior DOFs); without, every DOF is free and the system is the
-    cell's matrix in the global frame."""
+    zero trace every edge, facet and face DOF is fixed (the interior DOFs of
+    the second-order triangle, and of second-order Raviart-Thomas, stay free);
+    without, every DOF is free and the system is the cell's matrix in the
+    global frame."""
     if dim == 3:
         v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64) * 0.7
         c = np.array([[2, 0, 3, 1]], dtype=np.int32)
@@ -288,7 +294,8 @@ def test_vector_single_cell_with_and_without_free_dofs(family, dim):
         assert (G.n_rows, G.nnz, G.n_nodes) == (S.nfree, S.nnz, S.nent)
         np.testing.assert_array_equal(G.cell_dofs().cpu().numpy(), S.cell_dofs)
         if dirichlet:
-            assert G.n_rows == (2 if (family == "nedelec2" and dim == 2) else 0)
+            interior = {"nedelec2": 2 if dim == 2 else 0, "raviart_thomas2": dim}.get(family, 0)
+            assert G.n_rows == interior
         else:
             assert G.n_rows == G.cell_dofs().shape[1]
         if G.n_rows:
@@ -301,7 +308,8 @@ def test_vector_single_cell_with_and_without_free_dofs(family, dim):
 
 @pytest.mark.parametrize("family,dim,n", [("nedelec", 3, [3, 3, 2]), ("raviart_thomas", 3, [3, 2, 2]),
                                           ("nedelec", 2, [6, 5]), ("nedelec2", 3, [2, 2, 2]),
-                                          ("nedelec2", 2, [5, 4])])
+                                          ("nedelec2", 2, [5, 4]), ("raviart_thomas2", 3, [2, 2, 2]),
+                                          ("raviart_thomas2", 2, [5, 4])])
 def test_vector_element_pcg_matches_direct_solve_of_oracle(family, dim, n):
     say(f"[vector solve] {family} dim={dim} n={n}")
     v, c, coef, G, S = build_vector_pair(family, dim, n, True, 2, True, kappa=1.0)
@@ -398,6 +406,38 @@ def test_nedelec2_sampled_cells_numbering_and_solve_at_24():
     ws = torch.empty(F.pcg_query(G.n_rows), dtype=torch.uint8, device="cuda")
     # the curl-free fields are damped only by the mass term: Jacobi-PCG needs
     # a few 10^4 iterations here
+    info = F.pcg_solve(G.csr, G.rhs, xs, 1e-8, 60000, ws)
+    say(f"solve: iters {info['iters']} true relres {info['true_relres']:.2e}")
+    assert info["status"] == 0 and info["true_relres"] <= 2e-8
+
+
+def test_raviart_thomas2_sampled_cells_numbering_and_solve_at_24():
+    """Second-order Raviart-Thomas on the shuffled Kuhn subdivision of the
+    jittered 24^3 brick: -grad(k div u) + u = f with the manufactured field's
+    load, zero normal trace; the numbering bit-exact against the oracle's,
+    sampled element matrices and loads in the global frame, then Jacobi-PCG
+    to 1e-8."""
+    dim, n = 3, 24
+    say("[raviart_thomas2] 24^3 shuffled Kuhn")
+    v, c = simplex_mesh(dim, n, jitter=0.2, shuffle=True)
+    coef = lognormal_coefficients(c.shape[0])
+    src = (np.pi ** 2 + 1.0,) * 3
+    coeff = F.make_coeff("poisson", "fp64", source_kind=2, source=src, dim=dim)
+    G = F.Simplex(dim, v, c, 0, coeff, cell_coeff=coef, family="raviart_thomas2", kappa=1.0)
+    G.assemble()
+    torch.cuda.synchronize()
+    say(f"rows {G.n_rows} nnz {G.nnz} contributions {G.n_contrib}")
+    dof_of, code, nfree, _ = O.vector_number("raviart_thomas2", dim, len(v), c)
+    np.testing.assert_array_equal(G.cell_dofs().cpu().numpy(), code[dof_of])
+    assert G.n_rows == nfree
+    E, Fl = G.elements()
+    g = rng(97)
+    for K in list(g.integers(0, c.shape[0], size=24)) + [0, c.shape[0] - 1]:
+        A, f, _ = O.vector_element("raviart_thomas2", dim, v[c[K]], c[K], coef=coef[K], kappa=1.0, source_kind=2,
+                                   source=src)
+        assert rel(E[K], upper(A)) <= MATRIX_RTOL and rel(Fl[K], f) <= MATRIX_RTOL
+    xs = torch.zeros(G.n_rows, dtype=torch.float64, device="cuda")
+    ws = torch.empty(F.pcg_query(G.n_rows), dtype=torch.uint8, device="cuda")
     info = F.pcg_solve(G.csr, G.rhs, xs, 1e-8, 60000, ws)
     say(f"solve: iters {info['iters']} true relres {info['true_relres']:.2e}")
     assert info["status"] == 0 and info["true_relres"] <= 2e-8
