@@ -562,6 +562,20 @@ NEDELEC2_WORKLOAD = dict(dim=3, n=24, kappa=1.0, rtol=1e-8,
                               "assembly + Jacobi-PCG (CSR SpMV) to rtol 1e-8")
 
 
+RT2_WORKLOAD = dict(dim=3, n=24, kappa=1.0, rtol=1e-8,
+                    text="second-order Raviart-Thomas elements on tetrahedra (three fluxes per face, three interior "
+                         "moments): the Kuhn subdivision of the 24^3 unit-cube brick (82,944 tetrahedra, jittered "
+                         "+-0.2h, seed 17080), -grad(k div u) + u = f with lognormal k per cell (seed 17081), "
+                         "f = (pi^2 + 1) (sin pi x_r)_r, zero normal trace; FP64 assembly + Jacobi-PCG (CSR SpMV) to "
+                         "rtol 1e-8")
+
+
+def vector_source(family, kappa):
+    """The manufactured field's load factor: curl curl of the Nedelec field is
+    2 pi^2 times it, -grad div of the Raviart-Thomas field pi^2 times it."""
+    return ((math.pi ** 2 if family.startswith("raviart") else 2 * math.pi ** 2) + kappa,) * 3
+
+
 def simplex_element_bytes(ncells, ntri, nloc, nverts, dim):
     """Algorithmic bytes of the element kernel: the element matrices' upper
     triangles and the loads written, connectivity, coefficients and vertex
@@ -602,12 +616,14 @@ def simplex_cpu_baseline(wl, gpu_iters, ncells_full, nnz_full, n=12, cg_its=100)
 
 def simplex_form(args, F, torch, steps=3, warmup=1, family=None):
     """The simplicial workload (Lagrange P2, or with family "nedelec" /
-    "nedelec2" the first- / second-order edge elements): a step is the
+    "nedelec2" the first- / second-order edge elements, "raviart_thomas2" the
+    second-order facet elements): a step is the
     assembly (element kernel + gathers through the stored map) + Jacobi-PCG
     on the CSR, the numbering, pattern and gather map built once before
     timing (Sect. 11.1)."""
     from fe_inputs import lognormal_coefficients, simplex_mesh
-    wl = {None: SIMPLEX_WORKLOAD, "nedelec": NEDELEC_WORKLOAD, "nedelec2": NEDELEC2_WORKLOAD}[family]
+    wl = {None: SIMPLEX_WORKLOAD, "nedelec": NEDELEC_WORKLOAD, "nedelec2": NEDELEC2_WORKLOAD,
+          "raviart_thomas2": RT2_WORKLOAD}[family]
     dim, n = wl["dim"], wl["n"]
     v, c = simplex_mesh(dim, n, jitter=0.2)
     coef = lognormal_coefficients(c.shape[0])
@@ -616,7 +632,7 @@ def simplex_form(args, F, torch, steps=3, warmup=1, family=None):
         coeff = F.make_coeff("poisson", "fp64", source_kind=1, source=(1.0,), dim=dim)
         G = F.Simplex(dim, v, c, wl["k"], coeff, cell_coeff=coef)
     else:
-        src = (2 * math.pi ** 2 + wl["kappa"],) * 3
+        src = vector_source(family, wl["kappa"])
         coeff = F.make_coeff("poisson", "fp64", source_kind=2, source=src, dim=dim)
         G = F.Simplex(dim, v, c, 0, coeff, cell_coeff=coef, family=family, kappa=wl["kappa"])
     t_setup = time.perf_counter() - t0
@@ -697,7 +713,7 @@ def vector_cpu_baseline(wl, family, gpu_iters, ncells_full, nnz_full, n=16, cg_i
     from fe_inputs import lognormal_coefficients, simplex_mesh
     v, c = simplex_mesh(wl["dim"], n, jitter=0.2)
     coef = lognormal_coefficients(c.shape[0])
-    src = (2 * math.pi ** 2 + wl["kappa"],) * 3
+    src = vector_source(family, wl["kappa"])
     S = O.VectorSystem(family, wl["dim"], v, c, coef=coef, kappa=wl["kappa"], source_kind=2, source=src)
     t_asm = S.t_assemble
     t0 = time.perf_counter()
@@ -1052,7 +1068,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=256.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--form", default=None,
-                    choices=["batch", "serve", "precision", "dg", "stokes", "simplex", "nedelec", "nedelec2"],
+                    choices=["batch", "serve", "precision", "dg", "stokes", "simplex", "nedelec", "nedelec2",
+                             "raviart_thomas2"],
                     help="run only this form and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates the HBM byte counters)")
@@ -1099,6 +1116,11 @@ def main():
     if args.form == "nedelec":
         torch.cuda.set_device(0)
         print(json.dumps({"form": "nedelec", **simplex_form(args, F, torch, family="nedelec")}), flush=True)
+        return
+    if args.form == "raviart_thomas2":
+        torch.cuda.set_device(0)
+        print(json.dumps({"form": "raviart_thomas2",
+                          **simplex_form(args, F, torch, steps=2, warmup=1, family="raviart_thomas2")}), flush=True)
         return
     if args.form == "nedelec2":
         torch.cuda.set_device(0)
