@@ -170,7 +170,7 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
     __shared__ double sL[K1 * K1], sD[K1 * K1];
     // geometry of every quadrature point of the cell
     __shared__ double sJi[NQ][9];
-    __shared__ double sW[NQ], sWd[NQ], sXq[NQ][3];
+    __shared__ double sW[NQ], sGf[NQ][NC];
     __shared__ int sBad;
     // gradients of a slab of points, and their weights
     __shared__ __attribute__((aligned(16))) S sG[DIM][QS][NNP];
@@ -199,10 +199,9 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
         const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
         if (!(det > 0.0)) sBad = 1;
         const double wd = rt.gw[a0] * rt.gw[a1] * rt.gw[a2] * fabs(det);
-        sWd[q] = wd;
         sW[q] = wd * coef;
         for (int t = 0; t < 9; t++) sJi[q][t] = Ji[t];
-        for (int r = 0; r < 3; r++) sXq[q][r] = xq[r];
+        for (int c = 0; c < NC; c++) sGf[q][c] = wd * source_value_mf(p, xq, c);
     }
     __syncthreads();
 
@@ -300,8 +299,7 @@ __device__ __forceinline__ void k3_mfma_body(const SpaceArgs &s, const MeshArgs 
                         const int q = q0s + qq;
                         const int b0 = q % K1, b1 = (q / K1) % K1, b2 = q / (K1 * K1);
                         const double phi = sL[n0 * K1 + b0] * sL[n1 * K1 + b1] * sL[n2 * K1 + b2];
-                        const double xq[3] = {sXq[q][0], sXq[q][1], sXq[q][2]};
-                        facc[t] = __fma_rn(sWd[q] * source_value_mf(p, xq, c), phi, facc[t]);
+                        facc[t] = __fma_rn(sGf[q][c], phi, facc[t]);
                     }
                 }
             }
@@ -425,7 +423,7 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
     __shared__ double sX[8][3];
     __shared__ double sL[K1 * K1], sD[K1 * K1];
     __shared__ double sJi[NQ][9];
-    __shared__ double sW[NQ], sWd[NQ], sXq[NQ][3];
+    __shared__ double sW[NQ], sGf[NQ][NC];
     __shared__ double sDet0, sAlpha;
     __shared__ int sBad;
     __shared__ __attribute__((aligned(16))) S sG[DIM][NNP][PITCH];
@@ -454,10 +452,9 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
         const double det = geometry_mf<DIM>(Xl, xi, Ji, xq);
         if (!(det > 0.0)) sBad = 1;
         const double wd = rt.gw[a0] * rt.gw[a1] * rt.gw[a2] * fabs(det);
-        sWd[q] = wd;
         sW[q] = wd * coef;
         for (int t = 0; t < 9; t++) sJi[q][t] = Ji[t];
-        for (int r = 0; r < 3; r++) sXq[q][r] = xq[r];
+        for (int c = 0; c < NC; c++) sGf[q][c] = wd * source_value_mf(p, xq, c);
         if (q == 0) sDet0 = det;
     }
     __syncthreads();
@@ -575,24 +572,34 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // block rows: RPI rows per store instruction, a lane keeps its
-            // column; mirror rows (block columns): MPI per instruction
+            // column; mirror rows (block columns): MPI per instruction.  All
+            // staged values are read first (lanes beyond RPI or MPI read row
+            // or column 0 and store nothing), so the LDS reads are in flight
+            // together and the stores wait on none of them one by one.
             const int I0 = (ta * 16 + ch0) * NC, J0 = tb * 16 * NC;
+            const int rsub = lane / BC, rj = lane - rsub * BC, rs = rsub < RPI ? rsub : 0;
+            const int msub = lane / CHR, mi = lane - msub * CHR, ms = msub < MPI ? msub : 0;
+            Out vr[CHR / RPI], vm[BC / MPI];
+#pragma unroll
+            for (int it = 0; it < CHR / RPI; it++) vr[it] = stg[(it * RPI + rs) * BP + rj];
+#pragma unroll
+            for (int it = 0; it < BC / MPI; it++) vm[it] = stg[mi * BP + it * MPI + ms];
             {
-                const int rsub = lane / BC, jl = lane - rsub * BC, J = J0 + jl;
+                const int J = J0 + rj;
                 if (rsub < RPI && J < nloc)
-#pragma unroll 4
+#pragma unroll
                     for (int it = 0; it < CHR / RPI; it++) {
-                        const int il = it * RPI + rsub, I = I0 + il;
-                        if (I < nloc && !(diag && J < I)) Ec[I * nloc + J] = stg[il * BP + jl];
+                        const int I = I0 + it * RPI + rsub;
+                        if (I < nloc && !(diag && J < I)) Ec[I * nloc + J] = vr[it];
                     }
             }
             {
-                const int msub = lane / CHR, il = lane - msub * CHR, I = I0 + il;
+                const int I = I0 + mi;
                 if (msub < MPI && I < nloc)
-#pragma unroll 4
+#pragma unroll
                     for (int it = 0; it < BC / MPI; it++) {
-                        const int jl = it * MPI + msub, J = J0 + jl;
-                        if (J < nloc && !(diag && J <= I)) Ec[J * nloc + I] = stg[il * BP + jl];
+                        const int J = J0 + it * MPI + msub;
+                        if (J < nloc && !(diag && J <= I)) Ec[J * nloc + I] = vm[it];
                     }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -600,16 +607,30 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
-    // load vector (FP64, VALU): the points in ascending order, as the slab kernel
-    for (int row = tid; row < nloc; row += NTH) {
+    // load vector (FP64, VALU): the points in ascending order, each term
+    // (w |det J| f_c(x_q)) phi_a(x_q) rounded as in the slab kernel; the
+    // point factors were formed once per cell and a row keeps its 1D basis
+    // values in registers.  Rows go first to the upper half of the waves,
+    // which were given no more tile pairs than the lower half.
+#pragma unroll 1
+    for (int row = (tid + NTH / 2) % NTH; row < nloc; row += NTH) {
         const int a = row / NC, c = row % NC;
         const int n0 = a % K1, n1 = (a / K1) % K1, n2 = a / (K1 * K1);
+        double L0[K1], L1[K1];
+#pragma unroll
+        for (int b = 0; b < K1; b++) {
+            L0[b] = sL[n0 * K1 + b];
+            L1[b] = sL[n1 * K1 + b];
+        }
         double f = 0.0;
-        for (int q = 0; q < NQ; q++) {
-            const int b0 = q % K1, b1 = (q / K1) % K1, b2 = q / (K1 * K1);
-            const double phi = sL[n0 * K1 + b0] * sL[n1 * K1 + b1] * sL[n2 * K1 + b2];
-            const double xq[3] = {sXq[q][0], sXq[q][1], sXq[q][2]};
-            f = __fma_rn(sWd[q] * source_value_mf(p, xq, c), phi, f);
+#pragma unroll 1
+        for (int b2 = 0; b2 < K1; b2++) {
+            const double L2 = sL[n2 * K1 + b2];
+            const double *g = &sGf[K1 * K1 * b2][c];
+#pragma unroll
+            for (int b1 = 0; b1 < K1; b1++)
+#pragma unroll
+                for (int b0 = 0; b0 < K1; b0++) f = __fma_rn(g[(K1 * b1 + b0) * NC], L0[b0] * L1[b1] * L2, f);
         }
         F[cell * nloc + row] = f;
     }
