@@ -471,12 +471,14 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
     __syncthreads();
     const double alpha = sAlpha;
 
-    // scaled gradients of every point: thread -> (point gq, nodes gsub + TPQ j);
+    // scaled gradients of every point: thread -> (point gq, node lines u =
+    // n1 + K1 n2 from gsub in steps of TPQ, each line K1 nodes along the
+    // first axis, whose 1D values at the point stay in registers);
     // consecutive lanes write consecutive points of one node row
     {
         const int gq = tid % NQP, gsub = tid / NQP;
         const bool live = gq < NQ;
-        double Ji[9];
+        double Ji[9] = {};
         double sw = 0.0;
         int b0 = 0, b1 = 0, b2 = 0;
         if (live) {
@@ -487,21 +489,32 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
             b2 = gq / (K1 * K1);
             sw = sqrt(sW[gq]) * alpha;
         }
-#pragma unroll 4
-        for (int j = 0; j < NNP / TPQ; j++) {
-            const int node = gsub + TPQ * j;
-            double g[3] = {0.0, 0.0, 0.0};
-            if (live && node < nn) {
-                const int n0 = node % K1, n1 = (node / K1) % K1, n2 = node / (K1 * K1);
-                const double L0 = sL[n0 * K1 + b0], L1 = sL[n1 * K1 + b1], L2 = sL[n2 * K1 + b2];
-                const double gr[3] = {sD[n0 * K1 + b0] * L1 * L2, L0 * sD[n1 * K1 + b1] * L2,
-                                      L0 * L1 * sD[n2 * K1 + b2]};
+        double La[K1], Da[K1];
 #pragma unroll
-                for (int c = 0; c < 3; c++) g[c] = Ji[0 * 3 + c] * gr[0] + Ji[1 * 3 + c] * gr[1] + Ji[2 * 3 + c] * gr[2];
-            }
-#pragma unroll
-            for (int c = 0; c < 3; c++) sG[c][node][gq] = S(g[c] * sw);
+        for (int n = 0; n < K1; n++) {
+            La[n] = sL[n * K1 + b0];
+            Da[n] = sD[n * K1 + b0];
         }
+#pragma unroll 1
+        for (int u = gsub; u < K1 * K1; u += TPQ) {
+            const int n1 = u % K1, n2 = u / K1;
+            const double L1 = sL[n1 * K1 + b1], D1 = sD[n1 * K1 + b1];
+            const double L2 = sL[n2 * K1 + b2], D2 = sD[n2 * K1 + b2];
+#pragma unroll
+            for (int n0 = 0; n0 < K1; n0++) {
+                const double L0 = La[n0];
+                const double gr[3] = {Da[n0] * L1 * L2, L0 * D1 * L2, L0 * L1 * D2};
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const double g = Ji[0 * 3 + c] * gr[0] + Ji[1 * 3 + c] * gr[1] + Ji[2 * 3 + c] * gr[2];
+                    sG[c][n0 + K1 * u][gq] = S(live ? g * sw : 0.0);
+                }
+            }
+        }
+        // node rows past the last node are zero
+        for (int node = nn + gsub; node < NNP; node += TPQ)
+#pragma unroll
+            for (int c = 0; c < 3; c++) sG[c][node][gq] = S(0.0);
     }
     __syncthreads();
     if (tid == 0 && sBad) atomicOr(m.status, 1);
