@@ -392,6 +392,7 @@ struct Cell16Shape {
     static constexpr int NQP = (NQ + 31) / 32 * 32;  // points padded to the MFMA depth
     static constexpr int PITCH = NQP + 8;            // LDS row pitch (elements)
     static constexpr int NTH = NNP == 128 ? 512 : 256;
+    static constexpr int WPE = NNP == 32 ? 4 : NNP == 64 ? 3 : 1;  // waves per SIMD the registers must allow
 };
 
 template <class Pol, int PROB, int NNP>
@@ -650,7 +651,7 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
 }
 
 template <class Pol, int PROB, int NNP>
-__global__ __launch_bounds__(Cell16Shape<NNP>::NTH, 1) void k3_cell16_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p,
+__global__ __launch_bounds__(Cell16Shape<NNP>::NTH, Cell16Shape<NNP>::WPE) void k3_cell16_kernel(SpaceArgs s, MeshArgs m, ProblemArgs p,
                                                                             RefTables rt,
                                                                             typename Pol::Out *__restrict__ E,
                                                                             double *__restrict__ F)
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(Cell16Shape<NNP>::NTH, 1) void k3_cell16_kernel(Spa
 }
 
 template <class Pol, int PROB, int NNP>
-__global__ __launch_bounds__(Cell16Shape<NNP>::NTH, 1) void k3_cell16_batch_kernel(const AsmJob *__restrict__ jobs,
+__global__ __launch_bounds__(Cell16Shape<NNP>::NTH, Cell16Shape<NNP>::WPE) void k3_cell16_batch_kernel(const AsmJob *__restrict__ jobs,
                                                                                   const int32_t *__restrict__ boff,
                                                                                   int njobs)
 {
