@@ -49,6 +49,23 @@ struct PolF32 {
     __device__ static Acc mma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 
+// FP64 to FP16, correctly rounded, by round-to-odd (Boldo and Melquiond):
+// FP32 to nearest even, moved one unit toward zero where that rounded away
+// from zero and its last bit set where inexact (rounding to odd), then FP32
+// to FP16 to nearest even in hardware; FP32 carries 13 more bits than FP16,
+// so the second rounding gives the correctly rounded result.
+__device__ __forceinline__ _Float16 f64_to_f16(double x)
+{
+    const float t = float(x);
+    const double back = double(t);
+    uint32_t u = __float_as_uint(t);
+    if (back != x) {
+        if (fabs(back) > fabs(x)) u -= 1u;
+        u |= 1u;
+    }
+    return _Float16(__uint_as_float(u));
+}
+
 struct PolF16 {
     using S = _Float16;
     using V = h8_t;
@@ -57,6 +74,7 @@ struct PolF16 {
     static constexpr int KM = 32;  // a lane reads 8 consecutive points
     __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
     __device__ static Acc mma(V a, V b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+    __device__ static S cvt(double x) { return f64_to_f16(x); }
 };
 
 struct PolBF16 {
@@ -67,6 +85,7 @@ struct PolBF16 {
     static constexpr int KM = 32;
     __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
     __device__ static Acc mma(V a, V b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+    __device__ static S cvt(double x) { return S(x); }
 };
 
 template <int DIM>
@@ -508,7 +527,7 @@ __device__ __forceinline__ void k3_cell16_body(const SpaceArgs &s, const MeshArg
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     const double g = Ji[0 * 3 + c] * gr[0] + Ji[1 * 3 + c] * gr[1] + Ji[2 * 3 + c] * gr[2];
-                    sG[c][n0 + K1 * u][gq] = S(live ? g * sw : 0.0);
+                    sG[c][n0 + K1 * u][gq] = Pol::cvt(live ? g * sw : 0.0);
                 }
             }
         }
